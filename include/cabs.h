@@ -1,0 +1,251 @@
+/*
+ * cabs.h -- C ABI of libcabs, a GPU (AMD MI355X, gfx950) implementation of the
+ * data-parallel hot path of cascaded bilateral sampling (CABS): Zhang, Liu,
+ * Zhang, Xiong, Xing, Ye, "Seeing the forest from the trees in two looks:
+ * matrix sketching by cascaded bilateral sampling", arXiv:1607.07395.
+ *
+ * The problem (paper, Section 1): approximate an m x n matrix A that is only
+ * accessible through the rows and columns one asks for, in O(m + n) time and
+ * memory, by a small set of its own rows and columns.  The method (Algorithm 2):
+ * a uniformly sampled pilot sketch gives row and column embeddings P, Q; a
+ * weighted k-means on each (Section 3.2) picks representative rows and columns;
+ * the sketching routine of Section 4.1 turns them into A ~ C Umid R.
+ *
+ * Conventions for every call below
+ *   - Array arguments are DEVICE pointers unless the comment says "host".
+ *     The caller owns every buffer; the library allocates nothing inside a call
+ *     (scratch comes from the caller's workspace).
+ *   - Matrices are row-major.  Sampled rows are stored transposed: R^T is n x k.
+ *   - Calls are asynchronous on `stream` (a hipStream_t passed as void*; NULL =
+ *     the default stream).  Outputs are valid once the stream has reached the
+ *     end of the call's work.  The host-side return value only reports argument
+ *     and launch errors; conditions found on the device (rank loss) are written
+ *     to the result's `diag` array.
+ *   - Every call is deterministic: the same arguments give bitwise the same
+ *     outputs (all reductions run in a fixed order; no floating-point atomics).
+ *   - On error no work is enqueued and cabs_last_error() describes the problem.
+ */
+#ifndef CABS_H
+#define CABS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CABS_OK = 0,
+  CABS_EINVAL = -1,     /* bad argument: null pointer, size out of range, unsupported combination */
+  CABS_ENOMEM = -2,     /* workspace (or serving memory budget) too small */
+  CABS_ERANK = -3,      /* W has no singular value above the threshold (reported in diag[0]) */
+  CABS_EDEVICE = -4,    /* a HIP call failed */
+  CABS_EBUSY = -5,      /* serving: request not finished yet */
+  CABS_ECANCELED = -6   /* serving: request was cancelled */
+} cabs_status;
+
+/* Arithmetic precisions.  SVDs, eigen-decompositions, Grams for the
+ * orthogonalisation and all k x k algebra always run in FP64. */
+typedef enum { CABS_F64 = 0, CABS_F32 = 1, CABS_BF16 = 2, CABS_F16 = 3 } cabs_prec;
+
+/* How entries of A are obtained. */
+typedef enum {
+  CABS_SRC_DENSE = 0,   /* A stored row-major with leading dimension lda; sampled rows are
+                           gathered with coalesced row reads, sampled columns through LDS tiles */
+  CABS_SRC_LOWRANK = 1, /* A_ij = sum_t pf[i,t] s[t] qf[j,t] + noise_std * g(noise_seed, i, j),
+                           g a standard normal from Philox-4x64-10 at counter (i, j, 5, 0),
+                           key (noise_seed, 0), by Box-Muller; E is never stored */
+  CABS_SRC_RBF = 2      /* A_ij = exp(-|x_i - y_j|^2 / (2 sigma^2)) */
+} cabs_src;
+
+/* The monotone weight Upsilon(|P_l|) of the weighted k-means objective
+ * (Section 3.2): 1, |p|^param, 1/(1+exp(-param |p|)), or [|p| >= param]. */
+typedef enum { CABS_W_CONST = 0, CABS_W_POW = 1, CABS_W_SIGMOID = 2, CABS_W_STEP = 3 } cabs_weight;
+
+/* The sketching routine: the stabilised form of Section 4.1 (default), or the
+ * pseudo-skeleton A ~ C W^+ R of Eq. (W), Section 2.2. */
+typedef enum { CABS_SK_STABILIZED = 0, CABS_SK_PSEUDO_SKELETON = 1 } cabs_sketch_kind;
+
+/* Descriptor of the input matrix (an entry generator or a dense array).
+ * Table arrays (a, pf, qf, s, x, y) use precision `storage` (F64 or F32).
+ * The compute precision must be F64 when storage is F64. */
+typedef struct {
+  int32_t kind;          /* cabs_src */
+  int32_t storage;       /* cabs_prec of the table arrays: CABS_F64 or CABS_F32 */
+  int64_t m, n;
+  /* DENSE */
+  const void* a;         /* m x n, row stride lda elements */
+  int64_t lda;
+  /* LOWRANK */
+  const void* pf;        /* m x r */
+  const void* qf;        /* n x r */
+  const void* s;         /* r */
+  int32_t r;
+  int32_t reserved0;
+  double noise_std;
+  uint64_t noise_seed;
+  /* RBF */
+  const void* x;         /* m x d */
+  const void* y;         /* n x d (may equal x) */
+  int32_t d;
+  int32_t reserved1;
+  double sigma;
+} cabs_matrix;
+
+/* Parameters of one sketch.  Sample sizes: pilot k1_rows x k1_cols (Algorithm 2,
+ * pilot sampling), follow-up k2_rows x k2_cols (follow-up sampling); the output
+ * rank is at most min(k2_rows, k2_cols). */
+typedef struct {
+  int32_t k1_rows, k1_cols, k2_rows, k2_cols;
+  int32_t kmeans_iters;  /* c, Lloyd iterations per side (the paper uses 5) */
+  int32_t weight_kind;   /* cabs_weight */
+  double weight_param;
+  int32_t sketch_kind;   /* cabs_sketch_kind */
+  int32_t orthogonalize; /* 1: orthogonalise the pilot factors before embedding
+                            (supplementary Section 3), in FP64 */
+  double pinv_rtol;      /* components with sigma_i <= rtol * sigma_1 are dropped;
+                            <= 0 selects max(kr, kc) * eps(FP64) */
+  int32_t compute;       /* cabs_prec of entry evaluation, embeddings, distance GEMMs */
+  int32_t want_factors;  /* 1: also produce the orthogonalised factor form (Uf, S, Vf) */
+  uint64_t seed;         /* Philox key for every draw of the method */
+} cabs_params;
+
+/* Diagnostic slots written to cabs_result.diag (doubles). */
+enum {
+  CABS_DIAG_STATUS = 0,        /* 0 or CABS_ERANK */
+  CABS_DIAG_ENC_R_PILOT = 1,   /* weighted encoding error of the rows, pilot representatives (Section 3.1) */
+  CABS_DIAG_ENC_C_PILOT = 2,
+  CABS_DIAG_ENC_R_FINAL = 3,   /* ... after the last k-means iteration (before snapping) */
+  CABS_DIAG_ENC_C_FINAL = 4,
+  CABS_DIAG_TMAX_R = 5,        /* largest cluster size T (Section 3.1) */
+  CABS_DIAG_TMAX_C = 6,
+  CABS_DIAG_RANK_PILOT = 7,    /* kept components of the pilot sketch */
+  CABS_DIAG_RANK_FINAL = 8,
+  CABS_DIAG_ENTRIES = 9,       /* distinct entries of A read, summed over both rounds */
+  CABS_DIAG_GAP_R = 10,        /* smallest nearest/second-nearest centre gap, final assignment */
+  CABS_DIAG_GAP_C = 11,
+  CABS_DIAG_SIGMA1_PILOT = 12, /* largest singular value of W, pilot and follow-up */
+  CABS_DIAG_SIGMA1_FINAL = 13,
+  CABS_DIAG_LEN = 16
+};
+
+/* Outputs of cabs_sketch.  All buffers are caller-owned device memory.
+ * Element type of C, Rt, Uf, Vf is the compute precision. */
+typedef struct {
+  int64_t* idx_r;        /* [k2_rows] follow-up row indices, ascending */
+  int64_t* idx_c;        /* [k2_cols] follow-up column indices, ascending */
+  int64_t* pilot_r;      /* [k1_rows] pilot row indices, ascending (NULL: not returned) */
+  int64_t* pilot_c;      /* [k1_cols] */
+  void* C;               /* m x k2_cols: A(:, idx_c) */
+  void* Rt;              /* n x k2_rows: A(idx_r, :)^T */
+  double* Umid;          /* k2_cols x k2_rows: A ~ C Umid Rt^T */
+  void* Uf;              /* m x kf (kf = min(k2_rows, k2_cols)), orthonormal columns; NULL unless want_factors */
+  double* S;             /* kf singular values, descending */
+  void* Vf;              /* n x kf */
+  double* diag;          /* CABS_DIAG_LEN doubles (may be NULL) */
+} cabs_result;
+
+/* Library version string and the last error message of the calling thread. */
+const char* cabs_version(void);
+const char* cabs_last_error(void);
+
+/* Bytes of workspace cabs_sketch needs for this matrix and these parameters
+ * (0 on invalid arguments; see cabs_last_error). */
+size_t cabs_workspace_bytes(const cabs_matrix* mat, const cabs_params* prm);
+
+/* One CABS sketch (Algorithm 2): pilot sampling (Floyd on Philox, streams 0/1),
+ * pilot evaluation of C = A(:, I^c) and R^T, W = C(I^r, :); the sketching
+ * routine (Section 4.1) with an FP64 SVD of W; optional FP64 orthogonalisation
+ * (supplementary Section 3); embeddings P = U S^(1/2), Q = V S^(1/2) with
+ * weights Upsilon(|P_l|); c iterations of weighted k-means per side from the
+ * pilot sample; snapping of every centre to the nearest untaken row; follow-up
+ * evaluation and sketch.  ws must hold cabs_workspace_bytes() bytes, 256-byte
+ * aligned.  Returns CABS_EINVAL for k > dimension, null required pointers or an
+ * unsupported precision/source pair; CABS_ENOMEM if ws_bytes is too small. */
+cabs_status cabs_sketch(const cabs_matrix* mat, const cabs_params* prm, void* ws, size_t ws_bytes,
+                        cabs_result* out, void* stream);
+
+/* Relative Frobenius error |A - C Umid R|_F / |A|_F (the paper's error metric,
+ * Section 5) of a finished sketch.  n_samples = 0: exact, over all m*n entries;
+ * otherwise over n_samples i.i.d. uniform entries drawn with replacement from
+ * Philox stream 4 with key (seed, 0): sample t is (mulhi(w0, m), mulhi(w1, n)).
+ * out3 (device) receives {sum of squared residuals, sum of squared entries,
+ * ratio}.  ws must hold cabs_error_workspace_bytes() bytes. */
+size_t cabs_error_workspace_bytes(const cabs_matrix* mat, const cabs_params* prm, int64_t n_samples);
+cabs_status cabs_error(const cabs_matrix* mat, const cabs_params* prm, const cabs_result* res,
+                       int64_t n_samples, uint64_t seed, void* ws, size_t ws_bytes, double* out3,
+                       void* stream);
+
+/* ---- Stage entry points (the same kernels cabs_sketch runs, one at a time) ---- */
+
+/* k distinct indices from [0, n), uniform, ascending (Floyd's algorithm on
+ * Philox-4x64-10: draw t uses word 0 at counter (t, 0, stream_id, 0), key
+ * (seed, 0)).  Pilot sampling of Algorithm 2.  Requires 0 < k <= n, k <= 4096. */
+cabs_status cabs_sample(int64_t n, int32_t k, uint64_t seed, int32_t stream_id, int64_t* out, void* stream);
+
+/* C = A(:, idx) (m x k) or R^T = A(idx, :)^T (n x k) in precision `compute`:
+ * the sampled columns / rows of Algorithm 2.  idx: k device int64 in range. */
+cabs_status cabs_eval_cols(const cabs_matrix* mat, const int64_t* idx, int32_t k, int32_t compute, void* out,
+                           void* stream);
+cabs_status cabs_eval_rows_t(const cabs_matrix* mat, const int64_t* idx, int32_t k, int32_t compute, void* out,
+                             void* stream);
+
+/* Batched FP64 SVD by one-sided Jacobi: A_b (rows x cols, row-major) =
+ * U_b diag(S_b) V_b^T with p = min(rows, cols), U_b rows x p, V_b cols x p,
+ * S_b descending, the largest-magnitude entry of every column of U_b positive.
+ * Used on W in the sketching routine (Section 4.1).  rows, cols <= 1024.
+ * ws: cabs_svd_workspace_bytes() bytes. */
+size_t cabs_svd_workspace_bytes(int32_t batch, int32_t rows, int32_t cols);
+cabs_status cabs_svd(int32_t batch, int32_t rows, int32_t cols, const double* A, double* U, double* S, double* V,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* Weighted k-means (Section 3.2) on the rows of P (rows x dim, precision
+ * `compute`) with weights w (rows, FP64), from the k initial centres Z0
+ * (k x dim, FP64), for `iters` Lloyd iterations; then, if snap_out is not
+ * NULL, every centre (in index order) takes the nearest row not taken before
+ * it, written ascending to snap_out[k].  Z (k x dim FP64), labels (rows,
+ * int32, assignment to Z) and obj2 ({objective at Z0, objective at Z}) are
+ * outputs (obj2 and labels may be NULL).  Ties go to the lowest index.
+ * ws: cabs_kmeans_workspace_bytes() bytes. */
+size_t cabs_kmeans_workspace_bytes(int64_t rows, int32_t dim, int32_t k, int32_t compute);
+cabs_status cabs_kmeans(int64_t rows, int32_t dim, int32_t k, int32_t compute, const void* P, const double* w,
+                        const double* Z0, int32_t iters, double* Z, int32_t* labels, double* obj2,
+                        int64_t* snap_out, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- Continuous-batching server ---- */
+
+typedef struct cabs_server cabs_server;
+
+/* A server owns `max_slots` concurrent request slots on `device` (each with
+ * its own stream) and a device memory pool of hbm_budget_bytes from which
+ * request workspaces are carved.  Returns NULL on failure (see cabs_last_error). */
+cabs_server* cabs_server_create(int32_t device, size_t hbm_budget_bytes, int32_t max_slots);
+
+/* Queue a sketch.  `mat`, `prm` and the device buffers named by `out` must stay
+ * valid until the request completes or is cancelled.  The request is admitted
+ * when a slot is free and its workspace fits in the pool; a request that can
+ * never fit is rejected here with CABS_ENOMEM.  *ticket identifies it. */
+cabs_status cabs_submit(cabs_server* srv, const cabs_matrix* mat, const cabs_params* prm, const cabs_result* out,
+                        uint64_t* ticket);
+
+/* CABS_OK when finished (latency_s, host, may be NULL: submit-to-completion
+ * seconds), CABS_EBUSY while queued or running, CABS_ECANCELED if cancelled,
+ * CABS_EINVAL for an unknown ticket.  A finished ticket is forgotten after it is
+ * reported once. */
+cabs_status cabs_poll(cabs_server* srv, uint64_t ticket, double* latency_s);
+
+/* Cancel a request that has not been admitted yet (CABS_EBUSY if it already runs). */
+cabs_status cabs_cancel(cabs_server* srv, uint64_t ticket);
+
+/* Block until every submitted request has completed. */
+cabs_status cabs_server_drain(cabs_server* srv);
+
+/* Waits for running requests, then frees the pool and streams. */
+void cabs_server_destroy(cabs_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CABS_H */

@@ -232,21 +232,30 @@ def weighted_kmeans(p: np.ndarray, w: np.ndarray, z0: np.ndarray, iters: int) ->
                         min_gap=float(gap.min()) if gap.size else math.inf)
 
 
-def snap(p: np.ndarray, z: np.ndarray) -> np.ndarray:
+SNAP_TIE_RTOL = 1e-11
+
+
+def snap(p: np.ndarray, z: np.ndarray, tie_rtol: float = SNAP_TIE_RTOL) -> np.ndarray:
     """Replace every centre by its nearest in-sample point (Section 3.2).
 
     Reading: centres are visited in index order; each takes the nearest row of
-    P not taken by an earlier centre (lowest row index on ties), so the
-    follow-up sample holds distinct rows.  Returned sorted ascending.
+    P not taken by an earlier centre, so the follow-up sample holds distinct
+    rows.  Exact ties are common (the centre of a two-row cluster is the
+    midpoint of its rows), so distances within tie_rtol * (|Z_j| + sqrt(d_min))^2
+    of the nearest one count as equal and the lowest row index wins.  Returned
+    sorted ascending.
     """
     if z.shape[0] > p.shape[0]:
         raise ValueError("more centres than rows")
     d = cdist(p, z, "sqeuclidean")
+    zn = np.linalg.norm(z, axis=1)
     taken = np.zeros(p.shape[0], dtype=bool)
     out = np.empty(z.shape[0], dtype=np.int64)
     for j in range(z.shape[0]):
         dj = np.where(taken, np.inf, d[:, j])
-        l = int(np.argmin(dj))
+        dmin = float(dj.min())
+        tol = tie_rtol * (zn[j] + math.sqrt(dmin)) ** 2
+        l = int(np.flatnonzero(dj <= dmin + tol)[0])
         taken[l] = True
         out[j] = l
     return np.sort(out)

@@ -1,0 +1,113 @@
+"""ctypes declarations of the libcabs C ABI (include/cabs.h).
+
+Loading fails loudly when the shared library has not been built: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcabs.so")
+
+OK, EINVAL, ENOMEM, ERANK, EDEVICE, EBUSY, ECANCELED = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {OK: "CABS_OK", EINVAL: "CABS_EINVAL", ENOMEM: "CABS_ENOMEM", ERANK: "CABS_ERANK",
+                EDEVICE: "CABS_EDEVICE", EBUSY: "CABS_EBUSY", ECANCELED: "CABS_ECANCELED"}
+
+F64, F32, BF16, F16 = 0, 1, 2, 3
+SRC_DENSE, SRC_LOWRANK, SRC_RBF = 0, 1, 2
+W_CONST, W_POW, W_SIGMOID, W_STEP = 0, 1, 2, 3
+SK_STABILIZED, SK_PSEUDO_SKELETON = 0, 1
+
+DIAG_STATUS, DIAG_ENC_R_PILOT, DIAG_ENC_C_PILOT, DIAG_ENC_R_FINAL, DIAG_ENC_C_FINAL = 0, 1, 2, 3, 4
+DIAG_TMAX_R, DIAG_TMAX_C, DIAG_RANK_PILOT, DIAG_RANK_FINAL, DIAG_ENTRIES = 5, 6, 7, 8, 9
+DIAG_GAP_R, DIAG_GAP_C, DIAG_SIGMA1_PILOT, DIAG_SIGMA1_FINAL, DIAG_LEN = 10, 11, 12, 13, 16
+
+
+class CabsMatrix(C.Structure):
+    _fields_ = [
+        ("kind", C.c_int32), ("storage", C.c_int32), ("m", C.c_int64), ("n", C.c_int64),
+        ("a", C.c_void_p), ("lda", C.c_int64),
+        ("pf", C.c_void_p), ("qf", C.c_void_p), ("s", C.c_void_p), ("r", C.c_int32), ("reserved0", C.c_int32),
+        ("noise_std", C.c_double), ("noise_seed", C.c_uint64),
+        ("x", C.c_void_p), ("y", C.c_void_p), ("d", C.c_int32), ("reserved1", C.c_int32), ("sigma", C.c_double),
+    ]
+
+
+class CabsParams(C.Structure):
+    _fields_ = [
+        ("k1_rows", C.c_int32), ("k1_cols", C.c_int32), ("k2_rows", C.c_int32), ("k2_cols", C.c_int32),
+        ("kmeans_iters", C.c_int32), ("weight_kind", C.c_int32), ("weight_param", C.c_double),
+        ("sketch_kind", C.c_int32), ("orthogonalize", C.c_int32), ("pinv_rtol", C.c_double),
+        ("compute", C.c_int32), ("want_factors", C.c_int32), ("seed", C.c_uint64),
+    ]
+
+
+class CabsResult(C.Structure):
+    _fields_ = [
+        ("idx_r", C.c_void_p), ("idx_c", C.c_void_p), ("pilot_r", C.c_void_p), ("pilot_c", C.c_void_p),
+        ("C", C.c_void_p), ("Rt", C.c_void_p), ("Umid", C.c_void_p),
+        ("Uf", C.c_void_p), ("S", C.c_void_p), ("Vf", C.c_void_p), ("diag", C.c_void_p),
+    ]
+
+
+_P = C.c_void_p
+_SIGS = {
+    "cabs_version": (C.c_char_p, []),
+    "cabs_last_error": (C.c_char_p, []),
+    "cabs_workspace_bytes": (C.c_size_t, [C.POINTER(CabsMatrix), C.POINTER(CabsParams)]),
+    "cabs_sketch": (C.c_int, [C.POINTER(CabsMatrix), C.POINTER(CabsParams), _P, C.c_size_t, C.POINTER(CabsResult), _P]),
+    "cabs_error_workspace_bytes": (C.c_size_t, [C.POINTER(CabsMatrix), C.POINTER(CabsParams), C.c_int64]),
+    "cabs_error": (C.c_int, [C.POINTER(CabsMatrix), C.POINTER(CabsParams), C.POINTER(CabsResult), C.c_int64,
+                             C.c_uint64, _P, C.c_size_t, _P, _P]),
+    "cabs_sample": (C.c_int, [C.c_int64, C.c_int32, C.c_uint64, C.c_int32, _P, _P]),
+    "cabs_eval_cols": (C.c_int, [C.POINTER(CabsMatrix), _P, C.c_int32, C.c_int32, _P, _P]),
+    "cabs_eval_rows_t": (C.c_int, [C.POINTER(CabsMatrix), _P, C.c_int32, C.c_int32, _P, _P]),
+    "cabs_svd_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32]),
+    "cabs_svd": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+    "cabs_kmeans_workspace_bytes": (C.c_size_t, [C.c_int64, C.c_int32, C.c_int32, C.c_int32]),
+    "cabs_kmeans": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, C.c_int32, _P, _P, _P, _P,
+                              _P, C.c_size_t, _P]),
+    "cabs_server_create": (_P, [C.c_int32, C.c_size_t, C.c_int32]),
+    "cabs_submit": (C.c_int, [_P, C.POINTER(CabsMatrix), C.POINTER(CabsParams), C.POINTER(CabsResult),
+                              C.POINTER(C.c_uint64)]),
+    "cabs_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(C.c_double)]),
+    "cabs_cancel": (C.c_int, [_P, C.c_uint64]),
+    "cabs_server_drain": (C.c_int, [_P]),
+    "cabs_server_destroy": (None, [_P]),
+}
+
+_lib = None
+
+
+def exported_symbols() -> list[str]:
+    return list(_SIGS)
+
+
+def lib():
+    """The loaded libcabs.so (raises if it is missing or lacks a symbol)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libcabs.so is not built ({LIB_PATH}); run "
+                               "`python -m paper_1607_07395_amd.build` first")
+        handle = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+class CabsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = lib().cabs_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def check(status: int, where: str) -> None:
+    if status != OK:
+        raise CabsError(status, where)

@@ -1,0 +1,695 @@
+// libcabs host runtime: argument checking, workspace planning and the stage
+// sequence of one CABS sketch (Algorithm 2), behind the C ABI of cabs.h.
+//
+// Stage order of cabs_sketch (all enqueued on the caller's stream, no host
+// synchronisation):
+//   1  pilot indices I^r, I^c (Floyd on Philox streams 0 / 1)
+//   2  C = A(:, I^c), R^T = A(I^r, :)^T; W = C(I^r, :) in FP64
+//   3  SVD W = U_w S_w V_w^T (FP64 Jacobi)
+//   4  C^ = C V_w, R^ = R^T U_w with FP64 column norms N_c, N_r; kept components,
+//      S (stabilised: S_w sqrt(mn/(kr kc)); pseudo-skeleton: N_c N_r / S_w)
+//   5  orthogonalisation (supplementary Section 3) in FP64: Grams of C^ N_c^-1 and
+//      R^ N_r^-1, their eigen-decompositions, the SVD of T_u^T S T_v; the
+//      embedding maps M_u, M_v (k x k) such that P = C^ M_u, Q = R^ M_v hold
+//      U_o S_o^(1/2) and V_o S_o^(1/2)
+//   6  P, Q with row norms -> weights Upsilon(|P_l|)
+//   7  weighted k-means + snapping on P (rows) and Q (columns)
+//   8  C_bar, R_bar^T, W_bar; SVD; norms; Umid = V_w diag(S / (N_c N_r)) U_w^T
+//   9  optional factor form (Uf, S, Vf) by the same orthogonalisation
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+
+#include "../../include/cabs.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace cabs;
+
+// ---------------------------------------------------------------------------
+// Error reporting
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static cabs_status fail(cabs_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                              \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ != hipSuccess) return fail(CABS_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" const char* cabs_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char* cabs_version(void) { return "libcabs 0.1 (gfx950)"; }
+
+// ---------------------------------------------------------------------------
+// Small device kernels for the k x k bookkeeping
+// ---------------------------------------------------------------------------
+namespace {
+
+// Kept components and the scalings of the sketching routine (Section 4.1).
+__global__ void sketch_vec_kernel(int p, int kr, int kc, double m, double n, const double* __restrict__ sw,
+                                  const double* __restrict__ nc2, const double* __restrict__ nr2, double rtol, int kind,
+                                  double* __restrict__ invc, double* __restrict__ invr, double* __restrict__ sk,
+                                  double* __restrict__ dk, double* __restrict__ diag, int diag_rank, int diag_sig) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  const double eps = 2.220446049250313e-16;
+  const double s1 = sw[0];
+  const double tol = (rtol > 0.0 ? rtol : (double)(kr > kc ? kr : kc) * eps) * s1;
+  const double scale = sqrt(m * n / ((double)kr * (double)kc));
+  for (int i = threadIdx.x; i < p; i += blockDim.x) {
+    const double nc = sqrt(nc2[i]), nr = sqrt(nr2[i]), s = sw[i];
+    const bool keep = s1 > 0.0 && s > tol && nc > 0.0 && nr > 0.0;
+    double S = 0.0, D = 0.0;
+    if (keep) {
+      if (kind == CABS_SK_STABILIZED) { S = s * scale; D = S / (nc * nr); }
+      else { S = nc * nr / s; D = 1.0 / s; }
+      atomicAdd(&cnt, 1);
+    }
+    invc[i] = keep ? 1.0 / nc : 0.0;
+    invr[i] = keep ? 1.0 / nr : 0.0;
+    sk[i] = S;
+    dk[i] = D;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    diag[diag_rank] = (double)cnt;
+    diag[diag_sig] = s1;
+    if (cnt == 0) diag[CABS_DIAG_STATUS] = (double)CABS_ERANK;
+  }
+}
+
+// out[i][j] = dl[i] * G[i][j] * dr[j]   (batched: item b uses G + b*p*p)
+__global__ void scale2_kernel(int p, const double* __restrict__ G, const double* __restrict__ dl,
+                              const double* __restrict__ dr, double* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= p * p) return;
+  const int i = e / p, j = e % p;
+  out[e] = dl[i] * G[e] * dr[j];
+}
+
+// Eigen truncation of a PSD Gram with eigenvalues lam (descending):
+// fpos[j] = sqrt(lam_j), fneg[j] = 1/sqrt(lam_j) for kept j, 0 otherwise.
+__global__ void eig_vec_kernel(int p, const double* __restrict__ lam, double* __restrict__ fpos,
+                               double* __restrict__ fneg) {
+  const double eps = 2.220446049250313e-16;
+  const double lmax = lam[0];
+  for (int j = threadIdx.x; j < p; j += blockDim.x) {
+    const double l = lam[j];
+    const bool keep = lmax > 0.0 && l > (double)p * eps * lmax;
+    fpos[j] = keep ? sqrt(l) : 0.0;
+    fneg[j] = keep ? 1.0 / sqrt(l) : 0.0;
+  }
+}
+
+// v[j] = sqrt(max(s[j], 0))
+__global__ void sqrt_vec_kernel(int p, const double* __restrict__ s, double* __restrict__ out) {
+  for (int j = threadIdx.x; j < p; j += blockDim.x) out[j] = s[j] > 0.0 ? sqrt(s[j]) : 0.0;
+}
+
+// B = diag(v) as a dense p x p matrix.
+__global__ void diag_mat_kernel(int p, const double* __restrict__ a, const double* __restrict__ b,
+                                double* __restrict__ B) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= p * p) return;
+  const int i = e / p, j = e % p;
+  B[e] = i == j ? a[i] * (b ? (b[i] > 0.0 ? sqrt(b[i]) : 0.0) : 1.0) : 0.0;
+}
+
+// Weights Upsilon(|P_l|) from squared row norms (Section 3.2).
+__global__ void weights_kernel(int64_t rows, const double* __restrict__ rowsq, int kind, double prm,
+                               double* __restrict__ w) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const double x = sqrt(rowsq[r]);
+  double v = 1.0;
+  if (kind == CABS_W_POW) v = pow(x, prm);
+  else if (kind == CABS_W_SIGMOID) v = 1.0 / (1.0 + exp(-prm * x));
+  else if (kind == CABS_W_STEP) v = x >= prm ? 1.0 : 0.0;
+  w[r] = v;
+}
+
+__global__ void diag_init_kernel(double* __restrict__ diag, double entries) {
+  const int i = threadIdx.x;
+  if (i < CABS_DIAG_LEN) diag[i] = i == CABS_DIAG_ENTRIES ? entries : 0.0;
+}
+
+__global__ void copy_slot_kernel(const double* __restrict__ src, double* __restrict__ dst) {
+  if (threadIdx.x == 0) *dst = *src;
+}
+
+__global__ void copy_vec_kernel(int n, const double* __restrict__ src, double* __restrict__ dst) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+// Sign of every column of U (rows x p): the entry of largest magnitude, first on ties.
+__global__ void colsign_partial_kernel(int64_t rows, int p, int64_t rows_per, const void* __restrict__ U, int prec,
+                                       double* __restrict__ pmax, int64_t* __restrict__ pidx,
+                                       double* __restrict__ psgn) {
+  const int j = blockIdx.y * blockDim.x + threadIdx.x;
+  if (j >= p) return;
+  const int64_t r0 = blockIdx.x * rows_per;
+  const int64_t r1 = r0 + rows_per < rows ? r0 + rows_per : rows;
+  double best = -1.0, sg = 1.0;
+  int64_t bi = INT64_MAX;
+  for (int64_t r = r0; r < r1; ++r) {
+    double v;
+    switch (prec) {
+      case P_F64: v = ((const double*)U)[r * p + j]; break;
+      case P_F32: v = ((const float*)U)[r * p + j]; break;
+      case P_BF16: v = (double)(float)((const bf16*)U)[r * p + j]; break;
+      default: v = (double)(float)((const f16*)U)[r * p + j]; break;
+    }
+    if (fabs(v) > best) { best = fabs(v); bi = r; sg = v < 0.0 ? -1.0 : 1.0; }
+  }
+  const int64_t o = (int64_t)blockIdx.x * p + j;
+  pmax[o] = best;
+  pidx[o] = bi;
+  psgn[o] = sg;
+}
+
+__global__ void colsign_final_kernel(int nb, int p, const double* __restrict__ pmax, const int64_t* __restrict__ pidx,
+                                     const double* __restrict__ psgn, double* __restrict__ sgn) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= p) return;
+  double best = -1.0, sg = 1.0;
+  int64_t bi = INT64_MAX;
+  for (int b = 0; b < nb; ++b) {
+    const int64_t o = (int64_t)b * p + j;
+    if (pmax[o] > best || (pmax[o] == best && pidx[o] < bi)) { best = pmax[o]; bi = pidx[o]; sg = psgn[o]; }
+  }
+  sgn[j] = sg;
+}
+
+template <typename TC>
+__global__ void colscale_kernel(int64_t rows, int p, TC* __restrict__ U, const double* __restrict__ s) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * p) return;
+  const int j = (int)(e % p);
+  if (s[j] < 0.0) U[e] = from_f64<TC>(-to_f64(U[e]));
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Workspace planner
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* b) : base((char*)b) {}
+  template <typename T> T* take(size_t count) {
+    void* p = base ? base + off : nullptr;
+    off += (count * sizeof(T) + 255) & ~(size_t)255;
+    return (T*)p;
+  }
+  void* take_bytes(size_t bytes) {
+    void* p = base ? base + off : nullptr;
+    off += (bytes + 255) & ~(size_t)255;
+    return p;
+  }
+};
+
+// FP64 scratch of one sketching round with p components.
+struct RoundWs {
+  double *W, *Uw, *Sw, *Vw, *nc2, *nr2, *invc, *invr, *sk, *dk;
+  double *G2, *Gs2, *E2U, *E2S, *E2V, *fpos, *fneg;   // batched (2) Grams and eigen-decompositions
+  double *K, *Us, *S1, *Vs, *T1, *T2, *Mu, *Mv, *sq;
+  void *svd_ws, *gram_ws, *ts_ws;
+  void *Ch, *Rh;                                      // extrapolated vectors (compute precision)
+};
+
+struct Plan {
+  int prec, kr1, kc1, kr2, kc2, p1, p2;
+  int64_t m, n;
+};
+
+static void plan_round(Carve& cv, RoundWs& R, const Plan& pl, int kr, int kc, bool need_vectors, bool need_ortho) {
+  const int p = std::min(kr, kc);
+  const size_t eb = prec_bytes(pl.prec);
+  R.W = cv.take<double>((size_t)kr * kc);
+  R.Uw = cv.take<double>((size_t)kr * p);
+  R.Sw = cv.take<double>(p);
+  R.Vw = cv.take<double>((size_t)kc * p);
+  R.nc2 = cv.take<double>(p);
+  R.nr2 = cv.take<double>(p);
+  R.invc = cv.take<double>(p);
+  R.invr = cv.take<double>(p);
+  R.sk = cv.take<double>(p);
+  R.dk = cv.take<double>(p);
+  size_t svd_b = std::max(svd_ws_bytes(1, kr, kc), need_ortho ? std::max(svd_ws_bytes(2, p, p), svd_ws_bytes(1, p, p)) : 0);
+  R.svd_ws = cv.take_bytes(svd_b);
+  const int64_t mx = std::max(pl.m, pl.n);
+  R.ts_ws = cv.take_bytes(std::max(tsgemm_ws_bytes(mx, std::max(kr, kc), p, pl.prec), tsgemm_ws_bytes(mx, p, p, pl.prec)));
+  if (need_vectors) {
+    R.Ch = cv.take_bytes((size_t)pl.m * p * eb);
+    R.Rh = cv.take_bytes((size_t)pl.n * p * eb);
+  } else {
+    R.Ch = R.Rh = nullptr;
+  }
+  if (need_ortho) {
+    R.G2 = cv.take<double>(2 * (size_t)p * p);
+    R.Gs2 = cv.take<double>(2 * (size_t)p * p);
+    R.E2U = cv.take<double>(2 * (size_t)p * p);
+    R.E2S = cv.take<double>(2 * (size_t)p);
+    R.E2V = cv.take<double>(2 * (size_t)p * p);
+    R.fpos = cv.take<double>(2 * (size_t)p);
+    R.fneg = cv.take<double>(2 * (size_t)p);
+    R.K = cv.take<double>((size_t)p * p);
+    R.Us = cv.take<double>((size_t)p * p);
+    R.S1 = cv.take<double>(p);
+    R.Vs = cv.take<double>((size_t)p * p);
+    R.T1 = cv.take<double>((size_t)p * p);
+    R.T2 = cv.take<double>((size_t)p * p);
+    R.Mu = cv.take<double>((size_t)p * p);
+    R.Mv = cv.take<double>((size_t)p * p);
+    R.sq = cv.take<double>(p);
+    R.gram_ws = cv.take_bytes(gram_ws_bytes(mx, p));
+  } else {
+    R.Mu = cv.take<double>((size_t)p * p);
+    R.Mv = cv.take<double>((size_t)p * p);
+    R.G2 = R.Gs2 = R.E2U = R.E2S = R.E2V = R.fpos = R.fneg = R.K = R.Us = R.S1 = R.Vs = R.T1 = R.T2 = R.sq = nullptr;
+    R.gram_ws = nullptr;
+  }
+}
+
+struct SketchWs {
+  int64_t *Ir, *Ic, *Ir0, *Ic0;
+  void *C, *Rt, *P, *Q;
+  double *rowsqP, *rowsqQ, *wr, *wc, *Z0r, *Z0c, *Zr, *Zc, *diag, *obj;
+  void *kmr, *kmc;
+  RoundWs r1, r2;
+  double* sgn_ws;
+};
+
+static size_t plan_sketch(void* ws, const Plan& pl, const cabs_params* prm, SketchWs& S) {
+  Carve cv(ws);
+  const size_t eb = prec_bytes(pl.prec);
+  const int e = pl.p1;
+  S.Ir = cv.take<int64_t>(pl.kr1);
+  S.Ic = cv.take<int64_t>(pl.kc1);
+  S.Ir0 = cv.take<int64_t>(std::max(pl.kr2, 1));
+  S.Ic0 = cv.take<int64_t>(std::max(pl.kc2, 1));
+  S.C = cv.take_bytes((size_t)pl.m * pl.kc1 * eb);
+  S.Rt = cv.take_bytes((size_t)pl.n * pl.kr1 * eb);
+  S.P = cv.take_bytes((size_t)pl.m * e * eb);
+  S.Q = cv.take_bytes((size_t)pl.n * e * eb);
+  S.rowsqP = cv.take<double>(pl.m);
+  S.rowsqQ = cv.take<double>(pl.n);
+  S.wr = cv.take<double>(pl.m);
+  S.wc = cv.take<double>(pl.n);
+  S.Z0r = cv.take<double>((size_t)pl.kr2 * e);
+  S.Z0c = cv.take<double>((size_t)pl.kc2 * e);
+  S.Zr = cv.take<double>((size_t)pl.kr2 * e);
+  S.Zc = cv.take<double>((size_t)pl.kc2 * e);
+  S.diag = cv.take<double>(CABS_DIAG_LEN);
+  S.obj = cv.take<double>(8);
+  S.kmr = cv.take_bytes(kmeans_ws_bytes(pl.m, e, pl.kr2, pl.prec));
+  S.kmc = cv.take_bytes(kmeans_ws_bytes(pl.n, e, pl.kc2, pl.prec));
+  plan_round(cv, S.r1, pl, pl.kr1, pl.kc1, true, prm->orthogonalize != 0);
+  plan_round(cv, S.r2, pl, pl.kr2, pl.kc2, prm->want_factors != 0, prm->want_factors != 0);
+  S.sgn_ws = prm->want_factors ? cv.take<double>((size_t)3 * 256 * pl.p2) : nullptr;
+  return cv.off + 256;
+}
+
+static bool valid_prec(int p) { return p == CABS_F64 || p == CABS_F32 || p == CABS_BF16 || p == CABS_F16; }
+
+static cabs_status check_matrix(const cabs_matrix* mat) {
+  if (!mat) return fail(CABS_EINVAL, "null matrix descriptor");
+  if (mat->m <= 0 || mat->n <= 0) return fail(CABS_EINVAL, "matrix dimensions must be positive");
+  if (mat->m >= (int64_t)1 << 31 || mat->n >= (int64_t)1 << 31)
+    return fail(CABS_EINVAL, "matrix dimensions must be below 2^31");
+  if (mat->storage != CABS_F64 && mat->storage != CABS_F32) return fail(CABS_EINVAL, "storage must be F64 or F32");
+  switch (mat->kind) {
+    case CABS_SRC_DENSE:
+      if (!mat->a) return fail(CABS_EINVAL, "dense source needs a");
+      if (mat->lda < mat->n) return fail(CABS_EINVAL, "lda must be >= n");
+      break;
+    case CABS_SRC_LOWRANK:
+      if (!mat->pf || !mat->qf || !mat->s) return fail(CABS_EINVAL, "low-rank source needs pf, qf, s");
+      if (mat->r <= 0) return fail(CABS_EINVAL, "rank r must be positive");
+      if (!(mat->noise_std >= 0.0)) return fail(CABS_EINVAL, "noise_std must be >= 0");
+      break;
+    case CABS_SRC_RBF:
+      if (!mat->x || !mat->y) return fail(CABS_EINVAL, "RBF source needs x and y");
+      if (mat->d <= 0) return fail(CABS_EINVAL, "dimension d must be positive");
+      if (!(mat->sigma > 0.0)) return fail(CABS_EINVAL, "sigma must be positive");
+      break;
+    default:
+      return fail(CABS_EINVAL, "unknown source kind %d", mat->kind);
+  }
+  return CABS_OK;
+}
+
+static cabs_status check_compute(const cabs_matrix* mat, int compute) {
+  if (!valid_prec(compute)) return fail(CABS_EINVAL, "unknown compute precision %d", compute);
+  if (mat->storage == CABS_F64 && compute != CABS_F64)
+    return fail(CABS_EINVAL, "FP64 tables need FP64 compute");
+  if (mat->storage == CABS_F32 && compute == CABS_F64)
+    return fail(CABS_EINVAL, "FP64 compute needs FP64 tables");
+  return CABS_OK;
+}
+
+static cabs_status check_params(const cabs_matrix* mat, const cabs_params* prm) {
+  cabs_status s = check_matrix(mat);
+  if (s != CABS_OK) return s;
+  if (!prm) return fail(CABS_EINVAL, "null parameters");
+  s = check_compute(mat, prm->compute);
+  if (s != CABS_OK) return s;
+  const int ks[4] = {prm->k1_rows, prm->k1_cols, prm->k2_rows, prm->k2_cols};
+  for (int i = 0; i < 4; ++i)
+    if (ks[i] < 1 || ks[i] > 1024) return fail(CABS_EINVAL, "sample sizes must be in [1, 1024]");
+  if (prm->k1_rows > mat->m || prm->k2_rows > mat->m) return fail(CABS_EINVAL, "row sample size exceeds m");
+  if (prm->k1_cols > mat->n || prm->k2_cols > mat->n) return fail(CABS_EINVAL, "column sample size exceeds n");
+  if (prm->kmeans_iters < 0 || prm->kmeans_iters > 10000) return fail(CABS_EINVAL, "kmeans_iters out of range");
+  if (prm->weight_kind < CABS_W_CONST || prm->weight_kind > CABS_W_STEP) return fail(CABS_EINVAL, "unknown weight kind");
+  if (prm->sketch_kind != CABS_SK_STABILIZED && prm->sketch_kind != CABS_SK_PSEUDO_SKELETON)
+    return fail(CABS_EINVAL, "unknown sketch kind");
+  return CABS_OK;
+}
+
+static Plan make_plan(const cabs_matrix* mat, const cabs_params* prm) {
+  Plan pl;
+  pl.prec = prm->compute;
+  pl.kr1 = prm->k1_rows;
+  pl.kc1 = prm->k1_cols;
+  pl.kr2 = prm->k2_rows;
+  pl.kc2 = prm->k2_cols;
+  pl.p1 = std::min(pl.kr1, pl.kc1);
+  pl.p2 = std::min(pl.kr2, pl.kc2);
+  pl.m = mat->m;
+  pl.n = mat->n;
+  return pl;
+}
+
+static MatView view_of(const cabs_matrix* mat) {
+  MatView v;
+  v.kind = mat->kind;
+  v.storage = mat->storage;
+  v.m = mat->m;
+  v.n = mat->n;
+  v.a = mat->a;
+  v.lda = mat->lda;
+  v.pf = mat->pf;
+  v.qf = mat->qf;
+  v.s = mat->s;
+  v.r = mat->r;
+  v.noise_std = mat->noise_std;
+  v.noise_seed = mat->noise_seed;
+  v.x = mat->x;
+  v.y = mat->y;
+  v.d = mat->d;
+  v.sigma = mat->sigma;
+  return v;
+}
+
+// One sketching round on sampled C (m x kc), R^T (n x kr), W (kr x kc, FP64).
+// Computes the SVD of W, the norms and scalings; optionally the extrapolated
+// vectors C^, R^ and the orthogonalised embedding maps.
+static cabs_status run_round(const Plan& pl, RoundWs& R, int kr, int kc, const void* C, const void* Rt,
+                             const cabs_params* prm, bool vectors, bool ortho, double* diag, int slot_rank,
+                             int slot_sig, hipStream_t st) {
+  const int p = std::min(kr, kc);
+  HIP_TRY(launch_svd(1, kr, kc, R.W, 0, R.Uw, 0, R.Sw, 0, R.Vw, 0, R.svd_ws, st));
+  // C^ = C V_w, R^ = R^T U_w, with column norms
+  HIP_TRY(launch_tsgemm(pl.m, kc, p, pl.prec, C, R.Vw, vectors ? R.Ch : nullptr, R.nc2, nullptr, R.ts_ws, st));
+  HIP_TRY(launch_tsgemm(pl.n, kr, p, pl.prec, Rt, R.Uw, vectors ? R.Rh : nullptr, R.nr2, nullptr, R.ts_ws, st));
+  hipLaunchKernelGGL(sketch_vec_kernel, dim3(1), dim3(1024), 0, st, p, kr, kc, (double)pl.m, (double)pl.n, R.Sw, R.nc2,
+                     R.nr2, prm->pinv_rtol, prm->sketch_kind, R.invc, R.invr, R.sk, R.dk, diag, slot_rank, slot_sig);
+  HIP_TRY(hipGetLastError());
+  if (!vectors) return CABS_OK;
+  if (!ortho) {
+    // P = U S^(1/2) = C^ diag(invc sqrt(S)), Q = R^ diag(invr sqrt(S))
+    const unsigned gb = (unsigned)ceil_div((int64_t)p * p, 256);
+    hipLaunchKernelGGL(diag_mat_kernel, dim3(gb), dim3(256), 0, st, p, R.invc, R.sk, R.Mu);
+    hipLaunchKernelGGL(diag_mat_kernel, dim3(gb), dim3(256), 0, st, p, R.invr, R.sk, R.Mv);
+    HIP_TRY(hipGetLastError());
+    return CABS_OK;
+  }
+  const size_t pp = (size_t)p * p;
+  // Grams of the unit-norm factors U = C^ N_c^-1, V = R^ N_r^-1 (FP64).
+  HIP_TRY(launch_gram(pl.m, p, pl.prec, R.Ch, R.Gs2, R.gram_ws, st));
+  HIP_TRY(launch_gram(pl.n, p, pl.prec, R.Rh, R.Gs2 + pp, R.gram_ws, st));
+  const unsigned gb = (unsigned)ceil_div((int64_t)pp, 256);
+  hipLaunchKernelGGL(scale2_kernel, dim3(gb), dim3(256), 0, st, p, R.Gs2, R.invc, R.invc, R.G2);
+  hipLaunchKernelGGL(scale2_kernel, dim3(gb), dim3(256), 0, st, p, R.Gs2 + pp, R.invr, R.invr, R.G2 + pp);
+  // Eigen-decompositions G = E Lambda E^T (SVD of a PSD matrix), both in one launch.
+  HIP_TRY(launch_svd(2, p, p, R.G2, pp, R.E2U, pp, R.E2S, p, R.E2V, pp, R.svd_ws, st));
+  hipLaunchKernelGGL(eig_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.E2S, R.fpos, R.fneg);
+  hipLaunchKernelGGL(eig_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.E2S + p, R.fpos + p, R.fneg + p);
+  // T_u = E_u Lambda_u^(1/2);  K = T_u^T diag(S) T_v
+  HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, true, R.E2V + pp, p, false, R.fpos, R.sk, R.fpos + p, R.K, p, st));
+  HIP_TRY(launch_svd(1, p, p, R.K, 0, R.Us, 0, R.S1, 0, R.Vs, 0, R.svd_ws, st));
+  hipLaunchKernelGGL(sqrt_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.S1, R.sq);
+  // M_u = diag(invc) E_u diag(Lambda_u^-1/2) U_s diag(S_1^1/2), M_v likewise with V_s.
+  HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, false, R.Us, p, false, R.invc, R.fneg, R.sq, R.Mu, p, st));
+  HIP_TRY(launch_small_gemm(p, p, p, R.E2V + pp, p, false, R.Vs, p, false, R.invr, R.fneg + p, R.sq, R.Mv, p, st));
+  HIP_TRY(hipGetLastError());
+  return CABS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" size_t cabs_workspace_bytes(const cabs_matrix* mat, const cabs_params* prm) {
+  if (check_params(mat, prm) != CABS_OK) return 0;
+  SketchWs S;
+  return plan_sketch(nullptr, make_plan(mat, prm), prm, S);
+}
+
+extern "C" cabs_status cabs_sketch(const cabs_matrix* mat, const cabs_params* prm, void* ws, size_t ws_bytes,
+                                   cabs_result* out, void* stream) {
+  cabs_status s = check_params(mat, prm);
+  if (s != CABS_OK) return s;
+  if (!out || !out->idx_r || !out->idx_c || !out->C || !out->Rt || !out->Umid)
+    return fail(CABS_EINVAL, "result buffers idx_r, idx_c, C, Rt, Umid are required");
+  if (prm->want_factors && (!out->Uf || !out->S || !out->Vf))
+    return fail(CABS_EINVAL, "want_factors needs Uf, S, Vf");
+  if (!ws || ((uintptr_t)ws & 255)) return fail(CABS_EINVAL, "workspace must be non-null and 256-byte aligned");
+  const Plan pl = make_plan(mat, prm);
+  SketchWs S;
+  const size_t need = plan_sketch(nullptr, pl, prm, S);
+  if (ws_bytes < need) return fail(CABS_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  plan_sketch(ws, pl, prm, S);
+  hipStream_t st = (hipStream_t)stream;
+  const MatView mv = view_of(mat);
+  double* diag = out->diag ? out->diag : S.diag;
+  const int e = pl.p1;
+
+  const double entries = (double)pl.m * pl.kc1 + (double)pl.n * pl.kr1 - (double)pl.kr1 * pl.kc1 +
+                         (double)pl.m * pl.kc2 + (double)pl.n * pl.kr2 - (double)pl.kr2 * pl.kc2;
+  hipLaunchKernelGGL(diag_init_kernel, dim3(1), dim3(64), 0, st, diag, entries);
+  HIP_TRY(hipGetLastError());
+
+  // 1-2: pilot sampling and evaluation
+  int64_t* Ir = out->pilot_r ? out->pilot_r : S.Ir;
+  int64_t* Ic = out->pilot_c ? out->pilot_c : S.Ic;
+  HIP_TRY(launch_sample(pl.m, pl.kr1, prm->seed, STREAM_PILOT_ROWS, Ir, st));
+  HIP_TRY(launch_sample(pl.n, pl.kc1, prm->seed, STREAM_PILOT_COLS, Ic, st));
+  HIP_TRY(launch_eval(mv, false, Ic, pl.kc1, pl.prec, S.C, st));
+  HIP_TRY(launch_eval(mv, true, Ir, pl.kr1, pl.prec, S.Rt, st));
+  HIP_TRY(launch_gather_rows_f64(S.C, pl.prec, pl.kc1, Ir, pl.kr1, pl.kc1, S.r1.W, st));
+
+  // 3-5: pilot sketch and embedding maps
+  s = run_round(pl, S.r1, pl.kr1, pl.kc1, S.C, S.Rt, prm, true, prm->orthogonalize != 0, diag, CABS_DIAG_RANK_PILOT,
+                CABS_DIAG_SIGMA1_PILOT, st);
+  if (s != CABS_OK) return s;
+
+  // 6: embeddings and weights
+  HIP_TRY(launch_tsgemm(pl.m, e, e, pl.prec, S.r1.Ch, S.r1.Mu, S.P, nullptr, S.rowsqP, S.r1.ts_ws, st));
+  HIP_TRY(launch_tsgemm(pl.n, e, e, pl.prec, S.r1.Rh, S.r1.Mv, S.Q, nullptr, S.rowsqQ, S.r1.ts_ws, st));
+  hipLaunchKernelGGL(weights_kernel, dim3((unsigned)ceil_div(pl.m, 256)), dim3(256), 0, st, pl.m, S.rowsqP,
+                     prm->weight_kind, prm->weight_param, S.wr);
+  hipLaunchKernelGGL(weights_kernel, dim3((unsigned)ceil_div(pl.n, 256)), dim3(256), 0, st, pl.n, S.rowsqQ,
+                     prm->weight_kind, prm->weight_param, S.wc);
+  HIP_TRY(hipGetLastError());
+
+  // 7: weighted k-means from the pilot sample, then snapping
+  const int64_t* I0r = Ir;
+  const int64_t* I0c = Ic;
+  if (pl.kr2 > pl.kr1) {
+    HIP_TRY(launch_sample(pl.m, pl.kr2, prm->seed, STREAM_INIT_ROWS, S.Ir0, st));
+    I0r = S.Ir0;
+  }
+  if (pl.kc2 > pl.kc1) {
+    HIP_TRY(launch_sample(pl.n, pl.kc2, prm->seed, STREAM_INIT_COLS, S.Ic0, st));
+    I0c = S.Ic0;
+  }
+  HIP_TRY(launch_gather_rows_f64(S.P, pl.prec, e, I0r, pl.kr2, e, S.Z0r, st));
+  HIP_TRY(launch_gather_rows_f64(S.Q, pl.prec, e, I0c, pl.kc2, e, S.Z0c, st));
+  KMeansOut kr{S.Zr, nullptr, S.obj, diag + CABS_DIAG_TMAX_R, diag + CABS_DIAG_GAP_R, out->idx_r};
+  HIP_TRY(launch_kmeans(pl.m, e, pl.kr2, pl.prec, S.P, S.wr, S.Z0r, prm->kmeans_iters, kr, S.kmr, st));
+  KMeansOut kc{S.Zc, nullptr, S.obj + 2, diag + CABS_DIAG_TMAX_C, diag + CABS_DIAG_GAP_C, out->idx_c};
+  HIP_TRY(launch_kmeans(pl.n, e, pl.kc2, pl.prec, S.Q, S.wc, S.Z0c, prm->kmeans_iters, kc, S.kmc, st));
+  hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 0, diag + CABS_DIAG_ENC_R_PILOT);
+  hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 1, diag + CABS_DIAG_ENC_R_FINAL);
+  hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 2, diag + CABS_DIAG_ENC_C_PILOT);
+  hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 3, diag + CABS_DIAG_ENC_C_FINAL);
+  HIP_TRY(hipGetLastError());
+
+  // 8: follow-up evaluation and sketch
+  HIP_TRY(launch_eval(mv, false, out->idx_c, pl.kc2, pl.prec, out->C, st));
+  HIP_TRY(launch_eval(mv, true, out->idx_r, pl.kr2, pl.prec, out->Rt, st));
+  HIP_TRY(launch_gather_rows_f64(out->C, pl.prec, pl.kc2, out->idx_r, pl.kr2, pl.kc2, S.r2.W, st));
+  const bool fac = prm->want_factors != 0;
+  s = run_round(pl, S.r2, pl.kr2, pl.kc2, out->C, out->Rt, prm, fac, fac, diag, CABS_DIAG_RANK_FINAL,
+                CABS_DIAG_SIGMA1_FINAL, st);
+  if (s != CABS_OK) return s;
+  // Umid = V_w diag(D) U_w^T  (kc2 x kr2)
+  HIP_TRY(launch_small_gemm(pl.kc2, pl.kr2, pl.p2, S.r2.Vw, pl.p2, false, S.r2.Uw, pl.p2, true, nullptr, S.r2.dk,
+                            nullptr, out->Umid, pl.kr2, st));
+
+  // 9: optional factor form: Uf = C^ N_c^-1 E_u Lambda^-1/2 U_s, S = S_1, Vf likewise.
+  if (fac) {
+    const int p = pl.p2;
+    RoundWs& R = S.r2;
+    HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, false, R.Us, p, false, R.invc, R.fneg, nullptr, R.Mu, p, st));
+    HIP_TRY(launch_small_gemm(p, p, p, R.E2V + (size_t)p * p, p, false, R.Vs, p, false, R.invr, R.fneg + p, nullptr,
+                              R.Mv, p, st));
+    HIP_TRY(launch_tsgemm(pl.m, p, p, pl.prec, R.Ch, R.Mu, out->Uf, nullptr, nullptr, R.ts_ws, st));
+    HIP_TRY(launch_tsgemm(pl.n, p, p, pl.prec, R.Rh, R.Mv, out->Vf, nullptr, nullptr, R.ts_ws, st));
+    // signs: largest-magnitude entry of each Uf column positive
+    const int nb = (int)std::min<int64_t>(256, ceil_div(pl.m, 256));
+    const int64_t rows_per = ceil_div(pl.m, nb);
+    double* pm = S.sgn_ws;
+    int64_t* pi = (int64_t*)(S.sgn_ws + (size_t)256 * p);
+    double* ps = S.sgn_ws + 2 * (size_t)256 * p;
+    hipLaunchKernelGGL(colsign_partial_kernel, dim3(nb, (unsigned)ceil_div(p, 256)), dim3(256), 0, st, pl.m, p,
+                       rows_per, out->Uf, pl.prec, pm, pi, ps);
+    hipLaunchKernelGGL(colsign_final_kernel, dim3((unsigned)ceil_div(p, 256)), dim3(256), 0, st, nb, p, pm, pi, ps,
+                       R.sq);
+    const unsigned gu = (unsigned)ceil_div(pl.m * p, 256), gv = (unsigned)ceil_div(pl.n * p, 256);
+    switch (pl.prec) {
+      case P_F64:
+        hipLaunchKernelGGL(colscale_kernel<double>, dim3(gu), dim3(256), 0, st, pl.m, p, (double*)out->Uf, R.sq);
+        hipLaunchKernelGGL(colscale_kernel<double>, dim3(gv), dim3(256), 0, st, pl.n, p, (double*)out->Vf, R.sq);
+        break;
+      case P_F32:
+        hipLaunchKernelGGL(colscale_kernel<float>, dim3(gu), dim3(256), 0, st, pl.m, p, (float*)out->Uf, R.sq);
+        hipLaunchKernelGGL(colscale_kernel<float>, dim3(gv), dim3(256), 0, st, pl.n, p, (float*)out->Vf, R.sq);
+        break;
+      case P_BF16:
+        hipLaunchKernelGGL(colscale_kernel<bf16>, dim3(gu), dim3(256), 0, st, pl.m, p, (bf16*)out->Uf, R.sq);
+        hipLaunchKernelGGL(colscale_kernel<bf16>, dim3(gv), dim3(256), 0, st, pl.n, p, (bf16*)out->Vf, R.sq);
+        break;
+      default:
+        hipLaunchKernelGGL(colscale_kernel<f16>, dim3(gu), dim3(256), 0, st, pl.m, p, (f16*)out->Uf, R.sq);
+        hipLaunchKernelGGL(colscale_kernel<f16>, dim3(gv), dim3(256), 0, st, pl.n, p, (f16*)out->Vf, R.sq);
+        break;
+    }
+    hipLaunchKernelGGL(copy_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.S1, out->S);
+  }
+  HIP_TRY(hipGetLastError());
+  return CABS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Error metric
+// ---------------------------------------------------------------------------
+extern "C" size_t cabs_error_workspace_bytes(const cabs_matrix* mat, const cabs_params* prm, int64_t n_samples) {
+  if (check_params(mat, prm) != CABS_OK || n_samples < 0) return 0;
+  return error_ws_bytes(view_of(mat), prm->k2_cols, prm->k2_rows, prm->compute, n_samples);
+}
+
+extern "C" cabs_status cabs_error(const cabs_matrix* mat, const cabs_params* prm, const cabs_result* res,
+                                  int64_t n_samples, uint64_t seed, void* ws, size_t ws_bytes, double* out3,
+                                  void* stream) {
+  cabs_status s = check_params(mat, prm);
+  if (s != CABS_OK) return s;
+  if (!res || !res->C || !res->Rt || !res->Umid || !out3) return fail(CABS_EINVAL, "null result buffers");
+  if (n_samples < 0) return fail(CABS_EINVAL, "n_samples must be >= 0");
+  if (!ws || ((uintptr_t)ws & 255)) return fail(CABS_EINVAL, "workspace must be non-null and 256-byte aligned");
+  const MatView mv = view_of(mat);
+  const size_t need = error_ws_bytes(mv, prm->k2_cols, prm->k2_rows, prm->compute, n_samples);
+  if (ws_bytes < need) return fail(CABS_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  HIP_TRY(launch_error(mv, prm->k2_cols, prm->k2_rows, prm->compute, res->C, res->Umid, res->Rt, n_samples, seed, ws,
+                       out3, (hipStream_t)stream));
+  return CABS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Stage entry points
+// ---------------------------------------------------------------------------
+extern "C" cabs_status cabs_sample(int64_t n, int32_t k, uint64_t seed, int32_t stream_id, int64_t* out, void* stream) {
+  if (!out) return fail(CABS_EINVAL, "null output");
+  if (k <= 0 || k > 4096 || (int64_t)k > n) return fail(CABS_EINVAL, "need 0 < k <= min(n, 4096)");
+  if (stream_id < 0) return fail(CABS_EINVAL, "stream id must be >= 0");
+  HIP_TRY(launch_sample(n, k, seed, stream_id, out, (hipStream_t)stream));
+  return CABS_OK;
+}
+
+static cabs_status eval_common(const cabs_matrix* mat, const int64_t* idx, int32_t k, int32_t compute, void* out,
+                               void* stream, bool rows_t) {
+  cabs_status s = check_matrix(mat);
+  if (s != CABS_OK) return s;
+  s = check_compute(mat, compute);
+  if (s != CABS_OK) return s;
+  if (!idx || !out) return fail(CABS_EINVAL, "null index or output");
+  const int64_t lim = rows_t ? mat->m : mat->n;
+  if (k <= 0 || k > lim) return fail(CABS_EINVAL, "k out of range");
+  HIP_TRY(launch_eval(view_of(mat), rows_t, idx, k, compute, out, (hipStream_t)stream));
+  return CABS_OK;
+}
+
+extern "C" cabs_status cabs_eval_cols(const cabs_matrix* mat, const int64_t* idx, int32_t k, int32_t compute, void* out,
+                                      void* stream) {
+  return eval_common(mat, idx, k, compute, out, stream, false);
+}
+
+extern "C" cabs_status cabs_eval_rows_t(const cabs_matrix* mat, const int64_t* idx, int32_t k, int32_t compute,
+                                        void* out, void* stream) {
+  return eval_common(mat, idx, k, compute, out, stream, true);
+}
+
+extern "C" size_t cabs_svd_workspace_bytes(int32_t batch, int32_t rows, int32_t cols) {
+  if (batch <= 0 || rows <= 0 || cols <= 0 || rows > 1024 || cols > 1024) return 0;
+  return svd_ws_bytes(batch, rows, cols);
+}
+
+extern "C" cabs_status cabs_svd(int32_t batch, int32_t rows, int32_t cols, const double* A, double* U, double* S,
+                                double* V, void* ws, size_t ws_bytes, void* stream) {
+  if (batch <= 0 || rows <= 0 || cols <= 0 || rows > 1024 || cols > 1024)
+    return fail(CABS_EINVAL, "need batch > 0 and 0 < rows, cols <= 1024");
+  if (!A || !U || !S || !V || !ws) return fail(CABS_EINVAL, "null pointer");
+  if (ws_bytes < svd_ws_bytes(batch, rows, cols)) return fail(CABS_ENOMEM, "workspace too small");
+  const int64_t p = rows < cols ? rows : cols;
+  HIP_TRY(launch_svd(batch, rows, cols, A, (int64_t)rows * cols, U, (int64_t)rows * p, S, p, V, (int64_t)cols * p, ws,
+                     (hipStream_t)stream));
+  return CABS_OK;
+}
+
+extern "C" size_t cabs_kmeans_workspace_bytes(int64_t rows, int32_t dim, int32_t k, int32_t compute) {
+  if (rows <= 0 || dim <= 0 || dim > 1024 || k <= 0 || k > 1024 || k > rows || !valid_prec(compute)) return 0;
+  return kmeans_ws_bytes(rows, dim, k, compute);
+}
+
+extern "C" cabs_status cabs_kmeans(int64_t rows, int32_t dim, int32_t k, int32_t compute, const void* P, const double* w,
+                                   const double* Z0, int32_t iters, double* Z, int32_t* labels, double* obj2,
+                                   int64_t* snap_out, void* ws, size_t ws_bytes, void* stream) {
+  if (rows <= 0 || rows >= (int64_t)1 << 31 || dim <= 0 || dim > 1024 || k <= 0 || k > 1024 || k > rows)
+    return fail(CABS_EINVAL, "need 0 < k <= min(rows, 1024), 0 < dim <= 1024");
+  if (!valid_prec(compute)) return fail(CABS_EINVAL, "unknown precision");
+  if (!P || !w || !Z0 || !Z || !ws) return fail(CABS_EINVAL, "null pointer");
+  if (iters < 0) return fail(CABS_EINVAL, "iters must be >= 0");
+  if (ws_bytes < kmeans_ws_bytes(rows, dim, k, compute)) return fail(CABS_ENOMEM, "workspace too small");
+  KMeansOut o{Z, labels, obj2, nullptr, nullptr, snap_out};
+  HIP_TRY(launch_kmeans(rows, dim, k, compute, P, w, Z0, iters, o, ws, (hipStream_t)stream));
+  return CABS_OK;
+}

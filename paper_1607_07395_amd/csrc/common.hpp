@@ -1,0 +1,169 @@
+// Shared device-side definitions for the CABS library (gfx950 / CDNA4).
+//
+// * element types and conversions for the four compute precisions
+// * Philox-4x64-10 (Salmon, Moraes, Dror, Shaw, SC 2011) and the integer /
+//   unit-interval / normal maps used by every random draw of the method
+// * MFMA fragment helpers for 16x16 output tiles with FP64, FP32, BF16 and
+//   FP16 operands (FP32 accumulation for the 16-bit types)
+// * wave64 reductions
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cabs {
+
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(4))) double f64x4;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(8))) _Float16 f16x8;
+
+typedef __bf16 bf16;
+typedef _Float16 f16;
+
+constexpr int WAVE = 64;
+
+// ---------------------------------------------------------------------------
+// Conversions
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ double to_f64(T v) { return (double)v; }
+template <> __device__ __forceinline__ double to_f64<bf16>(bf16 v) { return (double)(float)v; }
+template <> __device__ __forceinline__ double to_f64<f16>(f16 v) { return (double)(float)v; }
+
+template <typename T> __device__ __forceinline__ float to_f32(T v) { return (float)v; }
+
+template <typename T> __device__ __forceinline__ T from_f64(double v) { return (T)v; }
+template <> __device__ __forceinline__ bf16 from_f64<bf16>(double v) { return (bf16)(float)v; }
+template <> __device__ __forceinline__ f16 from_f64<f16>(double v) { return (f16)(float)v; }
+
+template <typename T> __device__ __forceinline__ T from_f32(float v) { return (T)v; }
+
+// Accumulator type of a compute precision: FP64 for FP64, FP32 otherwise.
+template <typename T> struct Acc { typedef float type; };
+template <> struct Acc<double> { typedef double type; };
+
+// ---------------------------------------------------------------------------
+// Philox-4x64-10
+// ---------------------------------------------------------------------------
+struct u64x4 { uint64_t v[4]; };
+
+__device__ __forceinline__ void mulhilo64(uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo) {
+  lo = a * b;
+  hi = __umul64hi(a, b);
+}
+
+__device__ __forceinline__ u64x4 philox4x64(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                            uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint64_t hi0, lo0, hi1, lo1;
+    mulhilo64(M0, c0, hi0, lo0);
+    mulhilo64(M1, c2, hi1, lo1);
+    uint64_t n0 = hi1 ^ c1 ^ k0;
+    uint64_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += W0; k1 += W1;
+  }
+  u64x4 o; o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
+  return o;
+}
+
+// floor(x * bound / 2^64): an integer in [0, bound).
+__device__ __forceinline__ uint64_t mulhi_bound(uint64_t x, uint64_t bound) { return __umul64hi(x, bound); }
+
+// (0, 1] and [0, 1) from the top 53 bits.
+__device__ __forceinline__ double unit_open0(uint64_t x) { return ((double)(x >> 11) + 1.0) * 0x1.0p-53; }
+__device__ __forceinline__ double unit_open1(uint64_t x) { return (double)(x >> 11) * 0x1.0p-53; }
+
+enum : uint64_t {
+  STREAM_PILOT_ROWS = 0, STREAM_PILOT_COLS = 1, STREAM_INIT_ROWS = 2, STREAM_INIT_COLS = 3,
+  STREAM_ERROR = 4, STREAM_NOISE = 5
+};
+
+// Standard normal at counter (i, j, 5, 0), key (seed, 0), by Box-Muller.
+__device__ __forceinline__ double noise_f64(uint64_t seed, uint64_t i, uint64_t j) {
+  u64x4 w = philox4x64(i, j, STREAM_NOISE, 0, seed, 0);
+  double u1 = unit_open0(w.v[0]);
+  double u2 = unit_open1(w.v[1]);
+  return sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+}
+__device__ __forceinline__ float noise_f32(uint64_t seed, uint64_t i, uint64_t j) {
+  u64x4 w = philox4x64(i, j, STREAM_NOISE, 0, seed, 0);
+  float u1 = (float)unit_open0(w.v[0]);
+  float u2 = (float)unit_open1(w.v[1]);
+  return sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
+}
+
+// ---------------------------------------------------------------------------
+// Wave reductions (wave64)
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+  return v;
+}
+template <typename T> __device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) { T o = __shfl_xor(v, off, WAVE); v = o > v ? o : v; }
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// MFMA fragments.  A 16x16 output tile D = A_tile (16 x K) * B_tile (K x 16)
+// is built from steps of KSTEP along K.  Lane l owns row (l % 16) of A and
+// column (l % 16) of B, and the KPL = KSTEP/4 contraction indices of group
+// g = l / 16.  Because the contraction only sums over k, any assignment of k
+// values to (group, slot) works as long as A and B use the same one; every
+// kernel here hands lane l the KPL consecutive elements starting at 4-group
+// offset g * KPL of the current K block.  The output holds 4 accumulators per
+// lane, in column l % 16; their rows differ by instruction: the FP32-output
+// instructions give rows 4 * (l / 16) + i, the FP64 one gives rows l / 16 + 4 i
+// (out_row below).
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ int out_row(int g, int i) { return 4 * g + i; }
+template <> __device__ __forceinline__ int out_row<double>(int g, int i) { return g + 4 * i; }
+
+template <typename T> struct Mfma;
+
+template <> struct Mfma<double> {
+  static constexpr int KPL = 1;             // elements per lane per step
+  typedef double frag;
+  typedef f64x4 acc;
+  __device__ static __forceinline__ acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
+  __device__ static __forceinline__ acc mma(frag a, frag b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<float> {
+  static constexpr int KPL = 1;
+  typedef float frag;
+  typedef f32x4 acc;
+  __device__ static __forceinline__ acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static __forceinline__ acc mma(frag a, frag b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<bf16> {
+  static constexpr int KPL = 8;
+  typedef bf16x8 frag;
+  typedef f32x4 acc;
+  __device__ static __forceinline__ acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static __forceinline__ acc mma(frag a, frag b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<f16> {
+  static constexpr int KPL = 8;
+  typedef f16x8 frag;
+  typedef f32x4 acc;
+  __device__ static __forceinline__ acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
+  __device__ static __forceinline__ acc mma(frag a, frag b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+__host__ __device__ __forceinline__ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace cabs

@@ -1,0 +1,283 @@
+// Pilot / follow-up sampling and entry evaluation (Algorithm 2, steps 1 and 3).
+//
+// * sample_floyd: k distinct uniform indices by Floyd's algorithm on
+//   Philox-4x64-10, sorted ascending (one workgroup).
+// * eval (LOWRANK, RBF): the sampled columns C = A(:, J) or rows R^T =
+//   A(I, :)^T of a generator-defined matrix.  Both are one MFMA contraction
+//   with an epilogue: X (m x r) diag(s) Y[J]^T plus the counter-based noise for
+//   the low-rank source; |x|^2 + |y|^2 - 2 x.y then exp(-d/(2 sigma^2)) for the
+//   RBF source.  The factor / point tables are read once per 64-row tile.
+// * dense gathers: C = A(:, J) row by row (coalesced output rows); R^T =
+//   A(I, :)^T through a 64 x 64 LDS tile so that both the row reads of A and
+//   the writes of R^T are coalesced.
+#include "common.hpp"
+#include "gemm_core.hpp"
+#include "kernels.hpp"
+
+namespace cabs {
+
+// ---------------------------------------------------------------------------
+// Floyd sampling
+// ---------------------------------------------------------------------------
+constexpr int SAMPLE_MAX_K = 4096;
+
+__global__ __launch_bounds__(256) void sample_floyd_kernel(int64_t n, int k, uint64_t seed, uint64_t stream_id,
+                                                           int64_t* __restrict__ out) {
+  __shared__ int64_t draw[SAMPLE_MAX_K];
+  __shared__ int64_t keys[SAMPLE_MAX_K];
+  const int tid = threadIdx.x;
+  // 1. Every draw v_t = uniform in [0, n - k + t] is independent of the others.
+  for (int t = tid; t < k; t += blockDim.x) {
+    uint64_t j = (uint64_t)(n - k + t);
+    u64x4 w = philox4x64((uint64_t)t, 0, stream_id, 0, seed, 0);
+    draw[t] = (int64_t)mulhi_bound(w.v[0], j + 1);
+  }
+  __syncthreads();
+  // 2. The membership test is sequential in t.  Wave 0 runs it; slot t of the
+  // chosen list lives in lane t % 64 and is only ever read by that lane, so no
+  // cross-lane LDS ordering is needed.
+  if (tid < 64) {
+    for (int t = 0; t < k; ++t) {
+      const int64_t cand = draw[t];
+      bool hit = false;
+      for (int s = tid; s < t; s += 64) hit |= (keys[s] == cand);
+      const bool any = __ballot(hit) != 0;
+      if (tid == (t & 63)) keys[t] = any ? (n - k + t) : cand;
+    }
+  }
+  __syncthreads();
+  // 3. Bitonic sort of keys[0..P) (P = next power of two >= k, padded with +inf).
+  int P = 1;
+  while (P < k) P <<= 1;
+  for (int t = k + tid; t < P; t += blockDim.x) keys[t] = INT64_MAX;
+  __syncthreads();
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = tid; t < P; t += blockDim.x) {
+        int partner = t ^ stride;
+        if (partner > t) {
+          bool up = (t & size) == 0;
+          int64_t a = keys[t], b = keys[partner];
+          if ((a > b) == up) { keys[t] = b; keys[partner] = a; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int t = tid; t < k; t += blockDim.x) out[t] = keys[t];
+}
+
+hipError_t launch_sample(int64_t n, int k, uint64_t seed, int stream_id, int64_t* out, hipStream_t st) {
+  if (k <= 0 || k > SAMPLE_MAX_K || k > n) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sample_floyd_kernel, dim3(1), dim3(256), 0, st, n, k, seed, (uint64_t)stream_id, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Generator evaluation through the MFMA tile core
+// ---------------------------------------------------------------------------
+struct EvalArgs {
+  const void* X;  int64_t ldx; int64_t M;   // rows of the output (table of the un-sampled side)
+  const void* Y;  int64_t ldy;              // table of the sampled side, gathered through idx
+  const int64_t* idx; int64_t N;            // sampled indices (N = k)
+  const void* ys;                           // per-k scale (low-rank s) or null
+  int K;                                    // r or d
+  void* out; int64_t ldo;
+  int transposed;                           // 1: output row p is A column p (R^T)
+  double noise_std; uint64_t noise_seed;
+  double inv2s2;                            // 1 / (2 sigma^2)
+};
+
+constexpr int EVAL_NT = 8;
+
+template <typename TIn, typename TC, int SRC>
+__global__ __launch_bounds__(256) void eval_kernel(EvalArgs a) {
+  typedef typename Mfma<TC>::acc AccV;
+  typedef typename NormT<TIn>::type NrmT;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  const int64_t col0 = (int64_t)blockIdx.y * EVAL_NT * 16;
+  if (row0 >= a.M) return;
+  AccV acc[EVAL_NT];
+  NrmT xsq, ysq[EVAL_NT];
+  gemm_tile<TIn, TC, EVAL_NT, SRC == SRC_RBF>((const TIn*)a.X, a.ldx, a.M, row0, (const TIn*)a.Y, a.ldy, a.idx, a.N,
+                                              col0, (const TIn*)a.ys, a.K, acc, xsq, ysq);
+  const int g = lane >> 4;
+  const int c16 = lane & 15;
+  TC* out = (TC*)a.out;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int rr = out_row<TC>(g, i);
+    const int64_t row = row0 + rr;
+    NrmT xr = 0;
+    if (SRC == SRC_RBF) xr = __shfl(xsq, rr, 64);
+#pragma unroll
+    for (int t = 0; t < EVAL_NT; ++t) {
+      const int64_t col = col0 + t * 16 + c16;
+      if (row < a.M && col < a.N) {
+        typedef typename Acc<TC>::type AT;
+        AT v = (AT)acc[t][i];
+        if (SRC == SRC_LOWRANK) {
+          if (a.noise_std != 0.0) {
+            const int64_t sidx = a.idx[col];
+            const uint64_t ai = a.transposed ? (uint64_t)sidx : (uint64_t)row;
+            const uint64_t aj = a.transposed ? (uint64_t)row : (uint64_t)sidx;
+            if (sizeof(AT) == 8) v += (AT)(a.noise_std * noise_f64(a.noise_seed, ai, aj));
+            else v += (AT)((float)a.noise_std * noise_f32(a.noise_seed, ai, aj));
+          }
+        } else {
+          AT d2 = (AT)xr + (AT)ysq[t] - (AT)2 * v;
+          d2 = d2 > (AT)0 ? d2 : (AT)0;
+          if (sizeof(AT) == 8) v = (AT)exp(-(double)d2 * a.inv2s2);
+          else v = (AT)__expf(-(float)d2 * (float)a.inv2s2);
+        }
+        out[row * a.ldo + col] = from_f64<TC>((double)v);
+      }
+    }
+  }
+}
+
+template <typename TIn, typename TC>
+static hipError_t eval_dispatch_src(int src, const EvalArgs& a, dim3 grid, hipStream_t st) {
+  if (src == SRC_LOWRANK)
+    hipLaunchKernelGGL((eval_kernel<TIn, TC, SRC_LOWRANK>), grid, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((eval_kernel<TIn, TC, SRC_RBF>), grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Dense gathers
+// ---------------------------------------------------------------------------
+template <typename TIn, typename TC>
+__global__ __launch_bounds__(256) void dense_cols_kernel(const TIn* __restrict__ A, int64_t lda, int64_t m,
+                                                         const int64_t* __restrict__ idx, int k, TC* __restrict__ out) {
+  // 8 output rows per block; consecutive threads write consecutive columns of a row.
+  const int64_t p0 = (int64_t)blockIdx.x * 8;
+  for (int rr = 0; rr < 8; ++rr) {
+    const int64_t p = p0 + rr;
+    if (p >= m) break;
+    const TIn* arow = A + p * lda;
+    for (int a = threadIdx.x; a < k; a += blockDim.x) out[p * k + a] = from_f64<TC>((double)arow[idx[a]]);
+  }
+}
+
+template <typename TIn, typename TC>
+__global__ __launch_bounds__(256) void dense_rows_t_kernel(const TIn* __restrict__ A, int64_t lda, int64_t n,
+                                                           const int64_t* __restrict__ idx, int k,
+                                                           TC* __restrict__ out) {
+  // Tile: 64 columns of A (output rows p) x 64 sampled rows (output columns a).
+  __shared__ double tile[64][65];
+  const int64_t p0 = (int64_t)blockIdx.x * 64;
+  const int a0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63;
+  const int ty = threadIdx.x >> 6;  // 0..3
+  for (int al = ty; al < 64; al += 4) {
+    const int a = a0 + al;
+    const int64_t p = p0 + tx;
+    double v = 0.0;
+    if (a < k && p < n) v = (double)A[idx[a] * lda + p];  // coalesced along p
+    tile[al][tx] = v;
+  }
+  __syncthreads();
+  for (int pl = ty; pl < 64; pl += 4) {
+    const int64_t p = p0 + pl;
+    const int a = a0 + tx;
+    if (p < n && a < k) out[p * k + a] = from_f64<TC>(tile[tx][pl]);  // coalesced along a
+  }
+}
+
+template <typename TIn, typename TC>
+static hipError_t dense_dispatch(const MatView& mv, bool rows_t, const int64_t* idx, int k, void* out,
+                                 hipStream_t st) {
+  const TIn* A = (const TIn*)mv.a;
+  if (!rows_t) {
+    hipLaunchKernelGGL((dense_cols_kernel<TIn, TC>), dim3((unsigned)ceil_div(mv.m, 8)), dim3(256), 0, st, A, mv.lda,
+                       mv.m, idx, k, (TC*)out);
+  } else {
+    dim3 grid((unsigned)ceil_div(mv.n, 64), (unsigned)ceil_div(k, 64));
+    hipLaunchKernelGGL((dense_rows_t_kernel<TIn, TC>), grid, dim3(256), 0, st, A, mv.lda, mv.n, idx, k, (TC*)out);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_eval(const MatView& mv, bool rows_t, const int64_t* idx, int k, int compute, void* out,
+                       hipStream_t st) {
+  if (k <= 0) return hipErrorInvalidValue;
+  if (mv.kind == SRC_DENSE) {
+    if (mv.storage == P_F64) {
+      if (compute == P_F64) return dense_dispatch<double, double>(mv, rows_t, idx, k, out, st);
+      return hipErrorInvalidValue;
+    }
+    switch (compute) {
+      case P_F32: return dense_dispatch<float, float>(mv, rows_t, idx, k, out, st);
+      case P_BF16: return dense_dispatch<float, bf16>(mv, rows_t, idx, k, out, st);
+      case P_F16: return dense_dispatch<float, f16>(mv, rows_t, idx, k, out, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  EvalArgs a{};
+  const int64_t M = rows_t ? mv.n : mv.m;
+  if (mv.kind == SRC_LOWRANK) {
+    a.X = rows_t ? mv.qf : mv.pf;
+    a.Y = rows_t ? mv.pf : mv.qf;
+    a.ldx = a.ldy = mv.r;
+    a.K = mv.r;
+    a.ys = mv.s;
+  } else {
+    a.X = rows_t ? mv.y : mv.x;
+    a.Y = rows_t ? mv.x : mv.y;
+    a.ldx = a.ldy = mv.d;
+    a.K = mv.d;
+    a.ys = nullptr;
+    a.inv2s2 = 1.0 / (2.0 * mv.sigma * mv.sigma);
+  }
+  a.M = M;
+  a.idx = idx;
+  a.N = k;
+  a.out = out;
+  a.ldo = k;
+  a.transposed = rows_t ? 1 : 0;
+  a.noise_std = mv.noise_std;
+  a.noise_seed = mv.noise_seed;
+  dim3 grid((unsigned)ceil_div(M, 64), (unsigned)ceil_div(k, EVAL_NT * 16));
+  if (mv.storage == P_F64) {
+    if (compute == P_F64) return eval_dispatch_src<double, double>(mv.kind, a, grid, st);
+    return hipErrorInvalidValue;
+  }
+  switch (compute) {
+    case P_F32: return eval_dispatch_src<float, float>(mv.kind, a, grid, st);
+    case P_BF16: return eval_dispatch_src<float, bf16>(mv.kind, a, grid, st);
+    case P_F16: return eval_dispatch_src<float, f16>(mv.kind, a, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// W = C(I, :) in FP64
+// ---------------------------------------------------------------------------
+template <typename TC>
+__global__ __launch_bounds__(256) void gather_rows_f64_kernel(const TC* __restrict__ src, int64_t ld,
+                                                              const int64_t* __restrict__ idx, int k, int ncols,
+                                                              double* __restrict__ out) {
+  const int i = blockIdx.x;
+  if (i >= k) return;
+  const TC* row = src + idx[i] * ld;
+  for (int c = threadIdx.x; c < ncols; c += blockDim.x) out[(int64_t)i * ncols + c] = to_f64(row[c]);
+}
+
+hipError_t launch_gather_rows_f64(const void* src, int compute, int64_t ld, const int64_t* idx, int k, int ncols,
+                                  double* out, hipStream_t st) {
+  dim3 grid(k), block(256);
+  switch (compute) {
+    case P_F64: hipLaunchKernelGGL(gather_rows_f64_kernel<double>, grid, block, 0, st, (const double*)src, ld, idx, k, ncols, out); break;
+    case P_F32: hipLaunchKernelGGL(gather_rows_f64_kernel<float>, grid, block, 0, st, (const float*)src, ld, idx, k, ncols, out); break;
+    case P_BF16: hipLaunchKernelGGL(gather_rows_f64_kernel<bf16>, grid, block, 0, st, (const bf16*)src, ld, idx, k, ncols, out); break;
+    case P_F16: hipLaunchKernelGGL(gather_rows_f64_kernel<f16>, grid, block, 0, st, (const f16*)src, ld, idx, k, ncols, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace cabs

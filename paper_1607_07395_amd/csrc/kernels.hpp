@@ -1,0 +1,85 @@
+// Host-side launchers of the CABS device kernels (internal to libcabs).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cabs {
+
+enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_F16 = 3 };
+enum Src { SRC_DENSE = 0, SRC_LOWRANK = 1, SRC_RBF = 2 };
+
+inline size_t prec_bytes(int p) { return p == P_F64 ? 8 : p == P_F32 ? 4 : 2; }
+
+// Matrix descriptor as the kernels see it.
+struct MatView {
+  int kind;
+  int storage;
+  int64_t m, n;
+  const void* a;
+  int64_t lda;
+  const void* pf;
+  const void* qf;
+  const void* s;
+  int r;
+  double noise_std;
+  uint64_t noise_seed;
+  const void* x;
+  const void* y;
+  int d;
+  double sigma;
+};
+
+// --- sampling / entry evaluation (eval.hip) ---
+hipError_t launch_sample(int64_t n, int k, uint64_t seed, int stream_id, int64_t* out, hipStream_t st);
+// rows_t = false: out (m x k) = A(:, idx); rows_t = true: out (n x k) = A(idx, :)^T.
+hipError_t launch_eval(const MatView& mv, bool rows_t, const int64_t* idx, int k, int compute, void* out,
+                       hipStream_t st);
+// out (k x ncols, FP64) = src[idx[i], :] for a compute-precision row-major src with row stride ld.
+hipError_t launch_gather_rows_f64(const void* src, int compute, int64_t ld, const int64_t* idx, int k, int ncols,
+                                  double* out, hipStream_t st);
+
+// --- FP64 small dense algebra (svd.hip, small.hip) ---
+size_t svd_ws_bytes(int batch, int rows, int cols);
+// Batched one-sided Jacobi SVD; A_b rows x cols row-major, strides in elements between batch items.
+hipError_t launch_svd(int batch, int rows, int cols, const double* A, int64_t strideA, double* U, int64_t strideU,
+                      double* S, int64_t strideS, double* V, int64_t strideV, void* ws, hipStream_t st);
+
+// C (M x N) = alpha * op(A) diag(dl) ... : general small FP64 product
+//   C = diag(dl) * op(A) * diag(dm) * op(B) * diag(dr)   (any diag pointer may be null)
+// op(A) is M x K: A row-major (lda) or its transpose; same for B (K x N).
+hipError_t launch_small_gemm(int M, int N, int K, const double* A, int lda, bool transA, const double* B, int ldb,
+                             bool transB, const double* dl, const double* dm, const double* dr, double* C, int ldc,
+                             hipStream_t st);
+
+// --- tall-skinny products, Grams, norms (tsgemm.hip) ---
+// Y (M x N, compute) = X (M x K, compute) * B (K x N, FP64); B is converted to the compute
+// precision into bt_ws (N x K).  colsq (N, FP64) receives column sums of squares of Y when
+// non-null (partials in part_ws: ceil(M/64) x N doubles); rowsq (M, FP64) row sums of squares.
+// Y may be null (norms only).
+size_t tsgemm_ws_bytes(int64_t M, int K, int N, int compute);
+hipError_t launch_tsgemm(int64_t M, int K, int N, int compute, const void* X, const double* B, void* Y,
+                         double* colsq, double* rowsq, void* ws, hipStream_t st);
+// G (K x K, FP64) = X^T X for X (M x K, compute precision); deterministic two-stage reduction.
+size_t gram_ws_bytes(int64_t M, int K);
+hipError_t launch_gram(int64_t M, int K, int compute, const void* X, double* G, void* ws, hipStream_t st);
+
+// --- weighted k-means and snapping (kmeans.hip) ---
+size_t kmeans_ws_bytes(int64_t rows, int dim, int k, int compute);
+struct KMeansOut {
+  double* Z;         // k x dim FP64 (in: Z0 if z0 == nullptr)
+  int32_t* labels;   // rows (may be null)
+  double* obj2;      // {objective at Z0, objective at final Z} (may be null)
+  double* tmax;      // largest cluster of the final assignment (may be null)
+  double* gap;       // smallest best/second-best gap of the final assignment (may be null)
+  int64_t* snap;     // k snapped rows, ascending (may be null)
+};
+hipError_t launch_kmeans(int64_t rows, int dim, int k, int compute, const void* P, const double* w,
+                         const double* Z0, int iters, const KMeansOut& out, void* ws, hipStream_t st);
+
+// --- error metric (error.hip) ---
+size_t error_ws_bytes(const MatView& mv, int k2c, int k2r, int compute, int64_t n_samples);
+hipError_t launch_error(const MatView& mv, int k2c, int k2r, int compute, const void* C, const double* Umid,
+                        const void* Rt, int64_t n_samples, uint64_t seed, void* ws, double* out3, hipStream_t st);
+
+}  // namespace cabs

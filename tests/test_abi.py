@@ -1,0 +1,91 @@
+"""CPU checks of the C ABI: the library loads and exports every declared symbol;
+argument validation and workspace planning work without a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cabs.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(cabs_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("cabs_sketch", "cabs_error", "cabs_workspace_bytes", "cabs_last_error", "cabs_server_create",
+                 "cabs_submit", "cabs_poll", "cabs_cancel", "cabs_server_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1607_07395_amd import _ffi as F
+    lib = F.lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert sorted(F.exported_symbols()) == _declared()
+    assert lib.cabs_version().startswith(b"libcabs")
+
+
+def _desc(m=1000, n=800, r=20):
+    from paper_1607_07395_amd import _ffi as F
+    d = F.CabsMatrix()
+    d.kind, d.storage, d.m, d.n = F.SRC_LOWRANK, F.F32, m, n
+    d.pf = d.qf = d.s = 0x1000   # never dereferenced by the planner
+    d.r = r
+    d.noise_std = 1e-3
+    return d
+
+
+def test_workspace_planning_and_validation_on_cpu():
+    from paper_1607_07395_amd import _ffi as F
+    from paper_1607_07395_amd.api import make_params
+    lib = F.lib()
+    d = _desc()
+    p = make_params(20, 20, 20, 20, compute="f32")
+    ws = lib.cabs_workspace_bytes(C.byref(d), C.byref(p))
+    assert ws > 0
+    # linear in m + n: doubling both roughly doubles the workspace
+    d2 = _desc(2000, 1600)
+    ws2 = lib.cabs_workspace_bytes(C.byref(d2), C.byref(p))
+    assert 1.6 * ws < ws2 < 2.4 * ws
+    # invalid: k larger than m, FP64 compute on FP32 tables, unknown kind
+    bad = make_params(2000, 20, 20, 20)
+    assert lib.cabs_workspace_bytes(C.byref(d), C.byref(bad)) == 0
+    assert lib.cabs_workspace_bytes(C.byref(d), C.byref(make_params(20, 20, 20, 20, compute="f64"))) == 0
+    d.kind = 7
+    assert lib.cabs_workspace_bytes(C.byref(d), C.byref(p)) == 0
+    assert b"unknown source kind" in lib.cabs_last_error()
+
+
+def test_entry_points_reject_bad_arguments_without_launching():
+    from paper_1607_07395_amd import _ffi as F
+    from paper_1607_07395_amd.api import make_params
+    lib = F.lib()
+    d = _desc()
+    p = make_params(20, 20, 20, 20)
+    res = F.CabsResult()  # all null
+    assert lib.cabs_sketch(C.byref(d), C.byref(p), None, 0, C.byref(res), None) == F.EINVAL
+    assert lib.cabs_sample(10, 11, 0, 0, C.c_void_p(0x1000), None) == F.EINVAL
+    assert lib.cabs_sample(10, 3, 0, 0, None, None) == F.EINVAL
+    assert lib.cabs_svd(1, 2000, 3, None, None, None, None, None, 0, None) == F.EINVAL
+    assert lib.cabs_kmeans(10, 3, 11, F.F32, None, None, None, 1, None, None, None, None, None, 0, None) == F.EINVAL
+    assert lib.cabs_svd_workspace_bytes(1, 50, 50) > 0
+    assert lib.cabs_kmeans_workspace_bytes(10_000, 50, 50, F.F32) > 0
+    # workspace too small -> ENOMEM before anything is launched
+    res.idx_r = res.idx_c = res.C = res.Rt = res.Umid = 0x1000
+    assert lib.cabs_sketch(C.byref(d), C.byref(p), C.c_void_p(0x100000), 1024, C.byref(res), None) == F.ENOMEM
+    assert b"workspace too small" in lib.cabs_last_error()
+    # unaligned workspace
+    assert lib.cabs_sketch(C.byref(d), C.byref(p), C.c_void_p(0x100001), 1 << 40, C.byref(res), None) == F.EINVAL
+
+
+def test_server_rejects_invalid_creation():
+    from paper_1607_07395_amd import _ffi as F
+    lib = F.lib()
+    assert not lib.cabs_server_create(0, 1 << 20, 0)
+    assert not lib.cabs_server_create(0, 16, 4)

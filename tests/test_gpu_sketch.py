@@ -1,0 +1,172 @@
+"""End-to-end GPU parity of cabs_sketch / cabs_error against the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import cabs as oc
+from oracle import philox
+from oracle.matrices import Matrix
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1607_07395_amd import api as a
+    return a
+
+
+def _run(api, spec, prm_kw, compute="f64", storage=None):
+    storage = storage or ("f64" if compute == "f64" else "f32")
+    mat = api.DeviceMatrix(spec, storage=storage)
+    prm = api.make_params(compute=compute, **prm_kw)
+    res = api.sketch(mat, prm)
+    torch.cuda.synchronize()
+    return mat, prm, res
+
+
+def _oracle_params(kw):
+    kw = dict(kw)
+    return oc.Params(kw.pop("k1_rows"), kw.pop("k1_cols"), kw.pop("k2_rows"), kw.pop("k2_cols"),
+                     kmeans_iters=kw.pop("kmeans_iters", 5), weight_kind=kw.pop("weight", "const"),
+                     weight_param=kw.pop("weight_param", 0.0), sketch_kind=kw.pop("sketch", "stabilized"),
+                     orthogonalize=kw.pop("orthogonalize", True), pinv_rtol=kw.pop("pinv_rtol", 0.0),
+                     seed=kw.pop("seed", 0), factors=kw.pop("factors", False))
+
+
+def _approx_at(C, Umid, Rt, i, j):
+    return np.einsum("tk,tk->t", (C[i] @ Umid), Rt[j])
+
+
+def _compare_f64(api, spec, kw, tol=1e-10):
+    mat, prm, res = _run(api, spec, kw, "f64")
+    ref = oc.cabs(spec, _oracle_params(kw))
+    d = res.diagnostics()
+    assert d["status"] == 0
+    assert np.array_equal(res.pilot_r.cpu().numpy(), ref.pilot_rows)
+    assert np.array_equal(res.pilot_c.cpu().numpy(), ref.pilot_cols)
+    assert np.array_equal(res.idx_r.cpu().numpy(), ref.idx_r), (d["gap_r"], ref.km_r.min_gap)
+    assert np.array_equal(res.idx_c.cpu().numpy(), ref.idx_c), (d["gap_c"], ref.km_c.min_gap)
+    C, Rt, Umid = res.C.cpu().numpy(), res.Rt.cpu().numpy(), res.Umid.cpu().numpy()
+    amax = max(np.abs(ref.C).max(), np.abs(ref.Rt).max())
+    assert np.abs(C - ref.C).max() <= 1e-13 * amax * 10
+    assert np.abs(Rt - ref.Rt).max() <= 1e-13 * amax * 10
+    # the CUR product at sampled entries
+    i, j = philox.error_sample_indices(spec.m, spec.n, 20000, seed=99)
+    a_gpu = _approx_at(C, Umid, Rt, i, j)
+    a_ref = _approx_at(ref.C, ref.Umid, ref.Rt, i, j)
+    scale = np.sqrt(np.mean(Matrix(spec).entries(i, j) ** 2))
+    assert np.abs(a_gpu - a_ref).max() <= tol * scale
+    # diagnostics
+    assert d["rank_pilot"] == int(ref.pilot.keep.sum()) and d["rank_final"] == int(ref.final.keep.sum())
+    assert d["entries"] == ref.entries_touched
+    assert d["enc_r_pilot"] == pytest.approx(ref.km_r.e_initial, rel=1e-9)
+    assert d["enc_r_final"] == pytest.approx(ref.km_r.e_final, rel=1e-9)
+    assert d["enc_c_pilot"] == pytest.approx(ref.km_c.e_initial, rel=1e-9)
+    assert d["enc_c_final"] == pytest.approx(ref.km_c.e_final, rel=1e-9)
+    assert d["tmax_r"] == ref.km_r.max_cluster and d["tmax_c"] == ref.km_c.max_cluster
+    assert d["sigma1_pilot"] == pytest.approx(ref.pilot.sw[0], rel=1e-12)
+    return mat, prm, res, ref
+
+
+@pytest.mark.parametrize("scale,k,seed", [(0.1, 12, 0), (0.2, 20, 3), (0.137, 17, 5)])
+def test_sketch_f64_rbf_small(api, scale, k, seed):
+    spec, _ = workloads.config("rbf2000", scale)
+    _compare_f64(api, spec, dict(k1_rows=k, k1_cols=k, k2_rows=k, k2_cols=k, seed=seed))
+
+
+def test_sketch_f64_rbf_full_config(api):
+    """RBF 2000 x 2000, d = 10, 20 clusters, k = 50, c = 5, FP64, exact error."""
+    spec, c = workloads.config("rbf2000")
+    kw = dict(k1_rows=50, k1_cols=50, k2_rows=50, k2_cols=50, kmeans_iters=5, seed=0)
+    mat, prm, res, ref = _compare_f64(api, spec, kw)
+    e = api.error(mat, prm, res, 0).cpu().numpy()
+    want = oc.rel_error_exact(Matrix(spec), ref.C, ref.Umid, ref.Rt)
+    assert e[2] == pytest.approx(want, rel=1e-10)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(k1_rows=9, k1_cols=7, k2_rows=6, k2_cols=8, seed=2),
+    dict(k1_rows=10, k1_cols=10, k2_rows=10, k2_cols=10, orthogonalize=False, seed=1),
+    dict(k1_rows=10, k1_cols=10, k2_rows=10, k2_cols=10, sketch="pseudo_skeleton", seed=4),
+    dict(k1_rows=12, k1_cols=12, k2_rows=12, k2_cols=12, weight="pow", weight_param=2.0, seed=6),
+    dict(k1_rows=8, k1_cols=8, k2_rows=8, k2_cols=8, kmeans_iters=0, seed=7),
+])
+def test_sketch_f64_options(api, kw):
+    spec = workloads.lowrank_noise(700, 400, 15, seed=1, noise_std=1e-2, s_kind="scaled")
+    _compare_f64(api, spec, kw)
+
+
+def test_sketch_dense_source_and_exact_recovery(api):
+    spec = workloads.exact_rank(300, 220, 6, seed=4)
+    kw = dict(k1_rows=6, k1_cols=6, k2_rows=6, k2_cols=6, sketch="pseudo_skeleton", seed=3)
+    mat, prm, res, ref = _compare_f64(api, spec, kw)
+    e = api.error(mat, prm, res, 0).cpu().numpy()
+    assert e[2] < 1e-11
+
+
+def test_factor_form_f64(api):
+    spec, _ = workloads.config("rbf2000", 0.15)
+    kw = dict(k1_rows=14, k1_cols=14, k2_rows=14, k2_cols=14, factors=True, seed=8)
+    mat, prm, res, ref = _compare_f64(api, spec, kw)
+    u, s, v = ref.factors
+    S = res.S.cpu().numpy()
+    kept = int(ref.final.keep.sum())
+    assert np.allclose(S[:kept], s[:kept], rtol=0, atol=1e-10 * s[0])
+    Uf, Vf = res.Uf.cpu().numpy(), res.Vf.cpu().numpy()
+    assert np.abs(Uf[:, :kept].T @ Uf[:, :kept] - np.eye(kept)).max() < 1e-9
+    gaps = np.abs(np.diff(s[:kept]))
+    for j in range(kept):
+        g = min(gaps[j - 1] if j > 0 else np.inf, gaps[j] if j < kept - 1 else np.inf)
+        if g > 1e-3 * s[0]:
+            assert np.abs(Uf[:, j] - u[:, j]).max() < 1e-8, j
+            assert np.abs(Vf[:, j] - v[:, j]).max() < 1e-8, j
+
+
+def test_error_sampled_matches_oracle(api):
+    spec = workloads.lowrank_noise(900, 500, 20, seed=2, noise_std=1e-2, s_kind="scaled")
+    kw = dict(k1_rows=15, k1_cols=15, k2_rows=15, k2_cols=15, seed=1)
+    mat, prm, res, ref = _compare_f64(api, spec, kw)
+    e = api.error(mat, prm, res, 100_000, seed=5).cpu().numpy()
+    rel, num, den = oc.rel_error_sampled(Matrix(spec), ref.C, ref.Umid, ref.Rt, 100_000, 5)
+    assert e[0] == pytest.approx(num, rel=1e-8) and e[1] == pytest.approx(den, rel=1e-12)
+    assert e[2] == pytest.approx(rel, rel=1e-8)
+
+
+def test_zero_matrix_reports_rank_loss(api):
+    spec = workloads.dense_matrix(np.zeros((100, 80)))
+    mat, prm, res = _run(api, spec, dict(k1_rows=5, k1_cols=5, k2_rows=5, k2_cols=5))
+    d = res.diagnostics()
+    assert d["status"] == -3 and d["rank_pilot"] == 0
+    assert np.all(np.isfinite(res.Umid.cpu().numpy()))
+
+
+def test_determinism_bitwise(api):
+    spec, _ = workloads.config("rbf2000", 0.1)
+    kw = dict(k1_rows=12, k1_cols=12, k2_rows=12, k2_cols=12, seed=0)
+    _, _, r1 = _run(api, spec, kw, "f32")
+    _, _, r2 = _run(api, spec, kw, "f32")
+    for a, b in [(r1.C, r2.C), (r1.Rt, r2.Rt), (r1.Umid, r2.Umid), (r1.idx_r, r2.idx_r), (r1.diag, r2.diag)]:
+        assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("compute,ratio", [("f32", 1.01), ("bf16", 1.5), ("f16", 1.2)])
+def test_reduced_precision_against_oracle(api, compute, ratio):
+    """Pilot indices are bit-exact in every precision; the follow-up sketch error
+    stays within the stated factor of the oracle's error."""
+    spec, _ = workloads.config("lowrank1e5s", 0.03)
+    k = 30
+    kw = dict(k1_rows=k, k1_cols=k, k2_rows=k, k2_cols=k, seed=3)
+    mat, prm, res = _run(api, spec, kw, compute)
+    ref = oc.cabs(spec, _oracle_params(kw))
+    assert np.array_equal(res.pilot_r.cpu().numpy(), ref.pilot_rows)
+    assert np.array_equal(res.pilot_c.cpu().numpy(), ref.pilot_cols)
+    e = api.error(mat, prm, res, 200_000, seed=1).cpu().numpy()[2]
+    want, _, _ = oc.rel_error_sampled(Matrix(spec), ref.C, ref.Umid, ref.Rt, 200_000, 1)
+    assert e <= want * ratio + 1e-3, (e, want)
+    agree = np.mean(np.isin(res.idx_r.cpu().numpy(), ref.idx_r))
+    assert agree >= 0.5

@@ -1,0 +1,157 @@
+"""GPU parity of the individual stages against the FP64 oracle (through the C ABI)."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import cabs as oc
+from oracle import philox
+from oracle.matrices import Matrix
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1607_07395_amd import api as a
+    return a
+
+
+def _np(t):
+    return t.detach().float().cpu().numpy() if t.dtype in (torch.bfloat16, torch.float16) else t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("n,k,seed,sid", [(1, 1, 0, 0), (10, 10, 3, 1), (1000, 50, 0, 0), (2000, 50, 7, 1),
+                                         (10**6, 500, 1, 0), (10**6, 4096, 2, 3), (97, 96, 5, 2),
+                                         (2**40, 33, 9, 4)])
+def test_sample_bit_exact(api, n, k, seed, sid):
+    got = api.sample(n, k, seed, sid).cpu().numpy()
+    want = philox.floyd_sample(n, k, seed, sid)
+    assert np.array_equal(got, want)
+
+
+def _idx(n, k, seed):
+    return np.sort(np.random.default_rng(seed).choice(n, size=k, replace=False)).astype(np.int64)
+
+
+SPECS = {
+    "lowrank": lambda: workloads.lowrank_noise(301, 257, 37, seed=3, noise_std=0.05),
+    "rbf": lambda: workloads.rbf_mixture(301, 10, 5, 2.0, 1.0, seed=4),
+    "rbf_rect": lambda: workloads.MatrixSpec(kind="rbf", m=300, n=170, x=np.random.default_rng(1).normal(size=(300, 7)),
+                                              y=np.random.default_rng(2).normal(size=(170, 7)), sigma=2.5),
+    "dense": lambda: workloads.dense_matrix(np.random.default_rng(5).normal(size=(290, 333))),
+}
+
+
+@pytest.mark.parametrize("kind", list(SPECS))
+@pytest.mark.parametrize("compute,tol", [("f64", 1e-12), ("f32", 2e-5), ("bf16", 3e-2), ("f16", 4e-3)])
+def test_eval_cols_and_rows(api, kind, compute, tol):
+    spec = SPECS[kind]()
+    storage = "f64" if compute == "f64" else "f32"
+    mat = api.DeviceMatrix(spec, storage=storage)
+    om = Matrix(spec)
+    for k, seed in [(1, 0), (17, 1), (130, 2)]:
+        ic = _idx(spec.n, min(k, spec.n), seed)
+        ir = _idx(spec.m, min(k, spec.m), seed + 10)
+        c = _np(api.eval_cols(mat, torch.from_numpy(ic).cuda(), compute))
+        rt = _np(api.eval_rows_t(mat, torch.from_numpy(ir).cuda(), compute))
+        cw, rw = om.cols(ic), om.rows_t(ir)
+        scale = max(np.abs(cw).max(), np.abs(rw).max(), 1e-30)
+        assert c.shape == cw.shape and rt.shape == rw.shape
+        assert np.abs(c - cw).max() <= tol * scale, (kind, compute, k)
+        assert np.abs(rt - rw).max() <= tol * scale, (kind, compute, k)
+
+
+@pytest.mark.parametrize("rows,cols,seed", [(1, 1, 0), (5, 3, 1), (3, 5, 2), (50, 50, 3), (64, 40, 4), (40, 64, 5),
+                                            (200, 200, 6), (129, 200, 7)])
+def test_svd_against_lapack(api, rows, cols, seed):
+    rng = np.random.default_rng(seed)
+    a = rng.normal(size=(rows, cols)) * np.exp(-0.2 * np.arange(cols))[None, :]
+    U, S, V = (x.cpu().numpy() for x in api.svd(torch.from_numpy(a).cuda()))
+    u0, s0, v0 = oc.svd_canonical(a)
+    p = min(rows, cols)
+    assert np.allclose(S, s0, rtol=0, atol=1e-12 * s0[0])
+    assert np.abs(U * S @ V.T - a).max() <= 1e-12 * s0[0] * max(rows, cols)
+    # Singular vectors of numerically zero singular values (below the truncation
+    # threshold the sketch uses) are noise on both sides; only the rest is checked.
+    kept = int((s0 > 10 * max(rows, cols) * 2.2e-16 * s0[0]).sum())
+    assert np.abs(U[:, :kept].T @ U[:, :kept] - np.eye(kept)).max() < 1e-11
+    assert np.abs(V[:, :kept].T @ V[:, :kept] - np.eye(kept)).max() < 1e-11
+    gaps = np.minimum(np.abs(np.diff(np.r_[np.inf, s0])), np.abs(np.diff(np.r_[s0, -np.inf])))
+    for j in range(kept):
+        tol = 1e-13 * s0[0] / max(gaps[j], 1e-300) * 10
+        if tol < 1e-4:
+            assert np.abs(U[:, j] - u0[:, j]).max() <= tol, j
+            assert np.abs(V[:, j] - v0[:, j]).max() <= tol, j
+
+
+def test_svd_batched_and_rank_deficient(api):
+    rng = np.random.default_rng(9)
+    g = rng.normal(size=(30, 4))
+    a = np.stack([g @ g.T, rng.normal(size=(30, 30)), np.zeros((30, 30))])
+    U, S, V = (x.cpu().numpy() for x in api.svd(torch.from_numpy(a).cuda()))
+    for b in range(3):
+        s0 = np.linalg.svd(a[b], compute_uv=False)
+        assert np.allclose(S[b], s0, atol=1e-12 * max(s0[0], 1.0))
+        assert np.abs(U[b] * S[b] @ V[b].T - a[b]).max() <= 1e-11 * max(s0[0], 1.0)
+    # PSD input: the eigenvectors of the kept part agree on both sides
+    assert np.abs(U[0][:, :4] - V[0][:, :4]).max() < 1e-10
+
+
+def _blobs(m, d, k, seed, dtype=np.float64):
+    rng = np.random.default_rng(seed)
+    cen = rng.normal(scale=3.0, size=(k, d))
+    lab = rng.integers(0, k, size=m)
+    return (cen[lab] + rng.normal(size=(m, d))).astype(dtype)
+
+
+@pytest.mark.parametrize("m,d,k,weight", [(700, 5, 7, "const"), (2000, 50, 50, "pow"), (1500, 20, 130, "const"),
+                                          (513, 3, 1, "const")])
+def test_kmeans_and_snap_f64(api, m, d, k, weight):
+    p = _blobs(m, d, max(k // 2, 1), 11)
+    w = oc.upsilon(np.linalg.norm(p, axis=1), weight, 1.0)
+    z0 = p[np.linspace(0, m - 1, k).astype(int)]
+    for iters in (0, 1, 5):
+        Z, lab, obj, sn = api.kmeans(torch.from_numpy(p).cuda(), torch.from_numpy(w).cuda(),
+                                     torch.from_numpy(z0).cuda(), iters)
+        ref = oc.weighted_kmeans(p, w, z0, iters)
+        assert np.array_equal(lab.cpu().numpy(), ref.labels)
+        assert np.abs(Z.cpu().numpy() - ref.Z).max() <= 1e-12 * (1 + np.abs(ref.Z).max())
+        o = obj.cpu().numpy()
+        assert o[0] == pytest.approx(ref.e_initial, rel=1e-11)
+        assert o[1] == pytest.approx(ref.e_final, rel=1e-11)
+        assert np.array_equal(sn.cpu().numpy(), oc.snap(p, ref.Z))
+
+
+def test_kmeans_snap_conflicts_and_ties(api):
+    # many identical rows and coinciding centres: every candidate list is exhausted
+    p = np.zeros((600, 4))
+    p[300:] = 1.0
+    z0 = np.zeros((40, 4))
+    w = np.ones(600)
+    Z, lab, obj, sn = api.kmeans(torch.from_numpy(p).cuda(), torch.from_numpy(w).cuda(), torch.from_numpy(z0).cuda(), 2)
+    ref = oc.weighted_kmeans(p, w, z0, 2)
+    assert np.array_equal(lab.cpu().numpy(), ref.labels)
+    assert np.array_equal(sn.cpu().numpy(), oc.snap(p, ref.Z))
+
+
+def test_kmeans_f32_decisions_match_in_f32(api):
+    """The FP32 kernel decides argmin in FP32; compare with the oracle's decision
+    wherever the oracle's gap is above FP32 rounding, and otherwise require a tie."""
+    p = _blobs(3000, 16, 20, 12, np.float32)
+    z0 = p[:20].astype(np.float64)
+    w = np.ones(3000)
+    Z, lab, obj, sn = api.kmeans(torch.from_numpy(p).cuda(), torch.from_numpy(w).cuda(), torch.from_numpy(z0).cuda(), 0)
+    lab = lab.cpu().numpy()
+    pd = p.astype(np.float64)
+    zc = z0.astype(np.float32).astype(np.float64)
+    dist = ((pd[:, None, :] - zc[None]) ** 2).sum(-1)
+    ref = dist.argmin(1)
+    scale = (pd**2).sum(1) + (zc**2).sum(1).max()
+    gap = np.sort(dist, 1)[:, 1] - dist.min(1)
+    sure = gap > 1e-5 * scale
+    assert np.array_equal(lab[sure], ref[sure])
+    assert np.all(dist[~sure, lab[~sure]] - dist.min(1)[~sure] <= 1e-5 * scale[~sure])

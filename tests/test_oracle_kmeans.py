@@ -85,6 +85,23 @@ def test_snap_by_brute_force():
     assert len(set(got.tolist())) == z.shape[0]
 
 
+def test_snap_midpoint_tie_goes_to_the_lowest_row():
+    """A two-row cluster's centre is the midpoint: both rows are nearest."""
+    rng = np.random.default_rng(4)
+    p = rng.normal(size=(50, 6))
+    z = oc.centroid_update(p, np.ones(50), np.where(np.arange(50) == 17, 0, np.where(np.arange(50) == 31, 0, 1)),
+                           np.zeros((2, 6)))
+    assert oc.snap(p, z[:1]).tolist() == [17]
+    # without the tie window the choice would follow floating-point rounding
+    d = ((p[[17, 31]] - z[0]) ** 2).sum(1)
+    assert abs(d[0] - d[1]) <= 1e-12 * d.max()
+    # a real gap well above the window is not a tie
+    z2 = 0.6 * p[17] + 0.4 * p[31]
+    assert oc.snap(p, z2[None]).tolist() == [17]
+    z3 = 0.4 * p[17] + 0.6 * p[31]
+    assert oc.snap(p, z3[None]).tolist() == [31]
+
+
 def test_upsilon_kinds():
     x = np.array([0.0, 0.5, 2.0])
     assert oc.upsilon(x, "const", 3.0).tolist() == [1.0, 1.0, 1.0]
