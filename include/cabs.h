@@ -213,6 +213,19 @@ cabs_status cabs_kmeans(int64_t rows, int32_t dim, int32_t k, int32_t compute, c
                         const double* Z0, int32_t iters, double* Z, int32_t* labels, double* obj2,
                         int64_t* snap_out, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Kernel timing (diagnostics) ----
+ * When enabled, every launch of a kernel family is bracketed by two HIP events
+ * recorded on the stream it is launched on.  Families: "assign" (fused
+ * distance GEMM + argmin of the k-means), "eval" (entry evaluation / gathers),
+ * "tsgemm" (tall-skinny products), "gram", "svd", "snap" (top-T candidate
+ * pass), "centroid" (centroid partial sums), "error".  cabs_timing_read waits
+ * for the recorded events and returns the summed duration (milliseconds) and
+ * the number of launches since the last reset; CABS_EINVAL for an unknown
+ * family.  Timing adds two event records per launch. */
+cabs_status cabs_timing_enable(int32_t on);
+cabs_status cabs_timing_read(const char* family, double* total_ms, int64_t* launches);
+void cabs_timing_reset(void);
+
 /* ---- Continuous-batching server ---- */
 
 typedef struct cabs_server cabs_server;

@@ -69,6 +69,9 @@ _SIGS = {
     "cabs_kmeans_workspace_bytes": (C.c_size_t, [C.c_int64, C.c_int32, C.c_int32, C.c_int32]),
     "cabs_kmeans": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, C.c_int32, _P, _P, _P, _P,
                               _P, C.c_size_t, _P]),
+    "cabs_timing_enable": (C.c_int, [C.c_int32]),
+    "cabs_timing_read": (C.c_int, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "cabs_timing_reset": (None, []),
     "cabs_server_create": (_P, [C.c_int32, C.c_size_t, C.c_int32]),
     "cabs_submit": (C.c_int, [_P, C.POINTER(CabsMatrix), C.POINTER(CabsParams), C.POINTER(CabsResult),
                               C.POINTER(C.c_uint64)]),

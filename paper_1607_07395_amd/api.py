@@ -258,6 +258,24 @@ def kmeans(P: torch.Tensor, w: torch.Tensor, Z0: torch.Tensor, iters: int, snap:
     return Z, labels, obj2, sn
 
 
+def timing_enable(on: bool = True) -> None:
+    """cabs_timing_enable."""
+    F.check(F.lib().cabs_timing_enable(1 if on else 0), "cabs_timing_enable")
+
+
+def timing_reset() -> None:
+    """cabs_timing_reset."""
+    F.lib().cabs_timing_reset()
+
+
+def timing_read(family: str):
+    """cabs_timing_read -> (total milliseconds, launches)."""
+    ms = C.c_double(0.0)
+    n = C.c_int64(0)
+    F.check(F.lib().cabs_timing_read(family.encode(), C.byref(ms), C.byref(n)), "cabs_timing_read")
+    return ms.value, n.value
+
+
 class Server:
     """cabs_server_*: continuous-batching sketch server on one device."""
 

@@ -13,6 +13,7 @@
 #include "common.hpp"
 #include "gemm_core.hpp"
 #include "kernels.hpp"
+#include "timing.hpp"
 
 namespace cabs {
 
@@ -170,6 +171,7 @@ size_t error_ws_bytes(const MatView& mv, int k2c, int k2r, int compute, int64_t 
 template <typename TIn, typename TC>
 static hipError_t error_t(const MatView& mv, int kr, const TC* CU, const TC* Rt, int64_t ns, uint64_t seed,
                           double* part, double* out3, hipStream_t st) {
+  TimerScope ts(T_ERROR, st);
   int nb;
   if (ns > 0) {
     nb = ERR_NB;

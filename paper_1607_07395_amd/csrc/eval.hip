@@ -13,6 +13,7 @@
 #include "common.hpp"
 #include "gemm_core.hpp"
 #include "kernels.hpp"
+#include "timing.hpp"
 
 namespace cabs {
 
@@ -205,6 +206,7 @@ static hipError_t dense_dispatch(const MatView& mv, bool rows_t, const int64_t* 
 hipError_t launch_eval(const MatView& mv, bool rows_t, const int64_t* idx, int k, int compute, void* out,
                        hipStream_t st) {
   if (k <= 0) return hipErrorInvalidValue;
+  TimerScope ts(T_EVAL, st);
   if (mv.kind == SRC_DENSE) {
     if (mv.storage == P_F64) {
       if (compute == P_F64) return dense_dispatch<double, double>(mv, rows_t, idx, k, out, st);

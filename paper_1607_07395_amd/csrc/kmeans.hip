@@ -27,6 +27,7 @@
 #include "common.hpp"
 #include "gemm_core.hpp"
 #include "kernels.hpp"
+#include "timing.hpp"
 
 namespace cabs {
 
@@ -466,7 +467,12 @@ __global__ __launch_bounds__(256) void snap_merge_kernel(int nblk, const double*
 
 // Distances within tie_rtol * (|Z_j| + sqrt(d_min))^2 of the nearest untaken row
 // count as ties and go to the lowest row index (the centre of a two-row cluster
-// is equidistant from both rows).
+// is equidistant from both rows).  Wave 0 walks the centres in order using
+// candidate lists staged in LDS; the whole block joins only when a centre's
+// list cannot decide (every candidate taken, or the tie window reaches past
+// the list), and then scans every untaken row.
+constexpr int RES_CHUNK = 256;
+
 template <typename TC>
 __global__ __launch_bounds__(1024) void snap_resolve_kernel(int64_t rows, int dim, int k, const TC* __restrict__ P,
                                                             const TC* __restrict__ Zc, const double* __restrict__ znorm,
@@ -476,101 +482,128 @@ __global__ __launch_bounds__(1024) void snap_resolve_kernel(int64_t rows, int di
                                                             uint32_t* __restrict__ taken_bits,
                                                             int64_t* __restrict__ out) {
   __shared__ int64_t chosen[KM_MAXK];
-  __shared__ int64_t keys[KM_MAXK];
+  __shared__ double ld[RES_CHUNK * SNAP_T];
+  __shared__ int32_t lr[RES_CHUNK * SNAP_T];
+  __shared__ double lz[RES_CHUNK];
   __shared__ double bd[16];
   __shared__ int64_t br[16];
-  __shared__ int64_t pick;
+  __shared__ int sh_next, sh_marked;
   __shared__ double sh_dmin;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const double INF = __builtin_huge_val();
-  for (int j = 0; j < k; ++j) {
-    const double zn = sqrt(znorm[j]);
+  int j = 0;
+  int chunk0 = -RES_CHUNK;
+  int marked = 0;  // chosen[0 .. marked) are already in taken_bits
+  while (j < k) {
+    if (j >= chunk0 + RES_CHUNK) {  // stage the lists of centres [j, j + RES_CHUNK)
+      chunk0 = j;
+      const int n = (k - j < RES_CHUNK ? k - j : RES_CHUNK);
+      for (int e = tid; e < n * SNAP_T; e += 1024) {
+        ld[e] = top_d[(int64_t)j * SNAP_T + e];
+        lr[e] = top_r[(int64_t)j * SNAP_T + e];
+      }
+      for (int e = tid; e < n; e += 1024) lz[e] = sqrt(znorm[j + e]);
+      __syncthreads();
+    }
     if (wave == 0) {
-      int64_t found = -1;
-      double dmin = INF, tol = 0.0;
-      bool window_open = false;  // the tie window may extend past the candidate list
-      int q = 0;
-      for (; q < SNAP_T; ++q) {
-        const int32_t r = top_r[(int64_t)j * SNAP_T + q];
-        const double d = top_d[(int64_t)j * SNAP_T + q];
-        if (r == 0x7fffffff) break;
-        if (found >= 0 && d > dmin + tol) break;
-        bool hit = false;
-        for (int s = lane; s < j; s += 64) hit |= chosen[s] == (int64_t)r;
-        if (__ballot(hit) != 0) continue;
-        if (found < 0) {
-          dmin = d;
-          const double rr = zn + sqrt(d);
-          tol = tie_rtol * rr * rr;
-          found = r;
-        } else if (r < found) {
-          found = r;
+      int jj = j;
+      const int lim = (chunk0 + RES_CHUNK < k ? chunk0 + RES_CHUNK : k);
+      for (; jj < lim; ++jj) {
+        const double zn = lz[jj - chunk0];
+        int64_t found = -1;
+        double dmin = INF, tol = 0.0, last_d = INF;
+        int q = 0;
+        for (; q < SNAP_T; ++q) {
+          const int32_t r = lr[(jj - chunk0) * SNAP_T + q];
+          const double d = ld[(jj - chunk0) * SNAP_T + q];
+          if (r == 0x7fffffff) break;
+          if (found >= 0 && d > dmin + tol) break;
+          last_d = d;
+          bool hit = false;
+          for (int s = lane; s < jj; s += 64) hit |= chosen[s] == (int64_t)r;
+          if (__ballot(hit) != 0) continue;
+          if (found < 0) {
+            dmin = d;
+            const double rr = zn + sqrt(d);
+            tol = tie_rtol * rr * rr;
+            found = r;
+          } else if (r < found) {
+            found = r;
+          }
         }
+        const bool undecided = found < 0 || (q == SNAP_T && last_d <= dmin + tol);
+        if (undecided) break;
+        if (lane == 0) chosen[jj] = found;
+        __builtin_amdgcn_wave_barrier();
       }
-      if (q == SNAP_T && found >= 0) window_open = true;
-      if (lane == 0) pick = (found < 0 || window_open) ? -1 : found;
+      if (lane == 0) sh_next = jj;
     }
     __syncthreads();
-    if (pick < 0) {
-      // Full scan over the untaken rows: nearest distance, then the lowest row in its tie window.
-      double best = INF;
-      for (int64_t row = tid; row < rows; row += 1024) {
-        if (taken_bits[row >> 5] & (1u << (row & 31))) continue;
-        double dot = 0.0;
-        for (int c = 0; c < dim; ++c) dot += to_f64(P[row * dim + c]) * to_f64(Zc[(int64_t)j * dim + c]);
-        double d = pnorm[row] + znorm[j] - 2.0 * dot;
-        d = d > 0.0 ? d : 0.0;
-        if (d != d) d = INF;
-        best = d < best ? d : best;
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) { const double ob = __shfl_xor(best, off, 64); best = ob < best ? ob : best; }
-      if (lane == 0) bd[wave] = best;
-      __syncthreads();
-      if (tid == 0) {
-        double b = bd[0];
-        for (int w = 1; w < 16; ++w) b = bd[w] < b ? bd[w] : b;
-        sh_dmin = b;
-      }
-      __syncthreads();
-      const double dmin = sh_dmin;
-      const double rr = zn + sqrt(dmin < INF ? dmin : 0.0);
-      const double lim = dmin < INF ? dmin + tie_rtol * rr * rr : INF;
-      int64_t brow = INT64_MAX;
-      for (int64_t row = tid; row < rows && brow == INT64_MAX; row += 1024) {
-        if (taken_bits[row >> 5] & (1u << (row & 31))) continue;
-        double dot = 0.0;
-        for (int c = 0; c < dim; ++c) dot += to_f64(P[row * dim + c]) * to_f64(Zc[(int64_t)j * dim + c]);
-        double d = pnorm[row] + znorm[j] - 2.0 * dot;
-        d = d > 0.0 ? d : 0.0;
-        if (d != d) d = INF;
-        if (d <= lim) brow = row;
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const int64_t orow = __shfl_xor(brow, off, 64);
-        brow = orow < brow ? orow : brow;
-      }
-      if (lane == 0) br[wave] = brow;
-      __syncthreads();
-      if (tid == 0) {
-        int64_t r = br[0];
-        for (int w = 1; w < 16; ++w) r = br[w] < r ? br[w] : r;
-        if (r == INT64_MAX) {  // every untaken distance is NaN: lowest untaken row
-          for (int64_t row = 0; row < rows; ++row)
-            if (!(taken_bits[row >> 5] & (1u << (row & 31)))) { r = row; break; }
-        }
-        pick = r;
-      }
-      __syncthreads();
+    j = sh_next;
+    if (j >= k) break;
+    if (j >= chunk0 + RES_CHUNK) continue;  // next chunk
+    // Centre j needs a full scan: mark the rows chosen so far, then nearest
+    // distance over the untaken rows, then the lowest row in its tie window.
+    for (int s = marked + tid; s < j; s += 1024) atomicOr(&taken_bits[chosen[s] >> 5], 1u << (chosen[s] & 31));
+    marked = j;
+    __syncthreads();
+    const double zn = lz[j - chunk0];
+    double best = INF;
+    for (int64_t row = tid; row < rows; row += 1024) {
+      if (taken_bits[row >> 5] & (1u << (row & 31))) continue;
+      double dot = 0.0;
+      for (int c = 0; c < dim; ++c) dot += to_f64(P[row * dim + c]) * to_f64(Zc[(int64_t)j * dim + c]);
+      double d = pnorm[row] + znorm[j] - 2.0 * dot;
+      d = d > 0.0 ? d : 0.0;
+      if (d != d) d = INF;
+      best = d < best ? d : best;
     }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) { const double ob = __shfl_xor(best, off, 64); best = ob < best ? ob : best; }
+    if (lane == 0) bd[wave] = best;
+    __syncthreads();
     if (tid == 0) {
-      chosen[j] = pick;
-      taken_bits[pick >> 5] |= (1u << (pick & 31));
+      double b = bd[0];
+      for (int w = 1; w < 16; ++w) b = bd[w] < b ? bd[w] : b;
+      sh_dmin = b;
     }
     __syncthreads();
+    const double dmin = sh_dmin;
+    const double rr = zn + sqrt(dmin < INF ? dmin : 0.0);
+    const double lim = dmin < INF ? dmin + tie_rtol * rr * rr : INF;
+    int64_t brow = INT64_MAX;
+    for (int64_t row = tid; row < rows && brow == INT64_MAX; row += 1024) {
+      if (taken_bits[row >> 5] & (1u << (row & 31))) continue;
+      double dot = 0.0;
+      for (int c = 0; c < dim; ++c) dot += to_f64(P[row * dim + c]) * to_f64(Zc[(int64_t)j * dim + c]);
+      double d = pnorm[row] + znorm[j] - 2.0 * dot;
+      d = d > 0.0 ? d : 0.0;
+      if (d != d) d = INF;
+      if (d <= lim) brow = row;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const int64_t orow = __shfl_xor(brow, off, 64);
+      brow = orow < brow ? orow : brow;
+    }
+    if (lane == 0) br[wave] = brow;
+    __syncthreads();
+    if (tid == 0) {
+      int64_t r = br[0];
+      for (int w = 1; w < 16; ++w) r = br[w] < r ? br[w] : r;
+      if (r == INT64_MAX) {  // every untaken distance is NaN: lowest untaken row
+        for (int64_t row = 0; row < rows; ++row)
+          if (!(taken_bits[row >> 5] & (1u << (row & 31)))) { r = row; break; }
+      }
+      chosen[j] = r;
+      sh_marked = 0;
+    }
+    __syncthreads();
+    j += 1;
   }
-  // ascending order
+  __syncthreads();
+  // ascending order (reuses the candidate area as sort keys)
+  int64_t* keys = (int64_t*)ld;
   int P2 = 1;
   while (P2 < k) P2 <<= 1;
   for (int e = tid; e < P2; e += 1024) keys[e] = e < k ? chosen[e] : INT64_MAX;
@@ -604,7 +637,7 @@ struct KmWs {
 };
 
 static inline int snap_nblk(int64_t rows) {
-  int64_t nb = ceil_div(rows, 4096);
+  int64_t nb = ceil_div(rows, 512);
   if (nb > 256) nb = 256;
   return (int)(nb < 1 ? 1 : nb);
 }
@@ -675,8 +708,11 @@ static hipError_t kmeans_t(int compute, int64_t rows, int dim, int k, const void
 
   for (int it = 0; it <= iters; ++it) {
     const bool last = it == iters;
-    hipLaunchKernelGGL(assign_kernel<TC>, dim3(gA), dim3(256), 0, st, rows, dim, k, P, (const TC*)Zc, W.znorm,
-                       W.pnorm, labels, W.dmin, last ? W.gap : nullptr);
+    {
+      TimerScope ts(T_ASSIGN, st);
+      hipLaunchKernelGGL(assign_kernel<TC>, dim3(gA), dim3(256), 0, st, rows, dim, k, P, (const TC*)Zc, W.znorm,
+                         W.pnorm, labels, W.dmin, last ? W.gap : nullptr);
+    }
     if (it == 0 || last) {
       hipLaunchKernelGGL(wsum_partial_kernel, dim3(red_nb), dim3(256), 0, st, rows, w, W.dmin,
                          last ? W.gap : nullptr, W.red_s, W.red_g);
@@ -693,8 +729,11 @@ static hipError_t kmeans_t(int compute, int64_t rows, int dim, int k, const void
     if (last) break;
     hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)ceil_div(rows, 256)), dim3(256), 0, st, rows, nsb, labels,
                        W.rank_blk, W.offs, W.sorted);
-    hipLaunchKernelGGL(centroid_partial_kernel<TC>, dim3((unsigned)maxch), dim3(256), 0, st, dim, P, w, W.sorted,
-                       W.chunk_beg, W.chunk_end, W.nchunks, W.part, W.partw);
+    {
+      TimerScope ts(T_CENTROID, st);
+      hipLaunchKernelGGL(centroid_partial_kernel<TC>, dim3((unsigned)maxch), dim3(256), 0, st, dim, P, w, W.sorted,
+                         W.chunk_beg, W.chunk_end, W.nchunks, W.part, W.partw);
+    }
     hipLaunchKernelGGL(centroid_final_kernel<TC>, dim3(k), dim3(256), 0, st, k, dim, W.lchunk, W.part, W.partw, out.Z,
                        Zc, W.znorm);
   }
@@ -702,12 +741,15 @@ static hipError_t kmeans_t(int compute, int64_t rows, int dim, int k, const void
     const int nblk = snap_nblk(rows);
     const int64_t rpb = ceil_div(ceil_div(rows, nblk), SNAP_SUB) * SNAP_SUB;
     const int nblk_eff = (int)ceil_div(rows, rpb);
+    TimerScope ts(T_SNAP, st);
     hipLaunchKernelGGL(snap_topt_kernel<TC>, dim3(nblk_eff), dim3(256), 0, st, rows, dim, k, rpb, P, (const TC*)Zc,
                        W.znorm, W.pnorm, W.cand_d, W.cand_r);
     hipLaunchKernelGGL(snap_merge_kernel, dim3(k), dim3(256), 0, st, nblk_eff, W.cand_d, W.cand_r, W.top_d, W.top_r);
     const int64_t nbits = ceil_div(rows, 32);
     hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)ceil_div(nbits, 256)), dim3(256), 0, st, nbits, W.bits, 0u);
-    const double tie_rtol = sizeof(TC) == 8 ? 1e-11 : 1e-5;
+    // FP64: a relative tie window makes the choice independent of rounding order
+    // (and equal to the FP64 reference); other precisions compare exactly.
+    const double tie_rtol = sizeof(TC) == 8 ? 1e-11 : 0.0;
     hipLaunchKernelGGL(snap_resolve_kernel<TC>, dim3(1), dim3(1024), 0, st, rows, dim, k, P, (const TC*)Zc, W.znorm,
                        W.pnorm, W.top_d, W.top_r, tie_rtol, W.bits, out.snap);
   }

@@ -11,8 +11,11 @@
 // The output is sorted by singular value, descending, and the sign of each
 // pair is fixed so that the largest-magnitude entry of every left singular
 // vector is positive (first such entry on ties).
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
+#include "timing.hpp"
 
 namespace cabs {
 
@@ -22,14 +25,92 @@ constexpr int SVD_LDS_BYTES = 60 * 1024;
 
 __host__ __device__ static inline int even_up(int p) { return p + (p & 1); }
 
-// Per-matrix scratch in doubles: X (q*p), V (p*p), sigma (p), plus rank/sign (p ints each).
+constexpr int BJ_B = 8;               // columns per block of the block-Jacobi path
+constexpr int BJ_MAX_SWEEPS = 40;
+constexpr int BJ_INNER_SWEEPS = 2;
+
+// Number of column blocks (even) and padded column count of the block-Jacobi path.
+__host__ __device__ static inline int bj_blocks(int p) { int nb = (p + BJ_B - 1) / BJ_B; return nb + (nb & 1); }
+
+// Per-matrix scratch in doubles: X (q x P), V (P x P) with P >= p the padded
+// column count, sigma (p), rank / sign (p each), and 64 words of flags.
 __host__ __device__ static inline size_t svd_ws_doubles(int rows, int cols) {
   const size_t p = rows < cols ? rows : cols, q = rows < cols ? cols : rows;
-  return q * p + p * p + 3 * p + 64;
+  const size_t P = (size_t)bj_blocks((int)p) * BJ_B;
+  return q * P + P * P + 3 * p + 64;
 }
 
 size_t svd_ws_bytes(int batch, int rows, int cols) {
   return (size_t)batch * svd_ws_doubles(rows, cols) * sizeof(double) + 256;
+}
+
+// Singular values (column norms of the converged X), descending order, signs,
+// and the outputs in row-major U (rows x p), S (p), V (cols x p).  X is q x p
+// column-major with column stride ldx, V (p x p, rotations) with stride ldv.
+__device__ void svd_finalize(const double* X, int64_t xrs, int64_t xcs, const double* V, int64_t vrs, int64_t vcs, int q,
+                             int p, bool trans, double* sig, int* rank, double* sgn, double* Ub, double* Sb,
+                             double* Vb) {
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int nwaves = nthr >> 6;
+  // Singular values = column norms (one wave per column).
+  for (int j = wave; j < p; j += nwaves) {
+    double s2 = 0.0;
+    for (int i = lane; i < q; i += 64) s2 += X[i * xrs + j * xcs] * X[i * xrs + j * xcs];
+    s2 = wave_sum(s2);
+    if (lane == 0) sig[j] = sqrt(s2);
+  }
+  __syncthreads();
+  // Descending order, lower column index first on ties.
+  // NaN (from non-finite input) ranks below every number so that ranks stay a permutation.
+  for (int j = tid; j < p; j += nthr) {
+    const double sj = sig[j] == sig[j] ? sig[j] : -1.0;
+    int r = 0;
+    for (int i = 0; i < p; ++i) {
+      const double si = sig[i] == sig[i] ? sig[i] : -1.0;
+      r += (si > sj) || (si == sj && i < j);
+    }
+    rank[j] = r;
+  }
+  __syncthreads();
+  // Sign: the left singular vector of A is X[:, j] / sigma (not transposed) or V[:, j]
+  // (transposed); make its largest-magnitude entry positive.
+  for (int j = wave; j < p; j += nwaves) {
+    const double* lv = trans ? V + j * vcs : X + j * xcs;
+    const int64_t st = trans ? vrs : xrs;
+    const int len = trans ? p : q;
+    double best = -1.0;
+    int bi = 0x7fffffff;
+    double bval = 0.0;
+    for (int i = lane; i < len; i += 64) {
+      const double v = lv[i * st];
+      if (fabs(v) > best) { best = fabs(v); bi = i; bval = v; }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      const double ov = __shfl_xor(bval, off, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; bval = ov; }
+    }
+    if (lane == 0) sgn[j] = bval < 0.0 ? -1.0 : 1.0;
+  }
+  __syncthreads();
+  for (int j = tid; j < p; j += nthr) Sb[rank[j]] = sig[j];
+  // Left factor of the working problem: X / sigma (q x p); right: V (p x p).
+  for (int e = tid; e < q * p; e += nthr) {
+    const int j = e / q, i = e % q;
+    const double sj = sig[j];
+    const double v = sj > 0.0 ? sgn[j] * X[i * xrs + j * xcs] / sj : 0.0;
+    if (!trans) Ub[(int64_t)i * p + rank[j]] = v;   // U: rows x p
+    else Vb[(int64_t)i * p + rank[j]] = v;          // V: cols x p
+  }
+  for (int e = tid; e < p * p; e += nthr) {
+    const int j = e / p, i = e % p;
+    const double v = sgn[j] * V[i * vrs + j * vcs];
+    if (!trans) Vb[(int64_t)i * p + rank[j]] = v;   // V: cols x p
+    else Ub[(int64_t)i * p + rank[j]] = v;          // U: rows x p
+  }
 }
 
 __global__ __launch_bounds__(SVD_THREADS) void svd_jacobi_kernel(int rows, int cols, const double* __restrict__ A,
@@ -48,7 +129,8 @@ __global__ __launch_bounds__(SVD_THREADS) void svd_jacobi_kernel(int rows, int c
   double* base = ws + (size_t)b * svd_ws_doubles(rows, cols);
   double* X = use_lds ? lds : base;              // column-major q x p
   double* V = use_lds ? lds + (size_t)q * p : base + (size_t)q * p;  // column-major p x p
-  double* sig = base + (size_t)q * p + (size_t)p * p;
+  const size_t Pb = (size_t)bj_blocks(p) * BJ_B;
+  double* sig = base + (size_t)q * Pb + Pb * Pb;
   int* rank = (int*)(sig + p);
   double* sgn = sig + 2 * p;
   const double* Ab = A + b * strideA;
@@ -118,66 +200,358 @@ __global__ __launch_bounds__(SVD_THREADS) void svd_jacobi_kernel(int rows, int c
     if (done) break;
   }
 
-  // Singular values = column norms (one wave per column).
-  for (int j = wave; j < p; j += nwaves) {
-    double s2 = 0.0;
-    for (int i = lane; i < q; i += 64) s2 += X[(size_t)j * q + i] * X[(size_t)j * q + i];
-    s2 = wave_sum(s2);
-    if (lane == 0) sig[j] = sqrt(s2);
-  }
-  __syncthreads();
-  // Descending order, lower column index first on ties.
-  // NaN (from non-finite input) ranks below every number so that ranks stay a permutation.
-  for (int j = tid; j < p; j += SVD_THREADS) {
-    const double sj = sig[j] == sig[j] ? sig[j] : -1.0;
-    int r = 0;
-    for (int i = 0; i < p; ++i) {
-      const double si = sig[i] == sig[i] ? sig[i] : -1.0;
-      r += (si > sj) || (si == sj && i < j);
+  svd_finalize(X, 1, q, V, 1, p, q, p, trans, sig, rank, sgn, U + b * strideU, S + b * strideS, Vout + b * strideV);
+}
+
+// ---------------------------------------------------------------------------
+// Block one-sided Jacobi for larger matrices.
+//
+// The p working columns are split into blocks of 8 and every round pairs the
+// blocks (circle schedule).  For one pair of blocks: form the 16 x 16 FP64 Gram
+// of its columns on the MFMA, skip the pair if it is already orthogonal, else
+// diagonalise the Gram by cyclic two-sided Jacobi (relatively accurate on
+// positive definite matrices) while accumulating the rotation J, and replace
+// the 16 columns of X and V by X J and V J (MFMA again).  A sweep with no
+// rotation ends the iteration.  Columns below eps |X|_F are at the rounding
+// level of the block updates and are neither tested nor rotated.
+//
+// The first BJ_FAST_SWEEPS sweeps run as one launch per round with one
+// workgroup (4 waves) per block pair, spreading a round over many CUs; a
+// single-workgroup kernel then finishes the rare matrices that need more sweeps
+// (it returns at once when the matrix has converged) and writes the outputs.
+// X (q x P) and V (P x P) are row-major in the workspace.
+// ---------------------------------------------------------------------------
+constexpr int BJ_FAST_SWEEPS = 12;
+
+__device__ __forceinline__ int circle_pos(int pos, int round, int n) {
+  return pos == 0 ? 0 : 1 + (pos - 1 + round) % (n - 1);
+}
+
+// Round-robin schedule of 16 indices (8 disjoint pairs per round, 15 rounds).
+struct Sched16 {
+  int ia[15][8], ib[15][8];        // pair k of round r
+  int k[15][16], partner[15][16];  // pair index and partner of index c in round r
+};
+constexpr Sched16 make_sched16() {
+  Sched16 t{};
+  for (int r = 0; r < 15; ++r)
+    for (int k = 0; k < 8; ++k) {
+      const int a = k == 0 ? 0 : 1 + (k - 1 + r) % 15;
+      const int b = 1 + (15 - 1 - k + r) % 15;
+      t.ia[r][k] = a;
+      t.ib[r][k] = b;
+      t.k[r][a] = k;
+      t.k[r][b] = k;
+      t.partner[r][a] = b;
+      t.partner[r][b] = a;
     }
-    rank[j] = r;
+  return t;
+}
+__constant__ Sched16 kSched16 = make_sched16();
+
+struct BjView {
+  double* X; double* V; double* sig; int* rank; double* sgn; int* flags; double* fro2;
+  int q, p, P, nb;
+  bool trans;
+};
+
+__device__ __forceinline__ BjView bj_view(double* ws, int rows, int cols, int b) {
+  BjView v;
+  v.trans = rows < cols;
+  v.p = v.trans ? rows : cols;
+  v.q = v.trans ? cols : rows;
+  v.nb = bj_blocks(v.p);
+  v.P = v.nb * BJ_B;
+  double* base = ws + (size_t)b * svd_ws_doubles(rows, cols);
+  v.X = base;
+  v.V = base + (size_t)v.q * v.P;
+  v.sig = v.V + (size_t)v.P * v.P;
+  v.rank = (int*)(v.sig + v.p);
+  v.sgn = v.sig + 2 * (size_t)v.p;
+  v.flags = (int*)(v.sig + 3 * (size_t)v.p);  // [0] done, [1] sweeps used, [2 + s] sweep s rotated
+  v.fro2 = (double*)(v.flags + 64);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void bj_init_kernel(int rows, int cols, const double* __restrict__ A, int64_t strideA,
+                                                      double* __restrict__ ws) {
+  BjView v = bj_view(ws, rows, cols, blockIdx.y);
+  const double* Ab = A + blockIdx.y * strideA;
+  const int64_t nx = (int64_t)v.q * v.P, nv = (int64_t)v.P * v.P;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nx + nv; e += (int64_t)gridDim.x * 256) {
+    if (e < nx) {
+      const int i = (int)(e / v.P), j = (int)(e % v.P);
+      double x = 0.0;
+      if (j < v.p) x = v.trans ? Ab[(int64_t)j * cols + i] : Ab[(int64_t)i * cols + j];
+      v.X[e] = x;
+    } else {
+      const int64_t f = e - nx;
+      v.V[f] = (f / v.P == f % v.P) ? 1.0 : 0.0;
+    }
   }
+  if (blockIdx.x == 0 && threadIdx.x < 64) v.flags[threadIdx.x] = 0;
+}
+
+// |X|_F^2, invariant under the rotations, for the negligible-column floor.
+__global__ __launch_bounds__(256) void bj_norm_kernel(int rows, int cols, const double* __restrict__ A, int64_t strideA,
+                                                      double* __restrict__ ws) {
+  __shared__ double red[4];
+  BjView v = bj_view(ws, rows, cols, blockIdx.x);
+  const double* Ab = A + blockIdx.x * strideA;
+  double s = 0.0;
+  for (int64_t e = threadIdx.x; e < (int64_t)rows * cols; e += 256) s += Ab[e] * Ab[e];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  // Sign: the left singular vector of A is X[:, j] / sigma (not transposed) or V[:, j]
-  // (transposed); make its largest-magnitude entry positive.
-  for (int j = wave; j < p; j += nwaves) {
-    const double* lv = trans ? V + (size_t)j * p : X + (size_t)j * q;
-    const int len = trans ? p : q;
-    double best = -1.0;
-    int bi = 0x7fffffff;
-    double bval = 0.0;
-    for (int i = lane; i < len; i += 64) {
-      const double v = lv[i];
-      if (fabs(v) > best) { best = fabs(v); bi = i; bval = v; }
+  if (threadIdx.x == 0) v.fro2[0] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// Gram of the 16 columns cols(c) = block ba (c < 8) / bb (c >= 8), rows [r0, r1), by one wave.
+__device__ __forceinline__ f64x4 pair_gram(const BjView& v, int ba, int bb, int r0, int r1) {
+  const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
+  const int mycol = c16 < 8 ? ba * BJ_B + c16 : bb * BJ_B + c16 - 8;
+  const double* xc = v.X + mycol;
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  int r = r0;
+  for (; r + 16 <= r1; r += 16) {
+    double x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = xc[(size_t)(r + 4 * u + g) * v.P];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u], x[u], acc, 0, 0, 0);
+  }
+  for (; r < r1; r += 4) {
+    const double x = (r + g < r1) ? xc[(size_t)(r + g) * v.P] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// X <- X J, V <- V J on the pair's 16 columns for the 16-row tiles t = t0, t0 + dt, ...
+// jb[st] = J[4 st + g][c16].
+__device__ __forceinline__ void pair_apply(const BjView& v, int ba, int bb, const double (&jb)[4], int t0, int dt) {
+  const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
+  const int qt = (v.q + 15) >> 4, ntiles = qt + (v.P >> 4);
+  const int outcol = c16 < 8 ? ba * BJ_B + c16 : bb * BJ_B + c16 - 8;
+  for (int t = t0; t < ntiles; t += dt) {
+    double* mat;
+    int r0, nr;
+    if (t < qt) { mat = v.X; r0 = t * 16; nr = v.q; }
+    else { mat = v.V; r0 = (t - qt) * 16; nr = v.P; }
+    f64x4 d = {0.0, 0.0, 0.0, 0.0};
+    double a[4];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int kc = 4 * st + g;
+      const int colk = kc < 8 ? ba * BJ_B + kc : bb * BJ_B + kc - 8;
+      const int rr = r0 + c16;
+      a[st] = rr < nr ? mat[(size_t)rr * v.P + colk] : 0.0;
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ob = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      const double ov = __shfl_xor(bval, off, 64);
-      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; bval = ov; }
+    for (int st = 0; st < 4; ++st) d = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], jb[st], d, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rr = r0 + out_row<double>(g, i);
+      if (rr < nr) mat[(size_t)rr * v.P + outcol] = d[i];
     }
-    if (lane == 0) sgn[j] = bval < 0.0 ? -1.0 : 1.0;
+  }
+}
+
+// Rotation zeroing G[ia][ib] of the positive semidefinite G (one-sided Jacobi formulas).
+__device__ __forceinline__ bool jacobi_rot(double al, double be, double ga, double tol, double floor2, double& c,
+                                           double& sn) {
+  c = 1.0;
+  sn = 0.0;
+  if (!(al > floor2 && be > floor2 && fabs(ga) > tol * sqrt(al) * sqrt(be))) return false;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  c = 1.0 / sqrt(1.0 + t * t);
+  sn = c * t;
+  return true;
+}
+
+// One round of the fast phase: one workgroup (4 waves) per pair of blocks.
+__global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int round, int sweep,
+                                                       double* __restrict__ ws) {
+  __shared__ double gp[4][16][17];
+  __shared__ double G[16][17];
+  __shared__ double J[16][17];
+  __shared__ double cs[8][2];
+  __shared__ int nrot, any_off;
+  BjView v = bj_view(ws, rows, cols, blockIdx.y);
+  if (v.flags[0]) return;  // converged (uniform over the block)
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, c16 = lane & 15, g = lane >> 4;
+  const int pr = blockIdx.x;
+  const int ba = circle_pos(pr, round, v.nb), bb = circle_pos(v.nb - 1 - pr, round, v.nb);
+  {
+    const int r0 = (int)(((int64_t)v.q * wave) / 4), r1 = (int)(((int64_t)v.q * (wave + 1)) / 4);
+    const f64x4 acc = pair_gram(v, ba, bb, r0, r1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) gp[wave][out_row<double>(g, i)][c16] = acc[i];
+  }
+  if (tid == 0) { nrot = 0; any_off = 0; }
+  __syncthreads();
+  const double eps = 2.220446049250313e-16;
+  const double tol = eps * (v.q > 16 ? (double)v.q : 16.0);
+  const double floor2 = eps * eps * v.fro2[0];
+  {
+    const int i = tid >> 4, j = tid & 15;
+    G[i][j] = ((gp[0][i][j] + gp[1][i][j]) + gp[2][i][j]) + gp[3][i][j];
+    J[i][j] = i == j ? 1.0 : 0.0;
   }
   __syncthreads();
-  double* Ub = U + b * strideU;
-  double* Vb = Vout + b * strideV;
-  double* Sb = S + b * strideS;
-  for (int j = tid; j < p; j += SVD_THREADS) Sb[rank[j]] = sig[j];
-  // Left factor of the working problem: X / sigma (q x p); right: V (p x p).
-  for (int e = tid; e < q * p; e += SVD_THREADS) {
-    const int j = e / q, i = e % q;
-    const double sj = sig[j];
-    const double v = sj > 0.0 ? sgn[j] * X[e] / sj : 0.0;
-    if (!trans) Ub[(int64_t)i * p + rank[j]] = v;   // U: rows x p
-    else Vb[(int64_t)i * p + rank[j]] = v;          // V: cols x p
+  {
+    const int i = tid >> 4, j = tid & 15;
+    if (i < j && G[i][i] > floor2 && G[j][j] > floor2 && fabs(G[i][j]) > tol * sqrt(G[i][i]) * sqrt(G[j][j]))
+      any_off = 1;
   }
-  for (int e = tid; e < p * p; e += SVD_THREADS) {
-    const int j = e / p, i = e % p;
-    const double v = sgn[j] * V[e];
-    if (!trans) Vb[(int64_t)i * p + rank[j]] = v;   // V: cols x p
-    else Ub[(int64_t)i * p + rank[j]] = v;          // U: rows x p
+  __syncthreads();
+  if (!any_off) return;  // uniform
+  if (tid == 0) v.flags[2 + sweep] = 1;
+  for (int is = 0; is < BJ_INNER_SWEEPS; ++is) {
+    if (tid == 0) nrot = 0;
+    __syncthreads();
+    for (int r = 0; r < 15; ++r) {
+      if (tid < 8) {
+        const int ia = kSched16.ia[r][tid], ib = kSched16.ib[r][tid];
+        double c, sn;
+        if (jacobi_rot(G[ia][ia], G[ib][ib], G[ia][ib], tol, floor2, c, sn)) atomicAdd(&nrot, 1);
+        cs[tid][0] = c;
+        cs[tid][1] = sn;
+      }
+      __syncthreads();
+      if (tid < 128) {  // columns of G
+        const int k = tid >> 4, i = tid & 15, ia = kSched16.ia[r][k], ib = kSched16.ib[r][k];
+        const double c = cs[k][0], sn = cs[k][1], u = G[i][ia], w = G[i][ib];
+        G[i][ia] = c * u - sn * w;
+        G[i][ib] = sn * u + c * w;
+      } else {          // columns of J
+        const int t2 = tid - 128, k = t2 >> 4, i = t2 & 15, ia = kSched16.ia[r][k], ib = kSched16.ib[r][k];
+        const double c = cs[k][0], sn = cs[k][1], u = J[i][ia], w = J[i][ib];
+        J[i][ia] = c * u - sn * w;
+        J[i][ib] = sn * u + c * w;
+      }
+      __syncthreads();
+      if (tid < 128) {  // rows of G
+        const int k = tid >> 4, j = tid & 15, ia = kSched16.ia[r][k], ib = kSched16.ib[r][k];
+        const double c = cs[k][0], sn = cs[k][1], u = G[ia][j], w = G[ib][j];
+        G[ia][j] = c * u - sn * w;
+        G[ib][j] = sn * u + c * w;
+      }
+      __syncthreads();
+    }
+    if (nrot == 0) break;
+    __syncthreads();
   }
+  double jb[4];
+#pragma unroll
+  for (int st = 0; st < 4; ++st) jb[st] = J[4 * st + g][c16];
+  pair_apply(v, ba, bb, jb, wave, 4);
+}
+
+__global__ void bj_sweep_end_kernel(int rows, int cols, int sweep, double* __restrict__ ws) {
+  if (threadIdx.x != 0) return;
+  BjView v = bj_view(ws, rows, cols, blockIdx.x);
+  if (v.flags[0]) return;
+  v.flags[1] = sweep + 1;
+  if (v.flags[2 + sweep] == 0) v.flags[0] = 1;
+}
+
+// Remaining sweeps (if any) in one workgroup, one wave per pair; then the outputs.
+__global__ __launch_bounds__(1024) void bj_finish_kernel(int rows, int cols, int first_sweep, double* __restrict__ U,
+                                                         int64_t strideU, double* __restrict__ S, int64_t strideS,
+                                                         double* __restrict__ Vout, int64_t strideV,
+                                                         double* __restrict__ ws) {
+  __shared__ double Gs[16][16][17];
+  __shared__ double cs[16][8][2];
+  __shared__ int rotated;
+  const int b = blockIdx.x;
+  BjView v = bj_view(ws, rows, cols, b);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, c16 = lane & 15, g = lane >> 4;
+  const double eps = 2.220446049250313e-16;
+  const double tol = eps * (v.q > 16 ? (double)v.q : 16.0);
+  const double floor2 = eps * eps * v.fro2[0];
+  double (*G)[17] = Gs[wave];
+  const bool converged = v.flags[0] != 0;
+  for (int sweep = first_sweep; !converged && sweep < BJ_MAX_SWEEPS; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int round = 0; round < v.nb - 1; ++round) {
+      for (int pr = wave; pr < v.nb / 2; pr += 16) {
+        const int ba = circle_pos(pr, round, v.nb), bb = circle_pos(v.nb - 1 - pr, round, v.nb);
+        const f64x4 acc = pair_gram(v, ba, bb, 0, v.q);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) G[out_row<double>(g, i)][c16] = acc[i];
+        __builtin_amdgcn_wave_barrier();
+        bool off = false;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int e = lane + 64 * t, i = e >> 4, j = e & 15;
+          if (i < j && G[i][i] > floor2 && G[j][j] > floor2 && fabs(G[i][j]) > tol * sqrt(G[i][i]) * sqrt(G[j][j]))
+            off = true;
+        }
+        if (__ballot(off) == 0) continue;
+        if (lane == 0) rotated = 1;
+        double jr[4];  // J[4g + i][c16]
+#pragma unroll
+        for (int i = 0; i < 4; ++i) jr[i] = (4 * g + i == c16) ? 1.0 : 0.0;
+        for (int is = 0; is < BJ_INNER_SWEEPS; ++is) {
+          bool any = false;
+          for (int r = 0; r < 15; ++r) {
+            if (lane < 8) {
+              const int ia = kSched16.ia[r][lane], ib = kSched16.ib[r][lane];
+              double c, sn;
+              any |= jacobi_rot(G[ia][ia], G[ib][ib], G[ia][ib], tol, floor2, c, sn);
+              cs[wave][lane][0] = c;
+              cs[wave][lane][1] = sn;
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+              const int e = lane + 64 * t, k = e >> 4, i = e & 15, ia = kSched16.ia[r][k], ib = kSched16.ib[r][k];
+              const double c = cs[wave][k][0], sn = cs[wave][k][1], u = G[i][ia], w = G[i][ib];
+              G[i][ia] = c * u - sn * w;
+              G[i][ib] = sn * u + c * w;
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+              const int e = lane + 64 * t, k = e >> 4, j = e & 15, ia = kSched16.ia[r][k], ib = kSched16.ib[r][k];
+              const double c = cs[wave][k][0], sn = cs[wave][k][1], u = G[ia][j], w = G[ib][j];
+              G[ia][j] = c * u - sn * w;
+              G[ib][j] = sn * u + c * w;
+            }
+            {
+              const int k = kSched16.k[r][c16], ia = kSched16.ia[r][k], partner = kSched16.partner[r][c16];
+              const double c = cs[wave][k][0], sn = cs[wave][k][1];
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const double other = __shfl(jr[i], (lane & 48) | partner, 64);
+                jr[i] = c16 == ia ? c * jr[i] - sn * other : sn * other + c * jr[i];
+              }
+            }
+            __builtin_amdgcn_wave_barrier();
+          }
+          if (__ballot(any) == 0) break;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) G[4 * g + i][c16] = jr[i];
+        __builtin_amdgcn_wave_barrier();
+        double jb[4];
+#pragma unroll
+        for (int st = 0; st < 4; ++st) jb[st] = G[4 * st + g][c16];
+        pair_apply(v, ba, bb, jb, 0, 1);
+        __builtin_amdgcn_wave_barrier();
+      }
+      __syncthreads();
+    }
+    const int done = rotated == 0;
+    __syncthreads();
+    if (tid == 0) v.flags[1] = sweep + 1;
+    if (done) break;
+  }
+  svd_finalize(v.X, v.P, 1, v.V, v.P, 1, v.q, v.p, v.trans, v.sig, v.rank, v.sgn, U + b * strideU, S + b * strideS,
+               Vout + b * strideV);
 }
 
 hipError_t launch_svd(int batch, int rows, int cols, const double* A, int64_t strideA, double* U, int64_t strideU,
@@ -186,8 +560,25 @@ hipError_t launch_svd(int batch, int rows, int cols, const double* A, int64_t st
   const size_t p = rows < cols ? rows : cols, q = rows < cols ? cols : rows;
   const size_t lds_bytes = (q * p + p * p) * sizeof(double);
   const int use_lds = lds_bytes <= (size_t)SVD_LDS_BYTES ? 1 : 0;
-  hipLaunchKernelGGL(svd_jacobi_kernel, dim3(batch), dim3(SVD_THREADS), use_lds ? lds_bytes : 0, st, rows, cols, A,
-                     strideA, U, strideU, S, strideS, V, strideV, (double*)ws, use_lds);
+  TimerScope ts(T_SVD, st);
+  if (use_lds || p < 24) {
+    hipLaunchKernelGGL(svd_jacobi_kernel, dim3(batch), dim3(SVD_THREADS), use_lds ? lds_bytes : 0, st, rows, cols,
+                       A, strideA, U, strideU, S, strideS, V, strideV, (double*)ws, use_lds);
+    return hipGetLastError();
+  }
+  double* w = (double*)ws;
+  const int nb = bj_blocks((int)p);
+  const int64_t elems = (int64_t)q * nb * BJ_B + (int64_t)nb * BJ_B * nb * BJ_B;
+  hipLaunchKernelGGL(bj_init_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(elems, 256), 1024), batch), dim3(256), 0,
+                     st, rows, cols, A, strideA, w);
+  hipLaunchKernelGGL(bj_norm_kernel, dim3(batch), dim3(256), 0, st, rows, cols, A, strideA, w);
+  for (int sweep = 0; sweep < BJ_FAST_SWEEPS; ++sweep) {
+    for (int round = 0; round < nb - 1; ++round)
+      hipLaunchKernelGGL(bj_round_kernel, dim3(nb / 2, batch), dim3(256), 0, st, rows, cols, round, sweep, w);
+    hipLaunchKernelGGL(bj_sweep_end_kernel, dim3(batch), dim3(64), 0, st, rows, cols, sweep, w);
+  }
+  hipLaunchKernelGGL(bj_finish_kernel, dim3(batch), dim3(1024), 0, st, rows, cols, BJ_FAST_SWEEPS, U, strideU, S,
+                     strideS, V, strideV, w);
   return hipGetLastError();
 }
 

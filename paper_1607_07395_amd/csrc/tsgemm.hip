@@ -13,6 +13,7 @@
 #include "common.hpp"
 #include "gemm_core.hpp"
 #include "kernels.hpp"
+#include "timing.hpp"
 
 namespace cabs {
 
@@ -128,6 +129,7 @@ static hipError_t tsgemm_t(int64_t M, int K, int N, const void* X, const double*
 hipError_t launch_tsgemm(int64_t M, int K, int N, int compute, const void* X, const double* B, void* Y,
                          double* colsq, double* rowsq, void* ws, hipStream_t st) {
   if (M <= 0 || K <= 0 || N <= 0 || N > TS_MAXN) return hipErrorInvalidValue;
+  TimerScope ts(T_TSGEMM, st);
   switch (compute) {
     case P_F64: return tsgemm_t<double>(M, K, N, X, B, Y, colsq, rowsq, ws, st);
     case P_F32: return tsgemm_t<float>(M, K, N, X, B, Y, colsq, rowsq, ws, st);
@@ -223,6 +225,7 @@ size_t gram_ws_bytes(int64_t M, int K) {
 
 hipError_t launch_gram(int64_t M, int K, int compute, const void* X, double* G, void* ws, hipStream_t st) {
   if (M <= 0 || K <= 0) return hipErrorInvalidValue;
+  TimerScope ts(T_GRAM, st);
   const int nt = (K + 15) / 16;
   const int ntiles = nt * (nt + 1) / 2;
   const int nb = gram_nb(M);

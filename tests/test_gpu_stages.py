@@ -66,7 +66,8 @@ def test_eval_cols_and_rows(api, kind, compute, tol):
 
 
 @pytest.mark.parametrize("rows,cols,seed", [(1, 1, 0), (5, 3, 1), (3, 5, 2), (50, 50, 3), (64, 40, 4), (40, 64, 5),
-                                            (200, 200, 6), (129, 200, 7)])
+                                            (200, 200, 6), (129, 200, 7), (300, 257, 8), (500, 500, 9),
+                                            (64, 700, 10), (1024, 23, 11)])
 def test_svd_against_lapack(api, rows, cols, seed):
     rng = np.random.default_rng(seed)
     a = rng.normal(size=(rows, cols)) * np.exp(-0.2 * np.arange(cols))[None, :]
@@ -86,6 +87,18 @@ def test_svd_against_lapack(api, rows, cols, seed):
         if tol < 1e-4:
             assert np.abs(U[:, j] - u0[:, j]).max() <= tol, j
             assert np.abs(V[:, j] - v0[:, j]).max() <= tol, j
+
+
+def test_svd_block_path_batched(api):
+    rng = np.random.default_rng(12)
+    a = np.stack([rng.normal(size=(210, 210)) * np.exp(-0.05 * np.arange(210))[None, :],
+                  rng.normal(size=(210, 210))])
+    U, S, V = (x.cpu().numpy() for x in api.svd(torch.from_numpy(a).cuda()))
+    for b in range(2):
+        s0 = np.linalg.svd(a[b], compute_uv=False)
+        assert np.allclose(S[b], s0, atol=1e-12 * s0[0])
+        assert np.abs(U[b] * S[b] @ V[b].T - a[b]).max() <= 1e-11 * s0[0]
+        assert np.abs(U[b].T @ U[b] - np.eye(210)).max() < 1e-11
 
 
 def test_svd_batched_and_rank_deficient(api):
