@@ -167,6 +167,7 @@ def main():
             "rel_frobenius_error_mean": float(rel.mean()), "rel_frobenius_error_max": float(rel.max()),
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "rank_final": diag["rank_final"], "entries_touched": diag["entries"],
+            "snap_full_scans": [diag["snap_scans_r"], diag["snap_scans_c"]],
         },
         "roofline": {
             "kernel": "assign (fused distance GEMM + argmin)",

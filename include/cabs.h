@@ -127,6 +127,8 @@ enum {
   CABS_DIAG_GAP_C = 11,
   CABS_DIAG_SIGMA1_PILOT = 12, /* largest singular value of W, pilot and follow-up */
   CABS_DIAG_SIGMA1_FINAL = 13,
+  CABS_DIAG_SNAP_SCANS_R = 14, /* centres whose snap needed a scan of every row (candidate lists exhausted) */
+  CABS_DIAG_SNAP_SCANS_C = 15,
   CABS_DIAG_LEN = 16
 };
 

@@ -23,6 +23,7 @@ SK_STABILIZED, SK_PSEUDO_SKELETON = 0, 1
 DIAG_STATUS, DIAG_ENC_R_PILOT, DIAG_ENC_C_PILOT, DIAG_ENC_R_FINAL, DIAG_ENC_C_FINAL = 0, 1, 2, 3, 4
 DIAG_TMAX_R, DIAG_TMAX_C, DIAG_RANK_PILOT, DIAG_RANK_FINAL, DIAG_ENTRIES = 5, 6, 7, 8, 9
 DIAG_GAP_R, DIAG_GAP_C, DIAG_SIGMA1_PILOT, DIAG_SIGMA1_FINAL, DIAG_LEN = 10, 11, 12, 13, 16
+DIAG_SNAP_SCANS_R, DIAG_SNAP_SCANS_C = 14, 15
 
 
 class CabsMatrix(C.Structure):

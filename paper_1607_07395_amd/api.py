@@ -122,7 +122,8 @@ class SketchResult:
                 "tmax_r": int(d[F.DIAG_TMAX_R]), "tmax_c": int(d[F.DIAG_TMAX_C]),
                 "rank_pilot": int(d[F.DIAG_RANK_PILOT]), "rank_final": int(d[F.DIAG_RANK_FINAL]),
                 "entries": int(d[F.DIAG_ENTRIES]), "gap_r": d[F.DIAG_GAP_R], "gap_c": d[F.DIAG_GAP_C],
-                "sigma1_pilot": d[F.DIAG_SIGMA1_PILOT], "sigma1_final": d[F.DIAG_SIGMA1_FINAL]}
+                "sigma1_pilot": d[F.DIAG_SIGMA1_PILOT], "sigma1_final": d[F.DIAG_SIGMA1_FINAL],
+                "snap_scans_r": int(d[F.DIAG_SNAP_SCANS_R]), "snap_scans_c": int(d[F.DIAG_SNAP_SCANS_C])}
 
 
 def alloc_result(mat: DeviceMatrix, prm: F.CabsParams) -> SketchResult:

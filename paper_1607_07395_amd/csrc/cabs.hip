@@ -534,9 +534,11 @@ extern "C" cabs_status cabs_sketch(const cabs_matrix* mat, const cabs_params* pr
   }
   HIP_TRY(launch_gather_rows_f64(S.P, pl.prec, e, I0r, pl.kr2, e, S.Z0r, st));
   HIP_TRY(launch_gather_rows_f64(S.Q, pl.prec, e, I0c, pl.kc2, e, S.Z0c, st));
-  KMeansOut kr{S.Zr, nullptr, S.obj, diag + CABS_DIAG_TMAX_R, diag + CABS_DIAG_GAP_R, out->idx_r};
+  KMeansOut kr{S.Zr, nullptr, S.obj, diag + CABS_DIAG_TMAX_R, diag + CABS_DIAG_GAP_R, out->idx_r,
+               diag + CABS_DIAG_SNAP_SCANS_R};
   HIP_TRY(launch_kmeans(pl.m, e, pl.kr2, pl.prec, S.P, S.wr, S.Z0r, prm->kmeans_iters, kr, S.kmr, st));
-  KMeansOut kc{S.Zc, nullptr, S.obj + 2, diag + CABS_DIAG_TMAX_C, diag + CABS_DIAG_GAP_C, out->idx_c};
+  KMeansOut kc{S.Zc, nullptr, S.obj + 2, diag + CABS_DIAG_TMAX_C, diag + CABS_DIAG_GAP_C, out->idx_c,
+               diag + CABS_DIAG_SNAP_SCANS_C};
   HIP_TRY(launch_kmeans(pl.n, e, pl.kc2, pl.prec, S.Q, S.wc, S.Z0c, prm->kmeans_iters, kc, S.kmc, st));
   hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 0, diag + CABS_DIAG_ENC_R_PILOT);
   hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 1, diag + CABS_DIAG_ENC_R_FINAL);
@@ -689,7 +691,7 @@ extern "C" cabs_status cabs_kmeans(int64_t rows, int32_t dim, int32_t k, int32_t
   if (!P || !w || !Z0 || !Z || !ws) return fail(CABS_EINVAL, "null pointer");
   if (iters < 0) return fail(CABS_EINVAL, "iters must be >= 0");
   if (ws_bytes < kmeans_ws_bytes(rows, dim, k, compute)) return fail(CABS_ENOMEM, "workspace too small");
-  KMeansOut o{Z, labels, obj2, nullptr, nullptr, snap_out};
+  KMeansOut o{Z, labels, obj2, nullptr, nullptr, snap_out, nullptr};
   HIP_TRY(launch_kmeans(rows, dim, k, compute, P, w, Z0, iters, o, ws, (hipStream_t)stream));
   return CABS_OK;
 }

@@ -109,6 +109,11 @@ template <typename T> __device__ __forceinline__ T wave_max(T v) {
   for (int off = 32; off > 0; off >>= 1) { T o = __shfl_xor(v, off, WAVE); v = o > v ? o : v; }
   return v;
 }
+template <typename T> __device__ __forceinline__ T wave_min(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) { T o = __shfl_xor(v, off, WAVE); v = o < v ? o : v; }
+  return v;
+}
 
 // ---------------------------------------------------------------------------
 // MFMA fragments.  A 16x16 output tile D = A_tile (16 x K) * B_tile (K x 16)

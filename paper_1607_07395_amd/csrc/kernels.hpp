@@ -73,6 +73,7 @@ struct KMeansOut {
   double* tmax;      // largest cluster of the final assignment (may be null)
   double* gap;       // smallest best/second-best gap of the final assignment (may be null)
   int64_t* snap;     // k snapped rows, ascending (may be null)
+  double* fallbacks; // number of centres resolved by a full scan (may be null)
 };
 hipError_t launch_kmeans(int64_t rows, int dim, int k, int compute, const void* P, const double* w,
                          const double* Z0, int iters, const KMeansOut& out, void* ws, hipStream_t st);

@@ -81,10 +81,6 @@ __global__ __launch_bounds__(256) void copy_f64_kernel(int64_t n, const double* 
   if (e < n) dst[e] = src[e];
 }
 
-__global__ __launch_bounds__(256) void fill_u32_kernel(int64_t n, uint32_t* __restrict__ dst, uint32_t v) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e < n) dst[e] = v;
-}
 
 // ---------------------------------------------------------------------------
 // assign: fused distance GEMM + argmin
@@ -354,6 +350,14 @@ __global__ void wsum_final_kernel(int nb, const double* __restrict__ part_s, con
 // ---------------------------------------------------------------------------
 // Snapping
 // ---------------------------------------------------------------------------
+// Squared distance of a row to a centre from the norms and the MFMA dot
+// product.  Written with an explicit fma so that every kernel that needs it
+// rounds identically; NaN counts as +inf (never the nearest).
+__device__ __forceinline__ double snap_dist(double pn, double zn, double dot) {
+  const double d = __builtin_fma(-2.0, dot, pn + zn);
+  return d > 0.0 ? d : (d == d ? 0.0 : __builtin_huge_val());
+}
+
 template <typename AT>
 __device__ __forceinline__ void topt_insert(AT (&d)[SNAP_T], int (&r)[SNAP_T], AT nd, int nr) {
   // rows arrive in increasing order, so a new equal distance goes after the old ones
@@ -368,6 +372,14 @@ __device__ __forceinline__ void topt_insert(AT (&d)[SNAP_T], int (&r)[SNAP_T], A
   if (nd < d[0]) { d[0] = nd; r[0] = nr; }
 }
 
+// Per block of rows_per_block consecutive rows and per centre: the SNAP_T
+// nearest rows, sorted by (distance, row).  Sub-tiles of 64 rows x 64 centres
+// go through LDS; each wave keeps lists over its own 16 rows of every sub-tile
+// (lane = centre) and the four lists are merged at the end of a centre chunk.
+// A list holding fewer than SNAP_T rows means every other row of the block is
+// at +inf.  Each 16-centre column tile of gemm_tile is an independent MFMA
+// chain, so snap_resolve_kernel recomputes these distances bit-exactly from a
+// one-tile call at the same row and column offsets.
 template <typename TC>
 __global__ __launch_bounds__(256) void snap_topt_kernel(int64_t rows, int dim, int k, int64_t rows_per_block,
                                                         const TC* __restrict__ P, const TC* __restrict__ Zc,
@@ -376,7 +388,10 @@ __global__ __launch_bounds__(256) void snap_topt_kernel(int64_t rows, int dim, i
                                                         int32_t* __restrict__ cand_r) {
   typedef typename Mfma<TC>::acc AccV;
   typedef typename NormT<TC>::type NrmT;
-  __shared__ double dist[SNAP_SUB][SNAP_CC + 1];
+  constexpr int LDD = SNAP_CC + 1;
+  __shared__ double sm_d[SNAP_SUB * LDD];          // distance sub-tile; then per-wave list distances
+  __shared__ int32_t sm_r[4 * SNAP_T * SNAP_CC];   // per-wave list rows
+  static_assert(4 * SNAP_T * SNAP_CC <= SNAP_SUB * LDD, "list staging must fit the distance tile");
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, c16 = lane & 15;
   const int64_t rbeg = (int64_t)blockIdx.x * rows_per_block;
@@ -387,14 +402,13 @@ __global__ __launch_bounds__(256) void snap_topt_kernel(int64_t rows, int dim, i
     int tr[SNAP_T];
 #pragma unroll
     for (int q = 0; q < SNAP_T; ++q) { td[q] = __builtin_huge_val(); tr[q] = 0x7fffffff; }
-    const int myc = cc + threadIdx.x;  // centre tracked by this thread (threads < SNAP_CC)
+    const int myc = cc + lane;  // centre tracked by this lane
     for (int64_t s0 = rbeg; s0 < rend; s0 += SNAP_SUB) {
       const int64_t row0 = s0 + wave * 16;
       AccV acc[SNAP_NT];
       NrmT xs, ys[SNAP_NT];
-      if (row0 < rend) {
+      if (row0 < rend)
         gemm_tile<TC, TC, SNAP_NT, false>(P, dim, rend, row0, Zc, dim, nullptr, k, cc, nullptr, dim, acc, xs, ys);
-      }
 #pragma unroll
       for (int t = 0; t < SNAP_NT; ++t) {
         const int cl = t * 16 + c16;
@@ -404,28 +418,48 @@ __global__ __launch_bounds__(256) void snap_topt_kernel(int64_t rows, int dim, i
           const int rl = wave * 16 + out_row<TC>(g, i);
           const int64_t row = s0 + rl;
           double d = __builtin_huge_val();
-          if (row0 < rend && row < rend && col < k) {
-            d = pnorm[row] + znorm[col] - 2.0 * (double)acc[t][i];
-            d = d > 0.0 ? d : 0.0;
-          }
-          dist[rl][cl] = d;
+          if (row0 < rend && row < rend && col < k) d = snap_dist(pnorm[row], znorm[col], (double)acc[t][i]);
+          sm_d[rl * LDD + cl] = d;
         }
       }
       __syncthreads();
-      if (threadIdx.x < SNAP_CC && myc < k) {
-        for (int rl = 0; rl < SNAP_SUB; ++rl) {
+      if (myc < k) {
+        for (int q = 0; q < 16; ++q) {
+          const int rl = wave * 16 + q;
           const int64_t row = s0 + rl;
           if (row >= rend) break;
-          topt_insert<double>(td, tr, dist[rl][threadIdx.x], (int)row);
+          topt_insert<double>(td, tr, sm_d[rl * LDD + lane], (int)row);
         }
       }
       __syncthreads();
     }
-    if (threadIdx.x < SNAP_CC && myc < k) {
-      const int64_t base = ((int64_t)myc * nblk + blockIdx.x) * SNAP_T;
+    // merge the four per-wave lists of each centre
 #pragma unroll
-      for (int q = 0; q < SNAP_T; ++q) { cand_d[base + q] = td[q]; cand_r[base + q] = tr[q]; }
+    for (int q = 0; q < SNAP_T; ++q) {
+      sm_d[(wave * SNAP_T + q) * SNAP_CC + lane] = td[q];
+      sm_r[(wave * SNAP_T + q) * SNAP_CC + lane] = tr[q];
     }
+    __syncthreads();
+    if (wave == 0 && myc < k) {
+      int p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+      const int64_t base = ((int64_t)myc * nblk + blockIdx.x) * SNAP_T;
+      for (int q = 0; q < SNAP_T; ++q) {
+        double bd = __builtin_huge_val();
+        int br = 0x7fffffff, bw = -1;
+#define TOPT_HEAD(W, PW)                                                              \
+  if (PW < SNAP_T) {                                                                  \
+    const double hd = sm_d[((W) * SNAP_T + PW) * SNAP_CC + lane];                     \
+    const int hr = sm_r[((W) * SNAP_T + PW) * SNAP_CC + lane];                        \
+    if (hr != 0x7fffffff && (bw < 0 || hd < bd || (hd == bd && hr < br))) { bd = hd; br = hr; bw = W; } \
+  }
+        TOPT_HEAD(0, p0) TOPT_HEAD(1, p1) TOPT_HEAD(2, p2) TOPT_HEAD(3, p3)
+#undef TOPT_HEAD
+        p0 += bw == 0; p1 += bw == 1; p2 += bw == 2; p3 += bw == 3;
+        cand_d[base + q] = bw < 0 ? __builtin_huge_val() : bd;
+        cand_r[base + q] = bw < 0 ? 0x7fffffff : br;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -465,37 +499,68 @@ __global__ __launch_bounds__(256) void snap_merge_kernel(int nblk, const double*
   }
 }
 
-// Distances within tie_rtol * (|Z_j| + sqrt(d_min))^2 of the nearest untaken row
-// count as ties and go to the lowest row index (the centre of a two-row cluster
-// is equidistant from both rows).  Wave 0 walks the centres in order using
-// candidate lists staged in LDS; the whole block joins only when a centre's
-// list cannot decide (every candidate taken, or the tie window reaches past
-// the list), and then scans every untaken row.
-constexpr int RES_CHUNK = 256;
+// Snapping, in centre order: centre j takes the nearest row not taken by an
+// earlier centre; distances within tie_rtol * (|Z_j| + sqrt(d_min))^2 of the
+// nearest untaken one count as ties and go to the lowest row index (the
+// centre of a two-row cluster is equidistant from both rows).
+//
+// Wave 0 walks the centres using their merged top-SNAP_T lists staged in LDS;
+// taken rows live in an LDS hash set.  When a merged list cannot decide
+// (every candidate taken, or the tie window reaching past the list) the whole
+// block resolves the centre from the per-block lists: each block contributes
+// its first untaken candidate, and a block whose SNAP_T-th listed distance
+// lies inside the current window (so unlisted rows of that block might too) is
+// rescanned.  Rescans recompute the block's distances exactly as the top-T
+// pass did (same tile calls, same rounding) into dws; the window is
+// recomputed and the rescan set widened until no further block qualifies.
+constexpr int RES_CHUNK = 128;
+constexpr int RES_HT = 2048;  // hash slots for taken rows (k <= KM_MAXK = RES_HT / 2)
+constexpr int RES_MAXBLK = 256;
+
+__device__ __forceinline__ int res_slot(int32_t r) { return (int)(((uint32_t)r * 2654435761u) >> 21); }
+__device__ __forceinline__ bool res_has(const int32_t* ht, int32_t r) {
+  for (int h = res_slot(r);; h = (h + 1) & (RES_HT - 1)) {
+    const int32_t v = ht[h];
+    if (v == r) return true;
+    if (v < 0) return false;
+  }
+}
+__device__ __forceinline__ void res_put(int32_t* ht, int32_t r) {
+  int h = res_slot(r);
+  while (ht[h] >= 0 && ht[h] != r) h = (h + 1) & (RES_HT - 1);
+  ht[h] = r;
+}
 
 template <typename TC>
-__global__ __launch_bounds__(1024) void snap_resolve_kernel(int64_t rows, int dim, int k, const TC* __restrict__ P,
-                                                            const TC* __restrict__ Zc, const double* __restrict__ znorm,
-                                                            const double* __restrict__ pnorm,
-                                                            const double* __restrict__ top_d,
-                                                            const int32_t* __restrict__ top_r, double tie_rtol,
-                                                            uint32_t* __restrict__ taken_bits,
-                                                            int64_t* __restrict__ out) {
+__global__ __launch_bounds__(1024) void snap_resolve_kernel(
+    int64_t rows, int dim, int k, const TC* __restrict__ P, const TC* __restrict__ Zc,
+    const double* __restrict__ znorm, const double* __restrict__ pnorm, const double* __restrict__ top_d,
+    const int32_t* __restrict__ top_r, const double* __restrict__ cand_d, const int32_t* __restrict__ cand_r, int nblk,
+    int64_t rows_per_block, double tie_rtol, double* __restrict__ dws, int64_t* __restrict__ out,
+    double* __restrict__ nfall) {
+  typedef typename Mfma<TC>::acc AccV;
+  typedef typename NormT<TC>::type NrmT;
+  constexpr int32_t SENT = 0x7fffffff;
   __shared__ int64_t chosen[KM_MAXK];
+  __shared__ int32_t ht[RES_HT];
   __shared__ double ld[RES_CHUNK * SNAP_T];
   __shared__ int32_t lr[RES_CHUNK * SNAP_T];
   __shared__ double lz[RES_CHUNK];
-  __shared__ double bd[16];
-  __shared__ int64_t br[16];
-  __shared__ int sh_next, sh_marked;
-  __shared__ double sh_dmin;
+  __shared__ double b_fd[RES_MAXBLK], b_bound[RES_MAXBLK], b_smin[RES_MAXBLK];
+  __shared__ int32_t b_state[RES_MAXBLK];  // 0 list, 1 rescanned, 2 rescan pending
+  __shared__ double wred[16];
+  __shared__ int64_t wrow[16];
+  __shared__ int sh_next, sh_more;
+  __shared__ double sh_lim;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const double INF = __builtin_huge_val();
+  for (int e = tid; e < RES_HT; e += 1024) ht[e] = -1;
   int j = 0;
   int chunk0 = -RES_CHUNK;
-  int marked = 0;  // chosen[0 .. marked) are already in taken_bits
+  int fallbacks = 0;
   while (j < k) {
     if (j >= chunk0 + RES_CHUNK) {  // stage the lists of centres [j, j + RES_CHUNK)
+      __syncthreads();
       chunk0 = j;
       const int n = (k - j < RES_CHUNK ? k - j : RES_CHUNK);
       for (int e = tid; e < n * SNAP_T; e += 1024) {
@@ -503,26 +568,24 @@ __global__ __launch_bounds__(1024) void snap_resolve_kernel(int64_t rows, int di
         lr[e] = top_r[(int64_t)j * SNAP_T + e];
       }
       for (int e = tid; e < n; e += 1024) lz[e] = sqrt(znorm[j + e]);
-      __syncthreads();
     }
+    __syncthreads();
     if (wave == 0) {
       int jj = j;
       const int lim = (chunk0 + RES_CHUNK < k ? chunk0 + RES_CHUNK : k);
       for (; jj < lim; ++jj) {
         const double zn = lz[jj - chunk0];
-        int64_t found = -1;
+        int32_t found = SENT;
         double dmin = INF, tol = 0.0, last_d = INF;
         int q = 0;
         for (; q < SNAP_T; ++q) {
           const int32_t r = lr[(jj - chunk0) * SNAP_T + q];
           const double d = ld[(jj - chunk0) * SNAP_T + q];
-          if (r == 0x7fffffff) break;
-          if (found >= 0 && d > dmin + tol) break;
+          if (r == SENT) break;
+          if (found != SENT && d > dmin + tol) break;
           last_d = d;
-          bool hit = false;
-          for (int s = lane; s < jj; s += 64) hit |= chosen[s] == (int64_t)r;
-          if (__ballot(hit) != 0) continue;
-          if (found < 0) {
+          if (res_has(ht, r)) continue;
+          if (found == SENT) {
             dmin = d;
             const double rr = zn + sqrt(d);
             tol = tie_rtol * rr * rr;
@@ -531,10 +594,12 @@ __global__ __launch_bounds__(1024) void snap_resolve_kernel(int64_t rows, int di
             found = r;
           }
         }
-        const bool undecided = found < 0 || (q == SNAP_T && last_d <= dmin + tol);
+        // undecided: nothing untaken in the list, or a full list whose end is
+        // still inside the window (then unlisted rows may tie)
+        const bool undecided = found == SENT || (q == SNAP_T && last_d <= dmin + tol);
         if (undecided) break;
-        if (lane == 0) chosen[jj] = found;
-        __builtin_amdgcn_wave_barrier();
+        chosen[jj] = found;  // every lane writes the same value
+        res_put(ht, found);
       }
       if (lane == 0) sh_next = jj;
     }
@@ -542,68 +607,120 @@ __global__ __launch_bounds__(1024) void snap_resolve_kernel(int64_t rows, int di
     j = sh_next;
     if (j >= k) break;
     if (j >= chunk0 + RES_CHUNK) continue;  // next chunk
-    // Centre j needs a full scan: mark the rows chosen so far, then nearest
-    // distance over the untaken rows, then the lowest row in its tie window.
-    for (int s = marked + tid; s < j; s += 1024) atomicOr(&taken_bits[chosen[s] >> 5], 1u << (chosen[s] & 31));
-    marked = j;
-    __syncthreads();
+
+    // ---- centre j from the per-block lists ----
+    ++fallbacks;
     const double zn = lz[j - chunk0];
-    double best = INF;
-    for (int64_t row = tid; row < rows; row += 1024) {
-      if (taken_bits[row >> 5] & (1u << (row & 31))) continue;
-      double dot = 0.0;
-      for (int c = 0; c < dim; ++c) dot += to_f64(P[row * dim + c]) * to_f64(Zc[(int64_t)j * dim + c]);
-      double d = pnorm[row] + znorm[j] - 2.0 * dot;
-      d = d > 0.0 ? d : 0.0;
-      if (d != d) d = INF;
-      best = d < best ? d : best;
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) { const double ob = __shfl_xor(best, off, 64); best = ob < best ? ob : best; }
-    if (lane == 0) bd[wave] = best;
-    __syncthreads();
-    if (tid == 0) {
-      double b = bd[0];
-      for (int w = 1; w < 16; ++w) b = bd[w] < b ? bd[w] : b;
-      sh_dmin = b;
-    }
-    __syncthreads();
-    const double dmin = sh_dmin;
-    const double rr = zn + sqrt(dmin < INF ? dmin : 0.0);
-    const double lim = dmin < INF ? dmin + tie_rtol * rr * rr : INF;
-    int64_t brow = INT64_MAX;
-    for (int64_t row = tid; row < rows && brow == INT64_MAX; row += 1024) {
-      if (taken_bits[row >> 5] & (1u << (row & 31))) continue;
-      double dot = 0.0;
-      for (int c = 0; c < dim; ++c) dot += to_f64(P[row * dim + c]) * to_f64(Zc[(int64_t)j * dim + c]);
-      double d = pnorm[row] + znorm[j] - 2.0 * dot;
-      d = d > 0.0 ? d : 0.0;
-      if (d != d) d = INF;
-      if (d <= lim) brow = row;
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const int64_t orow = __shfl_xor(brow, off, 64);
-      brow = orow < brow ? orow : brow;
-    }
-    if (lane == 0) br[wave] = brow;
-    __syncthreads();
-    if (tid == 0) {
-      int64_t r = br[0];
-      for (int w = 1; w < 16; ++w) r = br[w] < r ? br[w] : r;
-      if (r == INT64_MAX) {  // every untaken distance is NaN: lowest untaken row
-        for (int64_t row = 0; row < rows; ++row)
-          if (!(taken_bits[row >> 5] & (1u << (row & 31)))) { r = row; break; }
+    const int64_t cbase = (int64_t)j * nblk * SNAP_T;
+    for (int b = tid; b < nblk; b += 1024) {
+      double fd = INF;
+      for (int q = 0; q < SNAP_T; ++q) {
+        const int32_t r = cand_r[cbase + b * SNAP_T + q];
+        if (r == SENT) break;
+        if (!res_has(ht, r)) { fd = cand_d[cbase + b * SNAP_T + q]; break; }
       }
-      chosen[j] = r;
-      sh_marked = 0;
+      const bool full = cand_r[cbase + b * SNAP_T + SNAP_T - 1] != SENT;
+      b_fd[b] = fd;
+      b_bound[b] = full ? cand_d[cbase + b * SNAP_T + SNAP_T - 1] : INF;
+      b_smin[b] = INF;
+      b_state[b] = 0;
     }
     __syncthreads();
-    j += 1;
+    const int cc = (j / SNAP_CC) * SNAP_CC;
+    const int col0 = cc + ((j - cc) / 16) * 16;
+    const int jc = j - col0;
+    for (;;) {
+      if (wave == 0) {
+        double m = INF;
+        for (int b = lane; b < nblk; b += 64) {
+          const double v = b_state[b] ? b_smin[b] : b_fd[b];
+          m = v < m ? v : m;
+        }
+        m = wave_min(m);
+        const double rr = zn + sqrt(m < INF ? m : 0.0);
+        const double lim = m < INF ? m + tie_rtol * rr * rr : INF;
+        bool any = false;
+        for (int b = lane; b < nblk; b += 64)
+          if (b_state[b] == 0 && b_bound[b] <= lim) { b_state[b] = 2; any = true; }
+        any = __ballot(any) != 0;
+        if (lane == 0) { sh_lim = lim; sh_more = any ? 1 : 0; }
+      }
+      __syncthreads();
+      if (!sh_more) break;
+      for (int b = 0; b < nblk; ++b) {
+        if (b_state[b] != 2) continue;  // uniform: LDS value read after a barrier
+        const int64_t rbeg = (int64_t)b * rows_per_block;
+        const int64_t rend = rbeg + rows_per_block < rows ? rbeg + rows_per_block : rows;
+        double mloc = INF;
+        // wave w handles rows s0 + 16 (w % 4) of sub-tiles s0 = rbeg + 64 (w / 4 + 4 u)
+        for (int64_t s0 = rbeg + (int64_t)SNAP_SUB * (wave >> 2); s0 < rend; s0 += (int64_t)SNAP_SUB * 4) {
+          const int64_t row0 = s0 + (wave & 3) * 16;
+          if (row0 >= rend) continue;
+          AccV acc[1];
+          NrmT xs, ys[1];
+          gemm_tile<TC, TC, 1, false>(P, dim, rend, row0, Zc, dim, nullptr, k, col0, nullptr, dim, acc, xs, ys);
+          if ((lane & 15) == jc) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int64_t row = row0 + out_row<TC>(lane >> 4, i);
+              if (row < rend) {
+                double d = snap_dist(pnorm[row], znorm[j], (double)acc[0][i]);
+                if (res_has(ht, (int32_t)row)) d = INF;
+                dws[row] = d;
+                mloc = d < mloc ? d : mloc;
+              }
+            }
+          }
+        }
+        mloc = wave_min(mloc);
+        if (lane == 0) wred[wave] = mloc;
+        __syncthreads();
+        if (tid == 0) {
+          double m = wred[0];
+          for (int w = 1; w < 16; ++w) m = wred[w] < m ? wred[w] : m;
+          b_smin[b] = m;
+          b_state[b] = 1;
+        }
+        __syncthreads();
+      }
+    }
+    // lowest untaken row inside the window
+    const double lim = sh_lim;
+    int64_t best = INT64_MAX;
+    for (int b = tid; b < nblk; b += 1024) {
+      if (b_state[b] != 0) continue;
+      for (int q = 0; q < SNAP_T; ++q) {
+        const int32_t r = cand_r[cbase + b * SNAP_T + q];
+        if (r == SENT || cand_d[cbase + b * SNAP_T + q] > lim) break;
+        if (!res_has(ht, r) && r < best) best = r;
+      }
+    }
+    for (int b = 0; b < nblk; ++b) {
+      if (b_state[b] != 1) continue;
+      const int64_t rbeg = (int64_t)b * rows_per_block;
+      const int64_t rend = rbeg + rows_per_block < rows ? rbeg + rows_per_block : rows;
+      for (int64_t row = rbeg + tid; row < rend && row < best; row += 1024)
+        if (dws[row] <= lim) { best = row; break; }
+    }
+    best = wave_min<int64_t>(best);
+    if (lane == 0) wrow[wave] = best;
+    __syncthreads();
+    if (tid == 0) {
+      int64_t r = wrow[0];
+      for (int w = 1; w < 16; ++w) r = wrow[w] < r ? wrow[w] : r;
+      if (r == INT64_MAX)  // unreachable while k <= rows: every block was rescanned at lim = +inf
+        for (r = 0; r < rows && res_has(ht, (int32_t)r); ++r) {}
+      chosen[j] = r;
+      res_put(ht, (int32_t)r);
+      sh_next = j + 1;
+    }
+    __syncthreads();
+    j = sh_next;
   }
   __syncthreads();
   // ascending order (reuses the candidate area as sort keys)
   int64_t* keys = (int64_t*)ld;
+  static_assert(RES_CHUNK * SNAP_T >= KM_MAXK, "sort keys must fit the staging area");
   int P2 = 1;
   while (P2 < k) P2 <<= 1;
   for (int e = tid; e < P2; e += 1024) keys[e] = e < k ? chosen[e] : INT64_MAX;
@@ -622,6 +739,7 @@ __global__ __launch_bounds__(1024) void snap_resolve_kernel(int64_t rows, int di
     }
   }
   for (int e = tid; e < k; e += 1024) out[e] = keys[e];
+  if (tid == 0 && nfall) *nfall = (double)fallbacks;
 }
 
 // ---------------------------------------------------------------------------
@@ -632,7 +750,7 @@ struct KmWs {
   int32_t* hist; int32_t* offs; int32_t* rank_blk; int32_t* sorted; int32_t* lstart;
   int32_t* chunk_lab; int32_t* chunk_beg; int32_t* chunk_end; int32_t* lchunk; int32_t* nchunks;
   double* part; double* partw; double* red_s; double* red_g; double* obj_tmp; double* tmax_tmp; double* gap_tmp;
-  double* cand_d; int32_t* cand_r; double* top_d; int32_t* top_r; uint32_t* bits;
+  double* cand_d; int32_t* cand_r; double* top_d; int32_t* top_r;
   size_t total;
 };
 
@@ -678,7 +796,6 @@ static KmWs km_layout(void* base, int64_t rows, int dim, int k, int compute) {
   w.cand_r = (int32_t*)take((size_t)k * nblk * SNAP_T * 4);
   w.top_d = (double*)take((size_t)k * SNAP_T * 8);
   w.top_r = (int32_t*)take((size_t)k * SNAP_T * 4);
-  w.bits = (uint32_t*)take((size_t)ceil_div(rows, 32) * 4);
   w.total = off;
   return w;
 }
@@ -745,20 +862,19 @@ static hipError_t kmeans_t(int compute, int64_t rows, int dim, int k, const void
     hipLaunchKernelGGL(snap_topt_kernel<TC>, dim3(nblk_eff), dim3(256), 0, st, rows, dim, k, rpb, P, (const TC*)Zc,
                        W.znorm, W.pnorm, W.cand_d, W.cand_r);
     hipLaunchKernelGGL(snap_merge_kernel, dim3(k), dim3(256), 0, st, nblk_eff, W.cand_d, W.cand_r, W.top_d, W.top_r);
-    const int64_t nbits = ceil_div(rows, 32);
-    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)ceil_div(nbits, 256)), dim3(256), 0, st, nbits, W.bits, 0u);
     // FP64: a relative tie window makes the choice independent of rounding order
     // (and equal to the FP64 reference); other precisions compare exactly.
     const double tie_rtol = sizeof(TC) == 8 ? 1e-11 : 0.0;
     hipLaunchKernelGGL(snap_resolve_kernel<TC>, dim3(1), dim3(1024), 0, st, rows, dim, k, P, (const TC*)Zc, W.znorm,
-                       W.pnorm, W.top_d, W.top_r, tie_rtol, W.bits, out.snap);
+                       W.pnorm, W.top_d, W.top_r, W.cand_d, W.cand_r, nblk_eff, rpb, tie_rtol, W.dmin, out.snap,
+                       out.fallbacks);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_kmeans(int64_t rows, int dim, int k, int compute, const void* P, const double* w, const double* Z0,
                          int iters, const KMeansOut& out, void* ws, hipStream_t st) {
-  if (rows <= 0 || dim <= 0 || k <= 0 || k > KM_MAXK || k > rows || iters < 0 || out.Z == nullptr)
+  if (rows <= 0 || rows > INT32_MAX || dim <= 0 || k <= 0 || k > KM_MAXK || k > rows || iters < 0 || out.Z == nullptr)
     return hipErrorInvalidValue;
   switch (compute) {
     case P_F64: return kmeans_t<double>(compute, rows, dim, k, P, w, Z0, iters, out, ws, st);

@@ -151,6 +151,30 @@ def test_kmeans_snap_conflicts_and_ties(api):
     assert np.array_equal(sn.cpu().numpy(), oc.snap(p, ref.Z))
 
 
+@pytest.mark.parametrize("m,d,k,seed", [(20000, 6, 300, 3), (70000, 12, 640, 4)])
+def test_snap_deep_exhaustion_f64(api, m, d, k, seed):
+    # centres packed around the data mean: later centres find their nearest
+    # rows taken in most blocks, so the per-block lists and block rescans decide
+    rng = np.random.default_rng(seed)
+    p = rng.normal(size=(m, d))
+    z0 = p.mean(0) + 0.05 * rng.normal(size=(k, d))
+    w = np.ones(m)
+    Z, lab, obj, sn = api.kmeans(torch.from_numpy(p).cuda(), torch.from_numpy(w).cuda(), torch.from_numpy(z0).cuda(), 0)
+    assert np.array_equal(sn.cpu().numpy(), oc.snap(p, z0))
+
+
+def test_snap_duplicate_rows_across_blocks_f64(api):
+    # 6 distinct points repeated over 9000 rows in random order: exact ties
+    # between blocks go to the lowest row index
+    rng = np.random.default_rng(8)
+    pts = rng.normal(size=(6, 5))
+    p = pts[rng.integers(0, 6, size=9000)]
+    z0 = pts[rng.integers(0, 6, size=150)] + 1e-3 * rng.normal(size=(150, 5))
+    w = np.ones(9000)
+    Z, lab, obj, sn = api.kmeans(torch.from_numpy(p).cuda(), torch.from_numpy(w).cuda(), torch.from_numpy(z0).cuda(), 0)
+    assert np.array_equal(sn.cpu().numpy(), oc.snap(p, z0))
+
+
 def test_kmeans_f32_decisions_match_in_f32(api):
     """The FP32 kernel decides argmin in FP32; compare with the oracle's decision
     wherever the oracle's gap is above FP32 rounding, and otherwise require a tie."""
