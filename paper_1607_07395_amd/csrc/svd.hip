@@ -210,7 +210,8 @@ __global__ __launch_bounds__(SVD_THREADS) void svd_jacobi_kernel(int rows, int c
 // blocks (circle schedule).  For one pair of blocks: form the 16 x 16 FP64 Gram
 // of its columns on the MFMA, skip the pair if it is already orthogonal, else
 // diagonalise the Gram by cyclic two-sided Jacobi (relatively accurate on
-// positive definite matrices) while accumulating the rotation J, and replace
+// positive definite matrices; one sweep per round in the fast phase,
+// BJ_INNER_SWEEPS in the finishing kernel) while accumulating the rotation J, and replace
 // the 16 columns of X and V by X J and V J (MFMA again).  A sweep with no
 // rotation ends the iteration.  Columns below eps |X|_F are at the rounding
 // level of the block updates and are neither tested nor rotated.
@@ -227,27 +228,18 @@ __device__ __forceinline__ int circle_pos(int pos, int round, int n) {
   return pos == 0 ? 0 : 1 + (pos - 1 + round) % (n - 1);
 }
 
-// Round-robin schedule of 16 indices (8 disjoint pairs per round, 15 rounds).
-struct Sched16 {
-  int ia[15][8], ib[15][8];        // pair k of round r
-  int k[15][16], partner[15][16];  // pair index and partner of index c in round r
-};
-constexpr Sched16 make_sched16() {
-  Sched16 t{};
-  for (int r = 0; r < 15; ++r)
-    for (int k = 0; k < 8; ++k) {
-      const int a = k == 0 ? 0 : 1 + (k - 1 + r) % 15;
-      const int b = 1 + (15 - 1 - k + r) % 15;
-      t.ia[r][k] = a;
-      t.ib[r][k] = b;
-      t.k[r][a] = k;
-      t.k[r][b] = k;
-      t.partner[r][a] = b;
-      t.partner[r][b] = a;
-    }
-  return t;
+// Round-robin schedule of 16 indices in 15 rounds of 8 disjoint pairs: index
+// 0 stays at position 0, the others rotate one position per round, and pair k
+// of round r joins positions k and 15 - k.
+__device__ __forceinline__ int s16_elem(int pos, int r) { return pos == 0 ? 0 : 1 + (pos - 1 + r) % 15; }
+__device__ __forceinline__ int s16_pos(int c, int r) { return c == 0 ? 0 : 1 + (c + 14 - r) % 15; }
+
+// LDS ordering between the lanes of one wave.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-__constant__ Sched16 kSched16 = make_sched16();
 
 struct BjView {
   double* X; double* V; double* sig; int* rank; double* sgn; int* flags; double* fro2;
@@ -306,82 +298,117 @@ __global__ __launch_bounds__(256) void bj_norm_kernel(int rows, int cols, const 
   if (threadIdx.x == 0) v.fro2[0] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
-// Gram of the 16 columns cols(c) = block ba (c < 8) / bb (c >= 8), rows [r0, r1), by one wave.
+// Gram of the 16 columns cols(c) = block ba (c < 8) / bb (c >= 8), rows [r0, r1), by one wave;
+// 8 row quads are loaded before their MFMAs.
 __device__ __forceinline__ f64x4 pair_gram(const BjView& v, int ba, int bb, int r0, int r1) {
   const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
   const int mycol = c16 < 8 ? ba * BJ_B + c16 : bb * BJ_B + c16 - 8;
   const double* xc = v.X + mycol;
   f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-  int r = r0;
-  for (; r + 16 <= r1; r += 16) {
-    double x[4];
+  for (int r = r0; r < r1; r += 32) {
+    double x[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) x[u] = xc[(size_t)(r + 4 * u + g) * v.P];
+    for (int u = 0; u < 8; ++u) {
+      const int rr = r + 4 * u + g;
+      x[u] = rr < r1 ? xc[(size_t)rr * v.P] : 0.0;
+    }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u], x[u], acc, 0, 0, 0);
-  }
-  for (; r < r1; r += 4) {
-    const double x = (r + g < r1) ? xc[(size_t)(r + g) * v.P] : 0.0;
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, acc, 0, 0, 0);
+    for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u], x[u], acc, 0, 0, 0);
   }
   return acc;
 }
 
-// X <- X J, V <- V J on the pair's 16 columns for the 16-row tiles t = t0, t0 + dt, ...
-// jb[st] = J[4 st + g][c16].
+// X <- X J, V <- V J on the pair's 16 columns for the 16-row tiles t = t0, t0 + dt, ...,
+// TB tiles' loads in flight at a time.  jb[st] = J[4 st + g][c16].
+template <int TB>
 __device__ __forceinline__ void pair_apply(const BjView& v, int ba, int bb, const double (&jb)[4], int t0, int dt) {
   const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
   const int qt = (v.q + 15) >> 4, ntiles = qt + (v.P >> 4);
   const int outcol = c16 < 8 ? ba * BJ_B + c16 : bb * BJ_B + c16 - 8;
-  for (int t = t0; t < ntiles; t += dt) {
-    double* mat;
-    int r0, nr;
-    if (t < qt) { mat = v.X; r0 = t * 16; nr = v.q; }
-    else { mat = v.V; r0 = (t - qt) * 16; nr = v.P; }
-    f64x4 d = {0.0, 0.0, 0.0, 0.0};
-    double a[4];
+  int colk[4];
 #pragma unroll
-    for (int st = 0; st < 4; ++st) {
-      const int kc = 4 * st + g;
-      const int colk = kc < 8 ? ba * BJ_B + kc : bb * BJ_B + kc - 8;
+  for (int st = 0; st < 4; ++st) {
+    const int kc = 4 * st + g;
+    colk[st] = kc < 8 ? ba * BJ_B + kc : bb * BJ_B + kc - 8;
+  }
+  for (int tb = t0; tb < ntiles; tb += TB * dt) {
+    double a[TB][4];
+#pragma unroll
+    for (int u = 0; u < TB; ++u) {
+      const int t = tb + u * dt;
+      const double* mat = t < qt ? v.X : v.V;
+      const int r0 = t < qt ? t * 16 : (t - qt) * 16, nr = t < qt ? v.q : v.P;
       const int rr = r0 + c16;
-      a[st] = rr < nr ? mat[(size_t)rr * v.P + colk] : 0.0;
+#pragma unroll
+      for (int st = 0; st < 4; ++st) a[u][st] = (t < ntiles && rr < nr) ? mat[(size_t)rr * v.P + colk[st]] : 0.0;
     }
 #pragma unroll
-    for (int st = 0; st < 4; ++st) d = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], jb[st], d, 0, 0, 0);
+    for (int u = 0; u < TB; ++u) {
+      const int t = tb + u * dt;
+      if (t >= ntiles) break;
+      double* mat = t < qt ? v.X : v.V;
+      const int r0 = t < qt ? t * 16 : (t - qt) * 16, nr = t < qt ? v.q : v.P;
+      f64x4 d = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int rr = r0 + out_row<double>(g, i);
-      if (rr < nr) mat[(size_t)rr * v.P + outcol] = d[i];
+      for (int st = 0; st < 4; ++st) d = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][st], jb[st], d, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int rr = r0 + out_row<double>(g, i);
+        if (rr < nr) mat[(size_t)rr * v.P + outcol] = d[i];
+      }
     }
   }
 }
 
-// Rotation zeroing G[ia][ib] of the positive semidefinite G (one-sided Jacobi formulas).
+// Hardware reciprocal and reciprocal square root, each refined by one Newton step.
+__device__ __forceinline__ double rcp_nr(double x) {
+  const double y = __builtin_amdgcn_rcp(x);
+  return __builtin_fma(y, __builtin_fma(-x, y, 1.0), y);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = __builtin_fma(-x * y, y, 1.0);
+  return __builtin_fma(0.5 * y, e, y);
+}
+
+// Rotation zeroing G[ia][ib] of the positive semidefinite G (one-sided Jacobi
+// formulas).  The angle only steers convergence; c = (1 + t^2)^(-1/2) and
+// s = c t make the rotation orthogonal to rounding, which is what the accuracy
+// of X J and V J rests on.  The skip test compares squares (no square roots).
 __device__ __forceinline__ bool jacobi_rot(double al, double be, double ga, double tol, double floor2, double& c,
                                            double& sn) {
   c = 1.0;
   sn = 0.0;
-  if (!(al > floor2 && be > floor2 && fabs(ga) > tol * sqrt(al) * sqrt(be))) return false;
-  const double zeta = (be - al) / (2.0 * ga);
-  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  c = 1.0 / sqrt(1.0 + t * t);
+  if (!(al > floor2 && be > floor2 && ga * ga > (tol * tol) * (al * be))) return false;
+  const double zeta = (be - al) * (0.5 * rcp_nr(ga));
+  const double z2 = __builtin_fma(zeta, zeta, 1.0);
+  const double t = __builtin_copysign(rcp_nr(fabs(zeta) + z2 * rsq_nr(z2)), zeta);
+  c = rsq_nr(__builtin_fma(t, t, 1.0));
   sn = c * t;
   return true;
 }
 
 // One round of the fast phase: one workgroup (4 waves) per pair of blocks.
+// The grid holds BJ_PIN workgroups per pair and only every BJ_PIN-th one works,
+// so that (with workgroups dealt round-robin to the 8 XCDs) all working groups
+// of a matrix share one L2 from round to round.  The 16 x 16 Gram is
+// diagonalised by one Jacobi sweep in wave 0: lane (kp, kq) owns the 2 x 2
+// block of G at row pair kp and column pair kq of the current step (and the
+// matching block of J), computes both rotations itself, and writes the
+// rotated block to the other half of a double buffer.
+constexpr int BJ_PIN = 8;
+
 __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int round, int sweep,
                                                        double* __restrict__ ws) {
+  if ((blockIdx.x % BJ_PIN) != (blockIdx.y % BJ_PIN)) return;
   __shared__ double gp[4][16][17];
-  __shared__ double G[16][17];
-  __shared__ double J[16][17];
-  __shared__ double cs[8][2];
-  __shared__ int nrot, any_off;
+  __shared__ double Gb[2][16][17];
+  __shared__ double Jb[2][16][17];
+  __shared__ int any_off;
   BjView v = bj_view(ws, rows, cols, blockIdx.y);
   if (v.flags[0]) return;  // converged (uniform over the block)
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, c16 = lane & 15, g = lane >> 4;
-  const int pr = blockIdx.x;
+  const int pr = blockIdx.x / BJ_PIN;
   const int ba = circle_pos(pr, round, v.nb), bb = circle_pos(v.nb - 1 - pr, round, v.nb);
   {
     const int r0 = (int)(((int64_t)v.q * wave) / 4), r1 = (int)(((int64_t)v.q * (wave + 1)) / 4);
@@ -389,64 +416,69 @@ __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int r
 #pragma unroll
     for (int i = 0; i < 4; ++i) gp[wave][out_row<double>(g, i)][c16] = acc[i];
   }
-  if (tid == 0) { nrot = 0; any_off = 0; }
   __syncthreads();
   const double eps = 2.220446049250313e-16;
   const double tol = eps * (v.q > 16 ? (double)v.q : 16.0);
   const double floor2 = eps * eps * v.fro2[0];
-  {
-    const int i = tid >> 4, j = tid & 15;
-    G[i][j] = ((gp[0][i][j] + gp[1][i][j]) + gp[2][i][j]) + gp[3][i][j];
-    J[i][j] = i == j ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  {
-    const int i = tid >> 4, j = tid & 15;
-    if (i < j && G[i][i] > floor2 && G[j][j] > floor2 && fabs(G[i][j]) > tol * sqrt(G[i][i]) * sqrt(G[j][j]))
-      any_off = 1;
-  }
-  __syncthreads();
-  if (!any_off) return;  // uniform
-  if (tid == 0) v.flags[2 + sweep] = 1;
-  for (int is = 0; is < BJ_INNER_SWEEPS; ++is) {
-    if (tid == 0) nrot = 0;
-    __syncthreads();
-    for (int r = 0; r < 15; ++r) {
-      if (tid < 8) {
-        const int ia = kSched16.ia[r][tid], ib = kSched16.ib[r][tid];
-        double c, sn;
-        if (jacobi_rot(G[ia][ia], G[ib][ib], G[ia][ib], tol, floor2, c, sn)) atomicAdd(&nrot, 1);
-        cs[tid][0] = c;
-        cs[tid][1] = sn;
-      }
-      __syncthreads();
-      if (tid < 128) {  // columns of G
-        const int k = tid >> 4, i = tid & 15, ia = kSched16.ia[r][k], ib = kSched16.ib[r][k];
-        const double c = cs[k][0], sn = cs[k][1], u = G[i][ia], w = G[i][ib];
-        G[i][ia] = c * u - sn * w;
-        G[i][ib] = sn * u + c * w;
-      } else {          // columns of J
-        const int t2 = tid - 128, k = t2 >> 4, i = t2 & 15, ia = kSched16.ia[r][k], ib = kSched16.ib[r][k];
-        const double c = cs[k][0], sn = cs[k][1], u = J[i][ia], w = J[i][ib];
-        J[i][ia] = c * u - sn * w;
-        J[i][ib] = sn * u + c * w;
-      }
-      __syncthreads();
-      if (tid < 128) {  // rows of G
-        const int k = tid >> 4, j = tid & 15, ia = kSched16.ia[r][k], ib = kSched16.ib[r][k];
-        const double c = cs[k][0], sn = cs[k][1], u = G[ia][j], w = G[ib][j];
-        G[ia][j] = c * u - sn * w;
-        G[ib][j] = sn * u + c * w;
-      }
-      __syncthreads();
+  if (wave == 0) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = lane + 64 * t, i = e >> 4, j = e & 15;
+      Gb[0][i][j] = ((gp[0][i][j] + gp[1][i][j]) + gp[2][i][j]) + gp[3][i][j];
+      Jb[0][i][j] = i == j ? 1.0 : 0.0;
     }
-    if (nrot == 0) break;
-    __syncthreads();
+    wave_lds_sync();
+    bool off = false;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = lane + 64 * t, i = e >> 4, j = e & 15;
+      const double gi = Gb[0][i][i], gj = Gb[0][j][j], gij = Gb[0][i][j];
+      if (i < j && gi > floor2 && gj > floor2 && gij * gij > (tol * tol) * (gi * gj)) off = true;
+    }
+    const bool anyo = __ballot(off) != 0;
+    int cur = 0;
+    if (anyo) {
+      const int kp = lane >> 3, kq = lane & 7;
+      const int j0 = 2 * kp, j1 = 2 * kp + 1;
+      for (int r = 0; r < 15; ++r) {
+        const int pa = s16_elem(kp, r), pb = s16_elem(15 - kp, r);
+        const int qa = s16_elem(kq, r), qb = s16_elem(15 - kq, r);
+        const double (*G)[17] = Gb[cur];
+        const double (*J)[17] = Jb[cur];
+        const double paa = G[pa][pa], pbb = G[pb][pb], pab = G[pa][pb];
+        const double qaa = G[qa][qa], qbb = G[qb][qb], qab = G[qa][qb];
+        const double b00 = G[pa][qa], b01 = G[pa][qb], b10 = G[pb][qa], b11 = G[pb][qb];
+        const double j00 = J[j0][qa], j01 = J[j0][qb], j10 = J[j1][qa], j11 = J[j1][qb];
+        double cp, sp, cq, sq;
+        jacobi_rot(paa, pbb, pab, tol, floor2, cp, sp);
+        jacobi_rot(qaa, qbb, qab, tol, floor2, cq, sq);
+        // columns (right rotation by pair kq), then rows (left rotation by pair kp)
+        const double c00 = cq * b00 - sq * b01, c01 = sq * b00 + cq * b01;
+        const double c10 = cq * b10 - sq * b11, c11 = sq * b10 + cq * b11;
+        double (*Gn)[17] = Gb[cur ^ 1];
+        double (*Jn)[17] = Jb[cur ^ 1];
+        Gn[pa][qa] = cp * c00 - sp * c10;
+        Gn[pb][qa] = sp * c00 + cp * c10;
+        Gn[pa][qb] = cp * c01 - sp * c11;
+        Gn[pb][qb] = sp * c01 + cp * c11;
+        Jn[j0][qa] = cq * j00 - sq * j01;
+        Jn[j0][qb] = sq * j00 + cq * j01;
+        Jn[j1][qa] = cq * j10 - sq * j11;
+        Jn[j1][qb] = sq * j10 + cq * j11;
+        cur ^= 1;
+        wave_lds_sync();
+      }
+    }
+    if (lane == 0) any_off = anyo ? cur + 1 : 0;
   }
+  __syncthreads();
+  const int ao = any_off;
+  if (!ao) return;  // uniform
+  if (tid == 0) v.flags[2 + sweep] = 1;
   double jb[4];
 #pragma unroll
-  for (int st = 0; st < 4; ++st) jb[st] = J[4 * st + g][c16];
-  pair_apply(v, ba, bb, jb, wave, 4);
+  for (int st = 0; st < 4; ++st) jb[st] = Jb[ao - 1][4 * st + g][c16];
+  pair_apply<8>(v, ba, bb, jb, wave, 4);
 }
 
 __global__ void bj_sweep_end_kernel(int rows, int cols, int sweep, double* __restrict__ ws) {
@@ -482,7 +514,7 @@ __global__ __launch_bounds__(1024) void bj_finish_kernel(int rows, int cols, int
         const f64x4 acc = pair_gram(v, ba, bb, 0, v.q);
 #pragma unroll
         for (int i = 0; i < 4; ++i) G[out_row<double>(g, i)][c16] = acc[i];
-        __builtin_amdgcn_wave_barrier();
+        wave_lds_sync();
         bool off = false;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -499,30 +531,31 @@ __global__ __launch_bounds__(1024) void bj_finish_kernel(int rows, int cols, int
           bool any = false;
           for (int r = 0; r < 15; ++r) {
             if (lane < 8) {
-              const int ia = kSched16.ia[r][lane], ib = kSched16.ib[r][lane];
+              const int ia = s16_elem(lane, r), ib = s16_elem(15 - lane, r);
               double c, sn;
               any |= jacobi_rot(G[ia][ia], G[ib][ib], G[ia][ib], tol, floor2, c, sn);
               cs[wave][lane][0] = c;
               cs[wave][lane][1] = sn;
             }
-            __builtin_amdgcn_wave_barrier();
+            wave_lds_sync();
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
-              const int e = lane + 64 * t, k = e >> 4, i = e & 15, ia = kSched16.ia[r][k], ib = kSched16.ib[r][k];
+              const int e = lane + 64 * t, k = e >> 4, i = e & 15, ia = s16_elem(k, r), ib = s16_elem(15 - k, r);
               const double c = cs[wave][k][0], sn = cs[wave][k][1], u = G[i][ia], w = G[i][ib];
               G[i][ia] = c * u - sn * w;
               G[i][ib] = sn * u + c * w;
             }
-            __builtin_amdgcn_wave_barrier();
+            wave_lds_sync();
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
-              const int e = lane + 64 * t, k = e >> 4, j = e & 15, ia = kSched16.ia[r][k], ib = kSched16.ib[r][k];
+              const int e = lane + 64 * t, k = e >> 4, j = e & 15, ia = s16_elem(k, r), ib = s16_elem(15 - k, r);
               const double c = cs[wave][k][0], sn = cs[wave][k][1], u = G[ia][j], w = G[ib][j];
               G[ia][j] = c * u - sn * w;
               G[ib][j] = sn * u + c * w;
             }
             {
-              const int k = kSched16.k[r][c16], ia = kSched16.ia[r][k], partner = kSched16.partner[r][c16];
+              const int pos = s16_pos(c16, r), k = pos < 15 - pos ? pos : 15 - pos, ia = s16_elem(k, r),
+                        partner = s16_elem(15 - pos, r);
               const double c = cs[wave][k][0], sn = cs[wave][k][1];
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
@@ -530,18 +563,18 @@ __global__ __launch_bounds__(1024) void bj_finish_kernel(int rows, int cols, int
                 jr[i] = c16 == ia ? c * jr[i] - sn * other : sn * other + c * jr[i];
               }
             }
-            __builtin_amdgcn_wave_barrier();
+            wave_lds_sync();
           }
           if (__ballot(any) == 0) break;
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) G[4 * g + i][c16] = jr[i];
-        __builtin_amdgcn_wave_barrier();
+        wave_lds_sync();
         double jb[4];
 #pragma unroll
         for (int st = 0; st < 4; ++st) jb[st] = G[4 * st + g][c16];
-        pair_apply(v, ba, bb, jb, 0, 1);
-        __builtin_amdgcn_wave_barrier();
+        pair_apply<4>(v, ba, bb, jb, 0, 1);
+        wave_lds_sync();
       }
       __syncthreads();
     }
@@ -574,7 +607,7 @@ hipError_t launch_svd(int batch, int rows, int cols, const double* A, int64_t st
   hipLaunchKernelGGL(bj_norm_kernel, dim3(batch), dim3(256), 0, st, rows, cols, A, strideA, w);
   for (int sweep = 0; sweep < BJ_FAST_SWEEPS; ++sweep) {
     for (int round = 0; round < nb - 1; ++round)
-      hipLaunchKernelGGL(bj_round_kernel, dim3(nb / 2, batch), dim3(256), 0, st, rows, cols, round, sweep, w);
+      hipLaunchKernelGGL(bj_round_kernel, dim3(nb / 2 * BJ_PIN, batch), dim3(256), 0, st, rows, cols, round, sweep, w);
     hipLaunchKernelGGL(bj_sweep_end_kernel, dim3(batch), dim3(64), 0, st, rows, cols, sweep, w);
   }
   hipLaunchKernelGGL(bj_finish_kernel, dim3(batch), dim3(1024), 0, st, rows, cols, BJ_FAST_SWEEPS, U, strideU, S,
