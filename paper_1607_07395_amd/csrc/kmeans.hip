@@ -152,6 +152,167 @@ __global__ __launch_bounds__(256) void assign_kernel(int64_t rows, int dim, int 
   }
 }
 
+// Fast assignment for FP32 / BF16 / FP16 and dim <= AF_KMAX.  A workgroup
+// (4 waves, 64 rows) keeps each wave's 16 rows as 16-byte MFMA fragments in
+// registers for the whole kernel, and streams the centres through LDS in
+// chunks of AF_CT x 16, stored in fragment order so that every B read is one
+// contiguous ds_read_b128 per wave (no bank conflicts).  The next chunk is
+// prefetched into registers while the current one is multiplied.  Per lane
+// the k blocks, MFMA steps and columns come in the same order as in
+// assign_kernel, so distances, labels and gaps are bit-identical to it.
+constexpr int AF_KMAX = 256;
+constexpr int AF_CT = 4;
+
+template <typename TC> struct Vec16;
+template <> struct Vec16<float> {
+  __device__ static __forceinline__ float frag(const uint4& v, int s) { return __uint_as_float((&v.x)[s]); }
+};
+template <> struct Vec16<bf16> {
+  __device__ static __forceinline__ bf16x8 frag(const uint4& v, int) { return __builtin_bit_cast(bf16x8, v); }
+};
+template <> struct Vec16<f16> {
+  __device__ static __forceinline__ f16x8 frag(const uint4& v, int) { return __builtin_bit_cast(f16x8, v); }
+};
+
+// 16-byte run of VE elements of row `row` starting at column k0 (zero outside the matrix).
+template <typename TC>
+__device__ __forceinline__ uint4 load_run(const TC* __restrict__ X, int64_t nrows, int ld, int64_t row, int k0,
+                                          bool aligned) {
+  constexpr int VE = 16 / sizeof(TC);
+  uint4 v = {0u, 0u, 0u, 0u};
+  if (row >= nrows || k0 >= ld) return v;
+  const TC* src = X + row * ld + k0;
+  if (aligned && k0 + VE <= ld) return *(const uint4*)src;
+  TC tmp[VE];
+#pragma unroll
+  for (int e = 0; e < VE; ++e) tmp[e] = k0 + e < ld ? src[e] : zero_of<TC>();
+  return __builtin_bit_cast(uint4, tmp);
+}
+
+template <typename TC>
+__global__ __launch_bounds__(256, 2) void assign_fast_kernel(int64_t rows, int dim, int k, const TC* __restrict__ P,
+                                                             const TC* __restrict__ Zc,
+                                                             const double* __restrict__ znorm,
+                                                             const double* __restrict__ pnorm,
+                                                             int32_t* __restrict__ labels, double* __restrict__ dmin,
+                                                             double* __restrict__ gap, int p_aligned) {
+  typedef typename Mfma<TC>::acc AccV;
+  constexpr int VE = 16 / sizeof(TC);          // elements per 16-byte run
+  constexpr int SPV = VE / Mfma<TC>::KPL;      // MFMA steps per run
+  constexpr int KBW = 4 * VE;                  // k per block (4 lane groups)
+  constexpr int NKB = AF_KMAX / KBW;
+  constexpr int PF = AF_CT * NKB * 64 / 256;   // prefetch runs per thread
+  extern __shared__ uint4 zs[];                // [AF_CT][nkb][64] runs
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int g = lane >> 4, c16 = lane & 15;
+  const int nkb = (dim + KBW - 1) / KBW;
+  // Zc is 256-byte aligned workspace; P may come from a caller
+  const bool aligned = (dim % VE) == 0;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  uint4 a[NKB];
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb)
+    a[kb] = kb < nkb ? load_run<TC>(P, rows, dim, row0 + c16, kb * KBW + g * VE, aligned && p_aligned)
+                     : uint4{0u, 0u, 0u, 0u};
+  const int per_chunk = AF_CT * nkb * 64;
+  uint4 pf[PF];
+  auto prefetch = [&](int cc) {
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int e = tid + 256 * u;
+      if (e < per_chunk) {
+        const int t = e / (nkb * 64), rem = e - t * nkb * 64, kb = rem >> 6, l = rem & 63;
+        pf[u] = load_run<TC>(Zc, k, dim, cc + 16 * t + (l & 15), kb * KBW + (l >> 4) * VE, aligned);
+      }
+    }
+  };
+  float best[4], second[4];
+  int bidx[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) { best[i] = __builtin_huge_valf(); second[i] = __builtin_huge_valf(); bidx[i] = 0x7fffffff; }
+  prefetch(0);
+  for (int cc = 0; cc < k; cc += AF_CT * 16) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int e = tid + 256 * u;
+      if (e < per_chunk) zs[e] = pf[u];
+    }
+    __syncthreads();
+    if (cc + AF_CT * 16 < k) prefetch(cc + AF_CT * 16);
+    AccV acc[AF_CT];
+#pragma unroll
+    for (int t = 0; t < AF_CT; ++t) acc[t] = Mfma<TC>::zero();
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+      if (kb < nkb) {
+        uint4 b[AF_CT];
+#pragma unroll
+        for (int t = 0; t < AF_CT; ++t) b[t] = zs[(t * nkb + kb) * 64 + lane];
+#pragma unroll
+        for (int s2 = 0; s2 < SPV; ++s2)
+#pragma unroll
+          for (int t = 0; t < AF_CT; ++t)
+            acc[t] = Mfma<TC>::mma(Vec16<TC>::frag(a[kb], s2), Vec16<TC>::frag(b[t], s2), acc[t]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < AF_CT; ++t) {
+      const int col = cc + t * 16 + c16;
+      if (col < k) {
+        const float zn = (float)znorm[col];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float d = zn - 2.0f * acc[t][i];
+          if (d < best[i]) { second[i] = best[i]; best[i] = d; bidx[i] = col; }
+          else if (d < second[i]) second[i] = d;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      const float ob = __shfl_xor(best[i], off, 64);
+      const int obi = __shfl_xor(bidx[i], off, 64);
+      const float os = __shfl_xor(second[i], off, 64);
+      merge_best(best[i], bidx[i], second[i], ob, obi, os);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t row = row0 + out_row<TC>(g, i);
+    if (c16 == i && row < rows) {
+      labels[row] = bidx[i] < k ? bidx[i] : 0;  // all-NaN rows fall back to centre 0
+      const double dd = pnorm[row] + (double)best[i];
+      dmin[row] = dd > 0.0 ? dd : 0.0;
+      if (gap) gap[row] = (double)second[i] - (double)best[i];
+    }
+  }
+}
+
+template <typename TC> struct AssignFast { static constexpr bool ok = true; };
+template <> struct AssignFast<double> { static constexpr bool ok = false; };
+
+template <typename TC>
+static void launch_assign(int64_t rows, int dim, int k, const TC* P, const TC* Zc, const double* znorm,
+                          const double* pnorm, int32_t* labels, double* dmin, double* gap, hipStream_t st) {
+  if constexpr (AssignFast<TC>::ok) {
+    if (dim <= AF_KMAX) {
+      constexpr int KBW = 4 * (16 / (int)sizeof(TC));
+      const int nkb = (dim + KBW - 1) / KBW;
+      const size_t lds = (size_t)AF_CT * nkb * 64 * 16;
+      const int p_aligned = ((uintptr_t)P % 16) == 0 ? 1 : 0;
+      hipLaunchKernelGGL(assign_fast_kernel<TC>, dim3((unsigned)ceil_div(rows, 64)), dim3(256), lds, st, rows, dim, k,
+                         P, Zc, znorm, pnorm, labels, dmin, gap, p_aligned);
+      return;
+    }
+  }
+  hipLaunchKernelGGL(assign_kernel<TC>, dim3((unsigned)ceil_div(rows, 64)), dim3(256), 0, st, rows, dim, k, P, Zc,
+                     znorm, pnorm, labels, dmin, gap);
+}
+
 // ---------------------------------------------------------------------------
 // Stable counting sort of rows by label
 // ---------------------------------------------------------------------------
@@ -811,7 +972,6 @@ static hipError_t kmeans_t(int compute, int64_t rows, int dim, int k, const void
   KmWs W = km_layout(ws, rows, dim, k, compute);
   TC* Zc = (TC*)W.Zc;
   const int64_t nsb = ceil_div(rows, HIST_SB);
-  const unsigned gA = (unsigned)ceil_div(rows, 64);
   const unsigned gR = (unsigned)ceil_div(rows, 4);
   const int64_t maxch = ceil_div(rows, CENT_CH) + k;
   int32_t* labels = out.labels ? out.labels : W.labels;
@@ -827,8 +987,7 @@ static hipError_t kmeans_t(int compute, int64_t rows, int dim, int k, const void
     const bool last = it == iters;
     {
       TimerScope ts(T_ASSIGN, st);
-      hipLaunchKernelGGL(assign_kernel<TC>, dim3(gA), dim3(256), 0, st, rows, dim, k, P, (const TC*)Zc, W.znorm,
-                         W.pnorm, labels, W.dmin, last ? W.gap : nullptr);
+      launch_assign<TC>(rows, dim, k, P, (const TC*)Zc, W.znorm, W.pnorm, labels, W.dmin, last ? W.gap : nullptr, st);
     }
     if (it == 0 || last) {
       hipLaunchKernelGGL(wsum_partial_kernel, dim3(red_nb), dim3(256), 0, st, rows, w, W.dmin,
