@@ -10,10 +10,14 @@ N(0, 1e-3^2); k1 = k2 = 200, c = 5, FP32; error from 1e7 sampled entries).
 Every step draws a fresh pilot sample (seed = step index), like the paper's
 repeated runs.  Inputs (generator tables) are resident in HBM before timing.
 
-Prints one JSON line: sketches/s, latency percentiles, the roofline figure of
-the dominant kernel (the fused distance GEMM + argmin of the k-means, timed
-with HIP events on its launch stream inside the timed region) and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+Two timed phases over the same workload:
+  * sequential: K sketches one after another on one stream, with per-kernel
+    family timing (HIP events on the launch stream) for the roofline figure of
+    the k-means distance GEMM + argmin kernel;
+  * served: K sketch requests (sketch + error) through the continuous-batching
+    server, closed loop with --slots requests in flight; `value` is this
+    whole-job throughput and p50/p99 are its submit-to-completion latencies.
+Also prints the FP64 CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -42,6 +46,7 @@ def parse():
     ap.add_argument("--compute", default=None, help="f64 | f32 | bf16 | f16 (default: the workload's)")
     ap.add_argument("--err-samples", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--slots", type=int, default=4, help="server slots (requests in flight) in the served phase")
     ap.add_argument("--cpu-scale", type=float, default=0.1,
                     help="row/column scale of the workload the CPU oracle is timed on")
     return ap.parse_args()
@@ -133,19 +138,54 @@ def main():
     t1 = time.perf_counter()
     api.timing_enable(False)
 
-    elapsed = t1 - t0
+    seq_elapsed = t1 - t0
     lat = np.array([a.elapsed_time(b) for a, b in evs])
-    rel = np.array([float(e[2].item()) for e in errs])
+    rel_seq = np.array([float(e[2].item()) for e in errs])
     diag = out.diagnostics()
 
-    # dominant kernel: fused distance GEMM + argmin; (c + 1) assignments per side per sketch
-    e = min(k, k)
-    flops = args.steps * (iters + 1) * 2.0 * (spec.m + spec.n) * e * k
+    # dominant throughput kernel: fused distance GEMM + argmin; (c + 1) assignments per side per sketch
+    flops = args.steps * (iters + 1) * 2.0 * (spec.m + spec.n) * k * k
     a_ms, a_n = api.timing_read("assign")
     achieved = flops / (a_ms * 1e-3) / 1e12 if a_ms > 0 else 0.0
     peak = PEAK_TFLOPS[compute]
     fam = {f: api.timing_read(f) for f in ("assign", "eval", "tsgemm", "gram", "svd", "snap", "centroid", "error")}
     api.timing_reset()
+
+    # ---- served phase: closed loop, `slots` requests in flight ----
+    S = max(1, args.slots)
+    req_bytes = max(api.workspace_bytes(mat, prm), api.error_workspace_bytes(mat, prm, ns))
+    srv = api.Server(0, hbm_budget_bytes=S * (req_bytes + (1 << 20)), max_slots=S)
+    sets = [(api.alloc_result(mat, prm), torch.zeros(3, dtype=torch.float64, device="cuda")) for _ in range(S)]
+
+    def served(n_req, seed0):
+        free = list(range(S))
+        live = {}
+        lats, rels = [], []
+        nxt = 0
+        while nxt < n_req or live:
+            while free and nxt < n_req:
+                j = free.pop()
+                p = api.make_params(k, k, k, k, kmeans_iters=iters, compute=compute, seed=seed0 + nxt)
+                t = srv.submit(mat, p, sets[j][0], err_samples=ns, err_seed=1000 + seed0 + nxt, err_out=sets[j][1])
+                live[t] = j
+                nxt += 1
+            for t in list(live):
+                r = srv.poll(t)
+                if r is not None:
+                    j = live.pop(t)
+                    lats.append(r * 1e3)
+                    rels.append(float(sets[j][1][2].item()))
+                    free.append(j)
+            time.sleep(0.0002)
+        return np.array(lats), np.array(rels)
+
+    served(min(S, max(1, args.warmup)), 20_000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s_lat, s_rel = served(args.steps, 0)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    srv.close()
 
     result = {
         "metric": METRIC,
@@ -164,13 +204,17 @@ def main():
             "workload": (f"{spec.kind} {spec.m}x{spec.n}" + (f" r={spec.r} noise={spec.noise_std:g}" if spec.kind == "lowrank"
                          else f" d={spec.d}") + f", k1=k2={k}, c={iters}, error from {ns} sampled entries"),
             "m": spec.m, "n": spec.n, "k": k, "kmeans_iters": iters, "err_samples": ns,
-            "rel_frobenius_error_mean": float(rel.mean()), "rel_frobenius_error_max": float(rel.max()),
-            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mode": f"served: continuous-batching server, {S} requests in flight (closed loop), sketch + error each",
+            "rel_frobenius_error_mean": float(s_rel.mean()), "rel_frobenius_error_max": float(s_rel.max()),
+            "p50_ms": float(np.percentile(s_lat, 50)), "p99_ms": float(np.percentile(s_lat, 99)),
+            "sequential": {"sketches_per_s": args.steps / seq_elapsed, "ms_per_step": 1e3 * seq_elapsed / args.steps,
+                           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                           "rel_frobenius_error_mean": float(rel_seq.mean())},
             "rank_final": diag["rank_final"], "entries_touched": diag["entries"],
             "snap_full_scans": [diag["snap_scans_r"], diag["snap_scans_c"]],
         },
         "roofline": {
-            "kernel": "assign (fused distance GEMM + argmin)",
+            "kernel": "assign_fast_kernel (k-means distance GEMM + argmin), sequential phase",
             "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak if peak else None, "traffic": None,
             "launches": a_n, "avg_launch_ms": a_ms / max(a_n, 1),

@@ -237,12 +237,17 @@ typedef struct cabs_server cabs_server;
  * request workspaces are carved.  Returns NULL on failure (see cabs_last_error). */
 cabs_server* cabs_server_create(int32_t device, size_t hbm_budget_bytes, int32_t max_slots);
 
-/* Queue a sketch.  `mat`, `prm` and the device buffers named by `out` must stay
- * valid until the request completes or is cancelled.  The request is admitted
- * when a slot is free and its workspace fits in the pool; a request that can
- * never fit is rejected here with CABS_ENOMEM.  *ticket identifies it. */
+/* Queue a sketch, optionally followed by its relative Frobenius error
+ * (cabs_error with err_samples and err_seed, result {num, den, ratio} into the
+ * device array err_out3; err_out3 = NULL requests no error estimate).  `mat`
+ * and `prm` are copied; the device buffers they and `out` name, and err_out3,
+ * must stay valid until the request completes or is cancelled.  The request is admitted when a slot
+ * is free and its workspace (the larger of the sketch's and the error's; the
+ * error runs after the sketch on the same stream and reuses it) fits in the
+ * pool; a request that can never fit is rejected here with CABS_ENOMEM, a
+ * negative err_samples with CABS_EINVAL.  *ticket identifies it. */
 cabs_status cabs_submit(cabs_server* srv, const cabs_matrix* mat, const cabs_params* prm, const cabs_result* out,
-                        uint64_t* ticket);
+                        int64_t err_samples, uint64_t err_seed, double* err_out3, uint64_t* ticket);
 
 /* CABS_OK when finished (latency_s, host, may be NULL: submit-to-completion
  * seconds), CABS_EBUSY while queued or running, CABS_ECANCELED if cancelled,

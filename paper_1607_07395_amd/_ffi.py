@@ -75,7 +75,7 @@ _SIGS = {
     "cabs_timing_reset": (None, []),
     "cabs_server_create": (_P, [C.c_int32, C.c_size_t, C.c_int32]),
     "cabs_submit": (C.c_int, [_P, C.POINTER(CabsMatrix), C.POINTER(CabsParams), C.POINTER(CabsResult),
-                              C.POINTER(C.c_uint64)]),
+                              C.c_int64, C.c_uint64, _P, C.POINTER(C.c_uint64)]),
     "cabs_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(C.c_double)]),
     "cabs_cancel": (C.c_int, [_P, C.c_uint64]),
     "cabs_server_drain": (C.c_int, [_P]),

@@ -161,6 +161,13 @@ def workspace_bytes(mat: DeviceMatrix, prm: F.CabsParams) -> int:
     return int(n)
 
 
+def error_workspace_bytes(mat: DeviceMatrix, prm: F.CabsParams, n_samples: int) -> int:
+    n = F.lib().cabs_error_workspace_bytes(C.byref(mat.desc), C.byref(prm), n_samples)
+    if n == 0:
+        raise F.CabsError(F.EINVAL, "cabs_error_workspace_bytes")
+    return int(n)
+
+
 def sketch(mat: DeviceMatrix, prm: F.CabsParams, ws: Optional[torch.Tensor] = None,
            out: Optional[SketchResult] = None, stream=None) -> SketchResult:
     """cabs_sketch: enqueue one CABS sketch on the current (or given) stream."""
@@ -286,11 +293,20 @@ class Server:
             raise F.CabsError(F.EINVAL, "cabs_server_create")
         self._live = {}
 
-    def submit(self, mat: DeviceMatrix, prm: F.CabsParams, out: SketchResult) -> int:
+    def submit(self, mat: DeviceMatrix, prm: F.CabsParams, out: SketchResult, err_samples: Optional[int] = None,
+               err_seed: int = 0, err_out: Optional[torch.Tensor] = None) -> int:
+        """Queue a sketch into `out`; with err_samples set, also its relative
+        Frobenius error into err_out (3 float64 on the device: num, den, ratio)."""
         t = C.c_uint64(0)
-        F.check(F.lib().cabs_submit(self.h, C.byref(mat.desc), C.byref(prm), C.byref(out.struct), C.byref(t)),
-                "cabs_submit")
-        self._live[t.value] = (mat, prm, out)
+        p3 = None
+        if err_samples is not None:
+            if err_out is None or err_out.numel() < 3 or err_out.dtype != torch.float64:
+                raise ValueError("err_out must be a float64 device tensor of 3 elements")
+            p3 = _ptr(err_out)
+        prm_copy = F.CabsParams.from_buffer_copy(prm)
+        F.check(F.lib().cabs_submit(self.h, C.byref(mat.desc), C.byref(prm_copy), C.byref(out.struct),
+                                    int(err_samples or 0), int(err_seed), p3, C.byref(t)), "cabs_submit")
+        self._live[t.value] = (mat, prm_copy, out, err_out)
         return t.value
 
     def poll(self, ticket: int):

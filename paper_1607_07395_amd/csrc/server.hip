@@ -72,6 +72,9 @@ struct Request {
   cabs_matrix mat;
   cabs_params prm;
   cabs_result res;
+  int64_t err_samples = 0;
+  uint64_t err_seed = 0;
+  double* err_out3 = nullptr;
   size_t ws_bytes;
   size_t ws_off = 0;
   int slot = -1;
@@ -133,7 +136,10 @@ static void scheduler(cabs_server* s) {
       s->queue.pop_front();
       r.ws_off = off;
       r.slot = slot;
-      const int st = cabs_sketch(&r.mat, &r.prm, s->pool_base + off, r.ws_bytes, &r.res, s->streams[slot]);
+      int st = cabs_sketch(&r.mat, &r.prm, s->pool_base + off, r.ws_bytes, &r.res, s->streams[slot]);
+      if (st == CABS_OK && r.err_out3)
+        st = cabs_error(&r.mat, &r.prm, &r.res, r.err_samples, r.err_seed, s->pool_base + off, r.ws_bytes, r.err_out3,
+                        s->streams[slot]);
       if (st != CABS_OK) {
         r.status = st;
         r.state = FAILED;
@@ -183,10 +189,16 @@ extern "C" cabs_server* cabs_server_create(int32_t device, size_t hbm_budget_byt
 }
 
 extern "C" cabs_status cabs_submit(cabs_server* s, const cabs_matrix* mat, const cabs_params* prm,
-                                   const cabs_result* out, uint64_t* ticket) {
-  if (!s || !mat || !prm || !out || !ticket) return CABS_EINVAL;
-  const size_t need = cabs_workspace_bytes(mat, prm);
+                                   const cabs_result* out, int64_t err_samples, uint64_t err_seed, double* err_out3,
+                                   uint64_t* ticket) {
+  if (!s || !mat || !prm || !out || !ticket || err_samples < 0) return CABS_EINVAL;
+  size_t need = cabs_workspace_bytes(mat, prm);
   if (need == 0) return CABS_EINVAL;
+  if (err_out3) {
+    const size_t ew = cabs_error_workspace_bytes(mat, prm, err_samples);
+    if (ew == 0) return CABS_EINVAL;
+    need = ew > need ? ew : need;
+  }
   if (need > s->budget) return CABS_ENOMEM;
   if (!out->idx_r || !out->idx_c || !out->C || !out->Rt || !out->Umid) return CABS_EINVAL;
   std::lock_guard<std::mutex> g(s->mu);
@@ -195,6 +207,9 @@ extern "C" cabs_status cabs_submit(cabs_server* s, const cabs_matrix* mat, const
   r.mat = *mat;
   r.prm = *prm;
   r.res = *out;
+  r.err_samples = err_samples;
+  r.err_seed = err_seed;
+  r.err_out3 = err_out3;
   r.ws_bytes = need;
   r.t_submit = Clock::now();
   s->reqs[r.ticket] = r;
