@@ -47,7 +47,13 @@ def parse():
     ap.add_argument("--err-samples", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--slots", type=int, default=4, help="server slots (requests in flight) in the served phase")
-    ap.add_argument("--cpu-scale", type=float, default=0.1,
+    ap.add_argument("--no-served", action="store_true", help="skip the served phases (profiling runs)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the BF16 served form and the scaled-signal workload")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="before timing, copy a buffer of this many MiB device-to-device once (a kernel of known "
+                         "traffic for calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--cpu-scale", type=float, default=0.15,
                     help="row/column scale of the workload the CPU oracle is timed on")
     return ap.parse_args()
 
@@ -106,6 +112,13 @@ def main():
     ns = cfg["err_samples"] if args.err_samples is None else args.err_samples
     k, iters = cfg["k"], cfg["iters"]
 
+    if args.copy_probe_mb > 0:
+        src = torch.ones(args.copy_probe_mb << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     mat = api.DeviceMatrix(spec, storage=storage)
     prm = api.make_params(k, k, k, k, kmeans_iters=iters, compute=compute, seed=0)
     ws = api._dev_alloc(api.workspace_bytes(mat, prm), mat.device)
@@ -153,39 +166,72 @@ def main():
 
     # ---- served phase: closed loop, `slots` requests in flight ----
     S = max(1, args.slots)
-    req_bytes = max(api.workspace_bytes(mat, prm), api.error_workspace_bytes(mat, prm, ns))
-    srv = api.Server(0, hbm_budget_bytes=S * (req_bytes + (1 << 20)), max_slots=S)
-    sets = [(api.alloc_result(mat, prm), torch.zeros(3, dtype=torch.float64, device="cuda")) for _ in range(S)]
 
-    def served(n_req, seed0):
-        free = list(range(S))
-        live = {}
-        lats, rels = [], []
-        nxt = 0
-        while nxt < n_req or live:
-            while free and nxt < n_req:
-                j = free.pop()
-                p = api.make_params(k, k, k, k, kmeans_iters=iters, compute=compute, seed=seed0 + nxt)
-                t = srv.submit(mat, p, sets[j][0], err_samples=ns, err_seed=1000 + seed0 + nxt, err_out=sets[j][1])
-                live[t] = j
-                nxt += 1
-            for t in list(live):
-                r = srv.poll(t)
-                if r is not None:
-                    j = live.pop(t)
-                    lats.append(r * 1e3)
-                    rels.append(float(sets[j][1][2].item()))
-                    free.append(j)
-            time.sleep(0.0002)
-        return np.array(lats), np.array(rels)
+    def served(mat_, comp, n_req, seed0):
+        p0 = api.make_params(k, k, k, k, kmeans_iters=iters, compute=comp, seed=0)
+        req_bytes = max(api.workspace_bytes(mat_, p0), api.error_workspace_bytes(mat_, p0, ns))
+        srv = api.Server(0, hbm_budget_bytes=S * (req_bytes + (1 << 20)), max_slots=S)
+        sets = [(api.alloc_result(mat_, p0), torch.zeros(3, dtype=torch.float64, device="cuda")) for _ in range(S)]
 
-    served(min(S, max(1, args.warmup)), 20_000)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s_lat, s_rel = served(args.steps, 0)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    srv.close()
+        def run(n, s0):
+            free = list(range(S))
+            live = {}
+            lats, rels = [], []
+            nxt = 0
+            while nxt < n or live:
+                while free and nxt < n:
+                    j = free.pop()
+                    p = api.make_params(k, k, k, k, kmeans_iters=iters, compute=comp, seed=s0 + nxt)
+                    t = srv.submit(mat_, p, sets[j][0], err_samples=ns, err_seed=1000 + s0 + nxt, err_out=sets[j][1])
+                    live[t] = j
+                    nxt += 1
+                for t in list(live):
+                    r = srv.poll(t)
+                    if r is not None:
+                        j = live.pop(t)
+                        lats.append(r * 1e3)
+                        rels.append(float(sets[j][1][2].item()))
+                        free.append(j)
+                time.sleep(0.0002)
+            return np.array(lats), np.array(rels)
+
+        try:
+            run(min(S, max(1, args.warmup)), 20_000)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lat_, rel_ = run(n_req, seed0)
+            torch.cuda.synchronize()
+            return time.perf_counter() - t0, lat_, rel_
+        finally:
+            srv.close()
+
+    if args.no_served:
+        elapsed, s_lat, s_rel = seq_elapsed, lat, rel_seq
+        mode = "sequential (served phase skipped)"
+    else:
+        elapsed, s_lat, s_rel = served(mat, compute, args.steps, 0)
+        mode = f"served: continuous-batching server, {S} requests in flight (closed loop), sketch + error each"
+    variants = {}
+    if not args.no_served and not args.no_variants and compute == "f32":
+        # the mixed-precision served form on the same workload and seeds
+        e_b, l_b, r_b = served(mat, "bf16", args.steps, 0)
+        variants["bf16_served"] = {
+            "sketches_per_s": args.steps / e_b, "p50_ms": float(np.percentile(l_b, 50)),
+            "p99_ms": float(np.percentile(l_b, 99)), "rel_frobenius_error_mean": float(r_b.mean()),
+            "error_ratio_to_f32_served": float(r_b.mean() / s_rel.mean())}
+    if not args.no_variants and args.config == "lowrank1e5":
+        # the same shape with s_i = sqrt(mn)/i, so that the signal dominates the noise
+        spec_s, _ = workloads.config("lowrank1e5s")
+        mat_s = api.DeviceMatrix(spec_s, storage=storage)
+        out_s = api.alloc_result(mat_s, prm)
+        rs = []
+        for i in range(3):
+            p = api.make_params(k, k, k, k, kmeans_iters=iters, compute=compute, seed=i)
+            api.sketch(mat_s, p, out=out_s)
+            rs.append(float(api.error(mat_s, p, out_s, ns, seed=1000 + i)[2].item()))
+        variants["scaled_signal_f32"] = {"workload": "as above with s_i = sqrt(mn)/i", "rel_frobenius_error_mean":
+                                         float(np.mean(rs)), "sketches": 3}
+        del mat_s, out_s
 
     result = {
         "metric": METRIC,
@@ -204,7 +250,7 @@ def main():
             "workload": (f"{spec.kind} {spec.m}x{spec.n}" + (f" r={spec.r} noise={spec.noise_std:g}" if spec.kind == "lowrank"
                          else f" d={spec.d}") + f", k1=k2={k}, c={iters}, error from {ns} sampled entries"),
             "m": spec.m, "n": spec.n, "k": k, "kmeans_iters": iters, "err_samples": ns,
-            "mode": f"served: continuous-batching server, {S} requests in flight (closed loop), sketch + error each",
+            "mode": mode,
             "rel_frobenius_error_mean": float(s_rel.mean()), "rel_frobenius_error_max": float(s_rel.max()),
             "p50_ms": float(np.percentile(s_lat, 50)), "p99_ms": float(np.percentile(s_lat, 99)),
             "sequential": {"sketches_per_s": args.steps / seq_elapsed, "ms_per_step": 1e3 * seq_elapsed / args.steps,
@@ -212,6 +258,7 @@ def main():
                            "rel_frobenius_error_mean": float(rel_seq.mean())},
             "rank_final": diag["rank_final"], "entries_touched": diag["entries"],
             "snap_full_scans": [diag["snap_scans_r"], diag["snap_scans_c"]],
+            **variants,
         },
         "roofline": {
             "kernel": "assign_fast_kernel (k-means distance GEMM + argmin), sequential phase",

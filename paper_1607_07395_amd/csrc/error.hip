@@ -1,15 +1,19 @@
 // Relative Frobenius error |A - C Umid R|_F / |A|_F of a finished sketch (the
 // paper's error metric, Section 5).
 //
-// First CU = C Umid (m x kr) by the tall-skinny product, so the approximation
-// is A~_ij = CU_i . Rt_j.
+// First CU = C Umid (m x kr) in FP64 (C converted exactly to FP64, products
+// accumulated in FP64), so the approximation is A~_ij = CU_i . Rt_j.  Umid can
+// have large entries when W has small singular values; its product with C and
+// R then cancels heavily, so it is formed and dotted in FP64 whatever the
+// compute precision: the error is that of the returned factors themselves.
 // * sampled: n_s i.i.d. uniform entries from Philox stream 4; each group of 16
 //   lanes evaluates one entry: the k-long dot product of two gathered rows and
 //   the entry of A from its generator (r-long dot plus the Box-Muller noise, or
 //   the RBF of two d-long points, or a dense read), accumulated in FP64.
-// * exact: every entry, in 16 x 128 tiles per wave: the approximation and the
-//   generator both through the MFMA tile core, squared differences reduced in
-//   FP64 per block and then in a fixed order.
+// * exact: every entry, in 16 x 128 tiles per wave: the approximation (FP64
+//   MFMA on CU and an FP64 copy of Rt) and the generator (FP64 MFMA on the
+//   tables), squared differences reduced in FP64 per block and then in a fixed
+//   order.
 #include "common.hpp"
 #include "gemm_core.hpp"
 #include "kernels.hpp"
@@ -51,7 +55,7 @@ __device__ __forceinline__ double entry_f64(const MatView& mv, int64_t i, int64_
 }
 
 template <typename TIn, typename TC>
-__global__ __launch_bounds__(256) void err_sampled_kernel(MatView mv, int kr, const TC* __restrict__ CU,
+__global__ __launch_bounds__(256) void err_sampled_kernel(MatView mv, int kr, const double* __restrict__ CU,
                                                           const TC* __restrict__ Rt, int64_t ns, uint64_t seed,
                                                           double* __restrict__ part) {
   __shared__ double rn[16], rd[16];
@@ -65,9 +69,9 @@ __global__ __launch_bounds__(256) void err_sampled_kernel(MatView mv, int kr, co
     const int64_t i = (int64_t)mulhi_bound(w.v[0], (uint64_t)mv.m);
     const int64_t j = (int64_t)mulhi_bound(w.v[1], (uint64_t)mv.n);
     double ap = 0.0;
-    const TC* cu = CU + i * kr;
+    const double* cu = CU + i * kr;
     const TC* rt = Rt + j * kr;
-    for (int a = l16; a < kr; a += 16) ap += to_f64(cu[a]) * to_f64(rt[a]);
+    for (int a = l16; a < kr; a += 16) ap += cu[a] * to_f64(rt[a]);
     ap += __shfl_xor(ap, 1, 64);
     ap += __shfl_xor(ap, 2, 64);
     ap += __shfl_xor(ap, 4, 64);
@@ -86,9 +90,10 @@ __global__ __launch_bounds__(256) void err_sampled_kernel(MatView mv, int kr, co
   }
 }
 
-template <typename TIn, typename TC>
-__global__ __launch_bounds__(256) void err_exact_kernel(MatView mv, int kr, const TC* __restrict__ CU,
-                                                        const TC* __restrict__ Rt, double* __restrict__ part) {
+template <typename TIn>
+__global__ __launch_bounds__(256) void err_exact_kernel(MatView mv, int kr, const double* __restrict__ CU,
+                                                        const double* __restrict__ Rt, double* __restrict__ part) {
+  typedef double TC;
   typedef typename Mfma<TC>::acc AccV;
   typedef typename NormT<TC>::type NrmC;
   typedef typename NormT<TIn>::type NrmI;
@@ -102,10 +107,10 @@ __global__ __launch_bounds__(256) void err_exact_kernel(MatView mv, int kr, cons
       AccV ap[ERR_NT];
       NrmC xs, ys[ERR_NT];
       gemm_tile<TC, TC, ERR_NT, false>(CU, kr, mv.m, row0, Rt, kr, nullptr, mv.n, col0, nullptr, kr, ap, xs, ys);
-      typedef typename Mfma<typename std::conditional<sizeof(TC) == 8, double, float>::type>::acc AccA;
+      typedef typename Mfma<double>::acc AccA;
       AccA av[ERR_NT];
       NrmI xa = 0, ya[ERR_NT];
-      typedef typename std::conditional<sizeof(TC) == 8, double, float>::type TA;
+      typedef double TA;
       if (mv.kind == SRC_LOWRANK) {
         gemm_tile<TIn, TA, ERR_NT, false>((const TIn*)mv.pf, mv.r, mv.m, row0, (const TIn*)mv.qf, mv.r, nullptr, mv.n,
                                           col0, (const TIn*)mv.s, mv.r, av, xa, ya);
@@ -164,13 +169,38 @@ static inline int64_t exact_nb(const MatView& mv) { return ceil_div(mv.m, 64); }
 
 size_t error_ws_bytes(const MatView& mv, int k2c, int k2r, int compute, int64_t n_samples) {
   const int64_t nb = n_samples > 0 ? ERR_NB : exact_nb(mv);
-  return al256e((size_t)mv.m * k2r * prec_bytes(compute)) + tsgemm_ws_bytes(mv.m, k2c, k2r, compute) +
-         al256e((size_t)nb * 2 * sizeof(double)) + 256;
+  size_t b = al256e((size_t)mv.m * k2r * sizeof(double)) + tsgemm_ws_bytes(mv.m, k2c, k2r, P_F64) +
+             al256e((size_t)nb * 2 * sizeof(double)) + 256;
+  if (compute != P_F64) {
+    b += al256e((size_t)mv.m * k2c * sizeof(double));                     // C in FP64
+    if (n_samples == 0) b += al256e((size_t)mv.n * k2r * sizeof(double));  // Rt in FP64 (exact mode)
+  }
+  return b;
+}
+
+template <typename TC>
+__global__ __launch_bounds__(256) void widen_kernel(int64_t n, const TC* __restrict__ src, double* __restrict__ dst) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) dst[e] = to_f64(src[e]);
+}
+
+template <typename TC>
+static void widen(int64_t n, const void* src, double* dst, hipStream_t st) {
+  const unsigned g = (unsigned)std::min<int64_t>(ceil_div(n, 256), 8192);
+  hipLaunchKernelGGL(widen_kernel<TC>, dim3(g), dim3(256), 0, st, n, (const TC*)src, dst);
+}
+
+static void widen_any(int compute, int64_t n, const void* src, double* dst, hipStream_t st) {
+  switch (compute) {
+    case P_F32: widen<float>(n, src, dst, st); break;
+    case P_BF16: widen<bf16>(n, src, dst, st); break;
+    case P_F16: widen<f16>(n, src, dst, st); break;
+    default: break;
+  }
 }
 
 template <typename TIn, typename TC>
-static hipError_t error_t(const MatView& mv, int kr, const TC* CU, const TC* Rt, int64_t ns, uint64_t seed,
-                          double* part, double* out3, hipStream_t st) {
+static hipError_t error_t(const MatView& mv, int kr, const double* CU, const TC* Rt, const double* Rt64, int64_t ns,
+                          uint64_t seed, double* part, double* out3, hipStream_t st) {
   TimerScope ts(T_ERROR, st);
   int nb;
   if (ns > 0) {
@@ -178,7 +208,7 @@ static hipError_t error_t(const MatView& mv, int kr, const TC* CU, const TC* Rt,
     hipLaunchKernelGGL((err_sampled_kernel<TIn, TC>), dim3(nb), dim3(256), 0, st, mv, kr, CU, Rt, ns, seed, part);
   } else {
     nb = (int)exact_nb(mv);
-    hipLaunchKernelGGL((err_exact_kernel<TIn, TC>), dim3(nb), dim3(256), 0, st, mv, kr, CU, Rt, part);
+    hipLaunchKernelGGL((err_exact_kernel<TIn>), dim3(nb), dim3(256), 0, st, mv, kr, CU, Rt64, part);
   }
   hipLaunchKernelGGL(err_final_kernel, dim3(1), dim3(64), 0, st, nb, part, out3);
   return hipGetLastError();
@@ -186,22 +216,36 @@ static hipError_t error_t(const MatView& mv, int kr, const TC* CU, const TC* Rt,
 
 hipError_t launch_error(const MatView& mv, int k2c, int k2r, int compute, const void* C, const double* Umid,
                         const void* Rt, int64_t n_samples, uint64_t seed, void* ws, double* out3, hipStream_t st) {
+  if (mv.storage == P_F64 && compute != P_F64) return hipErrorInvalidValue;
+  if (compute < P_F64 || compute > P_F16) return hipErrorInvalidValue;
   char* p = (char*)ws;
-  void* CU = p;
-  p += al256e((size_t)mv.m * k2r * prec_bytes(compute));
+  double* CU = (double*)p;
+  p += al256e((size_t)mv.m * k2r * sizeof(double));
   void* tws = p;
-  p += tsgemm_ws_bytes(mv.m, k2c, k2r, compute);
+  p += tsgemm_ws_bytes(mv.m, k2c, k2r, P_F64);
   double* part = (double*)p;
-  hipError_t e = launch_tsgemm(mv.m, k2c, k2r, compute, C, Umid, CU, nullptr, nullptr, tws, st);
-  if (e != hipSuccess) return e;
-  if (mv.storage == P_F64) {
-    if (compute != P_F64) return hipErrorInvalidValue;
-    return error_t<double, double>(mv, k2r, (const double*)CU, (const double*)Rt, n_samples, seed, part, out3, st);
+  p += al256e((size_t)(n_samples > 0 ? ERR_NB : exact_nb(mv)) * 2 * sizeof(double));
+  const double* C64 = (const double*)C;
+  const double* Rt64 = (const double*)Rt;
+  if (compute != P_F64) {
+    double* c64 = (double*)p;
+    p += al256e((size_t)mv.m * k2c * sizeof(double));
+    widen_any(compute, (int64_t)mv.m * k2c, C, c64, st);
+    C64 = c64;
+    if (n_samples == 0) {
+      double* r64 = (double*)p;
+      widen_any(compute, (int64_t)mv.n * k2r, Rt, r64, st);
+      Rt64 = r64;
+    }
   }
+  hipError_t e = launch_tsgemm(mv.m, k2c, k2r, P_F64, C64, Umid, CU, nullptr, nullptr, tws, st);
+  if (e != hipSuccess) return e;
+  if (mv.storage == P_F64)
+    return error_t<double, double>(mv, k2r, CU, (const double*)Rt, Rt64, n_samples, seed, part, out3, st);
   switch (compute) {
-    case P_F32: return error_t<float, float>(mv, k2r, (const float*)CU, (const float*)Rt, n_samples, seed, part, out3, st);
-    case P_BF16: return error_t<float, bf16>(mv, k2r, (const bf16*)CU, (const bf16*)Rt, n_samples, seed, part, out3, st);
-    case P_F16: return error_t<float, f16>(mv, k2r, (const f16*)CU, (const f16*)Rt, n_samples, seed, part, out3, st);
+    case P_F32: return error_t<float, float>(mv, k2r, CU, (const float*)Rt, Rt64, n_samples, seed, part, out3, st);
+    case P_BF16: return error_t<float, bf16>(mv, k2r, CU, (const bf16*)Rt, Rt64, n_samples, seed, part, out3, st);
+    case P_F16: return error_t<float, f16>(mv, k2r, CU, (const f16*)Rt, Rt64, n_samples, seed, part, out3, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -1,0 +1,117 @@
+"""Full-size GPU checks of the configurations the benchmark times (through the C ABI).
+
+At these sizes the oracle cannot run a whole sketch inside a test, so this
+file checks what it can compute one by one:
+  * pilot indices, bit-exact with the oracle's sampler;
+  * single entries of the follow-up C and R^T against the oracle's entry
+    function;
+  * the sketching routine re-run by the oracle on the GPU's own follow-up
+    samples, compared through the CUR product at sampled entries;
+  * the sampled error, recomputed by the oracle on the GPU's factors at the
+    same Philox samples;
+and properties that hold at any size (sorted distinct in-range indices, W̄ the
+same block whether read from C̄ or from R̄ᵀ, finite diagnostics).
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import cabs as oc
+from oracle import philox
+from oracle.matrices import Matrix
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    from paper_1607_07395_amd import api as a
+    return a
+
+
+def _sketch(api, name, seed, ns):
+    spec, cfg = workloads.config(name)
+    k, iters = cfg["k"], cfg["iters"]
+    mat = api.DeviceMatrix(spec, storage="f32")
+    prm = api.make_params(k, k, k, k, kmeans_iters=iters, compute="f32", seed=seed)
+    res = api.sketch(mat, prm)
+    e3 = api.error(mat, prm, res, ns, seed=seed + 1000)
+    torch.cuda.synchronize()
+    return spec, k, prm, res, e3
+
+
+def _indices(spec, k, prm, res):
+    m, n = spec.m, spec.n
+    assert np.array_equal(res.pilot_r.cpu().numpy(), philox.floyd_sample(m, k, prm.seed, 0))
+    assert np.array_equal(res.pilot_c.cpu().numpy(), philox.floyd_sample(n, k, prm.seed, 1))
+    ir, ic = res.idx_r.cpu().numpy(), res.idx_c.cpu().numpy()
+    for idx, hi in ((ir, m), (ic, n)):
+        assert idx.size == k and idx[0] >= 0 and idx[-1] < hi and np.all(np.diff(idx) > 0)
+    return ir, ic
+
+
+def _entries(spec, res, ir, ic, tol):
+    M = Matrix(spec)
+    rng = np.random.default_rng(7)
+    k = ir.size
+    rows = rng.integers(0, spec.m, 4000)
+    pos = rng.integers(0, k, 4000)
+    got = res.C[torch.from_numpy(rows).cuda(), torch.from_numpy(pos).cuda()].double().cpu().numpy()
+    ref = M.entries(rows, ic[pos])
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+    cols = rng.integers(0, spec.n, 4000)
+    got = res.Rt[torch.from_numpy(cols).cuda(), torch.from_numpy(pos).cuda()].double().cpu().numpy()
+    ref = M.entries(ir[pos], cols)
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+    # W̄ read from C̄ (rows idx_r) and from R̄ᵀ (rows idx_c) is the same block of A, up to
+    # the FP32 rounding of two separately evaluated copies of each entry
+    w_c = res.C[res.idx_r].double().cpu().numpy()
+    w_r = res.Rt[res.idx_c].double().cpu().numpy().T
+    assert np.abs(w_c - w_r).max() <= 1e-5 * np.abs(w_c).max()
+
+
+def _error(spec, res, e3, ns, seed):
+    """The GPU's sampled error against the oracle's arithmetic at the same samples and factors."""
+    M = Matrix(spec)
+    i, j = philox.error_sample_indices(spec.m, spec.n, ns, seed)
+    a = M.entries(i, j)
+    ci = res.C[torch.from_numpy(i).cuda()].double().cpu().numpy()
+    rj = res.Rt[torch.from_numpy(j).cuda()].double().cpu().numpy()
+    umid = res.Umid.cpu().numpy()
+    at = np.einsum("tk,tk->t", ci @ umid, rj)
+    num, den = float(((a - at) ** 2).sum()), float((a * a).sum())
+    g = e3.cpu().numpy()
+    assert g[1] == pytest.approx(den, rel=1e-6)
+    assert g[0] == pytest.approx(num, rel=1e-3)
+    assert g[2] == pytest.approx(np.sqrt(num / den), rel=1e-3)
+
+
+def test_lowrank_1e5_x_2e4_rank200_fullsize(api):
+    ns = 100_000
+    spec, k, prm, res, e3 = _sketch(api, "lowrank1e5", seed=3, ns=ns)
+    ir, ic = _indices(spec, k, prm, res)
+    _entries(spec, res, ir, ic, tol=1e-4)
+    _error(spec, res, e3, ns, seed=prm.seed + 1000)
+    # the follow-up sketching routine, re-run by the oracle on the GPU's own samples
+    c = res.C.double().cpu().numpy()
+    rt = res.Rt.double().cpu().numpy()
+    sk = oc.sketching(c, rt, c[ir], spec.m, spec.n)
+    rng = np.random.default_rng(11)
+    i, j = rng.integers(0, spec.m, 20000), rng.integers(0, spec.n, 20000)
+    gpu = np.einsum("tk,tk->t", c[i] @ res.Umid.cpu().numpy(), rt[j])
+    ref = np.einsum("tk,tk->t", c[i] @ sk.Umid, rt[j])
+    assert np.abs(gpu - ref).max() <= 1e-4 * np.sqrt(np.mean(ref * ref))
+    d = res.diagnostics()
+    assert d["rank_final"] == int(sk.keep.sum())
+
+
+def test_rbf_1e6_x_1e6_d64_k500_fullsize(api):
+    ns = 50_000
+    spec, k, prm, res, e3 = _sketch(api, "rbf1e6", seed=1, ns=ns)
+    ir, ic = _indices(spec, k, prm, res)
+    _entries(spec, res, ir, ic, tol=1e-5)
+    _error(spec, res, e3, ns, seed=prm.seed + 1000)
+    d = res.diagnostics()
+    assert 0 < d["rank_final"] <= k and np.isfinite(d["sigma1_final"])
