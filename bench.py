@@ -53,9 +53,25 @@ def parse():
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="before timing, copy a buffer of this many MiB device-to-device once (a kernel of known "
                          "traffic for calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE)")
-    ap.add_argument("--cpu-scale", type=float, default=0.15,
+    ap.add_argument("--cpu-scale", type=float, default=0.5,
                     help="row/column scale of the workload the CPU oracle is timed on")
     return ap.parse_args()
+
+
+def pmc_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (profiles/pmc_traffic.json), or None when the kernel's source has changed
+    since the counters were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "pmc_traffic.json")) as f:
+            rec = json.load(f)[kernel]
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+                return None
+        return float(rec["bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(config: str, scale: float, err_samples: int) -> dict:
@@ -263,7 +279,10 @@ def main():
         "roofline": {
             "kernel": "assign_fast_kernel (k-means distance GEMM + argmin), sequential phase",
             "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak if peak else None, "traffic": None,
+            "frac": achieved / peak if peak else None,
+            "traffic": pmc_traffic("assign_fast_kernel") if compute == "f32" and args.config == "lowrank1e5" else None,
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, calibrated on a device copy; "
+                            "profiles/lowrank1e5_f32_pmc_traffic.md)",
             "launches": a_n, "avg_launch_ms": a_ms / max(a_n, 1),
         },
         "kernel_ms_per_step": {f: v[0] / args.steps for f, v in fam.items()},
