@@ -374,18 +374,21 @@ __device__ __forceinline__ double rsq_nr(double x) {
 // Rotation zeroing G[ia][ib] of the positive semidefinite G (one-sided Jacobi
 // formulas).  The angle only steers convergence; c = (1 + t^2)^(-1/2) and
 // s = c t make the rotation orthogonal to rounding, which is what the accuracy
-// of X J and V J rests on.  The skip test compares squares (no square roots).
+// of X J and V J rests on.  Branch-free, so that the two rotations a lane
+// needs per step run as interleaved chains: the skip test (squares, no roots)
+// selects the identity at the end.  When it passes, |zeta| <= 1 / (2 eps tol),
+// so zeta^2 cannot overflow; when it fails the temporaries are discarded.
 __device__ __forceinline__ bool jacobi_rot(double al, double be, double ga, double tol, double floor2, double& c,
                                            double& sn) {
-  c = 1.0;
-  sn = 0.0;
-  if (!(al > floor2 && be > floor2 && ga * ga > (tol * tol) * (al * be))) return false;
-  const double zeta = (be - al) * (0.5 * rcp_nr(ga));
+  const bool rot = al > floor2 && be > floor2 && ga * ga > (tol * tol) * (al * be);
+  const double gs = rot ? ga : 1.0;
+  const double zeta = (be - al) * (0.5 * rcp_nr(gs));
   const double z2 = __builtin_fma(zeta, zeta, 1.0);
   const double t = __builtin_copysign(rcp_nr(fabs(zeta) + z2 * rsq_nr(z2)), zeta);
-  c = rsq_nr(__builtin_fma(t, t, 1.0));
-  sn = c * t;
-  return true;
+  const double cr = rsq_nr(__builtin_fma(t, t, 1.0));
+  c = rot ? cr : 1.0;
+  sn = rot ? cr * t : 0.0;
+  return rot;
 }
 
 // One round of the fast phase: one workgroup (4 waves) per pair of blocks.

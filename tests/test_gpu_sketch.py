@@ -127,12 +127,15 @@ def test_factor_form_f64(api):
             assert np.abs(Vf[:, j] - v[:, j]).max() < 1e-8, j
 
 
-def test_error_sampled_matches_oracle(api):
-    spec = workloads.lowrank_noise(900, 500, 20, seed=2, noise_std=1e-2, s_kind="scaled")
+@pytest.mark.parametrize("m,n,ns", [(900, 500, 100_000),    # bucketed by row, one row per bucket
+                                    (900, 500, 600),        # fewer samples than rows: direct gather
+                                    (20000, 300, 50_000)])  # bucketed, three rows per bucket
+def test_error_sampled_matches_oracle(api, m, n, ns):
+    spec = workloads.lowrank_noise(m, n, 20, seed=2, noise_std=1e-2, s_kind="scaled")
     kw = dict(k1_rows=15, k1_cols=15, k2_rows=15, k2_cols=15, seed=1)
     mat, prm, res, ref = _compare_f64(api, spec, kw)
-    e = api.error(mat, prm, res, 100_000, seed=5).cpu().numpy()
-    rel, num, den = oc.rel_error_sampled(Matrix(spec), ref.C, ref.Umid, ref.Rt, 100_000, 5)
+    e = api.error(mat, prm, res, ns, seed=5).cpu().numpy()
+    rel, num, den = oc.rel_error_sampled(Matrix(spec), ref.C, ref.Umid, ref.Rt, ns, 5)
     assert e[0] == pytest.approx(num, rel=1e-8) and e[1] == pytest.approx(den, rel=1e-12)
     assert e[2] == pytest.approx(rel, rel=1e-8)
 
