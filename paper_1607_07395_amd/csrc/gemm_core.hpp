@@ -57,8 +57,38 @@ template <> struct NormT<double> { typedef double type; };
 template <typename T> __device__ __forceinline__ float widen(T v) { return (float)v; }
 __device__ __forceinline__ double widen(double v) { return v; }
 
+// Sixty-four zero bytes that out-of-range loads are pointed at, so that the
+// loads need no branches (internal to each code object; never written).
+static __device__ double4 kTileZero[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+
+// LK consecutive elements p[k .. k+LK-1] of one row.  Whole runs are vector
+// loads (16-byte pieces); `ok` false reads zeros.  All loads of a k block are
+// issued before any of them is used, with no branch in between.
+template <typename TIn, int LK>
+__device__ __forceinline__ void tile_run_vec(const TIn* p, int k, bool ok, TIn (&v)[LK]) {
+  static_assert((LK * sizeof(TIn)) % 16 == 0, "vector runs are whole 16-byte pieces");
+  constexpr int NP = LK * sizeof(TIn) / 16;
+  const uint4* src = (const uint4*)(ok ? p + k : (const TIn*)kTileZero);
+  uint4 w[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) w[q] = src[q];
+  const TIn* e = (const TIn*)w;
+#pragma unroll
+  for (int q = 0; q < LK; ++q) v[q] = e[q];
+}
+template <typename TIn, int LK>
+__device__ __forceinline__ void tile_run_elem(const TIn* p, int k, int K, bool ok, TIn (&v)[LK]) {
+#pragma unroll
+  for (int q = 0; q < LK; ++q) v[q] = *((ok && k + q < K) ? p + k + q : (const TIn*)kTileZero);
+}
+
 // The tile core.  xsq / ysq receive the per-lane partial sums of squares of
 // the X row and of each Y row (over this lane's k-group) when WANT_SQ.
+// K blocks that lie wholly inside K use vector loads when the rows allow it
+// (leading dimensions a multiple of LK, 16-byte aligned bases); the last,
+// partial block uses element loads.  For tables of at most 4-byte elements
+// the next block's loads are issued before the current block's MFMAs.  The
+// MFMA sequence per output element is the same on every path.
 template <typename TIn, typename TC, int NT, bool WANT_SQ>
 __device__ __forceinline__ void gemm_tile(const TIn* __restrict__ X, int64_t ldx, int64_t M, int64_t row0,
                                           const TIn* __restrict__ Y, int64_t ldy, const int64_t* __restrict__ yidx,
@@ -70,6 +100,8 @@ __device__ __forceinline__ void gemm_tile(const TIn* __restrict__ X, int64_t ldx
   constexpr int LK = TileK<TC>::LK;
   constexpr int KPL = Mfma<TC>::KPL;
   constexpr int STEPS = LK / KPL;
+  constexpr bool VEC_OK = (LK * sizeof(TIn)) % 16 == 0;
+  constexpr bool PREFETCH = sizeof(TIn) <= 4;
   const int lane = threadIdx.x & 63;
   const int r = lane & 15;
   const int g = lane >> 4;
@@ -88,25 +120,39 @@ __device__ __forceinline__ void gemm_tile(const TIn* __restrict__ X, int64_t ldx
     if (WANT_SQ) ysq[t] = 0;
   }
   if (WANT_SQ) xsq = 0;
-  for (int kb = 0; kb < K; kb += 4 * LK) {
+  const bool vec = VEC_OK && (ldx % LK) == 0 && (ldy % LK) == 0 && (((uintptr_t)X | (uintptr_t)Y) & 15) == 0 &&
+                   (ys == nullptr || ((uintptr_t)ys & 15) == 0);
+  auto fetch = [&](int kb, TIn (&xv)[LK], TIn (&yv)[NT][LK], TIn (&sv)[LK]) {
     const int k = kb + g * LK;
+    if (vec && kb + 4 * LK <= K) {
+      if constexpr (VEC_OK) {
+        tile_run_vec<TIn, LK>(xp, k, xok, xv);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) tile_run_vec<TIn, LK>(yp[t], k, yok[t], yv[t]);
+        if (ys != nullptr) tile_run_vec<TIn, LK>(ys, k, true, sv);
+      }
+    } else {
+      tile_run_elem<TIn, LK>(xp, k, K, xok, xv);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) tile_run_elem<TIn, LK>(yp[t], k, K, yok[t], yv[t]);
+      if (ys != nullptr) tile_run_elem<TIn, LK>(ys, k, K, true, sv);
+    }
+  };
+  auto compute = [&](const TIn (&xv)[LK], const TIn (&yv)[NT][LK], const TIn (&sv)[LK]) {
     TC av[LK];
 #pragma unroll
     for (int e = 0; e < LK; ++e) {
-      bool ok = xok && (k + e < K);
-      TIn x = ok ? xp[k + e] : zero_of<TIn>();
-      if (WANT_SQ) xsq += (NT_t)widen(x) * (NT_t)widen(x);
-      av[e] = cvt<TC, TIn>(x);
+      if (WANT_SQ) xsq += (NT_t)widen(xv[e]) * (NT_t)widen(xv[e]);
+      av[e] = cvt<TC, TIn>(xv[e]);
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       TC bv[LK];
 #pragma unroll
       for (int e = 0; e < LK; ++e) {
-        bool ok = yok[t] && (k + e < K);
-        TIn y = ok ? yp[t][k + e] : zero_of<TIn>();
+        TIn y = yv[t][e];
         if (WANT_SQ) ysq[t] += (NT_t)widen(y) * (NT_t)widen(y);
-        if (ys != nullptr && ok) y = (TIn)(y * ys[k + e]);
+        if (ys != nullptr) y = (TIn)(y * sv[e]);
         bv[e] = cvt<TC, TIn>(y);
       }
 #pragma unroll
@@ -116,6 +162,33 @@ __device__ __forceinline__ void gemm_tile(const TIn* __restrict__ X, int64_t ldx
         for (int e = 0; e < KPL; ++e) { as_[e] = av[s * KPL + e]; bs_[e] = bv[s * KPL + e]; }
         acc[t] = Mfma<TC>::mma(FragPack<TC, KPL>::get(as_, 0), FragPack<TC, KPL>::get(bs_, 0), acc[t]);
       }
+    }
+  };
+  TIn xv[LK], yv[NT][LK], sv[LK];
+#pragma unroll
+  for (int e = 0; e < LK; ++e) sv[e] = zero_of<TIn>();
+  if constexpr (PREFETCH) {
+    if (K > 0) fetch(0, xv, yv, sv);
+    for (int kb = 0; kb < K; kb += 4 * LK) {
+      TIn xn[LK], yn[NT][LK], sn[LK];
+#pragma unroll
+      for (int e = 0; e < LK; ++e) sn[e] = zero_of<TIn>();
+      const bool more = kb + 4 * LK < K;
+      if (more) fetch(kb + 4 * LK, xn, yn, sn);
+      compute(xv, yv, sv);
+      if (more) {
+#pragma unroll
+        for (int e = 0; e < LK; ++e) { xv[e] = xn[e]; sv[e] = sn[e]; }
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int e = 0; e < LK; ++e) yv[t][e] = yn[t][e];
+      }
+    }
+  } else {
+    for (int kb = 0; kb < K; kb += 4 * LK) {
+      fetch(kb, xv, yv, sv);
+      compute(xv, yv, sv);
     }
   }
   if (WANT_SQ) {
