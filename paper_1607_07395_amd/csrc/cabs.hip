@@ -120,6 +120,22 @@ __global__ void sqrt_vec_kernel(int p, const double* __restrict__ s, double* __r
   for (int j = threadIdx.x; j < p; j += blockDim.x) out[j] = s[j] > 0.0 ? sqrt(s[j]) : 0.0;
 }
 
+// w[j] = s[j]^(-1/2) for s[j] > p eps s[0] (s descending), else 0
+__global__ void rsqrt_trunc_kernel(int p, const double* __restrict__ s, double* __restrict__ w) {
+  const double eps = 2.220446049250313e-16;
+  const double smax = s[0];
+  for (int j = threadIdx.x; j < p; j += blockDim.x) {
+    const bool keep = smax > 0.0 && s[j] > (double)p * eps * smax;
+    w[j] = keep ? 1.0 / sqrt(s[j]) : 0.0;
+  }
+}
+
+// out[j] = a[j] b[j]
+__global__ void mul_vec_kernel(int p, const double* __restrict__ a, const double* __restrict__ b,
+                               double* __restrict__ out) {
+  for (int j = threadIdx.x; j < p; j += blockDim.x) out[j] = a[j] * b[j];
+}
+
 // B = diag(v) as a dense p x p matrix.
 __global__ void diag_mat_kernel(int p, const double* __restrict__ a, const double* __restrict__ b,
                                 double* __restrict__ B) {
@@ -448,6 +464,24 @@ static cabs_status run_round(const Plan& pl, RoundWs& R, int kr, int kc, const v
   const unsigned gb = (unsigned)ceil_div((int64_t)pp, 256);
   hipLaunchKernelGGL(scale2_kernel, dim3(gb), dim3(256), 0, st, p, R.Gs2, R.invc, R.invc, R.G2);
   hipLaunchKernelGGL(scale2_kernel, dim3(gb), dim3(256), 0, st, p, R.Gs2 + pp, R.invr, R.invr, R.G2 + pp);
+  if (p <= PCHOL_MAXP) {
+    // Pivoted Cholesky G = R^T R of both Grams (rank-revealing: pivots <= p eps of the unit diagonal
+    // stop it), K = R_u diag(S) R_v^T, SVD(K) = U_s S_1 V_s^T.  Since K V_s = U_s S_1,
+    // R_u^-1 U_s = diag(S) R_v^T V_s S_1^-1, so without any triangular solve
+    //   M_u = diag(invc S) R_v^T V_s S_1^(-1/2),  M_v = diag(invr S) R_u^T U_s S_1^(-1/2)
+    // map C^ and R^ to P = U' S_1^(1/2), Q = V' S_1^(1/2) (components with S_1 <= p eps S_1[0] dropped).
+    const double eps = 2.220446049250313e-16;
+    HIP_TRY(launch_pchol(2, p, R.G2, pp, (double)p * eps, R.E2V, pp, st));
+    HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, false, R.E2V + pp, p, true, nullptr, R.sk, nullptr, R.K, p, st));
+    HIP_TRY(launch_svd(1, p, p, R.K, 0, R.Us, 0, R.S1, 0, R.Vs, 0, R.svd_ws, st));
+    hipLaunchKernelGGL(rsqrt_trunc_kernel, dim3(1), dim3(1024), 0, st, p, R.S1, R.sq);
+    hipLaunchKernelGGL(mul_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.invc, R.sk, R.fpos);
+    hipLaunchKernelGGL(mul_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.invr, R.sk, R.fpos + p);
+    HIP_TRY(launch_small_gemm(p, p, p, R.E2V + pp, p, true, R.Vs, p, false, R.fpos, nullptr, R.sq, R.Mu, p, st));
+    HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, true, R.Us, p, false, R.fpos + p, nullptr, R.sq, R.Mv, p, st));
+    HIP_TRY(hipGetLastError());
+    return CABS_OK;
+  }
   // Eigen-decompositions G = E Lambda E^T (SVD of a PSD matrix), both in one launch.
   HIP_TRY(launch_svd(2, p, p, R.G2, pp, R.E2U, pp, R.E2S, p, R.E2V, pp, R.svd_ws, st));
   hipLaunchKernelGGL(eig_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.E2S, R.fpos, R.fneg);
@@ -558,13 +592,20 @@ extern "C" cabs_status cabs_sketch(const cabs_matrix* mat, const cabs_params* pr
   HIP_TRY(launch_small_gemm(pl.kc2, pl.kr2, pl.p2, S.r2.Vw, pl.p2, false, S.r2.Uw, pl.p2, true, nullptr, S.r2.dk,
                             nullptr, out->Umid, pl.kr2, st));
 
-  // 9: optional factor form: Uf = C^ N_c^-1 E_u Lambda^-1/2 U_s, S = S_1, Vf likewise.
+  // 9: optional factor form: Uf = U' (orthonormal), S = S_1, Vf = V', mapped from C^ and R^.
   if (fac) {
     const int p = pl.p2;
     RoundWs& R = S.r2;
-    HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, false, R.Us, p, false, R.invc, R.fneg, nullptr, R.Mu, p, st));
-    HIP_TRY(launch_small_gemm(p, p, p, R.E2V + (size_t)p * p, p, false, R.Vs, p, false, R.invr, R.fneg + p, nullptr,
-                              R.Mv, p, st));
+    if (p <= PCHOL_MAXP) {  // Cholesky route: M_u = diag(invc S) R_v^T V_s S_1^-1, M_v likewise
+      hipLaunchKernelGGL(mul_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.sq, R.sq, R.fneg);
+      HIP_TRY(launch_small_gemm(p, p, p, R.E2V + (size_t)p * p, p, true, R.Vs, p, false, R.fpos, nullptr, R.fneg,
+                                R.Mu, p, st));
+      HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, true, R.Us, p, false, R.fpos + p, nullptr, R.fneg, R.Mv, p, st));
+    } else {  // eigen route: M_u = diag(invc) E_u Lambda_u^-1/2 U_s
+      HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, false, R.Us, p, false, R.invc, R.fneg, nullptr, R.Mu, p, st));
+      HIP_TRY(launch_small_gemm(p, p, p, R.E2V + (size_t)p * p, p, false, R.Vs, p, false, R.invr, R.fneg + p, nullptr,
+                                R.Mv, p, st));
+    }
     HIP_TRY(launch_tsgemm(pl.m, p, p, pl.prec, R.Ch, R.Mu, out->Uf, nullptr, nullptr, R.ts_ws, st));
     HIP_TRY(launch_tsgemm(pl.n, p, p, pl.prec, R.Rh, R.Mv, out->Vf, nullptr, nullptr, R.ts_ws, st));
     // signs: largest-magnitude entry of each Uf column positive

@@ -52,6 +52,12 @@ hipError_t launch_small_gemm(int M, int N, int K, const double* A, int lda, bool
                              bool transB, const double* dl, const double* dm, const double* dr, double* C, int ldc,
                              hipStream_t st);
 
+// Pivoted Cholesky of `batch` PSD p x p matrices (p <= PCHOL_MAXP): Rf row k = R's row k with columns in the
+// original order, rows from the numerical rank on zero (pivots <= tol stop the factorisation).
+hipError_t launch_pchol(int batch, int p, const double* G, int64_t strideG, double tol, double* Rf, int64_t strideR,
+                        hipStream_t st);
+constexpr int PCHOL_MAXP = 204;
+
 // --- tall-skinny products, Grams, norms (tsgemm.hip) ---
 // Y (M x N, compute) = X (M x K, compute) * B (K x N, FP64); B is converted to the compute
 // precision into bt_ws (N x K).  colsq (N, FP64) receives column sums of squares of Y when

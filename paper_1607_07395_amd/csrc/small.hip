@@ -58,4 +58,135 @@ hipError_t launch_small_gemm(int M, int N, int K, const double* A, int lda, bool
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Pivoted Cholesky of a batch of positive semidefinite p x p matrices (FP64),
+// one work-group each: G[order, order] ~ R^T R, R upper trapezoidal in pivot
+// order.  Output Rf (p x p, row-major): row k is R's row k with its columns in
+// the ORIGINAL index order (zero at indices pivoted earlier), rows from the
+// rank on are zero.  Step k takes the largest remaining diagonal (lowest index
+// on ties) and stops once it is <= tol (rank = k).
+//
+// The upper triangle of the symmetric matrix stays in registers: the 6 x 6
+// tiles (TR, TC), TR <= TC, of a 34 x 34 tile grid (p <= 204) are numbered row
+// by row and thread t < 595 of the 640 owns tile t.  A step broadcasts the pivot row
+// through LDS; each thread updates its tile by the outer product of 6 + 6
+// entries of that row; the diagonal is kept in LDS.
+constexpr int PC_T = 6;                   // tile edge
+constexpr int PC_G = 34;                  // tiles per dimension
+constexpr int PC_NT = PC_G * (PC_G + 1) / 2;
+constexpr int PC_MAXP = PC_G * PC_T;      // 204
+constexpr int PC_THREADS = 640;           // 10 waves: >= PC_NT tile owners
+
+__global__ __launch_bounds__(PC_THREADS) void pchol_kernel(int p, const double* __restrict__ G, int64_t strideG, double tol,
+                                                     double* __restrict__ Rf, int64_t strideR) {
+  __shared__ double rowk[PC_MAXP];
+  __shared__ double diagv[PC_MAXP];
+  __shared__ int done[PC_MAXP];
+  __shared__ double wbest[16];
+  __shared__ int wbi[16];
+  __shared__ int s_piv;
+  __shared__ double s_d;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const double* Gb = G + blockIdx.x * strideG;
+  double* Rb = Rf + blockIdx.x * strideR;
+  // tile of this thread: row-major over the upper triangle of the tile grid
+  int tr = 0, rem = tid;
+  while (tr < PC_G && rem >= PC_G - tr) { rem -= PC_G - tr; ++tr; }
+  const bool owner = tid < PC_NT;
+  const int r0 = owner ? PC_T * tr : PC_MAXP, c0 = owner ? PC_T * (tr + rem) : PC_MAXP;
+  double val[PC_T][PC_T];
+#pragma unroll
+  for (int a = 0; a < PC_T; ++a)
+#pragma unroll
+    for (int b = 0; b < PC_T; ++b)
+      val[a][b] = (r0 + a < p && c0 + b < p) ? Gb[(int64_t)(r0 + a) * p + c0 + b] : 0.0;
+  for (int c = tid; c < p; c += PC_THREADS) {
+    done[c] = 0;
+    diagv[c] = Gb[(int64_t)c * p + c];
+  }
+  __syncthreads();
+  int k = 0;
+  for (; k < p; ++k) {
+    // pivot: largest remaining diagonal, lowest index on ties
+    double bd = -1.0;
+    int bi = 0x7fffffff;
+    for (int c = tid; c < p; c += PC_THREADS)
+      if (!done[c] && (diagv[c] > bd || (diagv[c] == bd && c < bi))) { bd = diagv[c]; bi = c; }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double od = __shfl_xor(bd, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (od > bd || (od == bd && oi < bi)) { bd = od; bi = oi; }
+    }
+    if (lane == 0) { wbest[wave] = bd; wbi[wave] = bi; }
+    for (int c = tid; c < PC_MAXP; c += PC_THREADS) rowk[c] = 0.0;
+    __syncthreads();
+    if (tid == 0) {
+      double d = wbest[0];
+      int pi = wbi[0];
+      for (int w = 1; w < PC_THREADS / 64; ++w)
+        if (wbest[w] > d || (wbest[w] == d && wbi[w] < pi)) { d = wbest[w]; pi = wbi[w]; }
+      s_piv = pi;
+      s_d = d;
+    }
+    __syncthreads();
+    const double d = s_d;
+    const int piv = s_piv;
+    if (!(d > tol)) break;  // uniform: nothing left above the threshold
+    const double rkk = sqrt(d);
+    // the pivot row of R over the remaining indices: entries (piv, j >= piv) sit in the tile row of
+    // piv, entries (i < piv, piv) in its tile column; r_kk itself at piv
+    if (piv >= r0 && piv < r0 + PC_T) {
+#pragma unroll
+      for (int a = 0; a < PC_T; ++a)
+        if (r0 + a == piv) {
+#pragma unroll
+          for (int b = 0; b < PC_T; ++b) {
+            const int c = c0 + b;
+            if (c < p && c > piv && !done[c]) rowk[c] = val[a][b] / rkk;
+          }
+        }
+    }
+    if (piv >= c0 && piv < c0 + PC_T) {
+#pragma unroll
+      for (int b = 0; b < PC_T; ++b)
+        if (c0 + b == piv) {
+#pragma unroll
+          for (int a = 0; a < PC_T; ++a) {
+            const int c = r0 + a;
+            if (c < piv && !done[c]) rowk[c] = val[a][b] / rkk;
+          }
+        }
+    }
+    if (tid == 0) rowk[piv] = rkk;
+    __syncthreads();
+    // Schur complement of the upper triangle (rowk is zero at earlier pivots; the pivot's own row
+    // and column change but are never read again; rowk is zero-padded to PC_MAXP)
+    double rj[PC_T];
+#pragma unroll
+    for (int b = 0; b < PC_T; ++b) rj[b] = c0 + b < PC_MAXP ? rowk[c0 + b] : 0.0;
+#pragma unroll
+    for (int a = 0; a < PC_T; ++a) {
+      const double ra = r0 + a < PC_MAXP ? rowk[r0 + a] : 0.0;
+#pragma unroll
+      for (int b = 0; b < PC_T; ++b) val[a][b] -= ra * rj[b];
+    }
+    for (int c = tid; c < p; c += PC_THREADS) {
+      const double v = rowk[c];
+      Rb[(int64_t)k * p + c] = v;
+      diagv[c] -= v * v;
+    }
+    if (tid == 0) done[piv] = 1;
+    __syncthreads();
+  }
+  for (int e = tid; e < (p - k) * p; e += PC_THREADS) Rb[(int64_t)k * p + e] = 0.0;
+}
+
+hipError_t launch_pchol(int batch, int p, const double* G, int64_t strideG, double tol, double* Rf, int64_t strideR,
+                        hipStream_t st) {
+  if (batch <= 0 || p <= 0 || p > PC_MAXP) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(pchol_kernel, dim3(batch), dim3(PC_THREADS), 0, st, p, G, strideG, tol, Rf, strideR);
+  return hipGetLastError();
+}
+
 }  // namespace cabs
