@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--compute", default=None, help="f64 | f32 | bf16 | f16 (default: the workload's)")
     ap.add_argument("--err-samples", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--slots", type=int, default=4, help="server slots (requests in flight) in the served phase")
+    ap.add_argument("--slots", type=int, default=8, help="server slots (requests in flight) in the served phase")
     ap.add_argument("--no-served", action="store_true", help="skip the served phases (profiling runs)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the BF16 served form and the scaled-signal workload")
