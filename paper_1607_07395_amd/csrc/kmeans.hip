@@ -416,7 +416,14 @@ __global__ __launch_bounds__(256) void scatter_kernel(int64_t rows, int64_t nsb,
   sorted[offs[(int64_t)labels[row] * nsb + sb] + rank_blk[row]] = (int32_t)row;
 }
 
-template <typename TC>
+// One block per chunk (at most CENT_CH rows of one label).  The chunk's row
+// indices and weights are staged in LDS; thread (row lane rl, column piece cv)
+// sums rows rl, rl + RL, ... of the chunk in increasing order, with the loads
+// of eight rows issued before any is used (rows past the chunk read a zero
+// buffer with weight 0); the RL lane sums are then added in lane order.  A
+// column piece is VW columns (one 16-byte load) when rows are 16-byte
+// aligned, else one column.
+template <typename TC, bool VEC>
 __global__ __launch_bounds__(256) void centroid_partial_kernel(int dim, const TC* __restrict__ P,
                                                                const double* __restrict__ w,
                                                                const int32_t* __restrict__ sorted,
@@ -424,21 +431,81 @@ __global__ __launch_bounds__(256) void centroid_partial_kernel(int dim, const TC
                                                                const int32_t* __restrict__ chunk_end,
                                                                const int32_t* __restrict__ nchunks,
                                                                double* __restrict__ part, double* __restrict__ partw) {
+  constexpr int VW = VEC ? 16 / (int)sizeof(TC) : 1;
+  constexpr int B = 8;
+  __shared__ int32_t srow[CENT_CH];
+  __shared__ double swt[CENT_CH];
+  __shared__ double red[256 * VW];
   const int c = blockIdx.x;
   if (c >= *nchunks) return;
-  const int32_t b = chunk_beg[c], e = chunk_end[c];
-  for (int col = threadIdx.x; col < dim; col += 256) {
-    double acc = 0.0;
-    for (int32_t pos = b; pos < e; ++pos) {
-      const int64_t row = sorted[pos];
-      acc += w[row] * to_f64(P[row * dim + col]);
-    }
-    part[(int64_t)c * dim + col] = acc;
+  const int tid = threadIdx.x;
+  const int32_t b = chunk_beg[c];
+  const int n = chunk_end[c] - b;
+  if (tid < n) {
+    const int32_t r = sorted[b + tid];
+    srow[tid] = r;
+    swt[tid] = w[r];
   }
-  if (threadIdx.x == 0) {
-    double ws = 0.0;
-    for (int32_t pos = b; pos < e; ++pos) ws += w[sorted[pos]];
-    partw[c] = ws;
+  __syncthreads();
+  if (tid < 64) {  // chunk weight: four consecutive weights per lane, then a fixed butterfly
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < CENT_CH / 64; ++i) {
+      const int q = tid * (CENT_CH / 64) + i;
+      s += q < n ? swt[q] : 0.0;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (tid == 0) partw[c] = s;
+  }
+  const int ncv = (dim + VW - 1) / VW;
+  const int ncvp = ncv < 256 ? ncv : 256;
+  const int RL = 256 / ncvp;
+  const int rl = tid / ncvp, cvo = tid % ncvp;
+  const TC* zero = (const TC*)kTileZero;
+  for (int cv0 = 0; cv0 < ncv; cv0 += ncvp) {
+    const int cv = cv0 + cvo;
+    const bool act = rl < RL && cv < ncv;
+    double acc[VW];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) acc[e] = 0.0;
+    for (int p0 = act ? rl : n; p0 < n; p0 += B * RL) {
+      TC x[B][VW];
+      double wu[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int q = p0 + u * RL;
+        const bool ok = q < n;
+        const int qq = ok ? q : 0;
+        wu[u] = ok ? swt[qq] : 0.0;
+        const TC* src = ok ? P + (int64_t)srow[qq] * dim + cv * VW : zero;
+        if constexpr (VEC) {
+          const uint4 v4 = *(const uint4*)src;
+          const TC* e = (const TC*)&v4;
+#pragma unroll
+          for (int i = 0; i < VW; ++i) x[u][i] = e[i];
+        } else {
+          x[u][0] = *src;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u)
+#pragma unroll
+        for (int e = 0; e < VW; ++e) acc[e] = fma(wu[u], to_f64(x[u][e]), acc[e]);
+    }
+    if (cv0 > 0) __syncthreads();  // previous pass has read red
+    if (act) {
+#pragma unroll
+      for (int e = 0; e < VW; ++e) red[(rl * ncvp + cvo) * VW + e] = acc[e];
+    }
+    __syncthreads();
+    for (int j = tid; j < ncvp * VW; j += 256) {
+      const int col = cv0 * VW + j;
+      if (col >= dim) continue;
+      double s = red[j];
+      for (int l = 1; l < RL; ++l) s += red[l * ncvp * VW + j];
+      part[(int64_t)c * dim + col] = s;
+    }
   }
 }
 
@@ -1007,8 +1074,13 @@ static hipError_t kmeans_t(int compute, int64_t rows, int dim, int k, const void
                        W.rank_blk, W.offs, W.sorted);
     {
       TimerScope ts(T_CENTROID, st);
-      hipLaunchKernelGGL(centroid_partial_kernel<TC>, dim3((unsigned)maxch), dim3(256), 0, st, dim, P, w, W.sorted,
-                         W.chunk_beg, W.chunk_end, W.nchunks, W.part, W.partw);
+      const bool vec = ((uintptr_t)P % 16) == 0 && ((size_t)dim * sizeof(TC)) % 16 == 0;
+      if (vec)
+        hipLaunchKernelGGL((centroid_partial_kernel<TC, true>), dim3((unsigned)maxch), dim3(256), 0, st, dim, P, w,
+                           W.sorted, W.chunk_beg, W.chunk_end, W.nchunks, W.part, W.partw);
+      else
+        hipLaunchKernelGGL((centroid_partial_kernel<TC, false>), dim3((unsigned)maxch), dim3(256), 0, st, dim, P, w,
+                           W.sorted, W.chunk_beg, W.chunk_end, W.nchunks, W.part, W.partw);
     }
     hipLaunchKernelGGL(centroid_final_kernel<TC>, dim3(k), dim3(256), 0, st, k, dim, W.lchunk, W.part, W.partw, out.Z,
                        Zc, W.znorm);

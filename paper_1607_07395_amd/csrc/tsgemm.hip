@@ -141,104 +141,243 @@ hipError_t launch_tsgemm(int64_t M, int K, int N, int compute, const void* X, co
 
 // ---------------------------------------------------------------------------
 // Gram
+//
+// The grid is (row block) x (tile group).  A tile group is GRAM_TPB
+// consecutive tiles of the lower triangle (row-major), GRAM_TPW per wave.  A
+// block streams its rows through LDS in stages of `rs` rows: the stage is
+// loaded with coalesced element loads into registers while the previous one
+// is consumed (one 16x16x4 FP64 MFMA per tile and row quad, both operands
+// read from LDS).  Rows are added in increasing order, so each tile partial
+// has a fixed rounding order; partials are then summed over row blocks in
+// increasing block order by a second kernel.
 // ---------------------------------------------------------------------------
 constexpr int GRAM_TPW = 8;          // 16x16 tiles per wave
 constexpr int GRAM_TPB = 4 * GRAM_TPW;
-constexpr int GRAM_MAX_NB = 128;
+constexpr int GRAM_MAX_NB = 256;
+constexpr int GRAM_TARGET_BLOCKS = 768;  // three 256-thread blocks per CU
+constexpr int GRAM_MAX_RS = 64;
 
-static inline int gram_nb(int64_t M) {
-  int64_t nb = ceil_div(M, 512);
-  return (int)(nb < 1 ? 1 : nb > GRAM_MAX_NB ? GRAM_MAX_NB : nb);
+template <typename TC> struct GramEpt { static constexpr int v = 32; };
+template <> struct GramEpt<double> { static constexpr int v = 16; };
+
+struct GramPlan {
+  int nt, ntiles, ng, nb;
+  int64_t rows_per;
+};
+
+static inline int tri_row(int t) {
+  int a = (int)((std::sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((a + 1) * (a + 2) / 2 <= t) ++a;
+  while (a * (a + 1) / 2 > t) --a;
+  return a;
+}
+
+static inline GramPlan gram_plan(int64_t M, int K) {
+  GramPlan g;
+  g.nt = (K + 15) / 16;
+  g.ntiles = g.nt * (g.nt + 1) / 2;
+  g.ng = (int)ceil_div(g.ntiles, GRAM_TPB);
+  int64_t nb = ceil_div(GRAM_TARGET_BLOCKS, g.ng);
+  nb = std::min<int64_t>(nb, ceil_div(M, 16));
+  nb = std::max<int64_t>(1, std::min<int64_t>(nb, GRAM_MAX_NB));
+  if (nb > 8) nb = ceil_div(nb, 8) * 8;
+  g.rows_per = ceil_div(M, nb);
+  g.nb = (int)ceil_div(M, g.rows_per);
+  return g;
+}
+
+// Staging geometry of one tile group: kal columns are read by the fragments
+// (zero beyond K), kb = min(K, kal) are loaded, rows sit `stride` bytes apart
+// (16 elements of padding modulo 256 bytes, so the four rows of a fragment
+// fall on different LDS banks), and `rs` rows form one stage.
+struct GramStage {
+  int kal, kb, stride, rs;
+};
+__host__ __device__ inline GramStage gram_stage(int K, int ti_max, int esz, int ept) {
+  GramStage s;
+  s.kal = 16 * (ti_max + 1);
+  s.kb = K < s.kal ? K : s.kal;
+  const int want = 16 * esz;
+  s.stride = s.kal * esz + ((((want - s.kal * esz) % 256) + 256) % 256);
+  int rs = ((ept * 256) / s.kb) & ~3;
+  s.rs = rs < 4 ? 4 : rs > GRAM_MAX_RS ? GRAM_MAX_RS : rs;
+  return s;
+}
+
+__device__ __forceinline__ int tri_row_dev(int t) {
+  int a = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((a + 1) * (a + 2) / 2 <= t) ++a;
+  while (a * (a + 1) / 2 > t) --a;
+  return a;
 }
 
 template <typename TC>
-__global__ __launch_bounds__(256) void gram_kernel(int64_t M, int K, const TC* __restrict__ X, int ntiles,
-                                                   double* __restrict__ part) {
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int r = lane & 15, g = lane >> 4;
-  const int64_t nb = gridDim.x;
-  const int64_t rows_per = ceil_div(M, nb);
-  const int64_t rbeg = blockIdx.x * rows_per;
+__global__ __launch_bounds__(256) void gram_kernel(int64_t M, int K, const TC* __restrict__ X, int ntiles, int ng,
+                                                   int nb, int64_t rows_per, double* __restrict__ part) {
+  constexpr int EPT = GramEpt<TC>::v;
+  constexpr int ESZ = (int)sizeof(TC);
+  extern __shared__ __align__(16) unsigned char gram_lds[];
+  // XCD-aware order: consecutive block ids go to different XCDs, so the
+  // tile groups of one row block are given ids that share an XCD (and its L2).
+  const int id = blockIdx.x, xcd = id & 7, slot = id >> 3;
+  const int grp = slot % ng, rb = (slot / ng) * 8 + xcd;
+  if (rb >= nb) return;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
+  const int64_t rbeg = (int64_t)rb * rows_per;
   const int64_t rend = rbeg + rows_per < M ? rbeg + rows_per : M;
-  // Tiles of the lower triangle, enumerated row by row: tile t -> (ti, tj), tj <= ti.
+
   int ti[GRAM_TPW], tj[GRAM_TPW];
   bool ok[GRAM_TPW];
   f64x4 acc[GRAM_TPW];
 #pragma unroll
   for (int q = 0; q < GRAM_TPW; ++q) {
-    const int t = blockIdx.y * GRAM_TPB + wave * GRAM_TPW + q;
+    const int t = grp * GRAM_TPB + wave * GRAM_TPW + q;
     ok[q] = t < ntiles;
-    int a = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-    while ((a + 1) * (a + 2) / 2 <= t) ++a;
-    while (a * (a + 1) / 2 > t) --a;
-    ti[q] = a;
-    tj[q] = t - a * (a + 1) / 2;
+    const int a = tri_row_dev(ok[q] ? t : 0);
+    ti[q] = ok[q] ? a : 0;
+    tj[q] = ok[q] ? t - a * (a + 1) / 2 : 0;
     acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
   }
-  for (int64_t r0 = rbeg; r0 < rend; r0 += 4) {
-    const int64_t row = r0 + g;
-    const bool rok = row < rend;
-    const TC* xr = X + (rok ? row : 0) * K;
+  const int tlast = min(grp * GRAM_TPB + GRAM_TPB, ntiles) - 1;
+  const GramStage sg = gram_stage(K, tri_row_dev(tlast), ESZ, EPT);
+  const int rs = sg.rs, kb = sg.kb, stride = sg.stride;
+
+  // Fragment columns in [kb, kal) stay zero for the whole kernel.
+  for (int e = tid; e < rs * (sg.kal - kb); e += 256) {
+    const int row = e / (sg.kal - kb), col = kb + e % (sg.kal - kb);
+    *(TC*)(gram_lds + row * stride + col * ESZ) = (TC)0.0f;
+  }
+
+  // Element e = i*256 + tid of a stage is (row e / kb, column e % kb).
+  const int step_r = 256 / kb, step_c = 256 % kb;
+  const int row_t = tid / kb, col_t = tid % kb;
+  const TC* zero = (const TC*)kTileZero;
+  TC v[EPT];
+  auto load = [&](int64_t r0) {
+    int row = row_t, col = col_t;
+    asm volatile("" : "+v"(row), "+v"(col));  // recomputed per stage, not held in registers
 #pragma unroll
-    for (int q = 0; q < GRAM_TPW; ++q) {
-      if (!ok[q]) continue;
-      const int ca = ti[q] * 16 + r, cb = tj[q] * 16 + r;
-      const double av = (rok && ca < K) ? to_f64(xr[ca]) : 0.0;
-      const double bv = (rok && cb < K) ? to_f64(xr[cb]) : 0.0;
-      acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+    for (int i = 0; i < EPT; ++i) {
+      const bool in = row < rs && r0 + row < rend;
+      const TC* src = in ? X + (r0 + row) * (int64_t)K + col : zero;
+      v[i] = *src;
+      col += step_c;
+      row += step_r;
+      if (col >= kb) { col -= kb; ++row; }
+    }
+  };
+  auto store = [&]() {
+    int row = row_t, col = col_t;
+    asm volatile("" : "+v"(row), "+v"(col));  // recomputed per stage, not held in registers
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      if (row < rs) *(TC*)(gram_lds + row * stride + col * ESZ) = v[i];
+      col += step_c;
+      row += step_r;
+      if (col >= kb) { col -= kb; ++row; }
+    }
+  };
+
+  const int64_t nrows = rend > rbeg ? rend - rbeg : 0;
+  const int nst = (int)ceil_div(nrows, rs);
+  if (nst > 0) load(rbeg);
+  for (int s = 0; s < nst; ++s) {
+    __syncthreads();
+    store();
+    __syncthreads();
+    if (s + 1 < nst) load(rbeg + (int64_t)(s + 1) * rs);
+    const unsigned char* base = gram_lds + g * stride + r * ESZ;
+#pragma unroll 2
+    for (int qd = 0; qd < rs / 4; ++qd) {
+      const unsigned char* rowp = base + 4 * qd * stride;
+#pragma unroll
+      for (int q = 0; q < GRAM_TPW; ++q) {
+        if (!ok[q]) continue;  // uniform over the wave
+        const double av = to_f64(*(const TC*)(rowp + ti[q] * 16 * ESZ));
+        const double bv = to_f64(*(const TC*)(rowp + tj[q] * 16 * ESZ));
+        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
+      }
     }
   }
-  // part layout: [tile][block][256]
+  // part layout: [tile][row block][256]
 #pragma unroll
   for (int q = 0; q < GRAM_TPW; ++q) {
     if (!ok[q]) continue;
-    const int t = blockIdx.y * GRAM_TPB + wave * GRAM_TPW + q;
-    double* dst = part + ((int64_t)t * nb + blockIdx.x) * 256;
+    const int t = grp * GRAM_TPB + wave * GRAM_TPW + q;
+    double* dst = part + ((int64_t)t * nb + rb) * 256;
 #pragma unroll
     for (int i = 0; i < 4; ++i) dst[out_row<double>(g, i) * 16 + r] = acc[q][i];
   }
 }
 
+// One block per (tile, quarter of the tile): four groups of 64 threads sum
+// four fixed ranges of row blocks in increasing order, then the four sums are
+// added in a fixed order.
 __global__ __launch_bounds__(256) void gram_reduce_kernel(int K, int nb, const double* __restrict__ part,
                                                           double* __restrict__ G) {
+  __shared__ double red[4][64];
   const int t = blockIdx.x;
-  int a = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while ((a + 1) * (a + 2) / 2 <= t) ++a;
-  while (a * (a + 1) / 2 > t) --a;
+  const int a = tri_row_dev(t);
   const int ti = a, tj = t - a * (a + 1) / 2;
-  const int e = threadIdx.x;
+  const int e = blockIdx.y * 64 + (threadIdx.x & 63), c = threadIdx.x >> 6;
+  const int b0 = (int)(((int64_t)nb * c) / 4), b1 = (int)(((int64_t)nb * (c + 1)) / 4);
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += part[((int64_t)t * nb + b) * 256 + e];
+  for (int b = b0; b < b1; ++b) s += part[((int64_t)t * nb + b) * 256 + e];
+  red[c][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (c != 0) return;
+  const int l = threadIdx.x;
+  const double tot = (red[0][l] + red[1][l]) + (red[2][l] + red[3][l]);
   const int i = ti * 16 + e / 16, j = tj * 16 + e % 16;
   if (i < K && j < K) {
-    G[(int64_t)i * K + j] = s;
-    G[(int64_t)j * K + i] = s;
+    G[(int64_t)i * K + j] = tot;
+    G[(int64_t)j * K + i] = tot;
   }
 }
 
 size_t gram_ws_bytes(int64_t M, int K) {
-  const int nt = (K + 15) / 16;
-  const int64_t ntiles = (int64_t)nt * (nt + 1) / 2;
-  return align256((size_t)ntiles * gram_nb(M) * 256 * sizeof(double));
+  // The call may use any K' <= K (the retained rank), and the row-block count
+  // grows as the tile count falls, so take the largest product.
+  size_t best = 0;
+  for (int kk = 16; kk < K + 16; kk += 16) {
+    const GramPlan g = gram_plan(M, kk < K ? kk : K);
+    best = std::max(best, (size_t)g.ntiles * g.nb * 256 * sizeof(double));
+  }
+  return align256(best);
+}
+
+template <typename TC>
+static size_t gram_lds_bytes(const GramPlan& g, int K) {
+  size_t best = 0;
+  for (int grp = 0; grp < g.ng; ++grp) {
+    const int tlast = std::min(grp * GRAM_TPB + GRAM_TPB, g.ntiles) - 1;
+    const GramStage s = gram_stage(K, tri_row(tlast), (int)sizeof(TC), GramEpt<TC>::v);
+    best = std::max(best, (size_t)s.rs * s.stride);
+  }
+  return best;
+}
+
+template <typename TC>
+static void gram_launch(const GramPlan& g, int64_t M, int K, const TC* X, double* part, hipStream_t st) {
+  const int nblk = (int)(ceil_div(g.nb, 8) * 8 * g.ng);
+  hipLaunchKernelGGL(gram_kernel<TC>, dim3(nblk), dim3(256), gram_lds_bytes<TC>(g, K), st, M, K, X, g.ntiles, g.ng,
+                     g.nb, g.rows_per, part);
 }
 
 hipError_t launch_gram(int64_t M, int K, int compute, const void* X, double* G, void* ws, hipStream_t st) {
-  if (M <= 0 || K <= 0) return hipErrorInvalidValue;
+  // K <= 1024 keeps one stage within one register load per thread and element slot.
+  if (M <= 0 || K <= 0 || K > 1024) return hipErrorInvalidValue;
   TimerScope ts(T_GRAM, st);
-  const int nt = (K + 15) / 16;
-  const int ntiles = nt * (nt + 1) / 2;
-  const int nb = gram_nb(M);
-  dim3 grid(nb, (unsigned)ceil_div(ntiles, GRAM_TPB));
+  const GramPlan g = gram_plan(M, K);
   double* part = (double*)ws;
   switch (compute) {
-    case P_F64: hipLaunchKernelGGL(gram_kernel<double>, grid, dim3(256), 0, st, M, K, (const double*)X, ntiles, part); break;
-    case P_F32: hipLaunchKernelGGL(gram_kernel<float>, grid, dim3(256), 0, st, M, K, (const float*)X, ntiles, part); break;
-    case P_BF16: hipLaunchKernelGGL(gram_kernel<bf16>, grid, dim3(256), 0, st, M, K, (const bf16*)X, ntiles, part); break;
-    case P_F16: hipLaunchKernelGGL(gram_kernel<f16>, grid, dim3(256), 0, st, M, K, (const f16*)X, ntiles, part); break;
+    case P_F64: gram_launch<double>(g, M, K, (const double*)X, part, st); break;
+    case P_F32: gram_launch<float>(g, M, K, (const float*)X, part, st); break;
+    case P_BF16: gram_launch<bf16>(g, M, K, (const bf16*)X, part, st); break;
+    case P_F16: gram_launch<f16>(g, M, K, (const f16*)X, part, st); break;
     default: return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3(ntiles), dim3(256), 0, st, K, nb, part, G);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(g.ntiles, 4), dim3(256), 0, st, K, g.nb, part, G);
   return hipGetLastError();
 }
 
