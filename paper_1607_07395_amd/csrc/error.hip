@@ -24,6 +24,13 @@ namespace cabs {
 constexpr int ERR_NB = 1024;
 constexpr int ERR_NT = 8;
 
+// LDS writes of a wave visible to its other lanes (a wave-level fence).
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 static inline size_t al256e(size_t b) { return (b + 255) & ~(size_t)255; }
 
 template <typename TIn>
@@ -60,8 +67,9 @@ __device__ __forceinline__ void err_sample_ij(uint64_t t, uint64_t seed, int64_t
   j = (int64_t)mulhi_bound(w.v[1], (uint64_t)n);
 }
 
-// Sixteen zero bytes to point out-of-range loads at, so that loads need no branches.
-__device__ const double4 kZeroRun = {0.0, 0.0, 0.0, 0.0};
+// Thirty-two zero bytes to point out-of-range loads at, so that loads need no
+// branches (global memory, so that the selected pointer stays a global one).
+static __device__ double4 kZeroRun[1] = {{0.0, 0.0, 0.0, 0.0}};
 
 // Four consecutive elements p[e .. e+3] widened to FP64, zero from `lim` on.
 // VEC: len is a multiple of 4 and rows are 16-byte aligned, so a run is either
@@ -72,13 +80,13 @@ __device__ const double4 kZeroRun = {0.0, 0.0, 0.0, 0.0};
 template <typename T, bool VEC> struct Run4;
 template <> struct Run4<float, true> {
   __device__ static __forceinline__ void get(const float* p, int e, int lim, double (&o)[4]) {
-    const float4 v = *(const float4*)(e < lim ? p + e : (const float*)&kZeroRun);
+    const float4 v = *(const float4*)(e < lim ? p + e : (const float*)kZeroRun);
     o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
   }
 };
 template <> struct Run4<double, true> {
   __device__ static __forceinline__ void get(const double* p, int e, int lim, double (&o)[4]) {
-    const double* q = e < lim ? p + e : (const double*)&kZeroRun;
+    const double* q = e < lim ? p + e : (const double*)kZeroRun;
     const double2 a = *(const double2*)q, b = *(const double2*)(q + 2);
     o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
   }
@@ -86,7 +94,7 @@ template <> struct Run4<double, true> {
 template <typename T> struct Run4<T, true> {  // 16-bit types: one 8-byte load
   static_assert(sizeof(T) == 2, "16-bit element type expected");
   __device__ static __forceinline__ void get(const T* p, int e, int lim, double (&o)[4]) {
-    const uint2 v = *(const uint2*)(e < lim ? p + e : (const T*)&kZeroRun);
+    const uint2 v = *(const uint2*)(e < lim ? p + e : (const T*)kZeroRun);
     const T* h = (const T*)&v;
 #pragma unroll
     for (int w = 0; w < 4; ++w) o[w] = to_f64(h[w]);
@@ -95,79 +103,146 @@ template <typename T> struct Run4<T, true> {  // 16-bit types: one 8-byte load
 template <typename T> struct Run4<T, false> {
   __device__ static __forceinline__ void get(const T* p, int e, int lim, double (&o)[4]) {
 #pragma unroll
-    for (int w = 0; w < 4; ++w) o[w] = to_f64(*(e + w < lim ? p + e + w : (const T*)&kZeroRun));
+    for (int w = 0; w < 4; ++w) o[w] = to_f64(*(e + w < lim ? p + e + w : (const T*)kZeroRun));
   }
 };
 
-// sum over e < len of f(x[e], y[e]) by a 16-lane group: lane l16 takes the runs
-// starting at 4 l16 + 64 u; four runs (256 elements) of each operand are in flight.
-template <int KIND, bool VEC, typename TX, typename TY>
-__device__ __forceinline__ double group_dot(const TX* x, const TY* y, const TY* z, int len, int l16) {
-  double acc = 0.0;
+// Sum over the 16 lanes of a row (lanes 16 r .. 16 r + 15) by four DPP
+// exchanges (pairs, quads, half rows, rows).  Every lane of the row ends with
+// the same bits: each step adds the same two values on both partners.
+__device__ __forceinline__ int dpp_xchg(int v, int ctrl_id) {
+  switch (ctrl_id) {
+    case 0: return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    case 1: return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    case 2: return __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    default: return __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false); // row_mirror
+  }
+}
+__device__ __forceinline__ float row16_sum(float v) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) v += __int_as_float(dpp_xchg(__float_as_int(v), c));
+  return v;
+}
+__device__ __forceinline__ double row16_sum(double v) {
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int lo = dpp_xchg(__double2loint(v), c), hi = dpp_xchg(__double2hiint(v), c);
+    v += __hiloint2double(hi, lo);
+  }
+  return v;
+}
+
+// FP32 runs of four (same addressing as Run4, no widening).
+template <bool VEC>
+__device__ __forceinline__ void run4_f32(const float* p, int e, int lim, float (&o)[4]) {
+  if constexpr (VEC) {
+    const float4 v = *(const float4*)(e < lim ? p + e : (const float*)kZeroRun);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  } else {
+#pragma unroll
+    for (int w = 0; w < 4; ++w) o[w] = *(e + w < lim ? p + e + w : (const float*)kZeroRun);
+  }
+}
+
+// The source term of a low-rank entry, pf_i . diag(s) . qf_j, accumulates in
+// the table precision (FP32 tables: FP32, well inside the error estimate's
+// accuracy); the CUR value and the RBF distance accumulate in FP64.
+template <int SRC, typename TIn> struct SvT { typedef double type; };
+template <> struct SvT<SRC_LOWRANK, float> { typedef float type; };
+
+// The two dot products of one sample (i, j) by a 16-lane group: the CUR value
+// ap = CU_i . Rt_j, and the source term sv (low rank: pf_i . diag(s) . qf_j;
+// RBF: |x_i - y_j|^2; dense: the stored entry).  Lane l16 takes the runs
+// starting at 4 l16 + 64 u; the runs of all operands (256 elements each) are
+// loaded before any is used.
+template <int SRC, bool VEC, typename TIn, typename TC>
+__device__ __forceinline__ void sample_dots(const MatView& mv, int kr, const double* __restrict__ CU,
+                                            const TC* __restrict__ Rt, int64_t ii, int64_t jj, int l16, double& ap,
+                                            typename SvT<SRC, TIn>::type& sv) {
+  typedef typename SvT<SRC, TIn>::type SV;
+  const int tabn = SRC == SRC_LOWRANK ? mv.r : SRC == SRC_RBF ? mv.d : 0;
+  const TIn* xr = SRC == SRC_LOWRANK ? (const TIn*)mv.pf + ii * mv.r
+                                     : SRC == SRC_RBF ? (const TIn*)mv.x + ii * mv.d : nullptr;
+  const TIn* yr = SRC == SRC_LOWRANK ? (const TIn*)mv.qf + jj * mv.r
+                                     : SRC == SRC_RBF ? (const TIn*)mv.y + jj * mv.d : nullptr;
+  const TIn* sp = (const TIn*)mv.s;
+  const double* cu = CU + ii * kr;
+  const TC* rt = Rt + jj * kr;
+  ap = 0.0;
+  sv = (SV)0;
+  const int len = kr > tabn ? kr : tabn;
   for (int u0 = 0; u0 < len; u0 += 256) {
-    double a[4][4], b[4][4], c[4][4];
+    double a[4][4], b[4][4];
+    SV x[4][4], y[4][4], z[4][4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int e = u0 + 64 * v + 4 * l16;
-      Run4<TX, VEC>::get(x, e, len, a[v]);
-      Run4<TY, VEC>::get(y, e, len, b[v]);
-      if (KIND == 1) Run4<TY, VEC>::get(z, e, len, c[v]);
+      Run4<double, VEC>::get(cu, e, kr, a[v]);
+      Run4<TC, VEC>::get(rt, e, kr, b[v]);
+      if constexpr (SRC != SRC_DENSE) {
+        if constexpr (sizeof(SV) == 4) {
+          run4_f32<VEC>((const float*)xr, e, tabn, x[v]);
+          run4_f32<VEC>((const float*)yr, e, tabn, y[v]);
+        } else {
+          Run4<TIn, VEC>::get(xr, e, tabn, x[v]);
+          Run4<TIn, VEC>::get(yr, e, tabn, y[v]);
+        }
+      }
+      if constexpr (SRC == SRC_LOWRANK) {
+        if constexpr (sizeof(SV) == 4) run4_f32<VEC>((const float*)sp, e, tabn, z[v]);
+        else Run4<TIn, VEC>::get(sp, e, tabn, z[v]);
+      }
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
-        if (KIND == 0) acc += a[v][w] * b[v][w];                      // plain dot
-        else if (KIND == 1) acc += a[v][w] * c[v][w] * b[v][w];       // x . diag(z) . y
-        else { const double df = a[v][w] - b[v][w]; acc += df * df; }  // squared distance
+        ap += a[v][w] * b[v][w];
+        if constexpr (SRC == SRC_LOWRANK) sv += x[v][w] * z[v][w] * y[v][w];
+        if constexpr (SRC == SRC_RBF) { const SV df = x[v][w] - y[v][w]; sv += df * df; }
       }
   }
-  return acc;
+  if constexpr (SRC == SRC_DENSE) sv = l16 == 0 ? (double)((const TIn*)mv.a)[ii * mv.lda + jj] : 0.0;
 }
 
-// One sample per lane (t, when `valid`).  The per-sample scalar work (sample
-// indices, the noise of a low-rank entry, the RBF exponential, the residual)
-// runs once per lane; the two long dot products of each sample run on the
-// lane's 16-lane group, which works through its 16 lanes' samples in order,
-// and the owning lane keeps the reduced values.  vec: rows of CU, Rt and the
-// tables may be read as 16-byte runs (decided on the host from sizes and
-// pointer alignment).
-template <typename TIn, typename TC, bool VEC>
+// One sample per lane ((i, j), when `valid`).  The per-sample scalar work (the
+// noise of a low-rank entry, the RBF exponential, the residual) runs once per
+// lane; the sample indices and noise then go through LDS to the lane's 16-lane
+// group, which works through its 16 lanes' samples in order (two dot products
+// and two row sums each), and the owning lane keeps the reduced values.  VEC:
+// rows of CU, Rt and the tables may be read as 16-byte runs (decided on the
+// host from sizes and pointer alignment).
+struct ErrRec { int64_t i, j; };
+
+template <int SRC, typename TIn, typename TC, bool VEC>
 __device__ __forceinline__ void err_batch(const MatView& mv, int kr, const double* __restrict__ CU,
-                                          const TC* __restrict__ Rt, uint64_t seed, int64_t t, bool valid,
+                                          const TC* __restrict__ Rt, int64_t i, int64_t j, bool valid,
                                           double& num, double& den) {
-  const int lane = threadIdx.x & 63, l16 = lane & 15, base = lane & 48;
-  int64_t i = 0, j = 0;
+  typedef typename SvT<SRC, TIn>::type SV;
+  __shared__ ErrRec rec[256];
+  const int lane = threadIdx.x & 63, l16 = lane & 15;
+  const int gbase = threadIdx.x & ~15;
+  if (!valid) { i = 0; j = 0; }
   double nz = 0.0;
-  if (valid) {
-    err_sample_ij((uint64_t)t, seed, mv.m, mv.n, i, j);
-    if (mv.kind == SRC_LOWRANK && mv.noise_std != 0.0) nz = noise_f64(mv.noise_seed, (uint64_t)i, (uint64_t)j);
-  }
-  double my_ap = 0.0, my_s = 0.0;
+  if (SRC == SRC_LOWRANK && valid && mv.noise_std != 0.0) nz = noise_f64(mv.noise_seed, (uint64_t)i, (uint64_t)j);
+  rec[threadIdx.x] = ErrRec{i, j};
+  wave_lds_fence();
+  double my_ap = 0.0;
+  SV my_s = (SV)0;
   for (int q = 0; q < 16; ++q) {
-    const int64_t ii = __shfl(i, base + q, 64);
-    const int64_t jj = __shfl(j, base + q, 64);
-    double ap = group_dot<0, VEC, double, TC>(CU + ii * kr, Rt + jj * kr, nullptr, kr, l16);
-    double sv = 0.0;
-    if (mv.kind == SRC_DENSE) {
-      sv = l16 == 0 ? (double)((const TIn*)mv.a)[ii * mv.lda + jj] : 0.0;
-    } else if (mv.kind == SRC_LOWRANK) {
-      sv = group_dot<1, VEC, TIn, TIn>((const TIn*)mv.pf + ii * mv.r, (const TIn*)mv.qf + jj * mv.r, (const TIn*)mv.s,
-                                       mv.r, l16);
-    } else {
-      sv = group_dot<2, VEC, TIn, TIn>((const TIn*)mv.x + ii * mv.d, (const TIn*)mv.y + jj * mv.d, nullptr, mv.d, l16);
-    }
-#pragma unroll
-    for (int off = 1; off < 16; off <<= 1) {
-      ap += __shfl_xor(ap, off, 64);
-      sv += __shfl_xor(sv, off, 64);
-    }
+    const ErrRec r = rec[gbase + q];
+    double ap;
+    SV sv;
+    sample_dots<SRC, VEC, TIn, TC>(mv, kr, CU, Rt, r.i, r.j, l16, ap, sv);
+    ap = row16_sum(ap);
+    sv = row16_sum(sv);
     if (l16 == q) { my_ap = ap; my_s = sv; }
   }
+  wave_lds_fence();  // the next batch rewrites rec
   if (valid) {
-    double a = my_s;
-    if (mv.kind == SRC_LOWRANK) a += mv.noise_std * nz;
-    else if (mv.kind == SRC_RBF) a = exp(-my_s / (2.0 * mv.sigma * mv.sigma));
+    double a = (double)my_s;
+    if (SRC == SRC_LOWRANK) a += mv.noise_std * nz;
+    else if (SRC == SRC_RBF) a = exp(-a / (2.0 * mv.sigma * mv.sigma));
     num += (a - my_ap) * (a - my_ap);
     den += a * a;
   }
@@ -188,14 +263,16 @@ __device__ __forceinline__ void err_block_store(double num, double den, double* 
 
 // Samples taken in the order they are drawn: block b evaluates batches of 256
 // consecutive sample numbers b * 256, (b + nb) * 256, ...
-template <typename TIn, typename TC, bool VEC>
+template <int SRC, typename TIn, typename TC, bool VEC>
 __global__ __launch_bounds__(256) void err_sampled_kernel(MatView mv, int kr, const double* __restrict__ CU,
                                                           const TC* __restrict__ Rt, int64_t ns, uint64_t seed,
                                                           double* __restrict__ part) {
   double num = 0.0, den = 0.0;
   for (int64_t b0 = (int64_t)blockIdx.x * 256; b0 < ns; b0 += (int64_t)gridDim.x * 256) {
     const int64_t t = b0 + threadIdx.x;
-    err_batch<TIn, TC, VEC>(mv, kr, CU, Rt, seed, t, t < ns, num, den);
+    int64_t i = 0, j = 0;
+    if (t < ns) err_sample_ij((uint64_t)t, seed, mv.m, mv.n, i, j);
+    err_batch<SRC, TIn, TC, VEC>(mv, kr, CU, Rt, i, j, t < ns, num, den);
   }
   err_block_store(num, den, part, blockIdx.x);
 }
@@ -206,9 +283,12 @@ __global__ __launch_bounds__(256) void err_sampled_kernel(MatView mv, int kr, co
 // generator row and the FP64 row of CU) comes from cache after its first use
 // and only the column side is gathered per sample.  The grouping is a stable
 // counting sort of the sample numbers t (bucket-major, then chunk, then t), so
-// every sum is taken in a fixed order.
+// every sum is taken in a fixed order.  The counting pass stores each sample's
+// (i, j) by t, and the sort moves the pairs themselves, so the Philox draw of a
+// sample's indices is made once.
 // ---------------------------------------------------------------------------
-constexpr int EB_MAXB = 8192;   // buckets at most
+constexpr int EB_BBITS = 13;
+constexpr int EB_MAXB = 1 << EB_BBITS;   // buckets at most
 constexpr int EB_G = 512;       // sample chunks of the counting sort
 
 struct EbPlan { int64_t rb; int nbk; int64_t tchunk; };
@@ -216,18 +296,22 @@ struct EbPlan { int64_t rb; int nbk; int64_t tchunk; };
 static inline EbPlan eb_plan(int64_t m, int64_t ns) {
   EbPlan p;
   p.rb = ceil_div(m, EB_MAXB);
+  if (p.rb < 16) p.rb = 16;  // a full 16-row bucket per work-group
   p.nbk = (int)ceil_div(m, p.rb);
   p.tchunk = ceil_div(ns, EB_G);
   return p;
 }
 
-// The sorted path needs n_s < 2^31 (sample numbers kept as int32) and at least
-// one sample per row on average (else there is nothing to reuse).
-static inline bool eb_use(int64_t m, int64_t ns) { return ns >= m && ns < ((int64_t)1 << 31); }
+// The sorted path needs n_s, m, n < 2^31 (kept as int32) and at least one
+// sample per row on average (else there is nothing to reuse).
+static inline bool eb_use(int64_t m, int64_t n, int64_t ns) {
+  const int64_t lim = (int64_t)1 << 31;
+  return ns >= m && ns < lim && m < lim && n < lim;
+}
 
 
 __global__ __launch_bounds__(256) void eb_count_kernel(int64_t m, int64_t n, int64_t ns, uint64_t seed, EbPlan pl,
-                                                       int32_t* __restrict__ counts) {
+                                                       int2* __restrict__ ij, int32_t* __restrict__ counts) {
   __shared__ int32_t hist[EB_MAXB];
   for (int b = threadIdx.x; b < pl.nbk; b += 256) hist[b] = 0;
   __syncthreads();
@@ -236,6 +320,7 @@ __global__ __launch_bounds__(256) void eb_count_kernel(int64_t m, int64_t n, int
   for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) {
     int64_t i, j;
     err_sample_ij((uint64_t)t, seed, m, n, i, j);
+    ij[t] = make_int2((int)i, (int)j);
     atomicAdd(&hist[(int)(i / pl.rb)], 1);
   }
   __syncthreads();
@@ -307,13 +392,13 @@ __global__ __launch_bounds__(256) void eb_offsets_kernel(EbPlan pl, const int32_
   for (int q = 0; q < PER; ++q) { o[q] = run; run += v[q]; }
 }
 
-// Chunk g places its sample numbers, in increasing t within each bucket.  A
+// Chunk g places its samples' (i, j), in increasing t within each bucket.  A
 // round is 256 consecutive samples, 64 per wave; ranks among equal buckets
 // inside a wave come from shuffles, and the four waves place their samples in
 // wave order, each advancing the per-bucket run counters in LDS.
-__global__ __launch_bounds__(256) void eb_scatter_kernel(int64_t m, int64_t n, int64_t ns, uint64_t seed, EbPlan pl,
+__global__ __launch_bounds__(256) void eb_scatter_kernel(int64_t ns, EbPlan pl, const int2* __restrict__ ij,
                                                          const int32_t* __restrict__ offs,
-                                                         int32_t* __restrict__ sorted) {
+                                                         int2* __restrict__ sorted) {
   __shared__ int32_t run[EB_MAXB];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   for (int b = tid; b < pl.nbk; b += 256) run[b] = 0;
@@ -322,23 +407,23 @@ __global__ __launch_bounds__(256) void eb_scatter_kernel(int64_t m, int64_t n, i
   for (int64_t base = t0; base < t1; base += 256) {
     const int64_t t = base + tid;
     const bool valid = t < t1;
-    int b = -1;
-    if (valid) {
-      int64_t i, j;
-      err_sample_ij((uint64_t)t, seed, m, n, i, j);
-      b = (int)(i / pl.rb);
+    const int2 e = valid ? ij[t] : make_int2(0, 0);
+    const int b = valid ? (int)(e.x / pl.rb) : -1;
+    // lanes holding the same bucket: one ballot per bit of the bucket number
+    // (invalid lanes carry -1, whose top bit no valid bucket has)
+    uint64_t same = ~0ull;
+#pragma unroll
+    for (int bit = 0; bit < EB_BBITS + 1; ++bit) {
+      const bool on = (b >> bit) & 1;
+      const uint64_t bb = __ballot(on);
+      same &= on ? bb : ~bb;
     }
-    int rank = 0;
-    bool last = true;
-    for (int q = 0; q < 64; ++q) {
-      const int o = __shfl(b, q, 64);
-      rank += (q < lane) & (o == b);
-      last = last && !((q > lane) & (o == b));
-    }
+    const int rank = __builtin_popcountll(same & ((1ull << lane) - 1ull));
+    const bool last = ((same >> lane) >> 1) == 0;
     for (int w = 0; w < 4; ++w) {
       __syncthreads();
       if (wave == w && valid) {
-        sorted[offs[(int64_t)b * EB_G + blockIdx.x] + run[b] + rank] = (int32_t)t;
+        sorted[offs[(int64_t)b * EB_G + blockIdx.x] + run[b] + rank] = e;
         if (last) run[b] += rank + 1;
       }
     }
@@ -346,11 +431,11 @@ __global__ __launch_bounds__(256) void eb_scatter_kernel(int64_t m, int64_t n, i
 }
 
 // One work-group per bucket, in batches of 256 of the bucket's samples.
-template <typename TIn, typename TC, bool VEC>
+template <int SRC, typename TIn, typename TC, bool VEC>
 __global__ __launch_bounds__(256) void eb_eval_kernel(MatView mv, int kr, const double* __restrict__ CU,
-                                                      const TC* __restrict__ Rt, uint64_t seed,
+                                                      const TC* __restrict__ Rt,
                                                       const int32_t* __restrict__ starts,
-                                                      const int32_t* __restrict__ sorted,
+                                                      const int2* __restrict__ sorted,
                                                       double* __restrict__ part) {
   const int b = blockIdx.x;
   const int s0 = starts[b], s1 = starts[b + 1];
@@ -358,9 +443,168 @@ __global__ __launch_bounds__(256) void eb_eval_kernel(MatView mv, int kr, const 
   for (int b0 = s0; b0 < s1; b0 += 256) {
     const int s = b0 + (int)threadIdx.x;
     const bool valid = s < s1;
-    err_batch<TIn, TC, VEC>(mv, kr, CU, Rt, seed, valid ? (int64_t)sorted[s] : 0, valid, num, den);
+    const int2 e = valid ? sorted[s] : make_int2(0, 0);
+    err_batch<SRC, TIn, TC, VEC>(mv, kr, CU, Rt, (int64_t)e.x, (int64_t)e.y, valid, num, den);
   }
   err_block_store(num, den, part, b);
+}
+
+// Low-rank source with FP32 tables, buckets of at most ER_RB rows and k, r <=
+// ER_KMAX: one 16-lane group per row of the bucket.  The group keeps its row's
+// FP64 CU run and FP32 pf o s run in registers, so only the column side of a
+// sample (R^T_j and qf_j) is loaded per sample, with the next sample's loads
+// in flight while the current one is reduced.  The bucket's samples (in
+// bucket order) go through LDS in chunks of ER_CH: each wave ranks its 512 by
+// row (per-row running counts in LDS), the row segments are laid out in row
+// order and, within a row, in bucket order, and lane t draws the noise of
+// its samples on the way.  Sums are per row in sample order, then rows, then
+// blocks, in fixed orders.
+constexpr int ER_RB = 16;
+constexpr int ER_CH = 2048;
+constexpr int ER_KMAX = 256;
+
+template <typename TC, bool VEC>
+__global__ __launch_bounds__(256) void eb_eval_rows_kernel(MatView mv, int kr, const double* __restrict__ CU,
+                                                           const TC* __restrict__ Rt, EbPlan pl,
+                                                           const int32_t* __restrict__ starts,
+                                                           const int2* __restrict__ sorted,
+                                                           double* __restrict__ part) {
+  constexpr int SETS = ER_CH / 256;  // 64-record sets per wave and chunk
+  __shared__ int32_t sj[ER_CH];
+  __shared__ double snz[ER_CH];
+  __shared__ int wrun[4][ER_RB];
+  __shared__ int rbeg[ER_RB + 1];
+  __shared__ int wbase[4][ER_RB];
+  __shared__ double gn[16], gd[16];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, grp = tid >> 4;
+  const int b = blockIdx.x;
+  const int64_t row0 = (int64_t)b * pl.rb;
+  const int r = mv.r;
+  // this group's row: FP64 CU run and FP32 pf o s run (zero past k, r and the bucket)
+  const int64_t myrow = row0 + grp;
+  const bool rowok = grp < pl.rb && myrow < mv.m;
+  double cu[4][4];
+  float ps[4][4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int c = 64 * v + 4 * l16;
+    Run4<double, VEC>::get(CU + (rowok ? myrow : 0) * kr, c, rowok ? kr : 0, cu[v]);
+    float pv[4], sv4[4];
+    run4_f32<VEC>((const float*)mv.pf + (rowok ? myrow : 0) * r, c, rowok ? r : 0, pv);
+    run4_f32<VEC>((const float*)mv.s, c, r, sv4);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) ps[v][w] = pv[w] * sv4[w];
+  }
+  double num = 0.0, den = 0.0;  // kept by lane 0 of each group
+  const int s0 = starts[b], s1 = starts[b + 1];
+  for (int c0 = s0; c0 < s1; c0 += ER_CH) {
+    const int n = s1 - c0 < ER_CH ? s1 - c0 : ER_CH;
+    if (lane < ER_RB) wrun[wave][lane] = 0;
+    wave_lds_fence();
+    // pass A: wave w takes records w * 512 + 64 k + lane; rank within equal rows
+    int ro[SETS], jv[SETS], posl[SETS];
+    double nz[SETS];
+#pragma unroll
+    for (int k = 0; k < SETS; ++k) {
+      const int idx = wave * (ER_CH / 4) + 64 * k + lane;
+      const bool valid = idx < n;
+      const int2 e = valid ? sorted[c0 + idx] : make_int2(0, 0);
+      ro[k] = valid ? (int)(e.x - row0) : -1;
+      jv[k] = e.y;
+      nz[k] = (valid && mv.noise_std != 0.0) ? noise_f64(mv.noise_seed, (uint64_t)e.x, (uint64_t)e.y) : 0.0;
+      uint64_t same = ~0ull;
+#pragma unroll
+      for (int bit = 0; bit < 5; ++bit) {  // ro in [-1, 16): five bits tell them apart
+        const bool on = (ro[k] >> bit) & 1;
+        const uint64_t bb = __ballot(on);
+        same &= on ? bb : ~bb;
+      }
+      const int rank = __builtin_popcountll(same & ((1ull << lane) - 1ull));
+      const bool last = ((same >> lane) >> 1) == 0;
+      const int rs = valid ? ro[k] : 0;
+      posl[k] = wrun[wave][rs] + rank;
+      wave_lds_fence();
+      if (valid && last) wrun[wave][rs] += rank + 1;
+      wave_lds_fence();
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int run = 0;
+      for (int rr = 0; rr < ER_RB; ++rr) {
+        rbeg[rr] = run;
+        for (int w = 0; w < 4; ++w) { wbase[w][rr] = run; run += wrun[w][rr]; }
+      }
+      rbeg[ER_RB] = run;
+    }
+    __syncthreads();
+    // pass B: samples to their row segments
+#pragma unroll
+    for (int k = 0; k < SETS; ++k) {
+      if (ro[k] >= 0) {
+        const int pos = wbase[wave][ro[k]] + posl[k];
+        sj[pos] = jv[k];
+        snz[pos] = nz[k];
+      }
+    }
+    __syncthreads();
+    // group grp: the samples of its row, in order, with the next one's loads in flight
+    if (rowok) {
+      const int p0 = rbeg[grp], p1 = rbeg[grp + 1];
+      const float* qfb = (const float*)mv.qf;
+      double bq[4][4];
+      float yq[4][4];
+      auto fetch = [&](int p, double (&bo)[4][4], float (&yo)[4][4]) {
+        const int64_t j = sj[p];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int c = 64 * v + 4 * l16;
+          Run4<TC, VEC>::get(Rt + j * kr, c, kr, bo[v]);
+          run4_f32<VEC>(qfb + j * r, c, r, yo[v]);
+        }
+      };
+      if (p0 < p1) fetch(p0, bq, yq);
+      for (int p = p0; p < p1; ++p) {
+        double bc[4][4];
+        float yc[4][4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int w = 0; w < 4; ++w) { bc[v][w] = bq[v][w]; yc[v][w] = yq[v][w]; }
+        if (p + 1 < p1) fetch(p + 1, bq, yq);
+        double ap = 0.0;
+        float sv = 0.0f;
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            ap += cu[v][w] * bc[v][w];
+            sv += ps[v][w] * yc[v][w];
+          }
+        ap = row16_sum(ap);
+        sv = row16_sum(sv);
+        if (l16 == 0) {
+          const double av = (double)sv + mv.noise_std * snz[p];
+          num += (av - ap) * (av - ap);
+          den += av * av;
+        }
+      }
+    }
+    __syncthreads();  // sj / snz / wrun reused by the next chunk
+  }
+  if (l16 == 0) { gn[grp] = num; gd[grp] = den; }
+  __syncthreads();
+  if (tid == 0) {
+    double n2 = 0.0, d2 = 0.0;
+    for (int g = 0; g < 16; ++g) { n2 += gn[g]; d2 += gd[g]; }
+    part[2 * (int64_t)b] = n2;
+    part[2 * (int64_t)b + 1] = d2;
+  }
+}
+
+static inline bool er_rows_ok(const MatView& mv, int kr, int64_t ns) {
+  if (mv.kind != SRC_LOWRANK || mv.storage != P_F32) return false;
+  if (!eb_use(mv.m, mv.n, ns)) return false;
+  return eb_plan(mv.m, ns).rb <= ER_RB && kr <= ER_KMAX && mv.r <= ER_KMAX;
 }
 
 template <typename TIn>
@@ -453,19 +697,19 @@ __global__ __launch_bounds__(256) void err_final_kernel(int nb, const double* __
 
 static inline int64_t exact_nb(const MatView& mv) { return ceil_div(mv.m, 64); }
 
-static inline int64_t part_blocks(const MatView& mv, int64_t ns) {
+static inline int64_t part_blocks(const MatView& mv, int kr, int64_t ns) {
   if (ns == 0) return exact_nb(mv);
-  return eb_use(mv.m, ns) ? eb_plan(mv.m, ns).nbk : ERR_NB;
+  return eb_use(mv.m, mv.n, ns) ? eb_plan(mv.m, ns).nbk : ERR_NB;
 }
 
 static inline size_t eb_ws_bytes(const MatView& mv, int64_t ns) {
-  if (ns == 0 || !eb_use(mv.m, ns)) return 0;
+  if (ns == 0 || !eb_use(mv.m, mv.n, ns)) return 0;
   const EbPlan pl = eb_plan(mv.m, ns);
-  return 2 * al256e((size_t)pl.nbk * EB_G * 4) + 2 * al256e(((size_t)pl.nbk + 1) * 4) + al256e((size_t)ns * 4);
+  return 2 * al256e((size_t)pl.nbk * EB_G * 4) + 2 * al256e(((size_t)pl.nbk + 1) * 4) + 2 * al256e((size_t)ns * 8);
 }
 
 size_t error_ws_bytes(const MatView& mv, int k2c, int k2r, int compute, int64_t n_samples) {
-  const int64_t nb = part_blocks(mv, n_samples);
+  const int64_t nb = part_blocks(mv, k2r, n_samples);
   size_t b = al256e((size_t)mv.m * k2r * sizeof(double)) + tsgemm_ws_bytes(mv.m, k2c, k2r, P_F64) +
              al256e((size_t)nb * 2 * sizeof(double)) + eb_ws_bytes(mv, n_samples) + 256;
   if (compute != P_F64) {
@@ -495,6 +739,18 @@ static void widen_any(int compute, int64_t n, const void* src, double* dst, hipS
   }
 }
 
+// Calls f(source kind, vec) with both as compile-time constants.
+template <typename F>
+static void with_src(int kind, bool vec, F&& f) {
+  auto go = [&](auto src) {
+    if (vec) f(src, std::integral_constant<bool, true>{});
+    else f(src, std::integral_constant<bool, false>{});
+  };
+  if (kind == SRC_DENSE) go(std::integral_constant<int, SRC_DENSE>{});
+  else if (kind == SRC_LOWRANK) go(std::integral_constant<int, SRC_LOWRANK>{});
+  else go(std::integral_constant<int, SRC_RBF>{});
+}
+
 template <typename TIn, typename TC>
 static hipError_t error_t(const MatView& mv, int kr, const double* CU, const TC* Rt, const double* Rt64, int64_t ns,
                           uint64_t seed, double* part, char* ebws, double* out3, hipStream_t st) {
@@ -509,33 +765,41 @@ static hipError_t error_t(const MatView& mv, int kr, const double* CU, const TC*
   const bool vec = kr % 4 == 0 && al16(CU) && al16(Rt) &&
                    (mv.kind == SRC_DENSE || (tabn % 4 == 0 && al16(t0) && al16(t1) && al16(t2)));
   int nb;
-  if (ns > 0 && eb_use(mv.m, ns)) {
+  if (ns > 0 && eb_use(mv.m, mv.n, ns)) {
     const EbPlan pl = eb_plan(mv.m, ns);
     int32_t* counts = (int32_t*)ebws;
     int32_t* offs = (int32_t*)(ebws + al256e((size_t)pl.nbk * EB_G * 4));
     int32_t* totals = (int32_t*)((char*)offs + al256e((size_t)pl.nbk * EB_G * 4));
     int32_t* starts = (int32_t*)((char*)totals + al256e(((size_t)pl.nbk + 1) * 4));
-    int32_t* sorted = (int32_t*)((char*)starts + al256e(((size_t)pl.nbk + 1) * 4));
+    int2* ij = (int2*)((char*)starts + al256e(((size_t)pl.nbk + 1) * 4));
+    int2* sorted = (int2*)((char*)ij + al256e((size_t)ns * 8));
     const unsigned gw = (unsigned)ceil_div(pl.nbk, 4);
-    hipLaunchKernelGGL(eb_count_kernel, dim3(EB_G), dim3(256), 0, st, mv.m, mv.n, ns, seed, pl, counts);
+    hipLaunchKernelGGL(eb_count_kernel, dim3(EB_G), dim3(256), 0, st, mv.m, mv.n, ns, seed, pl, ij, counts);
     hipLaunchKernelGGL(eb_totals_kernel, dim3(gw), dim3(256), 0, st, pl, counts, totals);
     hipLaunchKernelGGL(eb_scan_kernel, dim3(1), dim3(1024), 0, st, pl, totals, starts);
     hipLaunchKernelGGL(eb_offsets_kernel, dim3(gw), dim3(256), 0, st, pl, counts, starts, offs);
-    hipLaunchKernelGGL(eb_scatter_kernel, dim3(EB_G), dim3(256), 0, st, mv.m, mv.n, ns, seed, pl, offs, sorted);
-    nb = pl.nbk;
-    if (vec)
-      hipLaunchKernelGGL((eb_eval_kernel<TIn, TC, true>), dim3(nb), dim3(256), 0, st, mv, kr, CU, Rt, seed, starts,
-                         sorted, part);
-    else
-      hipLaunchKernelGGL((eb_eval_kernel<TIn, TC, false>), dim3(nb), dim3(256), 0, st, mv, kr, CU, Rt, seed, starts,
-                         sorted, part);
+    hipLaunchKernelGGL(eb_scatter_kernel, dim3(EB_G), dim3(256), 0, st, ns, pl, ij, offs, sorted);
+    if (er_rows_ok(mv, kr, ns)) {
+      nb = pl.nbk;
+      if (vec)
+        hipLaunchKernelGGL((eb_eval_rows_kernel<TC, true>), dim3(nb), dim3(256), 0, st, mv, kr, CU, Rt, pl, starts,
+                           sorted, part);
+      else
+        hipLaunchKernelGGL((eb_eval_rows_kernel<TC, false>), dim3(nb), dim3(256), 0, st, mv, kr, CU, Rt, pl, starts,
+                           sorted, part);
+    } else {
+      nb = pl.nbk;
+      with_src(mv.kind, vec, [&](auto src, auto vc) {
+        hipLaunchKernelGGL((eb_eval_kernel<decltype(src)::value, TIn, TC, decltype(vc)::value>), dim3(nb), dim3(256), 0,
+                           st, mv, kr, CU, Rt, starts, sorted, part);
+      });
+    }
   } else if (ns > 0) {
     nb = ERR_NB;
-    if (vec)
-      hipLaunchKernelGGL((err_sampled_kernel<TIn, TC, true>), dim3(nb), dim3(256), 0, st, mv, kr, CU, Rt, ns, seed, part);
-    else
-      hipLaunchKernelGGL((err_sampled_kernel<TIn, TC, false>), dim3(nb), dim3(256), 0, st, mv, kr, CU, Rt, ns, seed,
-                         part);
+    with_src(mv.kind, vec, [&](auto src, auto vc) {
+      hipLaunchKernelGGL((err_sampled_kernel<decltype(src)::value, TIn, TC, decltype(vc)::value>), dim3(nb), dim3(256),
+                         0, st, mv, kr, CU, Rt, ns, seed, part);
+    });
   } else {
     nb = (int)exact_nb(mv);
     hipLaunchKernelGGL((err_exact_kernel<TIn>), dim3(nb), dim3(256), 0, st, mv, kr, CU, Rt64, part);
@@ -554,7 +818,7 @@ hipError_t launch_error(const MatView& mv, int k2c, int k2r, int compute, const 
   void* tws = p;
   p += tsgemm_ws_bytes(mv.m, k2c, k2r, P_F64);
   double* part = (double*)p;
-  p += al256e((size_t)part_blocks(mv, n_samples) * 2 * sizeof(double));
+  p += al256e((size_t)part_blocks(mv, k2r, n_samples) * 2 * sizeof(double));
   char* ebws = p;
   p += eb_ws_bytes(mv, n_samples);
   const double* C64 = (const double*)C;

@@ -61,6 +61,50 @@ __device__ __forceinline__ double widen(double v) { return v; }
 // loads need no branches (internal to each code object; never written).
 static __device__ double4 kTileZero[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
 
+// One 16-byte run of MFMA fragments: element s of the run as the fragment of
+// MFMA step s (FP32, FP64: one element per step; 16-bit types: the whole run).
+template <typename TC> struct Vec16;
+template <> struct Vec16<float> {
+  __device__ static __forceinline__ float frag(const uint4& v, int s) { return __uint_as_float((&v.x)[s]); }
+};
+template <> struct Vec16<double> {
+  __device__ static __forceinline__ double frag(const uint4& v, int s) {
+    return __hiloint2double((int)(&v.x)[2 * s + 1], (int)(&v.x)[2 * s]);
+  }
+};
+template <> struct Vec16<bf16> {
+  __device__ static __forceinline__ bf16x8 frag(const uint4& v, int) { return __builtin_bit_cast(bf16x8, v); }
+};
+template <> struct Vec16<f16> {
+  __device__ static __forceinline__ f16x8 frag(const uint4& v, int) { return __builtin_bit_cast(f16x8, v); }
+};
+
+// 16-byte run of 16 / sizeof(TC) elements of row `row` from column k0 (zero
+// outside the nrows x ld matrix).
+template <typename TC>
+__device__ __forceinline__ uint4 load_run(const TC* __restrict__ X, int64_t nrows, int ld, int64_t row, int k0,
+                                          bool aligned) {
+  constexpr int VE = 16 / sizeof(TC);
+  uint4 v = {0u, 0u, 0u, 0u};
+  if (row >= nrows || k0 >= ld) return v;
+  const TC* src = X + row * ld + k0;
+  if (aligned && k0 + VE <= ld) return *(const uint4*)src;
+  TC tmp[VE];
+#pragma unroll
+  for (int e = 0; e < VE; ++e) tmp[e] = k0 + e < ld ? src[e] : zero_of<TC>();
+  return __builtin_bit_cast(uint4, tmp);
+}
+
+// The same run of a matrix whose rows are whole 16-byte runs (ld a multiple
+// of 16 / sizeof(TC), 16-byte aligned base): a run is either inside or wholly
+// outside (then it reads zeros), so the load needs no branch.
+template <typename TC>
+__device__ __forceinline__ uint4 load_run_al(const TC* __restrict__ X, int64_t nrows, int ld, int64_t row, int k0,
+                                             bool in) {
+  const bool ok = in && row < nrows && k0 < ld;
+  return *(ok ? (const uint4*)(X + row * ld + k0) : (const uint4*)kTileZero);
+}
+
 // LK consecutive elements p[k .. k+LK-1] of one row.  Whole runs are vector
 // loads (16-byte pieces); `ok` false reads zeros.  All loads of a k block are
 // issued before any of them is used, with no branch in between.

@@ -19,11 +19,11 @@
 //              zero-weight clusters keep their centre).
 // Nothing uses floating-point atomics, so every run is bitwise reproducible.
 //
-// Snapping: per 4096-row block, the 16 nearest rows of every centre (MFMA
+// Snapping: per block of about 128 rows, the 16 nearest rows of every centre (MFMA
 // distance tiles staged in LDS); a per-centre merge of the block lists; then
 // one workgroup visits the centres in order and gives each the nearest row
-// not yet taken, falling back to a full scan of all rows when all 16
-// candidates are taken.
+// not yet taken, falling back to the per-block lists (and exact rescans of
+// the blocks whose lists may be incomplete) when the merged 16 cannot decide.
 #include "common.hpp"
 #include "gemm_core.hpp"
 #include "kernels.hpp"
@@ -39,6 +39,9 @@ constexpr int SNAP_T = 16;        // candidates kept per centre and block
 constexpr int SNAP_CC = 64;       // centres per LDS chunk in the top-T pass
 constexpr int SNAP_NT = SNAP_CC / 16;
 constexpr int SNAP_SUB = 64;      // rows per distance sub-tile
+constexpr int SNAP_ROWS = 128;    // rows per block of the top-T pass (a multiple of SNAP_SUB)
+constexpr int SNAP_MAXBLK = 2048; // row blocks at most
+constexpr int64_t SNAP_MAXCAND = (int64_t)1 << 19;  // k * blocks at most
 
 static inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -152,78 +155,47 @@ __global__ __launch_bounds__(256) void assign_kernel(int64_t rows, int dim, int 
   }
 }
 
-// Fast assignment for FP32 / BF16 / FP16 and dim <= AF_KMAX.  A workgroup
-// (4 waves, 64 rows) keeps each wave's 16 rows as 16-byte MFMA fragments in
-// registers for the whole kernel, and streams the centres through LDS in
-// chunks of AF_CT x 16, stored in fragment order so that every B read is one
-// contiguous ds_read_b128 per wave (no bank conflicts).  The next chunk is
-// prefetched into registers while the current one is multiplied.  Per lane
+// Fast assignment for FP32 / BF16 / FP16, dim <= AF_KMAX and rows that are
+// whole 16-byte runs (dim a multiple of 16 / sizeof(TC), P 16-byte aligned).
+// A workgroup (4 waves, 64 rows) keeps each wave's 16 rows as 16-byte MFMA
+// fragments in registers for the whole kernel, and streams the centres
+// through LDS in chunks of AF_CT x 16, stored in fragment order so that every
+// B read is one contiguous ds_read_b128 per wave (no bank conflicts).  The
+// next chunk is loaded into registers while the current one is multiplied.
+// NKB (k blocks) is a compile-time constant, so no load, store or MFMA needs a
+// run-time guard (k blocks past dim read zeros and add exact zeros).  Per lane
 // the k blocks, MFMA steps and columns come in the same order as in
 // assign_kernel, so distances, labels and gaps are bit-identical to it.
 constexpr int AF_KMAX = 256;
 constexpr int AF_CT = 4;
 
-template <typename TC> struct Vec16;
-template <> struct Vec16<float> {
-  __device__ static __forceinline__ float frag(const uint4& v, int s) { return __uint_as_float((&v.x)[s]); }
-};
-template <> struct Vec16<bf16> {
-  __device__ static __forceinline__ bf16x8 frag(const uint4& v, int) { return __builtin_bit_cast(bf16x8, v); }
-};
-template <> struct Vec16<f16> {
-  __device__ static __forceinline__ f16x8 frag(const uint4& v, int) { return __builtin_bit_cast(f16x8, v); }
-};
-
-// 16-byte run of VE elements of row `row` starting at column k0 (zero outside the matrix).
-template <typename TC>
-__device__ __forceinline__ uint4 load_run(const TC* __restrict__ X, int64_t nrows, int ld, int64_t row, int k0,
-                                          bool aligned) {
-  constexpr int VE = 16 / sizeof(TC);
-  uint4 v = {0u, 0u, 0u, 0u};
-  if (row >= nrows || k0 >= ld) return v;
-  const TC* src = X + row * ld + k0;
-  if (aligned && k0 + VE <= ld) return *(const uint4*)src;
-  TC tmp[VE];
-#pragma unroll
-  for (int e = 0; e < VE; ++e) tmp[e] = k0 + e < ld ? src[e] : zero_of<TC>();
-  return __builtin_bit_cast(uint4, tmp);
-}
-
-template <typename TC>
+template <typename TC, int NKB>
 __global__ __launch_bounds__(256, 2) void assign_fast_kernel(int64_t rows, int dim, int k, const TC* __restrict__ P,
                                                              const TC* __restrict__ Zc,
                                                              const double* __restrict__ znorm,
                                                              const double* __restrict__ pnorm,
                                                              int32_t* __restrict__ labels, double* __restrict__ dmin,
-                                                             double* __restrict__ gap, int p_aligned) {
+                                                             double* __restrict__ gap) {
   typedef typename Mfma<TC>::acc AccV;
-  constexpr int VE = 16 / sizeof(TC);          // elements per 16-byte run
-  constexpr int SPV = VE / Mfma<TC>::KPL;      // MFMA steps per run
-  constexpr int KBW = 4 * VE;                  // k per block (4 lane groups)
-  constexpr int NKB = AF_KMAX / KBW;
-  constexpr int PF = AF_CT * NKB * 64 / 256;   // prefetch runs per thread
-  extern __shared__ uint4 zs[];                // [AF_CT][nkb][64] runs
+  constexpr int VE = 16 / sizeof(TC);           // elements per 16-byte run
+  constexpr int SPV = VE / Mfma<TC>::KPL;       // MFMA steps per run
+  constexpr int KBW = 4 * VE;                   // k per block (4 lane groups)
+  constexpr int PER_CHUNK = AF_CT * NKB * 64;   // runs per centre chunk
+  constexpr int PF = (PER_CHUNK + 255) / 256;   // prefetch runs per thread
+  extern __shared__ uint4 zs[];                 // [AF_CT][NKB][64] runs
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int g = lane >> 4, c16 = lane & 15;
-  const int nkb = (dim + KBW - 1) / KBW;
-  // Zc is 256-byte aligned workspace; P may come from a caller
-  const bool aligned = (dim % VE) == 0;
   const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
   uint4 a[NKB];
 #pragma unroll
-  for (int kb = 0; kb < NKB; ++kb)
-    a[kb] = kb < nkb ? load_run<TC>(P, rows, dim, row0 + c16, kb * KBW + g * VE, aligned && p_aligned)
-                     : uint4{0u, 0u, 0u, 0u};
-  const int per_chunk = AF_CT * nkb * 64;
+  for (int kb = 0; kb < NKB; ++kb) a[kb] = load_run_al<TC>(P, rows, dim, row0 + c16, kb * KBW + g * VE, true);
   uint4 pf[PF];
   auto prefetch = [&](int cc) {
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
       const int e = tid + 256 * u;
-      if (e < per_chunk) {
-        const int t = e / (nkb * 64), rem = e - t * nkb * 64, kb = rem >> 6, l = rem & 63;
-        pf[u] = load_run<TC>(Zc, k, dim, cc + 16 * t + (l & 15), kb * KBW + (l >> 4) * VE, aligned);
-      }
+      const int t = e / (NKB * 64), rem = e - t * (NKB * 64), kb = rem >> 6, l = rem & 63;
+      pf[u] = load_run_al<TC>(Zc, k, dim, cc + 16 * t + (l & 15), kb * KBW + (l >> 4) * VE, e < PER_CHUNK);
     }
   };
   float best[4], second[4];
@@ -236,25 +208,35 @@ __global__ __launch_bounds__(256, 2) void assign_fast_kernel(int64_t rows, int d
 #pragma unroll
     for (int u = 0; u < PF; ++u) {
       const int e = tid + 256 * u;
-      if (e < per_chunk) zs[e] = pf[u];
+      if ((u + 1) * 256 <= PER_CHUNK || e < PER_CHUNK) zs[e] = pf[u];
     }
     __syncthreads();
     if (cc + AF_CT * 16 < k) prefetch(cc + AF_CT * 16);
     AccV acc[AF_CT];
 #pragma unroll
     for (int t = 0; t < AF_CT; ++t) acc[t] = Mfma<TC>::zero();
+    // tiles of the chunk that hold columns (a compile-time count per case, so
+    // a chunk with fewer than AF_CT tiles skips the empty ones)
+    auto mm = [&](auto ntc) {
+      constexpr int NT = decltype(ntc)::value;
 #pragma unroll
-    for (int kb = 0; kb < NKB; ++kb) {
-      if (kb < nkb) {
-        uint4 b[AF_CT];
+      for (int kb = 0; kb < NKB; ++kb) {
+        uint4 b[NT];
 #pragma unroll
-        for (int t = 0; t < AF_CT; ++t) b[t] = zs[(t * nkb + kb) * 64 + lane];
+        for (int t = 0; t < NT; ++t) b[t] = zs[(t * NKB + kb) * 64 + lane];
 #pragma unroll
         for (int s2 = 0; s2 < SPV; ++s2)
 #pragma unroll
-          for (int t = 0; t < AF_CT; ++t)
+          for (int t = 0; t < NT; ++t)
             acc[t] = Mfma<TC>::mma(Vec16<TC>::frag(a[kb], s2), Vec16<TC>::frag(b[t], s2), acc[t]);
       }
+    };
+    const int ntile = (k - cc + 15) / 16;
+    if (ntile >= AF_CT) mm(std::integral_constant<int, AF_CT>{});
+    else if constexpr (AF_CT == 4) {
+      if (ntile == 1) mm(std::integral_constant<int, 1>{});
+      else if (ntile == 2) mm(std::integral_constant<int, 2>{});
+      else mm(std::integral_constant<int, 3>{});
     }
 #pragma unroll
     for (int t = 0; t < AF_CT; ++t) {
@@ -292,6 +274,23 @@ __global__ __launch_bounds__(256, 2) void assign_fast_kernel(int64_t rows, int d
   }
 }
 
+// Compiled k-block counts per type (the smallest one >= the needed count is used).
+template <typename TC> struct AfNkb { static constexpr int v[4] = {2, 4, 7, 8}; };  // 16-bit types
+template <> struct AfNkb<float> { static constexpr int v[4] = {4, 8, 13, 16}; };
+
+template <typename TC, int I>
+static void assign_fast_launch(int nkb, int64_t rows, int dim, int k, const TC* P, const TC* Zc, const double* znorm,
+                               const double* pnorm, int32_t* labels, double* dmin, double* gap, hipStream_t st) {
+  constexpr int NKB = AfNkb<TC>::v[I];
+  if constexpr (I < 3) {
+    if (nkb > NKB)
+      return assign_fast_launch<TC, I + 1>(nkb, rows, dim, k, P, Zc, znorm, pnorm, labels, dmin, gap, st);
+  }
+  const size_t lds = (size_t)AF_CT * NKB * 64 * 16;
+  hipLaunchKernelGGL((assign_fast_kernel<TC, NKB>), dim3((unsigned)ceil_div(rows, 64)), dim3(256), lds, st, rows, dim,
+                     k, P, Zc, znorm, pnorm, labels, dmin, gap);
+}
+
 template <typename TC> struct AssignFast { static constexpr bool ok = true; };
 template <> struct AssignFast<double> { static constexpr bool ok = false; };
 
@@ -299,13 +298,10 @@ template <typename TC>
 static void launch_assign(int64_t rows, int dim, int k, const TC* P, const TC* Zc, const double* znorm,
                           const double* pnorm, int32_t* labels, double* dmin, double* gap, hipStream_t st) {
   if constexpr (AssignFast<TC>::ok) {
-    if (dim <= AF_KMAX) {
-      constexpr int KBW = 4 * (16 / (int)sizeof(TC));
-      const int nkb = (dim + KBW - 1) / KBW;
-      const size_t lds = (size_t)AF_CT * nkb * 64 * 16;
-      const int p_aligned = ((uintptr_t)P % 16) == 0 ? 1 : 0;
-      hipLaunchKernelGGL(assign_fast_kernel<TC>, dim3((unsigned)ceil_div(rows, 64)), dim3(256), lds, st, rows, dim, k,
-                         P, Zc, znorm, pnorm, labels, dmin, gap, p_aligned);
+    constexpr int VE = 16 / (int)sizeof(TC);
+    if (dim <= AF_KMAX && dim % VE == 0 && ((uintptr_t)P % 16) == 0 && ((uintptr_t)Zc % 16) == 0) {
+      const int nkb = (dim + 4 * VE - 1) / (4 * VE);
+      assign_fast_launch<TC, 0>(nkb, rows, dim, k, P, Zc, znorm, pnorm, labels, dmin, gap, st);
       return;
     }
   }
@@ -691,39 +687,74 @@ __global__ __launch_bounds__(256) void snap_topt_kernel(int64_t rows, int dim, i
   }
 }
 
-// Per centre: sort the nblk * SNAP_T candidates by (distance, row); keep SNAP_T.
-__global__ __launch_bounds__(256) void snap_merge_kernel(int nblk, const double* __restrict__ cand_d,
-                                                         const int32_t* __restrict__ cand_r, double* __restrict__ top_d,
-                                                         int32_t* __restrict__ top_r) {
-  __shared__ double sd[4096];
-  __shared__ int32_t sr[4096];
-  const int j = blockIdx.x;
-  const int n = nblk * SNAP_T;
-  int P2 = 1;
-  while (P2 < n) P2 <<= 1;
-  for (int e = threadIdx.x; e < P2; e += 256) {
-    if (e < n) { sd[e] = cand_d[(int64_t)j * n + e]; sr[e] = cand_r[(int64_t)j * n + e]; }
-    else { sd[e] = __builtin_huge_val(); sr[e] = 0x7fffffff; }
-  }
-  __syncthreads();
+// Per centre: the SNAP_T smallest (distance, row) pairs over the per-block
+// lists, each of which is sorted.  Rows are distinct, so exactly SNAP_T list
+// heads are no greater than tau, the SNAP_T-th smallest head; every pair of
+// the result is no greater than tau, and only those SNAP_T lists hold such
+// pairs.  So the heads are sorted to find tau, the pairs no greater than tau
+// (at most SNAP_T * SNAP_T) are gathered, and those are sorted.
+__device__ __forceinline__ bool pair_gt(double a, int32_t ra, double b, int32_t rb) {
+  return a > b || (a == b && ra > rb);
+}
+
+template <int N, int NT>
+__device__ __forceinline__ void bitonic_pairs(double* sd, int32_t* sr, int P2) {
   for (int size = 2; size <= P2; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int t = threadIdx.x; t < P2; t += 256) {
+      for (int t = threadIdx.x; t < P2; t += NT) {
         const int p = t ^ stride;
         if (p > t) {
           const bool up = (t & size) == 0;
           const double a = sd[t], b = sd[p];
-          const int ra = sr[t], rb = sr[p];
-          const bool gt = a > b || (a == b && ra > rb);
-          if (gt == up) { sd[t] = b; sd[p] = a; sr[t] = rb; sr[p] = ra; }
+          const int32_t ra = sr[t], rb = sr[p];
+          if (pair_gt(a, ra, b, rb) == up) { sd[t] = b; sd[p] = a; sr[t] = rb; sr[p] = ra; }
         }
       }
       __syncthreads();
     }
   }
-  if (threadIdx.x < SNAP_T) {
-    top_d[(int64_t)j * SNAP_T + threadIdx.x] = sd[threadIdx.x];
-    top_r[(int64_t)j * SNAP_T + threadIdx.x] = sr[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void snap_merge_kernel(int nblk, const double* __restrict__ cand_d,
+                                                         const int32_t* __restrict__ cand_r, double* __restrict__ top_d,
+                                                         int32_t* __restrict__ top_r) {
+  constexpr int32_t SENT = 0x7fffffff;
+  constexpr int NC = SNAP_T * SNAP_T;
+  __shared__ double hd[SNAP_MAXBLK];
+  __shared__ int32_t hr[SNAP_MAXBLK];
+  __shared__ double sd[NC];
+  __shared__ int32_t sr[NC];
+  __shared__ int cnt;
+  const int j = blockIdx.x, tid = threadIdx.x;
+  const int64_t base = (int64_t)j * nblk * SNAP_T;
+  const double INF = __builtin_huge_val();
+  int P2 = 1;
+  while (P2 < nblk) P2 <<= 1;
+  for (int e = tid; e < P2; e += 256) {
+    hd[e] = e < nblk ? cand_d[base + (int64_t)e * SNAP_T] : INF;
+    hr[e] = e < nblk ? cand_r[base + (int64_t)e * SNAP_T] : SENT;
+  }
+  for (int e = tid; e < NC; e += 256) { sd[e] = INF; sr[e] = SENT; }
+  if (tid == 0) cnt = 0;
+  __syncthreads();
+  bitonic_pairs<SNAP_MAXBLK, 256>(hd, hr, P2);
+  const double tau = P2 >= SNAP_T ? hd[SNAP_T - 1] : INF;
+  const int32_t taur = P2 >= SNAP_T ? hr[SNAP_T - 1] : SENT;
+  for (int b = tid; b < nblk; b += 256) {
+    const int64_t o = base + (int64_t)b * SNAP_T;
+    for (int q = 0; q < SNAP_T; ++q) {
+      const double d = cand_d[o + q];
+      const int32_t r = cand_r[o + q];
+      if (r == SENT || pair_gt(d, r, tau, taur)) break;
+      const int slot = atomicAdd(&cnt, 1);
+      if (slot < NC) { sd[slot] = d; sr[slot] = r; }
+    }
+  }
+  __syncthreads();
+  bitonic_pairs<NC, 256>(sd, sr, NC);
+  if (tid < SNAP_T) {
+    top_d[(int64_t)j * SNAP_T + tid] = sd[tid];
+    top_r[(int64_t)j * SNAP_T + tid] = sr[tid];
   }
 }
 
@@ -743,7 +774,6 @@ __global__ __launch_bounds__(256) void snap_merge_kernel(int nblk, const double*
 // recomputed and the rescan set widened until no further block qualifies.
 constexpr int RES_CHUNK = 128;
 constexpr int RES_HT = 2048;  // hash slots for taken rows (k <= KM_MAXK = RES_HT / 2)
-constexpr int RES_MAXBLK = 256;
 
 __device__ __forceinline__ int res_slot(int32_t r) { return (int)(((uint32_t)r * 2654435761u) >> 21); }
 __device__ __forceinline__ bool res_has(const int32_t* ht, int32_t r) {
@@ -774,8 +804,8 @@ __global__ __launch_bounds__(1024) void snap_resolve_kernel(
   __shared__ double ld[RES_CHUNK * SNAP_T];
   __shared__ int32_t lr[RES_CHUNK * SNAP_T];
   __shared__ double lz[RES_CHUNK];
-  __shared__ double b_fd[RES_MAXBLK], b_bound[RES_MAXBLK], b_smin[RES_MAXBLK];
-  __shared__ int32_t b_state[RES_MAXBLK];  // 0 list, 1 rescanned, 2 rescan pending
+  __shared__ double b_fd[SNAP_MAXBLK], b_bound[SNAP_MAXBLK], b_smin[SNAP_MAXBLK];
+  __shared__ int32_t b_state[SNAP_MAXBLK];  // 0 list, 1 rescanned, 2 rescan pending
   __shared__ double wred[16];
   __shared__ int64_t wrow[16];
   __shared__ int sh_next, sh_more;
@@ -982,9 +1012,12 @@ struct KmWs {
   size_t total;
 };
 
-static inline int snap_nblk(int64_t rows) {
-  int64_t nb = ceil_div(rows, 512);
-  if (nb > 256) nb = 256;
+// Row blocks of the top-T pass: about SNAP_ROWS rows each, at most
+// SNAP_MAXBLK, and at most SNAP_MAXCAND / k so the candidate lists stay bounded.
+static inline int snap_nblk(int64_t rows, int k) {
+  int64_t nb = ceil_div(rows, SNAP_ROWS);
+  const int64_t cap = std::min<int64_t>(SNAP_MAXBLK, std::max<int64_t>(1, SNAP_MAXCAND / k));
+  if (nb > cap) nb = cap;
   return (int)(nb < 1 ? 1 : nb);
 }
 constexpr int RED_NB = 256;
@@ -996,7 +1029,7 @@ static KmWs km_layout(void* base, int64_t rows, int dim, int k, int compute) {
   auto take = [&](size_t bytes) { void* q = p ? p + off : nullptr; off += al256(bytes); return q; };
   const int64_t nsb = ceil_div(rows, HIST_SB);
   const int64_t maxch = ceil_div(rows, CENT_CH) + k;
-  const int nblk = snap_nblk(rows);
+  const int nblk = snap_nblk(rows, k);
   w.Zc = take((size_t)k * dim * prec_bytes(compute));
   w.znorm = (double*)take(k * 8);
   w.pnorm = (double*)take(rows * 8);
@@ -1086,7 +1119,7 @@ static hipError_t kmeans_t(int compute, int64_t rows, int dim, int k, const void
                        Zc, W.znorm);
   }
   if (out.snap) {
-    const int nblk = snap_nblk(rows);
+    const int nblk = snap_nblk(rows, k);
     const int64_t rpb = ceil_div(ceil_div(rows, nblk), SNAP_SUB) * SNAP_SUB;
     const int nblk_eff = (int)ceil_div(rows, rpb);
     TimerScope ts(T_SNAP, st);

@@ -87,6 +87,152 @@ __global__ __launch_bounds__(256) void tsgemm_kernel(int64_t M, int K, int N, co
   }
 }
 
+// Fast path for K <= TSF_KMAX, rows of X and B^T whole 16-byte runs (K a
+// multiple of 16 / sizeof(TC), X 16-byte aligned): a workgroup (4 waves, 64 rows) keeps its rows
+// of X as 16-byte MFMA fragment runs in registers for the whole kernel and
+// streams B^T through LDS in chunks of CT column tiles, stored in fragment
+// order (each B read is one contiguous 16-byte LDS read per lane); the next
+// chunk is loaded into registers while the current one is multiplied.  Same
+// outputs as tsgemm_kernel (Y, FP64 row and per-block column sums of squares).
+constexpr int TSF_KMAX = 256;
+template <typename TC> struct TsfCT { static constexpr int v = 4; };
+template <> struct TsfCT<double> { static constexpr int v = 1; };
+
+template <typename TC>
+static size_t tsf_lds_bytes(int nkb, int N) {
+  return (size_t)TsfCT<TC>::v * nkb * 64 * 16 + (size_t)4 * N * sizeof(double);
+}
+
+template <typename TC> struct TsfOcc { static constexpr int v = 2; };
+template <> struct TsfOcc<double> { static constexpr int v = 1; };  // FP64 rows of K <= 256 fill 128 registers
+
+// NKB (k blocks of 4 runs) is a compile-time constant, so the loads, the LDS
+// stores and the MFMA sequence carry no run-time guards; k blocks past K read
+// zeros.
+template <typename TC, int NKB>
+__global__ __launch_bounds__(256, TsfOcc<TC>::v) void tsgemm_fast_kernel(int64_t M, int K, int N,
+                                                                         const TC* __restrict__ X,
+                                                                         const TC* __restrict__ Bt,
+                                                                         TC* __restrict__ Y,
+                                                                         double* __restrict__ colpart,
+                                                                         double* __restrict__ rowsq) {
+  typedef typename Mfma<TC>::acc AccV;
+  constexpr int CT = TsfCT<TC>::v;
+  constexpr int VE = 16 / sizeof(TC);          // elements per 16-byte run
+  constexpr int SPV = VE / Mfma<TC>::KPL;      // MFMA steps per run
+  constexpr int KBW = 4 * VE;                  // k per block (4 lane groups)
+  constexpr int PER_CHUNK = CT * NKB * 64;     // runs per chunk
+  constexpr int PF = (PER_CHUNK + 255) / 256;  // prefetch runs per thread
+  extern __shared__ uint4 tsf_lds[];
+  uint4* bs = tsf_lds;                                  // [CT][NKB][64] runs
+  double* cp = (double*)(tsf_lds + PER_CHUNK);          // [4][N] per-wave column sums
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int g = lane >> 4, c16 = lane & 15;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  uint4 a[NKB];
+#pragma unroll
+  for (int kb = 0; kb < NKB; ++kb) a[kb] = load_run_al<TC>(X, M, K, row0 + c16, kb * KBW + g * VE, true);
+  uint4 pf[PF];
+  auto prefetch = [&](int cc) {
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int e = tid + 256 * u;
+      const int t = e / (NKB * 64), rem = e - t * (NKB * 64), kb = rem >> 6, l = rem & 63;
+      pf[u] = load_run_al<TC>(Bt, N, K, cc + 16 * t + (l & 15), kb * KBW + (l >> 4) * VE, e < PER_CHUNK);
+    }
+  };
+  double rs[4] = {0.0, 0.0, 0.0, 0.0};
+  prefetch(0);
+  for (int cc = 0; cc < N; cc += CT * 16) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int e = tid + 256 * u;
+      if ((u + 1) * 256 <= PER_CHUNK || e < PER_CHUNK) bs[e] = pf[u];
+    }
+    __syncthreads();
+    if (cc + CT * 16 < N) prefetch(cc + CT * 16);
+    AccV acc[CT];
+#pragma unroll
+    for (int t = 0; t < CT; ++t) acc[t] = Mfma<TC>::zero();
+    // tiles of the chunk that hold columns (a compile-time count per case, so
+    // a chunk with fewer than CT tiles skips the empty ones)
+    auto mm = [&](auto ntc) {
+      constexpr int NT = decltype(ntc)::value;
+#pragma unroll
+      for (int kb = 0; kb < NKB; ++kb) {
+        uint4 b[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) b[t] = bs[(t * NKB + kb) * 64 + lane];
+#pragma unroll
+        for (int s2 = 0; s2 < SPV; ++s2)
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            acc[t] = Mfma<TC>::mma(Vec16<TC>::frag(a[kb], s2), Vec16<TC>::frag(b[t], s2), acc[t]);
+      }
+    };
+    const int ntile = (N - cc + 15) / 16;
+    if (ntile >= CT) mm(std::integral_constant<int, CT>{});
+    else if constexpr (CT == 4) {
+      if (ntile == 1) mm(std::integral_constant<int, 1>{});
+      else if (ntile == 2) mm(std::integral_constant<int, 2>{});
+      else mm(std::integral_constant<int, 3>{});
+    }
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      const int col = cc + t * 16 + c16;
+      double cs = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t row = row0 + out_row<TC>(g, i);
+        const bool ok = row < M && col < N;
+        const double v = ok ? (double)acc[t][i] : 0.0;
+        if (ok && Y != nullptr) Y[row * N + col] = from_f64<TC>(v);
+        rs[i] += v * v;
+        cs += v * v;
+      }
+      cs += __shfl_xor(cs, 16, 64);
+      cs += __shfl_xor(cs, 32, 64);
+      if (colpart != nullptr && g == 0 && col < N) cp[wave * N + col] = cs;
+    }
+  }
+  if (rowsq != nullptr) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double v = rs[i];
+      v += __shfl_xor(v, 1, 64);
+      v += __shfl_xor(v, 2, 64);
+      v += __shfl_xor(v, 4, 64);
+      v += __shfl_xor(v, 8, 64);
+      const int64_t row = row0 + out_row<TC>(g, i);
+      if (c16 == 0 && row < M) rowsq[row] = v;
+    }
+  }
+  if (colpart != nullptr) {
+    __syncthreads();
+    for (int col = tid; col < N; col += 256)
+      colpart[(int64_t)blockIdx.x * N + col] = ((cp[col] + cp[N + col]) + cp[2 * N + col]) + cp[3 * N + col];
+  }
+}
+
+// Compiled k-block counts per type (the smallest one >= the needed count is used).
+template <typename TC> struct TsfNkb;
+template <> struct TsfNkb<float> { static constexpr int v[4] = {4, 8, 13, 16}; };
+template <> struct TsfNkb<double> { static constexpr int v[4] = {8, 16, 25, 32}; };
+template <> struct TsfNkb<bf16> { static constexpr int v[4] = {2, 4, 7, 8}; };
+template <> struct TsfNkb<f16> { static constexpr int v[4] = {2, 4, 7, 8}; };
+
+template <typename TC, int I>
+static void tsf_launch_i(int nkb, dim3 grid, hipStream_t st, int64_t M, int K, int N, const TC* X, const TC* Bt, TC* Y,
+                         double* colpart, double* rowsq) {
+  constexpr int NKB = TsfNkb<TC>::v[I];
+  if constexpr (I < 3) {
+    if (nkb > NKB) return tsf_launch_i<TC, I + 1>(nkb, grid, st, M, K, N, X, Bt, Y, colpart, rowsq);
+  }
+  hipLaunchKernelGGL((tsgemm_fast_kernel<TC, NKB>), grid, dim3(256), tsf_lds_bytes<TC>(NKB, N), st, M, K, N, X, Bt, Y,
+                     colpart, rowsq);
+}
+
 // out[c] = sum over b of part[b * N + c], in a fixed order: 16 interleaved
 // segments per column, then the 16 segment sums in order.
 __global__ __launch_bounds__(256) void colreduce_kernel(int64_t nb, int N, const double* __restrict__ part,
@@ -120,8 +266,13 @@ static hipError_t tsgemm_t(int64_t M, int K, int N, const void* X, const double*
   double* part = (double*)((char*)ws + align256((size_t)K * N * sizeof(TC)));
   hipLaunchKernelGGL(convert_bt_kernel<TC>, dim3((unsigned)ceil_div((int64_t)K * N, 256)), dim3(256), 0, st, K, N, B, Bt);
   const int64_t nb = ceil_div(M, 64);
-  hipLaunchKernelGGL(tsgemm_kernel<TC>, dim3((unsigned)nb), dim3(256), 0, st, M, K, N, (const TC*)X, Bt, (TC*)Y,
-                     colsq ? part : nullptr, rowsq);
+  if (K <= TSF_KMAX && ((size_t)K * sizeof(TC)) % 16 == 0 && ((uintptr_t)X % 16) == 0) {
+    const int nkb = (int)ceil_div(K, 4 * (16 / (int)sizeof(TC)));
+    tsf_launch_i<TC, 0>(nkb, dim3((unsigned)nb), st, M, K, N, (const TC*)X, Bt, (TC*)Y, colsq ? part : nullptr, rowsq);
+  } else {
+    hipLaunchKernelGGL(tsgemm_kernel<TC>, dim3((unsigned)nb), dim3(256), 0, st, M, K, N, (const TC*)X, Bt, (TC*)Y,
+                       colsq ? part : nullptr, rowsq);
+  }
   if (colsq) hipLaunchKernelGGL(colreduce_kernel, dim3((unsigned)ceil_div(N, 16)), dim3(256), 0, st, nb, N, part, colsq);
   return hipGetLastError();
 }
