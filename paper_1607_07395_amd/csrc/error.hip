@@ -132,6 +132,33 @@ __device__ __forceinline__ double row16_sum(double v) {
   return v;
 }
 
+// Runs of four in the element type (same addressing as Run4, widened later).
+template <typename T, bool VEC> struct RawRun4 {
+  __device__ static __forceinline__ void get(const T* p, int e, int lim, T (&o)[4]) {
+    if constexpr (VEC) {
+      static_assert(sizeof(T) <= 8, "element type");
+      const T* src = e < lim ? p + e : (const T*)kZeroRun;
+      if constexpr (sizeof(T) == 8) {
+        const double2 a = *(const double2*)src, b = *(const double2*)(src + 2);
+        o[0] = __builtin_bit_cast(T, a.x); o[1] = __builtin_bit_cast(T, a.y);
+        o[2] = __builtin_bit_cast(T, b.x); o[3] = __builtin_bit_cast(T, b.y);
+      } else if constexpr (sizeof(T) == 4) {
+        const float4 v = *(const float4*)src;
+        o[0] = __builtin_bit_cast(T, v.x); o[1] = __builtin_bit_cast(T, v.y);
+        o[2] = __builtin_bit_cast(T, v.z); o[3] = __builtin_bit_cast(T, v.w);
+      } else {
+        const uint2 v = *(const uint2*)src;
+        const T* h = (const T*)&v;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) o[w] = h[w];
+      }
+    } else {
+#pragma unroll
+      for (int w = 0; w < 4; ++w) o[w] = *(e + w < lim ? p + e + w : (const T*)kZeroRun);
+    }
+  }
+};
+
 // FP32 runs of four (same addressing as Run4, no widening).
 template <bool VEC>
 __device__ __forceinline__ void run4_f32(const float* p, int e, int lim, float (&o)[4]) {
@@ -291,15 +318,24 @@ constexpr int EB_BBITS = 13;
 constexpr int EB_MAXB = 1 << EB_BBITS;   // buckets at most
 constexpr int EB_G = 512;       // sample chunks of the counting sort
 
-struct EbPlan { int64_t rb; int nbk; int64_t tchunk; };
+// Sample keys: row bucket (rb consecutive rows) times column stripe (sw
+// consecutive columns), row-bucket major: key = (i / rb) * ns + j / sw.
+struct EbPlan { int64_t rb; int nrb; int ns; int64_t sw; int nbk; int64_t tchunk; };
 
-static inline EbPlan eb_plan(int64_t m, int64_t ns) {
+static inline EbPlan eb_plan(int64_t m, int64_t n, int64_t nsamp, int stripes) {
   EbPlan p;
-  p.rb = ceil_div(m, EB_MAXB);
-  if (p.rb < 16) p.rb = 16;  // a full 16-row bucket per work-group
-  p.nbk = (int)ceil_div(m, p.rb);
-  p.tchunk = ceil_div(ns, EB_G);
+  p.ns = stripes;
+  p.sw = ceil_div(n, stripes);
+  p.rb = ceil_div(m, EB_MAXB / stripes);
+  if (p.rb < 16) p.rb = 16;  // at least a 16-row bucket per work-group
+  p.nrb = (int)ceil_div(m, p.rb);
+  p.nbk = p.nrb * stripes;
+  p.tchunk = ceil_div(nsamp, EB_G);
   return p;
+}
+
+__device__ __forceinline__ int eb_key(const EbPlan& p, int64_t i, int64_t j) {
+  return (int)(i / p.rb) * p.ns + (int)(j / p.sw);
 }
 
 // The sorted path needs n_s, m, n < 2^31 (kept as int32) and at least one
@@ -321,7 +357,7 @@ __global__ __launch_bounds__(256) void eb_count_kernel(int64_t m, int64_t n, int
     int64_t i, j;
     err_sample_ij((uint64_t)t, seed, m, n, i, j);
     ij[t] = make_int2((int)i, (int)j);
-    atomicAdd(&hist[(int)(i / pl.rb)], 1);
+    atomicAdd(&hist[eb_key(pl, i, j)], 1);
   }
   __syncthreads();
   for (int b = threadIdx.x; b < pl.nbk; b += 256) counts[(int64_t)b * EB_G + blockIdx.x] = hist[b];
@@ -408,7 +444,7 @@ __global__ __launch_bounds__(256) void eb_scatter_kernel(int64_t ns, EbPlan pl, 
     const int64_t t = base + tid;
     const bool valid = t < t1;
     const int2 e = valid ? ij[t] : make_int2(0, 0);
-    const int b = valid ? (int)(e.x / pl.rb) : -1;
+    const int b = valid ? eb_key(pl, e.x, e.y) : -1;
     // lanes holding the same bucket: one ballot per bit of the bucket number
     // (invalid lanes carry -1, whose top bit no valid bucket has)
     uint64_t same = ~0ull;
@@ -449,19 +485,24 @@ __global__ __launch_bounds__(256) void eb_eval_kernel(MatView mv, int kr, const 
   err_block_store(num, den, part, b);
 }
 
-// Low-rank source with FP32 tables, buckets of at most ER_RB rows and k, r <=
-// ER_KMAX: one 16-lane group per row of the bucket.  The group keeps its row's
-// FP64 CU run and FP32 pf o s run in registers, so only the column side of a
-// sample (R^T_j and qf_j) is loaded per sample, with the next sample's loads
-// in flight while the current one is reduced.  The bucket's samples (in
-// bucket order) go through LDS in chunks of ER_CH: each wave ranks its 512 by
-// row (per-row running counts in LDS), the row segments are laid out in row
-// order and, within a row, in bucket order, and lane t draws the noise of
-// its samples on the way.  Sums are per row in sample order, then rows, then
-// blocks, in fixed orders.
-constexpr int ER_RB = 16;
+// Low-rank source with FP32 tables, row buckets of at most ER_RB rows and k,
+// r <= ER_KMAX.  Samples are keyed by (row bucket, column stripe) with ER_S
+// stripes, one work-group per key; block ids are dealt to the XCDs in turn,
+// so all work-groups of a stripe run on one XCD and the column side of their
+// samples (R^T_j and qf_j) comes from that XCD's L2.  Within a work-group the
+// samples are laid out by row (16-lane group g takes rows g, g + 16, ...; a
+// row's samples stay in key order), every lane drawing the noise of the
+// samples it places.  A group walks its samples holding the current row's
+// FP64 CU run and FP32 pf o s run in registers, loads only the column side
+// per sample, with the next ER_D samples' loads in flight, and lane q keeps
+// the sums of every 16th sample so that residuals are formed 16 at a time.
+// Sums are per lane in sample order, then lanes, groups and work-groups, in
+// fixed orders.
+constexpr int ER_RB = 128;
 constexpr int ER_CH = 2048;
 constexpr int ER_KMAX = 256;
+constexpr int ER_D = 2;
+constexpr int ER_S = 8;
 
 template <typename TC, bool VEC>
 __global__ __launch_bounds__(256) void eb_eval_rows_kernel(MatView mv, int kr, const double* __restrict__ CU,
@@ -472,139 +513,202 @@ __global__ __launch_bounds__(256) void eb_eval_rows_kernel(MatView mv, int kr, c
   constexpr int SETS = ER_CH / 256;  // 64-record sets per wave and chunk
   __shared__ int32_t sj[ER_CH];
   __shared__ double snz[ER_CH];
+  __shared__ uint8_t sro[ER_CH];
+  __shared__ int2 tmp[ER_CH];
   __shared__ int wrun[4][ER_RB];
-  __shared__ int rbeg[ER_RB + 1];
   __shared__ int wbase[4][ER_RB];
+  __shared__ int gbeg[17];
   __shared__ double gn[16], gd[16];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, grp = tid >> 4;
-  const int b = blockIdx.x;
-  const int64_t row0 = (int64_t)b * pl.rb;
+  const int key = blockIdx.x;
+  const int64_t row0 = (int64_t)(key / pl.ns) * pl.rb;
   const int r = mv.r;
-  // this group's row: FP64 CU run and FP32 pf o s run (zero past k, r and the bucket)
-  const int64_t myrow = row0 + grp;
-  const bool rowok = grp < pl.rb && myrow < mv.m;
-  double cu[4][4];
-  float ps[4][4];
+  // per-lane byte offsets of the four runs in a row; with whole runs (VEC) a
+  // run past k or r is moved to the row's last run, whose values then meet a
+  // zero run of the row side (the other case loads element by element)
+  int off_rt[4], off_qf[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int c = 64 * v + 4 * l16;
-    Run4<double, VEC>::get(CU + (rowok ? myrow : 0) * kr, c, rowok ? kr : 0, cu[v]);
-    float pv[4], sv4[4];
-    run4_f32<VEC>((const float*)mv.pf + (rowok ? myrow : 0) * r, c, rowok ? r : 0, pv);
-    run4_f32<VEC>((const float*)mv.s, c, r, sv4);
-#pragma unroll
-    for (int w = 0; w < 4; ++w) ps[v][w] = pv[w] * sv4[w];
+    off_rt[v] = (c + 4 <= kr ? c : kr - 4) * (int)sizeof(TC);
+    off_qf[v] = (c + 4 <= r ? c : r - 4) * (int)sizeof(float);
   }
-  double num = 0.0, den = 0.0;  // kept by lane 0 of each group
-  const int s0 = starts[b], s1 = starts[b + 1];
+  double num = 0.0, den = 0.0;  // per lane: its samples' residuals
+  const int s0 = starts[key], s1 = starts[key + 1];
   for (int c0 = s0; c0 < s1; c0 += ER_CH) {
     const int n = s1 - c0 < ER_CH ? s1 - c0 : ER_CH;
-    if (lane < ER_RB) wrun[wave][lane] = 0;
+    for (int e = lane; e < ER_RB; e += 64) wrun[wave][e] = 0;
     wave_lds_fence();
-    // pass A: wave w takes records w * 512 + 64 k + lane; rank within equal rows
-    int ro[SETS], jv[SETS], posl[SETS];
-    double nz[SETS];
-#pragma unroll
+    // pass A: wave w takes records w * (ER_CH / 4) + 64 k + lane; rank within
+    // equal layout keys (row % 16, row / 16); (key, rank, column) to LDS
+#pragma unroll 1
     for (int k = 0; k < SETS; ++k) {
       const int idx = wave * (ER_CH / 4) + 64 * k + lane;
       const bool valid = idx < n;
       const int2 e = valid ? sorted[c0 + idx] : make_int2(0, 0);
-      ro[k] = valid ? (int)(e.x - row0) : -1;
-      jv[k] = e.y;
-      nz[k] = (valid && mv.noise_std != 0.0) ? noise_f64(mv.noise_seed, (uint64_t)e.x, (uint64_t)e.y) : 0.0;
+      const int ro = (int)(e.x - row0);
+      const int lk = valid ? ((ro & 15) << 3) | (ro >> 4) : -1;
       uint64_t same = ~0ull;
 #pragma unroll
-      for (int bit = 0; bit < 5; ++bit) {  // ro in [-1, 16): five bits tell them apart
-        const bool on = (ro[k] >> bit) & 1;
+      for (int bit = 0; bit < 8; ++bit) {  // lk in [-1, 128): eight bits tell them apart
+        const bool on = (lk >> bit) & 1;
         const uint64_t bb = __ballot(on);
         same &= on ? bb : ~bb;
       }
       const int rank = __builtin_popcountll(same & ((1ull << lane) - 1ull));
       const bool last = ((same >> lane) >> 1) == 0;
-      const int rs = valid ? ro[k] : 0;
-      posl[k] = wrun[wave][rs] + rank;
+      const int ls = valid ? lk : 0;
+      const int posl = wrun[wave][ls] + rank;
       wave_lds_fence();
-      if (valid && last) wrun[wave][rs] += rank + 1;
+      if (valid && last) wrun[wave][ls] += rank + 1;
+      tmp[idx] = make_int2(valid ? (lk << 16) | posl : -1, e.y);
       wave_lds_fence();
     }
     __syncthreads();
-    if (tid == 0) {
-      int run = 0;
-      for (int rr = 0; rr < ER_RB; ++rr) {
-        rbeg[rr] = run;
-        for (int w = 0; w < 4; ++w) { wbase[w][rr] = run; run += wrun[w][rr]; }
-      }
-      rbeg[ER_RB] = run;
-    }
-    __syncthreads();
-    // pass B: samples to their row segments
+    // layout: key lk's segment starts after all smaller keys; within a key, waves in order
+    if (tid < ER_RB) {
+      int tot = 0;
 #pragma unroll
+      for (int w = 0; w < 4; ++w) tot += wrun[w][tid];
+      wbase[0][tid] = tot;  // staged for the scan below
+    }
+    __syncthreads();
+    if (wave == 0) {  // exclusive scan of the ER_RB key totals, two per lane
+      const int a0 = wbase[0][2 * lane], a1 = wbase[0][2 * lane + 1];
+      int incl = a0 + a1;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int x = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += x;
+      }
+      const int ex = incl - a0 - a1;
+      wave_lds_fence();
+      int run0 = ex, run1 = ex + a0;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int c0w = wrun[w][2 * lane], c1w = wrun[w][2 * lane + 1];
+        wbase[w][2 * lane] = run0;
+        wbase[w][2 * lane + 1] = run1;
+        run0 += c0w;
+        run1 += c1w;
+      }
+      if ((lane & 3) == 0) gbeg[lane >> 2] = ex;  // key 8 g starts group g's segment
+      if (lane == 63) gbeg[16] = incl;
+    }
+    __syncthreads();
+    // pass B: samples to their segments, with their noise
+#pragma unroll 1
     for (int k = 0; k < SETS; ++k) {
-      if (ro[k] >= 0) {
-        const int pos = wbase[wave][ro[k]] + posl[k];
-        sj[pos] = jv[k];
-        snz[pos] = nz[k];
+      const int idx = wave * (ER_CH / 4) + 64 * k + lane;
+      const int2 t = tmp[idx];
+      if (idx < n && t.x >= 0) {
+        const int lk = t.x >> 16, pos = wbase[wave][lk] + (t.x & 0xffff);
+        const int ro = ((lk & 7) << 4) | (lk >> 3);
+        sj[pos] = t.y;
+        sro[pos] = (uint8_t)ro;
+        snz[pos] = mv.noise_std != 0.0 ? noise_f64(mv.noise_seed, (uint64_t)(row0 + ro), (uint64_t)t.y) : 0.0;
       }
     }
     __syncthreads();
-    // group grp: the samples of its row, in order, with the next one's loads in flight
-    if (rowok) {
-      const int p0 = rbeg[grp], p1 = rbeg[grp + 1];
-      const float* qfb = (const float*)mv.qf;
-      double bq[4][4];
-      float yq[4][4];
-      auto fetch = [&](int p, double (&bo)[4][4], float (&yo)[4][4]) {
+    // group grp: its samples in order, ER_D of them in flight
+    const int p0 = gbeg[grp], p1 = gbeg[grp + 1];
+    if (p0 < p1) {
+      const char* rtb = (const char*)Rt;
+      const char* qfb = (const char*)mv.qf;
+      TC bq[ER_D][4][4];  // raw R^T_j runs (widened at use)
+      float yq[ER_D][4][4];
+      auto fetch = [&](int p, TC (&bo)[4][4], float (&yo)[4][4]) {
         const int64_t j = sj[p];
+        const char* rrow = rtb + j * kr * (int64_t)sizeof(TC);
+        const char* qrow = qfb + j * r * (int64_t)sizeof(float);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int c = 64 * v + 4 * l16;
-          Run4<TC, VEC>::get(Rt + j * kr, c, kr, bo[v]);
-          run4_f32<VEC>(qfb + j * r, c, r, yo[v]);
+          if constexpr (VEC) {
+            RawRun4<TC, true>::get((const TC*)(rrow + off_rt[v]), 0, 4, bo[v]);
+            run4_f32<true>((const float*)(qrow + off_qf[v]), 0, 4, yo[v]);
+          } else {
+            const int c = 64 * v + 4 * l16;
+            RawRun4<TC, false>::get((const TC*)rrow, c, kr, bo[v]);
+            run4_f32<false>((const float*)qrow, c, r, yo[v]);
+          }
         }
       };
-      if (p0 < p1) fetch(p0, bq, yq);
-      for (int p = p0; p < p1; ++p) {
-        double bc[4][4];
-        float yc[4][4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
+      for (int d = 0; d < ER_D; ++d)
+        if (p0 + d < p1) fetch(p0 + d, bq[d], yq[d]);
+      double cu[4][4];
+      float ps[4][4];
+      int cur = -1;
+      double my_ap = 0.0;
+      float my_sv = 0.0f;
+      for (int p = p0; p < p1; p += ER_D) {
 #pragma unroll
-          for (int w = 0; w < 4; ++w) { bc[v][w] = bq[v][w]; yc[v][w] = yq[v][w]; }
-        if (p + 1 < p1) fetch(p + 1, bq, yq);
-        double ap = 0.0;
-        float sv = 0.0f;
+        for (int d = 0; d < ER_D; ++d) {
+          const int pp = p + d;
+          if (pp < p1) {
+            const int ro = sro[pp];
+            if (ro != cur) {  // the row side of a new row (uniform in the group)
+              cur = ro;
+              const int64_t row = row0 + ro;
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
+              for (int v = 0; v < 4; ++v) {
+                const int c = 64 * v + 4 * l16;
+                Run4<double, VEC>::get(CU + row * kr, c, kr, cu[v]);
+                float pv[4], sv4[4];
+                run4_f32<VEC>((const float*)mv.pf + row * r, c, r, pv);
+                run4_f32<VEC>((const float*)mv.s, c, r, sv4);
 #pragma unroll
-          for (int w = 0; w < 4; ++w) {
-            ap += cu[v][w] * bc[v][w];
-            sv += ps[v][w] * yc[v][w];
+                for (int w = 0; w < 4; ++w) ps[v][w] = pv[w] * sv4[w];
+              }
+            }
+            double ap = 0.0;
+            float sv = 0.0f;
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+              for (int w = 0; w < 4; ++w) {
+                ap += cu[v][w] * to_f64(bq[d][v][w]);
+                sv += ps[v][w] * yq[d][v][w];
+              }
+            if (pp + ER_D < p1) fetch(pp + ER_D, bq[d], yq[d]);
+            ap = row16_sum(ap);
+            sv = row16_sum(sv);
+            const int q = (pp - p0) & 15;
+            if (l16 == q) { my_ap = ap; my_sv = sv; }
+            if (q == 15 || pp + 1 == p1) {  // residuals of the last 16 samples, one per lane
+              if (l16 <= q) {
+                const double av = (double)my_sv + mv.noise_std * snz[pp - q + l16];
+                num += (av - my_ap) * (av - my_ap);
+                den += av * av;
+              }
+            }
           }
-        ap = row16_sum(ap);
-        sv = row16_sum(sv);
-        if (l16 == 0) {
-          const double av = (double)sv + mv.noise_std * snz[p];
-          num += (av - ap) * (av - ap);
-          den += av * av;
         }
       }
     }
-    __syncthreads();  // sj / snz / wrun reused by the next chunk
+    __syncthreads();  // LDS reused by the next chunk
   }
+  num = row16_sum(num);
+  den = row16_sum(den);
   if (l16 == 0) { gn[grp] = num; gd[grp] = den; }
   __syncthreads();
   if (tid == 0) {
     double n2 = 0.0, d2 = 0.0;
     for (int g = 0; g < 16; ++g) { n2 += gn[g]; d2 += gd[g]; }
-    part[2 * (int64_t)b] = n2;
-    part[2 * (int64_t)b + 1] = d2;
+    part[2 * (int64_t)key] = n2;
+    part[2 * (int64_t)key + 1] = d2;
   }
 }
 
 static inline bool er_rows_ok(const MatView& mv, int kr, int64_t ns) {
   if (mv.kind != SRC_LOWRANK || mv.storage != P_F32) return false;
   if (!eb_use(mv.m, mv.n, ns)) return false;
-  return eb_plan(mv.m, ns).rb <= ER_RB && kr <= ER_KMAX && mv.r <= ER_KMAX;
+  return eb_plan(mv.m, mv.n, ns, ER_S).rb <= ER_RB && kr >= 4 && kr <= ER_KMAX && mv.r >= 4 && mv.r <= ER_KMAX;
+}
+
+// The sorted path's plan: column stripes when the row kernel takes it.
+static inline EbPlan eb_plan_for(const MatView& mv, int kr, int64_t ns) {
+  return eb_plan(mv.m, mv.n, ns, er_rows_ok(mv, kr, ns) ? ER_S : 1);
 }
 
 template <typename TIn>
@@ -699,19 +803,19 @@ static inline int64_t exact_nb(const MatView& mv) { return ceil_div(mv.m, 64); }
 
 static inline int64_t part_blocks(const MatView& mv, int kr, int64_t ns) {
   if (ns == 0) return exact_nb(mv);
-  return eb_use(mv.m, mv.n, ns) ? eb_plan(mv.m, ns).nbk : ERR_NB;
+  return eb_use(mv.m, mv.n, ns) ? eb_plan_for(mv, kr, ns).nbk : ERR_NB;
 }
 
-static inline size_t eb_ws_bytes(const MatView& mv, int64_t ns) {
+static inline size_t eb_ws_bytes(const MatView& mv, int kr, int64_t ns) {
   if (ns == 0 || !eb_use(mv.m, mv.n, ns)) return 0;
-  const EbPlan pl = eb_plan(mv.m, ns);
+  const EbPlan pl = eb_plan_for(mv, kr, ns);
   return 2 * al256e((size_t)pl.nbk * EB_G * 4) + 2 * al256e(((size_t)pl.nbk + 1) * 4) + 2 * al256e((size_t)ns * 8);
 }
 
 size_t error_ws_bytes(const MatView& mv, int k2c, int k2r, int compute, int64_t n_samples) {
   const int64_t nb = part_blocks(mv, k2r, n_samples);
   size_t b = al256e((size_t)mv.m * k2r * sizeof(double)) + tsgemm_ws_bytes(mv.m, k2c, k2r, P_F64) +
-             al256e((size_t)nb * 2 * sizeof(double)) + eb_ws_bytes(mv, n_samples) + 256;
+             al256e((size_t)nb * 2 * sizeof(double)) + eb_ws_bytes(mv, k2r, n_samples) + 256;
   if (compute != P_F64) {
     b += al256e((size_t)mv.m * k2c * sizeof(double));                     // C in FP64
     if (n_samples == 0) b += al256e((size_t)mv.n * k2r * sizeof(double));  // Rt in FP64 (exact mode)
@@ -766,7 +870,7 @@ static hipError_t error_t(const MatView& mv, int kr, const double* CU, const TC*
                    (mv.kind == SRC_DENSE || (tabn % 4 == 0 && al16(t0) && al16(t1) && al16(t2)));
   int nb;
   if (ns > 0 && eb_use(mv.m, mv.n, ns)) {
-    const EbPlan pl = eb_plan(mv.m, ns);
+    const EbPlan pl = eb_plan_for(mv, kr, ns);
     int32_t* counts = (int32_t*)ebws;
     int32_t* offs = (int32_t*)(ebws + al256e((size_t)pl.nbk * EB_G * 4));
     int32_t* totals = (int32_t*)((char*)offs + al256e((size_t)pl.nbk * EB_G * 4));
@@ -820,7 +924,7 @@ hipError_t launch_error(const MatView& mv, int k2c, int k2r, int compute, const 
   double* part = (double*)p;
   p += al256e((size_t)part_blocks(mv, k2r, n_samples) * 2 * sizeof(double));
   char* ebws = p;
-  p += eb_ws_bytes(mv, n_samples);
+  p += eb_ws_bytes(mv, k2r, n_samples);
   const double* C64 = (const double*)C;
   const double* Rt64 = (const double*)Rt;
   if (compute != P_F64) {
