@@ -298,6 +298,10 @@ __global__ __launch_bounds__(256) void bj_norm_kernel(int rows, int cols, const 
   if (threadIdx.x == 0) v.fro2[0] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
+// A zero that out-of-range loads are pointed at (global memory, never written),
+// so that the loads need no branch.
+static __device__ double kBjZero[2] = {0.0, 0.0};
+
 // Gram of the 16 columns cols(c) = block ba (c < 8) / bb (c >= 8), rows [r0, r1), by one wave;
 // 8 row quads are loaded before their MFMAs.
 __device__ __forceinline__ f64x4 pair_gram(const BjView& v, int ba, int bb, int r0, int r1) {
@@ -310,7 +314,7 @@ __device__ __forceinline__ f64x4 pair_gram(const BjView& v, int ba, int bb, int 
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int rr = r + 4 * u + g;
-      x[u] = rr < r1 ? xc[(size_t)rr * v.P] : 0.0;
+      x[u] = *(rr < r1 ? xc + (size_t)rr * v.P : (const double*)kBjZero);
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u], x[u], acc, 0, 0, 0);
@@ -339,8 +343,9 @@ __device__ __forceinline__ void pair_apply(const BjView& v, int ba, int bb, cons
       const double* mat = t < qt ? v.X : v.V;
       const int r0 = t < qt ? t * 16 : (t - qt) * 16, nr = t < qt ? v.q : v.P;
       const int rr = r0 + c16;
+      const bool in = t < ntiles && rr < nr;
 #pragma unroll
-      for (int st = 0; st < 4; ++st) a[u][st] = (t < ntiles && rr < nr) ? mat[(size_t)rr * v.P + colk[st]] : 0.0;
+      for (int st = 0; st < 4; ++st) a[u][st] = *(in ? mat + (size_t)rr * v.P + colk[st] : (const double*)kBjZero);
     }
 #pragma unroll
     for (int u = 0; u < TB; ++u) {
@@ -361,10 +366,6 @@ __device__ __forceinline__ void pair_apply(const BjView& v, int ba, int bb, cons
 }
 
 // Hardware reciprocal and reciprocal square root, each refined by one Newton step.
-__device__ __forceinline__ double rcp_nr(double x) {
-  const double y = __builtin_amdgcn_rcp(x);
-  return __builtin_fma(y, __builtin_fma(-x, y, 1.0), y);
-}
 __device__ __forceinline__ double rsq_nr(double x) {
   const double y = __builtin_amdgcn_rsq(x);
   const double e = __builtin_fma(-x * y, y, 1.0);
@@ -382,9 +383,11 @@ __device__ __forceinline__ bool jacobi_rot(double al, double be, double ga, doub
                                            double& sn) {
   const bool rot = al > floor2 && be > floor2 && ga * ga > (tol * tol) * (al * be);
   const double gs = rot ? ga : 1.0;
-  const double zeta = (be - al) * (0.5 * rcp_nr(gs));
+  // t only steers the angle: the hardware reciprocal and root estimates are
+  // enough there; c gets a refined root, so that c^2 (1 + t^2) = 1 to rounding
+  const double zeta = (be - al) * (0.5 * __builtin_amdgcn_rcp(gs));
   const double z2 = __builtin_fma(zeta, zeta, 1.0);
-  const double t = __builtin_copysign(rcp_nr(fabs(zeta) + z2 * rsq_nr(z2)), zeta);
+  const double t = __builtin_copysign(__builtin_amdgcn_rcp(fabs(zeta) + z2 * __builtin_amdgcn_rsq(z2)), zeta);
   const double cr = rsq_nr(__builtin_fma(t, t, 1.0));
   c = rot ? cr : 1.0;
   sn = rot ? cr * t : 0.0;
@@ -443,9 +446,11 @@ __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int r
     if (anyo) {
       const int kp = lane >> 3, kq = lane & 7;
       const int j0 = 2 * kp, j1 = 2 * kp + 1;
+      // schedule positions of this lane's pairs, advanced step by step
+      // (s16_elem(pos, r + 1) is s16_elem(pos, r) + 1 cycled in 1..15 for pos > 0)
+      int pa = s16_elem(kp, 0), pb = s16_elem(15 - kp, 0), qa = s16_elem(kq, 0), qb = s16_elem(15 - kq, 0);
+      const auto adv = [](int pos, int e) { return pos == 0 ? 0 : (e == 15 ? 1 : e + 1); };
       for (int r = 0; r < 15; ++r) {
-        const int pa = s16_elem(kp, r), pb = s16_elem(15 - kp, r);
-        const int qa = s16_elem(kq, r), qb = s16_elem(15 - kq, r);
         const double (*G)[17] = Gb[cur];
         const double (*J)[17] = Jb[cur];
         const double paa = G[pa][pa], pbb = G[pb][pb], pab = G[pa][pb];
@@ -469,6 +474,10 @@ __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int r
         Jn[j1][qa] = cq * j10 - sq * j11;
         Jn[j1][qb] = sq * j10 + cq * j11;
         cur ^= 1;
+        pa = adv(kp, pa);
+        pb = adv(15 - kp, pb);
+        qa = adv(kq, qa);
+        qb = adv(15 - kq, qb);
         wave_lds_sync();
       }
     }
