@@ -303,8 +303,10 @@ __global__ __launch_bounds__(256) void bj_norm_kernel(int rows, int cols, const 
 static __device__ double kBjZero[2] = {0.0, 0.0};
 
 // Gram of the 16 columns cols(c) = block ba (c < 8) / bb (c >= 8), rows [r0, r1), by one wave;
-// 8 row quads are loaded before their MFMAs.
-__device__ __forceinline__ f64x4 pair_gram(const BjView& v, int ba, int bb, int r0, int r1) {
+// 8 row quads are loaded before their MFMAs.  With a stash, the rows are also
+// kept in LDS (xs[row][c]) for the rotation that follows.
+__device__ __forceinline__ f64x4 pair_gram(const BjView& v, int ba, int bb, int r0, int r1,
+                                           double (*xs)[17] = nullptr) {
   const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
   const int mycol = c16 < 8 ? ba * BJ_B + c16 : bb * BJ_B + c16 - 8;
   const double* xc = v.X + mycol;
@@ -318,6 +320,13 @@ __device__ __forceinline__ f64x4 pair_gram(const BjView& v, int ba, int bb, int 
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u], x[u], acc, 0, 0, 0);
+    if (xs != nullptr) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int rr = r + 4 * u + g;
+        if (rr < r1) xs[rr][c16] = x[u];
+      }
+    }
   }
   return acc;
 }
@@ -394,6 +403,59 @@ __device__ __forceinline__ bool jacobi_rot(double al, double be, double ga, doub
   return rot;
 }
 
+// Rotation of the pair's columns when the X rows sit in the LDS stash (q <=
+// BJ_QS): wave w rotates X tiles w, w + 4, ... from LDS and V tiles w, w + 4,
+// ... from vv, which it loaded before the inner solve.  jb[st] = J[4 st + g][c16].
+constexpr int BJ_QS = 256;
+
+__device__ __forceinline__ void pair_v_load(const BjView& v, int ba, int bb, int wave, double (&vv)[4][4]) {
+  const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
+  const int vt = v.P >> 4;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int t = wave + 4 * u, rr = t * 16 + c16;
+    const bool in = t < vt && rr < v.P;
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int kc = 4 * st + g;
+      const int col = kc < 8 ? ba * BJ_B + kc : bb * BJ_B + kc - 8;
+      vv[u][st] = *(in ? v.V + (size_t)rr * v.P + col : (const double*)kBjZero);
+    }
+  }
+}
+
+__device__ __forceinline__ void pair_apply_stash(const BjView& v, int ba, int bb, const double (&jb)[4], int wave,
+                                                 const double (*xs)[17], const double (&vv)[4][4]) {
+  const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
+  const int qt = (v.q + 15) >> 4, vt = v.P >> 4;
+  const int outcol = c16 < 8 ? ba * BJ_B + c16 : bb * BJ_B + c16 - 8;
+  f64x4 dx[4], dv[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int t = wave + 4 * u, rr = t * 16 + c16;
+    double a[4];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) a[st] = (t < qt && rr < v.q) ? xs[rr][4 * st + g] : 0.0;
+    dx[u] = f64x4{0.0, 0.0, 0.0, 0.0};
+    dv[u] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      dx[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], jb[st], dx[u], 0, 0, 0);
+      dv[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(vv[u][st], jb[st], dv[u], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int t = wave + 4 * u;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = t * 16 + out_row<double>(g, i);
+      if (t < qt && r < v.q) v.X[(size_t)r * v.P + outcol] = dx[u][i];
+      if (t < vt && r < v.P) v.V[(size_t)r * v.P + outcol] = dv[u][i];
+    }
+  }
+}
+
 // One round of the fast phase: one workgroup (4 waves) per pair of blocks.
 // The grid holds BJ_PIN workgroups per pair and only every BJ_PIN-th one works,
 // so that (with workgroups dealt round-robin to the 8 XCDs) all working groups
@@ -410,17 +472,21 @@ __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int r
   __shared__ double gp[4][16][17];
   __shared__ double Gb[2][16][17];
   __shared__ double Jb[2][16][17];
+  __shared__ double xs[BJ_QS][17];
   __shared__ int any_off;
   BjView v = bj_view(ws, rows, cols, blockIdx.y);
   if (v.flags[0]) return;  // converged (uniform over the block)
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, c16 = lane & 15, g = lane >> 4;
   const int pr = blockIdx.x / BJ_PIN;
   const int ba = circle_pos(pr, round, v.nb), bb = circle_pos(v.nb - 1 - pr, round, v.nb);
+  const bool stash = v.q <= BJ_QS;  // uniform
+  double vv[4][4];
   {
     const int r0 = (int)(((int64_t)v.q * wave) / 4), r1 = (int)(((int64_t)v.q * (wave + 1)) / 4);
-    const f64x4 acc = pair_gram(v, ba, bb, r0, r1);
+    const f64x4 acc = pair_gram(v, ba, bb, r0, r1, stash ? xs : nullptr);
 #pragma unroll
     for (int i = 0; i < 4; ++i) gp[wave][out_row<double>(g, i)][c16] = acc[i];
+    if (stash) pair_v_load(v, ba, bb, wave, vv);  // in flight during the inner solve
   }
   __syncthreads();
   const double eps = 2.220446049250313e-16;
@@ -490,7 +556,8 @@ __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int r
   double jb[4];
 #pragma unroll
   for (int st = 0; st < 4; ++st) jb[st] = Jb[ao - 1][4 * st + g][c16];
-  pair_apply<8>(v, ba, bb, jb, wave, 4);
+  if (stash) pair_apply_stash(v, ba, bb, jb, wave, xs, vv);
+  else pair_apply<8>(v, ba, bb, jb, wave, 4);
 }
 
 __global__ void bj_sweep_end_kernel(int rows, int cols, int sweep, double* __restrict__ ws) {
