@@ -345,58 +345,85 @@ __global__ __launch_bounds__(HIST_SB) void label_hist_kernel(int64_t rows, int k
   if (valid) rank_blk[row] = wh[wave][lab] + rin;
 }
 
+// Exclusive scan over the 1024 threads of a block (16 waves): wave scans by
+// shuffles, then the wave totals.
+template <typename T>
+__device__ __forceinline__ T block_excl_scan_1024(T v, T* wtot, T& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const T x = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += x;
+  }
+  if (lane == 63) wtot[wave] = incl;
+  __syncthreads();
+  T base = 0, tot = 0;
+  for (int w = 0; w < 16; ++w) {
+    const T t = wtot[w];
+    base += w < wave ? t : (T)0;
+    tot += t;
+  }
+  __syncthreads();  // wtot may be reused
+  total = tot;
+  return base + incl - v;
+}
+
 // One workgroup.  offs = exclusive scan of hist (label-major); label ranges;
-// chunk table; cluster-size maximum.
+// chunk table; cluster-size maximum.  All scans are block-parallel.
 __global__ __launch_bounds__(1024) void scan_kernel(int k, int64_t nsb, const int32_t* __restrict__ hist,
                                                     int32_t* __restrict__ offs, int32_t* __restrict__ lstart,
                                                     int32_t* __restrict__ chunk_lab, int32_t* __restrict__ chunk_beg,
                                                     int32_t* __restrict__ chunk_end, int32_t* __restrict__ lchunk,
                                                     int32_t* __restrict__ nchunks_out, double* __restrict__ tmax_out) {
-  __shared__ int64_t part[1024];
-  __shared__ int32_t cnt[KM_MAXK + 1];
+  __shared__ int64_t wtot64[16];
+  __shared__ int32_t wtot32[16];
+  __shared__ int32_t lst[KM_MAXK + 1];
   const int tid = threadIdx.x;
   const int64_t L = (int64_t)k * nsb;
   const int64_t per = ceil_div(L, 1024);
   const int64_t b0 = tid * per, b1 = b0 + per < L ? b0 + per : L;
   int64_t s = 0;
   for (int64_t e = b0; e < b1; ++e) s += hist[e];
-  part[tid] = s;
+  int64_t total;
+  int64_t run = block_excl_scan_1024<int64_t>(s, wtot64, total);
+  // the start of label j is the offset of its first block j * nsb
+  int64_t next = ceil_div(b0, nsb) * nsb;
+  for (int64_t e = b0; e < b1; ++e) {
+    const int32_t c = hist[e];
+    offs[e] = (int32_t)run;
+    if (e == next) { lst[e / nsb] = (int32_t)run; next += nsb; }
+    run += c;
+  }
+  if (tid == 0) lst[k] = (int32_t)total;
   __syncthreads();
+  // labels: counts, chunks (exclusive scan of the chunk counts), largest cluster
+  int32_t cnt = 0, nch = 0;
+  if (tid < k) {
+    cnt = lst[tid + 1] - lst[tid];
+    nch = (cnt + CENT_CH - 1) / CENT_CH;
+    lstart[tid] = lst[tid];
+  }
+  int32_t nch_total;
+  const int32_t ch0 = block_excl_scan_1024<int32_t>(nch, wtot32, nch_total);
+  int32_t mx = cnt;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) { const int32_t x = __shfl_xor(mx, o, 64); mx = x > mx ? x : mx; }
+  if ((tid & 63) == 0) wtot32[tid >> 6] = mx;
+  __syncthreads();
+  if (tid < k) lchunk[tid] = ch0;
   if (tid == 0) {
-    int64_t run = 0;
-    for (int t = 0; t < 1024; ++t) { const int64_t c = part[t]; part[t] = run; run += c; }
+    int32_t m = 0;
+    for (int w = 0; w < 16; ++w) m = wtot32[w] > m ? wtot32[w] : m;
+    lchunk[k] = nch_total;
+    *nchunks_out = nch_total;
+    if (tmax_out) *tmax_out = (double)m;
   }
-  __syncthreads();
-  int64_t run = part[tid];
-  for (int64_t e = b0; e < b1; ++e) { const int32_t c = hist[e]; offs[e] = (int32_t)run; run += c; }
-  __syncthreads();
-  // label starts and counts
-  for (int j = tid; j < k; j += 1024) {
-    const int32_t st = offs[(int64_t)j * nsb];
-    lstart[j] = st;
-    int64_t c = 0;
-    for (int64_t b = 0; b < nsb; ++b) c += hist[(int64_t)j * nsb + b];
-    cnt[j] = (int32_t)c;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    int32_t mx = 0, run_ch = 0;
-    for (int j = 0; j < k; ++j) {
-      mx = cnt[j] > mx ? cnt[j] : mx;
-      const int32_t nch = (cnt[j] + CENT_CH - 1) / CENT_CH;
-      lchunk[j] = run_ch;
-      run_ch += nch;
-    }
-    lchunk[k] = run_ch;
-    *nchunks_out = run_ch;
-    if (tmax_out) *tmax_out = (double)mx;
-  }
-  __syncthreads();
-  for (int j = tid; j < k; j += 1024) {
-    const int32_t st = lstart[j], en = st + cnt[j];
-    int32_t c = lchunk[j];
+  if (tid < k) {
+    const int32_t st = lst[tid], en = st + cnt;
+    int32_t c = ch0;
     for (int32_t b = st; b < en; b += CENT_CH, ++c) {
-      chunk_lab[c] = j;
+      chunk_lab[c] = tid;
       chunk_beg[c] = b;
       chunk_end[c] = b + CENT_CH < en ? b + CENT_CH : en;
     }

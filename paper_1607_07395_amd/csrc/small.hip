@@ -80,13 +80,10 @@ constexpr int PC_THREADS = 640;           // 10 waves: >= PC_NT tile owners
 __global__ __launch_bounds__(PC_THREADS) void pchol_kernel(int p, const double* __restrict__ G, int64_t strideG, double tol,
                                                      double* __restrict__ Rf, int64_t strideR) {
   __shared__ double rowk[PC_MAXP];
-  __shared__ double diagv[PC_MAXP];
-  __shared__ int done[PC_MAXP];
-  __shared__ double wbest[16];
-  __shared__ int wbi[16];
-  __shared__ int s_piv;
-  __shared__ double s_d;
+  __shared__ double wbest[2][16];
+  __shared__ int wbi[2][16];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  constexpr int NW = PC_THREADS / 64;
   const double* Gb = G + blockIdx.x * strideG;
   double* Rb = Rf + blockIdx.x * strideR;
   // tile of this thread: row-major over the upper triangle of the tile grid
@@ -100,42 +97,38 @@ __global__ __launch_bounds__(PC_THREADS) void pchol_kernel(int p, const double* 
 #pragma unroll
     for (int b = 0; b < PC_T; ++b)
       val[a][b] = (r0 + a < p && c0 + b < p) ? Gb[(int64_t)(r0 + a) * p + c0 + b] : 0.0;
-  for (int c = tid; c < p; c += PC_THREADS) {
-    done[c] = 0;
-    diagv[c] = Gb[(int64_t)c * p + c];
-  }
-  __syncthreads();
-  int k = 0;
-  for (; k < p; ++k) {
-    // pivot: largest remaining diagonal, lowest index on ties
-    double bd = -1.0;
-    int bi = 0x7fffffff;
-    for (int c = tid; c < p; c += PC_THREADS)
-      if (!done[c] && (diagv[c] > bd || (diagv[c] == bd && c < bi))) { bd = diagv[c]; bi = c; }
+  // index c = tid (p <= PC_MAXP < PC_THREADS): its remaining diagonal and whether it was pivoted
+  const bool mine = tid < p;
+  double diag = mine ? Gb[(int64_t)tid * p + tid] : 0.0;
+  bool done = !mine;
+  // candidate for the next pivot: largest remaining diagonal, lowest index on ties
+  auto propose = [&](int slot) {
+    double bd = done ? -1.0 : diag;
+    int bi = done ? 0x7fffffff : tid;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       const double od = __shfl_xor(bd, off, 64);
       const int oi = __shfl_xor(bi, off, 64);
       if (od > bd || (od == bd && oi < bi)) { bd = od; bi = oi; }
     }
-    if (lane == 0) { wbest[wave] = bd; wbi[wave] = bi; }
-    for (int c = tid; c < PC_MAXP; c += PC_THREADS) rowk[c] = 0.0;
-    __syncthreads();
-    if (tid == 0) {
-      double d = wbest[0];
-      int pi = wbi[0];
-      for (int w = 1; w < PC_THREADS / 64; ++w)
-        if (wbest[w] > d || (wbest[w] == d && wbi[w] < pi)) { d = wbest[w]; pi = wbi[w]; }
-      s_piv = pi;
-      s_d = d;
-    }
-    __syncthreads();
-    const double d = s_d;
-    const int piv = s_piv;
+    if (lane == 0) { wbest[slot][wave] = bd; wbi[slot][wave] = bi; }
+  };
+  propose(0);
+  __syncthreads();
+  int k = 0;
+  for (; k < p; ++k) {
+    const int slot = k & 1;
+    // every thread reduces the wave candidates the same way
+    double d = wbest[slot][0];
+    int piv = wbi[slot][0];
+#pragma unroll
+    for (int w = 1; w < NW; ++w)
+      if (wbest[slot][w] > d || (wbest[slot][w] == d && wbi[slot][w] < piv)) { d = wbest[slot][w]; piv = wbi[slot][w]; }
     if (!(d > tol)) break;  // uniform: nothing left above the threshold
     const double rkk = sqrt(d);
-    // the pivot row of R over the remaining indices: entries (piv, j >= piv) sit in the tile row of
-    // piv, entries (i < piv, piv) in its tile column; r_kk itself at piv
+    // the pivot row of R over all indices, written in full (zero at pivoted
+    // indices): entries (piv, j > piv) sit in the tile row of piv, entries
+    // (i < piv, piv) in its tile column, r_kk itself at piv
     if (piv >= r0 && piv < r0 + PC_T) {
 #pragma unroll
       for (int a = 0; a < PC_T; ++a)
@@ -143,7 +136,7 @@ __global__ __launch_bounds__(PC_THREADS) void pchol_kernel(int p, const double* 
 #pragma unroll
           for (int b = 0; b < PC_T; ++b) {
             const int c = c0 + b;
-            if (c < p && c > piv && !done[c]) rowk[c] = val[a][b] / rkk;
+            if (c < p && c > piv) rowk[c] = val[a][b] / rkk;
           }
         }
     }
@@ -154,14 +147,19 @@ __global__ __launch_bounds__(PC_THREADS) void pchol_kernel(int p, const double* 
 #pragma unroll
           for (int a = 0; a < PC_T; ++a) {
             const int c = r0 + a;
-            if (c < piv && !done[c]) rowk[c] = val[a][b] / rkk;
+            if (c < piv) rowk[c] = val[a][b] / rkk;
           }
         }
     }
-    if (tid == 0) rowk[piv] = rkk;
+    if (tid == piv) rowk[piv] = rkk;
+    if (tid >= p && tid < PC_MAXP) rowk[tid] = 0.0;  // padding read by the edge tiles
     __syncthreads();
-    // Schur complement of the upper triangle (rowk is zero at earlier pivots; the pivot's own row
-    // and column change but are never read again; rowk is zero-padded to PC_MAXP)
+    // entries at pivoted indices are exact zeros of the Schur complement, so
+    // the row may carry the (zero-valued) stored entries there; mask them
+    double rmine = mine && !done ? rowk[tid] : 0.0;
+    if (tid == piv) rmine = rkk;
+    // Schur complement of the upper triangle; the pivot's own row and column
+    // change but are never read again
     double rj[PC_T];
 #pragma unroll
     for (int b = 0; b < PC_T; ++b) rj[b] = c0 + b < PC_MAXP ? rowk[c0 + b] : 0.0;
@@ -171,12 +169,12 @@ __global__ __launch_bounds__(PC_THREADS) void pchol_kernel(int p, const double* 
 #pragma unroll
       for (int b = 0; b < PC_T; ++b) val[a][b] -= ra * rj[b];
     }
-    for (int c = tid; c < p; c += PC_THREADS) {
-      const double v = rowk[c];
-      Rb[(int64_t)k * p + c] = v;
-      diagv[c] -= v * v;
+    if (mine) {
+      Rb[(int64_t)k * p + tid] = rmine;
+      if (!done) diag -= rmine * rmine;
+      if (tid == piv) done = true;
     }
-    if (tid == 0) done[piv] = 1;
+    propose(slot ^ 1);
     __syncthreads();
   }
   for (int e = tid; e < (p - k) * p; e += PC_THREADS) Rb[(int64_t)k * p + e] = 0.0;
