@@ -510,42 +510,44 @@ __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int r
     const bool anyo = __ballot(off) != 0;
     int cur = 0;
     if (anyo) {
+      // G and the columns of J are kept in schedule-position order: step r
+      // stores G[s16_elem(a, r)][s16_elem(b, r)] at [a][b].  The lane's
+      // positions (kp, 15 - kp) x (kq, 15 - kq) are then the same at every
+      // step, and each rotated entry is written where its element sits at the
+      // next step (position p -> p - 1, 1 -> 15, 0 stays).  After the 15 steps
+      // of the sweep every element is back at its own position.
       const int kp = lane >> 3, kq = lane & 7;
+      const int A = kp, B = 15 - kp, C = kq, D = 15 - kq;
       const int j0 = 2 * kp, j1 = 2 * kp + 1;
-      // schedule positions of this lane's pairs, advanced step by step
-      // (s16_elem(pos, r + 1) is s16_elem(pos, r) + 1 cycled in 1..15 for pos > 0)
-      int pa = s16_elem(kp, 0), pb = s16_elem(15 - kp, 0), qa = s16_elem(kq, 0), qb = s16_elem(15 - kq, 0);
-      const auto adv = [](int pos, int e) { return pos == 0 ? 0 : (e == 15 ? 1 : e + 1); };
+      const auto nxt = [](int pos) { return pos == 0 ? 0 : (pos == 1 ? 15 : pos - 1); };
+      const int nA = nxt(A), nB = nxt(B), nC = nxt(C), nD = nxt(D);
+#pragma unroll
       for (int r = 0; r < 15; ++r) {
-        const double (*G)[17] = Gb[cur];
-        const double (*J)[17] = Jb[cur];
-        const double paa = G[pa][pa], pbb = G[pb][pb], pab = G[pa][pb];
-        const double qaa = G[qa][qa], qbb = G[qb][qb], qab = G[qa][qb];
-        const double b00 = G[pa][qa], b01 = G[pa][qb], b10 = G[pb][qa], b11 = G[pb][qb];
-        const double j00 = J[j0][qa], j01 = J[j0][qb], j10 = J[j1][qa], j11 = J[j1][qb];
+        const double (*G)[17] = Gb[r & 1];
+        const double (*J)[17] = Jb[r & 1];
+        const double paa = G[A][A], pbb = G[B][B], pab = G[A][B];
+        const double qaa = G[C][C], qbb = G[D][D], qab = G[C][D];
+        const double b00 = G[A][C], b01 = G[A][D], b10 = G[B][C], b11 = G[B][D];
+        const double j00 = J[j0][C], j01 = J[j0][D], j10 = J[j1][C], j11 = J[j1][D];
         double cp, sp, cq, sq;
         jacobi_rot(paa, pbb, pab, tol, floor2, cp, sp);
         jacobi_rot(qaa, qbb, qab, tol, floor2, cq, sq);
         // columns (right rotation by pair kq), then rows (left rotation by pair kp)
         const double c00 = cq * b00 - sq * b01, c01 = sq * b00 + cq * b01;
         const double c10 = cq * b10 - sq * b11, c11 = sq * b10 + cq * b11;
-        double (*Gn)[17] = Gb[cur ^ 1];
-        double (*Jn)[17] = Jb[cur ^ 1];
-        Gn[pa][qa] = cp * c00 - sp * c10;
-        Gn[pb][qa] = sp * c00 + cp * c10;
-        Gn[pa][qb] = cp * c01 - sp * c11;
-        Gn[pb][qb] = sp * c01 + cp * c11;
-        Jn[j0][qa] = cq * j00 - sq * j01;
-        Jn[j0][qb] = sq * j00 + cq * j01;
-        Jn[j1][qa] = cq * j10 - sq * j11;
-        Jn[j1][qb] = sq * j10 + cq * j11;
-        cur ^= 1;
-        pa = adv(kp, pa);
-        pb = adv(15 - kp, pb);
-        qa = adv(kq, qa);
-        qb = adv(15 - kq, qb);
+        double (*Gn)[17] = Gb[(r & 1) ^ 1];
+        double (*Jn)[17] = Jb[(r & 1) ^ 1];
+        Gn[nA][nC] = cp * c00 - sp * c10;
+        Gn[nB][nC] = sp * c00 + cp * c10;
+        Gn[nA][nD] = cp * c01 - sp * c11;
+        Gn[nB][nD] = sp * c01 + cp * c11;
+        Jn[j0][nC] = cq * j00 - sq * j01;
+        Jn[j0][nD] = sq * j00 + cq * j01;
+        Jn[j1][nC] = cq * j10 - sq * j11;
+        Jn[j1][nD] = sq * j10 + cq * j11;
         wave_lds_sync();
       }
+      cur = 1;  // 15 steps: the result is in buffer 1
     }
     if (lane == 0) any_off = anyo ? cur + 1 : 0;
   }
