@@ -37,7 +37,7 @@ __host__ __device__ static inline int bj_blocks(int p) { int nb = (p + BJ_B - 1)
 __host__ __device__ static inline size_t svd_ws_doubles(int rows, int cols) {
   const size_t p = rows < cols ? rows : cols, q = rows < cols ? cols : rows;
   const size_t P = (size_t)bj_blocks((int)p) * BJ_B;
-  return q * P + P * P + 3 * p + 64;
+  return 2 * q * P + P * P + 3 * p + 64;
 }
 
 size_t svd_ws_bytes(int batch, int rows, int cols) {
@@ -242,7 +242,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 struct BjView {
-  double* X; double* V; double* sig; int* rank; double* sgn; int* flags; double* fro2;
+  double* X; double* X1; double* V; double* sig; int* rank; double* sgn; int* flags; double* fro2;
   int q, p, P, nb;
   bool trans;
 };
@@ -262,6 +262,7 @@ __device__ __forceinline__ BjView bj_view(double* ws, int rows, int cols, int b)
   v.sgn = v.sig + 2 * (size_t)v.p;
   v.flags = (int*)(v.sig + 3 * (size_t)v.p);  // [0] done, [1] sweeps used, [2 + s] sweep s rotated
   v.fro2 = (double*)(v.flags + 64);
+  v.X1 = v.sig + 3 * (size_t)v.p + 64;  // second copy of X (the rounds alternate between the two)
   return v;
 }
 
@@ -331,10 +332,37 @@ __device__ __forceinline__ f64x4 pair_gram(const BjView& v, int ba, int bb, int 
   return acc;
 }
 
+// The same Gram for at most 64 rows [r0, r1): the 16 row quads are loaded by
+// pair_x_load in one batch, then multiplied and kept in the LDS stash.
+__device__ __forceinline__ void pair_x_load(const BjView& v, int ba, int bb, int r0, int r1, double (&x)[16]) {
+  const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
+  const int mycol = c16 < 8 ? ba * BJ_B + c16 : bb * BJ_B + c16 - 8;
+  const double* xc = v.X + mycol;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int rr = r0 + 4 * u + g;
+    x[u] = *(rr < r1 ? xc + (size_t)rr * v.P : (const double*)kBjZero);
+  }
+}
+
+__device__ __forceinline__ f64x4 pair_gram_regs(const double (&x)[16], int r0, int r1, double (*xs)[17]) {
+  const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int u = 0; u < 16; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u], x[u], acc, 0, 0, 0);
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int rr = r0 + 4 * u + g;
+    if (rr < r1) xs[rr][c16] = x[u];
+  }
+  return acc;
+}
+
 // X <- X J, V <- V J on the pair's 16 columns for the 16-row tiles t = t0, t0 + dt, ...,
 // TB tiles' loads in flight at a time.  jb[st] = J[4 st + g][c16].
 template <int TB>
-__device__ __forceinline__ void pair_apply(const BjView& v, int ba, int bb, const double (&jb)[4], int t0, int dt) {
+__device__ __forceinline__ void pair_apply(const BjView& v, double* xo, int ba, int bb, const double (&jb)[4], int t0,
+                                           int dt) {
   const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
   const int qt = (v.q + 15) >> 4, ntiles = qt + (v.P >> 4);
   const int outcol = c16 < 8 ? ba * BJ_B + c16 : bb * BJ_B + c16 - 8;
@@ -360,7 +388,7 @@ __device__ __forceinline__ void pair_apply(const BjView& v, int ba, int bb, cons
     for (int u = 0; u < TB; ++u) {
       const int t = tb + u * dt;
       if (t >= ntiles) break;
-      double* mat = t < qt ? v.X : v.V;
+      double* mat = t < qt ? xo : v.V;
       const int r0 = t < qt ? t * 16 : (t - qt) * 16, nr = t < qt ? v.q : v.P;
       f64x4 d = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -408,12 +436,21 @@ __device__ __forceinline__ bool jacobi_rot(double al, double be, double ga, doub
 // ... from vv, which it loaded before the inner solve.  jb[st] = J[4 st + g][c16].
 constexpr int BJ_QS = 256;
 
-__device__ __forceinline__ void pair_v_load(const BjView& v, int ba, int bb, int wave, double (&vv)[4][4]) {
+// With the stash, the 16-row tiles of X and of V are split between the
+// BJ_SPLIT workgroups of a pair: workgroup s, wave w rotates tiles
+// s + BJ_SPLIT (w + 4 u), u < BJ_NU, of each (q, P <= BJ_QS = 16 tiles).
+constexpr int BJ_SPLIT = 2;
+constexpr int BJ_NU = 4 / BJ_SPLIT;
+
+__device__ __forceinline__ int pair_tile(int s, int wave, int u) { return s + BJ_SPLIT * (wave + 4 * u); }
+
+__device__ __forceinline__ void pair_v_load(const BjView& v, int ba, int bb, int s, int wave,
+                                            double (&vv)[BJ_NU][4]) {
   const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
   const int vt = v.P >> 4;
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int t = wave + 4 * u, rr = t * 16 + c16;
+  for (int u = 0; u < BJ_NU; ++u) {
+    const int t = pair_tile(s, wave, u), rr = t * 16 + c16;
     const bool in = t < vt && rr < v.P;
 #pragma unroll
     for (int st = 0; st < 4; ++st) {
@@ -424,15 +461,16 @@ __device__ __forceinline__ void pair_v_load(const BjView& v, int ba, int bb, int
   }
 }
 
-__device__ __forceinline__ void pair_apply_stash(const BjView& v, int ba, int bb, const double (&jb)[4], int wave,
-                                                 const double (*xs)[17], const double (&vv)[4][4]) {
+__device__ __forceinline__ void pair_apply_stash(const BjView& v, double* xo, int ba, int bb, const double (&jb)[4],
+                                                 int s, int wave, const double (*xs)[17],
+                                                 const double (&vv)[BJ_NU][4]) {
   const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
   const int qt = (v.q + 15) >> 4, vt = v.P >> 4;
   const int outcol = c16 < 8 ? ba * BJ_B + c16 : bb * BJ_B + c16 - 8;
-  f64x4 dx[4], dv[4];
+  f64x4 dx[BJ_NU], dv[BJ_NU];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int t = wave + 4 * u, rr = t * 16 + c16;
+  for (int u = 0; u < BJ_NU; ++u) {
+    const int t = pair_tile(s, wave, u), rr = t * 16 + c16;
     double a[4];
 #pragma unroll
     for (int st = 0; st < 4; ++st) a[st] = (t < qt && rr < v.q) ? xs[rr][4 * st + g] : 0.0;
@@ -445,21 +483,56 @@ __device__ __forceinline__ void pair_apply_stash(const BjView& v, int ba, int bb
     }
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int t = wave + 4 * u;
+  for (int u = 0; u < BJ_NU; ++u) {
+    const int t = pair_tile(s, wave, u);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = t * 16 + out_row<double>(g, i);
-      if (t < qt && r < v.q) v.X[(size_t)r * v.P + outcol] = dx[u][i];
+      if (t < qt && r < v.q) xo[(size_t)r * v.P + outcol] = dx[u][i];
       if (t < vt && r < v.P) v.V[(size_t)r * v.P + outcol] = dv[u][i];
     }
   }
 }
 
-// One round of the fast phase: one workgroup (4 waves) per pair of blocks.
-// The grid holds BJ_PIN workgroups per pair and only every BJ_PIN-th one works,
-// so that (with workgroups dealt round-robin to the 8 XCDs) all working groups
-// of a matrix share one L2 from round to round.  The 16 x 16 Gram is
+// A pair that does not rotate carries its columns of X over to the other copy.
+__device__ __forceinline__ void pair_copy_stash(const BjView& v, double* xo, int ba, int bb, int s, int wave,
+                                                const double (*xs)[17]) {
+  const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
+  const int qt = (v.q + 15) >> 4;
+  const int outcol = c16 < 8 ? ba * BJ_B + c16 : bb * BJ_B + c16 - 8;
+#pragma unroll
+  for (int u = 0; u < BJ_NU; ++u) {
+    const int t = pair_tile(s, wave, u);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = t * 16 + out_row<double>(g, i);
+      if (t < qt && r < v.q) xo[(size_t)r * v.P + outcol] = xs[r][c16];
+    }
+  }
+}
+
+__device__ __forceinline__ void pair_copy(const BjView& v, double* xo, int ba, int bb, int t0, int dt) {
+  const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
+  const int qt = (v.q + 15) >> 4;
+  const int outcol = c16 < 8 ? ba * BJ_B + c16 : bb * BJ_B + c16 - 8;
+  for (int t = t0; t < qt; t += dt) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = t * 16 + out_row<double>(g, i);
+      if (r < v.q) xo[(size_t)r * v.P + outcol] = v.X[(size_t)r * v.P + outcol];
+    }
+  }
+}
+
+// One round of the fast phase: BJ_SPLIT workgroups (4 waves each) per pair of
+// blocks.  Each forms the pair's Gram and J itself (the same code on the same
+// data, so the same J bit for bit) and rotates its share of the row tiles.
+// The grid holds BJ_PIN workgroups per (pair, share) and only every BJ_PIN-th
+// one works, so that (with workgroups dealt round-robin to the 8 XCDs) all
+// working groups of a matrix share one L2 from round to round.  Since a
+// workgroup may rotate its tiles while the other one still reads the pair's
+// columns, round g (counted over the sweeps) reads copy g mod 2 of X and
+// writes copy (g + 1) mod 2, every pair writing all of its columns.  The 16 x 16 Gram is
 // diagonalised by one Jacobi sweep in wave 0: lane (kp, kq) owns the 2 x 2
 // block of G at row pair kp and column pair kq of the current step (and the
 // matching block of J), computes both rotations itself, and writes the
@@ -475,19 +548,33 @@ __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int r
   __shared__ double xs[BJ_QS][17];
   __shared__ int any_off;
   BjView v = bj_view(ws, rows, cols, blockIdx.y);
-  if (v.flags[0]) return;  // converged (uniform over the block)
+  const int gr = sweep * (v.nb - 1) + round;
+  double* const xo = (gr & 1) ? v.X : v.X1;
+  if (gr & 1) v.X = v.X1;  // v.X: the copy this round reads
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, c16 = lane & 15, g = lane >> 4;
-  const int pr = blockIdx.x / BJ_PIN;
+  const int pr = blockIdx.x / (BJ_PIN * BJ_SPLIT), share = (blockIdx.x / BJ_PIN) % BJ_SPLIT;
   const int ba = circle_pos(pr, round, v.nb), bb = circle_pos(v.nb - 1 - pr, round, v.nb);
   const bool stash = v.q <= BJ_QS;  // uniform
-  double vv[4][4];
+  // The converged flag and the column loads are issued together (the loads
+  // are harmless when the matrix has converged), so a round waits for one
+  // memory latency before its Gram instead of two or three.
+  const int done = v.flags[0];
+  double vv[BJ_NU][4];
   {
     const int r0 = (int)(((int64_t)v.q * wave) / 4), r1 = (int)(((int64_t)v.q * (wave + 1)) / 4);
-    const f64x4 acc = pair_gram(v, ba, bb, r0, r1, stash ? xs : nullptr);
+    f64x4 acc;
+    if (stash) {  // r1 - r0 <= BJ_QS / 4 = 64 rows: one batch of loads
+      double x[16];
+      pair_x_load(v, ba, bb, r0, r1, x);
+      pair_v_load(v, ba, bb, share, wave, vv);  // in flight during the inner solve
+      acc = pair_gram_regs(x, r0, r1, xs);
+    } else {
+      acc = pair_gram(v, ba, bb, r0, r1, nullptr);
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) gp[wave][out_row<double>(g, i)][c16] = acc[i];
-    if (stash) pair_v_load(v, ba, bb, wave, vv);  // in flight during the inner solve
   }
+  if (done) return;  // converged (uniform over the grid)
   __syncthreads();
   const double eps = 2.220446049250313e-16;
   const double tol = eps * (v.q > 16 ? (double)v.q : 16.0);
@@ -553,13 +640,17 @@ __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int r
   }
   __syncthreads();
   const int ao = any_off;
-  if (!ao) return;  // uniform
+  if (!ao) {  // uniform
+    if (stash) pair_copy_stash(v, xo, ba, bb, share, wave, xs);
+    else pair_copy(v, xo, ba, bb, share + BJ_SPLIT * wave, 4 * BJ_SPLIT);
+    return;
+  }
   if (tid == 0) v.flags[2 + sweep] = 1;
   double jb[4];
 #pragma unroll
   for (int st = 0; st < 4; ++st) jb[st] = Jb[ao - 1][4 * st + g][c16];
-  if (stash) pair_apply_stash(v, ba, bb, jb, wave, xs, vv);
-  else pair_apply<8>(v, ba, bb, jb, wave, 4);
+  if (stash) pair_apply_stash(v, xo, ba, bb, jb, share, wave, xs, vv);
+  else pair_apply<8>(v, xo, ba, bb, jb, share + BJ_SPLIT * wave, 4 * BJ_SPLIT);
 }
 
 __global__ void bj_sweep_end_kernel(int rows, int cols, int sweep, double* __restrict__ ws) {
@@ -585,6 +676,9 @@ __global__ __launch_bounds__(1024) void bj_finish_kernel(int rows, int cols, int
   const double tol = eps * (v.q > 16 ? (double)v.q : 16.0);
   const double floor2 = eps * eps * v.fro2[0];
   double (*G)[17] = Gs[wave];
+  // the copy of X the fast phase ended on (its sweeps have nb - 1 rounds, an odd number);
+  // the sweeps here work on it in place
+  if (v.flags[1] & 1) v.X = v.X1;
   const bool converged = v.flags[0] != 0;
   for (int sweep = first_sweep; !converged && sweep < BJ_MAX_SWEEPS; ++sweep) {
     if (tid == 0) rotated = 0;
@@ -654,7 +748,7 @@ __global__ __launch_bounds__(1024) void bj_finish_kernel(int rows, int cols, int
         double jb[4];
 #pragma unroll
         for (int st = 0; st < 4; ++st) jb[st] = G[4 * st + g][c16];
-        pair_apply<4>(v, ba, bb, jb, 0, 1);
+        pair_apply<4>(v, v.X, ba, bb, jb, 0, 1);
         wave_lds_sync();
       }
       __syncthreads();
@@ -688,7 +782,8 @@ hipError_t launch_svd(int batch, int rows, int cols, const double* A, int64_t st
   hipLaunchKernelGGL(bj_norm_kernel, dim3(batch), dim3(256), 0, st, rows, cols, A, strideA, w);
   for (int sweep = 0; sweep < BJ_FAST_SWEEPS; ++sweep) {
     for (int round = 0; round < nb - 1; ++round)
-      hipLaunchKernelGGL(bj_round_kernel, dim3(nb / 2 * BJ_PIN, batch), dim3(256), 0, st, rows, cols, round, sweep, w);
+      hipLaunchKernelGGL(bj_round_kernel, dim3(nb / 2 * BJ_SPLIT * BJ_PIN, batch), dim3(256), 0, st, rows, cols, round,
+                         sweep, w);
     hipLaunchKernelGGL(bj_sweep_end_kernel, dim3(batch), dim3(64), 0, st, rows, cols, sweep, w);
   }
   hipLaunchKernelGGL(bj_finish_kernel, dim3(batch), dim3(1024), 0, st, rows, cols, BJ_FAST_SWEEPS, U, strideU, S,
