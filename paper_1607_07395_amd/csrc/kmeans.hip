@@ -376,26 +376,49 @@ __global__ __launch_bounds__(1024) void scan_kernel(int k, int64_t nsb, const in
                                                     int32_t* __restrict__ chunk_lab, int32_t* __restrict__ chunk_beg,
                                                     int32_t* __restrict__ chunk_end, int32_t* __restrict__ lchunk,
                                                     int32_t* __restrict__ nchunks_out, double* __restrict__ tmax_out) {
-  __shared__ int64_t wtot64[16];
   __shared__ int32_t wtot32[16];
   __shared__ int32_t lst[KM_MAXK + 1];
+  __shared__ int32_t lch[KM_MAXK + 1];
   const int tid = threadIdx.x;
   const int64_t L = (int64_t)k * nsb;
-  const int64_t per = ceil_div(L, 1024);
-  const int64_t b0 = tid * per, b1 = b0 + per < L ? b0 + per : L;
-  int64_t s = 0;
-  for (int64_t e = b0; e < b1; ++e) s += hist[e];
-  int64_t total;
-  int64_t run = block_excl_scan_1024<int64_t>(s, wtot64, total);
-  // the start of label j is the offset of its first block j * nsb
-  int64_t next = ceil_div(b0, nsb) * nsb;
-  for (int64_t e = b0; e < b1; ++e) {
-    const int32_t c = hist[e];
-    offs[e] = (int32_t)run;
-    if (e == next) { lst[e / nsb] = (int32_t)run; next += nsb; }
-    run += c;
+  // Tiles of 1024 x SC_R entries: thread t owns entries [t SC_R, (t + 1) SC_R)
+  // of the tile (loaded together), scans them serially, and a block scan of
+  // the thread sums plus the running total of the earlier tiles gives the
+  // offsets.  The start of label j is the offset of its first block, j nsb.
+  constexpr int SC_R = 16;
+  int32_t carry = 0;
+  for (int64_t t0 = 0; t0 < L; t0 += 1024 * SC_R) {
+    const int64_t e0 = t0 + (int64_t)tid * SC_R;
+    int32_t c[SC_R];
+    if (e0 + SC_R <= L) {  // whole run: 16-byte loads (hist is 16-byte aligned, e0 a multiple of SC_R)
+#pragma unroll
+      for (int i = 0; i < SC_R; i += 4) {
+        const int4 q = *(const int4*)(hist + e0 + i);
+        c[i] = q.x; c[i + 1] = q.y; c[i + 2] = q.z; c[i + 3] = q.w;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < SC_R; ++i) c[i] = e0 + i < L ? hist[e0 + i] : 0;
+    }
+    int32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < SC_R; ++i) sum += c[i];
+    int32_t tile_total;
+    int32_t run = block_excl_scan_1024<int32_t>(sum, wtot32, tile_total) + carry;
+    int32_t lab = (int32_t)(e0 / nsb), rem = (int32_t)(e0 - (int64_t)lab * nsb);
+#pragma unroll
+    for (int i = 0; i < SC_R; ++i) {
+      const int64_t e = e0 + i;
+      if (e < L) {
+        offs[e] = run;
+        if (rem == 0) lst[lab] = run;
+      }
+      run += c[i];
+      if (++rem == nsb) { rem = 0; ++lab; }
+    }
+    carry += tile_total;
   }
-  if (tid == 0) lst[k] = (int32_t)total;
+  if (tid == 0) lst[k] = carry;
   __syncthreads();
   // labels: counts, chunks (exclusive scan of the chunk counts), largest cluster
   int32_t cnt = 0, nch = 0;
@@ -411,7 +434,7 @@ __global__ __launch_bounds__(1024) void scan_kernel(int k, int64_t nsb, const in
   for (int o = 32; o >= 1; o >>= 1) { const int32_t x = __shfl_xor(mx, o, 64); mx = x > mx ? x : mx; }
   if ((tid & 63) == 0) wtot32[tid >> 6] = mx;
   __syncthreads();
-  if (tid < k) lchunk[tid] = ch0;
+  if (tid < k) { lchunk[tid] = ch0; lch[tid] = ch0; }
   if (tid == 0) {
     int32_t m = 0;
     for (int w = 0; w < 16; ++w) m = wtot32[w] > m ? wtot32[w] : m;
@@ -419,14 +442,21 @@ __global__ __launch_bounds__(1024) void scan_kernel(int k, int64_t nsb, const in
     *nchunks_out = nch_total;
     if (tmax_out) *tmax_out = (double)m;
   }
-  if (tid < k) {
-    const int32_t st = lst[tid], en = st + cnt;
-    int32_t c = ch0;
-    for (int32_t b = st; b < en; b += CENT_CH, ++c) {
-      chunk_lab[c] = tid;
-      chunk_beg[c] = b;
-      chunk_end[c] = b + CENT_CH < en ? b + CENT_CH : en;
+  if (tid == 0) lch[k] = nch_total;
+  __syncthreads();
+  // chunk table: chunk c belongs to the label j with lch[j] <= c < lch[j + 1]
+  // (labels without rows have lch[j] == lch[j + 1] and never match)
+  for (int32_t c = tid; c < nch_total; c += 1024) {
+    int lo = 0, hi = k;  // lch[lo] <= c < lch[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (lch[mid] <= c) lo = mid;
+      else hi = mid;
     }
+    const int32_t b = lst[lo] + (c - lch[lo]) * CENT_CH, en = lst[lo + 1];
+    chunk_lab[c] = lo;
+    chunk_beg[c] = b;
+    chunk_end[c] = b + CENT_CH < en ? b + CENT_CH : en;
   }
 }
 
