@@ -99,6 +99,18 @@ __device__ __forceinline__ float noise_f32(uint64_t seed, uint64_t i, uint64_t j
 // ---------------------------------------------------------------------------
 // Wave reductions (wave64)
 // ---------------------------------------------------------------------------
+// Exchange between partner lanes within a row of 16 lanes, in four steps
+// that together connect the whole row: pairs, quads, half rows (lane i with
+// 7 - i), rows (lane i with 15 - i).
+__device__ __forceinline__ int dpp_xchg(int v, int ctrl_id) {
+  switch (ctrl_id) {
+    case 0: return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    case 1: return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    case 2: return __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    default: return __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false); // row_mirror
+  }
+}
+
 template <typename T> __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);

@@ -107,17 +107,9 @@ template <typename T> struct Run4<T, false> {
   }
 };
 
-// Sum over the 16 lanes of a row (lanes 16 r .. 16 r + 15) by four DPP
-// exchanges (pairs, quads, half rows, rows).  Every lane of the row ends with
-// the same bits: each step adds the same two values on both partners.
-__device__ __forceinline__ int dpp_xchg(int v, int ctrl_id) {
-  switch (ctrl_id) {
-    case 0: return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
-    case 1: return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
-    case 2: return __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);  // row_half_mirror
-    default: return __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false); // row_mirror
-  }
-}
+// Sum over the 16 lanes of a row (lanes 16 r .. 16 r + 15) by the four DPP
+// exchanges of dpp_xchg.  Every lane of the row ends with the same bits: each
+// step adds the same two values on both partners.
 __device__ __forceinline__ float row16_sum(float v) {
 #pragma unroll
   for (int c = 0; c < 4; ++c) v += __int_as_float(dpp_xchg(__float_as_int(v), c));

@@ -1,6 +1,8 @@
 // Small FP64 products for the k x k algebra of the sketching routine and the
 // orthogonalisation: C = diag(dl) op(A) diag(dm) op(B) diag(dr), one 16 x 16
 // output tile per wave on the FP64 MFMA (v_mfma_f64_16x16x4f64).
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -66,24 +68,27 @@ hipError_t launch_small_gemm(int M, int N, int K, const double* A, int lda, bool
 // rank on are zero.  Step k takes the largest remaining diagonal (lowest index
 // on ties) and stops once it is <= tol (rank = k).
 //
-// The upper triangle of the symmetric matrix stays in registers: the 6 x 6
-// tiles (TR, TC), TR <= TC, of a 34 x 34 tile grid (p <= 204) are numbered row
-// by row and thread t < 595 of the 640 owns tile t.  A step broadcasts the pivot row
-// through LDS; each thread updates its tile by the outer product of 6 + 6
-// entries of that row; the diagonal is kept in LDS.
-constexpr int PC_T = 6;                   // tile edge
-constexpr int PC_G = 34;                  // tiles per dimension
+// The upper triangle of the symmetric matrix stays in registers: the 8 x 8
+// tiles (TR, TC), TR <= TC, of a 26 x 26 tile grid (p <= 208) are numbered row
+// by row and thread t < 351 of the 384 owns tile t.  A step broadcasts the
+// pivot row of R through LDS (written by the owners of the pivot's tile row
+// and tile column, already divided by r_kk); each owner updates its tile by the
+// outer product of 8 + 8 entries of that row.  Thread c < p keeps the
+// remaining diagonal entry c, so only the first PC_CW waves hold pivot
+// candidates.
+constexpr int PC_T = 8;                   // tile edge
+constexpr int PC_G = 26;                  // tiles per dimension
 constexpr int PC_NT = PC_G * (PC_G + 1) / 2;
-constexpr int PC_MAXP = PC_G * PC_T;      // 204
-constexpr int PC_THREADS = 640;           // 10 waves: >= PC_NT tile owners
+constexpr int PC_MAXP = PC_G * PC_T;      // 208
+constexpr int PC_THREADS = 384;           // 6 waves: >= PC_NT tile owners, >= PC_MAXP diagonal keepers
+constexpr int PC_CW = (PC_MAXP + 63) / 64;  // waves with candidates
 
 __global__ __launch_bounds__(PC_THREADS) void pchol_kernel(int p, const double* __restrict__ G, int64_t strideG, double tol,
                                                      double* __restrict__ Rf, int64_t strideR) {
-  __shared__ double rowk[PC_MAXP];
-  __shared__ double wbest[2][16];
-  __shared__ int wbi[2][16];
+  __shared__ double rowk[PC_MAXP];  // row k of R
+  __shared__ double wbest[2][PC_CW];
+  __shared__ int wbi[2][PC_CW];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  constexpr int NW = PC_THREADS / 64;
   const double* Gb = G + blockIdx.x * strideG;
   double* Rb = Rf + blockIdx.x * strideR;
   // tile of this thread: row-major over the upper triangle of the tile grid
@@ -97,84 +102,131 @@ __global__ __launch_bounds__(PC_THREADS) void pchol_kernel(int p, const double* 
 #pragma unroll
     for (int b = 0; b < PC_T; ++b)
       val[a][b] = (r0 + a < p && c0 + b < p) ? Gb[(int64_t)(r0 + a) * p + c0 + b] : 0.0;
-  // index c = tid (p <= PC_MAXP < PC_THREADS): its remaining diagonal and whether it was pivoted
+  // index c = tid (p <= PC_MAXP <= PC_THREADS): its remaining diagonal and whether it was pivoted
   const bool mine = tid < p;
   double diag = mine ? Gb[(int64_t)tid * p + tid] : 0.0;
   bool done = !mine;
-  // candidate for the next pivot: largest remaining diagonal, lowest index on ties
+  // candidate for the next pivot: largest remaining diagonal, lowest index on
+  // ties (a commutative choice, so any reduction order gives the same one):
+  // DPP exchanges within rows of 16 lanes, then across the four rows
+  auto better = [](double od, int oi, double& bd, int& bi) {
+    if (od > bd || (od == bd && oi < bi)) { bd = od; bi = oi; }
+  };
   auto propose = [&](int slot) {
     double bd = done ? -1.0 : diag;
     int bi = done ? 0x7fffffff : tid;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
+    for (int c = 0; c < 4; ++c) {
+      const double od = __hiloint2double(dpp_xchg(__double2hiint(bd), c), dpp_xchg(__double2loint(bd), c));
+      const int oi = dpp_xchg(bi, c);
+      better(od, oi, bd, bi);
+    }
+#pragma unroll
+    for (int off = 16; off < 64; off <<= 1) {
       const double od = __shfl_xor(bd, off, 64);
       const int oi = __shfl_xor(bi, off, 64);
-      if (od > bd || (od == bd && oi < bi)) { bd = od; bi = oi; }
+      better(od, oi, bd, bi);
     }
     if (lane == 0) { wbest[slot][wave] = bd; wbi[slot][wave] = bi; }
   };
-  propose(0);
+  for (int e = tid; e < PC_MAXP; e += PC_THREADS) rowk[e] = 0.0;
+  if (wave < PC_CW) propose(0);  // uniform per wave
   __syncthreads();
   int k = 0;
   for (; k < p; ++k) {
     const int slot = k & 1;
-    // every thread reduces the wave candidates the same way
-    double d = wbest[slot][0];
-    int piv = wbi[slot][0];
+    // every thread reduces the wave candidates the same way (all loaded first;
+    // the empty asm keeps the loads together ahead of their uses)
+    double wd[PC_CW];
+    int wi[PC_CW];
 #pragma unroll
-    for (int w = 1; w < NW; ++w)
-      if (wbest[slot][w] > d || (wbest[slot][w] == d && wbi[slot][w] < piv)) { d = wbest[slot][w]; piv = wbi[slot][w]; }
+    for (int w = 0; w < PC_CW; ++w) {
+      wd[w] = wbest[slot][w];
+      wi[w] = wbi[slot][w];
+    }
+#pragma unroll
+    for (int w = 0; w < PC_CW; ++w) asm volatile("" : "+v"(wd[w]), "+v"(wi[w]));
+    double d = wd[0];
+    int piv = wi[0];
+#pragma unroll
+    for (int w = 1; w < PC_CW; ++w) better(wd[w], wi[w], d, piv);
     if (!(d > tol)) break;  // uniform: nothing left above the threshold
     const double rkk = sqrt(d);
-    // the pivot row of R over all indices, written in full (zero at pivoted
-    // indices): entries (piv, j > piv) sit in the tile row of piv, entries
-    // (i < piv, piv) in its tile column, r_kk itself at piv
-    if (piv >= r0 && piv < r0 + PC_T) {
-#pragma unroll
-      for (int a = 0; a < PC_T; ++a)
-        if (r0 + a == piv) {
-#pragma unroll
-          for (int b = 0; b < PC_T; ++b) {
-            const int c = c0 + b;
-            if (c < p && c > piv) rowk[c] = val[a][b] / rkk;
-          }
-        }
-    }
-    if (piv >= c0 && piv < c0 + PC_T) {
+    const double inv = 1.0 / rkk;
+    // Row k of R over all indices c: (pivot row of the Schur complement)[c] /
+    // r_kk, and r_kk at piv.  Entries (piv, c > piv) sit in the tile row of
+    // piv, entries (c <= piv, piv) in its tile column: the owners there write
+    // those indices of rowk.  The lanes of a wave that take part share one tile row
+    // (one r0) or one tile column (one c0), so the row (column) of the tile is
+    // a wave-uniform index: a scalar switch picks it with constant register
+    // indices.
+    auto emit_row = [&](auto A) {
+      constexpr int a = decltype(A)::value;
 #pragma unroll
       for (int b = 0; b < PC_T; ++b)
-        if (c0 + b == piv) {
+        if (c0 + b > piv) rowk[c0 + b] = val[a][b] * inv;
+    };
+    auto emit_col = [&](auto B) {
+      constexpr int b = decltype(B)::value;
 #pragma unroll
-          for (int a = 0; a < PC_T; ++a) {
-            const int c = r0 + a;
-            if (c < piv) rowk[c] = val[a][b] / rkk;
-          }
-        }
+      for (int a = 0; a < PC_T; ++a)
+        if (r0 + a <= piv) rowk[r0 + a] = r0 + a == piv ? rkk : val[a][b] * inv;
+    };
+    static_assert(PC_T == 8, "the switches below list 8 cases");
+    const int ai = piv - r0, bi = piv - c0;
+    if ((unsigned)ai < (unsigned)PC_T) {
+      switch (__builtin_amdgcn_readfirstlane(ai)) {
+        case 0: emit_row(std::integral_constant<int, 0>{}); break;
+        case 1: emit_row(std::integral_constant<int, 1>{}); break;
+        case 2: emit_row(std::integral_constant<int, 2>{}); break;
+        case 3: emit_row(std::integral_constant<int, 3>{}); break;
+        case 4: emit_row(std::integral_constant<int, 4>{}); break;
+        case 5: emit_row(std::integral_constant<int, 5>{}); break;
+        case 6: emit_row(std::integral_constant<int, 6>{}); break;
+        default: emit_row(std::integral_constant<int, 7>{}); break;
+      }
     }
-    if (tid == piv) rowk[piv] = rkk;
-    if (tid >= p && tid < PC_MAXP) rowk[tid] = 0.0;  // padding read by the edge tiles
+    if ((unsigned)bi < (unsigned)PC_T) {
+      switch (__builtin_amdgcn_readfirstlane(bi)) {
+        case 0: emit_col(std::integral_constant<int, 0>{}); break;
+        case 1: emit_col(std::integral_constant<int, 1>{}); break;
+        case 2: emit_col(std::integral_constant<int, 2>{}); break;
+        case 3: emit_col(std::integral_constant<int, 3>{}); break;
+        case 4: emit_col(std::integral_constant<int, 4>{}); break;
+        case 5: emit_col(std::integral_constant<int, 5>{}); break;
+        case 6: emit_col(std::integral_constant<int, 6>{}); break;
+        default: emit_col(std::integral_constant<int, 7>{}); break;
+      }
+    }
     __syncthreads();
-    // entries at pivoted indices are exact zeros of the Schur complement, so
-    // the row may carry the (zero-valued) stored entries there; mask them
-    double rmine = mine && !done ? rowk[tid] : 0.0;
-    if (tid == piv) rmine = rkk;
-    // Schur complement of the upper triangle; the pivot's own row and column
-    // change but are never read again
-    double rj[PC_T];
+    // Entries of rowk at indices pivoted earlier are zeros of the Schur
+    // complement up to rounding: they only update entries that are never read
+    // again, and R gets exact zeros there.
+    auto rk = [&](int c) { return rowk[c]; };
+    if (owner) {
+      // all loads first (the empty asm keeps the compiler from sinking a load
+      // into a branch of its own), then the outer product
+      double x[2 * PC_T];
 #pragma unroll
-    for (int b = 0; b < PC_T; ++b) rj[b] = c0 + b < PC_MAXP ? rowk[c0 + b] : 0.0;
+      for (int a = 0; a < PC_T; ++a) x[a] = rk(r0 + a);
 #pragma unroll
-    for (int a = 0; a < PC_T; ++a) {
-      const double ra = r0 + a < PC_MAXP ? rowk[r0 + a] : 0.0;
+      for (int b = 0; b < PC_T; ++b) x[PC_T + b] = rk(c0 + b);
 #pragma unroll
-      for (int b = 0; b < PC_T; ++b) val[a][b] -= ra * rj[b];
+      for (int i = 0; i < 2 * PC_T; ++i) asm volatile("" : "+v"(x[i]));
+      // Schur complement of the upper triangle; the pivot's own row and
+      // column change but are never read again
+#pragma unroll
+      for (int a = 0; a < PC_T; ++a)
+#pragma unroll
+        for (int b = 0; b < PC_T; ++b) val[a][b] -= x[a] * x[PC_T + b];
     }
     if (mine) {
+      const double rmine = done ? 0.0 : rk(tid);
       Rb[(int64_t)k * p + tid] = rmine;
       if (!done) diag -= rmine * rmine;
       if (tid == piv) done = true;
     }
-    propose(slot ^ 1);
+    if (wave < PC_CW) propose(slot ^ 1);  // uniform per wave
     __syncthreads();
   }
   for (int e = tid; e < (p - k) * p; e += PC_THREADS) Rb[(int64_t)k * p + e] = 0.0;
