@@ -260,7 +260,7 @@ __device__ __forceinline__ BjView bj_view(double* ws, int rows, int cols, int b)
   v.sig = v.V + (size_t)v.P * v.P;
   v.rank = (int*)(v.sig + v.p);
   v.sgn = v.sig + 2 * (size_t)v.p;
-  v.flags = (int*)(v.sig + 3 * (size_t)v.p);  // [0] done, [1] sweeps used, [2 + s] sweep s rotated
+  v.flags = (int*)(v.sig + 3 * (size_t)v.p);  // [2 + s]: sweep s rotated
   v.fro2 = (double*)(v.flags + 64);
   v.X1 = v.sig + 3 * (size_t)v.p + 64;  // second copy of X (the rounds alternate between the two)
   return v;
@@ -285,18 +285,23 @@ __global__ __launch_bounds__(256) void bj_init_kernel(int rows, int cols, const 
   if (blockIdx.x == 0 && threadIdx.x < 64) v.flags[threadIdx.x] = 0;
 }
 
-// |X|_F^2, invariant under the rotations, for the negligible-column floor.
-__global__ __launch_bounds__(256) void bj_norm_kernel(int rows, int cols, const double* __restrict__ A, int64_t strideA,
-                                                      double* __restrict__ ws) {
-  __shared__ double red[4];
+// |X|_F^2, invariant under the rotations, for the negligible-column floor
+// (fixed summation order: per thread, then per wave, then the waves in order).
+__global__ __launch_bounds__(1024) void bj_norm_kernel(int rows, int cols, const double* __restrict__ A, int64_t strideA,
+                                                       double* __restrict__ ws) {
+  __shared__ double red[16];
   BjView v = bj_view(ws, rows, cols, blockIdx.x);
   const double* Ab = A + blockIdx.x * strideA;
   double s = 0.0;
-  for (int64_t e = threadIdx.x; e < (int64_t)rows * cols; e += 256) s += Ab[e] * Ab[e];
+  for (int64_t e = threadIdx.x; e < (int64_t)rows * cols; e += 1024) s += Ab[e] * Ab[e];
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) v.fro2[0] = ((red[0] + red[1]) + red[2]) + red[3];
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += red[w];
+    v.fro2[0] = t;
+  }
 }
 
 // A zero that out-of-range loads are pointed at (global memory, never written),
@@ -558,7 +563,9 @@ __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int r
   // The converged flag and the column loads are issued together (the loads
   // are harmless when the matrix has converged), so a round waits for one
   // memory latency before its Gram instead of two or three.
-  const int done = v.flags[0];
+  // A sweep without rotations leaves X as it was (copied to the other copy),
+  // so every later sweep would find none either: the matrix has converged.
+  const int done = sweep > 0 && v.flags[2 + sweep - 1] == 0;
   double vv[BJ_NU][4];
   {
     const int r0 = (int)(((int64_t)v.q * wave) / 4), r1 = (int)(((int64_t)v.q * (wave + 1)) / 4);
@@ -653,12 +660,83 @@ __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int r
   else pair_apply<8>(v, xo, ba, bb, jb, share + BJ_SPLIT * wave, 4 * BJ_SPLIT);
 }
 
-__global__ void bj_sweep_end_kernel(int rows, int cols, int sweep, double* __restrict__ ws) {
-  if (threadIdx.x != 0) return;
-  BjView v = bj_view(ws, rows, cols, blockIdx.x);
-  if (v.flags[0]) return;
-  v.flags[1] = sweep + 1;
-  if (v.flags[2 + sweep] == 0) v.flags[0] = 1;
+// The outputs from row-major X (q x P) and V (P x P) by the 1024 threads of
+// one workgroup (the same results as svd_finalize).  Thread t works on column
+// t mod p over the rows of group t / p (up to 4 groups of contiguous rows, so
+// that loads along a row are contiguous across lanes); the groups' partial
+// sums and maxima are combined in group order, which for the maxima (largest
+// magnitude, lowest index on ties) gives the same entry as one scan.
+constexpr int BJF_MAXP = 1024;
+struct BjFinalLds {
+  double part2[BJF_MAXP];   // partial sums of squares
+  double pbest[BJF_MAXP];   // partial largest magnitude
+  double pval[BJF_MAXP];    // ... its value
+  int pidx[BJF_MAXP];       // ... its row
+  double sig[BJF_MAXP];
+  double sgn[BJF_MAXP];
+  int rank[BJF_MAXP];
+};
+
+__device__ void svd_finalize_rm(const BjView& v, BjFinalLds& L, double* Ub, double* Sb, double* Vb) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int p = v.p, q = v.q, P = v.P;
+  const int ng = p >= 1024 ? 1 : (1024 / p < 4 ? 1024 / p : 4);
+  const int j = tid % p, grp = tid / p;
+  if (grp < ng) {
+    double s2 = 0.0;
+    for (int i = (int)((int64_t)q * grp / ng), i1 = (int)((int64_t)q * (grp + 1) / ng); i < i1; ++i) {
+      const double x = v.X[(size_t)i * P + j];
+      s2 += x * x;
+    }
+    // left singular vector of A: X[:, j] / sigma (not transposed) or V[:, j] (transposed)
+    const double* lv = v.trans ? v.V : v.X;
+    const int len = v.trans ? p : q;
+    double best = -1.0, bval = 0.0;
+    int bi = 0x7fffffff;
+    for (int i = (int)((int64_t)len * grp / ng), i1 = (int)((int64_t)len * (grp + 1) / ng); i < i1; ++i) {
+      const double x = lv[(size_t)i * P + j];
+      if (fabs(x) > best) { best = fabs(x); bi = i; bval = x; }
+    }
+    L.part2[tid] = s2;
+    L.pbest[tid] = best;
+    L.pval[tid] = bval;
+    L.pidx[tid] = bi;
+  }
+  __syncthreads();
+  if (tid < p) {
+    double s2 = L.part2[tid], best = L.pbest[tid], bval = L.pval[tid];
+    int bi = L.pidx[tid];
+    for (int gi = 1; gi < ng; ++gi) {
+      const int t = gi * p + tid;
+      s2 += L.part2[t];
+      if (L.pbest[t] > best || (L.pbest[t] == best && L.pidx[t] < bi)) { best = L.pbest[t]; bi = L.pidx[t]; bval = L.pval[t]; }
+    }
+    L.sig[tid] = sqrt(s2);
+    L.sgn[tid] = bval < 0.0 ? -1.0 : 1.0;
+  }
+  __syncthreads();
+  // descending order, lower column index first on ties; NaN ranks below every number
+  if (tid < p) {
+    const double sj = L.sig[tid] == L.sig[tid] ? L.sig[tid] : -1.0;
+    int r = 0;
+    for (int i = 0; i < p; ++i) {
+      const double si = L.sig[i] == L.sig[i] ? L.sig[i] : -1.0;
+      r += (si > sj) || (si == sj && i < tid);
+    }
+    L.rank[tid] = r;
+    Sb[r] = L.sig[tid];
+  }
+  __syncthreads();
+  // left factor of the working problem X / sigma (q x p), right factor V (p x p)
+  double* const xo = v.trans ? Vb : Ub;
+  double* const vo = v.trans ? Ub : Vb;
+  for (int i = wave; i < q; i += 16)
+    for (int c = lane; c < p; c += 64) {
+      const double sc = L.sig[c];
+      xo[(int64_t)i * p + L.rank[c]] = sc > 0.0 ? L.sgn[c] * v.X[(size_t)i * P + c] / sc : 0.0;
+    }
+  for (int i = wave; i < p; i += 16)
+    for (int c = lane; c < p; c += 64) vo[(int64_t)i * p + L.rank[c]] = L.sgn[c] * v.V[(size_t)i * P + c];
 }
 
 // Remaining sweeps (if any) in one workgroup, one wave per pair; then the outputs.
@@ -669,6 +747,7 @@ __global__ __launch_bounds__(1024) void bj_finish_kernel(int rows, int cols, int
   __shared__ double Gs[16][16][17];
   __shared__ double cs[16][8][2];
   __shared__ int rotated;
+  __shared__ BjFinalLds fin;
   const int b = blockIdx.x;
   BjView v = bj_view(ws, rows, cols, b);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, c16 = lane & 15, g = lane >> 4;
@@ -678,8 +757,11 @@ __global__ __launch_bounds__(1024) void bj_finish_kernel(int rows, int cols, int
   double (*G)[17] = Gs[wave];
   // the copy of X the fast phase ended on (its sweeps have nb - 1 rounds, an odd number);
   // the sweeps here work on it in place
-  if (v.flags[1] & 1) v.X = v.X1;
-  const bool converged = v.flags[0] != 0;
+  int used = BJ_FAST_SWEEPS;  // sweeps run by the fast phase: through the first without rotations
+  for (int sw = 0; sw < BJ_FAST_SWEEPS; ++sw)
+    if (v.flags[2 + sw] == 0) { used = sw + 1; break; }
+  if (used & 1) v.X = v.X1;
+  const bool converged = v.flags[2 + used - 1] == 0;
   for (int sweep = first_sweep; !converged && sweep < BJ_MAX_SWEEPS; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
@@ -755,11 +837,10 @@ __global__ __launch_bounds__(1024) void bj_finish_kernel(int rows, int cols, int
     }
     const int done = rotated == 0;
     __syncthreads();
-    if (tid == 0) v.flags[1] = sweep + 1;
     if (done) break;
   }
-  svd_finalize(v.X, v.P, 1, v.V, v.P, 1, v.q, v.p, v.trans, v.sig, v.rank, v.sgn, U + b * strideU, S + b * strideS,
-               Vout + b * strideV);
+  __syncthreads();
+  svd_finalize_rm(v, fin, U + b * strideU, S + b * strideS, Vout + b * strideV);
 }
 
 hipError_t launch_svd(int batch, int rows, int cols, const double* A, int64_t strideA, double* U, int64_t strideU,
@@ -779,12 +860,11 @@ hipError_t launch_svd(int batch, int rows, int cols, const double* A, int64_t st
   const int64_t elems = (int64_t)q * nb * BJ_B + (int64_t)nb * BJ_B * nb * BJ_B;
   hipLaunchKernelGGL(bj_init_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(elems, 256), 1024), batch), dim3(256), 0,
                      st, rows, cols, A, strideA, w);
-  hipLaunchKernelGGL(bj_norm_kernel, dim3(batch), dim3(256), 0, st, rows, cols, A, strideA, w);
+  hipLaunchKernelGGL(bj_norm_kernel, dim3(batch), dim3(1024), 0, st, rows, cols, A, strideA, w);
   for (int sweep = 0; sweep < BJ_FAST_SWEEPS; ++sweep) {
     for (int round = 0; round < nb - 1; ++round)
       hipLaunchKernelGGL(bj_round_kernel, dim3(nb / 2 * BJ_SPLIT * BJ_PIN, batch), dim3(256), 0, st, rows, cols, round,
                          sweep, w);
-    hipLaunchKernelGGL(bj_sweep_end_kernel, dim3(batch), dim3(64), 0, st, rows, cols, sweep, w);
   }
   hipLaunchKernelGGL(bj_finish_kernel, dim3(batch), dim3(1024), 0, st, rows, cols, BJ_FAST_SWEEPS, U, strideU, S,
                      strideS, V, strideV, w);
