@@ -560,12 +560,10 @@ __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int r
   const int pr = blockIdx.x / (BJ_PIN * BJ_SPLIT), share = (blockIdx.x / BJ_PIN) % BJ_SPLIT;
   const int ba = circle_pos(pr, round, v.nb), bb = circle_pos(v.nb - 1 - pr, round, v.nb);
   const bool stash = v.q <= BJ_QS;  // uniform
-  // The converged flag and the column loads are issued together (the loads
-  // are harmless when the matrix has converged), so a round waits for one
-  // memory latency before its Gram instead of two or three.
   // A sweep without rotations leaves X as it was (copied to the other copy),
-  // so every later sweep would find none either: the matrix has converged.
-  const int done = sweep > 0 && v.flags[2 + sweep - 1] == 0;
+  // so every later sweep would find none either: the matrix has converged,
+  // and the rounds still launched return at once.
+  if (sweep > 0 && v.flags[2 + sweep - 1] == 0) return;  // uniform over the grid
   double vv[BJ_NU][4];
   {
     const int r0 = (int)(((int64_t)v.q * wave) / 4), r1 = (int)(((int64_t)v.q * (wave + 1)) / 4);
@@ -581,7 +579,6 @@ __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int r
 #pragma unroll
     for (int i = 0; i < 4; ++i) gp[wave][out_row<double>(g, i)][c16] = acc[i];
   }
-  if (done) return;  // converged (uniform over the grid)
   __syncthreads();
   const double eps = 2.220446049250313e-16;
   const double tol = eps * (v.q > 16 ? (double)v.q : 16.0);
