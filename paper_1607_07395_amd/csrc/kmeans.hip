@@ -619,13 +619,18 @@ __global__ __launch_bounds__(256) void wsum_partial_kernel(int64_t rows, const d
   }
 }
 
+// One wave: lane t sums partials t, t + 64, ... in order, then the lanes are
+// added in the fixed order of wave_sum.
 __global__ void wsum_final_kernel(int nb, const double* __restrict__ part_s, const double* __restrict__ part_g,
                                   double* __restrict__ out_s, double* __restrict__ out_g) {
-  if (threadIdx.x != 0) return;
   double s = 0.0, g = __builtin_huge_val();
-  for (int b = 0; b < nb; ++b) { s += part_s[b]; g = part_g[b] < g ? part_g[b] : g; }
-  if (out_s) *out_s = s;
-  if (out_g) *out_g = g;
+  for (int b = threadIdx.x; b < nb; b += 64) { s += part_s[b]; g = part_g[b] < g ? part_g[b] : g; }
+  s = wave_sum(s);
+  g = wave_min(g);
+  if (threadIdx.x == 0) {
+    if (out_s) *out_s = s;
+    if (out_g) *out_g = g;
+  }
 }
 
 // ---------------------------------------------------------------------------

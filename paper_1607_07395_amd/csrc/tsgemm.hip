@@ -235,19 +235,32 @@ static void tsf_launch_i(int nkb, dim3 grid, hipStream_t st, int64_t M, int K, i
 
 // out[c] = sum over b of part[b * N + c], in a fixed order: 16 interleaved
 // segments per column, then the 16 segment sums in order.
-__global__ __launch_bounds__(256) void colreduce_kernel(int64_t nb, int N, const double* __restrict__ part,
-                                                        double* __restrict__ out) {
-  __shared__ double seg[16][17];
+// Column sums of the row-block partials: 16 columns per block, the 64 row
+// segments of a column summed per thread with four loads in flight (fixed
+// order: per thread in row order, then the segments in order).
+__global__ __launch_bounds__(1024) void colreduce_kernel(int64_t nb, int N, const double* __restrict__ part,
+                                                         double* __restrict__ out) {
+  __shared__ double seg[64][17];
   const int cl = threadIdx.x & 15, s = threadIdx.x >> 4;
   const int col = blockIdx.x * 16 + cl;
   double acc = 0.0;
-  if (col < N)
-    for (int64_t b = s; b < nb; b += 16) acc += part[b * N + col];
+  if (col < N) {
+    int64_t b = s;
+    for (; b + 192 < nb; b += 256) {
+      const double x0 = part[b * N + col], x1 = part[(b + 64) * N + col];
+      const double x2 = part[(b + 128) * N + col], x3 = part[(b + 192) * N + col];
+      acc += x0;
+      acc += x1;
+      acc += x2;
+      acc += x3;
+    }
+    for (; b < nb; b += 64) acc += part[b * N + col];
+  }
   seg[s][cl] = acc;
   __syncthreads();
   if (s == 0 && col < N) {
     double t = 0.0;
-    for (int q = 0; q < 16; ++q) t += seg[q][cl];
+    for (int q = 0; q < 64; ++q) t += seg[q][cl];
     out[col] = t;
   }
 }
@@ -273,7 +286,7 @@ static hipError_t tsgemm_t(int64_t M, int K, int N, const void* X, const double*
     hipLaunchKernelGGL(tsgemm_kernel<TC>, dim3((unsigned)nb), dim3(256), 0, st, M, K, N, (const TC*)X, Bt, (TC*)Y,
                        colsq ? part : nullptr, rowsq);
   }
-  if (colsq) hipLaunchKernelGGL(colreduce_kernel, dim3((unsigned)ceil_div(N, 16)), dim3(256), 0, st, nb, N, part, colsq);
+  if (colsq) hipLaunchKernelGGL(colreduce_kernel, dim3((unsigned)ceil_div(N, 16)), dim3(1024), 0, st, nb, N, part, colsq);
   return hipGetLastError();
 }
 
