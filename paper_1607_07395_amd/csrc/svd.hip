@@ -444,7 +444,7 @@ constexpr int BJ_QS = 256;
 // With the stash, the 16-row tiles of X and of V are split between the
 // BJ_SPLIT workgroups of a pair: workgroup s, wave w rotates tiles
 // s + BJ_SPLIT (w + 4 u), u < BJ_NU, of each (q, P <= BJ_QS = 16 tiles).
-constexpr int BJ_SPLIT = 2;
+constexpr int BJ_SPLIT = 4;
 constexpr int BJ_NU = 4 / BJ_SPLIT;
 
 __device__ __forceinline__ int pair_tile(int s, int wave, int u) { return s + BJ_SPLIT * (wave + 4 * u); }
@@ -532,21 +532,16 @@ __device__ __forceinline__ void pair_copy(const BjView& v, double* xo, int ba, i
 // One round of the fast phase: BJ_SPLIT workgroups (4 waves each) per pair of
 // blocks.  Each forms the pair's Gram and J itself (the same code on the same
 // data, so the same J bit for bit) and rotates its share of the row tiles.
-// The grid holds BJ_PIN workgroups per (pair, share) and only every BJ_PIN-th
-// one works, so that (with workgroups dealt round-robin to the 8 XCDs) all
-// working groups of a matrix share one L2 from round to round.  Since a
-// workgroup may rotate its tiles while the other one still reads the pair's
-// columns, round g (counted over the sweeps) reads copy g mod 2 of X and
-// writes copy (g + 1) mod 2, every pair writing all of its columns.  The 16 x 16 Gram is
-// diagonalised by one Jacobi sweep in wave 0: lane (kp, kq) owns the 2 x 2
-// block of G at row pair kp and column pair kq of the current step (and the
-// matching block of J), computes both rotations itself, and writes the
-// rotated block to the other half of a double buffer.
-constexpr int BJ_PIN = 8;
+// Since a workgroup may rotate its tiles while another one still reads the
+// pair's columns, round g (counted over the sweeps) reads copy g mod 2 of X
+// and writes copy (g + 1) mod 2, every pair writing all of its columns.  The
+// 16 x 16 Gram is diagonalised by one Jacobi sweep in wave 0: lane (kp, kq)
+// owns the 2 x 2 block of G at row pair kp and column pair kq of the current
+// step (and the matching block of J), computes both rotations itself, and
+// writes the rotated block to the other half of a double buffer.
 
 __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int round, int sweep,
                                                        double* __restrict__ ws) {
-  if ((blockIdx.x % BJ_PIN) != (blockIdx.y % BJ_PIN)) return;
   __shared__ double gp[4][16][17];
   __shared__ double Gb[2][16][17];
   __shared__ double Jb[2][16][17];
@@ -557,7 +552,7 @@ __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int r
   double* const xo = (gr & 1) ? v.X : v.X1;
   if (gr & 1) v.X = v.X1;  // v.X: the copy this round reads
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, c16 = lane & 15, g = lane >> 4;
-  const int pr = blockIdx.x / (BJ_PIN * BJ_SPLIT), share = (blockIdx.x / BJ_PIN) % BJ_SPLIT;
+  const int pr = blockIdx.x / BJ_SPLIT, share = blockIdx.x % BJ_SPLIT;
   const int ba = circle_pos(pr, round, v.nb), bb = circle_pos(v.nb - 1 - pr, round, v.nb);
   const bool stash = v.q <= BJ_QS;  // uniform
   // A sweep without rotations leaves X as it was (copied to the other copy),
@@ -860,8 +855,8 @@ hipError_t launch_svd(int batch, int rows, int cols, const double* A, int64_t st
   hipLaunchKernelGGL(bj_norm_kernel, dim3(batch), dim3(1024), 0, st, rows, cols, A, strideA, w);
   for (int sweep = 0; sweep < BJ_FAST_SWEEPS; ++sweep) {
     for (int round = 0; round < nb - 1; ++round)
-      hipLaunchKernelGGL(bj_round_kernel, dim3(nb / 2 * BJ_SPLIT * BJ_PIN, batch), dim3(256), 0, st, rows, cols, round,
-                         sweep, w);
+      hipLaunchKernelGGL(bj_round_kernel, dim3(nb / 2 * BJ_SPLIT, batch), dim3(256), 0, st, rows, cols, round, sweep,
+                         w);
   }
   hipLaunchKernelGGL(bj_finish_kernel, dim3(batch), dim3(1024), 0, st, rows, cols, BJ_FAST_SWEEPS, U, strideU, S,
                      strideS, V, strideV, w);
