@@ -167,10 +167,10 @@ __global__ __launch_bounds__(256) void assign_kernel(int64_t rows, int dim, int 
 // the k blocks, MFMA steps and columns come in the same order as in
 // assign_kernel, so distances, labels and gaps are bit-identical to it.
 constexpr int AF_KMAX = 256;
-constexpr int AF_CT = 4;
+constexpr int AF_CT = 2;
 
 template <typename TC, int NKB>
-__global__ __launch_bounds__(256, 2) void assign_fast_kernel(int64_t rows, int dim, int k, const TC* __restrict__ P,
+__global__ __launch_bounds__(256, 3) void assign_fast_kernel(int64_t rows, int dim, int k, const TC* __restrict__ P,
                                                              const TC* __restrict__ Zc,
                                                              const double* __restrict__ znorm,
                                                              const double* __restrict__ pnorm,
@@ -232,11 +232,14 @@ __global__ __launch_bounds__(256, 2) void assign_fast_kernel(int64_t rows, int d
       }
     };
     const int ntile = (k - cc + 15) / 16;
+    static_assert(AF_CT == 2 || AF_CT == 4, "the partial chunks below cover AF_CT = 2 or 4");
     if (ntile >= AF_CT) mm(std::integral_constant<int, AF_CT>{});
     else if constexpr (AF_CT == 4) {
       if (ntile == 1) mm(std::integral_constant<int, 1>{});
       else if (ntile == 2) mm(std::integral_constant<int, 2>{});
       else mm(std::integral_constant<int, 3>{});
+    } else {
+      mm(std::integral_constant<int, 1>{});
     }
 #pragma unroll
     for (int t = 0; t < AF_CT; ++t) {
