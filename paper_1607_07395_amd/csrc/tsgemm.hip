@@ -95,7 +95,7 @@ __global__ __launch_bounds__(256) void tsgemm_kernel(int64_t M, int K, int N, co
 // chunk is loaded into registers while the current one is multiplied.  Same
 // outputs as tsgemm_kernel (Y, FP64 row and per-block column sums of squares).
 constexpr int TSF_KMAX = 256;
-template <typename TC> struct TsfCT { static constexpr int v = 4; };
+template <typename TC> struct TsfCT { static constexpr int v = 2; };
 template <> struct TsfCT<double> { static constexpr int v = 1; };
 
 template <typename TC>
@@ -103,7 +103,7 @@ static size_t tsf_lds_bytes(int nkb, int N) {
   return (size_t)TsfCT<TC>::v * nkb * 64 * 16 + (size_t)4 * N * sizeof(double);
 }
 
-template <typename TC> struct TsfOcc { static constexpr int v = 2; };
+template <typename TC> struct TsfOcc { static constexpr int v = 3; };
 template <> struct TsfOcc<double> { static constexpr int v = 1; };  // FP64 rows of K <= 256 fill 128 registers
 
 // NKB (k blocks of 4 runs) is a compile-time constant, so the loads, the LDS
@@ -172,11 +172,14 @@ __global__ __launch_bounds__(256, TsfOcc<TC>::v) void tsgemm_fast_kernel(int64_t
       }
     };
     const int ntile = (N - cc + 15) / 16;
+    static_assert(CT == 1 || CT == 2 || CT == 4, "the partial chunks below cover CT = 1, 2 or 4");
     if (ntile >= CT) mm(std::integral_constant<int, CT>{});
     else if constexpr (CT == 4) {
       if (ntile == 1) mm(std::integral_constant<int, 1>{});
       else if (ntile == 2) mm(std::integral_constant<int, 2>{});
       else mm(std::integral_constant<int, 3>{});
+    } else if constexpr (CT == 2) {
+      mm(std::integral_constant<int, 1>{});
     }
 #pragma unroll
     for (int t = 0; t < CT; ++t) {
