@@ -99,6 +99,14 @@ __device__ __forceinline__ float noise_f32(uint64_t seed, uint64_t i, uint64_t j
 // ---------------------------------------------------------------------------
 // Wave reductions (wave64)
 // ---------------------------------------------------------------------------
+// Order between the LDS accesses of the lanes of one wave (a wavefront-scope
+// fence around a wave barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Exchange between partner lanes within a row of 16 lanes, in four steps
 // that together connect the whole row: pairs, quads, half rows (lane i with
 // 7 - i), rows (lane i with 15 - i).

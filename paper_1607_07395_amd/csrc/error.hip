@@ -24,13 +24,6 @@ namespace cabs {
 constexpr int ERR_NB = 1024;
 constexpr int ERR_NT = 8;
 
-// LDS writes of a wave visible to its other lanes (a wave-level fence).
-__device__ __forceinline__ void wave_lds_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 static inline size_t al256e(size_t b) { return (b + 255) & ~(size_t)255; }
 
 template <typename TIn>
@@ -245,7 +238,7 @@ __device__ __forceinline__ void err_batch(const MatView& mv, int kr, const doubl
   double nz = 0.0;
   if (SRC == SRC_LOWRANK && valid && mv.noise_std != 0.0) nz = noise_f64(mv.noise_seed, (uint64_t)i, (uint64_t)j);
   rec[threadIdx.x] = ErrRec{i, j};
-  wave_lds_fence();
+  wave_lds_sync();
   double my_ap = 0.0;
   SV my_s = (SV)0;
   for (int q = 0; q < 16; ++q) {
@@ -257,7 +250,7 @@ __device__ __forceinline__ void err_batch(const MatView& mv, int kr, const doubl
     sv = row16_sum(sv);
     if (l16 == q) { my_ap = ap; my_s = sv; }
   }
-  wave_lds_fence();  // the next batch rewrites rec
+  wave_lds_sync();  // the next batch rewrites rec
   if (valid) {
     double a = (double)my_s;
     if (SRC == SRC_LOWRANK) a += mv.noise_std * nz;
@@ -336,7 +329,6 @@ static inline bool eb_use(int64_t m, int64_t n, int64_t ns) {
   const int64_t lim = (int64_t)1 << 31;
   return ns >= m && ns < lim && m < lim && n < lim;
 }
-
 
 __global__ __launch_bounds__(256) void eb_count_kernel(int64_t m, int64_t n, int64_t ns, uint64_t seed, EbPlan pl,
                                                        int2* __restrict__ ij, int32_t* __restrict__ counts) {
@@ -530,7 +522,7 @@ __global__ __launch_bounds__(256) void eb_eval_rows_kernel(MatView mv, int kr, c
   for (int c0 = s0; c0 < s1; c0 += ER_CH) {
     const int n = s1 - c0 < ER_CH ? s1 - c0 : ER_CH;
     for (int e = lane; e < ER_RB; e += 64) wrun[wave][e] = 0;
-    wave_lds_fence();
+    wave_lds_sync();
     // pass A: wave w takes records w * (ER_CH / 4) + 64 k + lane; rank within
     // equal layout keys (row % 16, row / 16); (key, rank, column) to LDS
 #pragma unroll 1
@@ -551,10 +543,10 @@ __global__ __launch_bounds__(256) void eb_eval_rows_kernel(MatView mv, int kr, c
       const bool last = ((same >> lane) >> 1) == 0;
       const int ls = valid ? lk : 0;
       const int posl = wrun[wave][ls] + rank;
-      wave_lds_fence();
+      wave_lds_sync();
       if (valid && last) wrun[wave][ls] += rank + 1;
       tmp[idx] = make_int2(valid ? (lk << 16) | posl : -1, e.y);
-      wave_lds_fence();
+      wave_lds_sync();
     }
     __syncthreads();
     // layout: key lk's segment starts after all smaller keys; within a key, waves in order
@@ -574,7 +566,7 @@ __global__ __launch_bounds__(256) void eb_eval_rows_kernel(MatView mv, int kr, c
         if (lane >= o) incl += x;
       }
       const int ex = incl - a0 - a1;
-      wave_lds_fence();
+      wave_lds_sync();
       int run0 = ex, run1 = ex + a0;
 #pragma unroll
       for (int w = 0; w < 4; ++w) {

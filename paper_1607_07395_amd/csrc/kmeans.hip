@@ -662,13 +662,16 @@ __device__ __forceinline__ void topt_insert(AT (&d)[SNAP_T], int (&r)[SNAP_T], A
 }
 
 // Per block of rows_per_block consecutive rows and per centre: the SNAP_T
-// nearest rows, sorted by (distance, row).  Sub-tiles of 64 rows x 64 centres
-// go through LDS; each wave keeps lists over its own 16 rows of every sub-tile
-// (lane = centre) and the four lists are merged at the end of a centre chunk.
-// A list holding fewer than SNAP_T rows means every other row of the block is
-// at +inf.  Each 16-centre column tile of gemm_tile is an independent MFMA
-// chain, so snap_resolve_kernel recomputes these distances bit-exactly from a
-// one-tile call at the same row and column offsets.
+// nearest rows, sorted by (distance, row).  Wave w takes the 64-centre chunks
+// w, w + 4, ... (lane = centre) and walks the block's rows in 16-row tiles:
+// it forms the tile's distances (gemm_tile over the chunk's 4 column tiles)
+// into its own LDS tile, then each lane inserts its centre's 16 distances in
+// row order.  One list per (block, centre), so each list fills once; no
+// barrier across waves.  A list holding fewer than SNAP_T rows means every
+// other row of the block is at +inf.  Each 16-centre column tile of gemm_tile
+// is an independent MFMA chain and every row tile starts 16-aligned from the
+// block start, so snap_resolve_kernel recomputes these distances bit-exactly
+// from a one-tile call at the same row and column offsets.
 template <typename TC>
 __global__ __launch_bounds__(256) void snap_topt_kernel(int64_t rows, int dim, int k, int64_t rows_per_block,
                                                         const TC* __restrict__ P, const TC* __restrict__ Zc,
@@ -678,77 +681,54 @@ __global__ __launch_bounds__(256) void snap_topt_kernel(int64_t rows, int dim, i
   typedef typename Mfma<TC>::acc AccV;
   typedef typename NormT<TC>::type NrmT;
   constexpr int LDD = SNAP_CC + 1;
-  __shared__ double sm_d[SNAP_SUB * LDD];          // distance sub-tile; then per-wave list distances
-  __shared__ int32_t sm_r[4 * SNAP_T * SNAP_CC];   // per-wave list rows
-  static_assert(4 * SNAP_T * SNAP_CC <= SNAP_SUB * LDD, "list staging must fit the distance tile");
+  __shared__ double sm_d[4][16 * LDD];  // per wave: 16 rows x 64 centres
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, c16 = lane & 15;
   const int64_t rbeg = (int64_t)blockIdx.x * rows_per_block;
   const int64_t rend = rbeg + rows_per_block < rows ? rbeg + rows_per_block : rows;
   const int nblk = gridDim.x;
-  for (int cc = 0; cc < k; cc += SNAP_CC) {
+  double* sd = sm_d[wave];
+  for (int cw = wave * SNAP_CC; cw < k; cw += 4 * SNAP_CC) {
     double td[SNAP_T];
     int tr[SNAP_T];
 #pragma unroll
     for (int q = 0; q < SNAP_T; ++q) { td[q] = __builtin_huge_val(); tr[q] = 0x7fffffff; }
-    const int myc = cc + lane;  // centre tracked by this lane
-    for (int64_t s0 = rbeg; s0 < rend; s0 += SNAP_SUB) {
-      const int64_t row0 = s0 + wave * 16;
+    const int myc = cw + lane;  // centre tracked by this lane
+    for (int64_t row0 = rbeg; row0 < rend; row0 += 16) {
       AccV acc[SNAP_NT];
       NrmT xs, ys[SNAP_NT];
-      if (row0 < rend)
-        gemm_tile<TC, TC, SNAP_NT, false>(P, dim, rend, row0, Zc, dim, nullptr, k, cc, nullptr, dim, acc, xs, ys);
+      gemm_tile<TC, TC, SNAP_NT, false>(P, dim, rend, row0, Zc, dim, nullptr, k, cw, nullptr, dim, acc, xs, ys);
 #pragma unroll
       for (int t = 0; t < SNAP_NT; ++t) {
         const int cl = t * 16 + c16;
-        const int col = cc + cl;
+        const int col = cw + cl;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int rl = wave * 16 + out_row<TC>(g, i);
-          const int64_t row = s0 + rl;
+          const int rl = out_row<TC>(g, i);
+          const int64_t row = row0 + rl;
           double d = __builtin_huge_val();
-          if (row0 < rend && row < rend && col < k) d = snap_dist(pnorm[row], znorm[col], (double)acc[t][i]);
-          sm_d[rl * LDD + cl] = d;
+          if (row < rend && col < k) d = snap_dist(pnorm[row], znorm[col], (double)acc[t][i]);
+          sd[rl * LDD + cl] = d;
         }
       }
-      __syncthreads();
+      wave_lds_sync();
       if (myc < k) {
         for (int q = 0; q < 16; ++q) {
-          const int rl = wave * 16 + q;
-          const int64_t row = s0 + rl;
+          const int64_t row = row0 + q;
           if (row >= rend) break;
-          topt_insert<double>(td, tr, sm_d[rl * LDD + lane], (int)row);
+          topt_insert<double>(td, tr, sd[q * LDD + lane], (int)row);
         }
       }
-      __syncthreads();
+      wave_lds_sync();  // the tile is rewritten next
     }
-    // merge the four per-wave lists of each centre
-#pragma unroll
-    for (int q = 0; q < SNAP_T; ++q) {
-      sm_d[(wave * SNAP_T + q) * SNAP_CC + lane] = td[q];
-      sm_r[(wave * SNAP_T + q) * SNAP_CC + lane] = tr[q];
-    }
-    __syncthreads();
-    if (wave == 0 && myc < k) {
-      int p0 = 0, p1 = 0, p2 = 0, p3 = 0;
+    if (myc < k) {
       const int64_t base = ((int64_t)myc * nblk + blockIdx.x) * SNAP_T;
+#pragma unroll
       for (int q = 0; q < SNAP_T; ++q) {
-        double bd = __builtin_huge_val();
-        int br = 0x7fffffff, bw = -1;
-#define TOPT_HEAD(W, PW)                                                              \
-  if (PW < SNAP_T) {                                                                  \
-    const double hd = sm_d[((W) * SNAP_T + PW) * SNAP_CC + lane];                     \
-    const int hr = sm_r[((W) * SNAP_T + PW) * SNAP_CC + lane];                        \
-    if (hr != 0x7fffffff && (bw < 0 || hd < bd || (hd == bd && hr < br))) { bd = hd; br = hr; bw = W; } \
-  }
-        TOPT_HEAD(0, p0) TOPT_HEAD(1, p1) TOPT_HEAD(2, p2) TOPT_HEAD(3, p3)
-#undef TOPT_HEAD
-        p0 += bw == 0; p1 += bw == 1; p2 += bw == 2; p3 += bw == 3;
-        cand_d[base + q] = bw < 0 ? __builtin_huge_val() : bd;
-        cand_r[base + q] = bw < 0 ? 0x7fffffff : br;
+        cand_d[base + q] = td[q];
+        cand_r[base + q] = tr[q];
       }
     }
-    __syncthreads();
   }
 }
 

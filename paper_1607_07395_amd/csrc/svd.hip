@@ -234,13 +234,6 @@ __device__ __forceinline__ int circle_pos(int pos, int round, int n) {
 __device__ __forceinline__ int s16_elem(int pos, int r) { return pos == 0 ? 0 : 1 + (pos - 1 + r) % 15; }
 __device__ __forceinline__ int s16_pos(int c, int r) { return c == 0 ? 0 : 1 + (c + 14 - r) % 15; }
 
-// LDS ordering between the lanes of one wave.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 struct BjView {
   double* X; double* X1; double* V; double* sig; int* rank; double* sgn; int* flags; double* fro2;
   int q, p, P, nb;
