@@ -876,33 +876,41 @@ __global__ __launch_bounds__(1024) void snap_resolve_kernel(
     if (wave == 0) {
       int jj = j;
       const int lim = (chunk0 + RES_CHUNK < k ? chunk0 + RES_CHUNK : k);
+      // One centre at a time, its list's SNAP_T candidates checked at once
+      // (lane q holds candidate q), with the decisions of a walk down the
+      // list: skip taken rows; the first untaken one fixes the tie window
+      // [d, d + tol]; the walk stops at the first later candidate outside it
+      // or at the list's end; the choice is the lowest untaken row walked
+      // over.  Undecided: nothing untaken, or a full list walked to its end
+      // inside the window (then unlisted rows may tie).
       for (; jj < lim; ++jj) {
         const double zn = lz[jj - chunk0];
-        int32_t found = SENT;
-        double dmin = INF, tol = 0.0, last_d = INF;
-        int q = 0;
-        for (; q < SNAP_T; ++q) {
-          const int32_t r = lr[(jj - chunk0) * SNAP_T + q];
-          const double d = ld[(jj - chunk0) * SNAP_T + q];
-          if (r == SENT) break;
-          if (found != SENT && d > dmin + tol) break;
-          last_d = d;
-          if (res_has(ht, r)) continue;
-          if (found == SENT) {
-            dmin = d;
-            const double rr = zn + sqrt(d);
-            tol = tie_rtol * rr * rr;
-            found = r;
-          } else if (r < found) {
-            found = r;
-          }
+        const int q = lane;
+        int32_t r = SENT;
+        double d = INF;
+        if (q < SNAP_T) {
+          r = lr[(jj - chunk0) * SNAP_T + q];
+          d = ld[(jj - chunk0) * SNAP_T + q];
         }
-        // undecided: nothing untaken in the list, or a full list whose end is
-        // still inside the window (then unlisted rows may tie)
-        const bool undecided = found == SENT || (q == SNAP_T && last_d <= dmin + tol);
-        if (undecided) break;
-        chosen[jj] = found;  // every lane writes the same value
-        res_put(ht, found);
+        const bool valid = r != SENT;  // lists hold their entries first, then SENT
+        const bool free_row = valid && !res_has(ht, r);
+        const uint64_t m_end = __ballot(q < SNAP_T && !valid);
+        const int q_end = m_end ? __builtin_ctzll(m_end) : SNAP_T;
+        const uint64_t m_free = __ballot(free_row && q < q_end);
+        if (m_free == 0) break;  // undecided
+        const int q0 = __builtin_ctzll(m_free);
+        const double dmin = __shfl(d, q0, 64);
+        const double rr = zn + sqrt(dmin);
+        const double tol = tie_rtol * rr * rr;
+        const uint64_t m_out = __ballot(q > q0 && q < q_end && d > dmin + tol);
+        const int q_stop = m_out ? __builtin_ctzll(m_out) : q_end;
+        if (q_stop == SNAP_T) break;  // undecided: a full list ends inside the window
+        const int32_t found = wave_min<int32_t>(free_row && q >= q0 && q < q_stop ? r : SENT);
+        if (lane == 0) {
+          chosen[jj] = found;
+          res_put(ht, found);
+        }
+        wave_lds_sync();  // the next centre's lookups see the new row
       }
       if (lane == 0) sh_next = jj;
     }
@@ -1061,6 +1069,7 @@ struct KmWs {
 // SNAP_MAXBLK, and at most SNAP_MAXCAND / k so the candidate lists stay bounded.
 static inline int snap_nblk(int64_t rows, int k) {
   int64_t nb = ceil_div(rows, SNAP_ROWS);
+  if (nb < 256) nb = ceil_div(rows, SNAP_SUB);  // few rows: 64-row blocks, so that more work-groups run
   const int64_t cap = std::min<int64_t>(SNAP_MAXBLK, std::max<int64_t>(1, SNAP_MAXCAND / k));
   if (nb > cap) nb = cap;
   return (int)(nb < 1 ? 1 : nb);
