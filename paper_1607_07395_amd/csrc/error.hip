@@ -389,7 +389,8 @@ __global__ __launch_bounds__(1024) void eb_scan_kernel(EbPlan pl, const int32_t*
   if (tid == 1023) starts[pl.nbk] = part[1023];
 }
 
-// Per bucket (one wave each): offsets of each chunk's run inside the bucket.
+// Per bucket (one wave each): offsets of each chunk's run inside the bucket,
+// stored chunk-major (offs[g * nbk + b]) so that a chunk reads its own row.
 __global__ __launch_bounds__(256) void eb_offsets_kernel(EbPlan pl, const int32_t* __restrict__ counts,
                                                          const int32_t* __restrict__ starts,
                                                          int32_t* __restrict__ offs) {
@@ -407,21 +408,24 @@ __global__ __launch_bounds__(256) void eb_offsets_kernel(EbPlan pl, const int32_
     if (lane >= off) incl += x;
   }
   int run = starts[b] + incl - sum;
-  int32_t* o = offs + (int64_t)b * EB_G + lane * PER;
 #pragma unroll
-  for (int q = 0; q < PER; ++q) { o[q] = run; run += v[q]; }
+  for (int q = 0; q < PER; ++q) {
+    offs[(int64_t)(lane * PER + q) * pl.nbk + b] = run;
+    run += v[q];
+  }
 }
 
-// Chunk g places its samples' (i, j), in increasing t within each bucket.  A
-// round is 256 consecutive samples, 64 per wave; ranks among equal buckets
-// inside a wave come from shuffles, and the four waves place their samples in
-// wave order, each advancing the per-bucket run counters in LDS.
+// Chunk g places its samples' (i, j), in increasing t within each bucket.  The
+// per-bucket write positions start at the chunk's offsets (read once, as one
+// row) and advance in LDS.  A round is 256 consecutive samples, 64 per wave;
+// ranks among equal buckets inside a wave come from ballots, and the four waves
+// place their samples in wave order.
 __global__ __launch_bounds__(256) void eb_scatter_kernel(int64_t ns, EbPlan pl, const int2* __restrict__ ij,
                                                          const int32_t* __restrict__ offs,
                                                          int2* __restrict__ sorted) {
   __shared__ int32_t run[EB_MAXB];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  for (int b = tid; b < pl.nbk; b += 256) run[b] = 0;
+  for (int b = tid; b < pl.nbk; b += 256) run[b] = offs[(int64_t)blockIdx.x * pl.nbk + b];
   const int64_t t0 = (int64_t)blockIdx.x * pl.tchunk;
   const int64_t t1 = t0 + pl.tchunk < ns ? t0 + pl.tchunk : ns;
   for (int64_t base = t0; base < t1; base += 256) {
@@ -443,7 +447,7 @@ __global__ __launch_bounds__(256) void eb_scatter_kernel(int64_t ns, EbPlan pl, 
     for (int w = 0; w < 4; ++w) {
       __syncthreads();
       if (wave == w && valid) {
-        sorted[offs[(int64_t)b * EB_G + blockIdx.x] + run[b] + rank] = e;
+        sorted[run[b] + rank] = e;
         if (last) run[b] += rank + 1;
       }
     }
