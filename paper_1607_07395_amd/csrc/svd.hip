@@ -13,6 +13,8 @@
 // vector is positive (first such entry on ties).
 #include <algorithm>
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "timing.hpp"
@@ -571,12 +573,25 @@ __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int r
   const double eps = 2.220446049250313e-16;
   const double tol = eps * (v.q > 16 ? (double)v.q : 16.0);
   const double floor2 = eps * eps * v.fro2[0];
+  // Round 0 of a sweep runs a full cyclic Jacobi sweep of the pair's 16 x 16
+  // Gram (15 steps, every pair of its columns); the other rounds only the 8
+  // steps that pair a column of block ba with one of block bb (step s: i with
+  // 8 + (i + s) mod 8).  Each pair of the matrix's columns is still visited
+  // once per sweep: pairs inside a block in round 0, pairs across blocks in
+  // the round where the blocks meet.
+  const bool full = round == 0;  // uniform
+  // Schedule positions: in the full sweep position p holds element
+  // s16_elem(p, r) at step r (start: the identity); in the cross steps the
+  // first block stays put and position 15 - k holds element 8 + (k + s) mod 8
+  // (start: e0(p) = p for p < 8, 23 - p for p >= 8, an involution).
+  const auto e0 = [full](int p) { return full || p < 8 ? p : 23 - p; };
   if (wave == 0) {
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int e = lane + 64 * t, i = e >> 4, j = e & 15;
-      Gb[0][i][j] = ((gp[0][i][j] + gp[1][i][j]) + gp[2][i][j]) + gp[3][i][j];
-      Jb[0][i][j] = i == j ? 1.0 : 0.0;
+      const int pi = e0(i), pj = e0(j);
+      Gb[0][i][j] = ((gp[0][pi][pj] + gp[1][pi][pj]) + gp[2][pi][pj]) + gp[3][pi][pj];
+      Jb[0][i][j] = i == pj ? 1.0 : 0.0;  // row: element, column: position
     }
     wave_lds_sync();
     bool off = false;
@@ -589,44 +604,52 @@ __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int r
     const bool anyo = __ballot(off) != 0;
     int cur = 0;
     if (anyo) {
-      // G and the columns of J are kept in schedule-position order: step r
-      // stores G[s16_elem(a, r)][s16_elem(b, r)] at [a][b].  The lane's
-      // positions (kp, 15 - kp) x (kq, 15 - kq) are then the same at every
+      // G and the columns of J are kept in schedule-position order, so the
+      // lane's positions (kp, 15 - kp) x (kq, 15 - kq) are the same at every
       // step, and each rotated entry is written where its element sits at the
-      // next step (position p -> p - 1, 1 -> 15, 0 stays).  After the 15 steps
-      // of the sweep every element is back at its own position.
+      // next step: full sweep p -> p - 1, 1 -> 15, 0 stays; cross steps
+      // p -> p + 1 for 8 <= p < 15, 15 -> 8, the first block stays.  After
+      // the 15 (8) steps every element is back at its start position.
       const int kp = lane >> 3, kq = lane & 7;
       const int A = kp, B = 15 - kp, C = kq, D = 15 - kq;
       const int j0 = 2 * kp, j1 = 2 * kp + 1;
-      const auto nxt = [](int pos) { return pos == 0 ? 0 : (pos == 1 ? 15 : pos - 1); };
-      const int nA = nxt(A), nB = nxt(B), nC = nxt(C), nD = nxt(D);
+      auto sweep_steps = [&](auto nsteps, auto nxt) {
+        constexpr int NS = decltype(nsteps)::value;
+        const int nA = nxt(A), nB = nxt(B), nC = nxt(C), nD = nxt(D);
 #pragma unroll
-      for (int r = 0; r < 15; ++r) {
-        const double (*G)[17] = Gb[r & 1];
-        const double (*J)[17] = Jb[r & 1];
-        const double paa = G[A][A], pbb = G[B][B], pab = G[A][B];
-        const double qaa = G[C][C], qbb = G[D][D], qab = G[C][D];
-        const double b00 = G[A][C], b01 = G[A][D], b10 = G[B][C], b11 = G[B][D];
-        const double j00 = J[j0][C], j01 = J[j0][D], j10 = J[j1][C], j11 = J[j1][D];
-        double cp, sp, cq, sq;
-        jacobi_rot(paa, pbb, pab, tol, floor2, cp, sp);
-        jacobi_rot(qaa, qbb, qab, tol, floor2, cq, sq);
-        // columns (right rotation by pair kq), then rows (left rotation by pair kp)
-        const double c00 = cq * b00 - sq * b01, c01 = sq * b00 + cq * b01;
-        const double c10 = cq * b10 - sq * b11, c11 = sq * b10 + cq * b11;
-        double (*Gn)[17] = Gb[(r & 1) ^ 1];
-        double (*Jn)[17] = Jb[(r & 1) ^ 1];
-        Gn[nA][nC] = cp * c00 - sp * c10;
-        Gn[nB][nC] = sp * c00 + cp * c10;
-        Gn[nA][nD] = cp * c01 - sp * c11;
-        Gn[nB][nD] = sp * c01 + cp * c11;
-        Jn[j0][nC] = cq * j00 - sq * j01;
-        Jn[j0][nD] = sq * j00 + cq * j01;
-        Jn[j1][nC] = cq * j10 - sq * j11;
-        Jn[j1][nD] = sq * j10 + cq * j11;
-        wave_lds_sync();
+        for (int r = 0; r < NS; ++r) {
+          const double (*G)[17] = Gb[r & 1];
+          const double (*J)[17] = Jb[r & 1];
+          const double paa = G[A][A], pbb = G[B][B], pab = G[A][B];
+          const double qaa = G[C][C], qbb = G[D][D], qab = G[C][D];
+          const double b00 = G[A][C], b01 = G[A][D], b10 = G[B][C], b11 = G[B][D];
+          const double j00 = J[j0][C], j01 = J[j0][D], j10 = J[j1][C], j11 = J[j1][D];
+          double cp, sp, cq, sq;
+          jacobi_rot(paa, pbb, pab, tol, floor2, cp, sp);
+          jacobi_rot(qaa, qbb, qab, tol, floor2, cq, sq);
+          // columns (right rotation by pair kq), then rows (left rotation by pair kp)
+          const double c00 = cq * b00 - sq * b01, c01 = sq * b00 + cq * b01;
+          const double c10 = cq * b10 - sq * b11, c11 = sq * b10 + cq * b11;
+          double (*Gn)[17] = Gb[(r & 1) ^ 1];
+          double (*Jn)[17] = Jb[(r & 1) ^ 1];
+          Gn[nA][nC] = cp * c00 - sp * c10;
+          Gn[nB][nC] = sp * c00 + cp * c10;
+          Gn[nA][nD] = cp * c01 - sp * c11;
+          Gn[nB][nD] = sp * c01 + cp * c11;
+          Jn[j0][nC] = cq * j00 - sq * j01;
+          Jn[j0][nD] = sq * j00 + cq * j01;
+          Jn[j1][nC] = cq * j10 - sq * j11;
+          Jn[j1][nD] = sq * j10 + cq * j11;
+          wave_lds_sync();
+        }
+      };
+      if (full) {
+        sweep_steps(std::integral_constant<int, 15>{}, [](int p) { return p == 0 ? 0 : (p == 1 ? 15 : p - 1); });
+        cur = 1;  // 15 steps: the result is in buffer 1
+      } else {
+        sweep_steps(std::integral_constant<int, 8>{}, [](int p) { return p < 8 ? p : (p < 15 ? p + 1 : 8); });
+        cur = 0;  // 8 steps: buffer 0
       }
-      cur = 1;  // 15 steps: the result is in buffer 1
     }
     if (lane == 0) any_off = anyo ? cur + 1 : 0;
   }
@@ -638,9 +661,9 @@ __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int r
     return;
   }
   if (tid == 0) v.flags[2 + sweep] = 1;
-  double jb[4];
+  double jb[4];  // J[4 st + g][c16]: its column c16 sits at position e0(c16)
 #pragma unroll
-  for (int st = 0; st < 4; ++st) jb[st] = Jb[ao - 1][4 * st + g][c16];
+  for (int st = 0; st < 4; ++st) jb[st] = Jb[ao - 1][4 * st + g][e0(c16)];
   if (stash) pair_apply_stash(v, xo, ba, bb, jb, share, wave, xs, vv);
   else pair_apply<8>(v, xo, ba, bb, jb, share + BJ_SPLIT * wave, 4 * BJ_SPLIT);
 }
