@@ -26,6 +26,8 @@ __global__ __launch_bounds__(256) void sample_floyd_kernel(int64_t n, int k, uin
                                                            int64_t* __restrict__ out) {
   __shared__ int64_t draw[SAMPLE_MAX_K];
   __shared__ int64_t keys[SAMPLE_MAX_K];
+  __shared__ uint8_t kept[SAMPLE_MAX_K], newk[SAMPLE_MAX_K];
+  __shared__ int changed;
   const int tid = threadIdx.x;
   // 1. Every draw v_t = uniform in [0, n - k + t] is independent of the others.
   for (int t = tid; t < k; t += blockDim.x) {
@@ -34,18 +36,31 @@ __global__ __launch_bounds__(256) void sample_floyd_kernel(int64_t n, int k, uin
     draw[t] = (int64_t)mulhi_bound(w.v[0], j + 1);
   }
   __syncthreads();
-  // 2. The membership test is sequential in t.  Wave 0 runs it; slot t of the
-  // chosen list lives in lane t % 64 and is only ever read by that lane, so no
-  // cross-lane LDS ordering is needed.
-  if (tid < 64) {
-    for (int t = 0; t < k; ++t) {
-      const int64_t cand = draw[t];
-      bool hit = false;
-      for (int s = tid; s < t; s += 64) hit |= (keys[s] == cand);
-      const bool any = __ballot(hit) != 0;
-      if (tid == (t & 63)) keys[t] = any ? (n - k + t) : cand;
+  // 2. Step t keeps its draw unless an earlier step chose that value: either an
+  // earlier draw that was kept, or an earlier replacement n - k + t'.  kept[t]
+  // depends only on kept[t' < t], so iterating "kept[t] from the current kept[]"
+  // from all-true is exact for one more leading t per pass; it stops at the
+  // first pass that changes nothing (duplicates are rare, so after a few).
+  for (int t = tid; t < k; t += blockDim.x) kept[t] = 1;
+  __syncthreads();
+  for (int pass = 0; pass <= k; ++pass) {
+    if (tid == 0) changed = 0;
+    __syncthreads();
+    for (int t = tid; t < k; t += blockDim.x) {
+      const int64_t v = draw[t];
+      int taken = 0;
+      for (int s = 0; s < t; ++s) taken |= kept[s] ? (draw[s] == v) : (n - k + s == v);
+      const int kt = !taken;
+      newk[t] = kt;
+      if (kt != kept[t]) changed = 1;
     }
+    __syncthreads();
+    const int any = changed;
+    for (int t = tid; t < k; t += blockDim.x) kept[t] = newk[t];
+    __syncthreads();
+    if (!any) break;  // uniform
   }
+  for (int t = tid; t < k; t += blockDim.x) keys[t] = kept[t] ? draw[t] : n - k + t;
   __syncthreads();
   // 3. Bitonic sort of keys[0..P) (P = next power of two >= k, padded with +inf).
   int P = 1;
