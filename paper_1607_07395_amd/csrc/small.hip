@@ -26,16 +26,26 @@ __global__ __launch_bounds__(256) void small_gemm_kernel(SmallGemmArgs g) {
   const int r = lane & 15, grp = lane >> 4;
   const int row = tm * 16 + r;   // A row owned for the A fragment
   const int col = tn * 16 + r;   // B column owned for the B fragment
+  // The loads of SG_U k-steps are issued together (from clamped, always valid
+  // addresses; out-of-range entries are replaced by zeros), then their MFMAs.
+  constexpr int SG_U = 8;
+  const int rowc = row < g.M ? row : 0, colc = col < g.N ? col : 0;
   f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-  for (int kb = 0; kb < g.K; kb += 4) {
-    const int k = kb + grp;
-    double av = 0.0, bv = 0.0;
-    if (k < g.K) {
-      if (row < g.M) av = g.transA ? g.A[(int64_t)k * g.lda + row] : g.A[(int64_t)row * g.lda + k];
-      if (col < g.N) bv = g.transB ? g.B[(int64_t)col * g.ldb + k] : g.B[(int64_t)k * g.ldb + col];
-      if (g.dm) av *= g.dm[k];
+  for (int kb = 0; kb < g.K; kb += 4 * SG_U) {
+    double av[SG_U], bv[SG_U];
+#pragma unroll
+    for (int u = 0; u < SG_U; ++u) {
+      const int k = kb + 4 * u + grp;
+      const bool kin = k < g.K;
+      const int kc = kin ? k : 0;
+      double a = g.transA ? g.A[(int64_t)kc * g.lda + rowc] : g.A[(int64_t)rowc * g.lda + kc];
+      const double b = g.transB ? g.B[(int64_t)colc * g.ldb + kc] : g.B[(int64_t)kc * g.ldb + colc];
+      if (g.dm) a *= g.dm[kc];
+      av[u] = kin && row < g.M ? a : 0.0;
+      bv[u] = kin && col < g.N ? b : 0.0;
     }
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < SG_U; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
   }
   const int oc = tn * 16 + r;
 #pragma unroll
