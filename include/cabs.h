@@ -54,8 +54,9 @@ typedef enum {
   CABS_SRC_DENSE = 0,   /* A stored row-major with leading dimension lda; sampled rows are
                            gathered with coalesced row reads, sampled columns through LDS tiles */
   CABS_SRC_LOWRANK = 1, /* A_ij = sum_t pf[i,t] s[t] qf[j,t] + noise_std * g(noise_seed, i, j),
-                           g a standard normal from Philox-4x64-10 at counter (i, j, 5, 0),
-                           key (noise_seed, 0), by Box-Muller; E is never stored */
+                           g a standard normal by Box-Muller on Philox-4x32-10 at counter
+                           (lo i, hi i, lo j, hi j), key (lo noise_seed, hi noise_seed): words
+                           1:0 give u1 in (0, 1], words 3:2 u2 in [0, 1); E is never stored */
   CABS_SRC_RBF = 2      /* A_ij = exp(-|x_i - y_j|^2 / (2 sigma^2)) */
 } cabs_src;
 

@@ -1,18 +1,22 @@
 """Counter-based random numbers for the oracle (test infrastructure only).
 
-Philox-4x64-10 is written out from its published definition (Salmon, Moraes,
-Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC 2011): ten
-rounds of two 64x64->128-bit multiplications with the constants below, the
-key bumped by two Weyl increments after every round.  The paper under study
+Philox-4x64-10 and Philox-4x32-10 are written out from their published
+definition (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as
+1, 2, 3", SC 2011): ten rounds of two full-width multiplications (64x64->128
+or 32x32->64 bits) with the constants below, the key bumped by two Weyl
+increments after every round.  The paper under study
 only says that the pilot rows and columns are chosen at random (Algorithm 2,
 pilot sampling); the reading taken here is: uniform sampling without
 replacement, rows and columns independent, realised with Floyd's algorithm on
 top of this generator so that a GPU can reproduce every draw bit for bit.
 
-Stream layout (counter = (a, b, stream, 0), key = (seed, 0)):
+Philox-4x64-10 stream layout (counter = (a, b, stream, 0), key = (seed, 0)):
   0 pilot rows, 1 pilot columns, 2/3 extra initial centres (rows/columns) when
-  the follow-up size exceeds the pilot size, 4 error-estimation samples,
-  5 the noise of the low-rank generator (counter = (i, j, 5, 0), key = noise seed).
+  the follow-up size exceeds the pilot size, 4 error-estimation samples.
+The noise of the low-rank generator, one draw per entry of A, uses the
+cheaper Philox-4x32-10 (its 32-bit products are what a GPU multiplies
+natively): counter = the 32-bit halves of (i, j), key = those of the noise
+seed.
 """
 from __future__ import annotations
 
@@ -30,7 +34,11 @@ STREAM_PILOT_COLS = 1
 STREAM_INIT_ROWS = 2
 STREAM_INIT_COLS = 3
 STREAM_ERROR = 4
-STREAM_NOISE = 5
+
+PHILOX32_M0 = np.uint64(0xD2511F53)
+PHILOX32_M1 = np.uint64(0xCD9E8D57)
+PHILOX32_W0 = np.uint64(0x9E3779B9)
+PHILOX32_W1 = np.uint64(0xBB67AE85)
 
 
 def _u64(x) -> np.ndarray:
@@ -85,15 +93,38 @@ def to_unit_open1(x) -> np.ndarray:
     return (_u64(x) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
 
 
-def normal_at(seed: int, i, j, stream: int = STREAM_NOISE) -> np.ndarray:
-    """Standard normal at counter (i, j, stream, 0), key (seed, 0).
+def philox4x32(c0, c1, c2, c3, k0, k1):
+    """Philox-4x32-10 block function on 32-bit words held in uint64 arrays.
 
-    Box-Muller on the first two words: sqrt(-2 ln u1) cos(2 pi u2) with
-    u1 in (0, 1] and u2 in [0, 1).
+    Each round multiplies words 0 and 2 by the round constants (32x32 -> 64
+    bits, exact in uint64), then mixes the high halves with words 1 and 3 and
+    the key: (hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0).
     """
-    w = philox4x64(_u64(i), _u64(j), np.uint64(stream), np.uint64(0), np.uint64(seed), np.uint64(0))
-    u1 = to_unit_open0(w[0])
-    u2 = to_unit_open1(w[1])
+    x = [_u64(c0) & _M32, _u64(c1) & _M32, _u64(c2) & _M32, _u64(c3) & _M32]
+    k0 = _u64(k0) & _M32
+    k1 = _u64(k1) & _M32
+    for _ in range(10):
+        p0 = PHILOX32_M0 * x[0]
+        p1 = PHILOX32_M1 * x[2]
+        x = [(p1 >> _S32) ^ x[1] ^ k0, p1 & _M32, (p0 >> _S32) ^ x[3] ^ k1, p0 & _M32]
+        k0 = (k0 + PHILOX32_W0) & _M32
+        k1 = (k1 + PHILOX32_W1) & _M32
+    return x
+
+
+def normal_at(seed: int, i, j) -> np.ndarray:
+    """Standard normal for entry (i, j) of the low-rank generator's noise.
+
+    Philox-4x32-10 at counter (lo(i), hi(i), lo(j), hi(j)), key (lo(seed),
+    hi(seed)); words 1:0 and 3:2 joined into 64-bit integers give u1 in (0, 1]
+    and u2 in [0, 1), and Box-Muller gives sqrt(-2 ln u1) cos(2 pi u2).
+    """
+    i = _u64(i)
+    j = _u64(j)
+    sd = np.uint64(seed)
+    w = philox4x32(i & _M32, i >> _S32, j & _M32, j >> _S32, sd & _M32, sd >> _S32)
+    u1 = to_unit_open0((w[1] << _S32) | w[0])
+    u2 = to_unit_open1((w[3] << _S32) | w[2])
     return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
 
 

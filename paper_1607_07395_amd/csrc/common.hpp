@@ -1,8 +1,8 @@
 // Shared device-side definitions for the CABS library (gfx950 / CDNA4).
 //
 // * element types and conversions for the four compute precisions
-// * Philox-4x64-10 (Salmon, Moraes, Dror, Shaw, SC 2011) and the integer /
-//   unit-interval / normal maps used by every random draw of the method
+// * Philox-4x64-10 and Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011)
+//   and the integer / unit-interval / normal maps used by every random draw
 // * MFMA fragment helpers for 16x16 output tiles with FP64, FP32, BF16 and
 //   FP16 operands (FP32 accumulation for the 16-bit types)
 // * wave64 reductions
@@ -79,20 +79,50 @@ __device__ __forceinline__ double unit_open1(uint64_t x) { return (double)(x >> 
 
 enum : uint64_t {
   STREAM_PILOT_ROWS = 0, STREAM_PILOT_COLS = 1, STREAM_INIT_ROWS = 2, STREAM_INIT_COLS = 3,
-  STREAM_ERROR = 4, STREAM_NOISE = 5
+  STREAM_ERROR = 4
 };
 
-// Standard normal at counter (i, j, 5, 0), key (seed, 0), by Box-Muller.
+// Philox-4x32-10: the same round structure on 32-bit words, one 32x32->64
+// product per multiplier and round.  It draws the noise of the low-rank
+// generator, one block per entry of A, where the 64-bit variant's products
+// (built from several 32-bit multiplies each) dominated entry evaluation.
+struct u32x4 { uint32_t v[4]; };
+
+__device__ __forceinline__ u32x4 philox4x32(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                            uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)M0 * c0, p1 = (uint64_t)M1 * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c0 = n0; c1 = (uint32_t)p1; c2 = n2; c3 = (uint32_t)p0;
+    k0 += W0; k1 += W1;
+  }
+  u32x4 o; o.v[0] = c0; o.v[1] = c1; o.v[2] = c2; o.v[3] = c3;
+  return o;
+}
+
+// The two 64-bit words of the noise block of entry (i, j): Philox-4x32-10 at
+// counter (lo i, hi i, lo j, hi j), key (lo seed, hi seed); words 1:0 and 3:2.
+__device__ __forceinline__ void noise_words(uint64_t seed, uint64_t i, uint64_t j, uint64_t& a, uint64_t& b) {
+  const u32x4 w = philox4x32((uint32_t)i, (uint32_t)(i >> 32), (uint32_t)j, (uint32_t)(j >> 32), (uint32_t)seed,
+                             (uint32_t)(seed >> 32));
+  a = ((uint64_t)w.v[1] << 32) | w.v[0];
+  b = ((uint64_t)w.v[3] << 32) | w.v[2];
+}
+
+// Standard normal of entry (i, j) by Box-Muller on those words.
 __device__ __forceinline__ double noise_f64(uint64_t seed, uint64_t i, uint64_t j) {
-  u64x4 w = philox4x64(i, j, STREAM_NOISE, 0, seed, 0);
-  double u1 = unit_open0(w.v[0]);
-  double u2 = unit_open1(w.v[1]);
-  return sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+  uint64_t a, b;
+  noise_words(seed, i, j, a, b);
+  return sqrt(-2.0 * log(unit_open0(a))) * cospi(2.0 * unit_open1(b));
 }
 __device__ __forceinline__ float noise_f32(uint64_t seed, uint64_t i, uint64_t j) {
-  u64x4 w = philox4x64(i, j, STREAM_NOISE, 0, seed, 0);
-  float u1 = (float)unit_open0(w.v[0]);
-  float u2 = (float)unit_open1(w.v[1]);
+  uint64_t a, b;
+  noise_words(seed, i, j, a, b);
+  const float u1 = (float)unit_open0(a), u2 = (float)unit_open1(b);
   return sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
 }
 

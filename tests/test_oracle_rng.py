@@ -9,11 +9,12 @@ import pytest
 from oracle import philox
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "philox4x64_10_kat.txt")
+GOLDEN32 = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
 
 
-def _kat_rows():
+def _kat_rows(path=GOLDEN):
     rows = []
-    with open(GOLDEN) as fh:
+    with open(path) as fh:
         for line in fh:
             line = line.strip()
             if line and not line.startswith("#"):
@@ -25,6 +26,24 @@ def _kat_rows():
 def test_philox_known_answers(row):
     out = philox.philox4x64(*[np.uint64(v) for v in row[:6]])
     assert [int(v) for v in out] == row[6:]
+
+
+@pytest.mark.parametrize("row", _kat_rows(GOLDEN32))
+def test_philox4x32_known_answers(row):
+    out = philox.philox4x32(*[np.uint64(v) for v in row[:6]])
+    assert [int(v) for v in out] == row[6:]
+
+
+def test_philox4x32_matches_a_plain_integer_round():
+    # one block recomputed with Python integers (arbitrary precision), round by round
+    c, k = [0x01234567, 0x89ABCDEF, 0xDEADBEEF, 0x00C0FFEE], [0x13579BDF, 0x2468ACE0]
+    x, kk = list(c), list(k)
+    for _ in range(10):
+        p0, p1 = 0xD2511F53 * x[0], 0xCD9E8D57 * x[2]
+        x = [(p1 >> 32) ^ x[1] ^ kk[0], p1 & 0xFFFFFFFF, (p0 >> 32) ^ x[3] ^ kk[1], p0 & 0xFFFFFFFF]
+        kk = [(kk[0] + 0x9E3779B9) & 0xFFFFFFFF, (kk[1] + 0xBB67AE85) & 0xFFFFFFFF]
+    got = philox.philox4x32(*[np.uint64(v) for v in c + k])
+    assert [int(v) for v in got] == x
 
 
 def test_philox_matches_numpy_bit_generator():
@@ -74,12 +93,19 @@ def test_normal_box_muller_value_and_moments():
     g = philox.normal_at(99, i, np.uint64(3))
     assert abs(g.mean()) < 0.01 and abs(g.var() - 1.0) < 0.01
     assert abs((g**4).mean() - 3.0) < 0.05
-    # One value recomputed by hand from the two words.
-    w = philox.philox4x64(np.uint64(17), np.uint64(3), np.uint64(5), np.uint64(0), np.uint64(99), np.uint64(0))
-    u1 = ((int(w[0]) >> 11) + 1) / 2.0**53
-    u2 = (int(w[1]) >> 11) / 2.0**53
+    # One value recomputed by hand from the four 32-bit words (64-bit halves of i, j and the seed).
+    i0, j0, sd = (5 << 32) + 17, 3, (7 << 32) + 99
+    w = [int(v) for v in philox.philox4x32(np.uint64(17), np.uint64(5), np.uint64(3), np.uint64(0),
+                                           np.uint64(99), np.uint64(7))]
+    u1 = ((((w[1] << 32) | w[0]) >> 11) + 1) / 2.0**53
+    u2 = (((w[3] << 32) | w[2]) >> 11) / 2.0**53
     want = math.sqrt(-2.0 * math.log(u1)) * math.cos(2.0 * math.pi * u2)
-    assert philox.normal_at(99, np.uint64(17), np.uint64(3)) == pytest.approx(want, rel=1e-15)
+    assert philox.normal_at(sd, np.uint64(i0), np.uint64(j0)) == pytest.approx(want, rel=1e-15)
+    # entries that differ only in the high halves of i, j or the seed draw different values
+    base = philox.normal_at(sd, np.uint64(i0), np.uint64(j0))
+    assert base != philox.normal_at(sd, np.uint64(17), np.uint64(j0))
+    assert base != philox.normal_at(sd, np.uint64(i0), np.uint64(j0 + (1 << 32)))
+    assert base != philox.normal_at(99, np.uint64(i0), np.uint64(j0))
 
 
 def test_floyd_basic_properties():

@@ -18,10 +18,11 @@ def test_lowrank_entries_by_brute_force():
     for i in range(9):
         for a, j in enumerate(cols):
             sig = sum(spec.pf[i, t] * spec.s[t] * spec.qf[j, t] for t in range(4))
-            w = philox.philox4x64(np.uint64(i), np.uint64(j), np.uint64(5), np.uint64(0),
-                                  np.uint64(spec.noise_seed), np.uint64(0))
-            u1 = ((int(w[0]) >> 11) + 1) / 2.0**53
-            u2 = (int(w[1]) >> 11) / 2.0**53
+            sd = int(spec.noise_seed)
+            w = [int(v) for v in philox.philox4x32(np.uint64(i), np.uint64(0), np.uint64(j), np.uint64(0),
+                                                   np.uint64(sd & 0xFFFFFFFF), np.uint64(sd >> 32))]
+            u1 = ((((w[1] << 32) | w[0]) >> 11) + 1) / 2.0**53
+            u2 = (((w[3] << 32) | w[2]) >> 11) / 2.0**53
             g = math.sqrt(-2 * math.log(u1)) * math.cos(2 * math.pi * u2)
             assert c[i, a] == pytest.approx(sig + 0.25 * g, rel=1e-13, abs=1e-15)
     rt = mat.rows_t(np.array([2, 5]))
