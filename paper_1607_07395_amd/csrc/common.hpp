@@ -119,11 +119,18 @@ __device__ __forceinline__ double noise_f64(uint64_t seed, uint64_t i, uint64_t 
   noise_words(seed, i, j, a, b);
   return sqrt(-2.0 * log(unit_open0(a))) * cospi(2.0 * unit_open1(b));
 }
+// The FP32 form (entries computed in FP32 or narrower).  u1 is the 53-bit
+// value rounded to float (relative error 2^-24: the radius sqrt(-2 ln u1)
+// would magnify an absolute error of 2^-24 for small u1) and goes through the
+// accurate logf; the hardware square root and cos(2 pi x) take the radius and
+// the top 24 bits of the second word (already in revolutions, so no range
+// reduction), both with errors of a few ulp that nothing magnifies.
 __device__ __forceinline__ float noise_f32(uint64_t seed, uint64_t i, uint64_t j) {
   uint64_t a, b;
   noise_words(seed, i, j, a, b);
-  const float u1 = (float)unit_open0(a), u2 = (float)unit_open1(b);
-  return sqrtf(-2.0f * logf(u1)) * cospif(2.0f * u2);
+  const float u1 = (float)unit_open0(a);
+  const float u2 = (float)(uint32_t)(b >> 40) * 0x1.0p-24f;
+  return __builtin_amdgcn_sqrtf(-2.0f * logf(u1)) * __builtin_amdgcn_cosf(u2);
 }
 
 // ---------------------------------------------------------------------------
