@@ -104,7 +104,11 @@ struct EvalArgs {
   double inv2s2;                            // 1 / (2 sigma^2)
 };
 
-constexpr int EVAL_NT = 8;
+// Five 16-column tiles per wave (80 columns): about 120 registers, so four
+// waves per SIMD overlap one wave's MFMAs with another's per-entry work (the
+// noise draw or the exponential); 2, 4, 7, 8 and 13 tiles measured slower or
+// equal on the 10^5 x 200 low-rank block.
+constexpr int EVAL_NT = 5;
 
 template <typename TIn, typename TC, int SRC>
 __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a) {
