@@ -172,7 +172,8 @@ cabs_status cabs_sketch(const cabs_matrix* mat, const cabs_params* prm, void* ws
 /* Relative Frobenius error |A - C Umid R|_F / |A|_F (the paper's error metric,
  * Section 5) of a finished sketch.  n_samples = 0: exact, over all m*n entries;
  * otherwise over n_samples i.i.d. uniform entries drawn with replacement from
- * Philox stream 4 with key (seed, 0): sample t is (mulhi(w0, m), mulhi(w1, n)).
+ * Philox-4x32-10 at counter (lo t, hi t, 4, 0), key (lo seed, hi seed): sample t is
+ * (mulhi(w, m), mulhi(w', n)) with w = words 1:0 and w' = words 3:2 as 64-bit integers.
  * out3 (device) receives {sum of squared residuals, sum of squared entries,
  * ratio}.  ws must hold cabs_error_workspace_bytes() bytes. */
 size_t cabs_error_workspace_bytes(const cabs_matrix* mat, const cabs_params* prm, int64_t n_samples);

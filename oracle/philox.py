@@ -12,11 +12,12 @@ top of this generator so that a GPU can reproduce every draw bit for bit.
 
 Philox-4x64-10 stream layout (counter = (a, b, stream, 0), key = (seed, 0)):
   0 pilot rows, 1 pilot columns, 2/3 extra initial centres (rows/columns) when
-  the follow-up size exceeds the pilot size, 4 error-estimation samples.
-The noise of the low-rank generator, one draw per entry of A, uses the
-cheaper Philox-4x32-10 (its 32-bit products are what a GPU multiplies
-natively): counter = the 32-bit halves of (i, j), key = those of the noise
-seed.
+  the follow-up size exceeds the pilot size.
+The two high-volume draws use the cheaper Philox-4x32-10 (its 32-bit
+products are what a GPU multiplies natively), key = the 32-bit halves of the
+seed: the error-estimation samples (counter (lo t, hi t, 4, 0)) and the noise
+of the low-rank generator, one draw per entry of A (counter = the 32-bit
+halves of (i, j)).
 """
 from __future__ import annotations
 
@@ -153,10 +154,14 @@ def floyd_sample(n: int, k: int, seed: int, stream: int) -> np.ndarray:
 def error_sample_indices(m: int, n: int, count: int, seed: int, start: int = 0):
     """The (i, j) entry positions used by the sampled error estimate.
 
-    Sample t sits at counter (t, 0, 4, 0): i = mulhi64(word0, m), j =
-    mulhi64(word1, n).  Samples are i.i.d. uniform over the m*n entries, drawn
-    with replacement.
+    Sample t takes the Philox-4x32-10 block at counter (lo t, hi t, 4, 0),
+    key (lo seed, hi seed); words 1:0 and 3:2 joined into 64-bit integers
+    give i = mulhi64(word, m) and j = mulhi64(word, n).  Samples are i.i.d.
+    uniform over the m*n entries, drawn with replacement.
     """
     t = np.arange(start, start + count, dtype=np.uint64)
-    w = philox4x64(t, 0, STREAM_ERROR, 0, seed, 0)
-    return mulhi64(w[0], np.uint64(m)).astype(np.int64), mulhi64(w[1], np.uint64(n)).astype(np.int64)
+    sd = np.uint64(seed)
+    w = philox4x32(t & _M32, t >> _S32, STREAM_ERROR, 0, sd & _M32, sd >> _S32)
+    wi = (w[1] << _S32) | w[0]
+    wj = (w[3] << _S32) | w[2]
+    return mulhi64(wi, np.uint64(m)).astype(np.int64), mulhi64(wj, np.uint64(n)).astype(np.int64)

@@ -54,10 +54,13 @@ __device__ __forceinline__ double entry_f64(const MatView& mv, int64_t i, int64_
   return s;
 }
 
+// Sample t: Philox-4x32-10 at counter (lo t, hi t, 4, 0), key (lo seed, hi
+// seed); i and j from the high words of 64x64 products of words 1:0 by m and
+// words 3:2 by n (uniform over the m x n entries, with replacement).
 __device__ __forceinline__ void err_sample_ij(uint64_t t, uint64_t seed, int64_t m, int64_t n, int64_t& i, int64_t& j) {
-  const u64x4 w = philox4x64(t, 0, STREAM_ERROR, 0, seed, 0);
-  i = (int64_t)mulhi_bound(w.v[0], (uint64_t)m);
-  j = (int64_t)mulhi_bound(w.v[1], (uint64_t)n);
+  const u32x4 w = philox4x32((uint32_t)t, (uint32_t)(t >> 32), STREAM_ERROR, 0, (uint32_t)seed, (uint32_t)(seed >> 32));
+  i = (int64_t)mulhi_bound(((uint64_t)w.v[1] << 32) | w.v[0], (uint64_t)m);
+  j = (int64_t)mulhi_bound(((uint64_t)w.v[3] << 32) | w.v[2], (uint64_t)n);
 }
 
 // Thirty-two zero bytes to point out-of-range loads at, so that loads need no

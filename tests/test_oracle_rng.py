@@ -142,3 +142,11 @@ def test_error_samples_are_uniform_and_in_range():
     assert counts.min() > 800 and counts.max() < 1200
     i2, j2 = philox.error_sample_indices(7, 11, 100, seed=4, start=500)
     assert np.array_equal(i2, i[500:600]) and np.array_equal(j2, j[500:600])
+    # one sample recomputed from its block with Python integers; a sample index past 2^32 and a
+    # seed past 2^32 use the high halves of the counter and key
+    t, sd, m, n = (3 << 32) + 5, (9 << 32) + 4, 10**6 + 3, 777
+    w = [int(v) for v in philox.philox4x32(np.uint64(5), np.uint64(3), np.uint64(4), np.uint64(0), np.uint64(4),
+                                           np.uint64(9))]
+    i3, j3 = philox.error_sample_indices(m, n, 1, seed=sd, start=t)
+    assert int(i3[0]) == ((((w[1] << 32) | w[0]) * m) >> 64)
+    assert int(j3[0]) == ((((w[3] << 32) | w[2]) * n) >> 64)
