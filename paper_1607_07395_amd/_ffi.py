@@ -67,6 +67,7 @@ _SIGS = {
     "cabs_eval_rows_t": (C.c_int, [C.POINTER(CabsMatrix), _P, C.c_int32, C.c_int32, _P, _P]),
     "cabs_svd_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32]),
     "cabs_svd": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, _P, _P, C.c_size_t, _P]),
+    "cabs_svd_ex": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, _P, _P, C.c_size_t, C.c_int32, _P]),
     "cabs_kmeans_workspace_bytes": (C.c_size_t, [C.c_int64, C.c_int32, C.c_int32, C.c_int32]),
     "cabs_kmeans": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, C.c_int32, _P, _P, _P, _P,
                               _P, C.c_size_t, _P]),

@@ -224,8 +224,9 @@ def eval_rows_t(mat: DeviceMatrix, idx: torch.Tensor, compute: str = "f32", stre
     return out
 
 
-def svd(a: torch.Tensor, stream=None):
-    """cabs_svd on a (batch, rows, cols) or (rows, cols) float64 device tensor -> U, S, V."""
+def svd(a: torch.Tensor, stream=None, fast_sweeps=None):
+    """cabs_svd (cabs_svd_ex when fast_sweeps is given) on a (batch, rows, cols) or (rows, cols)
+    float64 device tensor -> U, S, V."""
     squeeze = a.dim() == 2
     a3 = (a[None] if squeeze else a).contiguous()
     if a3.dtype != torch.float64:
@@ -239,8 +240,12 @@ def svd(a: torch.Tensor, stream=None):
     if need == 0:
         raise F.CabsError(F.EINVAL, "cabs_svd_workspace_bytes")
     ws = _dev_alloc(need, a.device)
-    F.check(F.lib().cabs_svd(b, rows, cols, _ptr(a3), _ptr(U), _ptr(S), _ptr(V), _ptr(ws), ws.numel(),
-                             _stream(stream)), "cabs_svd")
+    if fast_sweeps is None:
+        F.check(F.lib().cabs_svd(b, rows, cols, _ptr(a3), _ptr(U), _ptr(S), _ptr(V), _ptr(ws), ws.numel(),
+                                 _stream(stream)), "cabs_svd")
+    else:
+        F.check(F.lib().cabs_svd_ex(b, rows, cols, _ptr(a3), _ptr(U), _ptr(S), _ptr(V), _ptr(ws), ws.numel(),
+                                    int(fast_sweeps), _stream(stream)), "cabs_svd_ex")
     if squeeze:
         return U[0], S[0], V[0]
     return U, S, V

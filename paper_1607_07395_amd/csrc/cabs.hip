@@ -434,6 +434,8 @@ static MatView view_of(const cabs_matrix* mat) {
   return v;
 }
 
+constexpr int K_FAST_SWEEPS = 9;
+
 // One sketching round on sampled C (m x kc), R^T (n x kr), W (kr x kc, FP64).
 // Computes the SVD of W, the norms and scalings; optionally the extrapolated
 // vectors C^, R^ and the orthogonalised embedding maps.
@@ -473,7 +475,11 @@ static cabs_status run_round(const Plan& pl, RoundWs& R, int kr, int kc, const v
     const double eps = 2.220446049250313e-16;
     HIP_TRY(launch_pchol(2, p, R.G2, pp, (double)p * eps, R.E2V, pp, st));
     HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, false, R.E2V + pp, p, true, nullptr, R.sk, nullptr, R.K, p, st));
-    HIP_TRY(launch_svd(1, p, p, R.K, 0, R.Us, 0, R.S1, 0, R.Vs, 0, R.svd_ws, st));
+    // On the measured workloads the Jacobi iteration on K ends after 7-8 sweeps where the one
+    // on W takes 12; launching 9 sweeps round by round saves the launches of 3-5 sweeps that
+    // would only find the converged flag, and a K that needs more is finished by the
+    // single-workgroup kernel (same result, slower).
+    HIP_TRY(launch_svd(1, p, p, R.K, 0, R.Us, 0, R.S1, 0, R.Vs, 0, R.svd_ws, st, K_FAST_SWEEPS));
     hipLaunchKernelGGL(rsqrt_trunc_kernel, dim3(1), dim3(1024), 0, st, p, R.S1, R.sq);
     hipLaunchKernelGGL(mul_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.invc, R.sk, R.fpos);
     hipLaunchKernelGGL(mul_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.invr, R.sk, R.fpos + p);
@@ -706,16 +712,22 @@ extern "C" size_t cabs_svd_workspace_bytes(int32_t batch, int32_t rows, int32_t 
   return svd_ws_bytes(batch, rows, cols);
 }
 
-extern "C" cabs_status cabs_svd(int32_t batch, int32_t rows, int32_t cols, const double* A, double* U, double* S,
-                                double* V, void* ws, size_t ws_bytes, void* stream) {
+extern "C" cabs_status cabs_svd_ex(int32_t batch, int32_t rows, int32_t cols, const double* A, double* U, double* S,
+                                   double* V, void* ws, size_t ws_bytes, int32_t fast_sweeps, void* stream) {
   if (batch <= 0 || rows <= 0 || cols <= 0 || rows > 1024 || cols > 1024)
     return fail(CABS_EINVAL, "need batch > 0 and 0 < rows, cols <= 1024");
+  if (fast_sweeps < 1 || fast_sweeps > 12) return fail(CABS_EINVAL, "need 1 <= fast_sweeps <= 12");
   if (!A || !U || !S || !V || !ws) return fail(CABS_EINVAL, "null pointer");
   if (ws_bytes < svd_ws_bytes(batch, rows, cols)) return fail(CABS_ENOMEM, "workspace too small");
   const int64_t p = rows < cols ? rows : cols;
   HIP_TRY(launch_svd(batch, rows, cols, A, (int64_t)rows * cols, U, (int64_t)rows * p, S, p, V, (int64_t)cols * p, ws,
-                     (hipStream_t)stream));
+                     (hipStream_t)stream, fast_sweeps));
   return CABS_OK;
+}
+
+extern "C" cabs_status cabs_svd(int32_t batch, int32_t rows, int32_t cols, const double* A, double* U, double* S,
+                                double* V, void* ws, size_t ws_bytes, void* stream) {
+  return cabs_svd_ex(batch, rows, cols, A, U, S, V, ws, ws_bytes, 12, stream);
 }
 
 extern "C" size_t cabs_kmeans_workspace_bytes(int64_t rows, int32_t dim, int32_t k, int32_t compute) {

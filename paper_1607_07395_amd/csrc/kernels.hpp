@@ -42,8 +42,10 @@ hipError_t launch_gather_rows_f64(const void* src, int compute, int64_t ld, cons
 // --- FP64 small dense algebra (svd.hip, small.hip) ---
 size_t svd_ws_bytes(int batch, int rows, int cols);
 // Batched one-sided Jacobi SVD; A_b rows x cols row-major, strides in elements between batch items.
+// fast_sweeps (1 .. 12): sweeps launched round by round before the single-workgroup finisher.
 hipError_t launch_svd(int batch, int rows, int cols, const double* A, int64_t strideA, double* U, int64_t strideU,
-                      double* S, int64_t strideS, double* V, int64_t strideV, void* ws, hipStream_t st);
+                      double* S, int64_t strideS, double* V, int64_t strideV, void* ws, hipStream_t st,
+                      int fast_sweeps = 12);
 
 // C (M x N) = alpha * op(A) diag(dl) ... : general small FP64 product
 //   C = diag(dl) * op(A) * diag(dm) * op(B) * diag(dr)   (any diag pointer may be null)

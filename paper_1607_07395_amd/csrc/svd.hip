@@ -218,10 +218,12 @@ __global__ __launch_bounds__(SVD_THREADS) void svd_jacobi_kernel(int rows, int c
 // rotation ends the iteration.  Columns below eps |X|_F are at the rounding
 // level of the block updates and are neither tested nor rotated.
 //
-// The first BJ_FAST_SWEEPS sweeps run as one launch per round with one
-// workgroup (4 waves) per block pair, spreading a round over many CUs; a
-// single-workgroup kernel then finishes the rare matrices that need more sweeps
-// (it returns at once when the matrix has converged) and writes the outputs.
+// The first sweeps (at most BJ_FAST_SWEEPS, fewer where the caller expects
+// fast convergence) run as one launch per round with BJ_SPLIT workgroups per
+// block pair, spreading a round over many CUs; rounds after convergence return
+// at once but still cost a launch.  A single-workgroup kernel then finishes
+// the matrices that need more sweeps (it skips that step when the matrix has
+// converged) and writes the outputs.
 // X (q x P) and V (P x P) are row-major in the workspace.
 // ---------------------------------------------------------------------------
 constexpr int BJ_FAST_SWEEPS = 12;
@@ -765,8 +767,8 @@ __global__ __launch_bounds__(1024) void bj_finish_kernel(int rows, int cols, int
   double (*G)[17] = Gs[wave];
   // the copy of X the fast phase ended on (its sweeps have nb - 1 rounds, an odd number);
   // the sweeps here work on it in place
-  int used = BJ_FAST_SWEEPS;  // sweeps run by the fast phase: through the first without rotations
-  for (int sw = 0; sw < BJ_FAST_SWEEPS; ++sw)
+  int used = first_sweep;  // sweeps run by the fast phase: through the first without rotations
+  for (int sw = 0; sw < first_sweep; ++sw)
     if (v.flags[2 + sw] == 0) { used = sw + 1; break; }
   if (used & 1) v.X = v.X1;
   const bool converged = v.flags[2 + used - 1] == 0;
@@ -852,8 +854,10 @@ __global__ __launch_bounds__(1024) void bj_finish_kernel(int rows, int cols, int
 }
 
 hipError_t launch_svd(int batch, int rows, int cols, const double* A, int64_t strideA, double* U, int64_t strideU,
-                      double* S, int64_t strideS, double* V, int64_t strideV, void* ws, hipStream_t st) {
+                      double* S, int64_t strideS, double* V, int64_t strideV, void* ws, hipStream_t st,
+                      int fast_sweeps) {
   if (batch <= 0 || rows <= 0 || cols <= 0 || rows > 1024 || cols > 1024) return hipErrorInvalidValue;
+  if (fast_sweeps < 1 || fast_sweeps > BJ_FAST_SWEEPS) return hipErrorInvalidValue;
   const size_t p = rows < cols ? rows : cols, q = rows < cols ? cols : rows;
   const size_t lds_bytes = (q * p + p * p) * sizeof(double);
   const int use_lds = lds_bytes <= (size_t)SVD_LDS_BYTES ? 1 : 0;
@@ -869,12 +873,12 @@ hipError_t launch_svd(int batch, int rows, int cols, const double* A, int64_t st
   hipLaunchKernelGGL(bj_init_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(elems, 256), 1024), batch), dim3(256), 0,
                      st, rows, cols, A, strideA, w);
   hipLaunchKernelGGL(bj_norm_kernel, dim3(batch), dim3(1024), 0, st, rows, cols, A, strideA, w);
-  for (int sweep = 0; sweep < BJ_FAST_SWEEPS; ++sweep) {
+  for (int sweep = 0; sweep < fast_sweeps; ++sweep) {
     for (int round = 0; round < nb - 1; ++round)
       hipLaunchKernelGGL(bj_round_kernel, dim3(nb / 2 * BJ_SPLIT, batch), dim3(256), 0, st, rows, cols, round, sweep,
                          w);
   }
-  hipLaunchKernelGGL(bj_finish_kernel, dim3(batch), dim3(1024), 0, st, rows, cols, BJ_FAST_SWEEPS, U, strideU, S,
+  hipLaunchKernelGGL(bj_finish_kernel, dim3(batch), dim3(1024), 0, st, rows, cols, fast_sweeps, U, strideU, S,
                      strideS, V, strideV, w);
   return hipGetLastError();
 }

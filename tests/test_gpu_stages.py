@@ -106,6 +106,23 @@ def test_svd_block_path_unscaled(api, rows, cols, seed):
     assert np.abs(V.T @ V - np.eye(p)).max() < 1e-11
 
 
+@pytest.mark.parametrize("fast", [1, 2, 9, 12])
+def test_svd_block_path_finisher_sweeps(api, fast):
+    """The same Gaussian matrix (its iteration needs about 12 sweeps) with the
+    round-by-round phase cut after 1, 2, 9 or 12 sweeps: the single-work-group
+    kernel runs the rest from either copy of the working columns."""
+    rng = np.random.default_rng(21)
+    a = rng.normal(size=(232, 232))
+    U, S, V = (x.cpu().numpy() for x in api.svd(torch.from_numpy(a).cuda(), fast_sweeps=fast))
+    s0 = np.linalg.svd(a, compute_uv=False)
+    assert np.allclose(S, s0, rtol=0, atol=1e-12 * s0[0])
+    assert np.abs(U * S @ V.T - a).max() <= 1e-12 * s0[0] * 232
+    assert np.abs(U.T @ U - np.eye(232)).max() < 1e-11
+    assert np.abs(V.T @ V - np.eye(232)).max() < 1e-11
+    with pytest.raises(Exception):
+        api.svd(torch.from_numpy(a).cuda(), fast_sweeps=13)
+
+
 def test_svd_block_path_batched(api):
     rng = np.random.default_rng(12)
     a = np.stack([rng.normal(size=(210, 210)) * np.exp(-0.05 * np.arange(210))[None, :],
