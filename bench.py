@@ -55,6 +55,14 @@ def parse():
                          "traffic for calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--cpu-scale", type=float, default=0.5,
                     help="row/column scale of the workload the CPU oracle is timed on")
+    ap.add_argument("--stream", action="store_true",
+                    help="instead of the headline workload: the serving stream of uneven requests (Poisson "
+                         "arrivals at fractions of the closed-loop maximum, p50/p99 per point)")
+    ap.add_argument("--stream-requests", type=int, default=2000, help="requests per stream phase")
+    ap.add_argument("--stream-pool", type=int, default=16, help="distinct request matrices built and uploaded")
+    ap.add_argument("--stream-fracs", default="0.25,0.5,0.75,0.9",
+                    help="offered load points as fractions of the measured closed-loop maximum")
+    ap.add_argument("--stream-compute", default="bf16")
     return ap.parse_args()
 
 
@@ -108,12 +116,107 @@ def cpu_baseline(config: str, scale: float, err_samples: int) -> dict:
             "seconds": dt}
 
 
+def run_stream(args):
+    """The serving stream: requests of uneven shape (m, n log-uniform in [1e3, 5e5], low-rank + noise or RBF,
+    k in {16, ..., 256}, pilot size k, seed 1000 + id), sketches only.  The closed-loop maximum is measured
+    first (--slots requests in flight); then the same requests arrive as a Poisson process at each fraction
+    of that rate, and latency runs from arrival to completion (the server's submit-to-completion time plus
+    any delay of the host loop in submitting).  Host generation of a 5e5-row orthonormal basis takes
+    seconds, so the first --stream-pool recipes are built and uploaded once and request i runs on matrix
+    i mod pool with its own k and seed."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_1607_07395_amd import api
+
+    torch.cuda.set_device(0)
+    n_req = args.stream_requests
+    recs = workloads.request_stream(n_requests=n_req, qps=1.0, seed=0)
+    P = max(1, min(args.stream_pool, n_req))
+    t_b = time.perf_counter()
+    pool = []
+    for i in range(P):
+        pool.append(api.DeviceMatrix(workloads.request_matrix(recs[i]), storage="f32"))
+        print(f"stream: matrix {i + 1}/{P} {recs[i]['kind']} {recs[i]['m']}x{recs[i]['n']}", file=sys.stderr,
+              flush=True)
+    build_s = time.perf_counter() - t_b
+    comp, iters, S = args.stream_compute, 5, max(1, args.slots)
+
+    def params(i):
+        mat = pool[i % P]
+        k = min(recs[i]["k"], mat.spec.m, mat.spec.n)
+        return mat, api.make_params(k, k, k, k, kmeans_iters=iters, compute=comp, seed=recs[i]["seed"])
+
+    need = 0
+    for mat in pool:
+        kk = min(256, mat.spec.m, mat.spec.n)
+        need = max(need, api.workspace_bytes(mat, api.make_params(kk, kk, kk, kk, kmeans_iters=iters, compute=comp)))
+    srv = api.Server(0, hbm_budget_bytes=S * (need + (1 << 20)), max_slots=S)
+
+    def drive(ids, arrivals):
+        """Submit ids (closed loop when arrivals is None); returns latencies (ms) and the span (s)."""
+        live, lat, last = {}, [], 0.0
+        nxt, n = 0, len(ids)
+        t0 = time.perf_counter()
+        while nxt < n or live:
+            now = time.perf_counter() - t0
+            while nxt < n and ((arrivals is None and len(live) < S) or (arrivals is not None and arrivals[nxt] <= now)):
+                mat, prm = params(ids[nxt])
+                out = api.alloc_result(mat, prm)
+                lag = 0.0 if arrivals is None else (time.perf_counter() - t0) - arrivals[nxt]
+                live[srv.submit(mat, prm, out)] = (out, lag)
+                nxt += 1
+            for t in list(live):
+                r = srv.poll(t)
+                if r is not None:
+                    _, lag = live.pop(t)
+                    lat.append((r + lag) * 1e3)
+                    last = time.perf_counter() - t0
+            time.sleep(0.0002)
+        return np.array(lat), last
+
+    try:
+        drive(list(range(min(n_req, 2 * S))), None)  # warm-up
+        torch.cuda.synchronize()
+        lat, span = drive(list(range(n_req)), None)
+        lam = n_req / span
+        closed = {"sketches_per_s": lam, "p50_ms": float(np.percentile(lat, 50)),
+                  "p99_ms": float(np.percentile(lat, 99))}
+        print(f"stream: closed loop {lam:.1f} sketches/s", file=sys.stderr, flush=True)
+        points = []
+        for f in [float(x) for x in args.stream_fracs.split(",") if x]:
+            rng = np.random.default_rng(1)
+            arr = np.cumsum(rng.exponential(1.0 / (f * lam), size=n_req))
+            arr -= arr[0]
+            lat, span = drive(list(range(n_req)), arr)
+            points.append({"load_frac": f, "offered_per_s": f * lam, "sketches_per_s": n_req / span,
+                           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))})
+            print(f"stream: load {f:g} -> p50 {points[-1]['p50_ms']:.1f} ms, p99 {points[-1]['p99_ms']:.1f} ms",
+                  file=sys.stderr, flush=True)
+    finally:
+        srv.close()
+    kinds = [pool[i % P].spec.kind for i in range(n_req)]
+    print(json.dumps({
+        "metric": "serving stream: sketches/s and p50/p99 latency under Poisson arrivals",
+        "unit": "sketches/s", "n_gpus": 1, "dtype": comp, "data": "synthetic",
+        "config": {"workload": "uneven requests: m, n log-uniform in [1e3, 5e5], low-rank + noise (rank 16-256) "
+                               "or RBF (d = 32, 10-100 clusters), k in {16, 32, 64, 128, 256}, c = 5, sketch only",
+                   "requests": n_req, "matrix_pool": P, "slots": S,
+                   "pool_shapes": [[int(m.spec.m), int(m.spec.n), m.spec.kind] for m in pool],
+                   "lowrank_share": kinds.count("lowrank") / n_req, "pool_build_s": build_s},
+        "closed_loop": closed, "poisson": points}), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
         sys.exit(2)
+    if args.stream:
+        run_stream(args)
+        return
 
     import numpy as np
     import torch
