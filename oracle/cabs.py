@@ -23,6 +23,7 @@ EPS = float(np.finfo(np.float64).eps)
 
 WEIGHT_KINDS = ("const", "pow", "sigmoid", "step")
 SKETCH_KINDS = ("stabilized", "pseudo_skeleton")
+FOLLOW_UPS = ("kmeans", "hard")
 
 
 class RankError(RuntimeError):
@@ -45,6 +46,7 @@ class Params:
     pinv_rtol: float = 0.0           # <= 0: max(kr, kc) * eps * sigma_1
     seed: int = 0
     factors: bool = False            # also return the orthogonalised factor form of the result
+    follow_up: str = "kmeans"        # "hard": the hard-threshold variant of Section 5
 
     @classmethod
     def square(cls, k: int, **kw) -> "Params":
@@ -235,6 +237,18 @@ def weighted_kmeans(p: np.ndarray, w: np.ndarray, z0: np.ndarray, iters: int) ->
 SNAP_TIE_RTOL = 1e-11
 
 
+def hard_threshold(w: np.ndarray, k: int) -> np.ndarray:
+    """The hard-threshold follow-up of Section 5: the k rows with the largest
+    weighting coefficients (the weights of the weighted k-means objective,
+    Section 3.2), instead of the k-means centres.  Reading (the paper gives no
+    tie rule): equal weights go to the lower row index; NaN weights are never
+    chosen before a number.  Returned ascending."""
+    w = np.asarray(w, dtype=np.float64)
+    key = np.where(np.isnan(w), -np.inf, w)
+    order = np.lexsort((np.arange(w.size), -key))  # primary: weight descending; then index ascending
+    return np.sort(order[:k]).astype(np.int64)
+
+
 def snap(p: np.ndarray, z: np.ndarray, tie_rtol: float = SNAP_TIE_RTOL) -> np.ndarray:
     """Replace every centre by its nearest in-sample point (Section 3.2).
 
@@ -328,8 +342,8 @@ class Result:
     Q: np.ndarray
     w_r: np.ndarray
     w_c: np.ndarray
-    km_r: KMeansResult
-    km_c: KMeansResult
+    km_r: Optional[KMeansResult]
+    km_c: Optional[KMeansResult]
     entries_touched: int
     factors: Optional[tuple] = None
     pilot_C: Optional[np.ndarray] = None
@@ -347,6 +361,8 @@ def validate(m: int, n: int, prm: Params) -> None:
         raise ValueError("kmeans_iters must be >= 0")
     if prm.weight_kind not in WEIGHT_KINDS or prm.sketch_kind not in SKETCH_KINDS:
         raise ValueError("unknown weight or sketch kind")
+    if prm.follow_up not in FOLLOW_UPS:
+        raise ValueError("unknown follow-up kind")
 
 
 def cabs(spec, prm: Params, track: bool = False) -> Result:
@@ -385,15 +401,21 @@ def cabs(spec, prm: Params, track: bool = False) -> Result:
     p = uo * root
     q = vo * root
 
-    # Step 3: follow-up sampling by weighted k-means, then snapping.
+    # Step 3: follow-up sampling by weighted k-means, then snapping (or, in the
+    # hard-threshold variant of Section 5, the rows with the largest weights).
     w_r = upsilon(np.linalg.norm(p, axis=1), prm.weight_kind, prm.weight_param)
     w_c = upsilon(np.linalg.norm(q, axis=1), prm.weight_kind, prm.weight_param)
-    z0r = initial_centres(p, ir, prm.k2_rows, m, prm.seed, philox.STREAM_INIT_ROWS)
-    z0c = initial_centres(q, ic, prm.k2_cols, n, prm.seed, philox.STREAM_INIT_COLS)
-    km_r = weighted_kmeans(p, w_r, z0r, prm.kmeans_iters)
-    km_c = weighted_kmeans(q, w_c, z0c, prm.kmeans_iters)
-    jr = snap(p, km_r.Z)
-    jc = snap(q, km_c.Z)
+    if prm.follow_up == "hard":
+        km_r = km_c = None
+        jr = hard_threshold(w_r, prm.k2_rows)
+        jc = hard_threshold(w_c, prm.k2_cols)
+    else:
+        z0r = initial_centres(p, ir, prm.k2_rows, m, prm.seed, philox.STREAM_INIT_ROWS)
+        z0c = initial_centres(q, ic, prm.k2_cols, n, prm.seed, philox.STREAM_INIT_COLS)
+        km_r = weighted_kmeans(p, w_r, z0r, prm.kmeans_iters)
+        km_c = weighted_kmeans(q, w_c, z0c, prm.kmeans_iters)
+        jr = snap(p, km_r.Z)
+        jc = snap(q, km_c.Z)
 
     cb = mat.cols(jc)
     rtb = mat.rows_t(jr)

@@ -108,3 +108,35 @@ def test_sampled_error_against_brute_force_and_exact():
     assert exact == pytest.approx(np.linalg.norm(a - approx) / np.linalg.norm(a), rel=1e-12)
     big, _, _ = oc.rel_error_sampled(mat, res.C, res.Umid, res.Rt, 400_000, 22)
     assert big == pytest.approx(exact, rel=0.05)
+
+
+def test_hard_threshold_against_a_plain_sort():
+    rng = np.random.default_rng(4)
+    for m, k in [(1, 1), (10, 10), (50, 7), (300, 64)]:
+        w = np.round(rng.exponential(size=m), 1)  # rounded, so that many weights tie
+        got = oc.hard_threshold(w, k).tolist()
+        want = sorted(sorted(range(m), key=lambda i: (-w[i], i))[:k])
+        assert got == want
+    # constant weights: every row ties, so the first k rows
+    assert oc.hard_threshold(np.ones(20), 6).tolist() == list(range(6))
+    # a NaN weight ranks below every number
+    w = np.array([0.5, np.nan, 2.0, 0.1])
+    assert oc.hard_threshold(w, 3).tolist() == [0, 2, 3]
+
+
+def test_hard_threshold_follow_up_takes_the_largest_embedding_rows():
+    spec = workloads.exact_rank(90, 70, 6, seed=5)
+    prm = oc.Params.square(6, seed=3, weight_kind="pow", weight_param=2.0, follow_up="hard")
+    res = oc.cabs(spec, prm)
+    norms = np.linalg.norm(res.P, axis=1)
+    assert res.idx_r.tolist() == sorted(np.argsort(-norms, kind="stable")[:6].tolist())
+    assert res.km_r is None and res.km_c is None
+    # the chosen rows and columns feed the follow-up round: on an exact-rank input with a
+    # full-rank W the pseudo-skeleton form recovers A
+    res2 = oc.cabs(spec, oc.Params.square(6, seed=3, weight_kind="pow", weight_param=2.0, follow_up="hard",
+                                          sketch_kind="pseudo_skeleton"))
+    wb = res2.C[res2.idx_r, :]
+    assert np.linalg.matrix_rank(wb) == 6
+    assert oc.rel_error_exact(Matrix(spec), res2.C, res2.Umid, res2.Rt) < 1e-10
+    with pytest.raises(ValueError):
+        oc.cabs(spec, oc.Params.square(6, follow_up="nope"))
