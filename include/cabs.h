@@ -64,6 +64,14 @@ typedef enum {
  * (Section 3.2): 1, |p|^param, 1/(1+exp(-param |p|)), or [|p| >= param]. */
 typedef enum { CABS_W_CONST = 0, CABS_W_POW = 1, CABS_W_SIGMOID = 2, CABS_W_STEP = 3 } cabs_weight;
 
+/* Follow-up sampling (Algorithm 2, step 3).  KMEANS: weighted k-means on the
+ * pilot embeddings from the pilot sample, then each centre snapped to its
+ * nearest untaken row (Section 3.2).  HARD: the hard-threshold variant of
+ * Section 5: the k2 rows (columns) with the largest weights Upsilon(|P_l|),
+ * equal weights to the lower index, NaN weights last; no k-means, and the
+ * encoding-error diagnostics stay 0. */
+typedef enum { CABS_FOLLOW_KMEANS = 0, CABS_FOLLOW_HARD = 1 } cabs_follow_up;
+
 /* The sketching routine: the stabilised form of Section 4.1 (default), or the
  * pseudo-skeleton A ~ C W^+ R of Eq. (W), Section 2.2. */
 typedef enum { CABS_SK_STABILIZED = 0, CABS_SK_PSEUDO_SKELETON = 1 } cabs_sketch_kind;
@@ -109,6 +117,8 @@ typedef struct {
                             <= 0 selects max(kr, kc) * eps(FP64) */
   int32_t compute;       /* cabs_prec of entry evaluation, embeddings, distance GEMMs */
   int32_t want_factors;  /* 1: also produce the orthogonalised factor form (Uf, S, Vf) */
+  int32_t follow_up;     /* cabs_follow_up: how the follow-up rows and columns are chosen */
+  int32_t reserved;      /* must be 0 */
   uint64_t seed;         /* Philox key for every draw of the method */
 } cabs_params;
 

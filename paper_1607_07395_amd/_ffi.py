@@ -41,7 +41,8 @@ class CabsParams(C.Structure):
         ("k1_rows", C.c_int32), ("k1_cols", C.c_int32), ("k2_rows", C.c_int32), ("k2_cols", C.c_int32),
         ("kmeans_iters", C.c_int32), ("weight_kind", C.c_int32), ("weight_param", C.c_double),
         ("sketch_kind", C.c_int32), ("orthogonalize", C.c_int32), ("pinv_rtol", C.c_double),
-        ("compute", C.c_int32), ("want_factors", C.c_int32), ("seed", C.c_uint64),
+        ("compute", C.c_int32), ("want_factors", C.c_int32), ("follow_up", C.c_int32), ("reserved", C.c_int32),
+        ("seed", C.c_uint64),
     ]
 
 

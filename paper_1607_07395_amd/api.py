@@ -85,7 +85,7 @@ class DeviceMatrix:
 
 def make_params(k1_rows, k1_cols, k2_rows, k2_cols, kmeans_iters=5, weight="const", weight_param=0.0,
                 sketch="stabilized", orthogonalize=True, pinv_rtol=0.0, compute="f32", factors=False,
-                seed=0) -> F.CabsParams:
+                seed=0, follow_up="kmeans") -> F.CabsParams:
     p = F.CabsParams()
     p.k1_rows, p.k1_cols, p.k2_rows, p.k2_cols = k1_rows, k1_cols, k2_rows, k2_cols
     p.kmeans_iters = kmeans_iters
@@ -96,6 +96,7 @@ def make_params(k1_rows, k1_cols, k2_rows, k2_cols, kmeans_iters=5, weight="cons
     p.pinv_rtol = pinv_rtol
     p.compute = PREC[compute]
     p.want_factors = 1 if factors else 0
+    p.follow_up = {"kmeans": 0, "hard": 1}[follow_up]
     p.seed = seed
     return p
 

@@ -308,7 +308,7 @@ struct SketchWs {
   int64_t *Ir, *Ic, *Ir0, *Ic0;
   void *C, *Rt, *P, *Q;
   double *rowsqP, *rowsqQ, *wr, *wc, *Z0r, *Z0c, *Zr, *Zc, *diag, *obj;
-  void *kmr, *kmc;
+  void *kmr, *kmc, *selr, *selc;
   RoundWs r1, r2;
   double* sgn_ws;
 };
@@ -335,8 +335,15 @@ static size_t plan_sketch(void* ws, const Plan& pl, const cabs_params* prm, Sket
   S.Zc = cv.take<double>((size_t)pl.kc2 * e);
   S.diag = cv.take<double>(CABS_DIAG_LEN);
   S.obj = cv.take<double>(8);
-  S.kmr = cv.take_bytes(kmeans_ws_bytes(pl.m, e, pl.kr2, pl.prec));
-  S.kmc = cv.take_bytes(kmeans_ws_bytes(pl.n, e, pl.kc2, pl.prec));
+  if (prm->follow_up == CABS_FOLLOW_HARD) {
+    S.kmr = S.kmc = nullptr;
+    S.selr = cv.take_bytes(select_ws_bytes(pl.m));
+    S.selc = cv.take_bytes(select_ws_bytes(pl.n));
+  } else {
+    S.kmr = cv.take_bytes(kmeans_ws_bytes(pl.m, e, pl.kr2, pl.prec));
+    S.kmc = cv.take_bytes(kmeans_ws_bytes(pl.n, e, pl.kc2, pl.prec));
+    S.selr = S.selc = nullptr;
+  }
   plan_round(cv, S.r1, pl, pl.kr1, pl.kc1, true, prm->orthogonalize != 0);
   plan_round(cv, S.r2, pl, pl.kr2, pl.kc2, prm->want_factors != 0, prm->want_factors != 0);
   S.sgn_ws = prm->want_factors ? cv.take<double>((size_t)3 * 256 * pl.p2) : nullptr;
@@ -396,6 +403,11 @@ static cabs_status check_params(const cabs_matrix* mat, const cabs_params* prm) 
   if (prm->weight_kind < CABS_W_CONST || prm->weight_kind > CABS_W_STEP) return fail(CABS_EINVAL, "unknown weight kind");
   if (prm->sketch_kind != CABS_SK_STABILIZED && prm->sketch_kind != CABS_SK_PSEUDO_SKELETON)
     return fail(CABS_EINVAL, "unknown sketch kind");
+  if (prm->follow_up != CABS_FOLLOW_KMEANS && prm->follow_up != CABS_FOLLOW_HARD)
+    return fail(CABS_EINVAL, "unknown follow-up kind");
+  if (prm->reserved != 0) return fail(CABS_EINVAL, "reserved must be 0");
+  if (prm->follow_up == CABS_FOLLOW_HARD && (mat->m >= INT32_MAX || mat->n >= INT32_MAX))
+    return fail(CABS_EINVAL, "the hard-threshold selection needs m, n < 2^31 - 1");
   return CABS_OK;
 }
 
@@ -561,30 +573,37 @@ extern "C" cabs_status cabs_sketch(const cabs_matrix* mat, const cabs_params* pr
                      prm->weight_kind, prm->weight_param, S.wc);
   HIP_TRY(hipGetLastError());
 
-  // 7: weighted k-means from the pilot sample, then snapping
-  const int64_t* I0r = Ir;
-  const int64_t* I0c = Ic;
-  if (pl.kr2 > pl.kr1) {
-    HIP_TRY(launch_sample(pl.m, pl.kr2, prm->seed, STREAM_INIT_ROWS, S.Ir0, st));
-    I0r = S.Ir0;
+  // 7: follow-up sampling.  Hard-threshold variant (Section 5): the rows and
+  // columns with the largest weights.
+  if (prm->follow_up == CABS_FOLLOW_HARD) {
+    HIP_TRY(launch_select_topk(pl.m, S.wr, pl.kr2, out->idx_r, S.selr, st));
+    HIP_TRY(launch_select_topk(pl.n, S.wc, pl.kc2, out->idx_c, S.selc, st));
+  } else {
+    // Weighted k-means from the pilot sample, then snapping.
+    const int64_t* I0r = Ir;
+    const int64_t* I0c = Ic;
+    if (pl.kr2 > pl.kr1) {
+      HIP_TRY(launch_sample(pl.m, pl.kr2, prm->seed, STREAM_INIT_ROWS, S.Ir0, st));
+      I0r = S.Ir0;
+    }
+    if (pl.kc2 > pl.kc1) {
+      HIP_TRY(launch_sample(pl.n, pl.kc2, prm->seed, STREAM_INIT_COLS, S.Ic0, st));
+      I0c = S.Ic0;
+    }
+    HIP_TRY(launch_gather_rows_f64(S.P, pl.prec, e, I0r, pl.kr2, e, S.Z0r, st));
+    HIP_TRY(launch_gather_rows_f64(S.Q, pl.prec, e, I0c, pl.kc2, e, S.Z0c, st));
+    KMeansOut kr{S.Zr, nullptr, S.obj, diag + CABS_DIAG_TMAX_R, diag + CABS_DIAG_GAP_R, out->idx_r,
+                 diag + CABS_DIAG_SNAP_SCANS_R};
+    HIP_TRY(launch_kmeans(pl.m, e, pl.kr2, pl.prec, S.P, S.wr, S.Z0r, prm->kmeans_iters, kr, S.kmr, st));
+    KMeansOut kc{S.Zc, nullptr, S.obj + 2, diag + CABS_DIAG_TMAX_C, diag + CABS_DIAG_GAP_C, out->idx_c,
+                 diag + CABS_DIAG_SNAP_SCANS_C};
+    HIP_TRY(launch_kmeans(pl.n, e, pl.kc2, pl.prec, S.Q, S.wc, S.Z0c, prm->kmeans_iters, kc, S.kmc, st));
+    hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 0, diag + CABS_DIAG_ENC_R_PILOT);
+    hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 1, diag + CABS_DIAG_ENC_R_FINAL);
+    hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 2, diag + CABS_DIAG_ENC_C_PILOT);
+    hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 3, diag + CABS_DIAG_ENC_C_FINAL);
+    HIP_TRY(hipGetLastError());
   }
-  if (pl.kc2 > pl.kc1) {
-    HIP_TRY(launch_sample(pl.n, pl.kc2, prm->seed, STREAM_INIT_COLS, S.Ic0, st));
-    I0c = S.Ic0;
-  }
-  HIP_TRY(launch_gather_rows_f64(S.P, pl.prec, e, I0r, pl.kr2, e, S.Z0r, st));
-  HIP_TRY(launch_gather_rows_f64(S.Q, pl.prec, e, I0c, pl.kc2, e, S.Z0c, st));
-  KMeansOut kr{S.Zr, nullptr, S.obj, diag + CABS_DIAG_TMAX_R, diag + CABS_DIAG_GAP_R, out->idx_r,
-               diag + CABS_DIAG_SNAP_SCANS_R};
-  HIP_TRY(launch_kmeans(pl.m, e, pl.kr2, pl.prec, S.P, S.wr, S.Z0r, prm->kmeans_iters, kr, S.kmr, st));
-  KMeansOut kc{S.Zc, nullptr, S.obj + 2, diag + CABS_DIAG_TMAX_C, diag + CABS_DIAG_GAP_C, out->idx_c,
-               diag + CABS_DIAG_SNAP_SCANS_C};
-  HIP_TRY(launch_kmeans(pl.n, e, pl.kc2, pl.prec, S.Q, S.wc, S.Z0c, prm->kmeans_iters, kc, S.kmc, st));
-  hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 0, diag + CABS_DIAG_ENC_R_PILOT);
-  hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 1, diag + CABS_DIAG_ENC_R_FINAL);
-  hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 2, diag + CABS_DIAG_ENC_C_PILOT);
-  hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 3, diag + CABS_DIAG_ENC_C_FINAL);
-  HIP_TRY(hipGetLastError());
 
   // 8: follow-up evaluation and sketch
   HIP_TRY(launch_eval(mv, false, out->idx_c, pl.kc2, pl.prec, out->C, st));

@@ -39,6 +39,12 @@ hipError_t launch_eval(const MatView& mv, bool rows_t, const int64_t* idx, int k
 hipError_t launch_gather_rows_f64(const void* src, int compute, int64_t ld, const int64_t* idx, int k, int ncols,
                                   double* out, hipStream_t st);
 
+// --- hard-threshold follow-up selection (select.hip) ---
+// The k (1..1024) rows with the largest weights w (ties to the lower row, NaN last), written
+// ascending to out (device int64); rows < 2^31 - 1.
+size_t select_ws_bytes(int64_t rows);
+hipError_t launch_select_topk(int64_t rows, const double* w, int k, int64_t* out, void* ws, hipStream_t st);
+
 // --- FP64 small dense algebra (svd.hip, small.hip) ---
 size_t svd_ws_bytes(int batch, int rows, int cols);
 // Batched one-sided Jacobi SVD; A_b rows x cols row-major, strides in elements between batch items.

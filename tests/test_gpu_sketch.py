@@ -73,6 +73,34 @@ def _compare_f64(api, spec, kw, tol=1e-10):
     return mat, prm, res, ref
 
 
+@pytest.mark.parametrize("name,scale,k,wp,seed", [("rbf2000", 1.0, 50, 2.0, 1), ("lowrank1e5s", 0.05, 40, 1.0, 2),
+                                                  ("lowrank1e5s", 0.03, 64, 2.0, 4), ("rbf2000", 0.5, 30, 1.0, 3)])
+def test_sketch_f64_hard_threshold(api, name, scale, k, wp, seed):
+    """Hard-threshold follow-up (Section 5 variant) with POW weights: indices bit-exact with the
+    oracle (the k-th and (k+1)-th weights differ by > 1e-9 of the largest, so FP64 rounding on
+    either side cannot change the choice; 1000-5000 rows cover the LDS-only and the global merge
+    passes of the selection), the CUR product to 1e-10."""
+    spec, _ = workloads.config(name, scale)
+    kw = dict(k1_rows=k, k1_cols=k, k2_rows=k, k2_cols=k, seed=seed, weight="pow", weight_param=wp)
+    mat, prm, res = _run(api, spec, dict(kw, follow_up="hard"), "f64")
+    okw = _oracle_params(kw)
+    okw.follow_up = "hard"
+    ref = oc.cabs(spec, okw)
+    for w in (ref.w_r, ref.w_c):
+        s = np.sort(w)[::-1]
+        assert s[k - 1] - s[k] > 1e-9 * s[0]
+    d = res.diagnostics()
+    assert d["status"] == 0
+    assert np.array_equal(res.idx_r.cpu().numpy(), ref.idx_r)
+    assert np.array_equal(res.idx_c.cpu().numpy(), ref.idx_c)
+    assert d["enc_r_final"] == 0.0 and d["enc_c_final"] == 0.0
+    C, Rt, Umid = res.C.cpu().numpy(), res.Rt.cpu().numpy(), res.Umid.cpu().numpy()
+    i, j = philox.error_sample_indices(spec.m, spec.n, 20000, seed=98)
+    scale_a = np.sqrt(np.mean(Matrix(spec).entries(i, j) ** 2))
+    assert np.abs(_approx_at(C, Umid, Rt, i, j) - _approx_at(ref.C, ref.Umid, ref.Rt, i, j)).max() <= 1e-10 * scale_a
+    assert d["rank_final"] == int(ref.final.keep.sum())
+
+
 @pytest.mark.parametrize("scale,k,seed", [(0.1, 12, 0), (0.2, 20, 3), (0.137, 17, 5)])
 def test_sketch_f64_rbf_small(api, scale, k, seed):
     spec, _ = workloads.config("rbf2000", scale)
