@@ -446,8 +446,6 @@ static MatView view_of(const cabs_matrix* mat) {
   return v;
 }
 
-constexpr int K_FAST_SWEEPS = 9;
-
 // One sketching round on sampled C (m x kc), R^T (n x kr), W (kr x kc, FP64).
 // Computes the SVD of W, the norms and scalings; optionally the extrapolated
 // vectors C^, R^ and the orthogonalised embedding maps.
@@ -487,11 +485,7 @@ static cabs_status run_round(const Plan& pl, RoundWs& R, int kr, int kc, const v
     const double eps = 2.220446049250313e-16;
     HIP_TRY(launch_pchol(2, p, R.G2, pp, (double)p * eps, R.E2V, pp, st));
     HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, false, R.E2V + pp, p, true, nullptr, R.sk, nullptr, R.K, p, st));
-    // On the measured workloads the Jacobi iteration on K ends after 7-8 sweeps where the one
-    // on W takes 12; launching 9 sweeps round by round saves the launches of 3-5 sweeps that
-    // would only find the converged flag, and a K that needs more is finished by the
-    // single-workgroup kernel (same result, slower).
-    HIP_TRY(launch_svd(1, p, p, R.K, 0, R.Us, 0, R.S1, 0, R.Vs, 0, R.svd_ws, st, K_FAST_SWEEPS));
+    HIP_TRY(launch_svd(1, p, p, R.K, 0, R.Us, 0, R.S1, 0, R.Vs, 0, R.svd_ws, st));
     hipLaunchKernelGGL(rsqrt_trunc_kernel, dim3(1), dim3(1024), 0, st, p, R.S1, R.sq);
     hipLaunchKernelGGL(mul_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.invc, R.sk, R.fpos);
     hipLaunchKernelGGL(mul_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.invr, R.sk, R.fpos + p);
