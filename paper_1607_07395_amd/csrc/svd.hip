@@ -29,7 +29,8 @@ __host__ __device__ static inline int even_up(int p) { return p + (p & 1); }
 
 constexpr int BJ_B = 8;               // columns per block of the block-Jacobi path
 constexpr int BJ_MAX_SWEEPS = 40;
-constexpr int BJ_INNER_SWEEPS = 2;
+constexpr int BJ_INNER_SWEEPS = 1;   // inner sweeps per pair and round in the finishing kernel
+                                      // (one: more outer sweeps, each cheaper; 2 was slower)
 
 // Number of column blocks (even) and padded column count of the block-Jacobi path.
 __host__ __device__ static inline int bj_blocks(int p) { int nb = (p + BJ_B - 1) / BJ_B; return nb + (nb & 1); }
