@@ -145,6 +145,14 @@ __global__ void diag_mat_kernel(int p, const double* __restrict__ a, const doubl
   B[e] = i == j ? a[i] * (b ? (b[i] > 0.0 ? sqrt(b[i]) : 0.0) : 1.0) : 0.0;
 }
 
+// B (rows x cols) copied into Bp (rows x ldp), columns cols .. ldp - 1 zero.
+__global__ void pad_cols_kernel(int rows, int cols, int ldp, const double* __restrict__ B, double* __restrict__ Bp) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * ldp) return;
+  const int i = e / ldp, j = e % ldp;
+  Bp[e] = j < cols ? B[(int64_t)i * cols + j] : 0.0;
+}
+
 // Weights Upsilon(|P_l|) from squared row norms (Section 3.2).
 __global__ void weights_kernel(int64_t rows, const double* __restrict__ rowsq, int kind, double prm,
                                double* __restrict__ w) {
@@ -252,6 +260,7 @@ struct RoundWs {
 
 struct Plan {
   int prec, kr1, kc1, kr2, kc2, p1, p2;
+  int ep;  // columns of the stored embeddings P, Q: p1, padded to whole 16-byte runs in 16-bit compute
   int64_t m, n;
 };
 
@@ -308,6 +317,8 @@ struct SketchWs {
   int64_t *Ir, *Ic, *Ir0, *Ic0;
   void *C, *Rt, *P, *Q;
   double *rowsqP, *rowsqQ, *wr, *wc, *Z0r, *Z0c, *Zr, *Zc, *diag, *obj;
+  double *MuP, *MvP;  // the embedding maps with ep - p1 zero columns (16-bit compute, p1 not a multiple of 8)
+  void* ts6;
   void *kmr, *kmc, *selr, *selc;
   RoundWs r1, r2;
   double* sgn_ws;
@@ -316,23 +327,26 @@ struct SketchWs {
 static size_t plan_sketch(void* ws, const Plan& pl, const cabs_params* prm, SketchWs& S) {
   Carve cv(ws);
   const size_t eb = prec_bytes(pl.prec);
-  const int e = pl.p1;
+  const int e = pl.p1, ep = pl.ep;
   S.Ir = cv.take<int64_t>(pl.kr1);
   S.Ic = cv.take<int64_t>(pl.kc1);
   S.Ir0 = cv.take<int64_t>(std::max(pl.kr2, 1));
   S.Ic0 = cv.take<int64_t>(std::max(pl.kc2, 1));
   S.C = cv.take_bytes((size_t)pl.m * pl.kc1 * eb);
   S.Rt = cv.take_bytes((size_t)pl.n * pl.kr1 * eb);
-  S.P = cv.take_bytes((size_t)pl.m * e * eb);
-  S.Q = cv.take_bytes((size_t)pl.n * e * eb);
+  S.P = cv.take_bytes((size_t)pl.m * ep * eb);
+  S.Q = cv.take_bytes((size_t)pl.n * ep * eb);
   S.rowsqP = cv.take<double>(pl.m);
   S.rowsqQ = cv.take<double>(pl.n);
   S.wr = cv.take<double>(pl.m);
   S.wc = cv.take<double>(pl.n);
-  S.Z0r = cv.take<double>((size_t)pl.kr2 * e);
-  S.Z0c = cv.take<double>((size_t)pl.kc2 * e);
-  S.Zr = cv.take<double>((size_t)pl.kr2 * e);
-  S.Zc = cv.take<double>((size_t)pl.kc2 * e);
+  S.Z0r = cv.take<double>((size_t)pl.kr2 * ep);
+  S.Z0c = cv.take<double>((size_t)pl.kc2 * ep);
+  S.Zr = cv.take<double>((size_t)pl.kr2 * ep);
+  S.Zc = cv.take<double>((size_t)pl.kc2 * ep);
+  S.MuP = ep != e ? cv.take<double>((size_t)e * ep) : nullptr;
+  S.MvP = ep != e ? cv.take<double>((size_t)e * ep) : nullptr;
+  S.ts6 = ep != e ? cv.take_bytes(tsgemm_ws_bytes(std::max(pl.m, pl.n), e, ep, pl.prec)) : nullptr;
   S.diag = cv.take<double>(CABS_DIAG_LEN);
   S.obj = cv.take<double>(8);
   if (prm->follow_up == CABS_FOLLOW_HARD) {
@@ -340,8 +354,8 @@ static size_t plan_sketch(void* ws, const Plan& pl, const cabs_params* prm, Sket
     S.selr = cv.take_bytes(select_ws_bytes(pl.m));
     S.selc = cv.take_bytes(select_ws_bytes(pl.n));
   } else {
-    S.kmr = cv.take_bytes(kmeans_ws_bytes(pl.m, e, pl.kr2, pl.prec));
-    S.kmc = cv.take_bytes(kmeans_ws_bytes(pl.n, e, pl.kc2, pl.prec));
+    S.kmr = cv.take_bytes(kmeans_ws_bytes(pl.m, ep, pl.kr2, pl.prec));
+    S.kmc = cv.take_bytes(kmeans_ws_bytes(pl.n, ep, pl.kc2, pl.prec));
     S.selr = S.selc = nullptr;
   }
   plan_round(cv, S.r1, pl, pl.kr1, pl.kc1, true, prm->orthogonalize != 0);
@@ -420,6 +434,7 @@ static Plan make_plan(const cabs_matrix* mat, const cabs_params* prm) {
   pl.kc2 = prm->k2_cols;
   pl.p1 = std::min(pl.kr1, pl.kc1);
   pl.p2 = std::min(pl.kr2, pl.kc2);
+  pl.ep = (pl.prec == CABS_BF16 || pl.prec == CABS_F16) ? (pl.p1 + 7) / 8 * 8 : pl.p1;
   pl.m = mat->m;
   pl.n = mat->n;
   return pl;
@@ -537,7 +552,7 @@ extern "C" cabs_status cabs_sketch(const cabs_matrix* mat, const cabs_params* pr
   hipStream_t st = (hipStream_t)stream;
   const MatView mv = view_of(mat);
   double* diag = out->diag ? out->diag : S.diag;
-  const int e = pl.p1;
+  const int e = pl.p1, ep = pl.ep;
 
   const double entries = (double)pl.m * pl.kc1 + (double)pl.n * pl.kr1 - (double)pl.kr1 * pl.kc1 +
                          (double)pl.m * pl.kc2 + (double)pl.n * pl.kr2 - (double)pl.kr2 * pl.kc2;
@@ -559,8 +574,22 @@ extern "C" cabs_status cabs_sketch(const cabs_matrix* mat, const cabs_params* pr
   if (s != CABS_OK) return s;
 
   // 6: embeddings and weights
-  HIP_TRY(launch_tsgemm(pl.m, e, e, pl.prec, S.r1.Ch, S.r1.Mu, S.P, nullptr, S.rowsqP, S.r1.ts_ws, st));
-  HIP_TRY(launch_tsgemm(pl.n, e, e, pl.prec, S.r1.Rh, S.r1.Mv, S.Q, nullptr, S.rowsqQ, S.r1.ts_ws, st));
+  // In 16-bit compute with p1 not a multiple of 8 the embeddings get ep - p1 zero columns, so that
+  // their rows are whole 16-byte runs for the k-means kernels; zero columns add exact zeros to every
+  // distance, norm and centre.
+  const double* Mu = S.r1.Mu;
+  const double* Mv = S.r1.Mv;
+  void* ts6 = S.r1.ts_ws;
+  if (ep != e) {
+    const unsigned gp = (unsigned)ceil_div((int64_t)e * ep, 256);
+    hipLaunchKernelGGL(pad_cols_kernel, dim3(gp), dim3(256), 0, st, e, e, ep, S.r1.Mu, S.MuP);
+    hipLaunchKernelGGL(pad_cols_kernel, dim3(gp), dim3(256), 0, st, e, e, ep, S.r1.Mv, S.MvP);
+    Mu = S.MuP;
+    Mv = S.MvP;
+    ts6 = S.ts6;
+  }
+  HIP_TRY(launch_tsgemm(pl.m, e, ep, pl.prec, S.r1.Ch, Mu, S.P, nullptr, S.rowsqP, ts6, st));
+  HIP_TRY(launch_tsgemm(pl.n, e, ep, pl.prec, S.r1.Rh, Mv, S.Q, nullptr, S.rowsqQ, ts6, st));
   hipLaunchKernelGGL(weights_kernel, dim3((unsigned)ceil_div(pl.m, 256)), dim3(256), 0, st, pl.m, S.rowsqP,
                      prm->weight_kind, prm->weight_param, S.wr);
   hipLaunchKernelGGL(weights_kernel, dim3((unsigned)ceil_div(pl.n, 256)), dim3(256), 0, st, pl.n, S.rowsqQ,
@@ -584,14 +613,14 @@ extern "C" cabs_status cabs_sketch(const cabs_matrix* mat, const cabs_params* pr
       HIP_TRY(launch_sample(pl.n, pl.kc2, prm->seed, STREAM_INIT_COLS, S.Ic0, st));
       I0c = S.Ic0;
     }
-    HIP_TRY(launch_gather_rows_f64(S.P, pl.prec, e, I0r, pl.kr2, e, S.Z0r, st));
-    HIP_TRY(launch_gather_rows_f64(S.Q, pl.prec, e, I0c, pl.kc2, e, S.Z0c, st));
+    HIP_TRY(launch_gather_rows_f64(S.P, pl.prec, ep, I0r, pl.kr2, ep, S.Z0r, st));
+    HIP_TRY(launch_gather_rows_f64(S.Q, pl.prec, ep, I0c, pl.kc2, ep, S.Z0c, st));
     KMeansOut kr{S.Zr, nullptr, S.obj, diag + CABS_DIAG_TMAX_R, diag + CABS_DIAG_GAP_R, out->idx_r,
                  diag + CABS_DIAG_SNAP_SCANS_R};
-    HIP_TRY(launch_kmeans(pl.m, e, pl.kr2, pl.prec, S.P, S.wr, S.Z0r, prm->kmeans_iters, kr, S.kmr, st));
+    HIP_TRY(launch_kmeans(pl.m, ep, pl.kr2, pl.prec, S.P, S.wr, S.Z0r, prm->kmeans_iters, kr, S.kmr, st));
     KMeansOut kc{S.Zc, nullptr, S.obj + 2, diag + CABS_DIAG_TMAX_C, diag + CABS_DIAG_GAP_C, out->idx_c,
                  diag + CABS_DIAG_SNAP_SCANS_C};
-    HIP_TRY(launch_kmeans(pl.n, e, pl.kc2, pl.prec, S.Q, S.wc, S.Z0c, prm->kmeans_iters, kc, S.kmc, st));
+    HIP_TRY(launch_kmeans(pl.n, ep, pl.kc2, pl.prec, S.Q, S.wc, S.Z0c, prm->kmeans_iters, kc, S.kmc, st));
     hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 0, diag + CABS_DIAG_ENC_R_PILOT);
     hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 1, diag + CABS_DIAG_ENC_R_FINAL);
     hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 2, diag + CABS_DIAG_ENC_C_PILOT);

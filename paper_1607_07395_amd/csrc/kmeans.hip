@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256) void assign_kernel(int64_t rows, int dim, int 
   }
 }
 
-// Fast assignment for FP32 / BF16 / FP16, dim <= AF_KMAX and rows that are
+// Fast assignment for FP32 / BF16 / FP16, dim <= 256 (FP32) or 512 (16-bit) and rows that are
 // whole 16-byte runs (dim a multiple of 16 / sizeof(TC), P 16-byte aligned).
 // A workgroup (4 waves, 64 rows) keeps each wave's 16 rows as 16-byte MFMA
 // fragments in registers for the whole kernel, and streams the centres
@@ -166,7 +166,6 @@ __global__ __launch_bounds__(256) void assign_kernel(int64_t rows, int dim, int 
 // run-time guard (k blocks past dim read zeros and add exact zeros).  Per lane
 // the k blocks, MFMA steps and columns come in the same order as in
 // assign_kernel, so distances, labels and gaps are bit-identical to it.
-constexpr int AF_KMAX = 256;
 constexpr int AF_CT = 2;
 
 template <typename TC, int NKB>
@@ -278,14 +277,18 @@ __global__ __launch_bounds__(256, 3) void assign_fast_kernel(int64_t rows, int d
 }
 
 // Compiled k-block counts per type (the smallest one >= the needed count is used).
-template <typename TC> struct AfNkb { static constexpr int v[4] = {2, 4, 7, 8}; };  // 16-bit types
+// 16-bit types reach 512 dimensions (the 10^6-row RBF configuration's k = 500) in the same 64 registers of
+// row fragments that FP32 spends on 256.
+template <typename TC> struct AfNkb { static constexpr int v[5] = {2, 4, 7, 8, 16}; };  // 16-bit types
 template <> struct AfNkb<float> { static constexpr int v[4] = {4, 8, 13, 16}; };
+template <typename TC> constexpr int af_nkb_n() { return (int)(sizeof(AfNkb<TC>::v) / sizeof(int)); }
+template <typename TC> constexpr int af_dim_max() { return AfNkb<TC>::v[af_nkb_n<TC>() - 1] * 4 * (16 / (int)sizeof(TC)); }
 
 template <typename TC, int I>
 static void assign_fast_launch(int nkb, int64_t rows, int dim, int k, const TC* P, const TC* Zc, const double* znorm,
                                const double* pnorm, int32_t* labels, double* dmin, double* gap, hipStream_t st) {
   constexpr int NKB = AfNkb<TC>::v[I];
-  if constexpr (I < 3) {
+  if constexpr (I + 1 < af_nkb_n<TC>()) {
     if (nkb > NKB)
       return assign_fast_launch<TC, I + 1>(nkb, rows, dim, k, P, Zc, znorm, pnorm, labels, dmin, gap, st);
   }
@@ -302,7 +305,7 @@ static void launch_assign(int64_t rows, int dim, int k, const TC* P, const TC* Z
                           const double* pnorm, int32_t* labels, double* dmin, double* gap, hipStream_t st) {
   if constexpr (AssignFast<TC>::ok) {
     constexpr int VE = 16 / (int)sizeof(TC);
-    if (dim <= AF_KMAX && dim % VE == 0 && ((uintptr_t)P % 16) == 0 && ((uintptr_t)Zc % 16) == 0) {
+    if (dim <= af_dim_max<TC>() && dim % VE == 0 && ((uintptr_t)P % 16) == 0 && ((uintptr_t)Zc % 16) == 0) {
       const int nkb = (dim + 4 * VE - 1) / (4 * VE);
       assign_fast_launch<TC, 0>(nkb, rows, dim, k, P, Zc, znorm, pnorm, labels, dmin, gap, st);
       return;

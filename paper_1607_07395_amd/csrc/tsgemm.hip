@@ -87,14 +87,13 @@ __global__ __launch_bounds__(256) void tsgemm_kernel(int64_t M, int K, int N, co
   }
 }
 
-// Fast path for K <= TSF_KMAX, rows of X and B^T whole 16-byte runs (K a
+// Fast path for K <= 256 (512 for 16-bit types), rows of X and B^T whole 16-byte runs (K a
 // multiple of 16 / sizeof(TC), X 16-byte aligned): a workgroup (4 waves, 64 rows) keeps its rows
 // of X as 16-byte MFMA fragment runs in registers for the whole kernel and
 // streams B^T through LDS in chunks of CT column tiles, stored in fragment
 // order (each B read is one contiguous 16-byte LDS read per lane); the next
 // chunk is loaded into registers while the current one is multiplied.  Same
 // outputs as tsgemm_kernel (Y, FP64 row and per-block column sums of squares).
-constexpr int TSF_KMAX = 256;
 template <typename TC> struct TsfCT { static constexpr int v = 2; };
 template <> struct TsfCT<double> { static constexpr int v = 1; };
 
@@ -222,14 +221,16 @@ __global__ __launch_bounds__(256, TsfOcc<TC>::v) void tsgemm_fast_kernel(int64_t
 template <typename TC> struct TsfNkb;
 template <> struct TsfNkb<float> { static constexpr int v[4] = {4, 8, 13, 16}; };
 template <> struct TsfNkb<double> { static constexpr int v[4] = {8, 16, 25, 32}; };
-template <> struct TsfNkb<bf16> { static constexpr int v[4] = {2, 4, 7, 8}; };
-template <> struct TsfNkb<f16> { static constexpr int v[4] = {2, 4, 7, 8}; };
+template <> struct TsfNkb<bf16> { static constexpr int v[5] = {2, 4, 7, 8, 16}; };  // to K = 512
+template <> struct TsfNkb<f16> { static constexpr int v[5] = {2, 4, 7, 8, 16}; };
+template <typename TC> constexpr int tsf_nkb_n() { return (int)(sizeof(TsfNkb<TC>::v) / sizeof(int)); }
+template <typename TC> constexpr int tsf_k_max() { return TsfNkb<TC>::v[tsf_nkb_n<TC>() - 1] * 4 * (16 / (int)sizeof(TC)); }
 
 template <typename TC, int I>
 static void tsf_launch_i(int nkb, dim3 grid, hipStream_t st, int64_t M, int K, int N, const TC* X, const TC* Bt, TC* Y,
                          double* colpart, double* rowsq) {
   constexpr int NKB = TsfNkb<TC>::v[I];
-  if constexpr (I < 3) {
+  if constexpr (I + 1 < tsf_nkb_n<TC>()) {
     if (nkb > NKB) return tsf_launch_i<TC, I + 1>(nkb, grid, st, M, K, N, X, Bt, Y, colpart, rowsq);
   }
   hipLaunchKernelGGL((tsgemm_fast_kernel<TC, NKB>), grid, dim3(256), tsf_lds_bytes<TC>(NKB, N), st, M, K, N, X, Bt, Y,
@@ -282,7 +283,7 @@ static hipError_t tsgemm_t(int64_t M, int K, int N, const void* X, const double*
   double* part = (double*)((char*)ws + align256((size_t)K * N * sizeof(TC)));
   hipLaunchKernelGGL(convert_bt_kernel<TC>, dim3((unsigned)ceil_div((int64_t)K * N, 256)), dim3(256), 0, st, K, N, B, Bt);
   const int64_t nb = ceil_div(M, 64);
-  if (K <= TSF_KMAX && ((size_t)K * sizeof(TC)) % 16 == 0 && ((uintptr_t)X % 16) == 0) {
+  if (K <= tsf_k_max<TC>() && ((size_t)K * sizeof(TC)) % 16 == 0 && ((uintptr_t)X % 16) == 0) {
     const int nkb = (int)ceil_div(K, 4 * (16 / (int)sizeof(TC)));
     tsf_launch_i<TC, 0>(nkb, dim3((unsigned)nb), st, M, K, N, (const TC*)X, Bt, (TC*)Y, colsq ? part : nullptr, rowsq);
   } else {

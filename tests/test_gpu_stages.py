@@ -226,3 +226,26 @@ def test_kmeans_f32_decisions_match_in_f32(api):
     sure = gap > 1e-5 * scale
     assert np.array_equal(lab[sure], ref[sure])
     assert np.all(dist[~sure, lab[~sure]] - dist.min(1)[~sure] <= 1e-5 * scale[~sure])
+
+
+@pytest.mark.parametrize("dim,dt", [(320, "bf16"), (512, "bf16"), (512, "f16")])
+def test_kmeans_wide_16bit_fast_path_matches_generic(api, dim, dt):
+    """16-bit k-means with 257-512 dimensions (the fast assignment kernel's 16 k-block case)
+    against the generic kernel on the same values: a copy starting 2 bytes past a 16-byte
+    boundary takes the generic path.  The two keep the same per-lane k order, so labels,
+    centres, objective and snapped rows are bit-identical."""
+    dtype = {"bf16": torch.bfloat16, "f16": torch.float16}[dt]
+    rng = np.random.default_rng(dim)
+    rows = 4000
+    p = rng.normal(size=(rows, dim)).astype(np.float32)
+    z0 = torch.from_numpy(p[:48].astype(np.float64)).cuda()
+    w = torch.ones(rows, dtype=torch.float64, device="cuda")
+    pa = torch.from_numpy(p).to(dtype).cuda()
+    buf = torch.empty(rows * dim + 1, dtype=dtype, device="cuda")
+    pm = buf[1:].view(rows, dim)
+    pm.copy_(pa)
+    assert pa.data_ptr() % 16 == 0 and pm.data_ptr() % 16 != 0
+    fast = api.kmeans(pa, w, z0, 3)
+    gen = api.kmeans(pm, w, z0, 3)
+    for a, b in zip(fast, gen):
+        assert torch.equal(a, b)
