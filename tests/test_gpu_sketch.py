@@ -74,12 +74,14 @@ def _compare_f64(api, spec, kw, tol=1e-10):
 
 
 @pytest.mark.parametrize("name,scale,k,wp,seed", [("rbf2000", 1.0, 50, 2.0, 1), ("lowrank1e5s", 0.05, 40, 1.0, 2),
-                                                  ("lowrank1e5s", 0.03, 64, 2.0, 4), ("rbf2000", 0.5, 30, 1.0, 3)])
+                                                  ("lowrank1e5s", 0.03, 64, 2.0, 4), ("rbf2000", 0.5, 30, 1.0, 3),
+                                                  ("lowrank1e5s", 1.0, 24, 2.0, 5)])
 def test_sketch_f64_hard_threshold(api, name, scale, k, wp, seed):
     """Hard-threshold follow-up (Section 5 variant) with POW weights: indices bit-exact with the
     oracle (the k-th and (k+1)-th weights differ by > 1e-9 of the largest, so FP64 rounding on
-    either side cannot change the choice; 1000-5000 rows cover the LDS-only and the global merge
-    passes of the selection), the CUR product to 1e-10."""
+    either side cannot change the choice; 1000-5000 rows cover the LDS-only and the first global
+    merge passes of the selection, 10^5 rows (padded to 2^17) six levels of them), the CUR
+    product to 1e-10."""
     spec, _ = workloads.config(name, scale)
     kw = dict(k1_rows=k, k1_cols=k, k2_rows=k, k2_cols=k, seed=seed, weight="pow", weight_param=wp)
     mat, prm, res = _run(api, spec, dict(kw, follow_up="hard"), "f64")
