@@ -120,6 +120,21 @@ __device__ __forceinline__ void tile_run_vec(const TIn* p, int k, bool ok, TIn (
 #pragma unroll
   for (int q = 0; q < LK; ++q) v[q] = e[q];
 }
+// 16-bit elements in 8-byte pieces of four, for rows whose leading dimension
+// and K are multiples of 4 (8-byte aligned bases): each piece lies wholly
+// inside K or wholly outside (then it reads zeros), with the same values as
+// tile_run_elem and a quarter of its loads.
+template <typename TIn, int LK>
+__device__ __forceinline__ void tile_run_h8(const TIn* p, int k, int K, bool ok, TIn (&v)[LK]) {
+  static_assert(sizeof(TIn) == 2 && LK % 4 == 0, "8-byte pieces of four 16-bit elements");
+  uint2 w[LK / 4];
+#pragma unroll
+  for (int q = 0; q < LK / 4; ++q)
+    w[q] = *(const uint2*)((ok && k + 4 * q < K) ? p + k + 4 * q : (const TIn*)kTileZero);
+  const TIn* e = (const TIn*)w;
+#pragma unroll
+  for (int q = 0; q < LK; ++q) v[q] = e[q];
+}
 template <typename TIn, int LK>
 __device__ __forceinline__ void tile_run_elem(const TIn* p, int k, int K, bool ok, TIn (&v)[LK]) {
 #pragma unroll
@@ -166,6 +181,9 @@ __device__ __forceinline__ void gemm_tile(const TIn* __restrict__ X, int64_t ldx
   if (WANT_SQ) xsq = 0;
   const bool vec = VEC_OK && (ldx % LK) == 0 && (ldy % LK) == 0 && (((uintptr_t)X | (uintptr_t)Y) & 15) == 0 &&
                    (ys == nullptr || ((uintptr_t)ys & 15) == 0);
+  constexpr bool H8_OK = sizeof(TIn) == 2 && LK % 4 == 0;
+  const bool h8 = H8_OK && (ldx % 4) == 0 && (ldy % 4) == 0 && (K % 4) == 0 &&
+                  (((uintptr_t)X | (uintptr_t)Y) & 7) == 0 && (ys == nullptr || ((uintptr_t)ys & 7) == 0);
   auto fetch = [&](int kb, TIn (&xv)[LK], TIn (&yv)[NT][LK], TIn (&sv)[LK]) {
     const int k = kb + g * LK;
     if (vec && kb + 4 * LK <= K) {
@@ -174,6 +192,13 @@ __device__ __forceinline__ void gemm_tile(const TIn* __restrict__ X, int64_t ldx
 #pragma unroll
         for (int t = 0; t < NT; ++t) tile_run_vec<TIn, LK>(yp[t], k, yok[t], yv[t]);
         if (ys != nullptr) tile_run_vec<TIn, LK>(ys, k, true, sv);
+      }
+    } else if (h8) {
+      if constexpr (H8_OK) {
+        tile_run_h8<TIn, LK>(xp, k, K, xok, xv);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) tile_run_h8<TIn, LK>(yp[t], k, K, yok[t], yv[t]);
+        if (ys != nullptr) tile_run_h8<TIn, LK>(ys, k, K, true, sv);
       }
     } else {
       tile_run_elem<TIn, LK>(xp, k, K, xok, xv);

@@ -228,12 +228,13 @@ def test_kmeans_f32_decisions_match_in_f32(api):
     assert np.all(dist[~sure, lab[~sure]] - dist.min(1)[~sure] <= 1e-5 * scale[~sure])
 
 
-@pytest.mark.parametrize("dim,dt", [(320, "bf16"), (512, "bf16"), (512, "f16")])
+@pytest.mark.parametrize("dim,dt", [(320, "bf16"), (512, "bf16"), (512, "f16"), (20, "bf16"), (36, "f16")])
 def test_kmeans_wide_16bit_fast_path_matches_generic(api, dim, dt):
-    """16-bit k-means with 257-512 dimensions (the fast assignment kernel's 16 k-block case)
-    against the generic kernel on the same values: a copy starting 2 bytes past a 16-byte
-    boundary takes the generic path.  The two keep the same per-lane k order, so labels,
-    centres, objective and snapped rows are bit-identical."""
+    """16-bit k-means against the element-load path on the same values (a copy starting 2 bytes
+    past a 16-byte boundary loads element by element).  257-512 dimensions: the fast assignment
+    kernel's 16 k-block case; 20 and 36 dimensions (multiples of 4, not of 8): the tile kernels'
+    8-byte pieces.  All keep the same per-lane k order, so labels, centres, objective and
+    snapped rows are bit-identical."""
     dtype = {"bf16": torch.bfloat16, "f16": torch.float16}[dt]
     rng = np.random.default_rng(dim)
     rows = 4000
