@@ -214,12 +214,13 @@ size_t cabs_svd_workspace_bytes(int32_t batch, int32_t rows, int32_t cols);
 cabs_status cabs_svd(int32_t batch, int32_t rows, int32_t cols, const double* A, double* U, double* S, double* V,
                      void* ws, size_t ws_bytes, void* stream);
 /* cabs_svd with the split of the Jacobi sweeps chosen by the caller: the first
- * fast_sweeps (1 .. 12; cabs_svd uses 12) run as one launch per round over many
- * work-groups, the rest, if the iteration has not ended, in one work-group.
- * Every split meets the same convergence test and accuracy (the single
- * work-group applies its rotations in another grouping, so factors can differ
- * at the rounding level); a small value saves launches on matrices known to
- * converge in few sweeps.  Out-of-range fast_sweeps: CABS_EINVAL. */
+ * fast_sweeps (1 .. 24) run as one launch per round over many work-groups, the
+ * rest, if the iteration has not ended, in one work-group.  fast_sweeps = 0 is
+ * cabs_svd's choice: 12 up to min(rows, cols) = 256, 24 above.  Every split
+ * meets the same convergence test and accuracy (the single work-group applies
+ * its rotations in another grouping, so factors can differ at the rounding
+ * level); a small value saves launches on matrices known to converge in few
+ * sweeps.  Out-of-range fast_sweeps: CABS_EINVAL. */
 cabs_status cabs_svd_ex(int32_t batch, int32_t rows, int32_t cols, const double* A, double* U, double* S, double* V,
                         void* ws, size_t ws_bytes, int32_t fast_sweeps, void* stream);
 

@@ -758,7 +758,7 @@ extern "C" cabs_status cabs_svd_ex(int32_t batch, int32_t rows, int32_t cols, co
                                    double* V, void* ws, size_t ws_bytes, int32_t fast_sweeps, void* stream) {
   if (batch <= 0 || rows <= 0 || cols <= 0 || rows > 1024 || cols > 1024)
     return fail(CABS_EINVAL, "need batch > 0 and 0 < rows, cols <= 1024");
-  if (fast_sweeps < 1 || fast_sweeps > 12) return fail(CABS_EINVAL, "need 1 <= fast_sweeps <= 12");
+  if (fast_sweeps < 0 || fast_sweeps > 24) return fail(CABS_EINVAL, "need 0 <= fast_sweeps <= 24");
   if (!A || !U || !S || !V || !ws) return fail(CABS_EINVAL, "null pointer");
   if (ws_bytes < svd_ws_bytes(batch, rows, cols)) return fail(CABS_ENOMEM, "workspace too small");
   const int64_t p = rows < cols ? rows : cols;
@@ -769,7 +769,7 @@ extern "C" cabs_status cabs_svd_ex(int32_t batch, int32_t rows, int32_t cols, co
 
 extern "C" cabs_status cabs_svd(int32_t batch, int32_t rows, int32_t cols, const double* A, double* U, double* S,
                                 double* V, void* ws, size_t ws_bytes, void* stream) {
-  return cabs_svd_ex(batch, rows, cols, A, U, S, V, ws, ws_bytes, 12, stream);
+  return cabs_svd_ex(batch, rows, cols, A, U, S, V, ws, ws_bytes, 0, stream);
 }
 
 extern "C" size_t cabs_kmeans_workspace_bytes(int64_t rows, int32_t dim, int32_t k, int32_t compute) {

@@ -48,10 +48,11 @@ hipError_t launch_select_topk(int64_t rows, const double* w, int k, int64_t* out
 // --- FP64 small dense algebra (svd.hip, small.hip) ---
 size_t svd_ws_bytes(int batch, int rows, int cols);
 // Batched one-sided Jacobi SVD; A_b rows x cols row-major, strides in elements between batch items.
-// fast_sweeps (1 .. 12): sweeps launched round by round before the single-workgroup finisher.
+// fast_sweeps (1 .. 24): sweeps launched round by round before the single-workgroup finisher;
+// 0: 12 up to min(rows, cols) = 256, 24 above.
 hipError_t launch_svd(int batch, int rows, int cols, const double* A, int64_t strideA, double* U, int64_t strideU,
                       double* S, int64_t strideS, double* V, int64_t strideV, void* ws, hipStream_t st,
-                      int fast_sweeps = 12);
+                      int fast_sweeps = 0);
 
 // C (M x N) = alpha * op(A) diag(dl) ... : general small FP64 product
 //   C = diag(dl) * op(A) * diag(dm) * op(B) * diag(dr)   (any diag pointer may be null)

@@ -227,7 +227,11 @@ __global__ __launch_bounds__(SVD_THREADS) void svd_jacobi_kernel(int rows, int c
 // converged) and writes the outputs.
 // X (q x P) and V (P x P) are row-major in the workspace.
 // ---------------------------------------------------------------------------
-constexpr int BJ_FAST_SWEEPS = 12;
+constexpr int BJ_FAST_SWEEPS = 24;  // most sweeps launched round by round
+// The default split: 12 sweeps up to p = 256 (where the finisher's sweeps cost about twice the
+// round-by-round ones), 24 above (where a finisher sweep on one work-group costs several times a
+// round-by-round sweep, and a round that only finds the converged flag costs one launch).
+static inline int bj_default_fast_sweeps(int p) { return p > 256 ? 24 : 12; }
 
 __device__ __forceinline__ int circle_pos(int pos, int round, int n) {
   return pos == 0 ? 0 : 1 + (pos - 1 + round) % (n - 1);
@@ -858,6 +862,7 @@ hipError_t launch_svd(int batch, int rows, int cols, const double* A, int64_t st
                       double* S, int64_t strideS, double* V, int64_t strideV, void* ws, hipStream_t st,
                       int fast_sweeps) {
   if (batch <= 0 || rows <= 0 || cols <= 0 || rows > 1024 || cols > 1024) return hipErrorInvalidValue;
+  if (fast_sweeps == 0) fast_sweeps = bj_default_fast_sweeps(rows < cols ? rows : cols);
   if (fast_sweeps < 1 || fast_sweeps > BJ_FAST_SWEEPS) return hipErrorInvalidValue;
   const size_t p = rows < cols ? rows : cols, q = rows < cols ? cols : rows;
   const size_t lds_bytes = (q * p + p * p) * sizeof(double);

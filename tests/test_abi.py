@@ -84,8 +84,8 @@ def test_entry_points_reject_bad_arguments_without_launching():
     assert lib.cabs_sample(10, 11, 0, 0, C.c_void_p(0x1000), None) == F.EINVAL
     assert lib.cabs_sample(10, 3, 0, 0, None, None) == F.EINVAL
     assert lib.cabs_svd(1, 2000, 3, None, None, None, None, None, 0, None) == F.EINVAL
-    assert lib.cabs_svd_ex(1, 50, 50, None, None, None, None, None, 0, 0, None) == F.EINVAL
-    assert lib.cabs_svd_ex(1, 50, 50, None, None, None, None, None, 0, 13, None) == F.EINVAL
+    assert lib.cabs_svd_ex(1, 50, 50, None, None, None, None, None, 0, -1, None) == F.EINVAL
+    assert lib.cabs_svd_ex(1, 50, 50, None, None, None, None, None, 0, 25, None) == F.EINVAL
     assert lib.cabs_kmeans(10, 3, 11, F.F32, None, None, None, 1, None, None, None, None, None, 0, None) == F.EINVAL
     assert lib.cabs_svd_workspace_bytes(1, 50, 50) > 0
     assert lib.cabs_kmeans_workspace_bytes(10_000, 50, 50, F.F32) > 0
