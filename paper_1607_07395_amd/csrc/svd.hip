@@ -868,7 +868,7 @@ hipError_t launch_svd(int batch, int rows, int cols, const double* A, int64_t st
   const size_t lds_bytes = (q * p + p * p) * sizeof(double);
   const int use_lds = lds_bytes <= (size_t)SVD_LDS_BYTES ? 1 : 0;
   TimerScope ts(T_SVD, st);
-  if (use_lds || p < 24) {
+  if (p < 24) {
     hipLaunchKernelGGL(svd_jacobi_kernel, dim3(batch), dim3(SVD_THREADS), use_lds ? lds_bytes : 0, st, rows, cols,
                        A, strideA, U, strideU, S, strideS, V, strideV, (double*)ws, use_lds);
     return hipGetLastError();
