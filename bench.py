@@ -18,6 +18,10 @@ Two timed phases over the same workload:
     server, closed loop with --slots requests in flight; `value` is this
     whole-job throughput and p50/p99 are its submit-to-completion latencies.
 Also prints the FP64 CPU oracle timed on a bounded sample of the same workload.
+
+`--stream` replaces all of this with the serving stream of uneven requests
+(closed-loop maximum, then Poisson arrivals at fractions of it, p50/p99 from
+arrival to completion); `--config NAME` times another workload.
 """
 from __future__ import annotations
 
