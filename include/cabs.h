@@ -118,9 +118,14 @@ typedef struct {
   int32_t compute;       /* cabs_prec of entry evaluation, embeddings, distance GEMMs */
   int32_t want_factors;  /* 1: also produce the orthogonalised factor form (Uf, S, Vf) */
   int32_t follow_up;     /* cabs_follow_up: how the follow-up rows and columns are chosen */
-  int32_t reserved;      /* must be 0 */
+  int32_t flags;         /* CABS_FLAG_* bits; all others must be 0 */
   uint64_t seed;         /* Philox key for every draw of the method */
 } cabs_params;
+
+/* cabs_params.flags.  COUNT_ENTRIES: the entry-evaluation kernels count, on
+ * the device, every entry of A they evaluate or read (one integer atomic per
+ * wavefront; a debugging aid, off by default) into CABS_DIAG_ENTRIES. */
+enum { CABS_FLAG_COUNT_ENTRIES = 1 };
 
 /* Diagnostic slots written to cabs_result.diag (doubles). */
 enum {
@@ -133,7 +138,11 @@ enum {
   CABS_DIAG_TMAX_C = 6,
   CABS_DIAG_RANK_PILOT = 7,    /* kept components of the pilot sketch */
   CABS_DIAG_RANK_FINAL = 8,
-  CABS_DIAG_ENTRIES = 9,       /* distinct entries of A read, summed over both rounds */
+  CABS_DIAG_ENTRIES = 9,       /* with CABS_FLAG_COUNT_ENTRIES: entries of A evaluated over both rounds,
+                                  counted on the device (m k_c + n k_r per round; the k_r x k_c entries
+                                  of W are evaluated twice, once in C and once in R^T, so the distinct
+                                  entries touched are this minus k1_rows k1_cols + k2_rows k2_cols);
+                                  -1 when not counted */
   CABS_DIAG_GAP_R = 10,        /* smallest nearest/second-nearest centre gap, final assignment */
   CABS_DIAG_GAP_C = 11,
   CABS_DIAG_SIGMA1_PILOT = 12, /* largest singular value of W, pilot and follow-up */
@@ -263,13 +272,26 @@ cabs_server* cabs_server_create(int32_t device, size_t hbm_budget_bytes, int32_t
  * (cabs_error with err_samples and err_seed, result {num, den, ratio} into the
  * device array err_out3; err_out3 = NULL requests no error estimate).  `mat`
  * and `prm` are copied; the device buffers they and `out` name, and err_out3,
- * must stay valid until the request completes or is cancelled.  The request is admitted when a slot
- * is free and its workspace (the larger of the sketch's and the error's; the
- * error runs after the sketch on the same stream and reuses it) fits in the
- * pool; a request that can never fit is rejected here with CABS_ENOMEM, a
- * negative err_samples with CABS_EINVAL.  *ticket identifies it. */
+ * must stay valid until the request completes or is cancelled.
+ * Ordering: an event is recorded on `stream` (the caller's stream; NULL = the
+ * default stream) during this call, and the request's first kernel waits for
+ * it, so everything the caller enqueued on `stream` before submitting (writing
+ * the tables, clearing err_out3, reusing freed memory) is complete before the
+ * request touches those buffers.  Work the caller enqueues later is not
+ * ordered with the request: read the outputs only after cabs_poll reports it
+ * finished.
+ * Admission: a request is admitted when a slot is free and its workspace (the
+ * larger of the sketch's and the error's; the error runs after the sketch on
+ * the same stream and reuses it) fits in the pool.  Requests are considered
+ * in arrival order, but one that does not fit yet may be passed by later
+ * requests, at most 4 * max_slots times; after that nothing behind it is
+ * admitted until it fits.  A request that can never fit is rejected here with
+ * CABS_ENOMEM, a negative err_samples with CABS_EINVAL.  *ticket identifies it.
+ * If a launch fails after some of the request's kernels were enqueued, its
+ * workspace stays reserved until those kernels have finished, and cabs_poll
+ * then returns the error. */
 cabs_status cabs_submit(cabs_server* srv, const cabs_matrix* mat, const cabs_params* prm, const cabs_result* out,
-                        int64_t err_samples, uint64_t err_seed, double* err_out3, uint64_t* ticket);
+                        int64_t err_samples, uint64_t err_seed, double* err_out3, void* stream, uint64_t* ticket);
 
 /* CABS_OK when finished (latency_s, host, may be NULL: submit-to-completion
  * seconds), CABS_EBUSY while queued or running, CABS_ECANCELED if cancelled,

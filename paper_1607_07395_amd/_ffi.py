@@ -19,6 +19,7 @@ F64, F32, BF16, F16 = 0, 1, 2, 3
 SRC_DENSE, SRC_LOWRANK, SRC_RBF = 0, 1, 2
 W_CONST, W_POW, W_SIGMOID, W_STEP = 0, 1, 2, 3
 SK_STABILIZED, SK_PSEUDO_SKELETON = 0, 1
+FLAG_COUNT_ENTRIES = 1
 
 DIAG_STATUS, DIAG_ENC_R_PILOT, DIAG_ENC_C_PILOT, DIAG_ENC_R_FINAL, DIAG_ENC_C_FINAL = 0, 1, 2, 3, 4
 DIAG_TMAX_R, DIAG_TMAX_C, DIAG_RANK_PILOT, DIAG_RANK_FINAL, DIAG_ENTRIES = 5, 6, 7, 8, 9
@@ -41,7 +42,7 @@ class CabsParams(C.Structure):
         ("k1_rows", C.c_int32), ("k1_cols", C.c_int32), ("k2_rows", C.c_int32), ("k2_cols", C.c_int32),
         ("kmeans_iters", C.c_int32), ("weight_kind", C.c_int32), ("weight_param", C.c_double),
         ("sketch_kind", C.c_int32), ("orthogonalize", C.c_int32), ("pinv_rtol", C.c_double),
-        ("compute", C.c_int32), ("want_factors", C.c_int32), ("follow_up", C.c_int32), ("reserved", C.c_int32),
+        ("compute", C.c_int32), ("want_factors", C.c_int32), ("follow_up", C.c_int32), ("flags", C.c_int32),
         ("seed", C.c_uint64),
     ]
 
@@ -77,7 +78,7 @@ _SIGS = {
     "cabs_timing_reset": (None, []),
     "cabs_server_create": (_P, [C.c_int32, C.c_size_t, C.c_int32]),
     "cabs_submit": (C.c_int, [_P, C.POINTER(CabsMatrix), C.POINTER(CabsParams), C.POINTER(CabsResult),
-                              C.c_int64, C.c_uint64, _P, C.POINTER(C.c_uint64)]),
+                              C.c_int64, C.c_uint64, _P, _P, C.POINTER(C.c_uint64)]),
     "cabs_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(C.c_double)]),
     "cabs_cancel": (C.c_int, [_P, C.c_uint64]),
     "cabs_server_drain": (C.c_int, [_P]),

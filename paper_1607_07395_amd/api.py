@@ -85,7 +85,7 @@ class DeviceMatrix:
 
 def make_params(k1_rows, k1_cols, k2_rows, k2_cols, kmeans_iters=5, weight="const", weight_param=0.0,
                 sketch="stabilized", orthogonalize=True, pinv_rtol=0.0, compute="f32", factors=False,
-                seed=0, follow_up="kmeans") -> F.CabsParams:
+                seed=0, follow_up="kmeans", count_entries=False) -> F.CabsParams:
     p = F.CabsParams()
     p.k1_rows, p.k1_cols, p.k2_rows, p.k2_cols = k1_rows, k1_cols, k2_rows, k2_cols
     p.kmeans_iters = kmeans_iters
@@ -97,6 +97,7 @@ def make_params(k1_rows, k1_cols, k2_rows, k2_cols, kmeans_iters=5, weight="cons
     p.compute = PREC[compute]
     p.want_factors = 1 if factors else 0
     p.follow_up = {"kmeans": 0, "hard": 1}[follow_up]
+    p.flags = F.FLAG_COUNT_ENTRIES if count_entries else 0
     p.seed = seed
     return p
 
@@ -300,9 +301,11 @@ class Server:
         self._live = {}
 
     def submit(self, mat: DeviceMatrix, prm: F.CabsParams, out: SketchResult, err_samples: Optional[int] = None,
-               err_seed: int = 0, err_out: Optional[torch.Tensor] = None) -> int:
+               err_seed: int = 0, err_out: Optional[torch.Tensor] = None, stream=None) -> int:
         """Queue a sketch into `out`; with err_samples set, also its relative
-        Frobenius error into err_out (3 float64 on the device: num, den, ratio)."""
+        Frobenius error into err_out (3 float64 on the device: num, den, ratio).
+        The request runs after the work already enqueued on `stream` (default:
+        torch's current stream)."""
         t = C.c_uint64(0)
         p3 = None
         if err_samples is not None:
@@ -311,7 +314,8 @@ class Server:
             p3 = _ptr(err_out)
         prm_copy = F.CabsParams.from_buffer_copy(prm)
         F.check(F.lib().cabs_submit(self.h, C.byref(mat.desc), C.byref(prm_copy), C.byref(out.struct),
-                                    int(err_samples or 0), int(err_seed), p3, C.byref(t)), "cabs_submit")
+                                    int(err_samples or 0), int(err_seed), p3, _stream(stream), C.byref(t)),
+                "cabs_submit")
         self._live[t.value] = (mat, prm_copy, out, err_out)
         return t.value
 

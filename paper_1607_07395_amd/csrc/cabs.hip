@@ -166,9 +166,14 @@ __global__ void weights_kernel(int64_t rows, const double* __restrict__ rowsq, i
   w[r] = v;
 }
 
-__global__ void diag_init_kernel(double* __restrict__ diag, double entries) {
+__global__ void diag_init_kernel(double* __restrict__ diag, unsigned long long* __restrict__ counter, int counted) {
   const int i = threadIdx.x;
-  if (i < CABS_DIAG_LEN) diag[i] = i == CABS_DIAG_ENTRIES ? entries : 0.0;
+  if (i < CABS_DIAG_LEN) diag[i] = i == CABS_DIAG_ENTRIES ? (counted ? 0.0 : -1.0) : 0.0;
+  if (i == 0) *counter = 0ull;
+}
+
+__global__ void entries_out_kernel(const unsigned long long* __restrict__ counter, double* __restrict__ diag) {
+  if (threadIdx.x == 0) diag[CABS_DIAG_ENTRIES] = (double)*counter;
 }
 
 __global__ void copy_slot_kernel(const double* __restrict__ src, double* __restrict__ dst) {
@@ -317,6 +322,7 @@ struct SketchWs {
   int64_t *Ir, *Ic, *Ir0, *Ic0;
   void *C, *Rt, *P, *Q;
   double *rowsqP, *rowsqQ, *wr, *wc, *Z0r, *Z0c, *Zr, *Zc, *diag, *obj;
+  unsigned long long* entries;
   double *MuP, *MvP;  // the embedding maps with ep - p1 zero columns (16-bit compute, p1 not a multiple of 8)
   void* ts6;
   void *kmr, *kmc, *selr, *selc;
@@ -349,6 +355,7 @@ static size_t plan_sketch(void* ws, const Plan& pl, const cabs_params* prm, Sket
   S.ts6 = ep != e ? cv.take_bytes(tsgemm_ws_bytes(std::max(pl.m, pl.n), e, ep, pl.prec)) : nullptr;
   S.diag = cv.take<double>(CABS_DIAG_LEN);
   S.obj = cv.take<double>(8);
+  S.entries = cv.take<unsigned long long>(1);
   if (prm->follow_up == CABS_FOLLOW_HARD) {
     S.kmr = S.kmc = nullptr;
     S.selr = cv.take_bytes(select_ws_bytes(pl.m));
@@ -419,7 +426,7 @@ static cabs_status check_params(const cabs_matrix* mat, const cabs_params* prm) 
     return fail(CABS_EINVAL, "unknown sketch kind");
   if (prm->follow_up != CABS_FOLLOW_KMEANS && prm->follow_up != CABS_FOLLOW_HARD)
     return fail(CABS_EINVAL, "unknown follow-up kind");
-  if (prm->reserved != 0) return fail(CABS_EINVAL, "reserved must be 0");
+  if (prm->flags & ~CABS_FLAG_COUNT_ENTRIES) return fail(CABS_EINVAL, "unknown flag bits");
   if (prm->follow_up == CABS_FOLLOW_HARD && (mat->m >= INT32_MAX || mat->n >= INT32_MAX))
     return fail(CABS_EINVAL, "the hard-threshold selection needs m, n < 2^31 - 1");
   return CABS_OK;
@@ -554,9 +561,9 @@ extern "C" cabs_status cabs_sketch(const cabs_matrix* mat, const cabs_params* pr
   double* diag = out->diag ? out->diag : S.diag;
   const int e = pl.p1, ep = pl.ep;
 
-  const double entries = (double)pl.m * pl.kc1 + (double)pl.n * pl.kr1 - (double)pl.kr1 * pl.kc1 +
-                         (double)pl.m * pl.kc2 + (double)pl.n * pl.kr2 - (double)pl.kr2 * pl.kc2;
-  hipLaunchKernelGGL(diag_init_kernel, dim3(1), dim3(64), 0, st, diag, entries);
+  const bool counted = (prm->flags & CABS_FLAG_COUNT_ENTRIES) != 0;
+  unsigned long long* ecnt = counted ? S.entries : nullptr;
+  hipLaunchKernelGGL(diag_init_kernel, dim3(1), dim3(64), 0, st, diag, S.entries, counted ? 1 : 0);
   HIP_TRY(hipGetLastError());
 
   // 1-2: pilot sampling and evaluation
@@ -564,8 +571,8 @@ extern "C" cabs_status cabs_sketch(const cabs_matrix* mat, const cabs_params* pr
   int64_t* Ic = out->pilot_c ? out->pilot_c : S.Ic;
   HIP_TRY(launch_sample(pl.m, pl.kr1, prm->seed, STREAM_PILOT_ROWS, Ir, st));
   HIP_TRY(launch_sample(pl.n, pl.kc1, prm->seed, STREAM_PILOT_COLS, Ic, st));
-  HIP_TRY(launch_eval(mv, false, Ic, pl.kc1, pl.prec, S.C, st));
-  HIP_TRY(launch_eval(mv, true, Ir, pl.kr1, pl.prec, S.Rt, st));
+  HIP_TRY(launch_eval(mv, false, Ic, pl.kc1, pl.prec, S.C, st, ecnt));
+  HIP_TRY(launch_eval(mv, true, Ir, pl.kr1, pl.prec, S.Rt, st, ecnt));
   HIP_TRY(launch_gather_rows_f64(S.C, pl.prec, pl.kc1, Ir, pl.kr1, pl.kc1, S.r1.W, st));
 
   // 3-5: pilot sketch and embedding maps
@@ -629,8 +636,9 @@ extern "C" cabs_status cabs_sketch(const cabs_matrix* mat, const cabs_params* pr
   }
 
   // 8: follow-up evaluation and sketch
-  HIP_TRY(launch_eval(mv, false, out->idx_c, pl.kc2, pl.prec, out->C, st));
-  HIP_TRY(launch_eval(mv, true, out->idx_r, pl.kr2, pl.prec, out->Rt, st));
+  HIP_TRY(launch_eval(mv, false, out->idx_c, pl.kc2, pl.prec, out->C, st, ecnt));
+  HIP_TRY(launch_eval(mv, true, out->idx_r, pl.kr2, pl.prec, out->Rt, st, ecnt));
+  if (counted) hipLaunchKernelGGL(entries_out_kernel, dim3(1), dim3(64), 0, st, S.entries, diag);
   HIP_TRY(launch_gather_rows_f64(out->C, pl.prec, pl.kc2, out->idx_r, pl.kr2, pl.kc2, S.r2.W, st));
   const bool fac = prm->want_factors != 0;
   s = run_round(pl, S.r2, pl.kr2, pl.kc2, out->C, out->Rt, prm, fac, fac, diag, CABS_DIAG_RANK_FINAL,

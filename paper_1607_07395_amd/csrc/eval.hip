@@ -102,7 +102,15 @@ struct EvalArgs {
   int transposed;                           // 1: output row p is A column p (R^T)
   double noise_std; uint64_t noise_seed;
   double inv2s2;                            // 1 / (2 sigma^2)
+  unsigned long long* counter;              // entries evaluated (may be null)
 };
+
+// Adds a lane's count of entries to the counter: one atomic per wavefront.
+__device__ __forceinline__ void count_entries(unsigned long long* counter, int c) {
+  if (!counter) return;
+  c = wave_sum(c);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(counter, (unsigned long long)c);
+}
 
 // Five 16-column tiles per wave (80 columns): about 120 registers, so four
 // waves per SIMD overlap one wave's MFMAs with another's per-entry work (the
@@ -126,6 +134,7 @@ __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a) {
   const int g = lane >> 4;
   const int c16 = lane & 15;
   TC* out = (TC*)a.out;
+  int written = 0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int rr = out_row<TC>(g, i);
@@ -153,9 +162,11 @@ __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a) {
           else v = (AT)__expf(-(float)d2 * (float)a.inv2s2);
         }
         out[row * a.ldo + col] = from_f64<TC>((double)v);
+        ++written;
       }
     }
   }
+  count_entries(a.counter, written);
 }
 
 template <typename TIn, typename TC>
@@ -172,34 +183,45 @@ static hipError_t eval_dispatch_src(int src, const EvalArgs& a, dim3 grid, hipSt
 // ---------------------------------------------------------------------------
 template <typename TIn, typename TC>
 __global__ __launch_bounds__(256) void dense_cols_kernel(const TIn* __restrict__ A, int64_t lda, int64_t m,
-                                                         const int64_t* __restrict__ idx, int k, TC* __restrict__ out) {
+                                                         const int64_t* __restrict__ idx, int k, TC* __restrict__ out,
+                                                         unsigned long long* counter) {
   // 8 output rows per block; consecutive threads write consecutive columns of a row.
   const int64_t p0 = (int64_t)blockIdx.x * 8;
+  int read = 0;
   for (int rr = 0; rr < 8; ++rr) {
     const int64_t p = p0 + rr;
     if (p >= m) break;
     const TIn* arow = A + p * lda;
-    for (int a = threadIdx.x; a < k; a += blockDim.x) out[p * k + a] = from_f64<TC>((double)arow[idx[a]]);
+    for (int a = threadIdx.x; a < k; a += blockDim.x) {
+      out[p * k + a] = from_f64<TC>((double)arow[idx[a]]);
+      ++read;
+    }
   }
+  count_entries(counter, read);
 }
 
 template <typename TIn, typename TC>
 __global__ __launch_bounds__(256) void dense_rows_t_kernel(const TIn* __restrict__ A, int64_t lda, int64_t n,
                                                            const int64_t* __restrict__ idx, int k,
-                                                           TC* __restrict__ out) {
+                                                           TC* __restrict__ out, unsigned long long* counter) {
   // Tile: 64 columns of A (output rows p) x 64 sampled rows (output columns a).
   __shared__ double tile[64][65];
   const int64_t p0 = (int64_t)blockIdx.x * 64;
   const int a0 = blockIdx.y * 64;
   const int tx = threadIdx.x & 63;
   const int ty = threadIdx.x >> 6;  // 0..3
+  int read = 0;
   for (int al = ty; al < 64; al += 4) {
     const int a = a0 + al;
     const int64_t p = p0 + tx;
     double v = 0.0;
-    if (a < k && p < n) v = (double)A[idx[a] * lda + p];  // coalesced along p
+    if (a < k && p < n) {
+      v = (double)A[idx[a] * lda + p];  // coalesced along p
+      ++read;
+    }
     tile[al][tx] = v;
   }
+  count_entries(counter, read);
   __syncthreads();
   for (int pl = ty; pl < 64; pl += 4) {
     const int64_t p = p0 + pl;
@@ -210,31 +232,32 @@ __global__ __launch_bounds__(256) void dense_rows_t_kernel(const TIn* __restrict
 
 template <typename TIn, typename TC>
 static hipError_t dense_dispatch(const MatView& mv, bool rows_t, const int64_t* idx, int k, void* out,
-                                 hipStream_t st) {
+                                 hipStream_t st, unsigned long long* counter) {
   const TIn* A = (const TIn*)mv.a;
   if (!rows_t) {
     hipLaunchKernelGGL((dense_cols_kernel<TIn, TC>), dim3((unsigned)ceil_div(mv.m, 8)), dim3(256), 0, st, A, mv.lda,
-                       mv.m, idx, k, (TC*)out);
+                       mv.m, idx, k, (TC*)out, counter);
   } else {
     dim3 grid((unsigned)ceil_div(mv.n, 64), (unsigned)ceil_div(k, 64));
-    hipLaunchKernelGGL((dense_rows_t_kernel<TIn, TC>), grid, dim3(256), 0, st, A, mv.lda, mv.n, idx, k, (TC*)out);
+    hipLaunchKernelGGL((dense_rows_t_kernel<TIn, TC>), grid, dim3(256), 0, st, A, mv.lda, mv.n, idx, k, (TC*)out,
+                       counter);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_eval(const MatView& mv, bool rows_t, const int64_t* idx, int k, int compute, void* out,
-                       hipStream_t st) {
+                       hipStream_t st, unsigned long long* counter) {
   if (k <= 0) return hipErrorInvalidValue;
   TimerScope ts(T_EVAL, st);
   if (mv.kind == SRC_DENSE) {
     if (mv.storage == P_F64) {
-      if (compute == P_F64) return dense_dispatch<double, double>(mv, rows_t, idx, k, out, st);
+      if (compute == P_F64) return dense_dispatch<double, double>(mv, rows_t, idx, k, out, st, counter);
       return hipErrorInvalidValue;
     }
     switch (compute) {
-      case P_F32: return dense_dispatch<float, float>(mv, rows_t, idx, k, out, st);
-      case P_BF16: return dense_dispatch<float, bf16>(mv, rows_t, idx, k, out, st);
-      case P_F16: return dense_dispatch<float, f16>(mv, rows_t, idx, k, out, st);
+      case P_F32: return dense_dispatch<float, float>(mv, rows_t, idx, k, out, st, counter);
+      case P_BF16: return dense_dispatch<float, bf16>(mv, rows_t, idx, k, out, st, counter);
+      case P_F16: return dense_dispatch<float, f16>(mv, rows_t, idx, k, out, st, counter);
       default: return hipErrorInvalidValue;
     }
   }
@@ -262,6 +285,7 @@ hipError_t launch_eval(const MatView& mv, bool rows_t, const int64_t* idx, int k
   a.transposed = rows_t ? 1 : 0;
   a.noise_std = mv.noise_std;
   a.noise_seed = mv.noise_seed;
+  a.counter = counter;
   dim3 grid((unsigned)ceil_div(M, 64), (unsigned)ceil_div(k, EVAL_NT * 16));
   if (mv.storage == P_F64) {
     if (compute == P_F64) return eval_dispatch_src<double, double>(mv.kind, a, grid, st);

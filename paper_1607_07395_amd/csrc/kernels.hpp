@@ -33,8 +33,9 @@ struct MatView {
 // --- sampling / entry evaluation (eval.hip) ---
 hipError_t launch_sample(int64_t n, int k, uint64_t seed, int stream_id, int64_t* out, hipStream_t st);
 // rows_t = false: out (m x k) = A(:, idx); rows_t = true: out (n x k) = A(idx, :)^T.
+// counter (may be null): every entry evaluated or read is added to it on the device.
 hipError_t launch_eval(const MatView& mv, bool rows_t, const int64_t* idx, int k, int compute, void* out,
-                       hipStream_t st);
+                       hipStream_t st, unsigned long long* counter = nullptr);
 // out (k x ncols, FP64) = src[idx[i], :] for a compute-precision row-major src with row stride ld.
 hipError_t launch_gather_rows_f64(const void* src, int compute, int64_t ld, const int64_t* idx, int k, int ncols,
                                   double* out, hipStream_t st);

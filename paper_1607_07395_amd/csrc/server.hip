@@ -1,85 +1,48 @@
 // Continuous-batching sketch server.
 //
 // Requests of uneven size arrive from any thread (cabs_submit).  A scheduler
-// thread admits them in arrival order as soon as a slot (a HIP stream) is free
-// and their workspace fits in the device pool, launches the whole sketch on
-// the slot's stream, and retires it when the stream's completion event has
-// fired, returning its workspace to the pool.  Requests in different slots run
-// concurrently on the device; each one's kernels only touch its own buffers, so
-// its result is the same whether it runs alone or next to others.
+// thread admits them as soon as a slot (a HIP stream) is free and their
+// workspace fits in the device pool (serve_core.hpp: arrival order with a
+// bounded bypass, so a request that does not fit yet lets smaller ones pass a
+// limited number of times), enqueues the whole sketch on the slot's stream,
+// and retires it when the completion marker (an event) behind its last kernel
+// has fired, returning its workspace to the pool.  Requests in different slots
+// run concurrently on the device; each one's kernels only touch its own
+// buffers, so its result is the same whether it runs alone or next to others.
+//
+// Ordering: cabs_submit records an event on the caller's stream, and the slot
+// stream waits for it before the request's first kernel, so buffers the caller
+// wrote (or freed and reused) on its stream before submitting are ready.
+//
 // The pool is one device allocation made at creation, carved first-fit in
-// 256-byte units; nothing is allocated per request.
+// 256-byte units; nothing is allocated per request.  The server mutex guards
+// the bookkeeping only: the ~1000 launches of a sketch are enqueued outside it,
+// so cabs_submit and cabs_poll never wait for them.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
-#include <deque>
 #include <map>
 #include <mutex>
-#include <string>
 #include <thread>
 #include <vector>
 
 #include "../../include/cabs.h"
+#include "serve_core.hpp"
 
 namespace {
 
 using Clock = std::chrono::steady_clock;
 
-struct Block { size_t off, size; };
-
-// First-fit allocator over [0, capacity) with coalescing of free neighbours.
-class Pool {
- public:
-  explicit Pool(size_t cap) { free_.push_back({0, cap}); }
-  bool alloc(size_t bytes, size_t& off) {
-    bytes = (bytes + 255) & ~(size_t)255;
-    for (size_t i = 0; i < free_.size(); ++i) {
-      if (free_[i].size >= bytes) {
-        off = free_[i].off;
-        free_[i].off += bytes;
-        free_[i].size -= bytes;
-        if (free_[i].size == 0) free_.erase(free_.begin() + i);
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(size_t off, size_t bytes) {
-    bytes = (bytes + 255) & ~(size_t)255;
-    size_t i = 0;
-    while (i < free_.size() && free_[i].off < off) ++i;
-    free_.insert(free_.begin() + i, {off, bytes});
-    if (i + 1 < free_.size() && free_[i].off + free_[i].size == free_[i + 1].off) {
-      free_[i].size += free_[i + 1].size;
-      free_.erase(free_.begin() + i + 1);
-    }
-    if (i > 0 && free_[i - 1].off + free_[i - 1].size == free_[i].off) {
-      free_[i - 1].size += free_[i].size;
-      free_.erase(free_.begin() + i);
-    }
-  }
-
- private:
-  std::vector<Block> free_;
-};
-
-enum ReqState { QUEUED, RUNNING, DONE, CANCELED, FAILED };
-
-struct Request {
-  uint64_t ticket;
+struct ReqData {
   cabs_matrix mat;
   cabs_params prm;
   cabs_result res;
   int64_t err_samples = 0;
   uint64_t err_seed = 0;
   double* err_out3 = nullptr;
-  size_t ws_bytes;
-  size_t ws_off = 0;
-  int slot = -1;
-  ReqState state = QUEUED;
-  int status = CABS_OK;
+  hipEvent_t ready = nullptr;  // recorded on the caller's stream at submission
   Clock::time_point t_submit, t_done;
 };
 
@@ -89,73 +52,80 @@ struct cabs_server {
   int device;
   size_t budget;
   char* pool_base = nullptr;
-  Pool* pool = nullptr;
+  cabs_serve::Core* core = nullptr;
   std::vector<hipStream_t> streams;
-  std::vector<hipEvent_t> events;
-  std::vector<uint64_t> slot_req;      // ticket running in each slot (0 = free)
+  std::vector<hipEvent_t> events;      // completion marker of each slot
+  std::vector<hipEvent_t> free_events; // "ready" events for reuse
   std::mutex mu;
   std::condition_variable cv;          // wakes the scheduler
   std::condition_variable idle_cv;     // wakes drain()
-  std::deque<uint64_t> queue;
-  std::map<uint64_t, Request> reqs;
-  uint64_t next_ticket = 1;
+  std::map<uint64_t, ReqData> data;
   std::atomic<bool> stop{false};
   std::thread worker;
-  int running = 0;
 };
+
+static void stamp_done(cabs_server* s, const std::vector<uint64_t>& tickets) {
+  const Clock::time_point now = Clock::now();
+  for (uint64_t t : tickets) {
+    ReqData& d = s->data[t];
+    d.t_done = now;
+    if (d.ready) {
+      s->free_events.push_back(d.ready);
+      d.ready = nullptr;
+    }
+  }
+}
 
 static void scheduler(cabs_server* s) {
   (void)hipSetDevice(s->device);
   std::unique_lock<std::mutex> lk(s->mu);
   while (!s->stop.load()) {
     bool progressed = false;
-    // retire finished slots
-    for (size_t k = 0; k < s->streams.size(); ++k) {
-      const uint64_t t = s->slot_req[k];
-      if (!t) continue;
-      if (hipEventQuery(s->events[k]) == hipSuccess) {
-        Request& r = s->reqs[t];
-        r.t_done = Clock::now();
-        r.state = DONE;
-        s->pool->release(r.ws_off, r.ws_bytes);
-        s->slot_req[k] = 0;
-        --s->running;
-        progressed = true;
-      }
-    }
-    // admit in arrival order while a slot is free and the workspace fits
-    while (!s->queue.empty()) {
-      int slot = -1;
-      for (size_t k = 0; k < s->streams.size(); ++k)
-        if (!s->slot_req[k]) { slot = (int)k; break; }
-      if (slot < 0) break;
-      const uint64_t t = s->queue.front();
-      Request& r = s->reqs[t];
-      size_t off;
-      if (!s->pool->alloc(r.ws_bytes, off)) break;
-      s->queue.pop_front();
-      r.ws_off = off;
-      r.slot = slot;
-      int st = cabs_sketch(&r.mat, &r.prm, s->pool_base + off, r.ws_bytes, &r.res, s->streams[slot]);
-      if (st == CABS_OK && r.err_out3)
-        st = cabs_error(&r.mat, &r.prm, &r.res, r.err_samples, r.err_seed, s->pool_base + off, r.ws_bytes, r.err_out3,
-                        s->streams[slot]);
-      if (st != CABS_OK) {
-        r.status = st;
-        r.state = FAILED;
-        r.t_done = Clock::now();
-        s->pool->release(off, r.ws_bytes);
-        continue;
-      }
-      (void)hipEventRecord(s->events[slot], s->streams[slot]);
-      r.state = RUNNING;
-      s->slot_req[slot] = t;
-      ++s->running;
+    std::vector<uint64_t> ret =
+        s->core->retire([s](int slot) { return hipEventQuery(s->events[slot]) == hipSuccess; });
+    if (!ret.empty()) {
+      stamp_done(s, ret);
       progressed = true;
     }
-    if (s->queue.empty() && s->running == 0) s->idle_cv.notify_all();
+    std::vector<cabs_serve::Launch> adm = s->core->admit();
+    if (!adm.empty()) {
+      std::vector<ReqData> work;
+      work.reserve(adm.size());
+      for (const auto& a : adm) work.push_back(s->data[a.ticket]);
+      lk.unlock();
+      std::vector<int> status(adm.size(), CABS_OK);
+      std::vector<char> marker(adm.size(), 1);
+      for (size_t q = 0; q < adm.size(); ++q) {
+        ReqData& r = work[q];
+        hipStream_t st = s->streams[adm[q].slot];
+        void* ws = s->pool_base + adm[q].off;
+        const size_t wsb = adm[q].bytes;
+        int rc = CABS_OK;
+        if (r.ready && hipStreamWaitEvent(st, r.ready, 0) != hipSuccess) rc = CABS_EDEVICE;
+        if (rc == CABS_OK) rc = cabs_sketch(&r.mat, &r.prm, ws, wsb, &r.res, st);
+        if (rc == CABS_OK && r.err_out3)
+          rc = cabs_error(&r.mat, &r.prm, &r.res, r.err_samples, r.err_seed, ws, wsb, r.err_out3, st);
+        // The marker goes behind whatever was enqueued, also after an error: kernels queued before
+        // it may still run, so the workspace stays held until the marker has fired.
+        if (hipEventRecord(s->events[adm[q].slot], st) != hipSuccess) {
+          (void)hipStreamSynchronize(st);
+          marker[q] = 0;
+          if (rc == CABS_OK) rc = CABS_EDEVICE;
+        }
+        status[q] = rc;
+      }
+      lk.lock();
+      std::vector<uint64_t> ended;
+      for (size_t q = 0; q < adm.size(); ++q) {
+        s->core->launched(adm[q].ticket, status[q], marker[q] != 0);
+        if (!marker[q]) ended.push_back(adm[q].ticket);
+      }
+      stamp_done(s, ended);
+      progressed = true;
+    }
+    if (s->core->idle()) s->idle_cv.notify_all();
     if (!progressed) {
-      if (s->running > 0) {
+      if (s->core->running() > 0) {
         lk.unlock();
         std::this_thread::sleep_for(std::chrono::microseconds(20));
         lk.lock();
@@ -176,10 +146,9 @@ extern "C" cabs_server* cabs_server_create(int32_t device, size_t hbm_budget_byt
     delete s;
     return nullptr;
   }
-  s->pool = new Pool(hbm_budget_bytes);
+  s->core = new cabs_serve::Core(hbm_budget_bytes, max_slots, 4 * max_slots);
   s->streams.resize(max_slots);
   s->events.resize(max_slots);
-  s->slot_req.assign(max_slots, 0);
   for (int k = 0; k < max_slots; ++k) {
     (void)hipStreamCreateWithFlags(&s->streams[k], hipStreamNonBlocking);
     (void)hipEventCreateWithFlags(&s->events[k], hipEventDisableTiming);
@@ -190,7 +159,7 @@ extern "C" cabs_server* cabs_server_create(int32_t device, size_t hbm_budget_byt
 
 extern "C" cabs_status cabs_submit(cabs_server* s, const cabs_matrix* mat, const cabs_params* prm,
                                    const cabs_result* out, int64_t err_samples, uint64_t err_seed, double* err_out3,
-                                   uint64_t* ticket) {
+                                   void* stream, uint64_t* ticket) {
   if (!s || !mat || !prm || !out || !ticket || err_samples < 0) return CABS_EINVAL;
   size_t need = cabs_workspace_bytes(mat, prm);
   if (need == 0) return CABS_EINVAL;
@@ -202,19 +171,33 @@ extern "C" cabs_status cabs_submit(cabs_server* s, const cabs_matrix* mat, const
   if (need > s->budget) return CABS_ENOMEM;
   if (!out->idx_r || !out->idx_c || !out->C || !out->Rt || !out->Umid) return CABS_EINVAL;
   std::lock_guard<std::mutex> g(s->mu);
-  Request r;
-  r.ticket = s->next_ticket++;
+  hipEvent_t ev = nullptr;
+  if (!s->free_events.empty()) {
+    ev = s->free_events.back();
+    s->free_events.pop_back();
+  } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+    return CABS_EDEVICE;
+  }
+  if (hipEventRecord(ev, (hipStream_t)stream) != hipSuccess) {
+    s->free_events.push_back(ev);
+    return CABS_EDEVICE;
+  }
+  const uint64_t t = s->core->submit(need);
+  if (t == 0) {
+    s->free_events.push_back(ev);
+    return CABS_ENOMEM;
+  }
+  ReqData r;
   r.mat = *mat;
   r.prm = *prm;
   r.res = *out;
   r.err_samples = err_samples;
   r.err_seed = err_seed;
   r.err_out3 = err_out3;
-  r.ws_bytes = need;
+  r.ready = ev;
   r.t_submit = Clock::now();
-  s->reqs[r.ticket] = r;
-  s->queue.push_back(r.ticket);
-  *ticket = r.ticket;
+  s->data[t] = r;
+  *ticket = t;
   s->cv.notify_all();
   return CABS_OK;
 }
@@ -222,26 +205,29 @@ extern "C" cabs_status cabs_submit(cabs_server* s, const cabs_matrix* mat, const
 extern "C" cabs_status cabs_poll(cabs_server* s, uint64_t ticket, double* latency_s) {
   if (!s) return CABS_EINVAL;
   std::lock_guard<std::mutex> g(s->mu);
-  auto it = s->reqs.find(ticket);
-  if (it == s->reqs.end()) return CABS_EINVAL;
-  Request& r = it->second;
-  if (r.state == QUEUED || r.state == RUNNING) return CABS_EBUSY;
-  cabs_status st = r.state == CANCELED ? CABS_ECANCELED : r.state == FAILED ? (cabs_status)r.status : CABS_OK;
-  if (latency_s) *latency_s = std::chrono::duration<double>(r.t_done - r.t_submit).count();
-  s->reqs.erase(it);
+  const cabs_serve::Entry* e = s->core->find(ticket);
+  if (!e) return CABS_EINVAL;
+  if (e->state == cabs_serve::QUEUED || e->state == cabs_serve::LAUNCHING || e->state == cabs_serve::RUNNING)
+    return CABS_EBUSY;
+  const cabs_status st = e->state == cabs_serve::CANCELED ? CABS_ECANCELED
+                         : e->state == cabs_serve::FAILED ? (cabs_status)e->status
+                                                          : CABS_OK;
+  ReqData& d = s->data[ticket];
+  if (latency_s) *latency_s = std::chrono::duration<double>(d.t_done - d.t_submit).count();
+  if (d.ready) s->free_events.push_back(d.ready);
+  s->data.erase(ticket);
+  s->core->forget(ticket);
   return st;
 }
 
 extern "C" cabs_status cabs_cancel(cabs_server* s, uint64_t ticket) {
   if (!s) return CABS_EINVAL;
   std::lock_guard<std::mutex> g(s->mu);
-  auto it = s->reqs.find(ticket);
-  if (it == s->reqs.end()) return CABS_EINVAL;
-  if (it->second.state != QUEUED) return it->second.state == RUNNING ? CABS_EBUSY : CABS_OK;
-  for (auto q = s->queue.begin(); q != s->queue.end(); ++q)
-    if (*q == ticket) { s->queue.erase(q); break; }
-  it->second.state = CANCELED;
-  it->second.t_done = Clock::now();
+  const int rc = s->core->cancel(ticket);
+  if (rc < 0) return CABS_EINVAL;
+  if (rc > 0) return CABS_EBUSY;
+  auto it = s->data.find(ticket);
+  if (it != s->data.end() && it->second.t_done == Clock::time_point()) it->second.t_done = Clock::now();
   s->cv.notify_all();
   return CABS_OK;
 }
@@ -250,7 +236,7 @@ extern "C" cabs_status cabs_server_drain(cabs_server* s) {
   if (!s) return CABS_EINVAL;
   std::unique_lock<std::mutex> lk(s->mu);
   s->cv.notify_all();
-  s->idle_cv.wait(lk, [s] { return s->queue.empty() && s->running == 0; });
+  s->idle_cv.wait(lk, [s] { return s->core->idle(); });
   return CABS_OK;
 }
 
@@ -265,7 +251,10 @@ extern "C" void cabs_server_destroy(cabs_server* s) {
     (void)hipStreamDestroy(s->streams[k]);
     (void)hipEventDestroy(s->events[k]);
   }
+  for (auto& kv : s->data)
+    if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
+  for (hipEvent_t e : s->free_events) (void)hipEventDestroy(e);
   (void)hipFree(s->pool_base);
-  delete s->pool;
+  delete s->core;
   delete s;
 }

@@ -61,7 +61,7 @@ def test_workspace_planning_and_validation_on_cpu():
     assert lib.cabs_workspace_bytes(C.byref(d), C.byref(p)) == 0
     assert b"unknown source kind" in lib.cabs_last_error()
     # follow-up kind: the hard-threshold selection plans its own workspace; unknown kinds and a
-    # nonzero reserved field are rejected
+    # unknown flag bits are rejected
     d = _desc()
     h = make_params(20, 20, 20, 20, compute="f32", follow_up="hard")
     assert lib.cabs_workspace_bytes(C.byref(d), C.byref(h)) > 0
@@ -69,7 +69,7 @@ def test_workspace_planning_and_validation_on_cpu():
     assert lib.cabs_workspace_bytes(C.byref(d), C.byref(h)) == 0
     assert b"follow-up" in lib.cabs_last_error()
     h.follow_up = 0
-    h.reserved = 1
+    h.flags = 2
     assert lib.cabs_workspace_bytes(C.byref(d), C.byref(h)) == 0
 
 
