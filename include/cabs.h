@@ -246,6 +246,23 @@ cabs_status cabs_kmeans(int64_t rows, int32_t dim, int32_t k, int32_t compute, c
                         const double* Z0, int32_t iters, double* Z, int32_t* labels, double* obj2,
                         int64_t* snap_out, void* ws, size_t ws_bytes, void* stream);
 
+/* cabs_kmeans without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, kernels and results as cabs_kmeans;
+ * the scratch cabs_kmeans would carve from `ws` comes from a fixed array of
+ * CABS_KMEANS_NOALLOC_SCRATCH_BYTES in the library, one per device, held until
+ * the process ends.  The call allocates nothing; the first call on a device
+ * looks up that device's array.  Problems whose cabs_kmeans_workspace_bytes()
+ * exceeds the array (about 1e5 rows x 200 dimensions x 200 centres in FP32
+ * fits) return CABS_ENOMEM before anything is enqueued.  All calls on one
+ * device share its array: calls that overlap in time on that device (on
+ * different streams, or from different threads) race and must be serialised
+ * by the caller. */
+#define CABS_KMEANS_NOALLOC_SCRATCH_BYTES (64u << 20)
+cabs_status cabs_kmeans_noalloc(int64_t rows, int32_t dim, int32_t k, int32_t compute, const void* P,
+                                const double* w, const double* Z0, int32_t iters, double* Z, int32_t* labels,
+                                double* obj2, int64_t* snap_out, void* stream);
+
 /* ---- Kernel timing (diagnostics) ----
  * When enabled, every launch of a kernel family is bracketed by two HIP events
  * recorded on the stream it is launched on.  Families: "assign" (fused

@@ -20,6 +20,7 @@ SRC_DENSE, SRC_LOWRANK, SRC_RBF = 0, 1, 2
 W_CONST, W_POW, W_SIGMOID, W_STEP = 0, 1, 2, 3
 SK_STABILIZED, SK_PSEUDO_SKELETON = 0, 1
 FLAG_COUNT_ENTRIES = 1
+KMEANS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 DIAG_STATUS, DIAG_ENC_R_PILOT, DIAG_ENC_C_PILOT, DIAG_ENC_R_FINAL, DIAG_ENC_C_FINAL = 0, 1, 2, 3, 4
 DIAG_TMAX_R, DIAG_TMAX_C, DIAG_RANK_PILOT, DIAG_RANK_FINAL, DIAG_ENTRIES = 5, 6, 7, 8, 9
@@ -73,6 +74,8 @@ _SIGS = {
     "cabs_kmeans_workspace_bytes": (C.c_size_t, [C.c_int64, C.c_int32, C.c_int32, C.c_int32]),
     "cabs_kmeans": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, C.c_int32, _P, _P, _P, _P,
                               _P, C.c_size_t, _P]),
+    "cabs_kmeans_noalloc": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_int32, _P, _P, _P, C.c_int32, _P, _P,
+                                      _P, _P, _P]),
     "cabs_timing_enable": (C.c_int, [C.c_int32]),
     "cabs_timing_read": (C.c_int, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "cabs_timing_reset": (None, []),

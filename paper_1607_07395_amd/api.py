@@ -273,6 +273,24 @@ def kmeans(P: torch.Tensor, w: torch.Tensor, Z0: torch.Tensor, iters: int, snap:
     return Z, labels, obj2, sn
 
 
+def kmeans_noalloc(P: torch.Tensor, w: torch.Tensor, Z0: torch.Tensor, iters: int, snap: bool = True,
+                   out=None, stream=None):
+    """cabs_kmeans_noalloc -> (Z, labels, obj2, snapped indices or None).  Outputs are allocated
+    here unless `out` = (Z, labels, obj2, snap) is given; the library call itself allocates nothing."""
+    rows, dim = P.shape
+    k = Z0.shape[0]
+    prec = {torch.float64: F.F64, torch.float32: F.F32, torch.bfloat16: F.BF16, torch.float16: F.F16}[P.dtype]
+    dev = P.device
+    if out is None:
+        out = (torch.empty(k, dim, dtype=torch.float64, device=dev), torch.empty(rows, dtype=torch.int32, device=dev),
+               torch.empty(2, dtype=torch.float64, device=dev),
+               torch.empty(k, dtype=torch.int64, device=dev) if snap else None)
+    Z, labels, obj2, sn = out
+    F.check(F.lib().cabs_kmeans_noalloc(rows, dim, k, prec, _ptr(P), _ptr(w), _ptr(Z0), iters, _ptr(Z),
+                                        _ptr(labels), _ptr(obj2), _ptr(sn), _stream(stream)), "cabs_kmeans_noalloc")
+    return Z, labels, obj2, sn
+
+
 def timing_enable(on: bool = True) -> None:
     """cabs_timing_enable."""
     F.check(F.lib().cabs_timing_enable(1 if on else 0), "cabs_timing_enable")

@@ -21,6 +21,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "../../include/cabs.h"
@@ -794,6 +795,59 @@ extern "C" cabs_status cabs_kmeans(int64_t rows, int32_t dim, int32_t k, int32_t
   if (!P || !w || !Z0 || !Z || !ws) return fail(CABS_EINVAL, "null pointer");
   if (iters < 0) return fail(CABS_EINVAL, "iters must be >= 0");
   if (ws_bytes < kmeans_ws_bytes(rows, dim, k, compute)) return fail(CABS_ENOMEM, "workspace too small");
+  KMeansOut o{Z, labels, obj2, nullptr, nullptr, snap_out, nullptr};
+  HIP_TRY(launch_kmeans(rows, dim, k, compute, P, w, Z0, iters, o, ws, (hipStream_t)stream));
+  return CABS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// cabs_kmeans_noalloc: cabs_kmeans with its scratch in a fixed device array
+// ---------------------------------------------------------------------------
+// The array lives in the library's code object, one copy per device, for the
+// life of the process.  Host code never passes its name to a kernel (in host
+// code the name is only a stand-in): the device address of each device's copy
+// is looked up once, with that device current, and kept.  Nothing in the
+// k-means kernels needs the scratch to start at zero (every buffer they read is
+// written earlier in the same call), so consecutive calls need no clearing.
+static __device__ __align__(256) unsigned char scratch[CABS_KMEANS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static cabs_status scratch_on_current_device(void** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(CABS_EDEVICE, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(CABS_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CABS_OK;
+}
+
+extern "C" cabs_status cabs_kmeans_noalloc(int64_t rows, int32_t dim, int32_t k, int32_t compute, const void* P,
+                                           const double* w, const double* Z0, int32_t iters, double* Z,
+                                           int32_t* labels, double* obj2, int64_t* snap_out, void* stream) {
+  if (rows <= 0 || rows >= (int64_t)1 << 31 || dim <= 0 || dim > 1024 || k <= 0 || k > 1024 || k > rows)
+    return fail(CABS_EINVAL, "need 0 < k <= min(rows, 1024), 0 < dim <= 1024");
+  if (!valid_prec(compute)) return fail(CABS_EINVAL, "unknown precision");
+  if (!P || !w || !Z0 || !Z) return fail(CABS_EINVAL, "null pointer");
+  if (iters < 0) return fail(CABS_EINVAL, "iters must be >= 0");
+  const size_t need = kmeans_ws_bytes(rows, dim, k, compute);
+  if (need > (size_t)CABS_KMEANS_NOALLOC_SCRATCH_BYTES)
+    return fail(CABS_ENOMEM, "cabs_kmeans_noalloc: needs %zu bytes of scratch, the fixed array holds %zu", need,
+                (size_t)CABS_KMEANS_NOALLOC_SCRATCH_BYTES);
+  void* ws = nullptr;
+  const cabs_status s = scratch_on_current_device(&ws);
+  if (s != CABS_OK) return s;
   KMeansOut o{Z, labels, obj2, nullptr, nullptr, snap_out, nullptr};
   HIP_TRY(launch_kmeans(rows, dim, k, compute, P, w, Z0, iters, o, ws, (hipStream_t)stream));
   return CABS_OK;

@@ -87,6 +87,13 @@ def test_entry_points_reject_bad_arguments_without_launching():
     assert lib.cabs_svd_ex(1, 50, 50, None, None, None, None, None, 0, -1, None) == F.EINVAL
     assert lib.cabs_svd_ex(1, 50, 50, None, None, None, None, None, 0, 25, None) == F.EINVAL
     assert lib.cabs_kmeans(10, 3, 11, F.F32, None, None, None, 1, None, None, None, None, None, 0, None) == F.EINVAL
+    # the allocation-free k-means: invalid sizes, and problems beyond its fixed scratch, are rejected
+    # before any device call
+    fake = C.c_void_p(0x1000)
+    assert lib.cabs_kmeans_noalloc(10, 3, 11, F.F32, fake, fake, fake, 1, fake, None, None, None, None) == F.EINVAL
+    assert lib.cabs_kmeans_noalloc(1_000_000, 504, 500, F.BF16, fake, fake, fake, 1, fake, None, None, None,
+                                   None) == F.ENOMEM
+    assert b"fixed array" in lib.cabs_last_error()
     assert lib.cabs_svd_workspace_bytes(1, 50, 50) > 0
     assert lib.cabs_kmeans_workspace_bytes(10_000, 50, 50, F.F32) > 0
     # workspace too small -> ENOMEM before anything is launched
