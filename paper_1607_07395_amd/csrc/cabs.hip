@@ -266,7 +266,7 @@ struct RoundWs {
 
 struct Plan {
   int prec, kr1, kc1, kr2, kc2, p1, p2;
-  int ep;  // columns of the stored embeddings P, Q: p1, padded to whole 16-byte runs in 16-bit compute
+  int ep;  // columns of the stored embeddings P, Q: p1, padded to whole 16-byte runs in FP32 and 16-bit compute
   int64_t m, n;
 };
 
@@ -442,7 +442,9 @@ static Plan make_plan(const cabs_matrix* mat, const cabs_params* prm) {
   pl.kc2 = prm->k2_cols;
   pl.p1 = std::min(pl.kr1, pl.kc1);
   pl.p2 = std::min(pl.kr2, pl.kc2);
-  pl.ep = (pl.prec == CABS_BF16 || pl.prec == CABS_F16) ? (pl.p1 + 7) / 8 * 8 : pl.p1;
+  pl.ep = (pl.prec == CABS_BF16 || pl.prec == CABS_F16) ? (pl.p1 + 7) / 8 * 8
+          : pl.prec == CABS_F32                          ? (pl.p1 + 3) / 4 * 4
+                                                         : pl.p1;
   pl.m = mat->m;
   pl.n = mat->n;
   return pl;
@@ -582,9 +584,9 @@ extern "C" cabs_status cabs_sketch(const cabs_matrix* mat, const cabs_params* pr
   if (s != CABS_OK) return s;
 
   // 6: embeddings and weights
-  // In 16-bit compute with p1 not a multiple of 8 the embeddings get ep - p1 zero columns, so that
-  // their rows are whole 16-byte runs for the k-means kernels; zero columns add exact zeros to every
-  // distance, norm and centre.
+  // When p1 elements are not a whole number of 16-byte runs (FP32: p1 not a multiple of 4, 16-bit:
+  // of 8) the embeddings get ep - p1 zero columns, so that their rows are whole runs for the k-means
+  // kernels; zero columns add exact zeros to every distance, norm and centre.
   const double* Mu = S.r1.Mu;
   const double* Mv = S.r1.Mv;
   void* ts6 = S.r1.ts_ws;

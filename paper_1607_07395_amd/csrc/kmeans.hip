@@ -29,6 +29,10 @@
 #include "kernels.hpp"
 #include "timing.hpp"
 
+#include <algorithm>
+#include <atomic>
+#include <cstdlib>
+
 namespace cabs {
 
 constexpr int KM_NT = 8;          // centres per wave pass = 128
@@ -42,8 +46,22 @@ constexpr int SNAP_SUB = 64;      // rows per distance sub-tile
 constexpr int SNAP_ROWS = 128;    // rows per block of the top-T pass (a multiple of SNAP_SUB)
 constexpr int SNAP_MAXBLK = 2048; // row blocks at most
 constexpr int64_t SNAP_MAXCAND = (int64_t)1 << 19;  // k * blocks at most
+constexpr int AF_MAXG = 4;        // centre groups of the fast assignment at most
 
 static inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Compute units of the current device (looked up once per device).
+static int device_cus() {
+  static std::atomic<int> cus[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  int v = cus[dev].load(std::memory_order_relaxed);
+  if (v <= 0) {
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    cus[dev].store(v, std::memory_order_relaxed);
+  }
+  return v;
+}
 
 // ---------------------------------------------------------------------------
 // Small helpers
@@ -155,159 +173,303 @@ __global__ __launch_bounds__(256) void assign_kernel(int64_t rows, int dim, int 
   }
 }
 
-// Fast assignment for FP32 / BF16 / FP16, dim <= 256 (FP32) or 512 (16-bit) and rows that are
-// whole 16-byte runs (dim a multiple of 16 / sizeof(TC), P 16-byte aligned).
-// A workgroup (4 waves, 64 rows) keeps each wave's 16 rows as 16-byte MFMA
-// fragments in registers for the whole kernel, and streams the centres
-// through LDS in chunks of AF_CT x 16, stored in fragment order so that every
-// B read is one contiguous ds_read_b128 per wave (no bank conflicts).  The
-// next chunk is loaded into registers while the current one is multiplied.
-// NKB (k blocks) is a compile-time constant, so no load, store or MFMA needs a
-// run-time guard (k blocks past dim read zeros and add exact zeros).  Per lane
-// the k blocks, MFMA steps and columns come in the same order as in
+// Fast assignment for FP32 / BF16 / FP16, dim <= 512 and rows that are whole
+// 16-byte runs (dim a multiple of 16 / sizeof(TC), P and Zc 16-byte aligned).
+// A workgroup has 4 waves; each wave keeps RT row tiles of 16 rows as 16-byte
+// MFMA fragments in registers for the whole kernel and streams its centre
+// group through LDS in chunks of CT x 16 centres, stored in fragment order so
+// that every B read is one contiguous ds_read_b128 per wave (no bank
+// conflicts).  Each B fragment read from LDS feeds RT MFMAs: 16-bit types use
+// RT = 2, since one 16x16x32 MFMA per 1 KB LDS read would leave the CU's LDS
+// port, not the matrix cores, as the bound; FP32 MFMAs are 8x slower per byte
+// of B, so RT = 1 suffices there.
+//
+// Chunks are double-buffered in two LDS arrays and filled by direct
+// global-to-LDS loads (global_load_lds_dwordx4: lane l's 16 bytes land at
+// 16 l past the wave's LDS address, so one instruction fills one 1 KB
+// fragment block).  Chunk c + 1 is in flight while chunk c is multiplied, and
+// no registers hold it.  The two arrays are distinct objects, so the compiler
+// knows that reads of one do not wait for loads into the other; the explicit
+// vmcnt(0) + barrier before a chunk is used is the only wait.  NKB (k blocks)
+// is a compile-time constant, so no load, store or MFMA needs a run-time
+// guard (runs past dim or k come from a zero buffer and add exact zeros).
+//
+// blockIdx.y selects a group of gsize consecutive centres (a multiple of
+// CT x 16).  With one group the kernel writes labels, distances and gaps; with
+// several (rows too few to fill the chip in whole row tiles) every group
+// writes its (best, index, second) per row to pb/pi/ps and
+// assign_merge_kernel combines the groups.  The summary of a set of centres
+// (lexicographic minimum of (distance, index), second-smallest distance) is
+// merged exactly, so any grouping gives the same labels, distances and gaps.
+// Per output element the k blocks and MFMA steps come in the same order as in
 // assign_kernel, so distances, labels and gaps are bit-identical to it.
-constexpr int AF_CT = 2;
+#define CABS_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
 
-template <typename TC, int NKB>
-__global__ __launch_bounds__(256, 3) void assign_fast_kernel(int64_t rows, int dim, int k, const TC* __restrict__ P,
-                                                             const TC* __restrict__ Zc,
-                                                             const double* __restrict__ znorm,
-                                                             const double* __restrict__ pnorm,
-                                                             int32_t* __restrict__ labels, double* __restrict__ dmin,
-                                                             double* __restrict__ gap) {
+template <typename TC, int NKB, int RT, int CT, int OCC>
+__global__ __launch_bounds__(256, OCC) void assign_fast_kernel(int64_t rows, int dim, int k, int gsize,
+                                                               const TC* __restrict__ P, const TC* __restrict__ Zc,
+                                                               const double* __restrict__ znorm,
+                                                               const double* __restrict__ pnorm,
+                                                               int32_t* __restrict__ labels, double* __restrict__ dmin,
+                                                               double* __restrict__ gap, float* __restrict__ pb,
+                                                               int32_t* __restrict__ pi, float* __restrict__ ps) {
   typedef typename Mfma<TC>::acc AccV;
   constexpr int VE = 16 / sizeof(TC);           // elements per 16-byte run
   constexpr int SPV = VE / Mfma<TC>::KPL;       // MFMA steps per run
   constexpr int KBW = 4 * VE;                   // k per block (4 lane groups)
-  constexpr int PER_CHUNK = AF_CT * NKB * 64;   // runs per centre chunk
-  constexpr int PF = (PER_CHUNK + 255) / 256;   // prefetch runs per thread
-  extern __shared__ uint4 zs[];                 // [AF_CT][NKB][64] runs
+  constexpr int NBLK = CT * NKB;                // 1 KB fragment blocks per chunk
+  constexpr int BPW = (NBLK + 3) / 4;           // blocks issued per wave
+  constexpr int CW = CT * 16;                   // centres per chunk
+  __shared__ uint4 zb0[NBLK * 64];              // [CT][NKB][64] runs
+  __shared__ uint4 zb1[NBLK * 64];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int g = lane >> 4, c16 = lane & 15;
-  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
-  uint4 a[NKB];
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * RT);
+  const int cbeg = (int)blockIdx.y * gsize;
+  const int cend = cbeg + gsize < k ? cbeg + gsize : k;
+  uint4 a[RT][NKB];
 #pragma unroll
-  for (int kb = 0; kb < NKB; ++kb) a[kb] = load_run_al<TC>(P, rows, dim, row0 + c16, kb * KBW + g * VE, true);
-  uint4 pf[PF];
-  auto prefetch = [&](int cc) {
+  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      const int e = tid + 256 * u;
-      const int t = e / (NKB * 64), rem = e - t * (NKB * 64), kb = rem >> 6, l = rem & 63;
-      pf[u] = load_run_al<TC>(Zc, k, dim, cc + 16 * t + (l & 15), kb * KBW + (l >> 4) * VE, e < PER_CHUNK);
+    for (int kb = 0; kb < NKB; ++kb)
+      a[rt][kb] = load_run_al<TC>(P, rows, dim, row0 + rt * 16 + c16, kb * KBW + g * VE, true);
+  // Chunk loads: wave w fills fragment blocks w, w + 4, ...; the norms of this
+  // lane's centres come with them.
+  auto issue = [&](uint4* dst, int cc, double (&znf)[CT]) {
+#pragma unroll
+    for (int u = 0; u < BPW; ++u) {
+      const int blk = wave + 4 * u;
+      if (NBLK % 4 == 0 || blk < NBLK) {
+        const int t = blk / NKB, kb = blk - t * NKB;
+        const int c = cc + 16 * t + c16, k0 = kb * KBW + g * VE;
+        const TC* src = (c < k && k0 < dim) ? Zc + (int64_t)c * dim + k0 : (const TC*)kTileZero;
+        __builtin_amdgcn_global_load_lds((const void*)src, CABS_LDS_PTR(dst + blk * 64), 16, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      const int col = cc + t * 16 + c16;
+      znf[t] = znorm[col < k ? col : k - 1];
     }
   };
-  float best[4], second[4];
-  int bidx[4];
+  float best[RT][4], second[RT][4];
+  int bidx[RT][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) { best[i] = __builtin_huge_valf(); second[i] = __builtin_huge_valf(); bidx[i] = 0x7fffffff; }
-  prefetch(0);
-  for (int cc = 0; cc < k; cc += AF_CT * 16) {
-    __syncthreads();
+  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      const int e = tid + 256 * u;
-      if ((u + 1) * 256 <= PER_CHUNK || e < PER_CHUNK) zs[e] = pf[u];
+    for (int i = 0; i < 4; ++i) {
+      best[rt][i] = __builtin_huge_valf();
+      second[rt][i] = __builtin_huge_valf();
+      bidx[rt][i] = 0x7fffffff;
     }
-    __syncthreads();
-    if (cc + AF_CT * 16 < k) prefetch(cc + AF_CT * 16);
-    AccV acc[AF_CT];
+  auto compute = [&](const uint4* zs, int cc, const double (&znf)[CT]) {
+    AccV acc[RT][CT];
 #pragma unroll
-    for (int t = 0; t < AF_CT; ++t) acc[t] = Mfma<TC>::zero();
-    // tiles of the chunk that hold columns (a compile-time count per case, so
-    // a chunk with fewer than AF_CT tiles skips the empty ones)
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int t = 0; t < CT; ++t) acc[rt][t] = Mfma<TC>::zero();
+    // tiles of the chunk that hold centres of the group (a compile-time count
+    // per case, so a chunk with fewer than CT tiles skips the empty ones)
+    // The B fragments of k block kb + D are read while block kb is multiplied
+    // (D = 2 when a block has fewer than 8 MFMAs per read, so that the LDS
+    // latency stays covered); scheduling barriers keep the compiler from
+    // moving the reads next to their use.
     auto mm = [&](auto ntc) {
       constexpr int NT = decltype(ntc)::value;
+      constexpr int D = RT * SPV * NT >= 8 ? 1 : 2;
+      uint4 bq[D + 1][NT];
+#pragma unroll
+      for (int p = 0; p < D && p < NKB; ++p)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) bq[p][t] = zs[(t * NKB + p) * 64 + lane];
 #pragma unroll
       for (int kb = 0; kb < NKB; ++kb) {
-        uint4 b[NT];
+        if (kb + D < NKB) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t) b[t] = zs[(t * NKB + kb) * 64 + lane];
+          for (int t = 0; t < NT; ++t) bq[(kb + D) % (D + 1)][t] = zs[(t * NKB + kb + D) * 64 + lane];
+        }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int s2 = 0; s2 < SPV; ++s2)
 #pragma unroll
           for (int t = 0; t < NT; ++t)
-            acc[t] = Mfma<TC>::mma(Vec16<TC>::frag(a[kb], s2), Vec16<TC>::frag(b[t], s2), acc[t]);
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+              acc[rt][t] = Mfma<TC>::mma(Vec16<TC>::frag(a[rt][kb], s2), Vec16<TC>::frag(bq[kb % (D + 1)][t], s2),
+                                         acc[rt][t]);
+        __builtin_amdgcn_sched_barrier(0);
       }
     };
-    const int ntile = (k - cc + 15) / 16;
-    static_assert(AF_CT == 2 || AF_CT == 4, "the partial chunks below cover AF_CT = 2 or 4");
-    if (ntile >= AF_CT) mm(std::integral_constant<int, AF_CT>{});
-    else if constexpr (AF_CT == 4) {
-      if (ntile == 1) mm(std::integral_constant<int, 1>{});
-      else if (ntile == 2) mm(std::integral_constant<int, 2>{});
-      else mm(std::integral_constant<int, 3>{});
+    static_assert(CT == 1 || CT == 2, "the partial chunk below covers CT = 1 or 2");
+    if constexpr (CT == 2) {
+      if (cend - cc > 16) mm(std::integral_constant<int, 2>{});
+      else mm(std::integral_constant<int, 1>{});
     } else {
       mm(std::integral_constant<int, 1>{});
     }
+    // Branch-free running (best, index, second): a new strict minimum pushes the
+    // old best to second; otherwise the distance may still lower the second.
+    // Columns past the group are skipped through an infinite distance.
 #pragma unroll
-    for (int t = 0; t < AF_CT; ++t) {
+    for (int t = 0; t < CT; ++t) {
       const int col = cc + t * 16 + c16;
-      if (col < k) {
-        const float zn = (float)znorm[col];
+      const bool in = col < cend;
+      const float zn = (float)znf[t];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const float d = zn - 2.0f * acc[t][i];
-          if (d < best[i]) { second[i] = best[i]; best[i] = d; bidx[i] = col; }
-          else if (d < second[i]) second[i] = d;
+          const float d0 = zn - 2.0f * acc[rt][t][i];
+          const float d = in ? d0 : __builtin_huge_valf();
+          const bool lt = d < best[rt][i];
+          const float s2 = d < second[rt][i] ? d : second[rt][i];
+          second[rt][i] = lt ? best[rt][i] : s2;
+          best[rt][i] = lt ? d : best[rt][i];
+          bidx[rt][i] = lt ? col : bidx[rt][i];
+        }
+    }
+  };
+  double zn0[CT], zn1[CT];
+  issue(zb0, cbeg, zn0);
+  for (int cc = cbeg; cc < cend; cc += 2 * CW) {
+    __builtin_amdgcn_s_waitcnt(0x3f70);  // vmcnt(0): this wave's loads of the chunk in zb0
+    __syncthreads();                     // every wave's loads landed; zb1 is no longer read
+    if (cc + CW < cend) issue(zb1, cc + CW, zn1);
+    compute(zb0, cc, zn0);
+    if (cc + CW >= cend) break;
+    __builtin_amdgcn_s_waitcnt(0x3f70);
+    __syncthreads();
+    if (cc + 2 * CW < cend) issue(zb0, cc + 2 * CW, zn0);
+    compute(zb1, cc + CW, zn1);
+  }
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) {
+        const float ob = __shfl_xor(best[rt][i], off, 64);
+        const int obi = __shfl_xor(bidx[rt][i], off, 64);
+        const float os = __shfl_xor(second[rt][i], off, 64);
+        merge_best(best[rt][i], bidx[rt][i], second[rt][i], ob, obi, os);
+      }
+    }
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t row = row0 + rt * 16 + out_row<TC>(g, i);
+      if (c16 == i && row < rows) {
+        if (pb) {
+          const int64_t o = (int64_t)blockIdx.y * rows + row;
+          pb[o] = best[rt][i];
+          pi[o] = bidx[rt][i];
+          ps[o] = second[rt][i];
+        } else {
+          labels[row] = bidx[rt][i] < k ? bidx[rt][i] : 0;  // all-NaN rows fall back to centre 0
+          const double dd = pnorm[row] + (double)best[rt][i];
+          dmin[row] = dd > 0.0 ? dd : 0.0;
+          if (gap) gap[row] = (double)second[rt][i] - (double)best[rt][i];
         }
       }
     }
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-#pragma unroll
-    for (int off = 1; off < 16; off <<= 1) {
-      const float ob = __shfl_xor(best[i], off, 64);
-      const int obi = __shfl_xor(bidx[i], off, 64);
-      const float os = __shfl_xor(second[i], off, 64);
-      merge_best(best[i], bidx[i], second[i], ob, obi, os);
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t row = row0 + out_row<TC>(g, i);
-    if (c16 == i && row < rows) {
-      labels[row] = bidx[i] < k ? bidx[i] : 0;  // all-NaN rows fall back to centre 0
-      const double dd = pnorm[row] + (double)best[i];
-      dmin[row] = dd > 0.0 ? dd : 0.0;
-      if (gap) gap[row] = (double)second[i] - (double)best[i];
-    }
-  }
 }
 
-// Compiled k-block counts per type (the smallest one >= the needed count is used).
-// 16-bit types reach 512 dimensions (the 10^6-row RBF configuration's k = 500) in the same 64 registers of
-// row fragments that FP32 spends on 256.
-template <typename TC> struct AfNkb { static constexpr int v[5] = {2, 4, 7, 8, 16}; };  // 16-bit types
-template <> struct AfNkb<float> { static constexpr int v[4] = {4, 8, 13, 16}; };
-template <typename TC> constexpr int af_nkb_n() { return (int)(sizeof(AfNkb<TC>::v) / sizeof(int)); }
-template <typename TC> constexpr int af_dim_max() { return AfNkb<TC>::v[af_nkb_n<TC>() - 1] * 4 * (16 / (int)sizeof(TC)); }
+// Combines the G centre groups of assign_fast_kernel in group order.
+__global__ __launch_bounds__(256) void assign_merge_kernel(int64_t rows, int G, int k, const float* __restrict__ pb,
+                                                           const int32_t* __restrict__ pi, const float* __restrict__ ps,
+                                                           const double* __restrict__ pnorm,
+                                                           int32_t* __restrict__ labels, double* __restrict__ dmin,
+                                                           double* __restrict__ gap) {
+  const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (row >= rows) return;
+  float b = pb[row], s = ps[row];
+  int bi = pi[row];
+  for (int q = 1; q < G; ++q) {
+    const int64_t o = (int64_t)q * rows + row;
+    merge_best(b, bi, s, pb[o], pi[o], ps[o]);
+  }
+  labels[row] = bi < k ? bi : 0;
+  const double dd = pnorm[row] + (double)b;
+  dmin[row] = dd > 0.0 ? dd : 0.0;
+  if (gap) gap[row] = (double)s - (double)b;
+}
+
+// Compiled shapes per type: k blocks (the smallest count >= the needed one is
+// used), row tiles per wave, centre tiles per chunk and waves per SIMD.
+// FP32 above 256 dimensions keeps 128 registers of row fragments and streams
+// 16-centre chunks, so that the prefetch fits beside them at 2 waves per SIMD.
+template <typename TC> struct AfShape {
+  static constexpr int n = 5;
+  static constexpr int nkb[n] = {2, 4, 7, 8, 16};
+  static constexpr int rt[n] = {2, 2, 2, 2, 2};
+  static constexpr int ct[n] = {2, 2, 2, 2, 2};
+  static constexpr int occ[n] = {3, 3, 3, 3, 2};
+};
+template <> struct AfShape<float> {
+  static constexpr int n = 6;
+  static constexpr int nkb[n] = {4, 8, 13, 16, 24, 32};
+  static constexpr int rt[n] = {1, 1, 1, 1, 1, 1};
+  static constexpr int ct[n] = {2, 2, 2, 2, 1, 1};
+  static constexpr int occ[n] = {3, 3, 3, 3, 2, 2};
+};
+template <typename TC> constexpr int af_dim_max() { return AfShape<TC>::nkb[AfShape<TC>::n - 1] * 4 * (16 / (int)sizeof(TC)); }
+
+// Number of centre groups for a launch: whole rounds of resident work-groups
+// times (chunks per group + about one chunk's worth of row loading and
+// epilogue), plus half a chunk for the merge when groups are used.
+static int af_groups(int64_t wgs, int nchunk, int64_t slots) {
+  static const int forced = [] {
+    const char* e = getenv("CABS_ASSIGN_GROUPS");  // a fixed group count, for measurements
+    return e ? std::max(0, atoi(e)) : 0;
+  }();
+  if (forced > 0) return std::min(forced, std::min(nchunk, AF_MAXG));
+  int bestG = 1;
+  double bestc = (double)ceil_div(wgs, slots) * (nchunk + 1.0);
+  for (int G = 2; G <= std::min(nchunk, AF_MAXG); ++G) {
+    const int per = (int)ceil_div(nchunk, G);
+    const int Ge = (int)ceil_div(nchunk, per);
+    if (Ge != G) continue;
+    const double c = (double)ceil_div(wgs * G, slots) * (per + 1.0) + 0.5;
+    if (c < bestc) { bestc = c; bestG = G; }
+  }
+  return bestG;
+}
 
 template <typename TC, int I>
 static void assign_fast_launch(int nkb, int64_t rows, int dim, int k, const TC* P, const TC* Zc, const double* znorm,
-                               const double* pnorm, int32_t* labels, double* dmin, double* gap, hipStream_t st) {
-  constexpr int NKB = AfNkb<TC>::v[I];
-  if constexpr (I + 1 < af_nkb_n<TC>()) {
+                               const double* pnorm, int32_t* labels, double* dmin, double* gap, float* pb, int32_t* pi,
+                               float* ps, hipStream_t st) {
+  constexpr int NKB = AfShape<TC>::nkb[I], RT = AfShape<TC>::rt[I], CT = AfShape<TC>::ct[I];
+  constexpr int OCC = AfShape<TC>::occ[I];
+  if constexpr (I + 1 < AfShape<TC>::n) {
     if (nkb > NKB)
-      return assign_fast_launch<TC, I + 1>(nkb, rows, dim, k, P, Zc, znorm, pnorm, labels, dmin, gap, st);
+      return assign_fast_launch<TC, I + 1>(nkb, rows, dim, k, P, Zc, znorm, pnorm, labels, dmin, gap, pb, pi, ps, st);
   }
-  const size_t lds = (size_t)AF_CT * NKB * 64 * 16;
-  hipLaunchKernelGGL((assign_fast_kernel<TC, NKB>), dim3((unsigned)ceil_div(rows, 64)), dim3(256), lds, st, rows, dim,
-                     k, P, Zc, znorm, pnorm, labels, dmin, gap);
+  const int64_t wgs = ceil_div(rows, 64 * RT);
+  const int nchunk = (int)ceil_div(k, CT * 16);
+  const int G = pb ? af_groups(wgs, nchunk, (int64_t)device_cus() * OCC) : 1;
+  const int gsize = (int)ceil_div(nchunk, G) * CT * 16;
+  hipLaunchKernelGGL((assign_fast_kernel<TC, NKB, RT, CT, OCC>), dim3((unsigned)wgs, (unsigned)G), dim3(256), 0, st,
+                     rows, dim, k, gsize, P, Zc, znorm, pnorm, labels, dmin, gap, G > 1 ? pb : nullptr, pi, ps);
+  if (G > 1)
+    hipLaunchKernelGGL(assign_merge_kernel, dim3((unsigned)ceil_div(rows, 256)), dim3(256), 0, st, rows, G, k, pb, pi,
+                       ps, pnorm, labels, dmin, gap);
 }
 
 template <typename TC> struct AssignFast { static constexpr bool ok = true; };
 template <> struct AssignFast<double> { static constexpr bool ok = false; };
 
+// pb / pi / ps: AF_MAXG x rows partials for centre groups (null: one group).
 template <typename TC>
 static void launch_assign(int64_t rows, int dim, int k, const TC* P, const TC* Zc, const double* znorm,
-                          const double* pnorm, int32_t* labels, double* dmin, double* gap, hipStream_t st) {
+                          const double* pnorm, int32_t* labels, double* dmin, double* gap, float* pb, int32_t* pi,
+                          float* ps, hipStream_t st) {
   if constexpr (AssignFast<TC>::ok) {
     constexpr int VE = 16 / (int)sizeof(TC);
     if (dim <= af_dim_max<TC>() && dim % VE == 0 && ((uintptr_t)P % 16) == 0 && ((uintptr_t)Zc % 16) == 0) {
       const int nkb = (dim + 4 * VE - 1) / (4 * VE);
-      assign_fast_launch<TC, 0>(nkb, rows, dim, k, P, Zc, znorm, pnorm, labels, dmin, gap, st);
+      assign_fast_launch<TC, 0>(nkb, rows, dim, k, P, Zc, znorm, pnorm, labels, dmin, gap, pb, pi, ps, st);
       return;
     }
   }
@@ -375,63 +537,97 @@ __device__ __forceinline__ T block_excl_scan_1024(T v, T* wtot, T& total) {
   return base + incl - v;
 }
 
-// One workgroup.  offs = exclusive scan of hist (label-major); label ranges;
-// chunk table; cluster-size maximum.  All scans are block-parallel.
+// The exclusive scan of hist (label-major, k x nsb entries) runs over tiles of
+// SC_TILE entries, one work-group each: scan_tile_sum_kernel sums every tile,
+// scan_kernel adds the sums of the earlier tiles (in tile order) to its own
+// block scan and writes the offsets and the start of every label whose first
+// entry lies in the tile; label_chunks_kernel then forms cluster sizes, the
+// chunk table and the largest cluster from the label starts.
+constexpr int SC_R = 16;               // entries per thread
+constexpr int SC_TILE = 1024 * SC_R;   // entries per tile
+
+// Entries [e0, e0 + SC_R) of hist (16-byte loads when whole; hist is 16-byte
+// aligned and e0 a multiple of SC_R).
+__device__ __forceinline__ void scan_load(const int32_t* __restrict__ hist, int64_t L, int64_t e0, int32_t (&c)[SC_R]) {
+  if (e0 + SC_R <= L) {
+#pragma unroll
+    for (int i = 0; i < SC_R; i += 4) {
+      const int4 q = *(const int4*)(hist + e0 + i);
+      c[i] = q.x; c[i + 1] = q.y; c[i + 2] = q.z; c[i + 3] = q.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < SC_R; ++i) c[i] = e0 + i < L ? hist[e0 + i] : 0;
+  }
+}
+
+__global__ __launch_bounds__(1024) void scan_tile_sum_kernel(int64_t L, const int32_t* __restrict__ hist,
+                                                             int32_t* __restrict__ tsum) {
+  __shared__ int32_t wtot[16];
+  const int64_t e0 = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_R;
+  int32_t c[SC_R];
+  scan_load(hist, L, e0, c);
+  int32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < SC_R; ++i) s += c[i];
+  int32_t total;
+  block_excl_scan_1024<int32_t>(s, wtot, total);
+  if (threadIdx.x == 0) tsum[blockIdx.x] = total;
+}
+
 __global__ __launch_bounds__(1024) void scan_kernel(int k, int64_t nsb, const int32_t* __restrict__ hist,
-                                                    int32_t* __restrict__ offs, int32_t* __restrict__ lstart,
-                                                    int32_t* __restrict__ chunk_lab, int32_t* __restrict__ chunk_beg,
-                                                    int32_t* __restrict__ chunk_end, int32_t* __restrict__ lchunk,
-                                                    int32_t* __restrict__ nchunks_out, double* __restrict__ tmax_out) {
+                                                    const int32_t* __restrict__ tsum, int32_t* __restrict__ offs,
+                                                    int32_t* __restrict__ lstart) {
+  __shared__ int32_t wtot[16];
+  const int tid = threadIdx.x;
+  const int64_t L = (int64_t)k * nsb;
+  const int t = blockIdx.x;
+  // carry = sum of the earlier tiles' totals (integers: any order is exact)
+  int32_t part = 0;
+  for (int q = tid; q < t; q += 1024) part += tsum[q];
+  int32_t carry;
+  block_excl_scan_1024<int32_t>(part, wtot, carry);
+  const int64_t e0 = (int64_t)t * SC_TILE + (int64_t)tid * SC_R;
+  int32_t c[SC_R];
+  scan_load(hist, L, e0, c);
+  int32_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < SC_R; ++i) sum += c[i];
+  int32_t tile_total;
+  int32_t run = block_excl_scan_1024<int32_t>(sum, wtot, tile_total) + carry;
+  int32_t lab = (int32_t)(e0 / nsb), rem = (int32_t)(e0 - (int64_t)lab * nsb);
+#pragma unroll
+  for (int i = 0; i < SC_R; ++i) {
+    const int64_t e = e0 + i;
+    if (e < L) {
+      offs[e] = run;
+      if (rem == 0) lstart[lab] = run;
+    }
+    run += c[i];
+    if (++rem == nsb) { rem = 0; ++lab; }
+  }
+  if (t == (int)gridDim.x - 1 && tid == 0) lstart[k] = carry + tile_total;
+}
+
+// One workgroup: cluster sizes from the label starts, the chunk table (an
+// exclusive scan of the chunk counts) and the largest cluster.
+__global__ __launch_bounds__(1024) void label_chunks_kernel(int k, const int32_t* __restrict__ lstart,
+                                                            int32_t* __restrict__ chunk_lab,
+                                                            int32_t* __restrict__ chunk_beg,
+                                                            int32_t* __restrict__ chunk_end,
+                                                            int32_t* __restrict__ lchunk,
+                                                            int32_t* __restrict__ nchunks_out,
+                                                            double* __restrict__ tmax_out) {
   __shared__ int32_t wtot32[16];
   __shared__ int32_t lst[KM_MAXK + 1];
   __shared__ int32_t lch[KM_MAXK + 1];
   const int tid = threadIdx.x;
-  const int64_t L = (int64_t)k * nsb;
-  // Tiles of 1024 x SC_R entries: thread t owns entries [t SC_R, (t + 1) SC_R)
-  // of the tile (loaded together), scans them serially, and a block scan of
-  // the thread sums plus the running total of the earlier tiles gives the
-  // offsets.  The start of label j is the offset of its first block, j nsb.
-  constexpr int SC_R = 16;
-  int32_t carry = 0;
-  for (int64_t t0 = 0; t0 < L; t0 += 1024 * SC_R) {
-    const int64_t e0 = t0 + (int64_t)tid * SC_R;
-    int32_t c[SC_R];
-    if (e0 + SC_R <= L) {  // whole run: 16-byte loads (hist is 16-byte aligned, e0 a multiple of SC_R)
-#pragma unroll
-      for (int i = 0; i < SC_R; i += 4) {
-        const int4 q = *(const int4*)(hist + e0 + i);
-        c[i] = q.x; c[i + 1] = q.y; c[i + 2] = q.z; c[i + 3] = q.w;
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < SC_R; ++i) c[i] = e0 + i < L ? hist[e0 + i] : 0;
-    }
-    int32_t sum = 0;
-#pragma unroll
-    for (int i = 0; i < SC_R; ++i) sum += c[i];
-    int32_t tile_total;
-    int32_t run = block_excl_scan_1024<int32_t>(sum, wtot32, tile_total) + carry;
-    int32_t lab = (int32_t)(e0 / nsb), rem = (int32_t)(e0 - (int64_t)lab * nsb);
-#pragma unroll
-    for (int i = 0; i < SC_R; ++i) {
-      const int64_t e = e0 + i;
-      if (e < L) {
-        offs[e] = run;
-        if (rem == 0) lst[lab] = run;
-      }
-      run += c[i];
-      if (++rem == nsb) { rem = 0; ++lab; }
-    }
-    carry += tile_total;
-  }
-  if (tid == 0) lst[k] = carry;
+  for (int j = tid; j <= k; j += 1024) lst[j] = lstart[j];
   __syncthreads();
-  // labels: counts, chunks (exclusive scan of the chunk counts), largest cluster
   int32_t cnt = 0, nch = 0;
   if (tid < k) {
     cnt = lst[tid + 1] - lst[tid];
     nch = (cnt + CENT_CH - 1) / CENT_CH;
-    lstart[tid] = lst[tid];
   }
   int32_t nch_total;
   const int32_t ch0 = block_excl_scan_1024<int32_t>(nch, wtot32, nch_total);
@@ -447,8 +643,8 @@ __global__ __launch_bounds__(1024) void scan_kernel(int k, int64_t nsb, const in
     lchunk[k] = nch_total;
     *nchunks_out = nch_total;
     if (tmax_out) *tmax_out = (double)m;
+    lch[k] = nch_total;
   }
-  if (tid == 0) lch[k] = nch_total;
   __syncthreads();
   // chunk table: chunk c belongs to the label j with lch[j] <= c < lch[j + 1]
   // (labels without rows have lch[j] == lch[j + 1] and never match)
@@ -1065,6 +1261,7 @@ struct KmWs {
   int32_t* chunk_lab; int32_t* chunk_beg; int32_t* chunk_end; int32_t* lchunk; int32_t* nchunks;
   double* part; double* partw; double* red_s; double* red_g; double* obj_tmp; double* tmax_tmp; double* gap_tmp;
   double* cand_d; int32_t* cand_r; double* top_d; int32_t* top_r;
+  float* apb; int32_t* api; float* aps; int32_t* tsum;
   size_t total;
 };
 
@@ -1114,6 +1311,10 @@ static KmWs km_layout(void* base, int64_t rows, int dim, int k, int compute) {
   w.cand_r = (int32_t*)take((size_t)k * nblk * SNAP_T * 4);
   w.top_d = (double*)take((size_t)k * SNAP_T * 8);
   w.top_r = (int32_t*)take((size_t)k * SNAP_T * 4);
+  w.apb = (float*)take((size_t)AF_MAXG * rows * 4);
+  w.api = (int32_t*)take((size_t)AF_MAXG * rows * 4);
+  w.aps = (float*)take((size_t)AF_MAXG * rows * 4);
+  w.tsum = (int32_t*)take((size_t)ceil_div((int64_t)k * nsb, SC_TILE) * 4);
   w.total = off;
   return w;
 }
@@ -1133,6 +1334,7 @@ static hipError_t kmeans_t(int compute, int64_t rows, int dim, int k, const void
   const int64_t maxch = ceil_div(rows, CENT_CH) + k;
   int32_t* labels = out.labels ? out.labels : W.labels;
   const int red_nb = (int)(rows < RED_NB * 256 ? ceil_div(rows, 256) : RED_NB);
+  const unsigned ntile = (unsigned)ceil_div((int64_t)k * nsb, SC_TILE);
 
   if (Z0 != out.Z)
     hipLaunchKernelGGL(copy_f64_kernel, dim3((unsigned)ceil_div((int64_t)k * dim, 256)), dim3(256), 0, st,
@@ -1144,7 +1346,8 @@ static hipError_t kmeans_t(int compute, int64_t rows, int dim, int k, const void
     const bool last = it == iters;
     {
       TimerScope ts(T_ASSIGN, st);
-      launch_assign<TC>(rows, dim, k, P, (const TC*)Zc, W.znorm, W.pnorm, labels, W.dmin, last ? W.gap : nullptr, st);
+      launch_assign<TC>(rows, dim, k, P, (const TC*)Zc, W.znorm, W.pnorm, labels, W.dmin, last ? W.gap : nullptr,
+                        W.apb, W.api, W.aps, st);
     }
     if (it == 0 || last) {
       hipLaunchKernelGGL(wsum_partial_kernel, dim3(red_nb), dim3(256), 0, st, rows, w, W.dmin,
@@ -1157,8 +1360,10 @@ static hipError_t kmeans_t(int compute, int64_t rows, int dim, int k, const void
     }
     hipLaunchKernelGGL(label_hist_kernel, dim3((unsigned)nsb), dim3(HIST_SB), 0, st, rows, k, labels, W.hist,
                        W.rank_blk, nsb);
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, k, nsb, W.hist, W.offs, W.lstart, W.chunk_lab,
-                       W.chunk_beg, W.chunk_end, W.lchunk, W.nchunks, last ? (out.tmax ? out.tmax : W.tmax_tmp) : nullptr);
+    hipLaunchKernelGGL(scan_tile_sum_kernel, dim3(ntile), dim3(1024), 0, st, (int64_t)k * nsb, W.hist, W.tsum);
+    hipLaunchKernelGGL(scan_kernel, dim3(ntile), dim3(1024), 0, st, k, nsb, W.hist, W.tsum, W.offs, W.lstart);
+    hipLaunchKernelGGL(label_chunks_kernel, dim3(1), dim3(1024), 0, st, k, W.lstart, W.chunk_lab, W.chunk_beg,
+                       W.chunk_end, W.lchunk, W.nchunks, last ? (out.tmax ? out.tmax : W.tmax_tmp) : nullptr);
     if (last) break;
     hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)ceil_div(rows, 256)), dim3(256), 0, st, rows, nsb, labels,
                        W.rank_blk, W.offs, W.sorted);

@@ -292,18 +292,23 @@ def test_snap_duplicate_rows_across_blocks_f64(api):
     assert np.array_equal(sn.cpu().numpy(), oc.snap(p, z0))
 
 
-@pytest.mark.parametrize("dim,dt", [(320, "bf16"), (512, "bf16"), (512, "f16"), (20, "bf16"), (36, "f16")])
-def test_kmeans_wide_16bit_fast_path_matches_generic(api, dim, dt):
-    """16-bit k-means against the element-load path on the same values (a copy starting 2 bytes
-    past a 16-byte boundary loads element by element).  257-512 dimensions: the fast assignment
-    kernel's 16 k-block case; 20 and 36 dimensions (multiples of 4, not of 8): the tile kernels'
-    8-byte pieces.  All keep the same per-lane k order, so labels, centres, objective and
-    snapped rows are bit-identical."""
-    dtype = {"bf16": torch.bfloat16, "f16": torch.float16}[dt]
-    rng = np.random.default_rng(dim)
-    rows = 4000
+@pytest.mark.parametrize("dim,dt,rows,k", [(320, "bf16", 4000, 48), (512, "bf16", 4000, 48), (512, "f16", 4000, 48),
+                                           (20, "bf16", 4000, 48), (36, "f16", 4000, 48), (500, "f32", 4000, 48),
+                                           (200, "f32", 4000, 48), (384, "f32", 30000, 100),
+                                           (200, "bf16", 20000, 200), (504, "bf16", 60000, 500)])
+def test_kmeans_fast_path_matches_generic(api, dim, dt, rows, k):
+    """k-means through the fast assignment kernel against the generic tile kernel on the same
+    values (a copy starting one element past a 16-byte boundary takes the generic path).
+    257-512 dimensions: the fast kernel's widest k-block cases (FP32 above 256 dimensions
+    streams 16-centre chunks); 20 and 36 dimensions (multiples of 4, not of 8): the tile
+    kernels' 8-byte pieces.  The shapes cover one centre group and the 2-4 groups merged
+    when the rows are too few to fill the chip (4000 rows; 2e4 rows x 200 centres in BF16).
+    All keep the same per-element MFMA order, so labels, centres, objective and snapped rows
+    are bit-identical."""
+    dtype = {"bf16": torch.bfloat16, "f16": torch.float16, "f32": torch.float32}[dt]
+    rng = np.random.default_rng(dim + rows)
     p = rng.normal(size=(rows, dim)).astype(np.float32)
-    z0 = torch.from_numpy(p[:48].astype(np.float64)).cuda()
+    z0 = torch.from_numpy(p[:k].astype(np.float64)).cuda()
     w = torch.ones(rows, dtype=torch.float64, device="cuda")
     pa = torch.from_numpy(p).to(dtype).cuda()
     buf = torch.empty(rows * dim + 1, dtype=dtype, device="cuda")
