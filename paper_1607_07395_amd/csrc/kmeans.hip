@@ -396,9 +396,10 @@ __global__ __launch_bounds__(256) void assign_merge_kernel(int64_t rows, int G, 
 }
 
 // Compiled shapes per type: k blocks (the smallest count >= the needed one is
-// used), row tiles per wave, centre tiles per chunk and waves per SIMD.
-// FP32 above 256 dimensions keeps 128 registers of row fragments and streams
-// 16-centre chunks, so that the prefetch fits beside them at 2 waves per SIMD.
+// used), row tiles per wave, centre tiles per chunk and waves per SIMD.  The
+// two chunk buffers (2 x CT x NKB KB) must leave room in the CU's 160 KB of
+// LDS for that many work-groups: FP32 streams 16-centre chunks from 193
+// dimensions on.
 template <typename TC> struct AfShape {
   static constexpr int n = 5;
   static constexpr int nkb[n] = {2, 4, 7, 8, 16};
@@ -410,7 +411,7 @@ template <> struct AfShape<float> {
   static constexpr int n = 6;
   static constexpr int nkb[n] = {4, 8, 13, 16, 24, 32};
   static constexpr int rt[n] = {1, 1, 1, 1, 1, 1};
-  static constexpr int ct[n] = {2, 2, 2, 2, 1, 1};
+  static constexpr int ct[n] = {2, 2, 2, 1, 1, 1};
   static constexpr int occ[n] = {3, 3, 3, 3, 2, 2};
 };
 template <typename TC> constexpr int af_dim_max() { return AfShape<TC>::nkb[AfShape<TC>::n - 1] * 4 * (16 / (int)sizeof(TC)); }

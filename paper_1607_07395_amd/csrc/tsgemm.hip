@@ -20,16 +20,18 @@ namespace cabs {
 constexpr int TS_NT = 8;
 constexpr int TS_MAXN = 1024;
 
+// Bt (N x Kp, Kp >= K) = B^T in the compute precision, zeros in columns K..Kp-1.
 template <typename TC>
-__global__ __launch_bounds__(256) void convert_bt_kernel(int K, int N, const double* __restrict__ B, TC* __restrict__ Bt) {
+__global__ __launch_bounds__(256) void convert_bt_kernel(int K, int Kp, int N, const double* __restrict__ B,
+                                                         TC* __restrict__ Bt) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= K * N) return;
-  const int n = e / K, k = e % K;
-  Bt[e] = from_f64<TC>(B[(int64_t)k * N + n]);
+  if (e >= Kp * N) return;
+  const int n = e / Kp, k = e % Kp;
+  Bt[e] = k < K ? from_f64<TC>(B[(int64_t)k * N + n]) : from_f64<TC>(0.0);
 }
 
 template <typename TC>
-__global__ __launch_bounds__(256) void tsgemm_kernel(int64_t M, int K, int N, const TC* __restrict__ X,
+__global__ __launch_bounds__(256) void tsgemm_kernel(int64_t M, int K, int Kp, int N, const TC* __restrict__ X,
                                                      const TC* __restrict__ Bt, TC* __restrict__ Y,
                                                      double* __restrict__ colpart, double* __restrict__ rowsq) {
   typedef typename Mfma<TC>::acc AccV;
@@ -45,7 +47,7 @@ __global__ __launch_bounds__(256) void tsgemm_kernel(int64_t M, int K, int N, co
     AccV acc[TS_NT];
     NrmT xs, ysq[TS_NT];
     if (active) {
-      gemm_tile<TC, TC, TS_NT, false>(X, K, M, row0, Bt, K, nullptr, N, col0, nullptr, K, acc, xs, ysq);
+      gemm_tile<TC, TC, TS_NT, false>(X, K, M, row0, Bt, Kp, nullptr, N, col0, nullptr, K, acc, xs, ysq);
     } else {
 #pragma unroll
       for (int t = 0; t < TS_NT; ++t) acc[t] = Mfma<TC>::zero();
@@ -87,97 +89,153 @@ __global__ __launch_bounds__(256) void tsgemm_kernel(int64_t M, int K, int N, co
   }
 }
 
-// Fast path for K <= 256 (512 for 16-bit types), rows of X and B^T whole 16-byte runs (K a
-// multiple of 16 / sizeof(TC), X 16-byte aligned): a workgroup (4 waves, 64 rows) keeps its rows
-// of X as 16-byte MFMA fragment runs in registers for the whole kernel and
-// streams B^T through LDS in chunks of CT column tiles, stored in fragment
-// order (each B read is one contiguous 16-byte LDS read per lane); the next
-// chunk is loaded into registers while the current one is multiplied.  Same
+// Fast path for K <= 512 (FP32, 16-bit) or 256 (FP64): a workgroup (4 waves)
+// keeps its rows of X as 16-byte MFMA fragment runs in registers for the
+// whole kernel (RT row tiles of 16 per wave) and streams B^T through LDS in
+// chunks of CT column tiles, stored in fragment order (each B read is one
+// contiguous 16-byte LDS read per lane).  Chunks are double-buffered in two
+// LDS arrays filled by direct global-to-LDS loads (one global_load_lds_dwordx4
+// per 1 KB fragment block), so chunk c + 1 is in flight while chunk c is
+// multiplied; the B fragments of k block kb + D are read while block kb is
+// multiplied.  B^T is stored with its rows padded to whole runs (zeros), so
+// every B load is a whole run; rows of X that are not whole runs (K not a
+// multiple of 16 / sizeof(TC), or X not 16-byte aligned) are loaded once per
+// kernel in 8-byte pieces or element by element, with zeros past K.  Same
 // outputs as tsgemm_kernel (Y, FP64 row and per-block column sums of squares).
-template <typename TC> struct TsfCT { static constexpr int v = 2; };
-template <> struct TsfCT<double> { static constexpr int v = 1; };
+// Compiled shapes per type: k blocks (the smallest count >= the needed one is
+// used), row tiles per wave, column tiles per chunk and waves per SIMD.  The
+// chunk buffers and the column sums (4 N doubles) must leave room in the
+// CU's 160 KB of LDS for that many work-groups; 16-bit rows of 512 columns
+// take 128 registers, so one row tile per wave (two spill).
+template <typename TC> struct TsfShape {
+  static constexpr int n = 5;
+  static constexpr int nkb[n] = {2, 4, 7, 8, 16};
+  static constexpr int rt[n] = {2, 2, 2, 2, 1};
+  static constexpr int ct[n] = {2, 2, 2, 2, 2};
+  static constexpr int occ[n] = {3, 3, 3, 2, 2};
+};
+template <> struct TsfShape<float> {
+  static constexpr int n = 6;
+  static constexpr int nkb[n] = {4, 8, 13, 16, 24, 32};
+  static constexpr int rt[n] = {1, 1, 1, 1, 1, 1};
+  static constexpr int ct[n] = {2, 2, 1, 1, 1, 1};
+  static constexpr int occ[n] = {3, 3, 3, 3, 2, 2};
+};
+template <> struct TsfShape<double> {  // FP64 rows of K <= 256 fill 128 registers
+  static constexpr int n = 4;
+  static constexpr int nkb[n] = {8, 16, 25, 32};
+  static constexpr int rt[n] = {1, 1, 1, 1};
+  static constexpr int ct[n] = {1, 1, 1, 1};
+  static constexpr int occ[n] = {1, 1, 1, 1};
+};
+template <typename TC> constexpr int tsf_k_max() { return TsfShape<TC>::nkb[TsfShape<TC>::n - 1] * 4 * (16 / (int)sizeof(TC)); }
 
+#define CABS_TS_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
+
+// A run of row `row` of X from column k0: a whole 16-byte load when the rows
+// are whole aligned runs (mode 0), else 8-byte pieces of four 16-bit values
+// (mode 1: K a multiple of 4, 8-byte aligned rows) or single elements
+// (mode 2); zeros past K or M.
 template <typename TC>
-static size_t tsf_lds_bytes(int nkb, int N) {
-  return (size_t)TsfCT<TC>::v * nkb * 64 * 16 + (size_t)4 * N * sizeof(double);
+__device__ __forceinline__ uint4 tsf_load_a(const TC* __restrict__ X, int64_t M, int K, int64_t row, int k0, int mode) {
+  constexpr int VE = 16 / sizeof(TC);
+  if (mode == 0) return load_run_al<TC>(X, M, K, row, k0, true);
+  uint4 v = {0u, 0u, 0u, 0u};
+  if (row >= M) return v;
+  const TC* p = X + row * K;
+  if (mode == 1) {
+    uint2* w = (uint2*)&v;
+#pragma unroll
+    for (int q = 0; q < VE / 4; ++q)
+      if (k0 + 4 * q < K) w[q] = *(const uint2*)(p + k0 + 4 * q);
+  } else {
+    TC* e = (TC*)&v;
+#pragma unroll
+    for (int q = 0; q < VE; ++q)
+      if (k0 + q < K) e[q] = p[k0 + q];
+  }
+  return v;
 }
 
-template <typename TC> struct TsfOcc { static constexpr int v = 3; };
-template <> struct TsfOcc<double> { static constexpr int v = 1; };  // FP64 rows of K <= 256 fill 128 registers
-
-// NKB (k blocks of 4 runs) is a compile-time constant, so the loads, the LDS
-// stores and the MFMA sequence carry no run-time guards; k blocks past K read
-// zeros.
-template <typename TC, int NKB>
-__global__ __launch_bounds__(256, TsfOcc<TC>::v) void tsgemm_fast_kernel(int64_t M, int K, int N,
-                                                                         const TC* __restrict__ X,
-                                                                         const TC* __restrict__ Bt,
-                                                                         TC* __restrict__ Y,
-                                                                         double* __restrict__ colpart,
-                                                                         double* __restrict__ rowsq) {
+// NKB (k blocks of 4 runs) is a compile-time constant, so the B loads and the
+// MFMA sequence carry no run-time guards; k blocks past K read zeros.
+template <typename TC, int NKB, int RT, int CT, int OCC>
+__global__ __launch_bounds__(256, OCC) void tsgemm_fast_kernel(int64_t M, int K, int Kp, int N, int amode,
+                                                               const TC* __restrict__ X, const TC* __restrict__ Bt,
+                                                               TC* __restrict__ Y, double* __restrict__ colpart,
+                                                               double* __restrict__ rowsq) {
   typedef typename Mfma<TC>::acc AccV;
-  constexpr int CT = TsfCT<TC>::v;
   constexpr int VE = 16 / sizeof(TC);          // elements per 16-byte run
   constexpr int SPV = VE / Mfma<TC>::KPL;      // MFMA steps per run
   constexpr int KBW = 4 * VE;                  // k per block (4 lane groups)
-  constexpr int PER_CHUNK = CT * NKB * 64;     // runs per chunk
-  constexpr int PF = (PER_CHUNK + 255) / 256;  // prefetch runs per thread
-  extern __shared__ uint4 tsf_lds[];
-  uint4* bs = tsf_lds;                                  // [CT][NKB][64] runs
-  double* cp = (double*)(tsf_lds + PER_CHUNK);          // [4][N] per-wave column sums
+  constexpr int NBLK = CT * NKB;               // 1 KB fragment blocks per chunk
+  constexpr int BPW = (NBLK + 3) / 4;          // blocks issued per wave
+  constexpr int CW = CT * 16;                  // columns per chunk
+  __shared__ uint4 bb0[NBLK * 64];             // [CT][NKB][64] runs
+  __shared__ uint4 bb1[NBLK * 64];
+  extern __shared__ double tsf_cp[];           // [4][N] per-wave column sums
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int g = lane >> 4, c16 = lane & 15;
-  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
-  uint4 a[NKB];
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * RT);
+  uint4 a[RT][NKB];
 #pragma unroll
-  for (int kb = 0; kb < NKB; ++kb) a[kb] = load_run_al<TC>(X, M, K, row0 + c16, kb * KBW + g * VE, true);
-  uint4 pf[PF];
-  auto prefetch = [&](int cc) {
+  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      const int e = tid + 256 * u;
-      const int t = e / (NKB * 64), rem = e - t * (NKB * 64), kb = rem >> 6, l = rem & 63;
-      pf[u] = load_run_al<TC>(Bt, N, K, cc + 16 * t + (l & 15), kb * KBW + (l >> 4) * VE, e < PER_CHUNK);
+    for (int kb = 0; kb < NKB; ++kb) a[rt][kb] = tsf_load_a<TC>(X, M, K, row0 + rt * 16 + c16, kb * KBW + g * VE, amode);
+  auto issue = [&](uint4* dst, int cc) {
+#pragma unroll
+    for (int u = 0; u < BPW; ++u) {
+      const int blk = wave + 4 * u;
+      if (NBLK % 4 == 0 || blk < NBLK) {
+        const int t = blk / NKB, kb = blk - t * NKB;
+        const int c = cc + 16 * t + c16, k0 = kb * KBW + g * VE;
+        const TC* src = (c < N && k0 < Kp) ? Bt + (int64_t)c * Kp + k0 : (const TC*)kTileZero;
+        __builtin_amdgcn_global_load_lds((const void*)src, CABS_TS_LDS_PTR(dst + blk * 64), 16, 0, 0);
+      }
     }
   };
-  double rs[4] = {0.0, 0.0, 0.0, 0.0};
-  prefetch(0);
-  for (int cc = 0; cc < N; cc += CT * 16) {
-    __syncthreads();
+  double rs[RT][4];
 #pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      const int e = tid + 256 * u;
-      if ((u + 1) * 256 <= PER_CHUNK || e < PER_CHUNK) bs[e] = pf[u];
-    }
-    __syncthreads();
-    if (cc + CT * 16 < N) prefetch(cc + CT * 16);
-    AccV acc[CT];
+  for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-    for (int t = 0; t < CT; ++t) acc[t] = Mfma<TC>::zero();
-    // tiles of the chunk that hold columns (a compile-time count per case, so
-    // a chunk with fewer than CT tiles skips the empty ones)
+    for (int i = 0; i < 4; ++i) rs[rt][i] = 0.0;
+  auto compute = [&](const uint4* bs, int cc) {
+    AccV acc[RT][CT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int t = 0; t < CT; ++t) acc[rt][t] = Mfma<TC>::zero();
     auto mm = [&](auto ntc) {
       constexpr int NT = decltype(ntc)::value;
+      constexpr int D = RT * SPV * NT >= 8 ? 1 : 2;
+      uint4 bq[D + 1][NT];
+#pragma unroll
+      for (int p = 0; p < D && p < NKB; ++p)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) bq[p][t] = bs[(t * NKB + p) * 64 + lane];
 #pragma unroll
       for (int kb = 0; kb < NKB; ++kb) {
-        uint4 b[NT];
+        if (kb + D < NKB) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t) b[t] = bs[(t * NKB + kb) * 64 + lane];
+          for (int t = 0; t < NT; ++t) bq[(kb + D) % (D + 1)][t] = bs[(t * NKB + kb + D) * 64 + lane];
+        }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int s2 = 0; s2 < SPV; ++s2)
 #pragma unroll
           for (int t = 0; t < NT; ++t)
-            acc[t] = Mfma<TC>::mma(Vec16<TC>::frag(a[kb], s2), Vec16<TC>::frag(b[t], s2), acc[t]);
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+              acc[rt][t] = Mfma<TC>::mma(Vec16<TC>::frag(a[rt][kb], s2), Vec16<TC>::frag(bq[kb % (D + 1)][t], s2),
+                                         acc[rt][t]);
+        __builtin_amdgcn_sched_barrier(0);
       }
     };
-    const int ntile = (N - cc + 15) / 16;
-    static_assert(CT == 1 || CT == 2 || CT == 4, "the partial chunks below cover CT = 1, 2 or 4");
-    if (ntile >= CT) mm(std::integral_constant<int, CT>{});
-    else if constexpr (CT == 4) {
-      if (ntile == 1) mm(std::integral_constant<int, 1>{});
-      else if (ntile == 2) mm(std::integral_constant<int, 2>{});
-      else mm(std::integral_constant<int, 3>{});
-    } else if constexpr (CT == 2) {
+    static_assert(CT == 1 || CT == 2, "the partial chunk below covers CT = 1 or 2");
+    if constexpr (CT == 2) {
+      if (N - cc > 16) mm(std::integral_constant<int, 2>{});
+      else mm(std::integral_constant<int, 1>{});
+    } else {
       mm(std::integral_constant<int, 1>{});
     }
 #pragma unroll
@@ -185,56 +243,67 @@ __global__ __launch_bounds__(256, TsfOcc<TC>::v) void tsgemm_fast_kernel(int64_t
       const int col = cc + t * 16 + c16;
       double cs = 0.0;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int64_t row = row0 + out_row<TC>(g, i);
-        const bool ok = row < M && col < N;
-        const double v = ok ? (double)acc[t][i] : 0.0;
-        if (ok && Y != nullptr) Y[row * N + col] = from_f64<TC>(v);
-        rs[i] += v * v;
-        cs += v * v;
-      }
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int64_t row = row0 + rt * 16 + out_row<TC>(g, i);
+          const bool ok = row < M && col < N;
+          const double v = ok ? (double)acc[rt][t][i] : 0.0;
+          if (ok && Y != nullptr) Y[row * N + col] = from_f64<TC>(v);
+          rs[rt][i] += v * v;
+          cs += v * v;
+        }
       cs += __shfl_xor(cs, 16, 64);
       cs += __shfl_xor(cs, 32, 64);
-      if (colpart != nullptr && g == 0 && col < N) cp[wave * N + col] = cs;
+      if (colpart != nullptr && g == 0 && col < N) tsf_cp[wave * N + col] = cs;
     }
+  };
+  issue(bb0, 0);
+  for (int cc = 0; cc < N; cc += 2 * CW) {
+    __builtin_amdgcn_s_waitcnt(0x3f70);  // vmcnt(0): this wave's loads of the chunk in bb0
+    __syncthreads();                     // every wave's loads landed; bb1 is no longer read
+    if (cc + CW < N) issue(bb1, cc + CW);
+    compute(bb0, cc);
+    if (cc + CW >= N) break;
+    __builtin_amdgcn_s_waitcnt(0x3f70);
+    __syncthreads();
+    if (cc + 2 * CW < N) issue(bb0, cc + 2 * CW);
+    compute(bb1, cc + CW);
   }
   if (rowsq != nullptr) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      double v = rs[i];
-      v += __shfl_xor(v, 1, 64);
-      v += __shfl_xor(v, 2, 64);
-      v += __shfl_xor(v, 4, 64);
-      v += __shfl_xor(v, 8, 64);
-      const int64_t row = row0 + out_row<TC>(g, i);
-      if (c16 == 0 && row < M) rowsq[row] = v;
-    }
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        double v = rs[rt][i];
+        v += __shfl_xor(v, 1, 64);
+        v += __shfl_xor(v, 2, 64);
+        v += __shfl_xor(v, 4, 64);
+        v += __shfl_xor(v, 8, 64);
+        const int64_t row = row0 + rt * 16 + out_row<TC>(g, i);
+        if (c16 == 0 && row < M) rowsq[row] = v;
+      }
   }
   if (colpart != nullptr) {
     __syncthreads();
     for (int col = tid; col < N; col += 256)
-      colpart[(int64_t)blockIdx.x * N + col] = ((cp[col] + cp[N + col]) + cp[2 * N + col]) + cp[3 * N + col];
+      colpart[(int64_t)blockIdx.x * N + col] =
+          ((tsf_cp[col] + tsf_cp[N + col]) + tsf_cp[2 * N + col]) + tsf_cp[3 * N + col];
   }
 }
 
-// Compiled k-block counts per type (the smallest one >= the needed count is used).
-template <typename TC> struct TsfNkb;
-template <> struct TsfNkb<float> { static constexpr int v[4] = {4, 8, 13, 16}; };
-template <> struct TsfNkb<double> { static constexpr int v[4] = {8, 16, 25, 32}; };
-template <> struct TsfNkb<bf16> { static constexpr int v[5] = {2, 4, 7, 8, 16}; };  // to K = 512
-template <> struct TsfNkb<f16> { static constexpr int v[5] = {2, 4, 7, 8, 16}; };
-template <typename TC> constexpr int tsf_nkb_n() { return (int)(sizeof(TsfNkb<TC>::v) / sizeof(int)); }
-template <typename TC> constexpr int tsf_k_max() { return TsfNkb<TC>::v[tsf_nkb_n<TC>() - 1] * 4 * (16 / (int)sizeof(TC)); }
-
 template <typename TC, int I>
-static void tsf_launch_i(int nkb, dim3 grid, hipStream_t st, int64_t M, int K, int N, const TC* X, const TC* Bt, TC* Y,
-                         double* colpart, double* rowsq) {
-  constexpr int NKB = TsfNkb<TC>::v[I];
-  if constexpr (I + 1 < tsf_nkb_n<TC>()) {
-    if (nkb > NKB) return tsf_launch_i<TC, I + 1>(nkb, grid, st, M, K, N, X, Bt, Y, colpart, rowsq);
+static int64_t tsf_launch_i(int nkb, hipStream_t st, int64_t M, int K, int Kp, int N, int amode, const TC* X,
+                            const TC* Bt, TC* Y, double* colpart, double* rowsq) {
+  constexpr int NKB = TsfShape<TC>::nkb[I], RT = TsfShape<TC>::rt[I], CT = TsfShape<TC>::ct[I];
+  constexpr int OCC = TsfShape<TC>::occ[I];
+  if constexpr (I + 1 < TsfShape<TC>::n) {
+    if (nkb > NKB) return tsf_launch_i<TC, I + 1>(nkb, st, M, K, Kp, N, amode, X, Bt, Y, colpart, rowsq);
   }
-  hipLaunchKernelGGL((tsgemm_fast_kernel<TC, NKB>), grid, dim3(256), tsf_lds_bytes<TC>(NKB, N), st, M, K, N, X, Bt, Y,
-                     colpart, rowsq);
+  const int64_t nb = ceil_div(M, 64 * RT);
+  hipLaunchKernelGGL((tsgemm_fast_kernel<TC, NKB, RT, CT, OCC>), dim3((unsigned)nb), dim3(256),
+                     (size_t)4 * N * sizeof(double), st, M, K, Kp, N, amode, X, Bt, Y, colpart, rowsq);
+  return nb;
 }
 
 // out[c] = sum over b of part[b * N + c], in a fixed order: 16 interleaved
@@ -271,23 +340,35 @@ __global__ __launch_bounds__(1024) void colreduce_kernel(int64_t nb, int N, cons
 
 static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// B^T's rows padded to whole 16-byte runs.
+static inline int ts_kpad(int K, int compute) {
+  const int ve = (int)(16 / prec_bytes(compute));
+  return (K + ve - 1) / ve * ve;
+}
+
 size_t tsgemm_ws_bytes(int64_t M, int K, int N, int compute) {
   const size_t nb = (size_t)ceil_div(M, 64);
-  return align256((size_t)K * N * prec_bytes(compute)) + align256(nb * N * sizeof(double));
+  return align256((size_t)ts_kpad(K, compute) * N * prec_bytes(compute)) + align256(nb * N * sizeof(double));
 }
 
 template <typename TC>
 static hipError_t tsgemm_t(int64_t M, int K, int N, const void* X, const double* B, void* Y, double* colsq,
                            double* rowsq, void* ws, hipStream_t st) {
+  constexpr int VE = 16 / (int)sizeof(TC);
+  const int Kp = (K + VE - 1) / VE * VE;  // ts_kpad
   TC* Bt = (TC*)ws;
-  double* part = (double*)((char*)ws + align256((size_t)K * N * sizeof(TC)));
-  hipLaunchKernelGGL(convert_bt_kernel<TC>, dim3((unsigned)ceil_div((int64_t)K * N, 256)), dim3(256), 0, st, K, N, B, Bt);
-  const int64_t nb = ceil_div(M, 64);
-  if (K <= tsf_k_max<TC>() && ((size_t)K * sizeof(TC)) % 16 == 0 && ((uintptr_t)X % 16) == 0) {
-    const int nkb = (int)ceil_div(K, 4 * (16 / (int)sizeof(TC)));
-    tsf_launch_i<TC, 0>(nkb, dim3((unsigned)nb), st, M, K, N, (const TC*)X, Bt, (TC*)Y, colsq ? part : nullptr, rowsq);
+  double* part = (double*)((char*)ws + align256((size_t)Kp * N * sizeof(TC)));
+  hipLaunchKernelGGL(convert_bt_kernel<TC>, dim3((unsigned)ceil_div((int64_t)Kp * N, 256)), dim3(256), 0, st, K, Kp, N,
+                     B, Bt);
+  int64_t nb = ceil_div(M, 64);
+  if (K <= tsf_k_max<TC>()) {
+    // rows of X as whole aligned runs (0), 8-byte pieces of 16-bit values (1) or single elements (2)
+    const int amode = (K % VE == 0 && ((uintptr_t)X % 16) == 0) ? 0
+                      : (sizeof(TC) == 2 && K % 4 == 0 && ((uintptr_t)X % 8) == 0) ? 1 : 2;
+    const int nkb = (int)ceil_div(K, 4 * VE);
+    nb = tsf_launch_i<TC, 0>(nkb, st, M, K, Kp, N, amode, (const TC*)X, Bt, (TC*)Y, colsq ? part : nullptr, rowsq);
   } else {
-    hipLaunchKernelGGL(tsgemm_kernel<TC>, dim3((unsigned)nb), dim3(256), 0, st, M, K, N, (const TC*)X, Bt, (TC*)Y,
+    hipLaunchKernelGGL(tsgemm_kernel<TC>, dim3((unsigned)nb), dim3(256), 0, st, M, K, Kp, N, (const TC*)X, Bt, (TC*)Y,
                        colsq ? part : nullptr, rowsq);
   }
   if (colsq) hipLaunchKernelGGL(colreduce_kernel, dim3((unsigned)ceil_div(N, 16)), dim3(1024), 0, st, nb, N, part, colsq);
