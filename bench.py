@@ -1,27 +1,37 @@
 #!/usr/bin/env python3
 """Throughput of cascaded bilateral sampling (CABS) sketches on one MI355X.
 
-One step = one complete CABS sketch (pilot sampling and evaluation, pilot
-sketch with FP64 SVD and orthogonalisation, weighted k-means with snapping on
-both sides, follow-up evaluation and sketch) plus the relative Frobenius error
-of the result from i.i.d. sampled entries, on a synthetic low-rank-plus-noise
-matrix that is never materialised (1e5 x 2e4, rank 200, s_i = 1/i, noise
-N(0, 1e-3^2); k1 = k2 = 200, c = 5, FP32; error from 1e7 sampled entries).
-Every step draws a fresh pilot sample (seed = step index), like the paper's
-repeated runs.  Inputs (generator tables) are resident in HBM before timing.
+Headline workload: the 1e6 x 1e6 RBF kernel matrix over 1e6 points in d = 64
+from a 100-cluster Gaussian mixture (entries evaluated on the fly, never
+stored), k1 = k2 = 500, c = 20 k-means iterations, FP32 compute with the SVDs,
+Grams and orthogonalisation in FP64, relative Frobenius error from 1e7 sampled
+entries.  One step = one complete sketch (pilot sampling and evaluation, pilot
+sketch, weighted k-means with snapping on both sides, follow-up evaluation and
+sketch) plus its error estimate.  Every step draws a fresh pilot sample (sketch
+seed = step index; error sample seed 1000 + step).  Inputs (the point tables)
+are resident in HBM before timing.
 
-Two timed phases over the same workload:
+Phases on the headline workload:
   * sequential: K sketches one after another on one stream, with per-kernel
-    family timing (HIP events on the launch stream) for the roofline figure of
-    the k-means distance GEMM + argmin kernel;
-  * served: K sketch requests (sketch + error) through the continuous-batching
-    server, closed loop with --slots requests in flight; `value` is this
-    whole-job throughput and p50/p99 are its submit-to-completion latencies.
-Also prints the FP64 CPU oracle timed on a bounded sample of the same workload.
+    family timing (HIP events on the launch stream); the roofline figure is the
+    k-means distance GEMM + argmin kernel's;
+  * served (the headline `value`): the same K requests through the
+    continuous-batching server, closed loop, --slots requests in flight;
+    p50/p99 are its submit-to-completion latencies;
+  * precision: the same K requests served in BF16 and in FP16 (FP32
+    accumulation, FP64 SVDs and Grams), their errors on the same sampled
+    entries and the ratio to the FP32 errors; the FP64 path's errors on the
+    first seeds as the reference.
+Extra keys (skipped with --no-extras): the 1e5 x 2e4 low-rank + noise workload
+(served FP32 and BF16, its roofline figure), per-precision errors on the
+scaled-signal variant beside the FP64 oracle's own errors on the same sampled
+entries (tests/golden/oracle_errors_lowrank1e5s.json), and the serving stream
+of uneven requests (closed-loop maximum, then Poisson arrivals at 0.25-0.9 of
+it, p50/p99 from arrival).  Also prints the FP64 CPU oracle timed on a bounded
+sample of the headline workload.
 
-`--stream` replaces all of this with the serving stream of uneven requests
-(closed-loop maximum, then Poisson arrivals at fractions of it, p50/p99 from
-arrival to completion); `--config NAME` times another workload.
+`--stream` runs only the serving stream (5000 requests per phase by default);
+`--config NAME` times another workload.
 """
 from __future__ import annotations
 
@@ -38,31 +48,34 @@ if ROOT not in sys.path:
 
 METRIC = "rank-k sketches/s at fixed rel-Frobenius error; p50/p99 sketch latency"
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0}
-PEAK_HBM_GBS = 8000.0
 
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="lowrank1e5", help="workload name from workloads.CONFIGS")
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="rbf1e6", help="workload name from workloads.CONFIGS")
     ap.add_argument("--compute", default=None, help="f64 | f32 | bf16 | f16 (default: the workload's)")
     ap.add_argument("--err-samples", type=int, default=None)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--slots", type=int, default=8, help="server slots (requests in flight) in the served phase")
+    ap.add_argument("--slots", type=int, default=0,
+                    help="server slots (requests in flight); 0: 4 for workloads of 5e5 rows or more, else 8")
     ap.add_argument("--no-served", action="store_true", help="skip the served phases (profiling runs)")
-    ap.add_argument("--no-variants", action="store_true",
-                    help="skip the BF16 served form and the scaled-signal workload")
+    ap.add_argument("--no-variants", action="store_true", help="skip the BF16 / FP16 / FP64 precision phases")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the low-rank workloads and the serving stream (extra keys)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-scale", type=float, default=None,
+                    help="row/column scale of the workload the CPU oracle is timed on (default: 0.002 for the "
+                         "1e6-row RBF workload, 0.05 otherwise)")
+    ap.add_argument("--cpu-runs", type=int, default=5, help="oracle runs; the median is reported")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="before timing, copy a buffer of this many MiB device-to-device once (a kernel of known "
                          "traffic for calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE)")
-    ap.add_argument("--cpu-scale", type=float, default=0.5,
-                    help="row/column scale of the workload the CPU oracle is timed on")
-    ap.add_argument("--stream", action="store_true",
-                    help="instead of the headline workload: the serving stream of uneven requests (Poisson "
-                         "arrivals at fractions of the closed-loop maximum, p50/p99 per point)")
-    ap.add_argument("--stream-requests", type=int, default=2000, help="requests per stream phase")
+    ap.add_argument("--stream", action="store_true", help="only the serving stream of uneven requests")
+    ap.add_argument("--stream-requests", type=int, default=5000, help="requests per phase with --stream")
+    ap.add_argument("--extra-stream-requests", type=int, default=1000,
+                    help="requests per phase of the stream run among the extra keys")
     ap.add_argument("--stream-pool", type=int, default=16, help="distinct request matrices built and uploaded")
     ap.add_argument("--stream-fracs", default="0.25,0.5,0.75,0.9",
                     help="offered load points as fractions of the measured closed-loop maximum")
@@ -70,27 +83,31 @@ def parse():
     return ap.parse_args()
 
 
-def pmc_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
-    (profiles/pmc_traffic.json), or None when the kernel's source has changed
-    since the counters were taken."""
+def log(msg: str) -> None:
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def pmc_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed rocprofv3 counter summary
+    (profiles/pmc_traffic.json), or None when there is none or the kernel's source has changed since
+    the counters were taken."""
     import hashlib
     try:
         with open(os.path.join(ROOT, "profiles", "pmc_traffic.json")) as f:
-            rec = json.load(f)[kernel]
+            rec = json.load(f)[f"{kernel}@{workload}"]
         with open(os.path.join(ROOT, rec["source"]), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
                 return None
-        return float(rec["bytes_per_launch"])
+        return float(rec["bytes_per_launch"]), rec.get("profile")
     except (OSError, KeyError, ValueError):
         return None
 
 
-def cpu_baseline(config: str, scale: float, err_samples: int) -> dict:
-    """The FP64 oracle on the same workload with m and n scaled by `scale`
-    (k, c unchanged; error from err_samples * scale samples), one sketch.
-    The oracle's cost is linear in m + n (Section 4), so the measured rate is
-    scaled by (m_s + n_s) / (m + n) to sketches/s of the full workload."""
+def cpu_baseline(config: str, scale: float, err_samples: int, runs: int) -> dict:
+    """The FP64 oracle on the same workload with m and n scaled by `scale` (k = min(k, m, n), c
+    unchanged; error from err_samples * scale^2 samples, at least 1e4), `runs` sketches; the median
+    time is reported.  The oracle's cost is linear in m + n at fixed k and c (Section 4), so the rate
+    is scaled by (m_s + n_s) / (m + n) to sketches/s of the full workload."""
     import numpy as np
 
     import workloads
@@ -100,52 +117,173 @@ def cpu_baseline(config: str, scale: float, err_samples: int) -> dict:
     full, cfg = workloads.config(config)
     spec, _ = workloads.config(config, scale)
     k = min(cfg["k"], spec.m, spec.n)
-    ns = max(1, int(err_samples * scale))
-    t0 = time.perf_counter()
-    res = oc.cabs(spec, oc.Params.square(k, kmeans_iters=cfg["iters"], seed=0))
-    if ns > 0:
-        oc.rel_error_sampled(Matrix(spec), res.C, res.Umid, res.Rt, ns, 0)
-    dt = time.perf_counter() - t0
+    ns = max(10_000, int(err_samples * scale * scale)) if err_samples > 0 else 0
+    times, errs = [], []
+    for r in range(runs):
+        t0 = time.perf_counter()
+        res = oc.cabs(spec, oc.Params.square(k, kmeans_iters=cfg["iters"], seed=r))
+        if ns > 0:
+            e = oc.rel_error_sampled(Matrix(spec), res.C, res.Umid, res.Rt, ns, 1000 + r)[0]
+        else:
+            e = oc.rel_error_exact(Matrix(spec), res.C, res.Umid, res.Rt)
+        times.append(time.perf_counter() - t0)
+        errs.append(e)
+    dt = float(np.median(times))
     threads = None
     try:
         from threadpoolctl import threadpool_info
         threads = max((i.get("num_threads", 0) for i in threadpool_info()), default=None)
     except Exception:
         pass
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except Exception:
+        pass
     ratio = (spec.m + spec.n) / (full.m + full.n)
     return {"value": ratio / dt, "unit": "sketches/s", "cores": threads or os.cpu_count(), "kind": "oracle",
-            "sample": f"FP64 NumPy oracle, one sketch of the same workload at m={spec.m}, n={spec.n} "
-                      f"(scale {scale}), k={k}, c={cfg['iters']}, error from {ns} samples: {dt:.2f} s; "
-                      f"rate scaled by (m_s+n_s)/(m+n)={ratio:.3g} (cost linear in m+n)",
-            "seconds": dt}
+            "sample": f"FP64 NumPy/SciPy oracle, {runs} sketches (seeds 0..{runs - 1}) of the same workload at "
+                      f"m={spec.m}, n={spec.n} (scale {scale:g}), k={k}, c={cfg['iters']}, each with its error from "
+                      f"{ns if ns else 'all'} entries; median {dt:.2f} s per sketch; rate scaled by "
+                      f"(m_s+n_s)/(m+n)={ratio:.3g} (the cost is linear in m+n at fixed k and c)",
+            "seconds_median": dt, "seconds": times, "rel_frobenius_error": errs, "cpu_model": cpu}
 
 
-def run_stream(args):
+def served(api, mat, k, iters, comp, ns, n_req, seed0, slots, warmup):
+    """Closed loop: n_req sketch + error requests through the server with `slots` in flight.
+    Returns (wall seconds, latencies ms, errors) in request order of completion."""
+    import numpy as np
+    import torch
+
+    S = max(1, slots)
+    p0 = api.make_params(k, k, k, k, kmeans_iters=iters, compute=comp, seed=0)
+    req_bytes = max(api.workspace_bytes(mat, p0), api.error_workspace_bytes(mat, p0, ns))
+    srv = api.Server(0, hbm_budget_bytes=S * (req_bytes + (1 << 20)), max_slots=S)
+    sets = [(api.alloc_result(mat, p0), torch.zeros(3, dtype=torch.float64, device="cuda")) for _ in range(S)]
+
+    def run(n, s0):
+        free = list(range(S))
+        live = {}
+        lats, rels = [], {}
+        nxt = 0
+        while nxt < n or live:
+            while free and nxt < n:
+                j = free.pop()
+                p = api.make_params(k, k, k, k, kmeans_iters=iters, compute=comp, seed=s0 + nxt)
+                t = srv.submit(mat, p, sets[j][0], err_samples=ns, err_seed=1000 + s0 + nxt, err_out=sets[j][1])
+                live[t] = (j, nxt)
+                nxt += 1
+            for t in list(live):
+                r = srv.poll(t)
+                if r is not None:
+                    j, q = live.pop(t)
+                    lats.append(r * 1e3)
+                    rels[q] = float(sets[j][1][2].item())
+                    free.append(j)
+            time.sleep(0.0002)
+        return np.array(lats), np.array([rels[q] for q in range(n)])
+
+    try:
+        run(min(S, max(1, warmup)), 20_000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat, rel = run(n_req, seed0)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, lat, rel
+    finally:
+        srv.close()
+        del sets
+        torch.cuda.empty_cache()
+
+
+def sequential(api, mat, k, iters, comp, ns, seeds, timing=False):
+    """Sketch + error for each seed, one after another on one stream; returns
+    (wall seconds, per-step ms, errors, diagnostics of the last sketch, kernel family times)."""
+    import numpy as np
+    import torch
+
+    prm = api.make_params(k, k, k, k, kmeans_iters=iters, compute=comp, seed=0)
+    ws = api._dev_alloc(api.workspace_bytes(mat, prm), mat.device)
+    out = api.alloc_result(mat, prm)
+    ews = [None]
+
+    def step(s):
+        prm.seed = s
+        api.sketch(mat, prm, ws=ws, out=out)
+        e3 = api.error(mat, prm, out, ns, seed=1000 + s, ws=ews[0])
+        ews[0] = e3._ws
+        return e3
+
+    if timing:
+        api.timing_reset()
+        api.timing_enable(True)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in seeds]
+    errs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, s in enumerate(seeds):
+        evs[i][0].record()
+        errs.append(step(s))
+        evs[i][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fam = None
+    if timing:
+        api.timing_enable(False)
+        fam = {f: api.timing_read(f) for f in ("assign", "eval", "tsgemm", "gram", "svd", "snap", "centroid", "error")}
+        api.timing_reset()
+    lat = np.array([a.elapsed_time(b) for a, b in evs])
+    rel = np.array([float(e[2].item()) for e in errs])
+    diag = out.diagnostics()
+    del ws, out, ews
+    torch.cuda.empty_cache()
+    return wall, lat, rel, diag, fam
+
+
+def workload_name(spec, k, iters, ns) -> str:
+    src = (f"low-rank + noise {spec.m}x{spec.n}, r={spec.r}, noise={spec.noise_std:g}" if spec.kind == "lowrank"
+           else f"RBF kernel {spec.m}x{spec.n} over points in d={spec.d}")
+    return f"{src}, k1=k2={k}, c={iters}, error from {ns} sampled entries" if ns else \
+        f"{src}, k1=k2={k}, c={iters}, exact error"
+
+
+def assign_roofline(fam, spec, k, dim_alg, iters, n_sketch, comp):
+    """The k-means assignment family: 2 * rows * k2 * k1 flops per launch, (c + 1) launches per side
+    and sketch, divided by the summed HIP-event time of its launches."""
+    a_ms, a_n = fam["assign"]
+    flops = n_sketch * (iters + 1) * 2.0 * (spec.m + spec.n) * k * dim_alg
+    achieved = flops / (a_ms * 1e-3) / 1e12 if a_ms > 0 else 0.0
+    peak = PEAK_TFLOPS[comp]
+    return {"kernel": "assign_fast_kernel (k-means distance GEMM + argmin), sequential phase",
+            "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak if peak else None, "launches": a_n, "avg_launch_ms": a_ms / max(a_n, 1),
+            "flops_per_launch": 2.0 * (spec.m + spec.n) / 2 * k * dim_alg}
+
+
+def run_stream(api, args, n_req, quiet=False) -> dict:
     """The serving stream: requests of uneven shape (m, n log-uniform in [1e3, 5e5], low-rank + noise or RBF,
     k in {16, ..., 256}, pilot size k, seed 1000 + id), sketches only.  The closed-loop maximum is measured
-    first (--slots requests in flight); then the same requests arrive as a Poisson process at each fraction
-    of that rate, and latency runs from arrival to completion (the server's submit-to-completion time plus
-    any delay of the host loop in submitting).  Host generation of a 5e5-row orthonormal basis takes
+    first (--slots requests in flight, default 8); then the same requests arrive as a Poisson process at each
+    fraction of that rate, and latency runs from arrival to completion (the server's submit-to-completion time
+    plus any delay of the host loop in submitting).  Host generation of a 5e5-row orthonormal basis takes
     seconds, so the first --stream-pool recipes are built and uploaded once and request i runs on matrix
     i mod pool with its own k and seed."""
     import numpy as np
     import torch
 
     import workloads
-    from paper_1607_07395_amd import api
 
-    torch.cuda.set_device(0)
-    n_req = args.stream_requests
     recs = workloads.request_stream(n_requests=n_req, qps=1.0, seed=0)
     P = max(1, min(args.stream_pool, n_req))
     t_b = time.perf_counter()
     pool = []
     for i in range(P):
         pool.append(api.DeviceMatrix(workloads.request_matrix(recs[i]), storage="f32"))
-        print(f"stream: matrix {i + 1}/{P} {recs[i]['kind']} {recs[i]['m']}x{recs[i]['n']}", file=sys.stderr,
-              flush=True)
+        log(f"stream: matrix {i + 1}/{P} {recs[i]['kind']} {recs[i]['m']}x{recs[i]['n']}")
     build_s = time.perf_counter() - t_b
-    comp, iters, S = args.stream_compute, 5, max(1, args.slots)
+    comp, iters = args.stream_compute, 5
+    S = args.slots if args.slots > 0 else 8
 
     def params(i):
         mat = pool[i % P]
@@ -159,10 +297,10 @@ def run_stream(args):
     srv = api.Server(0, hbm_budget_bytes=S * (need + (1 << 20)), max_slots=S)
 
     def drive(ids, arrivals):
-        """Submit ids (closed loop when arrivals is None); returns latencies (ms) and the span (s)."""
-        live, lat, last = {}, [], 0.0
+        live, lat = {}, []
         nxt, n = 0, len(ids)
         t0 = time.perf_counter()
+        last = 0.0
         while nxt < n or live:
             now = time.perf_counter() - t0
             while nxt < n and ((arrivals is None and len(live) < S) or (arrivals is not None and arrivals[nxt] <= now)):
@@ -187,7 +325,7 @@ def run_stream(args):
         lam = n_req / span
         closed = {"sketches_per_s": lam, "p50_ms": float(np.percentile(lat, 50)),
                   "p99_ms": float(np.percentile(lat, 99))}
-        print(f"stream: closed loop {lam:.1f} sketches/s", file=sys.stderr, flush=True)
+        log(f"stream: closed loop {lam:.1f} sketches/s")
         points = []
         for f in [float(x) for x in args.stream_fracs.split(",") if x]:
             rng = np.random.default_rng(1)
@@ -196,20 +334,80 @@ def run_stream(args):
             lat, span = drive(list(range(n_req)), arr)
             points.append({"load_frac": f, "offered_per_s": f * lam, "sketches_per_s": n_req / span,
                            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))})
-            print(f"stream: load {f:g} -> p50 {points[-1]['p50_ms']:.1f} ms, p99 {points[-1]['p99_ms']:.1f} ms",
-                  file=sys.stderr, flush=True)
+            log(f"stream: load {f:g} -> p50 {points[-1]['p50_ms']:.1f} ms, p99 {points[-1]['p99_ms']:.1f} ms")
     finally:
         srv.close()
     kinds = [pool[i % P].spec.kind for i in range(n_req)]
-    print(json.dumps({
-        "metric": "serving stream: sketches/s and p50/p99 latency under Poisson arrivals",
-        "unit": "sketches/s", "n_gpus": 1, "dtype": comp, "data": "synthetic",
-        "config": {"workload": "uneven requests: m, n log-uniform in [1e3, 5e5], low-rank + noise (rank 16-256) "
-                               "or RBF (d = 32, 10-100 clusters), k in {16, 32, 64, 128, 256}, c = 5, sketch only",
-                   "requests": n_req, "matrix_pool": P, "slots": S,
-                   "pool_shapes": [[int(m.spec.m), int(m.spec.n), m.spec.kind] for m in pool],
-                   "lowrank_share": kinds.count("lowrank") / n_req, "pool_build_s": build_s},
-        "closed_loop": closed, "poisson": points}), flush=True)
+    res = {"workload": "uneven requests: m, n log-uniform in [1e3, 5e5], low-rank + noise (rank 16-256) or RBF "
+                       "(d = 32, 10-100 clusters), k in {16, 32, 64, 128, 256}, c = 5, sketch only",
+           "dtype": comp, "requests": n_req, "matrix_pool": P, "slots": S,
+           "pool_shapes": [[int(m.spec.m), int(m.spec.n), m.spec.kind] for m in pool],
+           "lowrank_share": kinds.count("lowrank") / n_req, "pool_build_s": build_s,
+           "closed_loop": closed, "poisson": points}
+    del pool
+    torch.cuda.empty_cache()
+    return res
+
+
+def lowrank_extras(api, args) -> dict:
+    """The 1e5 x 2e4 low-rank + noise workload (as specified: noise-dominated) served in FP32 and BF16,
+    with its assignment roofline figure, and per-precision errors on the scaled-signal variant next to
+    the FP64 oracle's errors on the same sampled entries."""
+    import numpy as np
+    import torch
+
+    import workloads
+
+    out = {}
+    spec, cfg = workloads.config("lowrank1e5")
+    k, iters, ns = cfg["k"], cfg["iters"], cfg["err_samples"]
+    mat = api.DeviceMatrix(spec, storage="f32")
+    sequential(api, mat, k, iters, "f32", ns, [30_000, 30_001])
+    wall, lat, rel, diag, fam = sequential(api, mat, k, iters, "f32", ns, list(range(5)), timing=True)
+    rf = assign_roofline(fam, spec, k, k, iters, 5, "f32")
+    rec = {"workload": workload_name(spec, k, iters, ns),
+           "sequential_f32": {"sketches_per_s": 5 / wall, "rel_frobenius_error_mean": float(rel.mean())},
+           "assign_roofline_f32": {kk: rf[kk] for kk in ("achieved", "peak", "frac", "avg_launch_ms")}}
+    n_req = 40
+    for comp in ("f32", "bf16"):
+        w, l, r = served(api, mat, k, iters, comp, ns, n_req, 0, 8, 2)
+        rec[f"served_{comp}"] = {"sketches_per_s": n_req / w, "p50_ms": float(np.percentile(l, 50)),
+                                 "p99_ms": float(np.percentile(l, 99)), "rel_frobenius_error_mean": float(r.mean())}
+        log(f"lowrank1e5 served {comp}: {n_req / w:.1f} sketches/s")
+    rec["note"] = ("as specified the noise dominates (|signal|_F ~ 1.28 against |E|_F ~ 44.7), so every rank-200 "
+                   "sketch has relative error ~1.39 and the error says nothing about the method; the scaled-signal "
+                   "variant below is the informative one")
+    out["lowrank1e5"] = rec
+    del mat
+    torch.cuda.empty_cache()
+
+    # scaled-signal variant: errors per precision on the same seeds and sampled entries
+    spec_s, cfg_s = workloads.config("lowrank1e5s")
+    golden = os.path.join(ROOT, "tests", "golden", "oracle_errors_lowrank1e5s.json")
+    oracle = {}
+    try:
+        with open(golden) as f:
+            oracle = {int(s): v["rel_error"] for s, v in json.load(f)["seeds"].items()}
+    except (OSError, KeyError, ValueError):
+        pass
+    seeds = sorted(oracle) if oracle else [0, 1, 2]
+    errs = {}
+    for comp in ("f64", "f32", "bf16", "f16"):
+        m_s = api.DeviceMatrix(spec_s, storage="f64" if comp == "f64" else "f32")
+        _, _, rel, _, _ = sequential(api, m_s, k, iters, comp, ns, seeds)
+        errs[comp] = [float(x) for x in rel]
+        del m_s
+        torch.cuda.empty_cache()
+    rec_s = {"workload": workload_name(spec_s, k, iters, ns) + " (s_i = sqrt(mn)/i)", "seeds": seeds,
+             "rel_frobenius_error": errs,
+             "fp64_oracle_rel_frobenius_error": [oracle.get(s) for s in seeds] if oracle else None,
+             "oracle_source": "tests/golden/oracle_errors_lowrank1e5s.json (written by make_oracle_errors.py, "
+                              "oracle only)"}
+    if oracle:
+        rec_s["ratio_to_fp64_oracle"] = {c: [e / oracle[s] for e, s in zip(v, seeds)] for c, v in errs.items()}
+    rec_s["ratio_to_f32"] = {c: float(np.mean(v) / np.mean(errs["f32"])) for c, v in errs.items()}
+    out["lowrank1e5s_errors"] = rec_s
+    return out
 
 
 def main():
@@ -218,9 +416,6 @@ def main():
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
         sys.exit(2)
-    if args.stream:
-        run_stream(args)
-        return
 
     import numpy as np
     import torch
@@ -229,11 +424,18 @@ def main():
     from paper_1607_07395_amd import api
 
     torch.cuda.set_device(0)
+    if args.stream:
+        res = run_stream(api, args, args.stream_requests)
+        print(json.dumps({"metric": "serving stream: sketches/s and p50/p99 latency under Poisson arrivals",
+                          "unit": "sketches/s", "n_gpus": 1, "data": "synthetic", **res}), flush=True)
+        return
+
     spec, cfg = workloads.config(args.config)
     compute = args.compute or cfg["precision"]
     storage = "f64" if compute == "f64" else "f32"
     ns = cfg["err_samples"] if args.err_samples is None else args.err_samples
     k, iters = cfg["k"], cfg["iters"]
+    S = args.slots if args.slots > 0 else (4 if max(spec.m, spec.n) >= 500_000 else 8)
 
     if args.copy_probe_mb > 0:
         src = torch.ones(args.copy_probe_mb << 18, dtype=torch.float32, device="cuda")
@@ -242,132 +444,59 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    log(f"{args.config}: {spec.m} x {spec.n}, k = {k}, c = {iters}, {compute}")
     mat = api.DeviceMatrix(spec, storage=storage)
-    prm = api.make_params(k, k, k, k, kmeans_iters=iters, compute=compute, seed=0)
-    ws = api._dev_alloc(api.workspace_bytes(mat, prm), mat.device)
-    out = api.alloc_result(mat, prm)
-    ews = None
 
-    def step(i):
-        nonlocal ews
-        prm.seed = i
-        api.sketch(mat, prm, ws=ws, out=out)
-        e3 = api.error(mat, prm, out, ns, seed=1000 + i, ws=ews)
-        ews = e3._ws
-        return e3
+    # ---- sequential phase ----
+    sequential(api, mat, k, iters, compute, ns, [10_000 + i for i in range(args.warmup)])
+    seq_wall, seq_lat, seq_rel, diag, fam = sequential(api, mat, k, iters, compute, ns, list(range(args.steps)),
+                                                       timing=True)
+    log(f"sequential: {1e3 * seq_wall / args.steps:.1f} ms per sketch + error")
+    roof = assign_roofline(fam, spec, k, k, iters, args.steps, compute)
+    tr = pmc_traffic("assign_fast_kernel", f"{args.config}-{compute}")
+    roof["traffic"] = tr[0] if tr else None
+    roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled on a device copy)"
+    roof["traffic_profile"] = tr[1] if tr else None
+    # P read once (rows x k1 elements), pnorm read, label and distance written: 20 bytes per row
+    elem = {"bf16": 2, "f16": 2, "f32": 4, "f64": 8}[compute]
+    roof["algorithmic_bytes_per_launch"] = (spec.m + spec.n) / 2 * (k * elem + 20.0)
 
-    for i in range(args.warmup):
-        step(10_000 + i)
-    torch.cuda.synchronize()
-
-    api.timing_reset()
-    api.timing_enable(True)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    errs = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        evs[i][0].record()
-        errs.append(step(i))
-        evs[i][1].record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    api.timing_enable(False)
-
-    seq_elapsed = t1 - t0
-    lat = np.array([a.elapsed_time(b) for a, b in evs])
-    rel_seq = np.array([float(e[2].item()) for e in errs])
-    diag = out.diagnostics()
-
-    # dominant throughput kernel: fused distance GEMM + argmin; (c + 1) assignments per side per sketch
-    flops = args.steps * (iters + 1) * 2.0 * (spec.m + spec.n) * k * k
-    a_ms, a_n = api.timing_read("assign")
-    achieved = flops / (a_ms * 1e-3) / 1e12 if a_ms > 0 else 0.0
-    peak = PEAK_TFLOPS[compute]
-    fam = {f: api.timing_read(f) for f in ("assign", "eval", "tsgemm", "gram", "svd", "snap", "centroid", "error")}
-    api.timing_reset()
-
-    # ---- served phase: closed loop, `slots` requests in flight ----
-    S = max(1, args.slots)
-
-    def served(mat_, comp, n_req, seed0):
-        p0 = api.make_params(k, k, k, k, kmeans_iters=iters, compute=comp, seed=0)
-        req_bytes = max(api.workspace_bytes(mat_, p0), api.error_workspace_bytes(mat_, p0, ns))
-        srv = api.Server(0, hbm_budget_bytes=S * (req_bytes + (1 << 20)), max_slots=S)
-        sets = [(api.alloc_result(mat_, p0), torch.zeros(3, dtype=torch.float64, device="cuda")) for _ in range(S)]
-
-        def run(n, s0):
-            free = list(range(S))
-            live = {}
-            lats, rels = [], []
-            nxt = 0
-            while nxt < n or live:
-                while free and nxt < n:
-                    j = free.pop()
-                    p = api.make_params(k, k, k, k, kmeans_iters=iters, compute=comp, seed=s0 + nxt)
-                    t = srv.submit(mat_, p, sets[j][0], err_samples=ns, err_seed=1000 + s0 + nxt, err_out=sets[j][1])
-                    live[t] = j
-                    nxt += 1
-                for t in list(live):
-                    r = srv.poll(t)
-                    if r is not None:
-                        j = live.pop(t)
-                        lats.append(r * 1e3)
-                        rels.append(float(sets[j][1][2].item()))
-                        free.append(j)
-                time.sleep(0.0002)
-            return np.array(lats), np.array(rels)
-
-        try:
-            run(min(S, max(1, args.warmup)), 20_000)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            lat_, rel_ = run(n_req, seed0)
-            torch.cuda.synchronize()
-            return time.perf_counter() - t0, lat_, rel_
-        finally:
-            srv.close()
-
+    # ---- served phase (headline value) ----
     if args.no_served:
-        elapsed, s_lat, s_rel = seq_elapsed, lat, rel_seq
+        elapsed, s_lat, s_rel = seq_wall, seq_lat, seq_rel
         mode = "sequential (served phase skipped)"
     else:
-        elapsed, s_lat, s_rel = served(mat, compute, args.steps, 0)
+        elapsed, s_lat, s_rel = served(api, mat, k, iters, compute, ns, args.steps, 0, S, args.warmup)
         mode = f"served: continuous-batching server, {S} requests in flight (closed loop), sketch + error each"
-    variants = {}
-    if not args.no_served and not args.no_variants and compute == "f32":
-        # the mixed-precision served form on the same workload and seeds
-        e_b, l_b, r_b = served(mat, "bf16", args.steps, 0)
-        variants["bf16_served"] = {
-            "sketches_per_s": args.steps / e_b, "p50_ms": float(np.percentile(l_b, 50)),
-            "p99_ms": float(np.percentile(l_b, 99)), "rel_frobenius_error_mean": float(r_b.mean()),
-            "error_ratio_to_f32_served": float(r_b.mean() / s_rel.mean())}
-    if not args.no_variants and args.config == "lowrank1e5":
-        # the same shape with s_i = sqrt(mn)/i, so that the signal dominates the noise
-        spec_s, _ = workloads.config("lowrank1e5s")
-        mat_s = api.DeviceMatrix(spec_s, storage=storage)
-        out_s = api.alloc_result(mat_s, prm)
-        def timed_sketches(**kw):
-            errs, times = [], []
-            for i in range(3):
-                p = api.make_params(k, k, k, k, kmeans_iters=iters, compute=compute, seed=i, **kw)
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                api.sketch(mat_s, p, out=out_s)
-                torch.cuda.synchronize()
-                times.append(time.perf_counter() - t0)
-                errs.append(float(api.error(mat_s, p, out_s, ns, seed=1000 + i)[2].item()))
-            return float(np.mean(errs)), 1e3 * float(np.median(times))
+        log(f"served {compute}: {args.steps / elapsed:.2f} sketches/s")
 
-        e_km, t_km = timed_sketches()
-        variants["scaled_signal_f32"] = {"workload": "as above with s_i = sqrt(mn)/i", "rel_frobenius_error_mean": e_km,
-                                         "sketch_ms_median": t_km, "sketches": 3}
-        # the hard-threshold follow-up of Section 5 (the k rows and columns of largest |P_l|^2)
-        e_h, t_h = timed_sketches(weight="pow", weight_param=2.0, follow_up="hard")
-        variants["scaled_signal_hard_threshold_f32"] = {
-            "workload": "as above with s_i = sqrt(mn)/i; follow-up: the k rows and columns of largest |P_l|^2",
-            "rel_frobenius_error_mean": e_h, "sketch_ms_median": t_h, "sketches": 3}
-        del mat_s, out_s
+    # ---- precision phases ----
+    precision = {}
+    if not args.no_variants and compute == "f32":
+        for comp in ("bf16", "f16"):
+            if args.no_served:
+                w, l, r, _, _ = sequential(api, mat, k, iters, comp, ns, list(range(args.steps)))
+            else:
+                w, l, r = served(api, mat, k, iters, comp, ns, args.steps, 0, S, args.warmup)
+            precision[f"{comp}_served" if not args.no_served else f"{comp}_sequential"] = {
+                "sketches_per_s": args.steps / w, "p50_ms": float(np.percentile(l, 50)),
+                "p99_ms": float(np.percentile(l, 99)), "rel_frobenius_error_mean": float(r.mean()),
+                "error_ratio_to_f32": float(r.mean() / s_rel.mean()),
+                "speedup_over_f32": float(elapsed / w),
+                "at_equal_error": bool(r.mean() <= 1.01 * s_rel.mean())}
+            log(f"{comp}: {args.steps / w:.2f} sketches/s, error ratio {r.mean() / s_rel.mean():.4f}")
+        # the FP64 path (parity-pinned to the FP64 oracle) on the first seeds, as the reference
+        nref = min(3, args.steps)
+        m64 = api.DeviceMatrix(spec, storage="f64")
+        w64, _, r64, _, _ = sequential(api, m64, k, iters, "f64", ns, list(range(nref)))
+        del m64
+        torch.cuda.empty_cache()
+        precision["f64_reference"] = {
+            "seeds": list(range(nref)), "rel_frobenius_error": [float(x) for x in r64],
+            "ms_per_sketch": 1e3 * w64 / nref,
+            "f32_error_same_seeds": [float(x) for x in s_rel[:nref]],
+            "note": "the FP64 GPU path, whose indices are bit-exact with the FP64 oracle and factors within 1e-10 "
+                    "in the parity tests; each error on the same sampled entries as the FP32/BF16/FP16 sketches"}
 
     result = {
         "metric": METRIC,
@@ -383,32 +512,31 @@ def main():
         "dtype": compute,
         "data": "synthetic",
         "config": {
-            "workload": (f"{spec.kind} {spec.m}x{spec.n}" + (f" r={spec.r} noise={spec.noise_std:g}" if spec.kind == "lowrank"
-                         else f" d={spec.d}") + f", k1=k2={k}, c={iters}, error from {ns} sampled entries"),
+            "workload": workload_name(spec, k, iters, ns),
             "m": spec.m, "n": spec.n, "k": k, "kmeans_iters": iters, "err_samples": ns,
-            "mode": mode,
+            "mode": mode, "slots": S,
             "rel_frobenius_error_mean": float(s_rel.mean()), "rel_frobenius_error_max": float(s_rel.max()),
             "p50_ms": float(np.percentile(s_lat, 50)), "p99_ms": float(np.percentile(s_lat, 99)),
-            "sequential": {"sketches_per_s": args.steps / seq_elapsed, "ms_per_step": 1e3 * seq_elapsed / args.steps,
-                           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                           "rel_frobenius_error_mean": float(rel_seq.mean())},
-            "rank_final": diag["rank_final"], "entries_touched": diag["entries"],
-            "snap_full_scans": [diag["snap_scans_r"], diag["snap_scans_c"]],
-            **variants,
+            "sequential": {"sketches_per_s": args.steps / seq_wall, "ms_per_step": 1e3 * seq_wall / args.steps,
+                           "p50_ms": float(np.percentile(seq_lat, 50)), "p99_ms": float(np.percentile(seq_lat, 99)),
+                           "rel_frobenius_error_mean": float(seq_rel.mean())},
+            "rank_final": diag["rank_final"], "snap_full_scans": [diag["snap_scans_r"], diag["snap_scans_c"]],
         },
-        "roofline": {
-            "kernel": "assign_fast_kernel (k-means distance GEMM + argmin), sequential phase",
-            "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak if peak else None,
-            "traffic": pmc_traffic("assign_fast_kernel") if compute == "f32" and args.config == "lowrank1e5" else None,
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE, calibrated on a device copy; "
-                            "profiles/lowrank1e5_f32_pmc_traffic.md)",
-            "launches": a_n, "avg_launch_ms": a_ms / max(a_n, 1),
-        },
+        "precision": precision,
+        "roofline": roof,
         "kernel_ms_per_step": {f: v[0] / args.steps for f, v in fam.items()},
     }
+    del mat
+    torch.cuda.empty_cache()
+
+    if not args.no_extras and args.config == "rbf1e6":
+        extras = lowrank_extras(api, args)
+        extras["stream"] = run_stream(api, args, args.extra_stream_requests)
+        result["extras"] = extras
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(args.config, args.cpu_scale, ns)
+        scale = args.cpu_scale if args.cpu_scale is not None else (0.002 if args.config == "rbf1e6" else 0.05)
+        log(f"cpu baseline: oracle at scale {scale:g}, {args.cpu_runs} runs")
+        result["cpu_baseline"] = cpu_baseline(args.config, scale, ns, args.cpu_runs)
     print(json.dumps(result), flush=True)
 
 
