@@ -306,6 +306,98 @@ static int64_t tsf_launch_i(int nkb, hipStream_t st, int64_t M, int K, int Kp, i
   return nb;
 }
 
+// FP64 products with K > 256 (rows too wide for registers) and without norms
+// (Y = X B only), X rows and B^T rows whole 16-byte runs (K even): 128 x 128
+// output tiles, 4 waves each owning a 64 x 64 quarter (16 MFMA tiles of
+// 16x16x4 FP64).  K runs in stages of 16, double-
+// buffered in LDS and filled by direct global-to-LDS loads; a stage holds
+// pairs of consecutive k of every row, ordered [pair][row], so one 16-byte LDS
+// read gives a lane its operand for two MFMA steps.  The contraction order is
+// free: in stage s, pair group t and step sigma, lane group g takes
+// k = 16 s + 8 t + 2 g + sigma, for A and B alike.  Row and column tiles are
+// dealt so that the column tiles of one row tile share an XCD (its L2 serves
+// the rows of X to all of them).
+constexpr int TF_W = 128;   // output tile edge
+constexpr int TF_KT = 16;   // k per stage
+constexpr int TF_NP = TF_KT / 2 * TF_W;  // 16-byte runs per operand and stage
+
+__global__ __launch_bounds__(256, 1) void tsgemm_f64_kernel(int64_t M, int K, int Kp, int N, int ntc,
+                                                            const double* __restrict__ X,
+                                                            const double* __restrict__ Bt, double* __restrict__ Y) {
+  __shared__ uint4 sa0[TF_NP], sa1[TF_NP], sb0[TF_NP], sb1[TF_NP];
+  const int id = blockIdx.x, xcd = id & 7, slot = id >> 3;
+  const int ct = slot % ntc;
+  const int64_t rt = (int64_t)(slot / ntc) * 8 + xcd;
+  const int64_t row0 = rt * TF_W;
+  if (row0 >= M) return;
+  const int col0 = ct * TF_W;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
+  const int wr = wave >> 1, wc = wave & 1;
+  // stage loads: instruction i (0..15) of an operand fills pair i / 2, rows / columns 64 (i & 1) .. + 63
+  auto issue = [&](uint4* da, uint4* db, int s) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = wave * 4 + u;  // 16 instructions per operand over 4 waves
+      const int p = i >> 1, rr = ((i & 1) << 6) + lane;
+      const int k0 = s * TF_KT + 2 * p;
+      const int64_t xr = row0 + rr;
+      const double* xa = (xr < M && k0 < K) ? X + xr * K + k0 : (const double*)kTileZero;
+      __builtin_amdgcn_global_load_lds((const void*)xa, CABS_TS_LDS_PTR(da + i * 64), 16, 0, 0);
+      const int bc = col0 + rr;
+      const double* xb = (bc < N && k0 < Kp) ? Bt + (int64_t)bc * Kp + k0 : (const double*)kTileZero;
+      __builtin_amdgcn_global_load_lds((const void*)xb, CABS_TS_LDS_PTR(db + i * 64), 16, 0, 0);
+    }
+  };
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  auto compute = [&](const uint4* sa, const uint4* sb) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      uint4 ra[4], rb[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) ra[a] = sa[(4 * t + g) * TF_W + 64 * wr + 16 * a + r];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) rb[b] = sb[(4 * t + g) * TF_W + 64 * wc + 16 * b + r];
+#pragma unroll
+      for (int sg = 0; sg < 2; ++sg)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(Vec16<double>::frag(ra[a], sg),
+                                                             Vec16<double>::frag(rb[b], sg), acc[a][b], 0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);  // one pair group's operands live at a time
+    }
+  };
+  const int nks = (K + TF_KT - 1) / TF_KT;
+  issue(sa0, sb0, 0);
+  for (int s = 0; s < nks; s += 2) {
+    __builtin_amdgcn_s_waitcnt(0x3f70);  // vmcnt(0): this wave's loads of stage s
+    __syncthreads();                     // every wave's loads landed; the other buffers are no longer read
+    if (s + 1 < nks) issue(sa1, sb1, s + 1);
+    compute(sa0, sb0);
+    if (s + 1 >= nks) break;
+    __builtin_amdgcn_s_waitcnt(0x3f70);
+    __syncthreads();
+    if (s + 2 < nks) issue(sa0, sb0, s + 2);
+    compute(sa1, sb1);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int col = col0 + 64 * wc + 16 * b + r;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t row = row0 + 64 * wr + 16 * a + out_row<double>(g, i);
+        if (row < M && col < N) Y[row * N + col] = acc[a][b][i];
+      }
+    }
+}
+
 // out[c] = sum over b of part[b * N + c], in a fixed order: 16 interleaved
 // segments per column, then the 16 segment sums in order.
 // Column sums of the row-block partials: 16 columns per block, the 64 row
@@ -361,6 +453,16 @@ static hipError_t tsgemm_t(int64_t M, int K, int N, const void* X, const double*
   hipLaunchKernelGGL(convert_bt_kernel<TC>, dim3((unsigned)ceil_div((int64_t)Kp * N, 256)), dim3(256), 0, st, K, Kp, N,
                      B, Bt);
   int64_t nb = ceil_div(M, 64);
+  if constexpr (sizeof(TC) == 8) {
+    if (K > tsf_k_max<double>() && colsq == nullptr && rowsq == nullptr && K % 2 == 0 && ((uintptr_t)X % 16) == 0 &&
+        Y != nullptr) {
+      const int ntc = (int)ceil_div(N, TF_W);
+      const int64_t nrt = ceil_div(ceil_div(M, TF_W), 8) * 8;
+      hipLaunchKernelGGL(tsgemm_f64_kernel, dim3((unsigned)(nrt * ntc)), dim3(256), 0, st, M, K, Kp, N, ntc,
+                         (const double*)X, (const double*)Bt, (double*)Y);
+      return hipGetLastError();
+    }
+  }
   if (K <= tsf_k_max<TC>()) {
     // rows of X as whole aligned runs (0), 8-byte pieces of 16-bit values (1) or single elements (2)
     const int amode = (K % VE == 0 && ((uintptr_t)X % 16) == 0) ? 0
@@ -391,26 +493,28 @@ hipError_t launch_tsgemm(int64_t M, int K, int N, int compute, const void* X, co
 // ---------------------------------------------------------------------------
 // Gram
 //
-// The grid is (row block) x (tile group).  A tile group is GRAM_TPB
-// consecutive tiles of the lower triangle (row-major), GRAM_TPW per wave.  A
-// block streams its rows through LDS in stages of `rs` rows: the stage is
-// loaded with coalesced element loads into registers while the previous one
-// is consumed (one 16x16x4 FP64 MFMA per tile and row quad, both operands
-// read from LDS).  Rows are added in increasing order, so each tile partial
-// has a fixed rounding order; partials are then summed over row blocks in
-// increasing block order by a second kernel.
+// G = X^T X with FP64 accumulation (16x16x4 FP64 MFMAs), X (M x K) in the
+// compute precision.  The lower triangle of G is covered by super-tiles of
+// 128 x 128 (I >= J); the grid is (row block) x (super-tile).  A block (4
+// waves, each owning a 64 x 64 quarter: 16 MFMA tiles) streams its rows of
+// the two 128-column strips of X through LDS in stages of GR_RS rows, loaded
+// into registers one stage ahead, and converts each fragment element to FP64
+// as it is read (products of FP32 or 16-bit values are exact in FP64).  The
+// MFMA's contraction runs over 4 rows of X per step (lane group g takes row
+// 4s + g), rows in increasing order, so each partial has a fixed rounding
+// order.  Each strip of X is read once per super-tile: 4.1 x X at K = 500
+// (9.3 x for 32-column tile groups).  The partials of the row blocks are
+// then summed in increasing block order by gram_reduce_kernel.  The blocks of
+// one row block are given ids that share an XCD (and its L2).
 // ---------------------------------------------------------------------------
-constexpr int GRAM_TPW = 8;          // 16x16 tiles per wave
-constexpr int GRAM_TPB = 4 * GRAM_TPW;
-constexpr int GRAM_MAX_NB = 256;
-constexpr int GRAM_TARGET_BLOCKS = 768;  // three 256-thread blocks per CU
-constexpr int GRAM_MAX_RS = 64;
-
-template <typename TC> struct GramEpt { static constexpr int v = 32; };
-template <> struct GramEpt<double> { static constexpr int v = 16; };
+constexpr int GR_W = 128;             // super-tile width (columns of G)
+constexpr int GR_RS = 32;             // rows per stage (16 for FP64, so that two blocks fit a CU's LDS)
+constexpr int GR_TARGET_BLOCKS = 512; // two 256-thread blocks per CU
 
 struct GramPlan {
-  int nt, ntiles, ng, nb;
+  int nst;        // 128-column strips
+  int ns;         // super-tiles (lower triangle incl. diagonal)
+  int nb;         // row blocks (a multiple of 8)
   int64_t rows_per;
 };
 
@@ -421,38 +525,6 @@ static inline int tri_row(int t) {
   return a;
 }
 
-static inline GramPlan gram_plan(int64_t M, int K) {
-  GramPlan g;
-  g.nt = (K + 15) / 16;
-  g.ntiles = g.nt * (g.nt + 1) / 2;
-  g.ng = (int)ceil_div(g.ntiles, GRAM_TPB);
-  int64_t nb = ceil_div(GRAM_TARGET_BLOCKS, g.ng);
-  nb = std::min<int64_t>(nb, ceil_div(M, 16));
-  nb = std::max<int64_t>(1, std::min<int64_t>(nb, GRAM_MAX_NB));
-  if (nb > 8) nb = ceil_div(nb, 8) * 8;
-  g.rows_per = ceil_div(M, nb);
-  g.nb = (int)ceil_div(M, g.rows_per);
-  return g;
-}
-
-// Staging geometry of one tile group: kal columns are read by the fragments
-// (zero beyond K), kb = min(K, kal) are loaded, rows sit `stride` bytes apart
-// (16 elements of padding modulo 256 bytes, so the four rows of a fragment
-// fall on different LDS banks), and `rs` rows form one stage.
-struct GramStage {
-  int kal, kb, stride, rs;
-};
-__host__ __device__ inline GramStage gram_stage(int K, int ti_max, int esz, int ept) {
-  GramStage s;
-  s.kal = 16 * (ti_max + 1);
-  s.kb = K < s.kal ? K : s.kal;
-  const int want = 16 * esz;
-  s.stride = s.kal * esz + ((((want - s.kal * esz) % 256) + 256) % 256);
-  int rs = ((ept * 256) / s.kb) & ~3;
-  s.rs = rs < 4 ? 4 : rs > GRAM_MAX_RS ? GRAM_MAX_RS : rs;
-  return s;
-}
-
 __device__ __forceinline__ int tri_row_dev(int t) {
   int a = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
   while ((a + 1) * (a + 2) / 2 <= t) ++a;
@@ -460,161 +532,193 @@ __device__ __forceinline__ int tri_row_dev(int t) {
   return a;
 }
 
+static inline GramPlan gram_plan(int64_t M, int K) {
+  GramPlan g;
+  g.nst = (K + GR_W - 1) / GR_W;
+  g.ns = g.nst * (g.nst + 1) / 2;
+  int64_t nb = ceil_div(GR_TARGET_BLOCKS, g.ns);
+  nb = std::min<int64_t>(nb, ceil_div(M, GR_RS));
+  nb = ceil_div(std::max<int64_t>(nb, 1), 8) * 8;
+  g.rows_per = ceil_div(ceil_div(M, nb), GR_RS) * GR_RS;
+  g.nb = (int)nb;
+  return g;
+}
+
+// LDS row stride of a staged strip: 128 elements plus 16 elements of padding,
+// so the four rows a fragment read touches start on different banks.
+template <typename TC> constexpr int gr_stride() { return GR_W + 16; }
+template <typename TC> constexpr int gr_rs() { return sizeof(TC) == 8 ? GR_RS / 2 : GR_RS; }
+
+// Elements [c0, c0 + 8) of row `row` (c0 a multiple of 8; zeros past K or rend).
+// mode 0: 16-byte runs of 16-bit values; 1: 8-byte pieces; 2: single elements.
 template <typename TC>
-__global__ __launch_bounds__(256) void gram_kernel(int64_t M, int K, const TC* __restrict__ X, int ntiles, int ng,
-                                                   int nb, int64_t rows_per, double* __restrict__ part) {
-  constexpr int EPT = GramEpt<TC>::v;
-  constexpr int ESZ = (int)sizeof(TC);
-  extern __shared__ __align__(16) unsigned char gram_lds[];
-  // XCD-aware order: consecutive block ids go to different XCDs, so the
-  // tile groups of one row block are given ids that share an XCD (and its L2).
-  const int id = blockIdx.x, xcd = id & 7, slot = id >> 3;
-  const int grp = slot % ng, rb = (slot / ng) * 8 + xcd;
-  if (rb >= nb) return;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
-  const int64_t rbeg = (int64_t)rb * rows_per;
-  const int64_t rend = rbeg + rows_per < M ? rbeg + rows_per : M;
-
-  int ti[GRAM_TPW], tj[GRAM_TPW];
-  bool ok[GRAM_TPW];
-  f64x4 acc[GRAM_TPW];
+__device__ __forceinline__ void gr_load8(const TC* __restrict__ X, int64_t ldx, int64_t row, int64_t rend, int K, int c0,
+                                         int mode, TC (&v)[8]) {
 #pragma unroll
-  for (int q = 0; q < GRAM_TPW; ++q) {
-    const int t = grp * GRAM_TPB + wave * GRAM_TPW + q;
-    ok[q] = t < ntiles;
-    const int a = tri_row_dev(ok[q] ? t : 0);
-    ti[q] = ok[q] ? a : 0;
-    tj[q] = ok[q] ? t - a * (a + 1) / 2 : 0;
-    acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
-  }
-  const int tlast = min(grp * GRAM_TPB + GRAM_TPB, ntiles) - 1;
-  const GramStage sg = gram_stage(K, tri_row_dev(tlast), ESZ, EPT);
-  const int rs = sg.rs, kb = sg.kb, stride = sg.stride;
-
-  // Fragment columns in [kb, kal) stay zero for the whole kernel.
-  for (int e = tid; e < rs * (sg.kal - kb); e += 256) {
-    const int row = e / (sg.kal - kb), col = kb + e % (sg.kal - kb);
-    *(TC*)(gram_lds + row * stride + col * ESZ) = (TC)0.0f;
-  }
-
-  // Element e = i*256 + tid of a stage is (row e / kb, column e % kb).
-  const int step_r = 256 / kb, step_c = 256 % kb;
-  const int row_t = tid / kb, col_t = tid % kb;
-  const TC* zero = (const TC*)kTileZero;
-  TC v[EPT];
-  auto load = [&](int64_t r0) {
-    int row = row_t, col = col_t;
-    asm volatile("" : "+v"(row), "+v"(col));  // recomputed per stage, not held in registers
+  for (int q = 0; q < 8; ++q) v[q] = from_f64<TC>(0.0);
+  if (row >= rend || c0 >= K) return;
+  const TC* p = X + row * ldx + c0;
+  if (c0 + 8 <= K && mode == 0 && sizeof(TC) == 2) {
+    const uint4 w = *(const uint4*)p;
+    const TC* e = (const TC*)&w;
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const bool in = row < rs && r0 + row < rend;
-      const TC* src = in ? X + (r0 + row) * (int64_t)K + col : zero;
-      v[i] = *src;
-      col += step_c;
-      row += step_r;
-      if (col >= kb) { col -= kb; ++row; }
+    for (int q = 0; q < 8; ++q) v[q] = e[q];
+  } else if (c0 + 8 <= K && mode <= 1 && sizeof(TC) <= 4) {
+    constexpr int PE = 8 / sizeof(TC);  // elements per 8-byte piece
+#pragma unroll
+    for (int q = 0; q < 8; q += PE) {
+      const uint2 w = *(const uint2*)(p + q);
+      const TC* e = (const TC*)&w;
+#pragma unroll
+      for (int u = 0; u < PE; ++u) v[q + u] = e[u];
     }
-  };
-  auto store = [&]() {
-    int row = row_t, col = col_t;
-    asm volatile("" : "+v"(row), "+v"(col));  // recomputed per stage, not held in registers
+  } else {
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      if (row < rs) *(TC*)(gram_lds + row * stride + col * ESZ) = v[i];
-      col += step_c;
-      row += step_r;
-      if (col >= kb) { col -= kb; ++row; }
-    }
-  };
-
-  const int64_t nrows = rend > rbeg ? rend - rbeg : 0;
-  const int nst = (int)ceil_div(nrows, rs);
-  if (nst > 0) load(rbeg);
-  for (int s = 0; s < nst; ++s) {
-    __syncthreads();
-    store();
-    __syncthreads();
-    if (s + 1 < nst) load(rbeg + (int64_t)(s + 1) * rs);
-    const unsigned char* base = gram_lds + g * stride + r * ESZ;
-#pragma unroll 2
-    for (int qd = 0; qd < rs / 4; ++qd) {
-      const unsigned char* rowp = base + 4 * qd * stride;
-#pragma unroll
-      for (int q = 0; q < GRAM_TPW; ++q) {
-        if (!ok[q]) continue;  // uniform over the wave
-        const double av = to_f64(*(const TC*)(rowp + ti[q] * 16 * ESZ));
-        const double bv = to_f64(*(const TC*)(rowp + tj[q] * 16 * ESZ));
-        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[q], 0, 0, 0);
-      }
-    }
-  }
-  // part layout: [tile][row block][256]
-#pragma unroll
-  for (int q = 0; q < GRAM_TPW; ++q) {
-    if (!ok[q]) continue;
-    const int t = grp * GRAM_TPB + wave * GRAM_TPW + q;
-    double* dst = part + ((int64_t)t * nb + rb) * 256;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) dst[out_row<double>(g, i) * 16 + r] = acc[q][i];
+    for (int q = 0; q < 8; ++q)
+      if (c0 + q < K) v[q] = p[q];
   }
 }
 
-// One block per (tile, quarter of the tile): four groups of 64 threads sum
-// four fixed ranges of row blocks in increasing order, then the four sums are
-// added in a fixed order.
+template <typename TC>
+__global__ __launch_bounds__(256, 2) void gram_kernel(int64_t M, int K, int64_t ldx, const TC* __restrict__ X, int ns,
+                                                      int nb, int64_t rows_per, int mode, double* __restrict__ part) {
+  constexpr int LS = gr_stride<TC>();
+  constexpr int RS = gr_rs<TC>();
+  constexpr int NV = 2 * RS * GR_W / 8 / 256;  // 8-element pieces per thread and stage (both strips)
+  __shared__ TC xs[2][2][RS * LS];           // [buffer][strip i / j][row][column]
+  const int id = blockIdx.x, xcd = id & 7, slot = id >> 3;
+  const int st = slot % ns, rb = (slot / ns) * 8 + xcd;
+  if (rb >= nb) return;
+  const int I = tri_row_dev(st), J = st - I * (I + 1) / 2;
+  const bool diag = I == J;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
+  const int wr = wave >> 1, wc = wave & 1;
+  const bool active = !(diag && wr < wc);  // strictly upper quarter of a diagonal super-tile: not needed
+  const int64_t rbeg = (int64_t)rb * rows_per;
+  const int64_t rend = rbeg + rows_per < M ? rbeg + rows_per : M;
+  const int nstage = rend > rbeg ? (int)ceil_div(rend - rbeg, RS) : 0;
+
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  // piece e = tid + 256 u: strip (e / (GR_RS * 16)), row, 8-column piece
+  TC pv[NV][8];
+  auto load = [&](int s) {
+    const int64_t r0 = rbeg + (int64_t)s * RS;
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int e = tid + 256 * u;
+      const int sj = e / (RS * 16), rem = e - sj * (RS * 16), row = rem >> 4, pc = rem & 15;
+      const int c0 = (sj ? J : I) * GR_W + 8 * pc;
+      if (sj && diag) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) pv[u][q] = from_f64<TC>(0.0);
+      } else {
+        gr_load8<TC>(X, ldx, r0 + row, rend, K, c0, mode, pv[u]);
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int e = tid + 256 * u;
+      const int sj = e / (RS * 16), rem = e - sj * (RS * 16), row = rem >> 4, pc = rem & 15;
+      TC* dst = &xs[buf][sj][row * LS + 8 * pc];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) dst[q] = pv[u][q];
+    }
+  };
+  if (nstage > 0) load(0);
+  for (int s = 0; s < nstage; ++s) {
+    const int buf = s & 1;
+    store(buf);
+    __syncthreads();
+    if (s + 1 < nstage) load(s + 1);
+    if (active) {
+      const TC* xi = &xs[buf][0][64 * wr + r];
+      const TC* xj = diag ? &xs[buf][0][64 * wc + r] : &xs[buf][1][64 * wc + r];
+#pragma unroll 2
+      for (int q = 0; q < RS / 4; ++q) {
+        const int ro = (4 * q + g) * LS;
+        double av[4], bv[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) av[a] = to_f64(xi[ro + 16 * a]);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bv[b] = to_f64(xj[ro + 16 * b]);
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+      }
+    }
+    // no barrier here: the next stage goes to the other buffer, and the one after it is written only
+    // once every wave has passed the next barrier, i.e. finished reading this one
+  }
+  // part layout: [super-tile][row block][128 x 128], element (i, j) of the super-tile at i * 128 + j
+  if (active) {
+    double* dst = part + ((int64_t)st * nb + rb) * (GR_W * GR_W);
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          dst[(64 * wr + 16 * a + out_row<double>(g, i)) * GR_W + 64 * wc + 16 * b + r] = acc[a][b][i];
+  }
+}
+
+// Per super-tile element: the row-block partials summed in increasing block
+// order by four groups of 64 threads over four fixed ranges, then the four
+// sums added in a fixed order; written to G and mirrored.
 __global__ __launch_bounds__(256) void gram_reduce_kernel(int K, int nb, const double* __restrict__ part,
                                                           double* __restrict__ G) {
   __shared__ double red[4][64];
-  const int t = blockIdx.x;
-  const int a = tri_row_dev(t);
-  const int ti = a, tj = t - a * (a + 1) / 2;
+  const int st = blockIdx.x;
+  const int I = tri_row_dev(st), J = st - I * (I + 1) / 2;
   const int e = blockIdx.y * 64 + (threadIdx.x & 63), c = threadIdx.x >> 6;
+  const int li = e / GR_W, lj = e % GR_W;
+  const int gi = I * GR_W + li, gj = J * GR_W + lj;
+  const bool need = gi < K && gj < K && gi >= gj;
   const int b0 = (int)(((int64_t)nb * c) / 4), b1 = (int)(((int64_t)nb * (c + 1)) / 4);
   double s = 0.0;
-  for (int b = b0; b < b1; ++b) s += part[((int64_t)t * nb + b) * 256 + e];
+  if (need)
+    for (int b = b0; b < b1; ++b) s += part[((int64_t)st * nb + b) * (GR_W * GR_W) + e];
   red[c][threadIdx.x & 63] = s;
   __syncthreads();
-  if (c != 0) return;
+  if (c != 0 || !need) return;
   const int l = threadIdx.x;
   const double tot = (red[0][l] + red[1][l]) + (red[2][l] + red[3][l]);
-  const int i = ti * 16 + e / 16, j = tj * 16 + e % 16;
-  if (i < K && j < K) {
-    G[(int64_t)i * K + j] = tot;
-    G[(int64_t)j * K + i] = tot;
-  }
+  G[(int64_t)gi * K + gj] = tot;
+  G[(int64_t)gj * K + gi] = tot;
 }
 
 size_t gram_ws_bytes(int64_t M, int K) {
-  // The call may use any K' <= K (the retained rank), and the row-block count
-  // grows as the tile count falls, so take the largest product.
+  // The call may use any K' <= K (the retained rank); the partials grow with the super-tile count.
   size_t best = 0;
-  for (int kk = 16; kk < K + 16; kk += 16) {
-    const GramPlan g = gram_plan(M, kk < K ? kk : K);
-    best = std::max(best, (size_t)g.ntiles * g.nb * 256 * sizeof(double));
+  for (int kk = 1; kk <= K; kk += (kk == 1 ? GR_W - 1 : GR_W)) {
+    const GramPlan g = gram_plan(M, std::min(kk, K));
+    best = std::max(best, (size_t)g.ns * g.nb * GR_W * GR_W * sizeof(double));
   }
+  const GramPlan g = gram_plan(M, K);
+  best = std::max(best, (size_t)g.ns * g.nb * GR_W * GR_W * sizeof(double));
   return align256(best);
 }
 
 template <typename TC>
-static size_t gram_lds_bytes(const GramPlan& g, int K) {
-  size_t best = 0;
-  for (int grp = 0; grp < g.ng; ++grp) {
-    const int tlast = std::min(grp * GRAM_TPB + GRAM_TPB, g.ntiles) - 1;
-    const GramStage s = gram_stage(K, tri_row(tlast), (int)sizeof(TC), GramEpt<TC>::v);
-    best = std::max(best, (size_t)s.rs * s.stride);
-  }
-  return best;
-}
-
-template <typename TC>
 static void gram_launch(const GramPlan& g, int64_t M, int K, const TC* X, double* part, hipStream_t st) {
-  const int nblk = (int)(ceil_div(g.nb, 8) * 8 * g.ng);
-  hipLaunchKernelGGL(gram_kernel<TC>, dim3(nblk), dim3(256), gram_lds_bytes<TC>(g, K), st, M, K, X, g.ntiles, g.ng,
-                     g.nb, g.rows_per, part);
+  // rows as 16-byte runs (16-bit types), 8-byte pieces, or elements
+  const size_t rowb = (size_t)K * sizeof(TC);
+  const int mode = (sizeof(TC) == 2 && rowb % 16 == 0 && ((uintptr_t)X % 16) == 0) ? 0
+                   : (sizeof(TC) <= 4 && rowb % 8 == 0 && ((uintptr_t)X % 8) == 0) ? 1 : 2;
+  const int nblk = g.nb * g.ns;
+  hipLaunchKernelGGL(gram_kernel<TC>, dim3(nblk), dim3(256), 0, st, M, K, (int64_t)K, X, g.ns, g.nb, g.rows_per, mode,
+                     part);
 }
 
 hipError_t launch_gram(int64_t M, int K, int compute, const void* X, double* G, void* ws, hipStream_t st) {
-  // K <= 1024 keeps one stage within one register load per thread and element slot.
   if (M <= 0 || K <= 0 || K > 1024) return hipErrorInvalidValue;
   TimerScope ts(T_GRAM, st);
   const GramPlan g = gram_plan(M, K);
@@ -626,7 +730,7 @@ hipError_t launch_gram(int64_t M, int K, int compute, const void* X, double* G, 
     case P_F16: gram_launch<f16>(g, M, K, (const f16*)X, part, st); break;
     default: return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3(g.ntiles, 4), dim3(256), 0, st, K, g.nb, part, G);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(g.ns, GR_W * GR_W / 64), dim3(256), 0, st, K, g.nb, part, G);
   return hipGetLastError();
 }
 
