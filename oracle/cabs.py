@@ -23,7 +23,7 @@ EPS = float(np.finfo(np.float64).eps)
 
 WEIGHT_KINDS = ("const", "pow", "sigmoid", "step")
 SKETCH_KINDS = ("stabilized", "pseudo_skeleton")
-FOLLOW_UPS = ("kmeans", "hard")
+FOLLOW_UPS = ("kmeans", "hard", "leverage")
 
 
 class RankError(RuntimeError):
@@ -46,7 +46,7 @@ class Params:
     pinv_rtol: float = 0.0           # <= 0: max(kr, kc) * eps * sigma_1
     seed: int = 0
     factors: bool = False            # also return the orthogonalised factor form of the result
-    follow_up: str = "kmeans"        # "hard": the hard-threshold variant of Section 5
+    follow_up: str = "kmeans"        # "hard" / "leverage": the hard-threshold / leverage variants of Section 5
 
     @classmethod
     def square(cls, k: int, **kw) -> "Params":
@@ -249,6 +249,31 @@ def hard_threshold(w: np.ndarray, k: int) -> np.ndarray:
     return np.sort(order[:k]).astype(np.int64)
 
 
+def leverage_scores(u: np.ndarray, s: np.ndarray, p: int) -> np.ndarray:
+    """Approximate leverage scores of the rows of A (Section 5's leverage variant, made possible
+    by the orthogonalisation of the supplementary material): the squared row norms of the pilot
+    sketch's left factor U (orthonormal after orthogonalisation).  Reading: only components whose
+    singular value exceeds p * eps * max(s), p = min(k1_rows, k1_cols), count, since a component
+    below that cut carries no information about A."""
+    s = np.asarray(s, dtype=np.float64)
+    keep = s > p * EPS * s.max() if s.size and s.max() > 0.0 else np.zeros(s.size, dtype=bool)
+    return (u[:, keep] ** 2).sum(axis=1)
+
+
+def leverage_sample(scores: np.ndarray, k: int, seed: int, stream: int) -> np.ndarray:
+    """k distinct rows drawn with probabilities proportional to `scores`, without replacement
+    (Section 5's leverage variant; the paper does not say how).  Reading: weighted sampling
+    without replacement by exponential races (Efraimidis and Spirakis, Inf. Proc. Letters 97(5),
+    2006): row i gets key ln(u_i) / score_i with u_i in (0, 1] from the counter-based generator
+    (unit_draws on `stream`), rows of score 0 get -inf, and the k largest keys are taken, equal
+    keys to the lower row.  This is the law of drawing k rows one after another, each with
+    probability proportional to its score among the rows not yet drawn.  Returned ascending."""
+    u = philox.unit_draws(scores.size, seed, stream)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        key = np.where(scores > 0.0, np.log(u) / np.where(scores > 0.0, scores, 1.0), -np.inf)
+    return hard_threshold(key, k)
+
+
 def snap(p: np.ndarray, z: np.ndarray, tie_rtol: float = SNAP_TIE_RTOL) -> np.ndarray:
     """Replace every centre by its nearest in-sample point (Section 3.2).
 
@@ -402,13 +427,19 @@ def cabs(spec, prm: Params, track: bool = False) -> Result:
     q = vo * root
 
     # Step 3: follow-up sampling by weighted k-means, then snapping (or, in the
-    # hard-threshold variant of Section 5, the rows with the largest weights).
+    # variants of Section 5, the rows with the largest weights, or rows drawn
+    # with probabilities proportional to approximate leverage scores).
     w_r = upsilon(np.linalg.norm(p, axis=1), prm.weight_kind, prm.weight_param)
     w_c = upsilon(np.linalg.norm(q, axis=1), prm.weight_kind, prm.weight_param)
     if prm.follow_up == "hard":
         km_r = km_c = None
         jr = hard_threshold(w_r, prm.k2_rows)
         jc = hard_threshold(w_c, prm.k2_cols)
+    elif prm.follow_up == "leverage":
+        km_r = km_c = None
+        p1 = min(prm.k1_rows, prm.k1_cols)
+        jr = leverage_sample(leverage_scores(uo, so, p1), prm.k2_rows, prm.seed, philox.STREAM_LEVERAGE_ROWS)
+        jc = leverage_sample(leverage_scores(vo, so, p1), prm.k2_cols, prm.seed, philox.STREAM_LEVERAGE_COLS)
     else:
         z0r = initial_centres(p, ir, prm.k2_rows, m, prm.seed, philox.STREAM_INIT_ROWS)
         z0c = initial_centres(q, ic, prm.k2_cols, n, prm.seed, philox.STREAM_INIT_COLS)

@@ -35,6 +35,8 @@ STREAM_PILOT_COLS = 1
 STREAM_INIT_ROWS = 2
 STREAM_INIT_COLS = 3
 STREAM_ERROR = 4
+STREAM_LEVERAGE_ROWS = 5
+STREAM_LEVERAGE_COLS = 6
 
 PHILOX32_M0 = np.uint64(0xD2511F53)
 PHILOX32_M1 = np.uint64(0xCD9E8D57)
@@ -149,6 +151,12 @@ def floyd_sample(n: int, k: int, seed: int, stream: int) -> np.ndarray:
     for vi, ji in zip(v.tolist(), j.tolist()):
         chosen.add(ji if vi in chosen else vi)
     return np.array(sorted(chosen), dtype=np.int64)
+
+
+def unit_draws(n: int, seed: int, stream: int) -> np.ndarray:
+    """u_i in (0, 1] for i = 0..n-1: word 0 of the Philox-4x64-10 block at counter (i, 0, stream, 0),
+    key (seed, 0), through to_unit_open0."""
+    return to_unit_open0(philox4x64(np.arange(n, dtype=np.uint64), 0, stream, 0, seed, 0)[0])
 
 
 def error_sample_indices(m: int, n: int, count: int, seed: int, start: int = 0):
