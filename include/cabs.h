@@ -68,9 +68,19 @@ typedef enum { CABS_W_CONST = 0, CABS_W_POW = 1, CABS_W_SIGMOID = 2, CABS_W_STEP
  * pilot embeddings from the pilot sample, then each centre snapped to its
  * nearest untaken row (Section 3.2).  HARD: the hard-threshold variant of
  * Section 5: the k2 rows (columns) with the largest weights Upsilon(|P_l|),
- * equal weights to the lower index, NaN weights last; no k-means, and the
- * encoding-error diagnostics stay 0. */
-typedef enum { CABS_FOLLOW_KMEANS = 0, CABS_FOLLOW_HARD = 1 } cabs_follow_up;
+ * equal weights to the lower index, NaN weights last.  LEVERAGE: the
+ * leverage variant of Section 5: k2 distinct rows (columns) drawn with
+ * probabilities proportional to approximate leverage scores, the squared row
+ * norms of the pilot sketch's left (right) factor (orthonormal when
+ * `orthogonalize` is set, as the supplementary orthogonalisation section
+ * intends) over the components whose singular value exceeds
+ * p eps max (p = min(k1_rows, k1_cols)); drawn without replacement by
+ * exponential races: row i gets the key ln(u_i) / score_i (-inf for score 0),
+ * u_i in (0, 1] from word 0 of Philox-4x64-10 at counter (i, 0, 5, 0) for rows
+ * and (i, 0, 6, 0) for columns, key (seed, 0), and the k2 largest keys are
+ * taken, equal keys to the lower index.  HARD and LEVERAGE run no k-means and
+ * leave the encoding-error diagnostics at 0; both need m, n < 2^31 - 1. */
+typedef enum { CABS_FOLLOW_KMEANS = 0, CABS_FOLLOW_HARD = 1, CABS_FOLLOW_LEVERAGE = 2 } cabs_follow_up;
 
 /* The sketching routine: the stabilised form of Section 4.1 (default), or the
  * pseudo-skeleton A ~ C W^+ R of Eq. (W), Section 2.2. */

@@ -96,7 +96,7 @@ def make_params(k1_rows, k1_cols, k2_rows, k2_cols, kmeans_iters=5, weight="cons
     p.pinv_rtol = pinv_rtol
     p.compute = PREC[compute]
     p.want_factors = 1 if factors else 0
-    p.follow_up = {"kmeans": 0, "hard": 1}[follow_up]
+    p.follow_up = {"kmeans": 0, "hard": 1, "leverage": 2}[follow_up]
     p.flags = F.FLAG_COUNT_ENTRIES if count_entries else 0
     p.seed = seed
     return p

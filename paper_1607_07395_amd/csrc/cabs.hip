@@ -167,6 +167,65 @@ __global__ void weights_kernel(int64_t rows, const double* __restrict__ rowsq, i
   w[r] = v;
 }
 
+// Reciprocals of the embedding's singular values over the kept components
+// (> p eps max), zero for the others, so that sum_t P_lt^2 inv_t is the
+// squared row norm of the factor behind P = U' diag(s)^(1/2).
+__global__ void lev_inv_kernel(int p, const double* __restrict__ s, double* __restrict__ inv) {
+  __shared__ double smax;
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int t = 0; t < p; ++t) m = s[t] > m ? s[t] : m;
+    smax = m;
+  }
+  __syncthreads();
+  const double cut = (double)p * 2.220446049250313e-16 * smax;
+  for (int t = threadIdx.x; t < p; t += blockDim.x) inv[t] = (smax > 0.0 && s[t] > cut) ? 1.0 / s[t] : 0.0;
+}
+
+// Leverage-variant keys (Section 5): score_l = sum_t P_lt^2 inv_t (FP64, one
+// wave per row, lane-strided partial sums then a fixed butterfly), key_l =
+// ln(u_l) / score_l with u_l in (0, 1] from Philox-4x64-10 at counter
+// (l, 0, stream, 0), key (seed, 0); -inf for a zero score.  The selection of
+// the k largest keys is the hard-threshold selection.
+template <typename TC>
+__global__ __launch_bounds__(256) void lev_keys_kernel(int64_t rows, int ld, int e, const TC* __restrict__ P,
+                                                       const double* __restrict__ inv, uint64_t seed, uint64_t stream,
+                                                       double* __restrict__ key) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= rows) return;
+  double s = 0.0;
+  for (int t = lane; t < e; t += 64) {
+    const double v = to_f64(P[row * ld + t]);
+    s += v * v * inv[t];
+  }
+  s = wave_sum(s);
+  if (lane == 0) {
+    const u64x4 w = philox4x64((uint64_t)row, 0, stream, 0, seed, 0);
+    const double u = unit_open0(w.v[0]);
+    key[row] = s > 0.0 ? log(u) / s : -__builtin_huge_val();
+  }
+}
+
+template <typename TC>
+static void launch_lev_keys(int64_t rows, int ld, int e, const void* P, const double* inv, uint64_t seed,
+                            uint64_t stream, double* key, hipStream_t st) {
+  hipLaunchKernelGGL(lev_keys_kernel<TC>, dim3((unsigned)ceil_div(rows, 4)), dim3(256), 0, st, rows, ld, e,
+                     (const TC*)P, inv, seed, stream, key);
+}
+
+static hipError_t launch_lev_keys_any(int prec, int64_t rows, int ld, int e, const void* P, const double* inv,
+                                      uint64_t seed, uint64_t stream, double* key, hipStream_t st) {
+  switch (prec) {
+    case CABS_F64: launch_lev_keys<double>(rows, ld, e, P, inv, seed, stream, key, st); break;
+    case CABS_F32: launch_lev_keys<float>(rows, ld, e, P, inv, seed, stream, key, st); break;
+    case CABS_BF16: launch_lev_keys<bf16>(rows, ld, e, P, inv, seed, stream, key, st); break;
+    case CABS_F16: launch_lev_keys<f16>(rows, ld, e, P, inv, seed, stream, key, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 __global__ void diag_init_kernel(double* __restrict__ diag, unsigned long long* __restrict__ counter, int counted) {
   const int i = threadIdx.x;
   if (i < CABS_DIAG_LEN) diag[i] = i == CABS_DIAG_ENTRIES ? (counted ? 0.0 : -1.0) : 0.0;
@@ -324,6 +383,7 @@ struct SketchWs {
   void *C, *Rt, *P, *Q;
   double *rowsqP, *rowsqQ, *wr, *wc, *Z0r, *Z0c, *Zr, *Zc, *diag, *obj;
   unsigned long long* entries;
+  double* levinv;      // leverage variant: reciprocal singular values of the kept components
   double *MuP, *MvP;  // the embedding maps with ep - p1 zero columns (16-bit compute, p1 not a multiple of 8)
   void* ts6;
   void *kmr, *kmc, *selr, *selc;
@@ -354,10 +414,11 @@ static size_t plan_sketch(void* ws, const Plan& pl, const cabs_params* prm, Sket
   S.MuP = ep != e ? cv.take<double>((size_t)e * ep) : nullptr;
   S.MvP = ep != e ? cv.take<double>((size_t)e * ep) : nullptr;
   S.ts6 = ep != e ? cv.take_bytes(tsgemm_ws_bytes(std::max(pl.m, pl.n), e, ep, pl.prec)) : nullptr;
+  S.levinv = cv.take<double>(std::max(e, 1));
   S.diag = cv.take<double>(CABS_DIAG_LEN);
   S.obj = cv.take<double>(8);
   S.entries = cv.take<unsigned long long>(1);
-  if (prm->follow_up == CABS_FOLLOW_HARD) {
+  if (prm->follow_up == CABS_FOLLOW_HARD || prm->follow_up == CABS_FOLLOW_LEVERAGE) {
     S.kmr = S.kmc = nullptr;
     S.selr = cv.take_bytes(select_ws_bytes(pl.m));
     S.selc = cv.take_bytes(select_ws_bytes(pl.n));
@@ -425,11 +486,12 @@ static cabs_status check_params(const cabs_matrix* mat, const cabs_params* prm) 
   if (prm->weight_kind < CABS_W_CONST || prm->weight_kind > CABS_W_STEP) return fail(CABS_EINVAL, "unknown weight kind");
   if (prm->sketch_kind != CABS_SK_STABILIZED && prm->sketch_kind != CABS_SK_PSEUDO_SKELETON)
     return fail(CABS_EINVAL, "unknown sketch kind");
-  if (prm->follow_up != CABS_FOLLOW_KMEANS && prm->follow_up != CABS_FOLLOW_HARD)
+  if (prm->follow_up != CABS_FOLLOW_KMEANS && prm->follow_up != CABS_FOLLOW_HARD &&
+      prm->follow_up != CABS_FOLLOW_LEVERAGE)
     return fail(CABS_EINVAL, "unknown follow-up kind");
   if (prm->flags & ~CABS_FLAG_COUNT_ENTRIES) return fail(CABS_EINVAL, "unknown flag bits");
-  if (prm->follow_up == CABS_FOLLOW_HARD && (mat->m >= INT32_MAX || mat->n >= INT32_MAX))
-    return fail(CABS_EINVAL, "the hard-threshold selection needs m, n < 2^31 - 1");
+  if (prm->follow_up != CABS_FOLLOW_KMEANS && (mat->m >= INT32_MAX || mat->n >= INT32_MAX))
+    return fail(CABS_EINVAL, "the hard-threshold and leverage selections need m, n < 2^31 - 1");
   return CABS_OK;
 }
 
@@ -609,6 +671,17 @@ extern "C" cabs_status cabs_sketch(const cabs_matrix* mat, const cabs_params* pr
   // 7: follow-up sampling.  Hard-threshold variant (Section 5): the rows and
   // columns with the largest weights.
   if (prm->follow_up == CABS_FOLLOW_HARD) {
+    HIP_TRY(launch_select_topk(pl.m, S.wr, pl.kr2, out->idx_r, S.selr, st));
+    HIP_TRY(launch_select_topk(pl.n, S.wc, pl.kc2, out->idx_c, S.selc, st));
+  } else if (prm->follow_up == CABS_FOLLOW_LEVERAGE) {
+    // Leverage variant (Section 5): keys from the squared row norms of the factors behind P and Q
+    // (P = U' diag(s)^(1/2), s = the orthogonalised singular values, or the sketch's S without
+    // orthogonalisation), then the k largest keys.  The weights buffers hold the keys.
+    const double* sv = prm->orthogonalize ? S.r1.S1 : S.r1.sk;
+    hipLaunchKernelGGL(lev_inv_kernel, dim3(1), dim3(256), 0, st, e, sv, S.levinv);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(launch_lev_keys_any(pl.prec, pl.m, ep, e, S.P, S.levinv, prm->seed, STREAM_LEVERAGE_ROWS, S.wr, st));
+    HIP_TRY(launch_lev_keys_any(pl.prec, pl.n, ep, e, S.Q, S.levinv, prm->seed, STREAM_LEVERAGE_COLS, S.wc, st));
     HIP_TRY(launch_select_topk(pl.m, S.wr, pl.kr2, out->idx_r, S.selr, st));
     HIP_TRY(launch_select_topk(pl.n, S.wc, pl.kc2, out->idx_c, S.selc, st));
   } else {

@@ -79,7 +79,7 @@ __device__ __forceinline__ double unit_open1(uint64_t x) { return (double)(x >> 
 
 enum : uint64_t {
   STREAM_PILOT_ROWS = 0, STREAM_PILOT_COLS = 1, STREAM_INIT_ROWS = 2, STREAM_INIT_COLS = 3,
-  STREAM_ERROR = 4
+  STREAM_ERROR = 4, STREAM_LEVERAGE_ROWS = 5, STREAM_LEVERAGE_COLS = 6
 };
 
 // Philox-4x32-10: the same round structure on 32-bit words, one 32x32->64
