@@ -60,12 +60,14 @@ def test_workspace_planning_and_validation_on_cpu():
     d.kind = 7
     assert lib.cabs_workspace_bytes(C.byref(d), C.byref(p)) == 0
     assert b"unknown source kind" in lib.cabs_last_error()
-    # follow-up kind: the hard-threshold selection plans its own workspace; unknown kinds and a
-    # unknown flag bits are rejected
+    # follow-up kind: the hard-threshold and leverage selections plan their own workspace;
+    # unknown kinds and unknown flag bits are rejected
     d = _desc()
     h = make_params(20, 20, 20, 20, compute="f32", follow_up="hard")
     assert lib.cabs_workspace_bytes(C.byref(d), C.byref(h)) > 0
-    h.follow_up = 2
+    lv = make_params(20, 20, 20, 20, compute="f32", follow_up="leverage")
+    assert lib.cabs_workspace_bytes(C.byref(d), C.byref(lv)) > 0
+    h.follow_up = 3
     assert lib.cabs_workspace_bytes(C.byref(d), C.byref(h)) == 0
     assert b"follow-up" in lib.cabs_last_error()
     h.follow_up = 0
