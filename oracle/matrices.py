@@ -42,6 +42,8 @@ class Matrix:
         if sp.kind == "rbf":
             d2 = cdist(sp.x[rows], sp.y[cols], "sqeuclidean")
             return np.exp(-np.maximum(d2, 0.0) / (2.0 * sp.sigma * sp.sigma))
+        if sp.kind == "csr":
+            return sp.sp[np.asarray(rows)][:, np.asarray(cols)].toarray().astype(np.float64)
         raise ValueError(sp.kind)
 
     def entries(self, i: np.ndarray, j: np.ndarray) -> np.ndarray:
@@ -60,6 +62,15 @@ class Matrix:
             diff = sp.x[i] - sp.y[j]
             d2 = np.einsum("tk,tk->t", diff, diff)
             return np.exp(-d2 / (2.0 * sp.sigma * sp.sigma))
+        if sp.kind == "csr":
+            # the nonzeros in row-major order have sorted keys i * n + j; an entry is listed or 0
+            a = sp.sp
+            if a.nnz == 0:
+                return np.zeros(i.shape)
+            keys = np.repeat(np.arange(self.m, dtype=np.int64), np.diff(a.indptr)) * self.n + a.indices
+            q = i * self.n + j
+            pos = np.minimum(np.searchsorted(keys, q), keys.size - 1)
+            return np.where(keys[pos] == q, a.data[pos], 0.0).astype(np.float64)
         raise ValueError(sp.kind)
 
     def full_rows(self, r0: int, r1: int) -> np.ndarray:

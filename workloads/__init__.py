@@ -12,6 +12,9 @@ from .gen import (  # noqa: F401
     dense_matrix,
     natural_scene_like,
     hubble_like,
+    sparse_matrix,
+    movie_like,
+    newsgroup_like,
     block_replicated,
     exact_rank,
     config,

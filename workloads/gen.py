@@ -32,6 +32,8 @@ class MatrixSpec:
                       generator at counter (i, j).
     kind = "rbf":     ``x`` (m x d), ``y`` (n x d), ``sigma``; A_ij =
                       exp(-|x_i - y_j|^2 / (2 sigma^2)).
+    kind = "csr":     ``sp``, a scipy.sparse CSR matrix (canonical: sorted,
+                      no duplicates) holding the nonzeros of A.
     All arrays are float64 and C-contiguous.
     """
 
@@ -47,6 +49,7 @@ class MatrixSpec:
     x: Optional[np.ndarray] = None
     y: Optional[np.ndarray] = None
     sigma: float = 1.0
+    sp: Optional[object] = None
     name: str = ""
 
     @property
@@ -57,7 +60,13 @@ class MatrixSpec:
     def d(self) -> int:
         return 0 if self.x is None else int(self.x.shape[1])
 
+    @property
+    def nnz(self) -> int:
+        return 0 if self.sp is None else int(self.sp.nnz)
+
     def nbytes(self) -> int:
+        if self.sp is not None:
+            return int(self.sp.data.nbytes + self.sp.indices.nbytes + self.sp.indptr.nbytes)
         seen, total = set(), 0
         for v in (self.a, self.pf, self.qf, self.s, self.x, self.y):
             if v is not None and id(v) not in seen:
@@ -186,6 +195,66 @@ def hubble_like(m: int = 15852, n: int = 12392, seed: int = 0, blobs: int = 4000
         xx = np.arange(xs.start, xs.stop)[None, :] - x0
         a[ys, xs] += h * np.exp(-(yy * yy + xx * xx) / (2.0 * w * w))
     return dense_matrix(np.minimum(a, 1.0), name=f"hubble-{m}x{n}")
+
+
+def _zipf_weights(n: int, a: float, rng: np.random.Generator) -> np.ndarray:
+    """Probabilities proportional to rank^-a over a random permutation of n items."""
+    w = np.arange(1, n + 1, dtype=np.float64) ** -a
+    w = w[rng.permutation(n)]
+    return w / w.sum()
+
+
+def _distinct_pairs(nnz: int, pr: np.ndarray, pc: np.ndarray, rng: np.random.Generator):
+    """nnz distinct (row, column) positions, rows and columns drawn independently with
+    probabilities pr and pc (repeated draws are discarded and drawn again)."""
+    m, n = pr.size, pc.size
+    key = np.empty(0, dtype=np.int64)
+    while key.size < nnz:
+        draw = int((nnz - key.size) * 1.3) + 1024
+        new = rng.choice(m, size=draw, p=pr).astype(np.int64) * n + rng.choice(n, size=draw, p=pc)
+        key = np.unique(np.concatenate([key, new]))
+    key = key[np.sort(rng.permutation(key.size)[:nnz])]
+    return key // n, key % n
+
+
+def sparse_matrix(rows: np.ndarray, cols: np.ndarray, vals: np.ndarray, m: int, n: int, name: str) -> MatrixSpec:
+    """A CSR source from (row, column, value) triplets (duplicates summed, explicit zeros dropped)."""
+    import scipy.sparse as sps
+    a = sps.csr_matrix((np.asarray(vals, dtype=np.float64), (np.asarray(rows), np.asarray(cols))), shape=(m, n))
+    a.sum_duplicates()
+    a.eliminate_zeros()
+    a.sort_indices()
+    a.indices = a.indices.astype(np.int32)
+    a.indptr = a.indptr.astype(np.int64)
+    return MatrixSpec(kind="csr", m=m, n=n, sp=a, name=name)
+
+
+def movie_like(m: int = 27000, n: int = 46000, density: float = 0.0056, seed: int = 0, rank: int = 12) -> MatrixSpec:
+    """Sparse stand-in for a movie-rating matrix (users x movies): density * m * n ratings at
+    distinct positions, user and movie degrees Zipf-distributed (exponent 0.7), integer ratings
+    1..5 from a rank-`rank` preference model plus user and movie offsets and noise."""
+    rng = np.random.default_rng(seed)
+    nnz = int(round(density * m * n))
+    i, j = _distinct_pairs(nnz, _zipf_weights(m, 0.7, rng), _zipf_weights(n, 0.7, rng), rng)
+    u = rng.normal(size=(m, rank)) / np.sqrt(rank)
+    v = rng.normal(size=(n, rank))
+    bu, bv = rng.normal(0.0, 0.4, m), rng.normal(0.0, 0.5, n)
+    r = 3.5 + bu[i] + bv[j] + np.einsum("tk,tk->t", u[i], v[j]) + rng.normal(0.0, 0.5, i.size)
+    return sparse_matrix(i, j, np.clip(np.rint(r), 1.0, 5.0), m, n, f"movie-like-{m}x{n}")
+
+
+def newsgroup_like(m: int = 18774, n: int = 61188, density: float = 0.0022, seed: int = 0) -> MatrixSpec:
+    """Sparse stand-in for a document-term count matrix: density * m * n nonzeros at distinct
+    positions, term frequencies Zipf-distributed (exponent 1.1), document lengths log-normal,
+    counts 1 + Poisson growing with the term's frequency."""
+    rng = np.random.default_rng(seed)
+    nnz = int(round(density * m * n))
+    pt = _zipf_weights(n, 1.1, rng)
+    dl = np.exp(rng.normal(0.0, 0.8, m))
+    pd = dl / dl.sum()
+    i, j = _distinct_pairs(nnz, pd, pt, rng)
+    lam = 0.3 + 2.0 * np.sqrt(pt[j] / pt.max())
+    return sparse_matrix(i, j, 1.0 + rng.poisson(lam), m, n, f"newsgroup-like-{m}x{n}")
 
 
 # Benchmark and parity configurations.  Each entry: matrix recipe + sketch sizes.
