@@ -57,7 +57,8 @@ typedef enum {
                            g a standard normal by Box-Muller on Philox-4x32-10 at counter
                            (lo i, hi i, lo j, hi j), key (lo noise_seed, hi noise_seed): words
                            1:0 give u1 in (0, 1], words 3:2 u2 in [0, 1); E is never stored */
-  CABS_SRC_RBF = 2      /* A_ij = exp(-|x_i - y_j|^2 / (2 sigma^2)) */
+  CABS_SRC_RBF = 2,     /* A_ij = exp(-|x_i - y_j|^2 / (2 sigma^2)) */
+  CABS_SRC_CSR = 3      /* sparse A, its nonzeros in both CSR and CSC order */
 } cabs_src;
 
 /* The monotone weight Upsilon(|P_l|) of the weighted k-means objective
@@ -110,6 +111,20 @@ typedef struct {
   int32_t d;
   int32_t reserved1;
   double sigma;
+  /* CSR (the sparse matrices of Section 5, Table 1): the nonzeros of A twice,
+   * so that sampled rows and sampled columns are both contiguous gathers.
+   * row_ptr (m + 1, int64, row_ptr[0] = 0, row_ptr[m] = nnz), col_idx (nnz,
+   * int32, strictly ascending within a row), vals (nnz, `storage`); col_ptr
+   * (n + 1), row_idx (nnz, strictly ascending within a column), vals_t (nnz)
+   * the same nonzeros in column order.  Entries not listed are 0.  The
+   * library does not check that the two orders hold the same matrix. */
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  const void* vals;
+  const int64_t* col_ptr;
+  const int32_t* row_idx;
+  const void* vals_t;
+  int64_t nnz;
 } cabs_matrix;
 
 /* Parameters of one sketch.  Sample sizes: pilot k1_rows x k1_cols (Algorithm 2,

@@ -16,7 +16,7 @@ STATUS_NAMES = {OK: "CABS_OK", EINVAL: "CABS_EINVAL", ENOMEM: "CABS_ENOMEM", ERA
                 EDEVICE: "CABS_EDEVICE", EBUSY: "CABS_EBUSY", ECANCELED: "CABS_ECANCELED"}
 
 F64, F32, BF16, F16 = 0, 1, 2, 3
-SRC_DENSE, SRC_LOWRANK, SRC_RBF = 0, 1, 2
+SRC_DENSE, SRC_LOWRANK, SRC_RBF, SRC_CSR = 0, 1, 2, 3
 W_CONST, W_POW, W_SIGMOID, W_STEP = 0, 1, 2, 3
 SK_STABILIZED, SK_PSEUDO_SKELETON = 0, 1
 FLAG_COUNT_ENTRIES = 1
@@ -35,6 +35,8 @@ class CabsMatrix(C.Structure):
         ("pf", C.c_void_p), ("qf", C.c_void_p), ("s", C.c_void_p), ("r", C.c_int32), ("reserved0", C.c_int32),
         ("noise_std", C.c_double), ("noise_seed", C.c_uint64),
         ("x", C.c_void_p), ("y", C.c_void_p), ("d", C.c_int32), ("reserved1", C.c_int32), ("sigma", C.c_double),
+        ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("vals", C.c_void_p),
+        ("col_ptr", C.c_void_p), ("row_idx", C.c_void_p), ("vals_t", C.c_void_p), ("nnz", C.c_int64),
     ]
 
 

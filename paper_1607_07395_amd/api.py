@@ -19,7 +19,7 @@ PREC = {"f64": F.F64, "f32": F.F32, "bf16": F.BF16, "f16": F.F16}
 TORCH_DTYPE = {F.F64: torch.float64, F.F32: torch.float32, F.BF16: torch.bfloat16, F.F16: torch.float16}
 WEIGHT = {"const": F.W_CONST, "pow": F.W_POW, "sigmoid": F.W_SIGMOID, "step": F.W_STEP}
 SKETCH = {"stabilized": F.SK_STABILIZED, "pseudo_skeleton": F.SK_PSEUDO_SKELETON}
-SOURCE = {"dense": F.SRC_DENSE, "lowrank": F.SRC_LOWRANK, "rbf": F.SRC_RBF}
+SOURCE = {"dense": F.SRC_DENSE, "lowrank": F.SRC_LOWRANK, "rbf": F.SRC_RBF, "csr": F.SRC_CSR}
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -70,6 +70,20 @@ class DeviceMatrix:
             self.x = put(spec.x)
             self.y = self.x if spec.y is spec.x else put(spec.y)
             d.x, d.y, d.d, d.sigma = self.x.data_ptr(), self.y.data_ptr(), spec.d, spec.sigma
+        elif spec.kind == "csr":
+            a = spec.sp
+            t = a.tocsc()
+            t.sort_indices()
+
+            def put_i(arr, dtype):
+                x = torch.from_numpy(np.ascontiguousarray(arr.astype(dtype))).to(self.device)
+                self._keep.append(x)
+                return x
+            self.row_ptr, self.col_idx, self.vals = put_i(a.indptr, np.int64), put_i(a.indices, np.int32), put(a.data)
+            self.col_ptr, self.row_idx, self.vals_t = put_i(t.indptr, np.int64), put_i(t.indices, np.int32), put(t.data)
+            d.row_ptr, d.col_idx, d.vals = self.row_ptr.data_ptr(), self.col_idx.data_ptr(), self.vals.data_ptr()
+            d.col_ptr, d.row_idx, d.vals_t = self.col_ptr.data_ptr(), self.row_idx.data_ptr(), self.vals_t.data_ptr()
+            d.nnz = int(a.nnz)
         else:
             raise ValueError(spec.kind)
         self.desc = d

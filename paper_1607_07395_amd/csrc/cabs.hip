@@ -456,6 +456,13 @@ static cabs_status check_matrix(const cabs_matrix* mat) {
       if (mat->d <= 0) return fail(CABS_EINVAL, "dimension d must be positive");
       if (!(mat->sigma > 0.0)) return fail(CABS_EINVAL, "sigma must be positive");
       break;
+    case CABS_SRC_CSR:
+      if (!mat->row_ptr || !mat->col_ptr || (mat->nnz > 0 && (!mat->col_idx || !mat->vals || !mat->row_idx ||
+                                                               !mat->vals_t)))
+        return fail(CABS_EINVAL, "CSR source needs row_ptr, col_idx, vals, col_ptr, row_idx, vals_t");
+      if (mat->nnz < 0) return fail(CABS_EINVAL, "nnz must be >= 0");
+      if (mat->m >= INT32_MAX || mat->n >= INT32_MAX) return fail(CABS_EINVAL, "CSR source needs m, n < 2^31 - 1");
+      break;
     default:
       return fail(CABS_EINVAL, "unknown source kind %d", mat->kind);
   }
@@ -530,6 +537,13 @@ static MatView view_of(const cabs_matrix* mat) {
   v.y = mat->y;
   v.d = mat->d;
   v.sigma = mat->sigma;
+  v.row_ptr = mat->row_ptr;
+  v.col_idx = mat->col_idx;
+  v.vals = mat->vals;
+  v.col_ptr = mat->col_ptr;
+  v.row_idx = mat->row_idx;
+  v.vals_t = mat->vals_t;
+  v.nnz = mat->nnz;
   return v;
 }
 

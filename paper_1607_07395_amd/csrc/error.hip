@@ -54,6 +54,19 @@ __device__ __forceinline__ double entry_f64(const MatView& mv, int64_t i, int64_
   return s;
 }
 
+// Entry (i, j) of a CSR source: a binary search of row i's ascending columns.
+template <typename TIn>
+__device__ __forceinline__ double csr_entry(const MatView& mv, int64_t i, int64_t j) {
+  int64_t lo = mv.row_ptr[i], hi = mv.row_ptr[i + 1];  // search [lo, hi)
+  const int32_t jj = (int32_t)j;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (mv.col_idx[mid] < jj) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < mv.row_ptr[i + 1] && mv.col_idx[lo] == jj) ? (double)((const TIn*)mv.vals)[lo] : 0.0;
+}
+
 // Sample t: Philox-4x32-10 at counter (lo t, hi t, 4, 0), key (lo seed, hi
 // seed); i and j from the high words of 64x64 products of words 1:0 by m and
 // words 3:2 by n (uniform over the m x n entries, with replacement).
@@ -194,7 +207,7 @@ __device__ __forceinline__ void sample_dots(const MatView& mv, int kr, const dou
       const int e = u0 + 64 * v + 4 * l16;
       Run4<double, VEC>::get(cu, e, kr, a[v]);
       Run4<TC, VEC>::get(rt, e, kr, b[v]);
-      if constexpr (SRC != SRC_DENSE) {
+      if constexpr (SRC == SRC_LOWRANK || SRC == SRC_RBF) {
         if constexpr (sizeof(SV) == 4) {
           run4_f32<VEC>((const float*)xr, e, tabn, x[v]);
           run4_f32<VEC>((const float*)yr, e, tabn, y[v]);
@@ -240,6 +253,7 @@ __device__ __forceinline__ void err_batch(const MatView& mv, int kr, const doubl
   if (!valid) { i = 0; j = 0; }
   double nz = 0.0;
   if (SRC == SRC_LOWRANK && valid && mv.noise_std != 0.0) nz = noise_f64(mv.noise_seed, (uint64_t)i, (uint64_t)j);
+  if (SRC == SRC_CSR && valid) nz = csr_entry<TIn>(mv, i, j);  // the stored entry or 0, one search per lane
   rec[threadIdx.x] = ErrRec{i, j};
   wave_lds_sync();
   double my_ap = 0.0;
@@ -258,6 +272,7 @@ __device__ __forceinline__ void err_batch(const MatView& mv, int kr, const doubl
     double a = (double)my_s;
     if (SRC == SRC_LOWRANK) a += mv.noise_std * nz;
     else if (SRC == SRC_RBF) a = exp(-a / (2.0 * mv.sigma * mv.sigma));
+    else if (SRC == SRC_CSR) a = nz;
     num += (a - my_ap) * (a - my_ap);
     den += a * a;
   }
@@ -768,6 +783,74 @@ __global__ __launch_bounds__(256) void err_exact_kernel(MatView mv, int kr, cons
   }
 }
 
+// Exact error over every entry of a CSR source: the same 16-row x 128-column
+// tiles of C U R as err_exact_kernel, with the tile of A built per wave in LDS:
+// zero-filled, then lane r < 16 finds the first nonzero of row row0 + r at or
+// after the tile's first column (binary search) and writes the row's nonzeros
+// inside the tile.  Sums in the same fixed order as err_exact_kernel.
+template <typename TIn>
+__global__ __launch_bounds__(256) void err_exact_csr_kernel(MatView mv, int kr, const double* __restrict__ CU,
+                                                            const double* __restrict__ Rt,
+                                                            double* __restrict__ part) {
+  typedef double TC;
+  typedef typename Mfma<TC>::acc AccV;
+  typedef typename NormT<TC>::type NrmC;
+  constexpr int TW = ERR_NT * 16;
+  __shared__ double at[4][16 * TW];
+  __shared__ double rn[4], rd[4];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, c16 = lane & 15;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+  double* tile = at[wave];
+  double num = 0.0, den = 0.0;
+  if (row0 < mv.m) {
+    for (int64_t col0 = 0; col0 < mv.n; col0 += TW) {
+      AccV ap[ERR_NT];
+      NrmC xs, ys[ERR_NT];
+      gemm_tile<TC, TC, ERR_NT, false>(CU, kr, mv.m, row0, Rt, kr, nullptr, mv.n, col0, nullptr, kr, ap, xs, ys);
+      for (int e = lane; e < 16 * TW; e += 64) tile[e] = 0.0;
+      wave_lds_sync();
+      if (lane < 16 && row0 + lane < mv.m) {
+        const int64_t r = row0 + lane;
+        int64_t lo = mv.row_ptr[r], hi = mv.row_ptr[r + 1];
+        const int64_t end = hi;
+        while (lo < hi) {
+          const int64_t mid = (lo + hi) >> 1;
+          if (mv.col_idx[mid] < col0) lo = mid + 1;
+          else hi = mid;
+        }
+        for (int64_t p = lo; p < end && mv.col_idx[p] < col0 + TW; ++p)
+          tile[lane * TW + (mv.col_idx[p] - col0)] = (double)((const TIn*)mv.vals)[p];
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int rr = out_row<TC>(g, i);
+        const int64_t row = row0 + rr;
+#pragma unroll
+        for (int t = 0; t < ERR_NT; ++t) {
+          const int64_t col = col0 + t * 16 + c16;
+          if (row < mv.m && col < mv.n) {
+            const double a = tile[rr * TW + t * 16 + c16];
+            const double r = a - (double)ap[t][i];
+            num += r * r;
+            den += a * a;
+          }
+        }
+      }
+      wave_lds_sync();  // the tile is rewritten next
+    }
+  }
+  num = wave_sum(num);
+  den = wave_sum(den);
+  if (lane == 0) { rn[wave] = num; rd[wave] = den; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = ((rn[0] + rn[1]) + rn[2]) + rn[3];
+    part[2 * blockIdx.x + 1] = ((rd[0] + rd[1]) + rd[2]) + rd[3];
+  }
+}
+
 // Sum of the block partials in a fixed order: thread t takes blocks t, t + 256, ...,
 // then a fixed tree over the threads.
 __global__ __launch_bounds__(256) void err_final_kernel(int nb, const double* __restrict__ part,
@@ -843,6 +926,7 @@ static void with_src(int kind, bool vec, F&& f) {
   };
   if (kind == SRC_DENSE) go(std::integral_constant<int, SRC_DENSE>{});
   else if (kind == SRC_LOWRANK) go(std::integral_constant<int, SRC_LOWRANK>{});
+  else if (kind == SRC_CSR) go(std::integral_constant<int, SRC_CSR>{});
   else go(std::integral_constant<int, SRC_RBF>{});
 }
 
@@ -858,7 +942,7 @@ static hipError_t error_t(const MatView& mv, int kr, const double* CU, const TC*
   const void* t2 = mv.kind == SRC_LOWRANK ? mv.s : mv.x;
   // vector runs need whole runs (lengths a multiple of 4) and 16-byte aligned bases
   const bool vec = kr % 4 == 0 && al16(CU) && al16(Rt) &&
-                   (mv.kind == SRC_DENSE || (tabn % 4 == 0 && al16(t0) && al16(t1) && al16(t2)));
+                   (mv.kind == SRC_DENSE || mv.kind == SRC_CSR || (tabn % 4 == 0 && al16(t0) && al16(t1) && al16(t2)));
   int nb;
   if (ns > 0 && eb_use(mv.m, mv.n, ns)) {
     const EbPlan pl = eb_plan_for(mv, kr, ns);
@@ -895,6 +979,9 @@ static hipError_t error_t(const MatView& mv, int kr, const double* CU, const TC*
       hipLaunchKernelGGL((err_sampled_kernel<decltype(src)::value, TIn, TC, decltype(vc)::value>), dim3(nb), dim3(256),
                          0, st, mv, kr, CU, Rt, ns, seed, part);
     });
+  } else if (mv.kind == SRC_CSR) {
+    nb = (int)exact_nb(mv);
+    hipLaunchKernelGGL((err_exact_csr_kernel<TIn>), dim3(nb), dim3(256), 0, st, mv, kr, CU, Rt64, part);
   } else {
     nb = (int)exact_nb(mv);
     hipLaunchKernelGGL((err_exact_kernel<TIn>), dim3(nb), dim3(256), 0, st, mv, kr, CU, Rt64, part);

@@ -10,10 +10,14 @@
 // * dense gathers: C = A(:, J) row by row (coalesced output rows); R^T =
 //   A(I, :)^T through a 64 x 64 LDS tile so that both the row reads of A and
 //   the writes of R^T are coalesced.
+// * sparse gathers (CSR source): zero fill, then the sampled columns (rows) of
+//   the column-ordered (row-ordered) nonzeros scattered into place.
 #include "common.hpp"
 #include "gemm_core.hpp"
 #include "kernels.hpp"
 #include "timing.hpp"
+
+#include <algorithm>
 
 namespace cabs {
 
@@ -245,10 +249,68 @@ static hipError_t dense_dispatch(const MatView& mv, bool rows_t, const int64_t* 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Sparse gathers (CSR source).  C = A(:, J): the output (m x k) is zero-filled,
+// then work-group t scatters the nonzeros of column J_t (contiguous in the
+// column-ordered copy) to out[i k + t]; R^T = A(I, :)^T likewise from the
+// row-ordered copy.  Every output entry is written by the fill and at most one
+// scatter, so the result does not depend on scheduling.
+// ---------------------------------------------------------------------------
+template <typename TC>
+__global__ __launch_bounds__(256) void sparse_fill_kernel(int64_t total, TC* __restrict__ out,
+                                                          unsigned long long* counter) {
+  int wrote = 0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    out[e] = from_f64<TC>(0.0);
+    ++wrote;
+  }
+  count_entries(counter, wrote);
+}
+
+template <typename TIn, typename TC>
+__global__ __launch_bounds__(256) void sparse_scatter_kernel(const int64_t* __restrict__ ptr,
+                                                             const int32_t* __restrict__ ind,
+                                                             const TIn* __restrict__ val,
+                                                             const int64_t* __restrict__ idx, int k,
+                                                             TC* __restrict__ out) {
+  const int t = blockIdx.x;
+  const int64_t c = idx[t];
+  const int64_t p0 = ptr[c], p1 = ptr[c + 1];
+  for (int64_t p = p0 + threadIdx.x; p < p1; p += 256) out[(int64_t)ind[p] * k + t] = from_f64<TC>((double)val[p]);
+}
+
+template <typename TIn, typename TC>
+static hipError_t sparse_dispatch(const MatView& mv, bool rows_t, const int64_t* idx, int k, void* out,
+                                  hipStream_t st, unsigned long long* counter) {
+  const int64_t M = rows_t ? mv.n : mv.m;
+  const int64_t total = M * k;
+  const unsigned g = (unsigned)std::min<int64_t>(ceil_div(total, 256), 16384);
+  hipLaunchKernelGGL(sparse_fill_kernel<TC>, dim3(g > 0 ? g : 1), dim3(256), 0, st, total, (TC*)out, counter);
+  if (rows_t)
+    hipLaunchKernelGGL((sparse_scatter_kernel<TIn, TC>), dim3(k), dim3(256), 0, st, mv.row_ptr, mv.col_idx,
+                       (const TIn*)mv.vals, idx, k, (TC*)out);
+  else
+    hipLaunchKernelGGL((sparse_scatter_kernel<TIn, TC>), dim3(k), dim3(256), 0, st, mv.col_ptr, mv.row_idx,
+                       (const TIn*)mv.vals_t, idx, k, (TC*)out);
+  return hipGetLastError();
+}
+
 hipError_t launch_eval(const MatView& mv, bool rows_t, const int64_t* idx, int k, int compute, void* out,
                        hipStream_t st, unsigned long long* counter) {
   if (k <= 0) return hipErrorInvalidValue;
   TimerScope ts(T_EVAL, st);
+  if (mv.kind == SRC_CSR) {
+    if (mv.storage == P_F64) {
+      if (compute == P_F64) return sparse_dispatch<double, double>(mv, rows_t, idx, k, out, st, counter);
+      return hipErrorInvalidValue;
+    }
+    switch (compute) {
+      case P_F32: return sparse_dispatch<float, float>(mv, rows_t, idx, k, out, st, counter);
+      case P_BF16: return sparse_dispatch<float, bf16>(mv, rows_t, idx, k, out, st, counter);
+      case P_F16: return sparse_dispatch<float, f16>(mv, rows_t, idx, k, out, st, counter);
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (mv.kind == SRC_DENSE) {
     if (mv.storage == P_F64) {
       if (compute == P_F64) return dense_dispatch<double, double>(mv, rows_t, idx, k, out, st, counter);

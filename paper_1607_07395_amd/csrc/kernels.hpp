@@ -7,7 +7,7 @@
 namespace cabs {
 
 enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_F16 = 3 };
-enum Src { SRC_DENSE = 0, SRC_LOWRANK = 1, SRC_RBF = 2 };
+enum Src { SRC_DENSE = 0, SRC_LOWRANK = 1, SRC_RBF = 2, SRC_CSR = 3 };
 
 inline size_t prec_bytes(int p) { return p == P_F64 ? 8 : p == P_F32 ? 4 : 2; }
 
@@ -28,6 +28,13 @@ struct MatView {
   const void* y;
   int d;
   double sigma;
+  const int64_t* row_ptr;  // CSR: the nonzeros in row order and in column order
+  const int32_t* col_idx;
+  const void* vals;
+  const int64_t* col_ptr;
+  const int32_t* row_idx;
+  const void* vals_t;
+  int64_t nnz;
 };
 
 // --- sampling / entry evaluation (eval.hip) ---

@@ -1,5 +1,6 @@
-"""Weighted k-means and snapping in FP32 / BF16 / FP16 at the shapes the benchmark runs,
-step by step against the FP64 oracle (Section 3.2, Eq. (wkmeans); snapping to in-sample points).
+"""Weighted k-means and snapping in FP32 / BF16 / FP16 at the shapes the benchmark runs (and in
+FP64 on sparse embeddings, whose exact ties rounding decides), step by step against the FP64
+oracle (Section 3.2, Eq. (wkmeans); snapping to in-sample points).
 
 Each Lloyd iteration of the GPU path is checked against the oracle's definition of that
 iteration applied to the GPU's own state, so one near-tie decided differently cannot make
@@ -23,7 +24,8 @@ Rounding bound of one computed distance (FP32 accumulation, K = dim terms): the 
 rounded once for FP32 inputs) and |z|^2 rounded to FP32, so
     |error| <= 2 (K + 2) u |p| |z| + 2 u |z|^2,   u = 2^-24,
 using sum_t |p_t z_t| <= |p| |z|.  The snap pass adds |p|^2 and |z|^2 in FP64 and takes the
-dot product from the same FP32 accumulation, so the same bound holds there.
+dot product from the same FP32 accumulation, so the same bound holds there.  FP64 compute: the
+same bound with u = 2^-53, and the snap replay also admits the kernel's FP64 tie window.
 """
 import math
 
@@ -39,7 +41,12 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 U32 = 2.0 ** -24
-TORCH_DT = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
+TORCH_DT = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16, "f64": torch.float64}
+
+
+def _unit(dt):
+    """Unit roundoff of the distance accumulation: FP64 for FP64 compute, FP32 otherwise."""
+    return 2.0 ** -53 if dt == "f64" else U32
 
 
 @pytest.fixture(scope="module")
@@ -53,17 +60,17 @@ def _as_kernel(x, dt):
     return torch.from_numpy(np.ascontiguousarray(x)).to(TORCH_DT[dt]).double().numpy()
 
 
-def _dist_bound(pn, zn, K):
+def _dist_bound(pn, zn, K, u=U32):
     """Rounding bound of one computed squared distance (see the module docstring)."""
-    return 2.0 * (K + 2) * U32 * pn * zn + 2.0 * U32 * zn * zn
+    return 2.0 * (K + 2) * u * pn * zn + 2.0 * u * zn * zn
 
 
-def _check_assignment(P, Zk, labels, K):
+def _check_assignment(P, Zk, labels, K, u=U32):
     """GPU labels at centres Zk (already in the kernel's type) against the oracle's assignment."""
     lab_ref, dmin_ref, gap_ref = oc.assign(P, Zk)
     pn = np.linalg.norm(P, axis=1)
     zmax = float(np.linalg.norm(Zk, axis=1).max())
-    b = _dist_bound(pn, zmax, K)
+    b = _dist_bound(pn, zmax, K, u)
     sure = gap_ref > 2.0 * b
     bad = np.flatnonzero(sure & (labels != lab_ref))
     assert bad.size == 0, (bad[:10], labels[bad[:10]], lab_ref[bad[:10]], gap_ref[bad[:10]], b[bad[:10]])
@@ -73,8 +80,10 @@ def _check_assignment(P, Zk, labels, K):
     return d_chosen, b, int((~sure).sum())
 
 
-def _replay_snap(P, Zk, snap_gpu, K):
-    """The greedy snap of the GPU's centres, replayed with the GPU's set deciding the ties."""
+def _replay_snap(P, Zk, snap_gpu, K, u=U32):
+    """The greedy snap of the GPU's centres, replayed with the GPU's set deciding the ties.  In
+    FP64 the kernel also counts distances within SNAP_TIE_RTOL (|Z_j| + sqrt(d_min))^2 of the
+    nearest as tied (lowest row), so the replay's window includes that."""
     D = cdist(P, Zk, "sqeuclidean")
     pn = np.linalg.norm(P, axis=1)
     zn = np.linalg.norm(Zk, axis=1)
@@ -84,13 +93,17 @@ def _replay_snap(P, Zk, snap_gpu, K):
     for j in range(Zk.shape[0]):
         dj = np.where(taken, np.inf, D[:, j])
         dmin = float(dj.min())
-        b = 2.0 * _dist_bound(pn, zn[j], K)
+        b = 2.0 * _dist_bound(pn, zn[j], K, u)
+        if u < U32:
+            b = b + oc.SNAP_TIE_RTOL * (zn[j] + np.sqrt(max(dmin, 0.0))) ** 2
         cand = np.flatnonzero(dj <= dmin + b)
         inset = [int(l) for l in cand if int(l) in gset]
         assert inset, (j, dmin, cand[:10])
         if cand.size > 1:
             ambiguous += 1
-        pick = min(inset, key=lambda l: (dj[l], l))
+        # FP32 and 16-bit compare exactly (the nearest computed distance wins); FP64 takes the
+        # lowest row inside its tie window, as the oracle's snap does
+        pick = min(inset) if u < U32 else min(inset, key=lambda l: (dj[l], l))
         taken[pick] = True
     assert np.array_equal(np.flatnonzero(taken), np.asarray(snap_gpu)), "replay does not take the GPU's rows"
     return ambiguous
@@ -117,13 +130,13 @@ def _stepwise(api, P, w, z0, iters, dt, snap=True):
             tol = 2.0 * P.shape[0] * 1.2e-16 * np.abs(Pk).max()
             assert np.abs(Z - want).max() <= tol, (t, np.abs(Z - want).max(), tol)
         Zk = _as_kernel(Z, dt)
-        d_chosen, b, unsure = _check_assignment(Pk, Zk, lab, K)
+        d_chosen, b, unsure = _check_assignment(Pk, Zk, lab, K, _unit(dt))
         unsure_total += unsure
         # objective at Z_t (obj[1] after t iterations; obj[0] is the one at Z_0)
         want_obj = float(w @ d_chosen)
         assert abs(obj[1] - want_obj) <= float(w @ b) + 1e-12 * want_obj, (t, obj[1], want_obj)
         if t == iters and snap:
-            amb = _replay_snap(Pk, Zk, sn.cpu().numpy(), K)
+            amb = _replay_snap(Pk, Zk, sn.cpu().numpy(), K, _unit(dt))
         Zprev, labprev = Z, lab
     return unsure_total, (amb if snap else None)
 
@@ -196,3 +209,19 @@ def test_sketch_f64_lowrank_1e5_fullsize_matches_oracle(api, lowrank_embeddings)
     spec, ref = lowrank_embeddings
     kw = dict(k1_rows=200, k1_cols=200, k2_rows=200, k2_cols=200, kmeans_iters=5, seed=0)
     compare_f64(api, spec, kw, ref=ref)
+
+
+@pytest.mark.parametrize("kind,k,seed", [("movie", 40, 0), ("news", 32, 3)])
+def test_kmeans_f64_sparse_embeddings_stepwise(api, kind, k, seed):
+    """FP64 k-means and snap on the pilot embeddings of sparse stand-ins (movie-like 3000 x 4600
+    at 8 %, newsgroup-like 1877 x 6118 at 10 %).  Rows whose sampled columns are all zero embed
+    to exactly 0 and several pilot rows coincide, so the oracle meets exact distance ties that the
+    GPU's expansion |z|^2 - 2 p.z decides by rounding: each step is checked against the oracle's
+    definition with ties inside the FP64 rounding bound (and the snap's tie window) allowed."""
+    import workloads
+    spec = workloads.movie_like(3000, 4600, 0.08, seed=1) if kind == "movie" else \
+        workloads.newsgroup_like(1877, 6118, 0.1, seed=2)
+    ref = oc.cabs(spec, oc.Params.square(k, kmeans_iters=5, seed=seed))
+    for P, idx, w in ((ref.P, ref.pilot_rows, ref.w_r), (ref.Q, ref.pilot_cols, ref.w_c)):
+        unsure, amb = _stepwise(api, P, w, P[idx], 5, "f64")
+        print(f"{kind}: undecidable assignments {unsure}, ambiguous snaps {amb}, zero rows {int((P == 0).all(1).sum())}")
