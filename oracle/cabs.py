@@ -23,7 +23,7 @@ EPS = float(np.finfo(np.float64).eps)
 
 WEIGHT_KINDS = ("const", "pow", "sigmoid", "step")
 SKETCH_KINDS = ("stabilized", "pseudo_skeleton")
-FOLLOW_UPS = ("kmeans", "hard", "leverage")
+FOLLOW_UPS = ("kmeans", "hard", "leverage", "pilot")
 
 
 class RankError(RuntimeError):
@@ -46,7 +46,8 @@ class Params:
     pinv_rtol: float = 0.0           # <= 0: max(kr, kc) * eps * sigma_1
     seed: int = 0
     factors: bool = False            # also return the orthogonalised factor form of the result
-    follow_up: str = "kmeans"        # "hard" / "leverage": the hard-threshold / leverage variants of Section 5
+    follow_up: str = "kmeans"        # "hard" / "leverage": the hard-threshold / leverage variants of Section 5;
+                                     # "pilot": no follow-up round, the output is the pilot sketch (step 2)
 
     @classmethod
     def square(cls, k: int, **kw) -> "Params":
@@ -388,6 +389,8 @@ def validate(m: int, n: int, prm: Params) -> None:
         raise ValueError("unknown weight or sketch kind")
     if prm.follow_up not in FOLLOW_UPS:
         raise ValueError("unknown follow-up kind")
+    if prm.follow_up == "pilot" and (prm.k2_rows != prm.k1_rows or prm.k2_cols != prm.k1_cols):
+        raise ValueError("the pilot sketch alone needs k2 = k1 on both sides")
 
 
 def cabs(spec, prm: Params, track: bool = False) -> Result:
@@ -418,6 +421,12 @@ def cabs(spec, prm: Params, track: bool = False) -> Result:
 
     # Step 2: pilot sketching and embeddings.
     pilot = sketching(c, rt, w, m, n, prm.sketch_kind, prm.pinv_rtol)
+    if prm.follow_up == "pilot":
+        # the one-shot pilot sketch of Section 5's comparison: steps 3 and 4 are skipped
+        factors = orthogonalize(pilot.U, pilot.S, pilot.V) if prm.factors else None
+        return Result(pilot_rows=ir, pilot_cols=ic, idx_r=ir, idx_c=ic, C=c, Rt=rt, Umid=pilot.Umid,
+                      pilot=pilot, final=pilot, P=None, Q=None, w_r=None, w_c=None, km_r=None, km_c=None,
+                      entries_touched=touched, factors=factors, pilot_C=c, pilot_Rt=rt, pilot_sigma=None)
     if prm.orthogonalize:
         uo, so, vo = orthogonalize(pilot.U, pilot.S, pilot.V)
     else:

@@ -93,3 +93,12 @@ class Matrix:
         if self.mask is not None:
             self.mask[idx, :] = True
         return np.ascontiguousarray(self._block(idx, np.arange(self.n)).T)
+
+    def block(self, rows: np.ndarray, cols: np.ndarray) -> np.ndarray:
+        """A(rows, cols), len(rows) x len(cols): the target block of the resampling CUR."""
+        rows = np.asarray(rows, dtype=np.int64)
+        cols = np.asarray(cols, dtype=np.int64)
+        self.entries_read += rows.size * cols.size
+        if self.mask is not None:
+            self.mask[np.ix_(rows, cols)] = True
+        return self._block(rows, cols)

@@ -37,6 +37,8 @@ STREAM_INIT_COLS = 3
 STREAM_ERROR = 4
 STREAM_LEVERAGE_ROWS = 5
 STREAM_LEVERAGE_COLS = 6
+STREAM_TARGET_ROWS = 7   # target sampling of the bilateral resampling CUR (Algorithm 1)
+STREAM_TARGET_COLS = 8
 
 PHILOX32_M0 = np.uint64(0xD2511F53)
 PHILOX32_M1 = np.uint64(0xCD9E8D57)
