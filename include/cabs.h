@@ -80,8 +80,18 @@ typedef enum { CABS_W_CONST = 0, CABS_W_POW = 1, CABS_W_SIGMOID = 2, CABS_W_STEP
  * u_i in (0, 1] from word 0 of Philox-4x64-10 at counter (i, 0, 5, 0) for rows
  * and (i, 0, 6, 0) for columns, key (seed, 0), and the k2 largest keys are
  * taken, equal keys to the lower index.  HARD and LEVERAGE run no k-means and
- * leave the encoding-error diagnostics at 0; both need m, n < 2^31 - 1. */
-typedef enum { CABS_FOLLOW_KMEANS = 0, CABS_FOLLOW_HARD = 1, CABS_FOLLOW_LEVERAGE = 2 } cabs_follow_up;
+ * leave the encoding-error diagnostics at 0; both need m, n < 2^31 - 1.
+ * PILOT: no follow-up round; the output is the pilot sketch itself (step 2 of
+ * Algorithm 2, the "pilot-sketch" method of Section 5's comparison): idx_r,
+ * idx_c are the pilot sample, C, Rt, Umid its sketch; needs k2 = k1 on both
+ * sides; only the FINAL rank and sigma diagnostics (copied to the PILOT slots)
+ * are written. */
+typedef enum {
+  CABS_FOLLOW_KMEANS = 0,
+  CABS_FOLLOW_HARD = 1,
+  CABS_FOLLOW_LEVERAGE = 2,
+  CABS_FOLLOW_PILOT = 3
+} cabs_follow_up;
 
 /* The sketching routine: the stabilised form of Section 4.1 (default), or the
  * pseudo-skeleton A ~ C W^+ R of Eq. (W), Section 2.2. */
@@ -225,6 +235,59 @@ cabs_status cabs_error(const cabs_matrix* mat, const cabs_params* prm, const cab
                        int64_t n_samples, uint64_t seed, void* ws, size_t ws_bytes, double* out3,
                        void* stream);
 
+/* ---- Bilateral resampling CUR (Algorithm 1, Section 2.2) ----
+ *
+ * The family of linear-cost sketches that the paper compares CABS with: a base
+ * sample gives C = A(:, Ib_c) (m x kb_cols) and R^T = A(Ib_r, :)^T (n x kb_rows);
+ * a target sample selects Cbar = C(It_r, :) (kt_rows x kb_cols), Rbar =
+ * R(:, It_c) (kb_rows x kt_cols) and the block M = A(It_r, It_c); the middle
+ * factor is the minimum-norm minimiser of |M - Cbar U Rbar|_F,
+ *   Umid = Cbar^+ M Rbar^+   (kb_cols x kb_rows),  A ~ C Umid Rt^T.
+ * Each pseudo-inverse comes from an FP64 SVD (cabs_svd) and drops the singular
+ * values <= tol = (pinv_rtol > 0 ? pinv_rtol : max(rows, cols) eps) sigma_1,
+ * and, if rank_cap > 0, all but the rank_cap largest.
+ * tgt_r = tgt_c = NULL means the target sample IS the base sample: the
+ * pseudo-skeleton Eq. (W), Umid = W^+ with W = A(Ib_r, Ib_c) read out of C
+ * (one SVD, no block evaluation); with base_r = base_c on a square symmetric
+ * positive semi-definite A this is the Nystrom method.  Sketch-CUR is the
+ * general case with independently drawn samples (cabs_sample; the library's
+ * convention: base from streams 0 / 1, target from streams 7 / 8, with a
+ * target size three times the base size as in Section 5).
+ * The C, Rt and Umid outputs have the layout of cabs_result, so cabs_error
+ * takes them with k2_rows = kb_rows, k2_cols = kb_cols.
+ * Indices are device int64 arrays (any order, repeats allowed) that must lie in
+ * range: the call does not read them on the host.  Sizes: 1 <= kb <= 1024,
+ * 1 <= kt <= 4096, kb and kt at most the dimension they sample.
+ * diag (device, CABS_BRCUR_DIAG_LEN doubles, may be NULL): status (0 or
+ * CABS_ERANK when a pseudo-inverse keeps nothing; Umid is then zero), kept
+ * components and sigma_1 of Cbar and Rbar (of W twice when the samples
+ * coincide). */
+typedef struct {
+  int32_t kb_rows, kb_cols;  /* base sample sizes: rows of R, columns of C */
+  int32_t kt_rows, kt_cols;  /* target sample sizes (ignored when the target is the base) */
+  int32_t compute;           /* cabs_prec of C, Rt and the block M; the solve is FP64 */
+  int32_t rank_cap;          /* 0: every component above tol */
+  double pinv_rtol;          /* <= 0: max(rows, cols) eps */
+  int32_t flags;             /* must be 0 */
+  int32_t reserved;
+} cabs_brcur_params;
+
+enum {
+  CABS_BRCUR_DIAG_STATUS = 0,
+  CABS_BRCUR_DIAG_RANK_C = 1,
+  CABS_BRCUR_DIAG_RANK_R = 2,
+  CABS_BRCUR_DIAG_SIGMA1_C = 3,
+  CABS_BRCUR_DIAG_SIGMA1_R = 4,
+  CABS_BRCUR_DIAG_LEN = 8
+};
+
+/* Workspace bytes of cabs_brcur (same_sample: 1 when the target is the base);
+ * 0 on invalid arguments. */
+size_t cabs_brcur_workspace_bytes(const cabs_matrix* mat, const cabs_brcur_params* prm, int32_t same_sample);
+cabs_status cabs_brcur(const cabs_matrix* mat, const cabs_brcur_params* prm, const int64_t* base_r,
+                       const int64_t* base_c, const int64_t* tgt_r, const int64_t* tgt_c, void* ws, size_t ws_bytes,
+                       void* C, void* Rt, double* Umid, double* diag, void* stream);
+
 /* ---- Stage entry points (the same kernels cabs_sketch runs, one at a time) ---- */
 
 /* k distinct indices from [0, n), uniform, ascending (Floyd's algorithm on
@@ -242,7 +305,9 @@ cabs_status cabs_eval_rows_t(const cabs_matrix* mat, const int64_t* idx, int32_t
 /* Batched FP64 SVD by one-sided Jacobi: A_b (rows x cols, row-major) =
  * U_b diag(S_b) V_b^T with p = min(rows, cols), U_b rows x p, V_b cols x p,
  * S_b descending, the largest-magnitude entry of every column of U_b positive.
- * Used on W in the sketching routine (Section 4.1).  rows, cols <= 1024.
+ * Used on W in the sketching routine (Section 4.1) and on the target rows and
+ * columns of the resampling CUR (Algorithm 1).  min(rows, cols) <= 1024,
+ * max(rows, cols) <= 4096.
  * ws: cabs_svd_workspace_bytes() bytes. */
 size_t cabs_svd_workspace_bytes(int32_t batch, int32_t rows, int32_t cols);
 cabs_status cabs_svd(int32_t batch, int32_t rows, int32_t cols, const double* A, double* U, double* S, double* V,

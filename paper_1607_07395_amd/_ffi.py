@@ -19,6 +19,7 @@ F64, F32, BF16, F16 = 0, 1, 2, 3
 SRC_DENSE, SRC_LOWRANK, SRC_RBF, SRC_CSR = 0, 1, 2, 3
 W_CONST, W_POW, W_SIGMOID, W_STEP = 0, 1, 2, 3
 SK_STABILIZED, SK_PSEUDO_SKELETON = 0, 1
+FOLLOW_KMEANS, FOLLOW_HARD, FOLLOW_LEVERAGE, FOLLOW_PILOT = 0, 1, 2, 3
 FLAG_COUNT_ENTRIES = 1
 KMEANS_NOALLOC_SCRATCH_BYTES = 64 << 20
 
@@ -26,6 +27,8 @@ DIAG_STATUS, DIAG_ENC_R_PILOT, DIAG_ENC_C_PILOT, DIAG_ENC_R_FINAL, DIAG_ENC_C_FI
 DIAG_TMAX_R, DIAG_TMAX_C, DIAG_RANK_PILOT, DIAG_RANK_FINAL, DIAG_ENTRIES = 5, 6, 7, 8, 9
 DIAG_GAP_R, DIAG_GAP_C, DIAG_SIGMA1_PILOT, DIAG_SIGMA1_FINAL, DIAG_LEN = 10, 11, 12, 13, 16
 DIAG_SNAP_SCANS_R, DIAG_SNAP_SCANS_C = 14, 15
+BRCUR_DIAG_STATUS, BRCUR_DIAG_RANK_C, BRCUR_DIAG_RANK_R, BRCUR_DIAG_SIGMA1_C, BRCUR_DIAG_SIGMA1_R = 0, 1, 2, 3, 4
+BRCUR_DIAG_LEN = 8
 
 
 class CabsMatrix(C.Structure):
@@ -58,6 +61,14 @@ class CabsResult(C.Structure):
     ]
 
 
+class CabsBrCurParams(C.Structure):
+    _fields_ = [
+        ("kb_rows", C.c_int32), ("kb_cols", C.c_int32), ("kt_rows", C.c_int32), ("kt_cols", C.c_int32),
+        ("compute", C.c_int32), ("rank_cap", C.c_int32), ("pinv_rtol", C.c_double), ("flags", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
+
+
 _P = C.c_void_p
 _SIGS = {
     "cabs_version": (C.c_char_p, []),
@@ -67,6 +78,9 @@ _SIGS = {
     "cabs_error_workspace_bytes": (C.c_size_t, [C.POINTER(CabsMatrix), C.POINTER(CabsParams), C.c_int64]),
     "cabs_error": (C.c_int, [C.POINTER(CabsMatrix), C.POINTER(CabsParams), C.POINTER(CabsResult), C.c_int64,
                              C.c_uint64, _P, C.c_size_t, _P, _P]),
+    "cabs_brcur_workspace_bytes": (C.c_size_t, [C.POINTER(CabsMatrix), C.POINTER(CabsBrCurParams), C.c_int32]),
+    "cabs_brcur": (C.c_int, [C.POINTER(CabsMatrix), C.POINTER(CabsBrCurParams), _P, _P, _P, _P, _P, C.c_size_t,
+                             _P, _P, _P, _P, _P]),
     "cabs_sample": (C.c_int, [C.c_int64, C.c_int32, C.c_uint64, C.c_int32, _P, _P]),
     "cabs_eval_cols": (C.c_int, [C.POINTER(CabsMatrix), _P, C.c_int32, C.c_int32, _P, _P]),
     "cabs_eval_rows_t": (C.c_int, [C.POINTER(CabsMatrix), _P, C.c_int32, C.c_int32, _P, _P]),

@@ -19,6 +19,7 @@ PREC = {"f64": F.F64, "f32": F.F32, "bf16": F.BF16, "f16": F.F16}
 TORCH_DTYPE = {F.F64: torch.float64, F.F32: torch.float32, F.BF16: torch.bfloat16, F.F16: torch.float16}
 WEIGHT = {"const": F.W_CONST, "pow": F.W_POW, "sigmoid": F.W_SIGMOID, "step": F.W_STEP}
 SKETCH = {"stabilized": F.SK_STABILIZED, "pseudo_skeleton": F.SK_PSEUDO_SKELETON}
+FOLLOW = {"kmeans": F.FOLLOW_KMEANS, "hard": F.FOLLOW_HARD, "leverage": F.FOLLOW_LEVERAGE, "pilot": F.FOLLOW_PILOT}
 SOURCE = {"dense": F.SRC_DENSE, "lowrank": F.SRC_LOWRANK, "rbf": F.SRC_RBF, "csr": F.SRC_CSR}
 
 
@@ -110,7 +111,7 @@ def make_params(k1_rows, k1_cols, k2_rows, k2_cols, kmeans_iters=5, weight="cons
     p.pinv_rtol = pinv_rtol
     p.compute = PREC[compute]
     p.want_factors = 1 if factors else 0
-    p.follow_up = {"kmeans": 0, "hard": 1, "leverage": 2}[follow_up]
+    p.follow_up = FOLLOW[follow_up]
     p.flags = F.FLAG_COUNT_ENTRIES if count_entries else 0
     p.seed = seed
     return p
@@ -213,6 +214,94 @@ def error(mat: DeviceMatrix, prm: F.CabsParams, res: SketchResult, n_samples: in
     F.check(st, "cabs_error")
     out3._ws = ws
     return out3
+
+
+# ---------------------------------------------------------------------------
+# Bilateral resampling CUR (cabs_brcur) and its special cases
+# ---------------------------------------------------------------------------
+STREAM_PILOT_ROWS, STREAM_PILOT_COLS, STREAM_TARGET_ROWS, STREAM_TARGET_COLS = 0, 1, 7, 8
+
+
+@dataclasses.dataclass
+class BrCurResult:
+    base_r: torch.Tensor
+    base_c: torch.Tensor
+    tgt_r: Optional[torch.Tensor]
+    tgt_c: Optional[torch.Tensor]
+    C: torch.Tensor
+    Rt: torch.Tensor
+    Umid: torch.Tensor
+    diag: torch.Tensor
+    params: F.CabsParams          # sizes and precision for cabs_error (k2 = the base sizes)
+    struct: F.CabsResult          # C, Rt, Umid for cabs_error
+
+    def diagnostics(self) -> dict:
+        d = self.diag.cpu().numpy()
+        return {"status": int(d[F.BRCUR_DIAG_STATUS]), "rank_c": int(d[F.BRCUR_DIAG_RANK_C]),
+                "rank_r": int(d[F.BRCUR_DIAG_RANK_R]), "sigma1_c": d[F.BRCUR_DIAG_SIGMA1_C],
+                "sigma1_r": d[F.BRCUR_DIAG_SIGMA1_R]}
+
+
+def brcur(mat: DeviceMatrix, base_r: torch.Tensor, base_c: torch.Tensor, tgt_r: Optional[torch.Tensor] = None,
+          tgt_c: Optional[torch.Tensor] = None, compute: str = "f32", pinv_rtol: float = 0.0, rank_cap: int = 0,
+          ws: Optional[torch.Tensor] = None, stream=None) -> BrCurResult:
+    """cabs_brcur: Algorithm 1 on device index tensors (no target: the target sample is the base sample)."""
+    prm = F.CabsBrCurParams()
+    prm.kb_rows, prm.kb_cols = base_r.numel(), base_c.numel()
+    same = tgt_r is None
+    prm.kt_rows = prm.kb_rows if same else tgt_r.numel()
+    prm.kt_cols = prm.kb_cols if same else tgt_c.numel()
+    prm.compute = PREC[compute]
+    prm.rank_cap = rank_cap
+    prm.pinv_rtol = pinv_rtol
+    need = int(F.lib().cabs_brcur_workspace_bytes(C.byref(mat.desc), C.byref(prm), 1 if same else 0))
+    if need == 0:
+        raise F.CabsError(F.EINVAL, "cabs_brcur_workspace_bytes: " + F.lib().cabs_last_error().decode())
+    if ws is None or ws.numel() < need:
+        ws = _dev_alloc(need, mat.device)
+    dt = TORCH_DTYPE[prm.compute]
+    dev = mat.device
+    c = torch.empty(mat.m, prm.kb_cols, dtype=dt, device=dev)
+    rt = torch.empty(mat.n, prm.kb_rows, dtype=dt, device=dev)
+    umid = torch.empty(prm.kb_cols, prm.kb_rows, dtype=torch.float64, device=dev)
+    diag = torch.empty(F.BRCUR_DIAG_LEN, dtype=torch.float64, device=dev)
+    st = F.lib().cabs_brcur(C.byref(mat.desc), C.byref(prm), _ptr(base_r), _ptr(base_c), _ptr(tgt_r), _ptr(tgt_c),
+                            _ptr(ws), ws.numel(), _ptr(c), _ptr(rt), _ptr(umid), _ptr(diag), _stream(stream))
+    F.check(st, "cabs_brcur")
+    eprm = make_params(prm.kb_rows, prm.kb_cols, prm.kb_rows, prm.kb_cols, compute=compute)
+    s = F.CabsResult()
+    s.C, s.Rt, s.Umid = c.data_ptr(), rt.data_ptr(), umid.data_ptr()
+    res = BrCurResult(base_r, base_c, tgt_r, tgt_c, c, rt, umid, diag, eprm, s)
+    res._ws = ws
+    return res
+
+
+def sketch_cur(mat: DeviceMatrix, k_rows: int, k_cols: int, seed: int, ratio: int = 3, compute: str = "f32",
+               pinv_rtol: float = 0.0, rank_cap: int = 0, stream=None) -> BrCurResult:
+    """Sketch-CUR: uniform base sample (streams 0 / 1) and an independent target sample ratio times as
+    large (streams 7 / 8), both by cabs_sample."""
+    br = sample(mat.m, k_rows, seed, STREAM_PILOT_ROWS, mat.device, stream)
+    bc = sample(mat.n, k_cols, seed, STREAM_PILOT_COLS, mat.device, stream)
+    tr = sample(mat.m, min(mat.m, ratio * k_rows), seed, STREAM_TARGET_ROWS, mat.device, stream)
+    tc = sample(mat.n, min(mat.n, ratio * k_cols), seed, STREAM_TARGET_COLS, mat.device, stream)
+    return brcur(mat, br, bc, tr, tc, compute, pinv_rtol, rank_cap, stream=stream)
+
+
+def pseudo_skeleton(mat: DeviceMatrix, k_rows: int, k_cols: int, seed: int, compute: str = "f32",
+                    pinv_rtol: float = 0.0, rank_cap: int = 0, stream=None) -> BrCurResult:
+    """Eq. (W) on the uniform base sample: A ~ C W^+ R."""
+    br = sample(mat.m, k_rows, seed, STREAM_PILOT_ROWS, mat.device, stream)
+    bc = sample(mat.n, k_cols, seed, STREAM_PILOT_COLS, mat.device, stream)
+    return brcur(mat, br, bc, None, None, compute, pinv_rtol, rank_cap, stream=stream)
+
+
+def nystrom(mat: DeviceMatrix, k: int, seed: int, compute: str = "f32", pinv_rtol: float = 0.0, rank_cap: int = 0,
+            stream=None) -> BrCurResult:
+    """Nystrom: one uniform sample (stream 1) for the rows and columns of a square matrix."""
+    if mat.m != mat.n:
+        raise ValueError("the Nystrom method needs a square matrix")
+    i = sample(mat.n, k, seed, STREAM_PILOT_COLS, mat.device, stream)
+    return brcur(mat, i, i, None, None, compute, pinv_rtol, rank_cap, stream=stream)
 
 
 def sample(n: int, k: int, seed: int, stream_id: int, device="cuda", stream=None) -> torch.Tensor:

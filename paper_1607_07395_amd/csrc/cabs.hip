@@ -395,6 +395,14 @@ static size_t plan_sketch(void* ws, const Plan& pl, const cabs_params* prm, Sket
   Carve cv(ws);
   const size_t eb = prec_bytes(pl.prec);
   const int e = pl.p1, ep = pl.ep;
+  if (prm->follow_up == CABS_FOLLOW_PILOT) {  // one round: the output buffers hold the pilot sample and sketch
+    S = SketchWs{};
+    S.diag = cv.take<double>(CABS_DIAG_LEN);
+    S.entries = cv.take<unsigned long long>(1);
+    plan_round(cv, S.r2, pl, pl.kr2, pl.kc2, prm->want_factors != 0, prm->want_factors != 0);
+    S.sgn_ws = prm->want_factors ? cv.take<double>((size_t)3 * 256 * pl.p2) : nullptr;
+    return cv.off + 256;
+  }
   S.Ir = cv.take<int64_t>(pl.kr1);
   S.Ic = cv.take<int64_t>(pl.kc1);
   S.Ir0 = cv.take<int64_t>(std::max(pl.kr2, 1));
@@ -494,10 +502,13 @@ static cabs_status check_params(const cabs_matrix* mat, const cabs_params* prm) 
   if (prm->sketch_kind != CABS_SK_STABILIZED && prm->sketch_kind != CABS_SK_PSEUDO_SKELETON)
     return fail(CABS_EINVAL, "unknown sketch kind");
   if (prm->follow_up != CABS_FOLLOW_KMEANS && prm->follow_up != CABS_FOLLOW_HARD &&
-      prm->follow_up != CABS_FOLLOW_LEVERAGE)
+      prm->follow_up != CABS_FOLLOW_LEVERAGE && prm->follow_up != CABS_FOLLOW_PILOT)
     return fail(CABS_EINVAL, "unknown follow-up kind");
+  if (prm->follow_up == CABS_FOLLOW_PILOT && (prm->k2_rows != prm->k1_rows || prm->k2_cols != prm->k1_cols))
+    return fail(CABS_EINVAL, "the pilot sketch alone needs k2 = k1 on both sides");
   if (prm->flags & ~CABS_FLAG_COUNT_ENTRIES) return fail(CABS_EINVAL, "unknown flag bits");
-  if (prm->follow_up != CABS_FOLLOW_KMEANS && (mat->m >= INT32_MAX || mat->n >= INT32_MAX))
+  if ((prm->follow_up == CABS_FOLLOW_HARD || prm->follow_up == CABS_FOLLOW_LEVERAGE) &&
+      (mat->m >= INT32_MAX || mat->n >= INT32_MAX))
     return fail(CABS_EINVAL, "the hard-threshold and leverage selections need m, n < 2^31 - 1");
   return CABS_OK;
 }
@@ -645,84 +656,94 @@ extern "C" cabs_status cabs_sketch(const cabs_matrix* mat, const cabs_params* pr
   hipLaunchKernelGGL(diag_init_kernel, dim3(1), dim3(64), 0, st, diag, S.entries, counted ? 1 : 0);
   HIP_TRY(hipGetLastError());
 
-  // 1-2: pilot sampling and evaluation
-  int64_t* Ir = out->pilot_r ? out->pilot_r : S.Ir;
-  int64_t* Ic = out->pilot_c ? out->pilot_c : S.Ic;
-  HIP_TRY(launch_sample(pl.m, pl.kr1, prm->seed, STREAM_PILOT_ROWS, Ir, st));
-  HIP_TRY(launch_sample(pl.n, pl.kc1, prm->seed, STREAM_PILOT_COLS, Ic, st));
-  HIP_TRY(launch_eval(mv, false, Ic, pl.kc1, pl.prec, S.C, st, ecnt));
-  HIP_TRY(launch_eval(mv, true, Ir, pl.kr1, pl.prec, S.Rt, st, ecnt));
-  HIP_TRY(launch_gather_rows_f64(S.C, pl.prec, pl.kc1, Ir, pl.kr1, pl.kc1, S.r1.W, st));
-
-  // 3-5: pilot sketch and embedding maps
-  s = run_round(pl, S.r1, pl.kr1, pl.kc1, S.C, S.Rt, prm, true, prm->orthogonalize != 0, diag, CABS_DIAG_RANK_PILOT,
-                CABS_DIAG_SIGMA1_PILOT, st);
-  if (s != CABS_OK) return s;
-
-  // 6: embeddings and weights
-  // When p1 elements are not a whole number of 16-byte runs (FP32: p1 not a multiple of 4, 16-bit:
-  // of 8) the embeddings get ep - p1 zero columns, so that their rows are whole runs for the k-means
-  // kernels; zero columns add exact zeros to every distance, norm and centre.
-  const double* Mu = S.r1.Mu;
-  const double* Mv = S.r1.Mv;
-  void* ts6 = S.r1.ts_ws;
-  if (ep != e) {
-    const unsigned gp = (unsigned)ceil_div((int64_t)e * ep, 256);
-    hipLaunchKernelGGL(pad_cols_kernel, dim3(gp), dim3(256), 0, st, e, e, ep, S.r1.Mu, S.MuP);
-    hipLaunchKernelGGL(pad_cols_kernel, dim3(gp), dim3(256), 0, st, e, e, ep, S.r1.Mv, S.MvP);
-    Mu = S.MuP;
-    Mv = S.MvP;
-    ts6 = S.ts6;
-  }
-  HIP_TRY(launch_tsgemm(pl.m, e, ep, pl.prec, S.r1.Ch, Mu, S.P, nullptr, S.rowsqP, ts6, st));
-  HIP_TRY(launch_tsgemm(pl.n, e, ep, pl.prec, S.r1.Rh, Mv, S.Q, nullptr, S.rowsqQ, ts6, st));
-  hipLaunchKernelGGL(weights_kernel, dim3((unsigned)ceil_div(pl.m, 256)), dim3(256), 0, st, pl.m, S.rowsqP,
-                     prm->weight_kind, prm->weight_param, S.wr);
-  hipLaunchKernelGGL(weights_kernel, dim3((unsigned)ceil_div(pl.n, 256)), dim3(256), 0, st, pl.n, S.rowsqQ,
-                     prm->weight_kind, prm->weight_param, S.wc);
-  HIP_TRY(hipGetLastError());
-
-  // 7: follow-up sampling.  Hard-threshold variant (Section 5): the rows and
-  // columns with the largest weights.
-  if (prm->follow_up == CABS_FOLLOW_HARD) {
-    HIP_TRY(launch_select_topk(pl.m, S.wr, pl.kr2, out->idx_r, S.selr, st));
-    HIP_TRY(launch_select_topk(pl.n, S.wc, pl.kc2, out->idx_c, S.selc, st));
-  } else if (prm->follow_up == CABS_FOLLOW_LEVERAGE) {
-    // Leverage variant (Section 5): keys from the squared row norms of the factors behind P and Q
-    // (P = U' diag(s)^(1/2), s = the orthogonalised singular values, or the sketch's S without
-    // orthogonalisation), then the k largest keys.  The weights buffers hold the keys.
-    const double* sv = prm->orthogonalize ? S.r1.S1 : S.r1.sk;
-    hipLaunchKernelGGL(lev_inv_kernel, dim3(1), dim3(256), 0, st, e, sv, S.levinv);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(launch_lev_keys_any(pl.prec, pl.m, ep, e, S.P, S.levinv, prm->seed, STREAM_LEVERAGE_ROWS, S.wr, st));
-    HIP_TRY(launch_lev_keys_any(pl.prec, pl.n, ep, e, S.Q, S.levinv, prm->seed, STREAM_LEVERAGE_COLS, S.wc, st));
-    HIP_TRY(launch_select_topk(pl.m, S.wr, pl.kr2, out->idx_r, S.selr, st));
-    HIP_TRY(launch_select_topk(pl.n, S.wc, pl.kc2, out->idx_c, S.selc, st));
+  if (prm->follow_up == CABS_FOLLOW_PILOT) {
+    // The pilot sketch alone: the pilot sample is the output sample, and step 8
+    // below is the pilot round (steps 1-3 of Algorithm 2).
+    HIP_TRY(launch_sample(pl.m, pl.kr1, prm->seed, STREAM_PILOT_ROWS, out->idx_r, st));
+    HIP_TRY(launch_sample(pl.n, pl.kc1, prm->seed, STREAM_PILOT_COLS, out->idx_c, st));
+    if (out->pilot_r) HIP_TRY(launch_sample(pl.m, pl.kr1, prm->seed, STREAM_PILOT_ROWS, out->pilot_r, st));
+    if (out->pilot_c) HIP_TRY(launch_sample(pl.n, pl.kc1, prm->seed, STREAM_PILOT_COLS, out->pilot_c, st));
   } else {
-    // Weighted k-means from the pilot sample, then snapping.
-    const int64_t* I0r = Ir;
-    const int64_t* I0c = Ic;
-    if (pl.kr2 > pl.kr1) {
-      HIP_TRY(launch_sample(pl.m, pl.kr2, prm->seed, STREAM_INIT_ROWS, S.Ir0, st));
-      I0r = S.Ir0;
+    // 1-2: pilot sampling and evaluation
+    int64_t* Ir = out->pilot_r ? out->pilot_r : S.Ir;
+    int64_t* Ic = out->pilot_c ? out->pilot_c : S.Ic;
+    HIP_TRY(launch_sample(pl.m, pl.kr1, prm->seed, STREAM_PILOT_ROWS, Ir, st));
+    HIP_TRY(launch_sample(pl.n, pl.kc1, prm->seed, STREAM_PILOT_COLS, Ic, st));
+    HIP_TRY(launch_eval(mv, false, Ic, pl.kc1, pl.prec, S.C, st, ecnt));
+    HIP_TRY(launch_eval(mv, true, Ir, pl.kr1, pl.prec, S.Rt, st, ecnt));
+    HIP_TRY(launch_gather_rows_f64(S.C, pl.prec, pl.kc1, Ir, pl.kr1, pl.kc1, S.r1.W, st));
+
+    // 3-5: pilot sketch and embedding maps
+    s = run_round(pl, S.r1, pl.kr1, pl.kc1, S.C, S.Rt, prm, true, prm->orthogonalize != 0, diag, CABS_DIAG_RANK_PILOT,
+                  CABS_DIAG_SIGMA1_PILOT, st);
+    if (s != CABS_OK) return s;
+
+    // 6: embeddings and weights
+    // When p1 elements are not a whole number of 16-byte runs (FP32: p1 not a multiple of 4, 16-bit:
+    // of 8) the embeddings get ep - p1 zero columns, so that their rows are whole runs for the k-means
+    // kernels; zero columns add exact zeros to every distance, norm and centre.
+    const double* Mu = S.r1.Mu;
+    const double* Mv = S.r1.Mv;
+    void* ts6 = S.r1.ts_ws;
+    if (ep != e) {
+      const unsigned gp = (unsigned)ceil_div((int64_t)e * ep, 256);
+      hipLaunchKernelGGL(pad_cols_kernel, dim3(gp), dim3(256), 0, st, e, e, ep, S.r1.Mu, S.MuP);
+      hipLaunchKernelGGL(pad_cols_kernel, dim3(gp), dim3(256), 0, st, e, e, ep, S.r1.Mv, S.MvP);
+      Mu = S.MuP;
+      Mv = S.MvP;
+      ts6 = S.ts6;
     }
-    if (pl.kc2 > pl.kc1) {
-      HIP_TRY(launch_sample(pl.n, pl.kc2, prm->seed, STREAM_INIT_COLS, S.Ic0, st));
-      I0c = S.Ic0;
-    }
-    HIP_TRY(launch_gather_rows_f64(S.P, pl.prec, ep, I0r, pl.kr2, ep, S.Z0r, st));
-    HIP_TRY(launch_gather_rows_f64(S.Q, pl.prec, ep, I0c, pl.kc2, ep, S.Z0c, st));
-    KMeansOut kr{S.Zr, nullptr, S.obj, diag + CABS_DIAG_TMAX_R, diag + CABS_DIAG_GAP_R, out->idx_r,
-                 diag + CABS_DIAG_SNAP_SCANS_R};
-    HIP_TRY(launch_kmeans(pl.m, ep, pl.kr2, pl.prec, S.P, S.wr, S.Z0r, prm->kmeans_iters, kr, S.kmr, st));
-    KMeansOut kc{S.Zc, nullptr, S.obj + 2, diag + CABS_DIAG_TMAX_C, diag + CABS_DIAG_GAP_C, out->idx_c,
-                 diag + CABS_DIAG_SNAP_SCANS_C};
-    HIP_TRY(launch_kmeans(pl.n, ep, pl.kc2, pl.prec, S.Q, S.wc, S.Z0c, prm->kmeans_iters, kc, S.kmc, st));
-    hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 0, diag + CABS_DIAG_ENC_R_PILOT);
-    hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 1, diag + CABS_DIAG_ENC_R_FINAL);
-    hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 2, diag + CABS_DIAG_ENC_C_PILOT);
-    hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 3, diag + CABS_DIAG_ENC_C_FINAL);
+    HIP_TRY(launch_tsgemm(pl.m, e, ep, pl.prec, S.r1.Ch, Mu, S.P, nullptr, S.rowsqP, ts6, st));
+    HIP_TRY(launch_tsgemm(pl.n, e, ep, pl.prec, S.r1.Rh, Mv, S.Q, nullptr, S.rowsqQ, ts6, st));
+    hipLaunchKernelGGL(weights_kernel, dim3((unsigned)ceil_div(pl.m, 256)), dim3(256), 0, st, pl.m, S.rowsqP,
+                       prm->weight_kind, prm->weight_param, S.wr);
+    hipLaunchKernelGGL(weights_kernel, dim3((unsigned)ceil_div(pl.n, 256)), dim3(256), 0, st, pl.n, S.rowsqQ,
+                       prm->weight_kind, prm->weight_param, S.wc);
     HIP_TRY(hipGetLastError());
+
+    // 7: follow-up sampling.  Hard-threshold variant (Section 5): the rows and
+    // columns with the largest weights.
+    if (prm->follow_up == CABS_FOLLOW_HARD) {
+      HIP_TRY(launch_select_topk(pl.m, S.wr, pl.kr2, out->idx_r, S.selr, st));
+      HIP_TRY(launch_select_topk(pl.n, S.wc, pl.kc2, out->idx_c, S.selc, st));
+    } else if (prm->follow_up == CABS_FOLLOW_LEVERAGE) {
+      // Leverage variant (Section 5): keys from the squared row norms of the factors behind P and Q
+      // (P = U' diag(s)^(1/2), s = the orthogonalised singular values, or the sketch's S without
+      // orthogonalisation), then the k largest keys.  The weights buffers hold the keys.
+      const double* sv = prm->orthogonalize ? S.r1.S1 : S.r1.sk;
+      hipLaunchKernelGGL(lev_inv_kernel, dim3(1), dim3(256), 0, st, e, sv, S.levinv);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(launch_lev_keys_any(pl.prec, pl.m, ep, e, S.P, S.levinv, prm->seed, STREAM_LEVERAGE_ROWS, S.wr, st));
+      HIP_TRY(launch_lev_keys_any(pl.prec, pl.n, ep, e, S.Q, S.levinv, prm->seed, STREAM_LEVERAGE_COLS, S.wc, st));
+      HIP_TRY(launch_select_topk(pl.m, S.wr, pl.kr2, out->idx_r, S.selr, st));
+      HIP_TRY(launch_select_topk(pl.n, S.wc, pl.kc2, out->idx_c, S.selc, st));
+    } else {
+      // Weighted k-means from the pilot sample, then snapping.
+      const int64_t* I0r = Ir;
+      const int64_t* I0c = Ic;
+      if (pl.kr2 > pl.kr1) {
+        HIP_TRY(launch_sample(pl.m, pl.kr2, prm->seed, STREAM_INIT_ROWS, S.Ir0, st));
+        I0r = S.Ir0;
+      }
+      if (pl.kc2 > pl.kc1) {
+        HIP_TRY(launch_sample(pl.n, pl.kc2, prm->seed, STREAM_INIT_COLS, S.Ic0, st));
+        I0c = S.Ic0;
+      }
+      HIP_TRY(launch_gather_rows_f64(S.P, pl.prec, ep, I0r, pl.kr2, ep, S.Z0r, st));
+      HIP_TRY(launch_gather_rows_f64(S.Q, pl.prec, ep, I0c, pl.kc2, ep, S.Z0c, st));
+      KMeansOut kr{S.Zr, nullptr, S.obj, diag + CABS_DIAG_TMAX_R, diag + CABS_DIAG_GAP_R, out->idx_r,
+                   diag + CABS_DIAG_SNAP_SCANS_R};
+      HIP_TRY(launch_kmeans(pl.m, ep, pl.kr2, pl.prec, S.P, S.wr, S.Z0r, prm->kmeans_iters, kr, S.kmr, st));
+      KMeansOut kc{S.Zc, nullptr, S.obj + 2, diag + CABS_DIAG_TMAX_C, diag + CABS_DIAG_GAP_C, out->idx_c,
+                   diag + CABS_DIAG_SNAP_SCANS_C};
+      HIP_TRY(launch_kmeans(pl.n, ep, pl.kc2, pl.prec, S.Q, S.wc, S.Z0c, prm->kmeans_iters, kc, S.kmc, st));
+      hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 0, diag + CABS_DIAG_ENC_R_PILOT);
+      hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 1, diag + CABS_DIAG_ENC_R_FINAL);
+      hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 2, diag + CABS_DIAG_ENC_C_PILOT);
+      hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 3, diag + CABS_DIAG_ENC_C_FINAL);
+      HIP_TRY(hipGetLastError());
+    }
+
   }
 
   // 8: follow-up evaluation and sketch
@@ -737,6 +758,12 @@ extern "C" cabs_status cabs_sketch(const cabs_matrix* mat, const cabs_params* pr
   // Umid = V_w diag(D) U_w^T  (kc2 x kr2)
   HIP_TRY(launch_small_gemm(pl.kc2, pl.kr2, pl.p2, S.r2.Vw, pl.p2, false, S.r2.Uw, pl.p2, true, nullptr, S.r2.dk,
                             nullptr, out->Umid, pl.kr2, st));
+  if (prm->follow_up == CABS_FOLLOW_PILOT) {
+    hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, diag + CABS_DIAG_RANK_FINAL, diag + CABS_DIAG_RANK_PILOT);
+    hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, diag + CABS_DIAG_SIGMA1_FINAL,
+                       diag + CABS_DIAG_SIGMA1_PILOT);
+    HIP_TRY(hipGetLastError());
+  }
 
   // 9: optional factor form: Uf = U' (orthonormal), S = S_1, Vf = V', mapped from C^ and R^.
   if (fac) {
@@ -814,6 +841,185 @@ extern "C" cabs_status cabs_error(const cabs_matrix* mat, const cabs_params* prm
 }
 
 // ---------------------------------------------------------------------------
+// Bilateral resampling CUR (Algorithm 1): Umid = Cbar^+ M Rbar^+, or W^+ when
+// the target sample is the base sample (Eq. W).
+// ---------------------------------------------------------------------------
+namespace {
+
+__global__ void brcur_diag_init_kernel(double* __restrict__ diag) {
+  if (threadIdx.x < CABS_BRCUR_DIAG_LEN) diag[threadIdx.x] = 0.0;
+}
+
+// Reciprocals of the kept singular values (descending S of a rows x cols
+// matrix): sigma_i > tol and i < cap (cap > 0); 0 for the dropped ones.
+__global__ void pinv_scale_kernel(int p, int rows, int cols, const double* __restrict__ S, double rtol, int cap,
+                                  double* __restrict__ inv, double* __restrict__ diag, int slot_rank, int slot_sig,
+                                  int slot_rank2, int slot_sig2) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  const double eps = 2.220446049250313e-16;
+  const double s1 = S[0];
+  const double tol = (rtol > 0.0 ? rtol : (double)(rows > cols ? rows : cols) * eps) * s1;
+  for (int i = threadIdx.x; i < p; i += blockDim.x) {
+    const bool keep = s1 > 0.0 && S[i] > tol && (cap <= 0 || i < cap);
+    inv[i] = keep ? 1.0 / S[i] : 0.0;
+    if (keep) atomicAdd(&cnt, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    diag[slot_rank] = (double)cnt;
+    diag[slot_sig] = s1;
+    if (slot_rank2 >= 0) diag[slot_rank2] = (double)cnt;
+    if (slot_sig2 >= 0) diag[slot_sig2] = s1;
+    if (cnt == 0) diag[CABS_BRCUR_DIAG_STATUS] = (double)CABS_ERANK;
+  }
+}
+
+template <typename TC>
+__global__ __launch_bounds__(256) void widen_f64_kernel(int64_t n, const TC* __restrict__ in, double* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) out[e] = to_f64(in[e]);
+}
+
+static hipError_t launch_widen_f64(int prec, int64_t n, const void* in, double* out, hipStream_t st) {
+  const dim3 g((unsigned)std::min<int64_t>(ceil_div(n, 256), 4096)), b(256);
+  switch (prec) {
+    case P_F32: hipLaunchKernelGGL(widen_f64_kernel<float>, g, b, 0, st, n, (const float*)in, out); break;
+    case P_BF16: hipLaunchKernelGGL(widen_f64_kernel<bf16>, g, b, 0, st, n, (const bf16*)in, out); break;
+    case P_F16: hipLaunchKernelGGL(widen_f64_kernel<f16>, g, b, 0, st, n, (const f16*)in, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+struct BrWs {
+  double *Cb, *U1, *S1, *V1, *inv1;            // Cbar (W when the samples coincide) and its SVD
+  double *Rb, *U2, *S2, *V2, *inv2;            // Rbar^T and its SVD
+  double *M64, *T1, *T2, *T3, *diag;
+  void *Mtc, *blk_ws, *svd_ws;
+};
+
+static size_t plan_brcur(void* ws, const MatView& mv, const cabs_brcur_params* prm, bool same, BrWs& B) {
+  Carve cv(ws);
+  B = BrWs{};
+  const int kbr = prm->kb_rows, kbc = prm->kb_cols;
+  const int ktr = same ? kbr : prm->kt_rows, ktc = same ? kbc : prm->kt_cols;
+  const int p1 = std::min(ktr, kbc), p2 = std::min(ktc, kbr);
+  B.Cb = cv.take<double>((size_t)ktr * kbc);
+  B.U1 = cv.take<double>((size_t)ktr * p1);
+  B.S1 = cv.take<double>(p1);
+  B.V1 = cv.take<double>((size_t)kbc * p1);
+  B.inv1 = cv.take<double>(p1);
+  B.diag = cv.take<double>(CABS_BRCUR_DIAG_LEN);
+  size_t svd_b = svd_ws_bytes(1, ktr, kbc);
+  if (!same) {
+    B.Rb = cv.take<double>((size_t)ktc * kbr);
+    B.U2 = cv.take<double>((size_t)ktc * p2);
+    B.S2 = cv.take<double>(p2);
+    B.V2 = cv.take<double>((size_t)kbr * p2);
+    B.inv2 = cv.take<double>(p2);
+    B.M64 = cv.take<double>((size_t)ktr * ktc);
+    B.Mtc = prm->compute == CABS_F64 ? (void*)B.M64 : cv.take_bytes((size_t)ktr * ktc * prec_bytes(prm->compute));
+    B.T1 = cv.take<double>((size_t)p1 * ktc);
+    B.T2 = cv.take<double>((size_t)p1 * p2);
+    B.T3 = cv.take<double>((size_t)kbc * p2);
+    B.blk_ws = cv.take_bytes(eval_block_ws_bytes(mv, ktr));
+    svd_b = std::max(svd_b, svd_ws_bytes(1, ktc, kbr));
+  }
+  B.svd_ws = cv.take_bytes(svd_b);
+  return cv.off + 256;
+}
+
+static cabs_status check_brcur(const cabs_matrix* mat, const cabs_brcur_params* prm, bool same) {
+  cabs_status s = check_matrix(mat);
+  if (s != CABS_OK) return s;
+  if (!prm) return fail(CABS_EINVAL, "null parameters");
+  s = check_compute(mat, prm->compute);
+  if (s != CABS_OK) return s;
+  if (prm->kb_rows < 1 || prm->kb_rows > 1024 || prm->kb_cols < 1 || prm->kb_cols > 1024)
+    return fail(CABS_EINVAL, "base sample sizes must be in [1, 1024]");
+  if (prm->kb_rows > mat->m || prm->kb_cols > mat->n) return fail(CABS_EINVAL, "base sample size exceeds the dimension");
+  if (!same) {
+    if (prm->kt_rows < 1 || prm->kt_rows > 4096 || prm->kt_cols < 1 || prm->kt_cols > 4096)
+      return fail(CABS_EINVAL, "target sample sizes must be in [1, 4096]");
+    if (prm->kt_rows > mat->m || prm->kt_cols > mat->n)
+      return fail(CABS_EINVAL, "target sample size exceeds the dimension");
+  }
+  if (prm->rank_cap < 0) return fail(CABS_EINVAL, "rank_cap must be >= 0");
+  if (prm->flags != 0) return fail(CABS_EINVAL, "unknown flag bits");
+  return CABS_OK;
+}
+
+}  // namespace
+
+extern "C" size_t cabs_brcur_workspace_bytes(const cabs_matrix* mat, const cabs_brcur_params* prm,
+                                             int32_t same_sample) {
+  if (check_brcur(mat, prm, same_sample != 0) != CABS_OK) return 0;
+  BrWs B;
+  return plan_brcur(nullptr, view_of(mat), prm, same_sample != 0, B);
+}
+
+extern "C" cabs_status cabs_brcur(const cabs_matrix* mat, const cabs_brcur_params* prm, const int64_t* base_r,
+                                  const int64_t* base_c, const int64_t* tgt_r, const int64_t* tgt_c, void* ws,
+                                  size_t ws_bytes, void* C, void* Rt, double* Umid, double* diag, void* stream) {
+  if ((tgt_r == nullptr) != (tgt_c == nullptr)) return fail(CABS_EINVAL, "give both target samples or neither");
+  const bool same = tgt_r == nullptr;
+  cabs_status s = check_brcur(mat, prm, same);
+  if (s != CABS_OK) return s;
+  if (!base_r || !base_c || !C || !Rt || !Umid) return fail(CABS_EINVAL, "base samples, C, Rt and Umid are required");
+  if (!ws || ((uintptr_t)ws & 255)) return fail(CABS_EINVAL, "workspace must be non-null and 256-byte aligned");
+  const MatView mv = view_of(mat);
+  BrWs B;
+  const size_t need = plan_brcur(nullptr, mv, prm, same, B);
+  if (ws_bytes < need) return fail(CABS_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  plan_brcur(ws, mv, prm, same, B);
+  hipStream_t st = (hipStream_t)stream;
+  double* dg = diag ? diag : B.diag;
+  const int prec = prm->compute;
+  const int kbr = prm->kb_rows, kbc = prm->kb_cols;
+  hipLaunchKernelGGL(brcur_diag_init_kernel, dim3(1), dim3(64), 0, st, dg);
+  HIP_TRY(hipGetLastError());
+  // step 1: the bases C = A(:, Ib_c), R^T = A(Ib_r, :)^T
+  HIP_TRY(launch_eval(mv, false, base_c, kbc, prec, C, st));
+  HIP_TRY(launch_eval(mv, true, base_r, kbr, prec, Rt, st));
+  if (same) {
+    // Eq. (W): W = C(Ib_r, :), Umid = V_w diag(1 / sigma) U_w^T over the kept components
+    const int p = std::min(kbr, kbc);
+    HIP_TRY(launch_gather_rows_f64(C, prec, kbc, base_r, kbr, kbc, B.Cb, st));
+    HIP_TRY(launch_svd(1, kbr, kbc, B.Cb, 0, B.U1, 0, B.S1, 0, B.V1, 0, B.svd_ws, st));
+    hipLaunchKernelGGL(pinv_scale_kernel, dim3(1), dim3(1024), 0, st, p, kbr, kbc, B.S1, prm->pinv_rtol,
+                       prm->rank_cap, B.inv1, dg, (int)CABS_BRCUR_DIAG_RANK_C, (int)CABS_BRCUR_DIAG_SIGMA1_C,
+                       (int)CABS_BRCUR_DIAG_RANK_R, (int)CABS_BRCUR_DIAG_SIGMA1_R);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(launch_small_gemm(kbc, kbr, p, B.V1, p, false, B.U1, p, true, nullptr, B.inv1, nullptr, Umid, kbr, st));
+    return CABS_OK;
+  }
+  const int ktr = prm->kt_rows, ktc = prm->kt_cols;
+  const int p1 = std::min(ktr, kbc), p2 = std::min(ktc, kbr);
+  // step 2: the bases on the target sample, Cbar (kt_r x kb_c) and Rbar^T (kt_c x kb_r), in FP64
+  HIP_TRY(launch_gather_rows_f64(C, prec, kbc, tgt_r, ktr, kbc, B.Cb, st));
+  HIP_TRY(launch_gather_rows_f64(Rt, prec, kbr, tgt_c, ktc, kbr, B.Rb, st));
+  // step 3: the target block M = A(It_r, It_c)
+  HIP_TRY(launch_eval_block(mv, tgt_r, ktr, tgt_c, ktc, prec, B.Mtc, B.blk_ws, st));
+  if (prec != CABS_F64) HIP_TRY(launch_widen_f64(prec, (int64_t)ktr * ktc, B.Mtc, B.M64, st));
+  // step 4: Cbar = U1 S1 V1^T, Rbar^T = U2 S2 V2^T (so Rbar^+ = U2 S2^-1 V2^T);
+  //   Umid = V1 S1^-1 (U1^T M U2) S2^-1 V2^T
+  HIP_TRY(launch_svd(1, ktr, kbc, B.Cb, 0, B.U1, 0, B.S1, 0, B.V1, 0, B.svd_ws, st));
+  hipLaunchKernelGGL(pinv_scale_kernel, dim3(1), dim3(1024), 0, st, p1, ktr, kbc, B.S1, prm->pinv_rtol,
+                     prm->rank_cap, B.inv1, dg, (int)CABS_BRCUR_DIAG_RANK_C, (int)CABS_BRCUR_DIAG_SIGMA1_C, -1, -1);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(launch_svd(1, ktc, kbr, B.Rb, 0, B.U2, 0, B.S2, 0, B.V2, 0, B.svd_ws, st));
+  hipLaunchKernelGGL(pinv_scale_kernel, dim3(1), dim3(1024), 0, st, p2, ktc, kbr, B.S2, prm->pinv_rtol,
+                     prm->rank_cap, B.inv2, dg, (int)CABS_BRCUR_DIAG_RANK_R, (int)CABS_BRCUR_DIAG_SIGMA1_R, -1, -1);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(launch_small_gemm(p1, ktc, ktr, B.U1, p1, true, B.M64, ktc, false, B.inv1, nullptr, nullptr, B.T1, ktc, st));
+  HIP_TRY(launch_small_gemm(p1, p2, ktc, B.T1, ktc, false, B.U2, p2, false, nullptr, nullptr, B.inv2, B.T2, p2, st));
+  HIP_TRY(launch_small_gemm(kbc, p2, p1, B.V1, p1, false, B.T2, p2, false, nullptr, nullptr, nullptr, B.T3, p2, st));
+  HIP_TRY(launch_small_gemm(kbc, kbr, p2, B.T3, p2, false, B.V2, p2, true, nullptr, nullptr, nullptr, Umid, kbr, st));
+  return CABS_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Stage entry points
 // ---------------------------------------------------------------------------
 extern "C" cabs_status cabs_sample(int64_t n, int32_t k, uint64_t seed, int32_t stream_id, int64_t* out, void* stream) {
@@ -847,15 +1053,19 @@ extern "C" cabs_status cabs_eval_rows_t(const cabs_matrix* mat, const int64_t* i
   return eval_common(mat, idx, k, compute, out, stream, true);
 }
 
+static bool svd_shape_ok(int32_t batch, int32_t rows, int32_t cols) {
+  return batch > 0 && rows > 0 && cols > 0 && std::min(rows, cols) <= 1024 && std::max(rows, cols) <= 4096;
+}
+
 extern "C" size_t cabs_svd_workspace_bytes(int32_t batch, int32_t rows, int32_t cols) {
-  if (batch <= 0 || rows <= 0 || cols <= 0 || rows > 1024 || cols > 1024) return 0;
+  if (!svd_shape_ok(batch, rows, cols)) return 0;
   return svd_ws_bytes(batch, rows, cols);
 }
 
 extern "C" cabs_status cabs_svd_ex(int32_t batch, int32_t rows, int32_t cols, const double* A, double* U, double* S,
                                    double* V, void* ws, size_t ws_bytes, int32_t fast_sweeps, void* stream) {
-  if (batch <= 0 || rows <= 0 || cols <= 0 || rows > 1024 || cols > 1024)
-    return fail(CABS_EINVAL, "need batch > 0 and 0 < rows, cols <= 1024");
+  if (!svd_shape_ok(batch, rows, cols))
+    return fail(CABS_EINVAL, "need batch > 0, 0 < min(rows, cols) <= 1024 and max(rows, cols) <= 4096");
   if (fast_sweeps < 0 || fast_sweeps > 24) return fail(CABS_EINVAL, "need 0 <= fast_sweeps <= 24");
   if (!A || !U || !S || !V || !ws) return fail(CABS_EINVAL, "null pointer");
   if (ws_bytes < svd_ws_bytes(batch, rows, cols)) return fail(CABS_ENOMEM, "workspace too small");

@@ -54,19 +54,6 @@ __device__ __forceinline__ double entry_f64(const MatView& mv, int64_t i, int64_
   return s;
 }
 
-// Entry (i, j) of a CSR source: a binary search of row i's ascending columns.
-template <typename TIn>
-__device__ __forceinline__ double csr_entry(const MatView& mv, int64_t i, int64_t j) {
-  int64_t lo = mv.row_ptr[i], hi = mv.row_ptr[i + 1];  // search [lo, hi)
-  const int32_t jj = (int32_t)j;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (mv.col_idx[mid] < jj) lo = mid + 1;
-    else hi = mid;
-  }
-  return (lo < mv.row_ptr[i + 1] && mv.col_idx[lo] == jj) ? (double)((const TIn*)mv.vals)[lo] : 0.0;
-}
-
 // Sample t: Philox-4x32-10 at counter (lo t, hi t, 4, 0), key (lo seed, hi
 // seed); i and j from the high words of 64x64 products of words 1:0 by m and
 // words 3:2 by n (uniform over the m x n entries, with replacement).

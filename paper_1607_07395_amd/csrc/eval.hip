@@ -104,6 +104,7 @@ struct EvalArgs {
   int K;                                    // r or d
   void* out; int64_t ldo;
   int transposed;                           // 1: output row p is A column p (R^T)
+  const int64_t* ridx;                      // X rows gathered from these rows of A (null: row p is row p)
   double noise_std; uint64_t noise_seed;
   double inv2s2;                            // 1 / (2 sigma^2)
   unsigned long long* counter;              // entries evaluated (may be null)
@@ -154,8 +155,9 @@ __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a) {
         if (SRC == SRC_LOWRANK) {
           if (a.noise_std != 0.0) {
             const int64_t sidx = a.idx[col];
-            const uint64_t ai = a.transposed ? (uint64_t)sidx : (uint64_t)row;
-            const uint64_t aj = a.transposed ? (uint64_t)row : (uint64_t)sidx;
+            const int64_t grow = a.ridx ? a.ridx[row] : row;
+            const uint64_t ai = a.transposed ? (uint64_t)sidx : (uint64_t)grow;
+            const uint64_t aj = a.transposed ? (uint64_t)grow : (uint64_t)sidx;
             if (sizeof(AT) == 8) v += (AT)(a.noise_std * noise_f64(a.noise_seed, ai, aj));
             else v += (AT)((float)a.noise_std * noise_f32(a.noise_seed, ai, aj));
           }
@@ -357,6 +359,105 @@ hipError_t launch_eval(const MatView& mv, bool rows_t, const int64_t* idx, int k
     case P_F32: return eval_dispatch_src<float, float>(mv.kind, a, grid, st);
     case P_BF16: return eval_dispatch_src<float, bf16>(mv.kind, a, grid, st);
     case P_F16: return eval_dispatch_src<float, f16>(mv.kind, a, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Target block M = A(I, J) of the resampling CUR (Algorithm 1, step 3).  The
+// generator sources gather the K-wide rows of I into a compact table and run
+// the column evaluation on it (the same tile arithmetic as C = A(:, J), with
+// the noise keyed on the original row); the stored sources read the entries.
+// ---------------------------------------------------------------------------
+template <typename TIn>
+__global__ __launch_bounds__(256) void gather_table_rows_kernel(const TIn* __restrict__ X, int ld,
+                                                                const int64_t* __restrict__ idx, int k,
+                                                                TIn* __restrict__ out) {
+  const int64_t total = (int64_t)k * ld;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e / ld, c = e % ld;
+    out[e] = X[idx[i] * ld + c];
+  }
+}
+
+template <typename TIn, typename TC>
+__global__ __launch_bounds__(256) void dense_block_kernel(const TIn* __restrict__ A, int64_t lda,
+                                                          const int64_t* __restrict__ ri, const int64_t* __restrict__ ci,
+                                                          int kc, TC* __restrict__ out) {
+  const int i = blockIdx.y;
+  const TIn* arow = A + ri[i] * lda;
+  for (int j = blockIdx.x * 256 + threadIdx.x; j < kc; j += gridDim.x * 256)
+    out[(int64_t)i * kc + j] = from_f64<TC>((double)arow[ci[j]]);
+}
+
+template <typename TIn, typename TC>
+__global__ __launch_bounds__(256) void csr_block_kernel(MatView mv, const int64_t* __restrict__ ri,
+                                                        const int64_t* __restrict__ ci, int kc, TC* __restrict__ out) {
+  const int i = blockIdx.y;
+  const int64_t r = ri[i];
+  for (int j = blockIdx.x * 256 + threadIdx.x; j < kc; j += gridDim.x * 256)
+    out[(int64_t)i * kc + j] = from_f64<TC>(csr_entry<TIn>(mv, r, ci[j]));
+}
+
+size_t eval_block_ws_bytes(const MatView& mv, int kr) {
+  const size_t eb = mv.storage == P_F64 ? 8 : 4;
+  if (mv.kind == SRC_LOWRANK) return (size_t)kr * mv.r * eb + 256;
+  if (mv.kind == SRC_RBF) return (size_t)kr * mv.d * eb + 256;
+  return 256;
+}
+
+template <typename TIn, typename TC>
+static hipError_t block_dispatch(const MatView& mv, const int64_t* ri, int kr, const int64_t* ci, int kc, void* out,
+                                 void* ws, hipStream_t st) {
+  const dim3 sgrid((unsigned)ceil_div(kc, 256), (unsigned)kr);
+  if (mv.kind == SRC_DENSE) {
+    hipLaunchKernelGGL((dense_block_kernel<TIn, TC>), sgrid, dim3(256), 0, st, (const TIn*)mv.a, mv.lda, ri, ci, kc,
+                       (TC*)out);
+    return hipGetLastError();
+  }
+  if (mv.kind == SRC_CSR) {
+    hipLaunchKernelGGL((csr_block_kernel<TIn, TC>), sgrid, dim3(256), 0, st, mv, ri, ci, kc, (TC*)out);
+    return hipGetLastError();
+  }
+  EvalArgs a{};
+  const int K = mv.kind == SRC_LOWRANK ? mv.r : mv.d;
+  const TIn* X = (const TIn*)(mv.kind == SRC_LOWRANK ? mv.pf : mv.x);
+  TIn* Xg = (TIn*)ws;
+  const unsigned gg = (unsigned)std::min<int64_t>(ceil_div((int64_t)kr * K, 256), 4096);
+  hipLaunchKernelGGL((gather_table_rows_kernel<TIn>), dim3(gg), dim3(256), 0, st, X, K, ri, kr, Xg);
+  a.X = Xg;
+  a.ldx = K;
+  a.M = kr;
+  a.Y = mv.kind == SRC_LOWRANK ? mv.qf : mv.y;
+  a.ldy = K;
+  a.K = K;
+  a.ys = mv.kind == SRC_LOWRANK ? mv.s : nullptr;
+  a.inv2s2 = mv.kind == SRC_RBF ? 1.0 / (2.0 * mv.sigma * mv.sigma) : 0.0;
+  a.idx = ci;
+  a.N = kc;
+  a.out = out;
+  a.ldo = kc;
+  a.transposed = 0;
+  a.ridx = ri;
+  a.noise_std = mv.kind == SRC_LOWRANK ? mv.noise_std : 0.0;
+  a.noise_seed = mv.noise_seed;
+  a.counter = nullptr;
+  dim3 grid((unsigned)ceil_div(kr, 64), (unsigned)ceil_div(kc, EVAL_NT * 16));
+  return eval_dispatch_src<TIn, TC>(mv.kind, a, grid, st);
+}
+
+hipError_t launch_eval_block(const MatView& mv, const int64_t* ri, int kr, const int64_t* ci, int kc, int compute,
+                             void* out, void* ws, hipStream_t st) {
+  if (kr <= 0 || kc <= 0 || kr > 65535) return hipErrorInvalidValue;
+  TimerScope ts(T_EVAL, st);
+  if (mv.storage == P_F64) {
+    if (compute == P_F64) return block_dispatch<double, double>(mv, ri, kr, ci, kc, out, ws, st);
+    return hipErrorInvalidValue;
+  }
+  switch (compute) {
+    case P_F32: return block_dispatch<float, float>(mv, ri, kr, ci, kc, out, ws, st);
+    case P_BF16: return block_dispatch<float, bf16>(mv, ri, kr, ci, kc, out, ws, st);
+    case P_F16: return block_dispatch<float, f16>(mv, ri, kr, ci, kc, out, ws, st);
     default: return hipErrorInvalidValue;
   }
 }

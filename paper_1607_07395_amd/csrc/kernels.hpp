@@ -37,12 +37,30 @@ struct MatView {
   int64_t nnz;
 };
 
+// Entry (i, j) of a CSR source: a binary search of row i's ascending columns.
+template <typename TIn>
+__device__ __forceinline__ double csr_entry(const MatView& mv, int64_t i, int64_t j) {
+  int64_t lo = mv.row_ptr[i], hi = mv.row_ptr[i + 1];  // search [lo, hi)
+  const int32_t jj = (int32_t)j;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (mv.col_idx[mid] < jj) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < mv.row_ptr[i + 1] && mv.col_idx[lo] == jj) ? (double)((const TIn*)mv.vals)[lo] : 0.0;
+}
+
 // --- sampling / entry evaluation (eval.hip) ---
 hipError_t launch_sample(int64_t n, int k, uint64_t seed, int stream_id, int64_t* out, hipStream_t st);
 // rows_t = false: out (m x k) = A(:, idx); rows_t = true: out (n x k) = A(idx, :)^T.
 // counter (may be null): every entry evaluated or read is added to it on the device.
 hipError_t launch_eval(const MatView& mv, bool rows_t, const int64_t* idx, int k, int compute, void* out,
                        hipStream_t st, unsigned long long* counter = nullptr);
+// out (kr x kc, row-major, compute precision) = A(ri, ci): the target block of the resampling CUR.
+// ws: eval_block_ws_bytes(mv, kr) bytes (the generator rows of ri, for the low-rank and RBF sources).
+size_t eval_block_ws_bytes(const MatView& mv, int kr);
+hipError_t launch_eval_block(const MatView& mv, const int64_t* ri, int kr, const int64_t* ci, int kc, int compute,
+                             void* out, void* ws, hipStream_t st);
 // out (k x ncols, FP64) = src[idx[i], :] for a compute-precision row-major src with row stride ld.
 hipError_t launch_gather_rows_f64(const void* src, int compute, int64_t ld, const int64_t* idx, int k, int ncols,
                                   double* out, hipStream_t st);

@@ -861,7 +861,8 @@ __global__ __launch_bounds__(1024) void bj_finish_kernel(int rows, int cols, int
 hipError_t launch_svd(int batch, int rows, int cols, const double* A, int64_t strideA, double* U, int64_t strideU,
                       double* S, int64_t strideS, double* V, int64_t strideV, void* ws, hipStream_t st,
                       int fast_sweeps) {
-  if (batch <= 0 || rows <= 0 || cols <= 0 || rows > 1024 || cols > 1024) return hipErrorInvalidValue;
+  if (batch <= 0 || rows <= 0 || cols <= 0 || std::min(rows, cols) > 1024 || std::max(rows, cols) > 4096)
+    return hipErrorInvalidValue;
   if (fast_sweeps == 0) fast_sweeps = bj_default_fast_sweeps(rows < cols ? rows : cols);
   if (fast_sweeps < 1 || fast_sweeps > BJ_FAST_SWEEPS) return hipErrorInvalidValue;
   const size_t p = rows < cols ? rows : cols, q = rows < cols ? cols : rows;

@@ -67,7 +67,12 @@ def test_workspace_planning_and_validation_on_cpu():
     assert lib.cabs_workspace_bytes(C.byref(d), C.byref(h)) > 0
     lv = make_params(20, 20, 20, 20, compute="f32", follow_up="leverage")
     assert lib.cabs_workspace_bytes(C.byref(d), C.byref(lv)) > 0
-    h.follow_up = 3
+    pil = make_params(20, 30, 20, 30, compute="f32", follow_up="pilot")
+    assert 0 < lib.cabs_workspace_bytes(C.byref(d), C.byref(pil)) < lib.cabs_workspace_bytes(C.byref(d), C.byref(p))
+    pil.k2_cols = 31   # the pilot sketch alone keeps the pilot sizes
+    assert lib.cabs_workspace_bytes(C.byref(d), C.byref(pil)) == 0
+    assert b"k2 = k1" in lib.cabs_last_error()
+    h.follow_up = 4
     assert lib.cabs_workspace_bytes(C.byref(d), C.byref(h)) == 0
     assert b"follow-up" in lib.cabs_last_error()
     h.follow_up = 0
@@ -85,7 +90,9 @@ def test_entry_points_reject_bad_arguments_without_launching():
     assert lib.cabs_sketch(C.byref(d), C.byref(p), None, 0, C.byref(res), None) == F.EINVAL
     assert lib.cabs_sample(10, 11, 0, 0, C.c_void_p(0x1000), None) == F.EINVAL
     assert lib.cabs_sample(10, 3, 0, 0, None, None) == F.EINVAL
-    assert lib.cabs_svd(1, 2000, 3, None, None, None, None, None, 0, None) == F.EINVAL
+    assert lib.cabs_svd(1, 5000, 3, None, None, None, None, None, 0, None) == F.EINVAL
+    assert lib.cabs_svd(1, 1100, 1100, None, None, None, None, None, 0, None) == F.EINVAL
+    assert lib.cabs_svd_workspace_bytes(1, 4096, 1024) > 0 and lib.cabs_svd_workspace_bytes(1, 4097, 10) == 0
     assert lib.cabs_svd_ex(1, 50, 50, None, None, None, None, None, 0, -1, None) == F.EINVAL
     assert lib.cabs_svd_ex(1, 50, 50, None, None, None, None, None, 0, 25, None) == F.EINVAL
     assert lib.cabs_kmeans(10, 3, 11, F.F32, None, None, None, 1, None, None, None, None, None, 0, None) == F.EINVAL
@@ -104,6 +111,37 @@ def test_entry_points_reject_bad_arguments_without_launching():
     assert b"workspace too small" in lib.cabs_last_error()
     # unaligned workspace
     assert lib.cabs_sketch(C.byref(d), C.byref(p), C.c_void_p(0x100001), 1 << 40, C.byref(res), None) == F.EINVAL
+
+
+def test_brcur_planning_and_validation_on_cpu():
+    from paper_1607_07395_amd import _ffi as F
+    lib = F.lib()
+    d = _desc()
+    p = F.CabsBrCurParams()
+    p.kb_rows, p.kb_cols, p.kt_rows, p.kt_cols, p.compute = 20, 30, 60, 90, F.F32
+    gen = lib.cabs_brcur_workspace_bytes(C.byref(d), C.byref(p), 0)
+    same = lib.cabs_brcur_workspace_bytes(C.byref(d), C.byref(p), 1)
+    assert gen > same > 0
+    # the target sizes are ignored when the target is the base sample
+    p.kt_rows = 5000
+    assert lib.cabs_brcur_workspace_bytes(C.byref(d), C.byref(p), 1) == same
+    assert lib.cabs_brcur_workspace_bytes(C.byref(d), C.byref(p), 0) == 0
+    p.kt_rows = 60
+    for field, value in (("kb_rows", 0), ("kb_cols", 1025), ("kt_cols", 4097), ("kt_cols", 801), ("rank_cap", -1),
+                         ("flags", 1), ("compute", F.F64)):
+        old = getattr(p, field)
+        setattr(p, field, value)
+        assert lib.cabs_brcur_workspace_bytes(C.byref(d), C.byref(p), 0) == 0, field
+        setattr(p, field, old)
+    fake = C.c_void_p(0x1000)
+    # one target pointer without the other, missing outputs, a short workspace: rejected before any launch
+    assert lib.cabs_brcur(C.byref(d), C.byref(p), fake, fake, fake, None, fake, 1 << 30, fake, fake, fake, None,
+                          None) == F.EINVAL
+    assert lib.cabs_brcur(C.byref(d), C.byref(p), fake, fake, None, None, C.c_void_p(0x100000), 1 << 30, fake, fake,
+                          None, None, None) == F.EINVAL
+    assert lib.cabs_brcur(C.byref(d), C.byref(p), fake, fake, fake, fake, C.c_void_p(0x100000), 1024, fake, fake,
+                          fake, None, None) == F.ENOMEM
+    assert b"workspace too small" in lib.cabs_last_error()
 
 
 def test_server_rejects_invalid_creation():
