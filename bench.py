@@ -32,6 +32,13 @@ sample of the headline workload.
 
 `--stream` runs only the serving stream (5000 requests per phase by default);
 `--config NAME` times another workload.
+
+`--sweep` runs only the sampling-rate comparison of Section 5 (Fig. 5(a)) on
+synthetic stand-ins for Table 1's matrices: for rates k / sqrt(mn) of 1, 2, 5
+and 10 % (sizes above 1024 skipped), the mean exact relative Frobenius error
+over 20 seeds of the six linear-cost methods (Sketch-CUR with a three times
+larger target sample, pseudo-skeleton, pilot sketch, and the follow-up sketch
+by weighted k-means, leverage scores and hard threshold), all in FP64.
 """
 from __future__ import annotations
 
@@ -73,6 +80,10 @@ def parse():
                     help="before timing, copy a buffer of this many MiB device-to-device once (a kernel of known "
                          "traffic for calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--stream", action="store_true", help="only the serving stream of uneven requests")
+    ap.add_argument("--sweep", action="store_true", help="only the sampling-rate comparison of the linear-cost methods")
+    ap.add_argument("--sweep-matrices", default="scene,hubble,movie,news")
+    ap.add_argument("--sweep-rates", default="0.01,0.02,0.05,0.10")
+    ap.add_argument("--sweep-repeats", type=int, default=20)
     ap.add_argument("--stream-requests", type=int, default=5000, help="requests per phase with --stream")
     ap.add_argument("--extra-stream-requests", type=int, default=1000,
                     help="requests per phase of the stream run among the extra keys")
@@ -410,6 +421,70 @@ def lowrank_extras(api, args) -> dict:
     return out
 
 
+SWEEP_METHODS = ("sketch_cur", "pseudo_skeleton", "pilot", "kmeans", "leverage", "hard")
+
+
+def sweep_matrix(name: str):
+    import workloads
+    return {"scene": workloads.natural_scene_like, "hubble": workloads.hubble_like, "movie": workloads.movie_like,
+            "news": workloads.newsgroup_like}[name]()
+
+
+def rate_sweep(api, args) -> dict:
+    """Mean exact error of each linear-cost method over the seeds, per matrix and sampling rate.
+
+    Weights of the follow-up sampling: constant on the dense stand-ins and POW(2) on the sparse ones
+    (slowly growing for dense, fast growing for sparse input, Section 3.2); the hard threshold ranks
+    by the embedding norm, which every increasing weight orders alike, POW(2) here.  Pilot and
+    follow-up sizes are both k; c = 5 k-means iterations."""
+    import numpy as np
+    import torch
+
+    rows = []
+    for name in args.sweep_matrices.split(","):
+        t0 = time.time()
+        spec = sweep_matrix(name)
+        sparse = spec.kind == "csr"
+        mat = api.DeviceMatrix(spec, storage="f64")
+        log(f"sweep {name}: {spec.m} x {spec.n} ({'sparse' if sparse else 'dense'}), built in {time.time() - t0:.1f} s")
+        for rate in (float(r) for r in args.sweep_rates.split(",")):
+            k = int(round(rate * math.sqrt(spec.m * spec.n)))
+            if k > 1024:
+                rows.append({"matrix": name, "rate": rate, "k": k, "skipped": "k above the 1024 sample-size limit"})
+                continue
+            row = {"matrix": name, "rate": rate, "k": k}
+            for method in SWEEP_METHODS:
+                errs, t1 = [], time.time()
+                for seed in range(args.sweep_repeats):
+                    if method == "sketch_cur":
+                        r = api.sketch_cur(mat, k, k, seed, ratio=3, compute="f64")
+                        e = api.error(mat, r.params, r, 0)
+                    elif method == "pseudo_skeleton":
+                        r = api.pseudo_skeleton(mat, k, k, seed, compute="f64")
+                        e = api.error(mat, r.params, r, 0)
+                    else:
+                        weight = "pow" if (sparse or method == "hard") else "const"
+                        prm = api.make_params(k, k, k, k, kmeans_iters=5, weight=weight,
+                                              weight_param=2.0 if weight == "pow" else 0.0, compute="f64",
+                                              seed=seed, follow_up=method)
+                        r = api.sketch(mat, prm)
+                        e = api.error(mat, prm, r, 0)
+                    errs.append(e[2])
+                errs = torch.stack(errs).cpu().numpy()
+                row[method] = {"mean": float(errs.mean()), "std": float(errs.std()),
+                               "median": float(np.median(errs)),
+                               "ms_per_sketch_and_error": 1e3 * (time.time() - t1) / len(errs)}
+                log(f"    {name} k = {k} {method}: mean error {row[method]['mean']:.4g} "
+                    f"({row[method]['ms_per_sketch_and_error']:.0f} ms per sketch + exact error)")
+            rows.append(row)
+            log(f"  rate {rate:g} (k = {k}): " + ", ".join(f"{m} {row[m]['mean']:.4g}" for m in SWEEP_METHODS))
+        del mat
+        torch.cuda.empty_cache()
+    return {"metric": "mean exact relative Frobenius error of the linear-cost methods against the sampling rate "
+                      "k / sqrt(mn) (Section 5, Fig. 5(a))", "unit": "relative Frobenius error", "dtype": "f64",
+            "repeats": args.sweep_repeats, "data": "synthetic stand-ins for Table 1's matrices", "rows": rows}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -424,6 +499,9 @@ def main():
     from paper_1607_07395_amd import api
 
     torch.cuda.set_device(0)
+    if args.sweep:
+        print(json.dumps(rate_sweep(api, args)), flush=True)
+        return
     if args.stream:
         res = run_stream(api, args, args.stream_requests)
         print(json.dumps({"metric": "serving stream: sketches/s and p50/p99 latency under Poisson arrivals",

@@ -868,7 +868,9 @@ __device__ __forceinline__ void topt_insert(AT (&d)[SNAP_T], int (&r)[SNAP_T], A
 // into its own LDS tile, then each lane inserts its centre's 16 distances in
 // row order.  One list per (block, centre), so each list fills once; no
 // barrier across waves.  A list holding fewer than SNAP_T rows means every
-// other row of the block is at +inf.  Each 16-centre column tile of gemm_tile
+// other row of the block is at +inf.  Rows of norm 0 are left out (+inf): they
+// form one class of equal distance to every centre, which the resolver handles
+// as a single candidate (its lowest untaken row).  Each 16-centre column tile of gemm_tile
 // is an independent MFMA chain and every row tile starts 16-aligned from the
 // block start, so snap_resolve_kernel recomputes these distances bit-exactly
 // from a one-tile call at the same row and column offsets.
@@ -907,7 +909,7 @@ __global__ __launch_bounds__(256) void snap_topt_kernel(int64_t rows, int dim, i
           const int rl = out_row<TC>(g, i);
           const int64_t row = row0 + rl;
           double d = __builtin_huge_val();
-          if (row < rend && col < k) d = snap_dist(pnorm[row], znorm[col], (double)acc[t][i]);
+          if (row < rend && col < k && pnorm[row] != 0.0) d = snap_dist(pnorm[row], znorm[col], (double)acc[t][i]);
           sd[rl * LDD + cl] = d;
         }
       }
@@ -1003,6 +1005,61 @@ __global__ __launch_bounds__(256) void snap_merge_kernel(int nblk, const double*
   }
 }
 
+// Rows of FP64 squared norm 0, ascending (the all-zero rows of sparse
+// embeddings): block b counts its contiguous chunk, one block turns the counts
+// into offsets (zoff[ZR_NB] = the total), block b writes its chunk's rows.
+constexpr int ZR_NB = 256;
+
+__device__ __forceinline__ void zr_chunk(int64_t rows, int b, int64_t& r0, int64_t& r1) {
+  const int64_t ch = (rows + ZR_NB - 1) / ZR_NB;
+  r0 = (int64_t)b * ch;
+  r1 = r0 + ch < rows ? r0 + ch : rows;
+}
+
+__global__ __launch_bounds__(256) void zero_rows_count_kernel(int64_t rows, const double* __restrict__ pnorm,
+                                                              int32_t* __restrict__ zcnt) {
+  __shared__ int wc[4];
+  int64_t r0, r1;
+  zr_chunk(rows, blockIdx.x, r0, r1);
+  int c = 0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) c += pnorm[r] == 0.0 ? 1 : 0;
+  c = wave_sum(c);
+  if ((threadIdx.x & 63) == 0) wc[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) zcnt[blockIdx.x] = wc[0] + wc[1] + wc[2] + wc[3];
+}
+
+__global__ void zero_rows_scan_kernel(const int32_t* __restrict__ zcnt, int32_t* __restrict__ zoff) {
+  if (threadIdx.x == 0) {
+    int32_t s = 0;
+    for (int b = 0; b < ZR_NB; ++b) { zoff[b] = s; s += zcnt[b]; }
+    zoff[ZR_NB] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void zero_rows_write_kernel(int64_t rows, const double* __restrict__ pnorm,
+                                                              const int32_t* __restrict__ zoff,
+                                                              int32_t* __restrict__ zrows) {
+  __shared__ int wc[4];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int64_t r0, r1;
+  zr_chunk(rows, blockIdx.x, r0, r1);
+  int32_t base = zoff[blockIdx.x];
+  for (int64_t t0 = r0; t0 < r1; t0 += 256) {
+    const int64_t r = t0 + threadIdx.x;
+    const bool z = r < r1 && pnorm[r] == 0.0;
+    const uint64_t m = __ballot(z);
+    if (lane == 0) wc[wave] = __builtin_popcountll(m);
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wave; ++w) before += wc[w];
+    const int tot = wc[0] + wc[1] + wc[2] + wc[3];
+    if (z) zrows[base + before + __builtin_popcountll(m & ((1ull << lane) - 1))] = (int32_t)r;
+    base += tot;
+    __syncthreads();  // wc is rewritten next
+  }
+}
+
 // Snapping, in centre order: centre j takes the nearest row not taken by an
 // earlier centre; distances within tie_rtol * (|Z_j| + sqrt(d_min))^2 of the
 // nearest untaken one count as ties and go to the lowest row index (the
@@ -1017,6 +1074,11 @@ __global__ __launch_bounds__(256) void snap_merge_kernel(int nblk, const double*
 // rescanned.  Rescans recompute the block's distances exactly as the top-T
 // pass did (same tile calls, same rounding) into dws; the window is
 // recomputed and the rescan set widened until no further block qualifies.
+// Rows of norm 0 are in no list and no rescan: all of them lie at the same
+// distance snap_dist(0, |Z_j|^2, 0) from centre j (the value the tile pass
+// gives them), so of that class only its lowest untaken row can be chosen,
+// and they are taken in ascending order: one candidate per centre, read from
+// the ascending list zrows at a moving position.
 constexpr int RES_CHUNK = 128;
 constexpr int RES_HT = 2048;  // hash slots for taken rows (k <= KM_MAXK = RES_HT / 2)
 
@@ -1039,11 +1101,14 @@ __global__ __launch_bounds__(1024) void snap_resolve_kernel(
     int64_t rows, int dim, int k, const TC* __restrict__ P, const TC* __restrict__ Zc,
     const double* __restrict__ znorm, const double* __restrict__ pnorm, const double* __restrict__ top_d,
     const int32_t* __restrict__ top_r, const double* __restrict__ cand_d, const int32_t* __restrict__ cand_r, int nblk,
-    int64_t rows_per_block, double tie_rtol, double* __restrict__ dws, int64_t* __restrict__ out,
-    double* __restrict__ nfall) {
+    int64_t rows_per_block, double tie_rtol, double* __restrict__ dws, const int32_t* __restrict__ zrows,
+    const int32_t* __restrict__ zoff, int64_t* __restrict__ out, double* __restrict__ nfall) {
   typedef typename Mfma<TC>::acc AccV;
   typedef typename NormT<TC>::type NrmT;
   constexpr int32_t SENT = 0x7fffffff;
+  const int32_t nzero = zoff[ZR_NB];
+  __shared__ int32_t sh_zp;             // zrows[sh_zp] is the lowest untaken row of norm 0
+  __shared__ double lzn[RES_CHUNK];     // |Z_j|^2 of the staged centres
   __shared__ int64_t chosen[KM_MAXK];
   __shared__ int32_t ht[RES_HT];
   __shared__ double ld[RES_CHUNK * SNAP_T];
@@ -1058,6 +1123,7 @@ __global__ __launch_bounds__(1024) void snap_resolve_kernel(
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const double INF = __builtin_huge_val();
   for (int e = tid; e < RES_HT; e += 1024) ht[e] = -1;
+  if (tid == 0) sh_zp = 0;
   int j = 0;
   int chunk0 = -RES_CHUNK;
   int fallbacks = 0;
@@ -1070,19 +1136,23 @@ __global__ __launch_bounds__(1024) void snap_resolve_kernel(
         ld[e] = top_d[(int64_t)j * SNAP_T + e];
         lr[e] = top_r[(int64_t)j * SNAP_T + e];
       }
-      for (int e = tid; e < n; e += 1024) lz[e] = sqrt(znorm[j + e]);
+      for (int e = tid; e < n; e += 1024) {
+        lzn[e] = znorm[j + e];
+        lz[e] = sqrt(lzn[e]);
+      }
     }
     __syncthreads();
     if (wave == 0) {
       int jj = j;
       const int lim = (chunk0 + RES_CHUNK < k ? chunk0 + RES_CHUNK : k);
       // One centre at a time, its list's SNAP_T candidates checked at once
-      // (lane q holds candidate q), with the decisions of a walk down the
-      // list: skip taken rows; the first untaken one fixes the tie window
-      // [d, d + tol]; the walk stops at the first later candidate outside it
-      // or at the list's end; the choice is the lowest untaken row walked
-      // over.  Undecided: nothing untaken, or a full list walked to its end
-      // inside the window (then unlisted rows may tie).
+      // (lane q holds candidate q), plus the zero-norm class's candidate:
+      // dmin is the nearer of the first untaken listed row and that class;
+      // the choice is the lowest untaken row within [dmin, dmin + tol] among
+      // the listed rows and the class.  Undecided: no candidate at all, or a
+      // full list whose last distance lies inside the window (then unlisted
+      // rows may be inside too).
+      int zp = sh_zp;
       for (; jj < lim; ++jj) {
         const double zn = lz[jj - chunk0];
         const int q = lane;
@@ -1097,21 +1167,26 @@ __global__ __launch_bounds__(1024) void snap_resolve_kernel(
         const uint64_t m_end = __ballot(q < SNAP_T && !valid);
         const int q_end = m_end ? __builtin_ctzll(m_end) : SNAP_T;
         const uint64_t m_free = __ballot(free_row && q < q_end);
-        if (m_free == 0) break;  // undecided
-        const int q0 = __builtin_ctzll(m_free);
-        const double dmin = __shfl(d, q0, 64);
+        const double dfree = m_free ? __shfl(d, __builtin_ctzll(m_free), 64) : INF;
+        const bool has0 = zp < nzero;
+        const double d0 = has0 ? snap_dist(0.0, lzn[jj - chunk0], 0.0) : INF;
+        const double dmin = dfree < d0 ? dfree : d0;
+        if (!(dmin < INF)) break;  // undecided
         const double rr = zn + sqrt(dmin);
-        const double tol = tie_rtol * rr * rr;
-        const uint64_t m_out = __ballot(q > q0 && q < q_end && d > dmin + tol);
-        const int q_stop = m_out ? __builtin_ctzll(m_out) : q_end;
-        if (q_stop == SNAP_T) break;  // undecided: a full list ends inside the window
-        const int32_t found = wave_min<int32_t>(free_row && q >= q0 && q < q_stop ? r : SENT);
+        const double wlim = dmin + tie_rtol * rr * rr;
+        const double dlast = __shfl(d, SNAP_T - 1, 64);
+        if (q_end == SNAP_T && dlast <= wlim) break;  // undecided: a full list ends inside the window
+        int32_t found = wave_min<int32_t>(free_row && q < q_end && d <= wlim ? r : SENT);
+        const bool take0 = has0 && d0 <= wlim && zrows[zp] < found;
+        if (take0) found = zrows[zp];
         if (lane == 0) {
           chosen[jj] = found;
-          res_put(ht, found);
+          if (!take0) res_put(ht, found);
         }
+        if (take0) ++zp;
         wave_lds_sync();  // the next centre's lookups see the new row
       }
+      if (lane == 0) sh_zp = zp;
       if (lane == 0) sh_next = jj;
     }
     __syncthreads();
@@ -1142,7 +1217,7 @@ __global__ __launch_bounds__(1024) void snap_resolve_kernel(
     const int jc = j - col0;
     for (;;) {
       if (wave == 0) {
-        double m = INF;
+        double m = sh_zp < nzero ? snap_dist(0.0, lzn[j - chunk0], 0.0) : INF;
         for (int b = lane; b < nblk; b += 64) {
           const double v = b_state[b] ? b_smin[b] : b_fd[b];
           m = v < m ? v : m;
@@ -1158,15 +1233,15 @@ __global__ __launch_bounds__(1024) void snap_resolve_kernel(
       }
       __syncthreads();
       if (!sh_more) break;
-      for (int b = 0; b < nblk; ++b) {
-        if (b_state[b] != 2) continue;  // uniform: LDS value read after a barrier
+      // Rescans, one block per wave (the whole block's 16-row tiles, the same tile calls and
+      // rounding as the top-T pass), then one barrier: sparse embeddings with many identical rows
+      // send most centres here, and every block of such a tie class qualifies.
+      for (int b = wave; b < nblk; b += 16) {
+        if (b_state[b] != 2) continue;  // uniform within the wave: LDS value read after a barrier
         const int64_t rbeg = (int64_t)b * rows_per_block;
         const int64_t rend = rbeg + rows_per_block < rows ? rbeg + rows_per_block : rows;
         double mloc = INF;
-        // wave w handles rows s0 + 16 (w % 4) of sub-tiles s0 = rbeg + 64 (w / 4 + 4 u)
-        for (int64_t s0 = rbeg + (int64_t)SNAP_SUB * (wave >> 2); s0 < rend; s0 += (int64_t)SNAP_SUB * 4) {
-          const int64_t row0 = s0 + (wave & 3) * 16;
-          if (row0 >= rend) continue;
+        for (int64_t row0 = rbeg; row0 < rend; row0 += 16) {
           AccV acc[1];
           NrmT xs, ys[1];
           gemm_tile<TC, TC, 1, false>(P, dim, rend, row0, Zc, dim, nullptr, k, col0, nullptr, dim, acc, xs, ys);
@@ -1176,7 +1251,7 @@ __global__ __launch_bounds__(1024) void snap_resolve_kernel(
               const int64_t row = row0 + out_row<TC>(lane >> 4, i);
               if (row < rend) {
                 double d = snap_dist(pnorm[row], znorm[j], (double)acc[0][i]);
-                if (res_has(ht, (int32_t)row)) d = INF;
+                if (pnorm[row] == 0.0 || res_has(ht, (int32_t)row)) d = INF;
                 dws[row] = d;
                 mloc = d < mloc ? d : mloc;
               }
@@ -1184,16 +1259,12 @@ __global__ __launch_bounds__(1024) void snap_resolve_kernel(
           }
         }
         mloc = wave_min(mloc);
-        if (lane == 0) wred[wave] = mloc;
-        __syncthreads();
-        if (tid == 0) {
-          double m = wred[0];
-          for (int w = 1; w < 16; ++w) m = wred[w] < m ? wred[w] : m;
-          b_smin[b] = m;
+        if (lane == 0) {
+          b_smin[b] = mloc;
           b_state[b] = 1;
         }
-        __syncthreads();
       }
+      __syncthreads();
     }
     // lowest untaken row inside the window
     const double lim = sh_lim;
@@ -1219,10 +1290,16 @@ __global__ __launch_bounds__(1024) void snap_resolve_kernel(
     if (tid == 0) {
       int64_t r = wrow[0];
       for (int w = 1; w < 16; ++w) r = wrow[w] < r ? wrow[w] : r;
-      if (r == INT64_MAX)  // unreachable while k <= rows: every block was rescanned at lim = +inf
-        for (r = 0; r < rows && res_has(ht, (int32_t)r); ++r) {}
+      const int zp = sh_zp;
+      if (zp < nzero && snap_dist(0.0, lzn[j - chunk0], 0.0) <= lim && zrows[zp] < r) {
+        r = zrows[zp];
+        sh_zp = zp + 1;
+      } else {
+        if (r == INT64_MAX)  // unreachable while k <= rows: every block was rescanned at lim = +inf
+          for (r = 0; r < rows && (res_has(ht, (int32_t)r) || pnorm[r] == 0.0); ++r) {}
+        res_put(ht, (int32_t)r);
+      }
       chosen[j] = r;
-      res_put(ht, (int32_t)r);
       sh_next = j + 1;
     }
     __syncthreads();
@@ -1261,7 +1338,7 @@ struct KmWs {
   int32_t* hist; int32_t* offs; int32_t* rank_blk; int32_t* sorted; int32_t* lstart;
   int32_t* chunk_lab; int32_t* chunk_beg; int32_t* chunk_end; int32_t* lchunk; int32_t* nchunks;
   double* part; double* partw; double* red_s; double* red_g; double* obj_tmp; double* tmax_tmp; double* gap_tmp;
-  double* cand_d; int32_t* cand_r; double* top_d; int32_t* top_r;
+  double* cand_d; int32_t* cand_r; double* top_d; int32_t* top_r; int32_t* zrows; int32_t* zcnt;
   float* apb; int32_t* api; float* aps; int32_t* tsum;
   size_t total;
 };
@@ -1312,6 +1389,8 @@ static KmWs km_layout(void* base, int64_t rows, int dim, int k, int compute) {
   w.cand_r = (int32_t*)take((size_t)k * nblk * SNAP_T * 4);
   w.top_d = (double*)take((size_t)k * SNAP_T * 8);
   w.top_r = (int32_t*)take((size_t)k * SNAP_T * 4);
+  w.zrows = (int32_t*)take(rows * 4);
+  w.zcnt = (int32_t*)take(2 * (ZR_NB + 1) * 4);
   w.apb = (float*)take((size_t)AF_MAXG * rows * 4);
   w.api = (int32_t*)take((size_t)AF_MAXG * rows * 4);
   w.aps = (float*)take((size_t)AF_MAXG * rows * 4);
@@ -1389,12 +1468,16 @@ static hipError_t kmeans_t(int compute, int64_t rows, int dim, int k, const void
     hipLaunchKernelGGL(snap_topt_kernel<TC>, dim3(nblk_eff), dim3(256), 0, st, rows, dim, k, rpb, P, (const TC*)Zc,
                        W.znorm, W.pnorm, W.cand_d, W.cand_r);
     hipLaunchKernelGGL(snap_merge_kernel, dim3(k), dim3(256), 0, st, nblk_eff, W.cand_d, W.cand_r, W.top_d, W.top_r);
+    int32_t* zoff = W.zcnt + ZR_NB + 1;
+    hipLaunchKernelGGL(zero_rows_count_kernel, dim3(ZR_NB), dim3(256), 0, st, rows, W.pnorm, W.zcnt);
+    hipLaunchKernelGGL(zero_rows_scan_kernel, dim3(1), dim3(64), 0, st, W.zcnt, zoff);
+    hipLaunchKernelGGL(zero_rows_write_kernel, dim3(ZR_NB), dim3(256), 0, st, rows, W.pnorm, zoff, W.zrows);
     // FP64: a relative tie window makes the choice independent of rounding order
     // (and equal to the FP64 reference); other precisions compare exactly.
     const double tie_rtol = sizeof(TC) == 8 ? 1e-11 : 0.0;
     hipLaunchKernelGGL(snap_resolve_kernel<TC>, dim3(1), dim3(1024), 0, st, rows, dim, k, P, (const TC*)Zc, W.znorm,
-                       W.pnorm, W.top_d, W.top_r, W.cand_d, W.cand_r, nblk_eff, rpb, tie_rtol, W.dmin, out.snap,
-                       out.fallbacks);
+                       W.pnorm, W.top_d, W.top_r, W.cand_d, W.cand_r, nblk_eff, rpb, tie_rtol, W.dmin, W.zrows, zoff,
+                       out.snap, out.fallbacks);
   }
   return hipGetLastError();
 }

@@ -211,17 +211,20 @@ def test_sketch_f64_lowrank_1e5_fullsize_matches_oracle(api, lowrank_embeddings)
     compare_f64(api, spec, kw, ref=ref)
 
 
-@pytest.mark.parametrize("kind,k,seed", [("movie", 40, 0), ("news", 32, 3)])
-def test_kmeans_f64_sparse_embeddings_stepwise(api, kind, k, seed):
+@pytest.mark.parametrize("kind,k,seed,dt", [("movie", 40, 0, "f64"), ("news", 32, 3, "f64"), ("news", 64, 4, "f64"),
+                                             ("movie", 48, 5, "f32"), ("news", 40, 6, "bf16")])
+def test_kmeans_f64_sparse_embeddings_stepwise(api, kind, k, seed, dt):
     """FP64 k-means and snap on the pilot embeddings of sparse stand-ins (movie-like 3000 x 4600
     at 8 %, newsgroup-like 1877 x 6118 at 10 %).  Rows whose sampled columns are all zero embed
     to exactly 0 and several pilot rows coincide, so the oracle meets exact distance ties that the
     GPU's expansion |z|^2 - 2 p.z decides by rounding: each step is checked against the oracle's
-    definition with ties inside the FP64 rounding bound (and the snap's tie window) allowed."""
+    definition with ties inside the FP64 rounding bound (and the snap's tie window) allowed.  The
+    rows of norm 0 are the snap's one shared candidate class (most centres of the column side take
+    one of them); FP32 and BF16 embeddings are checked in their own precision."""
     import workloads
     spec = workloads.movie_like(3000, 4600, 0.08, seed=1) if kind == "movie" else \
         workloads.newsgroup_like(1877, 6118, 0.1, seed=2)
     ref = oc.cabs(spec, oc.Params.square(k, kmeans_iters=5, seed=seed))
     for P, idx, w in ((ref.P, ref.pilot_rows, ref.w_r), (ref.Q, ref.pilot_cols, ref.w_c)):
-        unsure, amb = _stepwise(api, P, w, P[idx], 5, "f64")
+        unsure, amb = _stepwise(api, P, w, P[idx], 5, dt)
         print(f"{kind}: undecidable assignments {unsure}, ambiguous snaps {amb}, zero rows {int((P == 0).all(1).sum())}")
