@@ -85,6 +85,30 @@ def test_unequal_sample_sizes_and_factor_form():
     assert res2.idx_r.size == 6
 
 
+def test_initial_centres_with_more_centres_than_pilot_rows():
+    """k2 > k1: the k-means start is k2 distinct rows of the embedding drawn uniformly (each row in
+    with probability k2 / n, checked by counting over seeds), the rows and the columns from their
+    own streams; k2 <= k1: the first k2 pilot rows."""
+    rng = np.random.default_rng(0)
+    emb = rng.normal(size=(12, 3))
+    pilot = np.array([1, 4, 9])
+    assert np.array_equal(oc.initial_centres(emb, pilot, 2, 12, 0, philox.STREAM_INIT_ROWS), emb[[1, 4]])
+    counts = np.zeros(12)
+    for seed in range(6000):
+        z = oc.initial_centres(emb, pilot, 5, 12, seed, philox.STREAM_INIT_ROWS)
+        # every centre is a row of emb, all distinct (brute-force match)
+        hit = np.all(np.isclose(z[:, None, :], emb[None, :, :], rtol=0, atol=0), axis=2)
+        assert np.all(hit.sum(1) == 1)
+        rows = hit.argmax(1)
+        assert np.unique(rows).size == 5
+        counts[rows] += 1
+    from scipy import stats
+    assert stats.chisquare(counts, np.full(12, 6000 * 5 / 12)).pvalue > 1e-3
+    zr = oc.initial_centres(emb, pilot, 5, 12, 3, philox.STREAM_INIT_ROWS)
+    zc = oc.initial_centres(emb, pilot, 5, 12, 3, philox.STREAM_INIT_COLS)
+    assert not np.array_equal(zr, zc)
+
+
 def test_invalid_parameters_raise():
     spec, _ = workloads.config("rbf2000", 0.01)
     with pytest.raises(ValueError):
