@@ -349,18 +349,20 @@ __global__ __launch_bounds__(256) void eb_count_kernel(int64_t m, int64_t n, int
     atomicAdd(&hist[eb_key(pl, i, j)], 1);
   }
   __syncthreads();
-  for (int b = threadIdx.x; b < pl.nbk; b += 256) counts[(int64_t)b * EB_G + blockIdx.x] = hist[b];
+  // chunk-major (counts[g * nbk + b]): each chunk writes its histogram as one contiguous row
+  for (int b = threadIdx.x; b < pl.nbk; b += 256) counts[(int64_t)blockIdx.x * pl.nbk + b] = hist[b];
 }
 
-// Per bucket (one wave each): the total over chunks.
+// Per bucket (one thread each, consecutive buckets in consecutive lanes, so
+// every read of a chunk's row is contiguous): the total over chunks.
 __global__ __launch_bounds__(256) void eb_totals_kernel(EbPlan pl, const int32_t* __restrict__ counts,
                                                         int32_t* __restrict__ totals) {
-  const int b = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int b = blockIdx.x * 256 + threadIdx.x;
   if (b >= pl.nbk) return;
   int s = 0;
-  for (int g = lane; g < EB_G; g += 64) s += counts[(int64_t)b * EB_G + g];
-  s = wave_sum(s);
-  if (lane == 0) totals[b] = s;
+#pragma unroll 8
+  for (int g = 0; g < EB_G; ++g) s += counts[(int64_t)g * pl.nbk + b];
+  totals[b] = s;
 }
 
 // One work-group: exclusive scan of the bucket totals.
@@ -394,29 +396,21 @@ __global__ __launch_bounds__(1024) void eb_scan_kernel(EbPlan pl, const int32_t*
   if (tid == 1023) starts[pl.nbk] = part[1023];
 }
 
-// Per bucket (one wave each): offsets of each chunk's run inside the bucket,
-// stored chunk-major (offs[g * nbk + b]) so that a chunk reads its own row.
+// Per bucket (one thread each, as above): offsets of each chunk's run inside
+// the bucket, stored chunk-major (offs[g * nbk + b]) so that a chunk reads its
+// own row.
 __global__ __launch_bounds__(256) void eb_offsets_kernel(EbPlan pl, const int32_t* __restrict__ counts,
                                                          const int32_t* __restrict__ starts,
                                                          int32_t* __restrict__ offs) {
-  constexpr int PER = EB_G / 64;
-  const int b = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int b = blockIdx.x * 256 + threadIdx.x;
   if (b >= pl.nbk) return;
-  const int32_t* c = counts + (int64_t)b * EB_G + lane * PER;
-  int v[PER], sum = 0;
-#pragma unroll
-  for (int q = 0; q < PER; ++q) { v[q] = c[q]; sum += v[q]; }
-  int incl = sum;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int x = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += x;
-  }
-  int run = starts[b] + incl - sum;
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    offs[(int64_t)(lane * PER + q) * pl.nbk + b] = run;
-    run += v[q];
+  int run = starts[b];
+#pragma unroll 8
+  for (int g = 0; g < EB_G; ++g) {
+    const int64_t e = (int64_t)g * pl.nbk + b;
+    const int c = counts[e];
+    offs[e] = run;
+    run += c;
   }
 }
 
@@ -939,7 +933,7 @@ static hipError_t error_t(const MatView& mv, int kr, const double* CU, const TC*
     int32_t* starts = (int32_t*)((char*)totals + al256e(((size_t)pl.nbk + 1) * 4));
     int2* ij = (int2*)((char*)starts + al256e(((size_t)pl.nbk + 1) * 4));
     int2* sorted = (int2*)((char*)ij + al256e((size_t)ns * 8));
-    const unsigned gw = (unsigned)ceil_div(pl.nbk, 4);
+    const unsigned gw = (unsigned)ceil_div(pl.nbk, 256);
     hipLaunchKernelGGL(eb_count_kernel, dim3(EB_G), dim3(256), 0, st, mv.m, mv.n, ns, seed, pl, ij, counts);
     hipLaunchKernelGGL(eb_totals_kernel, dim3(gw), dim3(256), 0, st, pl, counts, totals);
     hipLaunchKernelGGL(eb_scan_kernel, dim3(1), dim3(1024), 0, st, pl, totals, starts);
