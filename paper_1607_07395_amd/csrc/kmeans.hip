@@ -861,12 +861,105 @@ __device__ __forceinline__ void topt_insert(AT (&d)[SNAP_T], int (&r)[SNAP_T], A
   if (nd < d[0]) { d[0] = nd; r[0] = nr; }
 }
 
+// The distances of RT 16-row tiles x SNAP_NT 16-centre tiles at once, with
+// gemm_tile's loads and MFMA sequence (k blocks of 4 LK elements, lane group g
+// holding elements g LK .. g LK + LK - 1 of a block, STEPS MFMAs per block in
+// element order) but each centre fragment loaded once for the RT row tiles
+// instead of once per tile.  Per output element the MFMA sequence is
+// gemm_tile's, so the values are bit-identical to a one-tile gemm_tile call at
+// the same row and column offsets (the resolver's rescans rely on that).
+template <typename TC, int RT>
+__device__ __forceinline__ void snap_tile_rt(const TC* __restrict__ P, int dim, int64_t M, int64_t row0,
+                                             const TC* __restrict__ Zc, int k, int col0,
+                                             typename Mfma<TC>::acc (&acc)[RT][SNAP_NT]) {
+  constexpr int LK = TileK<TC>::LK;
+  constexpr int KPL = Mfma<TC>::KPL;
+  constexpr int STEPS = LK / KPL;
+  constexpr int NT = SNAP_NT;
+  constexpr bool PREFETCH = false;  // two waves per SIMD hide the load latency instead
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  const TC* xp[RT];
+  bool xok[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int64_t row = row0 + 16 * rt + r;
+    xok[rt] = row < M;
+    xp[rt] = P + (xok[rt] ? row : 0) * dim;
+  }
+  const TC* yp[NT];
+  bool yok[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int c = col0 + 16 * t + r;
+    yok[t] = c < k;
+    yp[t] = Zc + (int64_t)(yok[t] ? c : 0) * dim;
+  }
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[rt][t] = Mfma<TC>::zero();
+  const bool vec = (dim % LK) == 0 && (((uintptr_t)P | (uintptr_t)Zc) & 15) == 0;
+  auto fetch = [&](int kb, TC (&xv)[RT][LK], TC (&yv)[NT][LK]) {
+    const int kk = kb + g * LK;
+    if (vec && kb + 4 * LK <= dim) {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) tile_run_vec<TC, LK>(xp[rt], kk, xok[rt], xv[rt]);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) tile_run_vec<TC, LK>(yp[t], kk, yok[t], yv[t]);
+    } else {
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) tile_run_elem<TC, LK>(xp[rt], kk, dim, xok[rt], xv[rt]);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) tile_run_elem<TC, LK>(yp[t], kk, dim, yok[t], yv[t]);
+    }
+  };
+  auto compute = [&](const TC (&xv)[RT][LK], const TC (&yv)[NT][LK]) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int s2 = 0; s2 < STEPS; ++s2) {
+          TC as_[KPL], bs_[KPL];
+#pragma unroll
+          for (int e = 0; e < KPL; ++e) { as_[e] = xv[rt][s2 * KPL + e]; bs_[e] = yv[t][s2 * KPL + e]; }
+          acc[rt][t] = Mfma<TC>::mma(FragPack<TC, KPL>::get(as_, 0), FragPack<TC, KPL>::get(bs_, 0), acc[rt][t]);
+        }
+  };
+  TC xv[RT][LK], yv[NT][LK];
+  if constexpr (PREFETCH) {
+    if (dim > 0) fetch(0, xv, yv);
+    for (int kb = 0; kb < dim; kb += 4 * LK) {
+      TC xn[RT][LK], yn[NT][LK];
+      const bool more = kb + 4 * LK < dim;
+      if (more) fetch(kb + 4 * LK, xn, yn);
+      compute(xv, yv);
+      if (more) {
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+          for (int e = 0; e < LK; ++e) xv[rt][e] = xn[rt][e];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int e = 0; e < LK; ++e) yv[t][e] = yn[t][e];
+      }
+    }
+  } else {
+    for (int kb = 0; kb < dim; kb += 4 * LK) {
+      fetch(kb, xv, yv);
+      compute(xv, yv);
+    }
+  }
+}
+
 // Per block of rows_per_block consecutive rows and per centre: the SNAP_T
 // nearest rows, sorted by (distance, row).  Wave w takes the 64-centre chunks
-// w, w + 4, ... (lane = centre) and walks the block's rows in 16-row tiles:
-// it forms the tile's distances (gemm_tile over the chunk's 4 column tiles)
-// into its own LDS tile, then each lane inserts its centre's 16 distances in
-// row order.  One list per (block, centre), so each list fills once; no
+// w, w + 4, ... (lane = centre) and walks the block's rows in groups of SRT
+// 16-row tiles: it forms the group's distances (snap_tile_rt over the chunk's
+// 4 column tiles, each centre fragment loaded once per group), then, tile by
+// tile through its own LDS tile, each lane inserts its centre's 16 distances
+// in row order.  One list per (block, centre), so each list fills once; no
 // barrier across waves.  A list holding fewer than SNAP_T rows means every
 // other row of the block is at +inf.  Rows of norm 0 are left out (+inf): they
 // form one class of equal distance to every centre, which the resolver handles
@@ -881,9 +974,9 @@ __global__ __launch_bounds__(256) void snap_topt_kernel(int64_t rows, int dim, i
                                                         const double* __restrict__ pnorm, double* __restrict__ cand_d,
                                                         int32_t* __restrict__ cand_r) {
   typedef typename Mfma<TC>::acc AccV;
-  typedef typename NormT<TC>::type NrmT;
+  constexpr int SRT = 2;  // row tiles sharing each centre fragment load
   constexpr int LDD = SNAP_CC + 1;
-  __shared__ double sm_d[4][16 * LDD];  // per wave: 16 rows x 64 centres
+  __shared__ double sm_d[4][16 * SRT * LDD];  // per wave: 16 SRT rows x 64 centres
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, c16 = lane & 15;
   const int64_t rbeg = (int64_t)blockIdx.x * rows_per_block;
@@ -896,26 +989,30 @@ __global__ __launch_bounds__(256) void snap_topt_kernel(int64_t rows, int dim, i
 #pragma unroll
     for (int q = 0; q < SNAP_T; ++q) { td[q] = __builtin_huge_val(); tr[q] = 0x7fffffff; }
     const int myc = cw + lane;  // centre tracked by this lane
-    for (int64_t row0 = rbeg; row0 < rend; row0 += 16) {
-      AccV acc[SNAP_NT];
-      NrmT xs, ys[SNAP_NT];
-      gemm_tile<TC, TC, SNAP_NT, false>(P, dim, rend, row0, Zc, dim, nullptr, k, cw, nullptr, dim, acc, xs, ys);
+    for (int64_t row0 = rbeg; row0 < rend; row0 += 16 * SRT) {
+      {
+        AccV acc[SRT][SNAP_NT];
+        snap_tile_rt<TC, SRT>(P, dim, rend, row0, Zc, k, cw, acc);
 #pragma unroll
-      for (int t = 0; t < SNAP_NT; ++t) {
-        const int cl = t * 16 + c16;
-        const int col = cw + cl;
+        for (int rt = 0; rt < SRT; ++rt)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int rl = out_row<TC>(g, i);
-          const int64_t row = row0 + rl;
-          double d = __builtin_huge_val();
-          if (row < rend && col < k && pnorm[row] != 0.0) d = snap_dist(pnorm[row], znorm[col], (double)acc[t][i]);
-          sd[rl * LDD + cl] = d;
-        }
+          for (int t = 0; t < SNAP_NT; ++t) {
+            const int cl = t * 16 + c16;
+            const int col = cw + cl;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int rl = 16 * rt + out_row<TC>(g, i);
+              const int64_t row = row0 + rl;
+              double d = __builtin_huge_val();
+              if (row < rend && col < k && pnorm[row] != 0.0)
+                d = snap_dist(pnorm[row], znorm[col], (double)acc[rt][t][i]);
+              sd[rl * LDD + cl] = d;
+            }
+          }
       }
       wave_lds_sync();
       if (myc < k) {
-        for (int q = 0; q < 16; ++q) {
+        for (int q = 0; q < 16 * SRT; ++q) {
           const int64_t row = row0 + q;
           if (row >= rend) break;
           topt_insert<double>(td, tr, sd[q * LDD + lane], (int)row);
