@@ -81,6 +81,8 @@ def parse():
                          "traffic for calibrating rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--stream", action="store_true", help="only the serving stream of uneven requests")
     ap.add_argument("--sweep", action="store_true", help="only the sampling-rate comparison of the linear-cost methods")
+    ap.add_argument("--sketch-batch", action="store_true",
+                    help="only: same-shape sketches one by one on one stream against cabs_sketch_batch")
     ap.add_argument("--sweep-matrices", default="scene,hubble,movie,news")
     ap.add_argument("--sweep-rates", default="0.01,0.02,0.05,0.10")
     ap.add_argument("--sweep-repeats", type=int, default=20)
@@ -91,6 +93,8 @@ def parse():
     ap.add_argument("--stream-fracs", default="0.25,0.5,0.75,0.9",
                     help="offered load points as fractions of the measured closed-loop maximum")
     ap.add_argument("--stream-compute", default="bf16")
+    ap.add_argument("--stream-group", type=int, default=1,
+                    help="same-shape requests admitted together share their SVD launches, up to this many (1: off)")
     return ap.parse_args()
 
 
@@ -306,15 +310,18 @@ def run_stream(api, args, n_req, quiet=False) -> dict:
         kk = min(256, mat.spec.m, mat.spec.n)
         need = max(need, api.workspace_bytes(mat, api.make_params(kk, kk, kk, kk, kmeans_iters=iters, compute=comp)))
     srv = api.Server(0, hbm_budget_bytes=S * (need + (1 << 20)), max_slots=S)
+    srv.set_group(args.stream_group)
 
-    def drive(ids, arrivals):
+    def drive(ids, arrivals, burst=False):
         live, lat = {}, []
         nxt, n = 0, len(ids)
         t0 = time.perf_counter()
         last = 0.0
         while nxt < n or live:
             now = time.perf_counter() - t0
-            while nxt < n and ((arrivals is None and len(live) < S) or (arrivals is not None and arrivals[nxt] <= now)):
+            quota = (S if not live else 0) if burst else S - len(live)  # closed loop: refill; bursts: S at once
+            while nxt < n and ((arrivals is None and quota > 0) or (arrivals is not None and arrivals[nxt] <= now)):
+                quota -= 1
                 mat, prm = params(ids[nxt])
                 out = api.alloc_result(mat, prm)
                 lag = 0.0 if arrivals is None else (time.perf_counter() - t0) - arrivals[nxt]
@@ -337,6 +344,11 @@ def run_stream(api, args, n_req, quiet=False) -> dict:
         closed = {"sketches_per_s": lam, "p50_ms": float(np.percentile(lat, 50)),
                   "p99_ms": float(np.percentile(lat, 99))}
         log(f"stream: closed loop {lam:.1f} sketches/s")
+        # bursts: S requests submitted together, the next burst when all have finished
+        lat_b, span_b = drive(list(range(n_req)), None, burst=True)
+        bursts = {"sketches_per_s": n_req / span_b, "p50_ms": float(np.percentile(lat_b, 50)),
+                  "p99_ms": float(np.percentile(lat_b, 99))}
+        log(f"stream: bursts of {S}: {n_req / span_b:.1f} sketches/s")
         points = []
         for f in [float(x) for x in args.stream_fracs.split(",") if x]:
             rng = np.random.default_rng(1)
@@ -351,10 +363,10 @@ def run_stream(api, args, n_req, quiet=False) -> dict:
     kinds = [pool[i % P].spec.kind for i in range(n_req)]
     res = {"workload": "uneven requests: m, n log-uniform in [1e3, 5e5], low-rank + noise (rank 16-256) or RBF "
                        "(d = 32, 10-100 clusters), k in {16, 32, 64, 128, 256}, c = 5, sketch only",
-           "dtype": comp, "requests": n_req, "matrix_pool": P, "slots": S,
+           "dtype": comp, "requests": n_req, "matrix_pool": P, "slots": S, "group_max": args.stream_group,
            "pool_shapes": [[int(m.spec.m), int(m.spec.n), m.spec.kind] for m in pool],
            "lowrank_share": kinds.count("lowrank") / n_req, "pool_build_s": build_s,
-           "closed_loop": closed, "poisson": points}
+           "closed_loop": closed, "bursts": bursts, "poisson": points}
     del pool
     torch.cuda.empty_cache()
     return res
@@ -485,6 +497,42 @@ def rate_sweep(api, args) -> dict:
             "repeats": args.sweep_repeats, "data": "synthetic stand-ins for Table 1's matrices", "rows": rows}
 
 
+def sketch_batch_compare(api, args) -> dict:
+    """Four same-shape requests (uneven m, n from the request-stream recipe, BF16, c = 5) on one stream:
+    cabs_sketch four times against one cabs_sketch_batch, which shares each SVD launch."""
+    import torch
+
+    import workloads
+    rows = []
+    for k in (32, 64, 128, 256):
+        recs = workloads.request_stream(n_requests=4, qps=1e3, seed=21, m_range=(5_000, 60_000), ks=(k,))
+        mats = [api.DeviceMatrix(workloads.request_matrix(r), storage="f32") for r in recs]
+        prms = [api.make_params(k, k, k, k, kmeans_iters=5, compute="bf16", seed=r["seed"]) for r in recs]
+        outs = [api.alloc_result(m, p) for m, p in zip(mats, prms)]
+        wss = [torch.empty(api.workspace_bytes(m, p), dtype=torch.uint8, device="cuda") for m, p in zip(mats, prms)]
+
+        def one_by_one():
+            for m, p, o, w in zip(mats, prms, outs, wss):
+                api.sketch(m, p, ws=w, out=o)
+
+        def batched():
+            api.sketch_batch(mats, prms)
+
+        res = {}
+        for name, fn in (("one_by_one", one_by_one), ("batched", batched)):
+            for _ in range(2):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                fn()
+            torch.cuda.synchronize()
+            res[name] = 1e3 * (time.perf_counter() - t0) / (4 * args.steps)
+        rows.append({"k": k, "ms_per_sketch_one_by_one": res["one_by_one"], "ms_per_sketch_batched": res["batched"]})
+        log(f"k = {k}: {res['one_by_one']:.2f} ms per sketch one by one, {res['batched']:.2f} ms batched")
+    return {"metric": "ms per sketch, four same-shape BF16 requests on one stream", "rows": rows}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -501,6 +549,9 @@ def main():
     torch.cuda.set_device(0)
     if args.sweep:
         print(json.dumps(rate_sweep(api, args)), flush=True)
+        return
+    if args.sketch_batch:
+        print(json.dumps(sketch_batch_compare(api, args)), flush=True)
         return
     if args.stream:
         res = run_stream(api, args, args.stream_requests)

@@ -223,6 +223,18 @@ size_t cabs_workspace_bytes(const cabs_matrix* mat, const cabs_params* prm);
 cabs_status cabs_sketch(const cabs_matrix* mat, const cabs_params* prm, void* ws, size_t ws_bytes,
                         cabs_result* out, void* stream);
 
+/* cabs_sketch on `count` (1..4) requests of the same shape at once: equal
+ * sample sizes, compute precision, orthogonalize and follow_up, and (for
+ * count > 1) no factor form.  The requests' kernels run one after another on
+ * `stream`, except that each FP64 SVD of the sketch (Section 4.1's W and the
+ * orthogonalisation's) is one launch for all of them.  Request g has its own
+ * matrix mats[g], parameters prms[g] (seeds may differ), workspace ws[g] of
+ * ws_bytes[g] (cabs_workspace_bytes of that request) and outputs outs[g]; the
+ * results are bitwise those of cabs_sketch.  CABS_EINVAL for a count outside
+ * 1..4 or requests of different shapes; otherwise as cabs_sketch. */
+cabs_status cabs_sketch_batch(int32_t count, const cabs_matrix* mats, const cabs_params* prms, void* const* ws,
+                              const size_t* ws_bytes, cabs_result* outs, void* stream);
+
 /* Relative Frobenius error |A - C Umid R|_F / |A|_F (the paper's error metric,
  * Section 5) of a finished sketch.  n_samples = 0: exact, over all m*n entries;
  * otherwise over n_samples i.i.d. uniform entries drawn with replacement from
@@ -408,6 +420,19 @@ cabs_status cabs_poll(cabs_server* srv, uint64_t ticket, double* latency_s);
 
 /* Cancel a request that has not been admitted yet (CABS_EBUSY if it already runs). */
 cabs_status cabs_cancel(cabs_server* srv, uint64_t ticket);
+
+/* Requests admitted together whose sketches have the same shape (equal sample
+ * sizes, compute precision, orthogonalize and follow_up, no factor form) run
+ * as a group of up to group_max (1..4; default 1 = never): each request on
+ * its own slot stream, with each FP64 SVD of the sketch (Section 4.1's W, and
+ * the orthogonalisation's) batched into one launch for the whole group, the
+ * members' streams joining before it and waiting for it after.  Results are
+ * bitwise those of the requests run alone.  Off by default because the
+ * separate SVD chains of concurrent slots already overlap on the device and
+ * the joins make each member wait for the slowest (measured: 4 % fewer
+ * sketches/s on the uneven request stream).  CABS_EINVAL for a size outside
+ * 1..4. */
+cabs_status cabs_server_set_group(cabs_server* srv, int32_t group_max);
 
 /* Block until every submitted request has completed. */
 cabs_status cabs_server_drain(cabs_server* srv);

@@ -75,6 +75,8 @@ _SIGS = {
     "cabs_last_error": (C.c_char_p, []),
     "cabs_workspace_bytes": (C.c_size_t, [C.POINTER(CabsMatrix), C.POINTER(CabsParams)]),
     "cabs_sketch": (C.c_int, [C.POINTER(CabsMatrix), C.POINTER(CabsParams), _P, C.c_size_t, C.POINTER(CabsResult), _P]),
+    "cabs_sketch_batch": (C.c_int, [C.c_int32, C.POINTER(CabsMatrix), C.POINTER(CabsParams), C.POINTER(C.c_void_p),
+                                    C.POINTER(C.c_size_t), C.POINTER(CabsResult), _P]),
     "cabs_error_workspace_bytes": (C.c_size_t, [C.POINTER(CabsMatrix), C.POINTER(CabsParams), C.c_int64]),
     "cabs_error": (C.c_int, [C.POINTER(CabsMatrix), C.POINTER(CabsParams), C.POINTER(CabsResult), C.c_int64,
                              C.c_uint64, _P, C.c_size_t, _P, _P]),
@@ -100,6 +102,7 @@ _SIGS = {
                               C.c_int64, C.c_uint64, _P, _P, C.POINTER(C.c_uint64)]),
     "cabs_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(C.c_double)]),
     "cabs_cancel": (C.c_int, [_P, C.c_uint64]),
+    "cabs_server_set_group": (C.c_int, [_P, C.c_int32]),
     "cabs_server_drain": (C.c_int, [_P]),
     "cabs_server_destroy": (None, [_P]),
 }

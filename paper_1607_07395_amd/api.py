@@ -200,6 +200,22 @@ def sketch(mat: DeviceMatrix, prm: F.CabsParams, ws: Optional[torch.Tensor] = No
     return out
 
 
+def sketch_batch(mats, prms, stream=None):
+    """cabs_sketch_batch: 1-4 same-shape sketches with their SVDs batched; returns their results."""
+    n = len(mats)
+    M = (F.CabsMatrix * n)(*[m.desc for m in mats])
+    P = (F.CabsParams * n)(*prms)
+    outs = [alloc_result(m, p) for m, p in zip(mats, prms)]
+    R = (F.CabsResult * n)(*[o.struct for o in outs])
+    wss = [_dev_alloc(workspace_bytes(m, p), m.device) for m, p in zip(mats, prms)]
+    W = (C.c_void_p * n)(*[w.data_ptr() for w in wss])
+    B = (C.c_size_t * n)(*[w.numel() for w in wss])
+    F.check(F.lib().cabs_sketch_batch(n, M, P, W, B, R, _stream(stream)), "cabs_sketch_batch")
+    for o, w in zip(outs, wss):
+        o._ws = w
+    return outs
+
+
 def error(mat: DeviceMatrix, prm: F.CabsParams, res: SketchResult, n_samples: int = 0, seed: int = 0,
           ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
     """cabs_error: returns a device tensor [sum sq residual, sum sq entries, ratio]."""
@@ -451,6 +467,11 @@ class Server:
 
     def cancel(self, ticket: int) -> int:
         return F.lib().cabs_cancel(self.h, ticket)
+
+    def set_group(self, group_max: int) -> None:
+        """cabs_server_set_group: same-shape requests admitted together share their SVD launches
+        (1..4 per group; 1 turns it off)."""
+        F.check(F.lib().cabs_server_set_group(self.h, int(group_max)), "cabs_server_set_group")
 
     def drain(self):
         F.check(F.lib().cabs_server_drain(self.h), "cabs_server_drain")

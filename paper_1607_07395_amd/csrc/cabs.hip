@@ -23,9 +23,11 @@
 #include <algorithm>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/cabs.h"
 #include "common.hpp"
+#include "group.hpp"
 #include "kernels.hpp"
 
 using namespace cabs;
@@ -558,19 +560,76 @@ static MatView view_of(const cabs_matrix* mat) {
   return v;
 }
 
-// One sketching round on sampled C (m x kc), R^T (n x kr), W (kr x kc, FP64).
-// Computes the SVD of W, the norms and scalings; optionally the extrapolated
-// vectors C^, R^ and the orthogonalised embedding maps.
-static cabs_status run_round(const Plan& pl, RoundWs& R, int kr, int kc, const void* C, const void* Rt,
-                             const cabs_params* prm, bool vectors, bool ortho, double* diag, int slot_rank,
-                             int slot_sig, hipStream_t st) {
+// ---------------------------------------------------------------------------
+// The sketch as a sequence of phases between its FP64 SVDs.  advance() runs a
+// request's kernels up to its next SVD and describes that SVD (SvdJob); the
+// caller runs it (cabs_sketch: at once; a server group: one batched launch
+// for several same-shape requests, each item in its own workspace, so the
+// results are the same bits either way) and calls advance() again.
+//
+// One sketching round on sampled C (m x kc), R^T (n x kr), W (kr x kc, FP64):
+//   SVD of W | norms and scalings (sketch_vec); with `ortho` the Grams and
+//   either pivoted Cholesky factors or (p > PCHOL_MAXP) | the eigen-
+//   decompositions of both Grams | then K | the SVD of K | the embedding maps.
+// ---------------------------------------------------------------------------
+struct SvdJob {
+  int n = 0, rows = 0, cols = 0;  // n items (0: no SVD, the sketch has finished)
+  const double* A[2];
+  double *U[2], *S[2], *V[2], *W[2];
+};
+
+enum Phase {
+  PH_START = 0,
+  PH_R1_AFTER_W,     // round 1: after the SVD of W
+  PH_R1_AFTER_EIG,   // round 1: after the Grams' eigen-decompositions
+  PH_R1_AFTER_K,     // round 1: after the SVD of K
+  PH_R2_AFTER_W,
+  PH_R2_AFTER_EIG,
+  PH_R2_AFTER_K,
+  PH_DONE
+};
+
+struct SketchRun {
+  const cabs_matrix* mat;
+  const cabs_params* prm;
+  cabs_result* out;
+  Plan pl;
+  SketchWs S;
+  MatView mv;
+  double* diag;
+  hipStream_t st;
+  bool counted;
+  unsigned long long* ecnt;
+  int phase;
+};
+
+static void svd_job_one(SvdJob& j, int rows, int cols, const double* A, double* U, double* S, double* V, void* ws) {
+  j.n = 1;
+  j.rows = rows;
+  j.cols = cols;
+  j.A[0] = A;
+  j.U[0] = U;
+  j.S[0] = S;
+  j.V[0] = V;
+  j.W[0] = (double*)ws;
+}
+
+// Round part after the SVD of W: C^ = C V_w, R^ = R^T U_w with norms, the
+// kept components and scalings; with `ortho` the Grams, then either the
+// pivoted Cholesky factors and K (next: the SVD of K) or the eigen-
+// decompositions of both Grams (next).  `next` receives the following SVD.
+static cabs_status round_after_w(const SketchRun& c, RoundWs& R, int kr, int kc, const void* C, const void* Rt,
+                                 bool vectors, bool ortho, int slot_rank, int slot_sig, SvdJob& next, bool& eig) {
+  const Plan& pl = c.pl;
+  hipStream_t st = c.st;
   const int p = std::min(kr, kc);
-  HIP_TRY(launch_svd(1, kr, kc, R.W, 0, R.Uw, 0, R.Sw, 0, R.Vw, 0, R.svd_ws, st));
-  // C^ = C V_w, R^ = R^T U_w, with column norms
+  next.n = 0;
+  eig = false;
   HIP_TRY(launch_tsgemm(pl.m, kc, p, pl.prec, C, R.Vw, vectors ? R.Ch : nullptr, R.nc2, nullptr, R.ts_ws, st));
   HIP_TRY(launch_tsgemm(pl.n, kr, p, pl.prec, Rt, R.Uw, vectors ? R.Rh : nullptr, R.nr2, nullptr, R.ts_ws, st));
   hipLaunchKernelGGL(sketch_vec_kernel, dim3(1), dim3(1024), 0, st, p, kr, kc, (double)pl.m, (double)pl.n, R.Sw, R.nc2,
-                     R.nr2, prm->pinv_rtol, prm->sketch_kind, R.invc, R.invr, R.sk, R.dk, diag, slot_rank, slot_sig);
+                     R.nr2, c.prm->pinv_rtol, c.prm->sketch_kind, R.invc, R.invr, R.sk, R.dk, c.diag, slot_rank,
+                     slot_sig);
   HIP_TRY(hipGetLastError());
   if (!vectors) return CABS_OK;
   if (!ortho) {
@@ -590,14 +649,48 @@ static cabs_status run_round(const Plan& pl, RoundWs& R, int kr, int kc, const v
   hipLaunchKernelGGL(scale2_kernel, dim3(gb), dim3(256), 0, st, p, R.Gs2 + pp, R.invr, R.invr, R.G2 + pp);
   if (p <= PCHOL_MAXP) {
     // Pivoted Cholesky G = R^T R of both Grams (rank-revealing: pivots <= p eps of the unit diagonal
-    // stop it), K = R_u diag(S) R_v^T, SVD(K) = U_s S_1 V_s^T.  Since K V_s = U_s S_1,
-    // R_u^-1 U_s = diag(S) R_v^T V_s S_1^-1, so without any triangular solve
-    //   M_u = diag(invc S) R_v^T V_s S_1^(-1/2),  M_v = diag(invr S) R_u^T U_s S_1^(-1/2)
-    // map C^ and R^ to P = U' S_1^(1/2), Q = V' S_1^(1/2) (components with S_1 <= p eps S_1[0] dropped).
+    // stop it), K = R_u diag(S) R_v^T, then the SVD of K (next).
     const double eps = 2.220446049250313e-16;
     HIP_TRY(launch_pchol(2, p, R.G2, pp, (double)p * eps, R.E2V, pp, st));
     HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, false, R.E2V + pp, p, true, nullptr, R.sk, nullptr, R.K, p, st));
-    HIP_TRY(launch_svd(1, p, p, R.K, 0, R.Us, 0, R.S1, 0, R.Vs, 0, R.svd_ws, st));
+    svd_job_one(next, p, p, R.K, R.Us, R.S1, R.Vs, R.svd_ws);
+    return CABS_OK;
+  }
+  // Eigen-decompositions G = E Lambda E^T (SVD of a PSD matrix) of both Grams (next, two items).
+  eig = true;
+  next.n = 2;
+  next.rows = next.cols = p;
+  const size_t wsd = svd_ws_item_doubles(p, p);
+  for (int i = 0; i < 2; ++i) {
+    next.A[i] = R.G2 + i * pp;
+    next.U[i] = R.E2U + i * pp;
+    next.S[i] = R.E2S + i * p;
+    next.V[i] = R.E2V + i * pp;
+    next.W[i] = (double*)R.svd_ws + i * wsd;
+  }
+  return CABS_OK;
+}
+
+// Eigen route, after the Grams' eigen-decompositions: K = T_u^T diag(S) T_v (next: its SVD).
+static cabs_status round_after_eig(const SketchRun& c, RoundWs& R, int p, SvdJob& next) {
+  hipStream_t st = c.st;
+  hipLaunchKernelGGL(eig_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.E2S, R.fpos, R.fneg);
+  hipLaunchKernelGGL(eig_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.E2S + p, R.fpos + p, R.fneg + p);
+  // T_u = E_u Lambda_u^(1/2);  K = T_u^T diag(S) T_v
+  const size_t pp = (size_t)p * p;
+  HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, true, R.E2V + pp, p, false, R.fpos, R.sk, R.fpos + p, R.K, p, st));
+  svd_job_one(next, p, p, R.K, R.Us, R.S1, R.Vs, R.svd_ws);
+  return CABS_OK;
+}
+
+// After the SVD of K: the embedding maps M_u, M_v.
+static cabs_status round_after_k(const SketchRun& c, RoundWs& R, int p, bool eig) {
+  hipStream_t st = c.st;
+  const size_t pp = (size_t)p * p;
+  if (!eig) {
+    // Since K V_s = U_s S_1, R_u^-1 U_s = diag(S) R_v^T V_s S_1^-1, so without any triangular solve
+    //   M_u = diag(invc S) R_v^T V_s S_1^(-1/2),  M_v = diag(invr S) R_u^T U_s S_1^(-1/2)
+    // map C^ and R^ to P = U' S_1^(1/2), Q = V' S_1^(1/2) (components with S_1 <= p eps S_1[0] dropped).
     hipLaunchKernelGGL(rsqrt_trunc_kernel, dim3(1), dim3(1024), 0, st, p, R.S1, R.sq);
     hipLaunchKernelGGL(mul_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.invc, R.sk, R.fpos);
     hipLaunchKernelGGL(mul_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.invr, R.sk, R.fpos + p);
@@ -606,13 +699,6 @@ static cabs_status run_round(const Plan& pl, RoundWs& R, int kr, int kc, const v
     HIP_TRY(hipGetLastError());
     return CABS_OK;
   }
-  // Eigen-decompositions G = E Lambda E^T (SVD of a PSD matrix), both in one launch.
-  HIP_TRY(launch_svd(2, p, p, R.G2, pp, R.E2U, pp, R.E2S, p, R.E2V, pp, R.svd_ws, st));
-  hipLaunchKernelGGL(eig_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.E2S, R.fpos, R.fneg);
-  hipLaunchKernelGGL(eig_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.E2S + p, R.fpos + p, R.fneg + p);
-  // T_u = E_u Lambda_u^(1/2);  K = T_u^T diag(S) T_v
-  HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, true, R.E2V + pp, p, false, R.fpos, R.sk, R.fpos + p, R.K, p, st));
-  HIP_TRY(launch_svd(1, p, p, R.K, 0, R.Us, 0, R.S1, 0, R.Vs, 0, R.svd_ws, st));
   hipLaunchKernelGGL(sqrt_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.S1, R.sq);
   // M_u = diag(invc) E_u diag(Lambda_u^-1/2) U_s diag(S_1^1/2), M_v likewise with V_s.
   HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, false, R.Us, p, false, R.invc, R.fneg, R.sq, R.Mu, p, st));
@@ -621,19 +707,8 @@ static cabs_status run_round(const Plan& pl, RoundWs& R, int kr, int kc, const v
   return CABS_OK;
 }
 
-}  // namespace
-
-// ---------------------------------------------------------------------------
-// C ABI
-// ---------------------------------------------------------------------------
-extern "C" size_t cabs_workspace_bytes(const cabs_matrix* mat, const cabs_params* prm) {
-  if (check_params(mat, prm) != CABS_OK) return 0;
-  SketchWs S;
-  return plan_sketch(nullptr, make_plan(mat, prm), prm, S);
-}
-
-extern "C" cabs_status cabs_sketch(const cabs_matrix* mat, const cabs_params* prm, void* ws, size_t ws_bytes,
-                                   cabs_result* out, void* stream) {
+static cabs_status sketch_begin(SketchRun& c, const cabs_matrix* mat, const cabs_params* prm, void* ws,
+                                size_t ws_bytes, cabs_result* out, hipStream_t st) {
   cabs_status s = check_params(mat, prm);
   if (s != CABS_OK) return s;
   if (!out || !out->idx_r || !out->idx_c || !out->C || !out->Rt || !out->Umid)
@@ -641,120 +716,124 @@ extern "C" cabs_status cabs_sketch(const cabs_matrix* mat, const cabs_params* pr
   if (prm->want_factors && (!out->Uf || !out->S || !out->Vf))
     return fail(CABS_EINVAL, "want_factors needs Uf, S, Vf");
   if (!ws || ((uintptr_t)ws & 255)) return fail(CABS_EINVAL, "workspace must be non-null and 256-byte aligned");
-  const Plan pl = make_plan(mat, prm);
-  SketchWs S;
-  const size_t need = plan_sketch(nullptr, pl, prm, S);
+  c.mat = mat;
+  c.prm = prm;
+  c.out = out;
+  c.pl = make_plan(mat, prm);
+  const size_t need = plan_sketch(nullptr, c.pl, prm, c.S);
   if (ws_bytes < need) return fail(CABS_ENOMEM, "workspace too small: %zu < %zu bytes", ws_bytes, need);
-  plan_sketch(ws, pl, prm, S);
-  hipStream_t st = (hipStream_t)stream;
-  const MatView mv = view_of(mat);
-  double* diag = out->diag ? out->diag : S.diag;
-  const int e = pl.p1, ep = pl.ep;
+  plan_sketch(ws, c.pl, prm, c.S);
+  c.st = st;
+  c.mv = view_of(mat);
+  c.diag = out->diag ? out->diag : c.S.diag;
+  c.counted = (prm->flags & CABS_FLAG_COUNT_ENTRIES) != 0;
+  c.ecnt = c.counted ? c.S.entries : nullptr;
+  c.phase = PH_START;
+  return CABS_OK;
+}
 
-  const bool counted = (prm->flags & CABS_FLAG_COUNT_ENTRIES) != 0;
-  unsigned long long* ecnt = counted ? S.entries : nullptr;
-  hipLaunchKernelGGL(diag_init_kernel, dim3(1), dim3(64), 0, st, diag, S.entries, counted ? 1 : 0);
+// Steps 6-7 (embeddings, weights, follow-up sampling) after the pilot round.
+static cabs_status sketch_middle(SketchRun& c) {
+  const Plan& pl = c.pl;
+  SketchWs& S = c.S;
+  const cabs_params* prm = c.prm;
+  cabs_result* out = c.out;
+  hipStream_t st = c.st;
+  double* diag = c.diag;
+  const int e = pl.p1, ep = pl.ep;
+  int64_t* Ir = out->pilot_r ? out->pilot_r : S.Ir;
+  int64_t* Ic = out->pilot_c ? out->pilot_c : S.Ic;
+  // 6: embeddings and weights
+  // When p1 elements are not a whole number of 16-byte runs (FP32: p1 not a multiple of 4, 16-bit:
+  // of 8) the embeddings get ep - p1 zero columns, so that their rows are whole runs for the k-means
+  // kernels; zero columns add exact zeros to every distance, norm and centre.
+  const double* Mu = S.r1.Mu;
+  const double* Mv = S.r1.Mv;
+  void* ts6 = S.r1.ts_ws;
+  if (ep != e) {
+    const unsigned gp = (unsigned)ceil_div((int64_t)e * ep, 256);
+    hipLaunchKernelGGL(pad_cols_kernel, dim3(gp), dim3(256), 0, st, e, e, ep, S.r1.Mu, S.MuP);
+    hipLaunchKernelGGL(pad_cols_kernel, dim3(gp), dim3(256), 0, st, e, e, ep, S.r1.Mv, S.MvP);
+    Mu = S.MuP;
+    Mv = S.MvP;
+    ts6 = S.ts6;
+  }
+  HIP_TRY(launch_tsgemm(pl.m, e, ep, pl.prec, S.r1.Ch, Mu, S.P, nullptr, S.rowsqP, ts6, st));
+  HIP_TRY(launch_tsgemm(pl.n, e, ep, pl.prec, S.r1.Rh, Mv, S.Q, nullptr, S.rowsqQ, ts6, st));
+  hipLaunchKernelGGL(weights_kernel, dim3((unsigned)ceil_div(pl.m, 256)), dim3(256), 0, st, pl.m, S.rowsqP,
+                     prm->weight_kind, prm->weight_param, S.wr);
+  hipLaunchKernelGGL(weights_kernel, dim3((unsigned)ceil_div(pl.n, 256)), dim3(256), 0, st, pl.n, S.rowsqQ,
+                     prm->weight_kind, prm->weight_param, S.wc);
   HIP_TRY(hipGetLastError());
 
-  if (prm->follow_up == CABS_FOLLOW_PILOT) {
-    // The pilot sketch alone: the pilot sample is the output sample, and step 8
-    // below is the pilot round (steps 1-3 of Algorithm 2).
-    HIP_TRY(launch_sample(pl.m, pl.kr1, prm->seed, STREAM_PILOT_ROWS, out->idx_r, st));
-    HIP_TRY(launch_sample(pl.n, pl.kc1, prm->seed, STREAM_PILOT_COLS, out->idx_c, st));
-    if (out->pilot_r) HIP_TRY(launch_sample(pl.m, pl.kr1, prm->seed, STREAM_PILOT_ROWS, out->pilot_r, st));
-    if (out->pilot_c) HIP_TRY(launch_sample(pl.n, pl.kc1, prm->seed, STREAM_PILOT_COLS, out->pilot_c, st));
-  } else {
-    // 1-2: pilot sampling and evaluation
-    int64_t* Ir = out->pilot_r ? out->pilot_r : S.Ir;
-    int64_t* Ic = out->pilot_c ? out->pilot_c : S.Ic;
-    HIP_TRY(launch_sample(pl.m, pl.kr1, prm->seed, STREAM_PILOT_ROWS, Ir, st));
-    HIP_TRY(launch_sample(pl.n, pl.kc1, prm->seed, STREAM_PILOT_COLS, Ic, st));
-    HIP_TRY(launch_eval(mv, false, Ic, pl.kc1, pl.prec, S.C, st, ecnt));
-    HIP_TRY(launch_eval(mv, true, Ir, pl.kr1, pl.prec, S.Rt, st, ecnt));
-    HIP_TRY(launch_gather_rows_f64(S.C, pl.prec, pl.kc1, Ir, pl.kr1, pl.kc1, S.r1.W, st));
-
-    // 3-5: pilot sketch and embedding maps
-    s = run_round(pl, S.r1, pl.kr1, pl.kc1, S.C, S.Rt, prm, true, prm->orthogonalize != 0, diag, CABS_DIAG_RANK_PILOT,
-                  CABS_DIAG_SIGMA1_PILOT, st);
-    if (s != CABS_OK) return s;
-
-    // 6: embeddings and weights
-    // When p1 elements are not a whole number of 16-byte runs (FP32: p1 not a multiple of 4, 16-bit:
-    // of 8) the embeddings get ep - p1 zero columns, so that their rows are whole runs for the k-means
-    // kernels; zero columns add exact zeros to every distance, norm and centre.
-    const double* Mu = S.r1.Mu;
-    const double* Mv = S.r1.Mv;
-    void* ts6 = S.r1.ts_ws;
-    if (ep != e) {
-      const unsigned gp = (unsigned)ceil_div((int64_t)e * ep, 256);
-      hipLaunchKernelGGL(pad_cols_kernel, dim3(gp), dim3(256), 0, st, e, e, ep, S.r1.Mu, S.MuP);
-      hipLaunchKernelGGL(pad_cols_kernel, dim3(gp), dim3(256), 0, st, e, e, ep, S.r1.Mv, S.MvP);
-      Mu = S.MuP;
-      Mv = S.MvP;
-      ts6 = S.ts6;
-    }
-    HIP_TRY(launch_tsgemm(pl.m, e, ep, pl.prec, S.r1.Ch, Mu, S.P, nullptr, S.rowsqP, ts6, st));
-    HIP_TRY(launch_tsgemm(pl.n, e, ep, pl.prec, S.r1.Rh, Mv, S.Q, nullptr, S.rowsqQ, ts6, st));
-    hipLaunchKernelGGL(weights_kernel, dim3((unsigned)ceil_div(pl.m, 256)), dim3(256), 0, st, pl.m, S.rowsqP,
-                       prm->weight_kind, prm->weight_param, S.wr);
-    hipLaunchKernelGGL(weights_kernel, dim3((unsigned)ceil_div(pl.n, 256)), dim3(256), 0, st, pl.n, S.rowsqQ,
-                       prm->weight_kind, prm->weight_param, S.wc);
+  // 7: follow-up sampling.  Hard-threshold variant (Section 5): the rows and
+  // columns with the largest weights.
+  if (prm->follow_up == CABS_FOLLOW_HARD) {
+    HIP_TRY(launch_select_topk(pl.m, S.wr, pl.kr2, out->idx_r, S.selr, st));
+    HIP_TRY(launch_select_topk(pl.n, S.wc, pl.kc2, out->idx_c, S.selc, st));
+  } else if (prm->follow_up == CABS_FOLLOW_LEVERAGE) {
+    // Leverage variant (Section 5): keys from the squared row norms of the factors behind P and Q
+    // (P = U' diag(s)^(1/2), s = the orthogonalised singular values, or the sketch's S without
+    // orthogonalisation), then the k largest keys.  The weights buffers hold the keys.
+    const double* sv = prm->orthogonalize ? S.r1.S1 : S.r1.sk;
+    hipLaunchKernelGGL(lev_inv_kernel, dim3(1), dim3(256), 0, st, e, sv, S.levinv);
     HIP_TRY(hipGetLastError());
-
-    // 7: follow-up sampling.  Hard-threshold variant (Section 5): the rows and
-    // columns with the largest weights.
-    if (prm->follow_up == CABS_FOLLOW_HARD) {
-      HIP_TRY(launch_select_topk(pl.m, S.wr, pl.kr2, out->idx_r, S.selr, st));
-      HIP_TRY(launch_select_topk(pl.n, S.wc, pl.kc2, out->idx_c, S.selc, st));
-    } else if (prm->follow_up == CABS_FOLLOW_LEVERAGE) {
-      // Leverage variant (Section 5): keys from the squared row norms of the factors behind P and Q
-      // (P = U' diag(s)^(1/2), s = the orthogonalised singular values, or the sketch's S without
-      // orthogonalisation), then the k largest keys.  The weights buffers hold the keys.
-      const double* sv = prm->orthogonalize ? S.r1.S1 : S.r1.sk;
-      hipLaunchKernelGGL(lev_inv_kernel, dim3(1), dim3(256), 0, st, e, sv, S.levinv);
-      HIP_TRY(hipGetLastError());
-      HIP_TRY(launch_lev_keys_any(pl.prec, pl.m, ep, e, S.P, S.levinv, prm->seed, STREAM_LEVERAGE_ROWS, S.wr, st));
-      HIP_TRY(launch_lev_keys_any(pl.prec, pl.n, ep, e, S.Q, S.levinv, prm->seed, STREAM_LEVERAGE_COLS, S.wc, st));
-      HIP_TRY(launch_select_topk(pl.m, S.wr, pl.kr2, out->idx_r, S.selr, st));
-      HIP_TRY(launch_select_topk(pl.n, S.wc, pl.kc2, out->idx_c, S.selc, st));
-    } else {
-      // Weighted k-means from the pilot sample, then snapping.
-      const int64_t* I0r = Ir;
-      const int64_t* I0c = Ic;
-      if (pl.kr2 > pl.kr1) {
-        HIP_TRY(launch_sample(pl.m, pl.kr2, prm->seed, STREAM_INIT_ROWS, S.Ir0, st));
-        I0r = S.Ir0;
-      }
-      if (pl.kc2 > pl.kc1) {
-        HIP_TRY(launch_sample(pl.n, pl.kc2, prm->seed, STREAM_INIT_COLS, S.Ic0, st));
-        I0c = S.Ic0;
-      }
-      HIP_TRY(launch_gather_rows_f64(S.P, pl.prec, ep, I0r, pl.kr2, ep, S.Z0r, st));
-      HIP_TRY(launch_gather_rows_f64(S.Q, pl.prec, ep, I0c, pl.kc2, ep, S.Z0c, st));
-      KMeansOut kr{S.Zr, nullptr, S.obj, diag + CABS_DIAG_TMAX_R, diag + CABS_DIAG_GAP_R, out->idx_r,
-                   diag + CABS_DIAG_SNAP_SCANS_R};
-      HIP_TRY(launch_kmeans(pl.m, ep, pl.kr2, pl.prec, S.P, S.wr, S.Z0r, prm->kmeans_iters, kr, S.kmr, st));
-      KMeansOut kc{S.Zc, nullptr, S.obj + 2, diag + CABS_DIAG_TMAX_C, diag + CABS_DIAG_GAP_C, out->idx_c,
-                   diag + CABS_DIAG_SNAP_SCANS_C};
-      HIP_TRY(launch_kmeans(pl.n, ep, pl.kc2, pl.prec, S.Q, S.wc, S.Z0c, prm->kmeans_iters, kc, S.kmc, st));
-      hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 0, diag + CABS_DIAG_ENC_R_PILOT);
-      hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 1, diag + CABS_DIAG_ENC_R_FINAL);
-      hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 2, diag + CABS_DIAG_ENC_C_PILOT);
-      hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 3, diag + CABS_DIAG_ENC_C_FINAL);
-      HIP_TRY(hipGetLastError());
+    HIP_TRY(launch_lev_keys_any(pl.prec, pl.m, ep, e, S.P, S.levinv, prm->seed, STREAM_LEVERAGE_ROWS, S.wr, st));
+    HIP_TRY(launch_lev_keys_any(pl.prec, pl.n, ep, e, S.Q, S.levinv, prm->seed, STREAM_LEVERAGE_COLS, S.wc, st));
+    HIP_TRY(launch_select_topk(pl.m, S.wr, pl.kr2, out->idx_r, S.selr, st));
+    HIP_TRY(launch_select_topk(pl.n, S.wc, pl.kc2, out->idx_c, S.selc, st));
+  } else {
+    // Weighted k-means from the pilot sample, then snapping.
+    const int64_t* I0r = Ir;
+    const int64_t* I0c = Ic;
+    if (pl.kr2 > pl.kr1) {
+      HIP_TRY(launch_sample(pl.m, pl.kr2, prm->seed, STREAM_INIT_ROWS, S.Ir0, st));
+      I0r = S.Ir0;
     }
-
+    if (pl.kc2 > pl.kc1) {
+      HIP_TRY(launch_sample(pl.n, pl.kc2, prm->seed, STREAM_INIT_COLS, S.Ic0, st));
+      I0c = S.Ic0;
+    }
+    HIP_TRY(launch_gather_rows_f64(S.P, pl.prec, ep, I0r, pl.kr2, ep, S.Z0r, st));
+    HIP_TRY(launch_gather_rows_f64(S.Q, pl.prec, ep, I0c, pl.kc2, ep, S.Z0c, st));
+    KMeansOut kr{S.Zr, nullptr, S.obj, diag + CABS_DIAG_TMAX_R, diag + CABS_DIAG_GAP_R, out->idx_r,
+                 diag + CABS_DIAG_SNAP_SCANS_R};
+    HIP_TRY(launch_kmeans(pl.m, ep, pl.kr2, pl.prec, S.P, S.wr, S.Z0r, prm->kmeans_iters, kr, S.kmr, st));
+    KMeansOut kc{S.Zc, nullptr, S.obj + 2, diag + CABS_DIAG_TMAX_C, diag + CABS_DIAG_GAP_C, out->idx_c,
+                 diag + CABS_DIAG_SNAP_SCANS_C};
+    HIP_TRY(launch_kmeans(pl.n, ep, pl.kc2, pl.prec, S.Q, S.wc, S.Z0c, prm->kmeans_iters, kc, S.kmc, st));
+    hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 0, diag + CABS_DIAG_ENC_R_PILOT);
+    hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 1, diag + CABS_DIAG_ENC_R_FINAL);
+    hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 2, diag + CABS_DIAG_ENC_C_PILOT);
+    hipLaunchKernelGGL(copy_slot_kernel, dim3(1), dim3(64), 0, st, S.obj + 3, diag + CABS_DIAG_ENC_C_FINAL);
+    HIP_TRY(hipGetLastError());
   }
+  return CABS_OK;
+}
 
-  // 8: follow-up evaluation and sketch
-  HIP_TRY(launch_eval(mv, false, out->idx_c, pl.kc2, pl.prec, out->C, st, ecnt));
-  HIP_TRY(launch_eval(mv, true, out->idx_r, pl.kr2, pl.prec, out->Rt, st, ecnt));
-  if (counted) hipLaunchKernelGGL(entries_out_kernel, dim3(1), dim3(64), 0, st, S.entries, diag);
-  HIP_TRY(launch_gather_rows_f64(out->C, pl.prec, pl.kc2, out->idx_r, pl.kr2, pl.kc2, S.r2.W, st));
+// Follow-up evaluation (step 8) up to W-bar: C-bar, R-bar^T and W-bar = C-bar(I-bar^r, :).
+static cabs_status sketch_followup_eval(SketchRun& c, SvdJob& next) {
+  const Plan& pl = c.pl;
+  cabs_result* out = c.out;
+  hipStream_t st = c.st;
+  HIP_TRY(launch_eval(c.mv, false, out->idx_c, pl.kc2, pl.prec, out->C, st, c.ecnt));
+  HIP_TRY(launch_eval(c.mv, true, out->idx_r, pl.kr2, pl.prec, out->Rt, st, c.ecnt));
+  if (c.counted) hipLaunchKernelGGL(entries_out_kernel, dim3(1), dim3(64), 0, st, c.S.entries, c.diag);
+  HIP_TRY(launch_gather_rows_f64(out->C, pl.prec, pl.kc2, out->idx_r, pl.kr2, pl.kc2, c.S.r2.W, st));
+  RoundWs& R = c.S.r2;
+  svd_job_one(next, pl.kr2, pl.kc2, R.W, R.Uw, R.Sw, R.Vw, R.svd_ws);
+  return CABS_OK;
+}
+
+// After the follow-up round: U_mid, the pilot-only diagnostics and the optional factor form (step 9).
+static cabs_status sketch_final(SketchRun& c) {
+  const Plan& pl = c.pl;
+  SketchWs& S = c.S;
+  const cabs_params* prm = c.prm;
+  cabs_result* out = c.out;
+  hipStream_t st = c.st;
+  double* diag = c.diag;
   const bool fac = prm->want_factors != 0;
-  s = run_round(pl, S.r2, pl.kr2, pl.kc2, out->C, out->Rt, prm, fac, fac, diag, CABS_DIAG_RANK_FINAL,
-                CABS_DIAG_SIGMA1_FINAL, st);
-  if (s != CABS_OK) return s;
   // Umid = V_w diag(D) U_w^T  (kc2 x kr2)
   HIP_TRY(launch_small_gemm(pl.kc2, pl.kr2, pl.p2, S.r2.Vw, pl.p2, false, S.r2.Uw, pl.p2, true, nullptr, S.r2.dk,
                             nullptr, out->Umid, pl.kr2, st));
@@ -814,6 +893,202 @@ extern "C" cabs_status cabs_sketch(const cabs_matrix* mat, const cabs_params* pr
   }
   HIP_TRY(hipGetLastError());
   return CABS_OK;
+}
+
+// Runs the sketch up to its next SVD (described in `job`) or to its end (job.n = 0).
+static cabs_status sketch_advance(SketchRun& c, SvdJob& job) {
+  const Plan& pl = c.pl;
+  SketchWs& S = c.S;
+  const cabs_params* prm = c.prm;
+  cabs_result* out = c.out;
+  hipStream_t st = c.st;
+  const bool ortho = prm->orthogonalize != 0, fac = prm->want_factors != 0;
+  job.n = 0;
+  cabs_status s = CABS_OK;
+  bool eig = false;
+  switch (c.phase) {
+    case PH_START: {
+      hipLaunchKernelGGL(diag_init_kernel, dim3(1), dim3(64), 0, st, c.diag, S.entries, c.counted ? 1 : 0);
+      HIP_TRY(hipGetLastError());
+      if (prm->follow_up == CABS_FOLLOW_PILOT) {
+        // The pilot sketch alone: the pilot sample is the output sample, and the follow-up
+        // round below is the pilot round (steps 1-3 of Algorithm 2).
+        HIP_TRY(launch_sample(pl.m, pl.kr1, prm->seed, STREAM_PILOT_ROWS, out->idx_r, st));
+        HIP_TRY(launch_sample(pl.n, pl.kc1, prm->seed, STREAM_PILOT_COLS, out->idx_c, st));
+        if (out->pilot_r) HIP_TRY(launch_sample(pl.m, pl.kr1, prm->seed, STREAM_PILOT_ROWS, out->pilot_r, st));
+        if (out->pilot_c) HIP_TRY(launch_sample(pl.n, pl.kc1, prm->seed, STREAM_PILOT_COLS, out->pilot_c, st));
+        c.phase = PH_R2_AFTER_W;
+        return sketch_followup_eval(c, job);
+      }
+      // 1-2: pilot sampling and evaluation
+      int64_t* Ir = out->pilot_r ? out->pilot_r : S.Ir;
+      int64_t* Ic = out->pilot_c ? out->pilot_c : S.Ic;
+      HIP_TRY(launch_sample(pl.m, pl.kr1, prm->seed, STREAM_PILOT_ROWS, Ir, st));
+      HIP_TRY(launch_sample(pl.n, pl.kc1, prm->seed, STREAM_PILOT_COLS, Ic, st));
+      HIP_TRY(launch_eval(c.mv, false, Ic, pl.kc1, pl.prec, S.C, st, c.ecnt));
+      HIP_TRY(launch_eval(c.mv, true, Ir, pl.kr1, pl.prec, S.Rt, st, c.ecnt));
+      HIP_TRY(launch_gather_rows_f64(S.C, pl.prec, pl.kc1, Ir, pl.kr1, pl.kc1, S.r1.W, st));
+      // 3: the SVD of W (next)
+      svd_job_one(job, pl.kr1, pl.kc1, S.r1.W, S.r1.Uw, S.r1.Sw, S.r1.Vw, S.r1.svd_ws);
+      c.phase = PH_R1_AFTER_W;
+      return CABS_OK;
+    }
+    case PH_R1_AFTER_W:
+      // 4-5: pilot sketch and embedding maps
+      s = round_after_w(c, S.r1, pl.kr1, pl.kc1, S.C, S.Rt, true, ortho, CABS_DIAG_RANK_PILOT, CABS_DIAG_SIGMA1_PILOT,
+                        job, eig);
+      if (s != CABS_OK) return s;
+      if (job.n) {
+        c.phase = eig ? PH_R1_AFTER_EIG : PH_R1_AFTER_K;
+        return CABS_OK;
+      }
+      s = sketch_middle(c);
+      if (s != CABS_OK) return s;
+      c.phase = PH_R2_AFTER_W;
+      return sketch_followup_eval(c, job);
+    case PH_R1_AFTER_EIG:
+      c.phase = PH_R1_AFTER_K;
+      return round_after_eig(c, S.r1, pl.p1, job);
+    case PH_R1_AFTER_K:
+      s = round_after_k(c, S.r1, pl.p1, pl.p1 > PCHOL_MAXP);
+      if (s != CABS_OK) return s;
+      s = sketch_middle(c);
+      if (s != CABS_OK) return s;
+      c.phase = PH_R2_AFTER_W;
+      return sketch_followup_eval(c, job);
+    case PH_R2_AFTER_W:
+      s = round_after_w(c, S.r2, pl.kr2, pl.kc2, out->C, out->Rt, fac, fac, CABS_DIAG_RANK_FINAL,
+                        CABS_DIAG_SIGMA1_FINAL, job, eig);
+      if (s != CABS_OK) return s;
+      if (job.n) {
+        c.phase = eig ? PH_R2_AFTER_EIG : PH_R2_AFTER_K;
+        return CABS_OK;
+      }
+      c.phase = PH_DONE;
+      return sketch_final(c);
+    case PH_R2_AFTER_EIG:
+      c.phase = PH_R2_AFTER_K;
+      return round_after_eig(c, S.r2, pl.p2, job);
+    case PH_R2_AFTER_K:
+      s = round_after_k(c, S.r2, pl.p2, pl.p2 > PCHOL_MAXP);
+      if (s != CABS_OK) return s;
+      c.phase = PH_DONE;
+      return sketch_final(c);
+    default:
+      return fail(CABS_EINVAL, "sketch already finished");
+  }
+}
+
+static hipError_t run_svd_job(const SvdJob* const* jobs, int njobs, hipStream_t st) {
+  SvdItems it{};
+  int n = 0;
+  for (int q = 0; q < njobs; ++q)
+    for (int i = 0; i < jobs[q]->n; ++i) {
+      if (n >= SVD_MAX_PTR) return hipErrorInvalidValue;
+      it.Ap[n] = jobs[q]->A[i];
+      it.Up[n] = jobs[q]->U[i];
+      it.Sp[n] = jobs[q]->S[i];
+      it.Vp[n] = jobs[q]->V[i];
+      it.Wp[n] = jobs[q]->W[i];
+      ++n;
+    }
+  it.n_ptr = n;
+  return launch_svd_items(n, jobs[0]->rows, jobs[0]->cols, it, st);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" size_t cabs_workspace_bytes(const cabs_matrix* mat, const cabs_params* prm) {
+  if (check_params(mat, prm) != CABS_OK) return 0;
+  SketchWs S;
+  return plan_sketch(nullptr, make_plan(mat, prm), prm, S);
+}
+
+extern "C" cabs_status cabs_sketch(const cabs_matrix* mat, const cabs_params* prm, void* ws, size_t ws_bytes,
+                                   cabs_result* out, void* stream) {
+  SketchRun c;
+  cabs_status s = sketch_begin(c, mat, prm, ws, ws_bytes, out, (hipStream_t)stream);
+  if (s != CABS_OK) return s;
+  for (;;) {
+    SvdJob job;
+    s = sketch_advance(c, job);
+    if (s != CABS_OK) return s;
+    if (job.n == 0) return CABS_OK;
+    const SvdJob* jp = &job;
+    HIP_TRY(run_svd_job(&jp, 1, c.st));
+  }
+}
+
+// Same-shape requests run phase by phase, each on its own stream, with each
+// SVD of the sketch batched into one launch on the first stream (the other
+// streams join it before and wait for it after, through the caller's events).
+namespace cabs {
+bool sketch_groupable(const cabs_params* a, const cabs_params* b) {
+  return a->k1_rows == b->k1_rows && a->k1_cols == b->k1_cols && a->k2_rows == b->k2_rows &&
+         a->k2_cols == b->k2_cols && a->compute == b->compute && a->orthogonalize == b->orthogonalize &&
+         a->want_factors == b->want_factors && a->follow_up == b->follow_up && a->want_factors == 0;
+}
+
+cabs_status sketch_group(int G, const cabs_matrix* const* mats, const cabs_params* const* prms,
+                         cabs_result* const* outs, void* const* ws, const size_t* ws_bytes, const hipStream_t* streams,
+                         const hipEvent_t* join_ev, hipEvent_t fork_ev, cabs_status* status) {
+  if (G < 1 || G > 4) return fail(CABS_EINVAL, "group size must be in [1, 4]");
+  std::vector<SketchRun> c(G);
+  for (int g = 0; g < G; ++g) {
+    status[g] = sketch_begin(c[g], mats[g], prms[g], ws[g], ws_bytes[g], outs[g], streams[g]);
+    if (status[g] != CABS_OK) return status[g];
+    if (g > 0 && !sketch_groupable(prms[0], prms[g])) return fail(CABS_EINVAL, "requests of different shapes");
+  }
+  for (;;) {
+    SvdJob job[4];
+    const SvdJob* jp[4];
+    for (int g = 0; g < G; ++g) {
+      status[g] = sketch_advance(c[g], job[g]);
+      if (status[g] != CABS_OK) return status[g];
+      jp[g] = &job[g];
+    }
+    if (job[0].n == 0) return CABS_OK;  // same phases for every member
+    bool other = false;
+    for (int g = 1; g < G; ++g) {
+      if (streams[g] == streams[0]) continue;  // already ordered
+      other = true;
+      HIP_TRY(hipEventRecord(join_ev[g], streams[g]));
+      HIP_TRY(hipStreamWaitEvent(streams[0], join_ev[g], 0));
+    }
+    HIP_TRY(run_svd_job(jp, G, streams[0]));
+    if (other) {
+      HIP_TRY(hipEventRecord(fork_ev, streams[0]));
+      for (int g = 1; g < G; ++g)
+        if (streams[g] != streams[0]) HIP_TRY(hipStreamWaitEvent(streams[g], fork_ev, 0));
+    }
+  }
+}
+}  // namespace cabs
+
+extern "C" cabs_status cabs_sketch_batch(int32_t count, const cabs_matrix* mats, const cabs_params* prms,
+                                         void* const* ws, const size_t* ws_bytes, cabs_result* outs, void* stream) {
+  if (count < 1 || count > 4 || !mats || !prms || !ws || !ws_bytes || !outs)
+    return fail(CABS_EINVAL, "need 1 <= count <= 4 and non-null arrays");
+  for (int g = 1; g < count; ++g)
+    if (!cabs::sketch_groupable(&prms[0], &prms[g]))
+      return fail(CABS_EINVAL, "request %d differs in shape from request 0 (or wants the factor form)", g);
+  if (count > 1 && prms[0].want_factors) return fail(CABS_EINVAL, "the factor form is not batched");
+  const cabs_matrix* mp[4];
+  const cabs_params* pp[4];
+  cabs_result* op[4];
+  hipStream_t sts[4];
+  hipEvent_t evs[4] = {nullptr, nullptr, nullptr, nullptr};
+  cabs_status gst[4];
+  for (int g = 0; g < count; ++g) {
+    mp[g] = &mats[g];
+    pp[g] = &prms[g];
+    op[g] = &outs[g];
+    sts[g] = (hipStream_t)stream;
+  }
+  return cabs::sketch_group(count, mp, pp, op, ws, ws_bytes, sts, evs, nullptr, gst);
 }
 
 // ---------------------------------------------------------------------------

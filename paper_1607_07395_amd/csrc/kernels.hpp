@@ -73,9 +73,26 @@ hipError_t launch_select_topk(int64_t rows, const double* w, int k, int64_t* out
 
 // --- FP64 small dense algebra (svd.hip, small.hip) ---
 size_t svd_ws_bytes(int batch, int rows, int cols);
+size_t svd_ws_item_doubles(int rows, int cols);  // one item's share of svd_ws_bytes, in doubles
 // Batched one-sided Jacobi SVD; A_b rows x cols row-major, strides in elements between batch items.
 // fast_sweeps (1 .. 24): sweeps launched round by round before the single-workgroup finisher;
 // 0: 12 up to min(rows, cols) = 256, 24 above.
+// Item b of a batched SVD: A_b, U_b, S_b, V_b and its workspace (svd_ws_doubles
+// per item) at fixed strides from the base pointers, or, with n_ptr = batch
+// (at most SVD_MAX_PTR), from the pointer lists.
+constexpr int SVD_MAX_PTR = 8;
+struct SvdItems {
+  const double* A;
+  double *U, *S, *V, *W;
+  int64_t sA, sU, sS, sV, sW;
+  int n_ptr;
+  const double* Ap[SVD_MAX_PTR];
+  double* Up[SVD_MAX_PTR];
+  double* Sp[SVD_MAX_PTR];
+  double* Vp[SVD_MAX_PTR];
+  double* Wp[SVD_MAX_PTR];
+};
+hipError_t launch_svd_items(int batch, int rows, int cols, const SvdItems& it, hipStream_t st, int fast_sweeps = 0);
 hipError_t launch_svd(int batch, int rows, int cols, const double* A, int64_t strideA, double* U, int64_t strideU,
                       double* S, int64_t strideS, double* V, int64_t strideV, void* ws, hipStream_t st,
                       int fast_sweeps = 0);

@@ -10,6 +10,13 @@
 // run concurrently on the device; each one's kernels only touch its own
 // buffers, so its result is the same whether it runs alone or next to others.
 //
+// With group_max > 1 (cabs_server_set_group; off by default), requests
+// admitted in the same round whose sketches have the same shape (the same
+// sample sizes, precision and options) run as a group: each on its own slot
+// stream, with every FP64 SVD of the sketch batched into one launch for the
+// group (group.hpp); the results are bitwise those of the same requests run
+// alone.
+//
 // Ordering: cabs_submit records an event on the caller's stream, and the slot
 // stream waits for it before the request's first kernel, so buffers the caller
 // wrote (or freed and reused) on its stream before submitting are ready.
@@ -29,6 +36,7 @@
 #include <vector>
 
 #include "../../include/cabs.h"
+#include "group.hpp"
 #include "serve_core.hpp"
 
 namespace {
@@ -55,6 +63,8 @@ struct cabs_server {
   cabs_serve::Core* core = nullptr;
   std::vector<hipStream_t> streams;
   std::vector<hipEvent_t> events;      // completion marker of each slot
+  std::vector<hipEvent_t> join_events; // a group member's stream before a shared SVD (and the fork after it)
+  int group_max = 1;                   // off by default: see cabs_server_set_group
   std::vector<hipEvent_t> free_events; // "ready" events for reuse
   std::mutex mu;
   std::condition_variable cv;          // wakes the scheduler
@@ -92,27 +102,77 @@ static void scheduler(cabs_server* s) {
       std::vector<ReqData> work;
       work.reserve(adm.size());
       for (const auto& a : adm) work.push_back(s->data[a.ticket]);
+      const int gmax = s->group_max;
       lk.unlock();
       std::vector<int> status(adm.size(), CABS_OK);
       std::vector<char> marker(adm.size(), 1);
+      // groups of same-shape requests (in admission order)
+      std::vector<std::vector<size_t>> groups;
       for (size_t q = 0; q < adm.size(); ++q) {
-        ReqData& r = work[q];
-        hipStream_t st = s->streams[adm[q].slot];
-        void* ws = s->pool_base + adm[q].off;
-        const size_t wsb = adm[q].bytes;
-        int rc = CABS_OK;
-        if (r.ready && hipStreamWaitEvent(st, r.ready, 0) != hipSuccess) rc = CABS_EDEVICE;
-        if (rc == CABS_OK) rc = cabs_sketch(&r.mat, &r.prm, ws, wsb, &r.res, st);
-        if (rc == CABS_OK && r.err_out3)
-          rc = cabs_error(&r.mat, &r.prm, &r.res, r.err_samples, r.err_seed, ws, wsb, r.err_out3, st);
-        // The marker goes behind whatever was enqueued, also after an error: kernels queued before
-        // it may still run, so the workspace stays held until the marker has fired.
-        if (hipEventRecord(s->events[adm[q].slot], st) != hipSuccess) {
-          (void)hipStreamSynchronize(st);
-          marker[q] = 0;
-          if (rc == CABS_OK) rc = CABS_EDEVICE;
+        bool placed = false;
+        for (auto& gset : groups)
+          if ((int)gset.size() < gmax && cabs::sketch_groupable(&work[gset[0]].prm, &work[q].prm)) {
+            gset.push_back(q);
+            placed = true;
+            break;
+          }
+        if (!placed) groups.push_back({q});
+      }
+      for (const auto& gset : groups) {
+        const int G = (int)gset.size();
+        std::vector<int> rc(G, CABS_OK);
+        for (int g = 0; g < G; ++g) {
+          ReqData& r = work[gset[g]];
+          if (r.ready && hipStreamWaitEvent(s->streams[adm[gset[g]].slot], r.ready, 0) != hipSuccess)
+            rc[g] = CABS_EDEVICE;
         }
-        status[q] = rc;
+        bool all_ok = true;
+        for (int g = 0; g < G; ++g) all_ok = all_ok && rc[g] == CABS_OK;
+        if (G == 1) {
+          const size_t q = gset[0];
+          ReqData& r = work[q];
+          if (rc[0] == CABS_OK)
+            rc[0] = cabs_sketch(&r.mat, &r.prm, s->pool_base + adm[q].off, adm[q].bytes, &r.res,
+                                s->streams[adm[q].slot]);
+        } else if (all_ok) {
+          const cabs_matrix* mats[4];
+          const cabs_params* prms[4];
+          cabs_result* outs[4];
+          void* wss[4];
+          size_t wsb[4];
+          hipStream_t sts[4];
+          hipEvent_t jev[4];
+          cabs_status gst[4];
+          for (int g = 0; g < G; ++g) {
+            const size_t q = gset[g];
+            mats[g] = &work[q].mat;
+            prms[g] = &work[q].prm;
+            outs[g] = &work[q].res;
+            wss[g] = s->pool_base + adm[q].off;
+            wsb[g] = adm[q].bytes;
+            sts[g] = s->streams[adm[q].slot];
+            jev[g] = s->join_events[adm[q].slot];
+            gst[g] = CABS_OK;
+          }
+          const cabs_status grc = cabs::sketch_group(G, mats, prms, outs, wss, wsb, sts, jev, jev[0], gst);
+          for (int g = 0; g < G; ++g) rc[g] = gst[g] != CABS_OK ? gst[g] : grc;
+        }
+        for (int g = 0; g < G; ++g) {
+          const size_t q = gset[g];
+          ReqData& r = work[q];
+          hipStream_t st = s->streams[adm[q].slot];
+          void* ws = s->pool_base + adm[q].off;
+          if (rc[g] == CABS_OK && r.err_out3)
+            rc[g] = cabs_error(&r.mat, &r.prm, &r.res, r.err_samples, r.err_seed, ws, adm[q].bytes, r.err_out3, st);
+          // The marker goes behind whatever was enqueued, also after an error: kernels queued before
+          // it may still run, so the workspace stays held until the marker has fired.
+          if (hipEventRecord(s->events[adm[q].slot], st) != hipSuccess) {
+            (void)hipStreamSynchronize(st);
+            marker[q] = 0;
+            if (rc[g] == CABS_OK) rc[g] = CABS_EDEVICE;
+          }
+          status[q] = rc[g];
+        }
       }
       lk.lock();
       std::vector<uint64_t> ended;
@@ -149,9 +209,11 @@ extern "C" cabs_server* cabs_server_create(int32_t device, size_t hbm_budget_byt
   s->core = new cabs_serve::Core(hbm_budget_bytes, max_slots, 4 * max_slots);
   s->streams.resize(max_slots);
   s->events.resize(max_slots);
+  s->join_events.resize(max_slots);
   for (int k = 0; k < max_slots; ++k) {
     (void)hipStreamCreateWithFlags(&s->streams[k], hipStreamNonBlocking);
     (void)hipEventCreateWithFlags(&s->events[k], hipEventDisableTiming);
+    (void)hipEventCreateWithFlags(&s->join_events[k], hipEventDisableTiming);
   }
   s->worker = std::thread(scheduler, s);
   return s;
@@ -232,6 +294,13 @@ extern "C" cabs_status cabs_cancel(cabs_server* s, uint64_t ticket) {
   return CABS_OK;
 }
 
+extern "C" cabs_status cabs_server_set_group(cabs_server* s, int32_t group_max) {
+  if (!s || group_max < 1 || group_max > 4) return CABS_EINVAL;
+  std::lock_guard<std::mutex> g(s->mu);
+  s->group_max = group_max;
+  return CABS_OK;
+}
+
 extern "C" cabs_status cabs_server_drain(cabs_server* s) {
   if (!s) return CABS_EINVAL;
   std::unique_lock<std::mutex> lk(s->mu);
@@ -250,6 +319,7 @@ extern "C" void cabs_server_destroy(cabs_server* s) {
     (void)hipStreamSynchronize(s->streams[k]);
     (void)hipStreamDestroy(s->streams[k]);
     (void)hipEventDestroy(s->events[k]);
+    (void)hipEventDestroy(s->join_events[k]);
   }
   for (auto& kv : s->data)
     if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);

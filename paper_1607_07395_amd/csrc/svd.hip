@@ -43,9 +43,22 @@ __host__ __device__ static inline size_t svd_ws_doubles(int rows, int cols) {
   return 2 * q * P + P * P + 3 * p + 64;
 }
 
+size_t svd_ws_item_doubles(int rows, int cols) { return svd_ws_doubles(rows, cols); }
+
 size_t svd_ws_bytes(int batch, int rows, int cols) {
   return (size_t)batch * svd_ws_doubles(rows, cols) * sizeof(double) + 256;
 }
+
+// Item b of a batch: its input, outputs and scratch, at fixed strides from
+// base pointers, or from per-item pointer lists (n_ptr > 0: same-shape
+// matrices that live in different requests' workspaces).
+__device__ __forceinline__ const double* item_a(const SvdItems& it, int b) {
+  return it.n_ptr ? it.Ap[b] : it.A + b * it.sA;
+}
+__device__ __forceinline__ double* item_u(const SvdItems& it, int b) { return it.n_ptr ? it.Up[b] : it.U + b * it.sU; }
+__device__ __forceinline__ double* item_s(const SvdItems& it, int b) { return it.n_ptr ? it.Sp[b] : it.S + b * it.sS; }
+__device__ __forceinline__ double* item_v(const SvdItems& it, int b) { return it.n_ptr ? it.Vp[b] : it.V + b * it.sV; }
+__device__ __forceinline__ double* item_w(const SvdItems& it, int b) { return it.n_ptr ? it.Wp[b] : it.W + b * it.sW; }
 
 // Singular values (column norms of the converged X), descending order, signs,
 // and the outputs in row-major U (rows x p), S (p), V (cols x p).  X is q x p
@@ -116,12 +129,7 @@ __device__ void svd_finalize(const double* X, int64_t xrs, int64_t xcs, const do
   }
 }
 
-__global__ __launch_bounds__(SVD_THREADS) void svd_jacobi_kernel(int rows, int cols, const double* __restrict__ A,
-                                                                  int64_t strideA, double* __restrict__ U,
-                                                                  int64_t strideU, double* __restrict__ S,
-                                                                  int64_t strideS, double* __restrict__ Vout,
-                                                                  int64_t strideV, double* __restrict__ ws,
-                                                                  int use_lds) {
+__global__ __launch_bounds__(SVD_THREADS) void svd_jacobi_kernel(int rows, int cols, SvdItems it, int use_lds) {
   extern __shared__ double lds[];
   __shared__ int rotated;
   const int b = blockIdx.x;
@@ -129,14 +137,14 @@ __global__ __launch_bounds__(SVD_THREADS) void svd_jacobi_kernel(int rows, int c
   const int p = trans ? rows : cols;
   const int q = trans ? cols : rows;
   const int pe = even_up(p);
-  double* base = ws + (size_t)b * svd_ws_doubles(rows, cols);
+  double* base = item_w(it, b);
   double* X = use_lds ? lds : base;              // column-major q x p
   double* V = use_lds ? lds + (size_t)q * p : base + (size_t)q * p;  // column-major p x p
   const size_t Pb = (size_t)bj_blocks(p) * BJ_B;
   double* sig = base + (size_t)q * Pb + Pb * Pb;
   int* rank = (int*)(sig + p);
   double* sgn = sig + 2 * p;
-  const double* Ab = A + b * strideA;
+  const double* Ab = item_a(it, b);
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int lane = tid & 63;
@@ -203,7 +211,7 @@ __global__ __launch_bounds__(SVD_THREADS) void svd_jacobi_kernel(int rows, int c
     if (done) break;
   }
 
-  svd_finalize(X, 1, q, V, 1, p, q, p, trans, sig, rank, sgn, U + b * strideU, S + b * strideS, Vout + b * strideV);
+  svd_finalize(X, 1, q, V, 1, p, q, p, trans, sig, rank, sgn, item_u(it, b), item_s(it, b), item_v(it, b));
 }
 
 // ---------------------------------------------------------------------------
@@ -249,14 +257,13 @@ struct BjView {
   bool trans;
 };
 
-__device__ __forceinline__ BjView bj_view(double* ws, int rows, int cols, int b) {
+__device__ __forceinline__ BjView bj_view(double* base, int rows, int cols) {
   BjView v;
   v.trans = rows < cols;
   v.p = v.trans ? rows : cols;
   v.q = v.trans ? cols : rows;
   v.nb = bj_blocks(v.p);
   v.P = v.nb * BJ_B;
-  double* base = ws + (size_t)b * svd_ws_doubles(rows, cols);
   v.X = base;
   v.V = base + (size_t)v.q * v.P;
   v.sig = v.V + (size_t)v.P * v.P;
@@ -268,10 +275,9 @@ __device__ __forceinline__ BjView bj_view(double* ws, int rows, int cols, int b)
   return v;
 }
 
-__global__ __launch_bounds__(256) void bj_init_kernel(int rows, int cols, const double* __restrict__ A, int64_t strideA,
-                                                      double* __restrict__ ws) {
-  BjView v = bj_view(ws, rows, cols, blockIdx.y);
-  const double* Ab = A + blockIdx.y * strideA;
+__global__ __launch_bounds__(256) void bj_init_kernel(int rows, int cols, SvdItems it) {
+  BjView v = bj_view(item_w(it, blockIdx.y), rows, cols);
+  const double* Ab = item_a(it, blockIdx.y);
   const int64_t nx = (int64_t)v.q * v.P, nv = (int64_t)v.P * v.P;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nx + nv; e += (int64_t)gridDim.x * 256) {
     if (e < nx) {
@@ -289,11 +295,10 @@ __global__ __launch_bounds__(256) void bj_init_kernel(int rows, int cols, const 
 
 // |X|_F^2, invariant under the rotations, for the negligible-column floor
 // (fixed summation order: per thread, then per wave, then the waves in order).
-__global__ __launch_bounds__(1024) void bj_norm_kernel(int rows, int cols, const double* __restrict__ A, int64_t strideA,
-                                                       double* __restrict__ ws) {
+__global__ __launch_bounds__(1024) void bj_norm_kernel(int rows, int cols, SvdItems it) {
   __shared__ double red[16];
-  BjView v = bj_view(ws, rows, cols, blockIdx.x);
-  const double* Ab = A + blockIdx.x * strideA;
+  BjView v = bj_view(item_w(it, blockIdx.x), rows, cols);
+  const double* Ab = item_a(it, blockIdx.x);
   double s = 0.0;
   for (int64_t e = threadIdx.x; e < (int64_t)rows * cols; e += 1024) s += Ab[e] * Ab[e];
   s = wave_sum(s);
@@ -542,14 +547,13 @@ __device__ __forceinline__ void pair_copy(const BjView& v, double* xo, int ba, i
 // step (and the matching block of J), computes both rotations itself, and
 // writes the rotated block to the other half of a double buffer.
 
-__global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int round, int sweep,
-                                                       double* __restrict__ ws) {
+__global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int round, int sweep, SvdItems it) {
   __shared__ double gp[4][16][17];
   __shared__ double Gb[2][16][17];
   __shared__ double Jb[2][16][17];
   __shared__ double xs[BJ_QS][17];
   __shared__ int any_off;
-  BjView v = bj_view(ws, rows, cols, blockIdx.y);
+  BjView v = bj_view(item_w(it, blockIdx.y), rows, cols);
   const int gr = sweep * (v.nb - 1) + round;
   double* const xo = (gr & 1) ? v.X : v.X1;
   if (gr & 1) v.X = v.X1;  // v.X: the copy this round reads
@@ -755,16 +759,13 @@ __device__ void svd_finalize_rm(const BjView& v, BjFinalLds& L, double* Ub, doub
 }
 
 // Remaining sweeps (if any) in one workgroup, one wave per pair; then the outputs.
-__global__ __launch_bounds__(1024) void bj_finish_kernel(int rows, int cols, int first_sweep, double* __restrict__ U,
-                                                         int64_t strideU, double* __restrict__ S, int64_t strideS,
-                                                         double* __restrict__ Vout, int64_t strideV,
-                                                         double* __restrict__ ws) {
+__global__ __launch_bounds__(1024) void bj_finish_kernel(int rows, int cols, int first_sweep, SvdItems it) {
   __shared__ double Gs[16][16][17];
   __shared__ double cs[16][8][2];
   __shared__ int rotated;
   __shared__ BjFinalLds fin;
   const int b = blockIdx.x;
-  BjView v = bj_view(ws, rows, cols, b);
+  BjView v = bj_view(item_w(it, b), rows, cols);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, c16 = lane & 15, g = lane >> 4;
   const double eps = 2.220446049250313e-16;
   const double tol = eps * (v.q > 16 ? (double)v.q : 16.0);
@@ -855,14 +856,13 @@ __global__ __launch_bounds__(1024) void bj_finish_kernel(int rows, int cols, int
     if (done) break;
   }
   __syncthreads();
-  svd_finalize_rm(v, fin, U + b * strideU, S + b * strideS, Vout + b * strideV);
+  svd_finalize_rm(v, fin, item_u(it, b), item_s(it, b), item_v(it, b));
 }
 
-hipError_t launch_svd(int batch, int rows, int cols, const double* A, int64_t strideA, double* U, int64_t strideU,
-                      double* S, int64_t strideS, double* V, int64_t strideV, void* ws, hipStream_t st,
-                      int fast_sweeps) {
+hipError_t launch_svd_items(int batch, int rows, int cols, const SvdItems& it, hipStream_t st, int fast_sweeps) {
   if (batch <= 0 || rows <= 0 || cols <= 0 || std::min(rows, cols) > 1024 || std::max(rows, cols) > 4096)
     return hipErrorInvalidValue;
+  if (it.n_ptr && (it.n_ptr != batch || batch > SVD_MAX_PTR)) return hipErrorInvalidValue;
   if (fast_sweeps == 0) fast_sweeps = bj_default_fast_sweeps(rows < cols ? rows : cols);
   if (fast_sweeps < 1 || fast_sweeps > BJ_FAST_SWEEPS) return hipErrorInvalidValue;
   const size_t p = rows < cols ? rows : cols, q = rows < cols ? cols : rows;
@@ -870,24 +870,39 @@ hipError_t launch_svd(int batch, int rows, int cols, const double* A, int64_t st
   const int use_lds = lds_bytes <= (size_t)SVD_LDS_BYTES ? 1 : 0;
   TimerScope ts(T_SVD, st);
   if (p < 24) {
-    hipLaunchKernelGGL(svd_jacobi_kernel, dim3(batch), dim3(SVD_THREADS), use_lds ? lds_bytes : 0, st, rows, cols,
-                       A, strideA, U, strideU, S, strideS, V, strideV, (double*)ws, use_lds);
+    hipLaunchKernelGGL(svd_jacobi_kernel, dim3(batch), dim3(SVD_THREADS), use_lds ? lds_bytes : 0, st, rows, cols, it,
+                       use_lds);
     return hipGetLastError();
   }
-  double* w = (double*)ws;
   const int nb = bj_blocks((int)p);
   const int64_t elems = (int64_t)q * nb * BJ_B + (int64_t)nb * BJ_B * nb * BJ_B;
   hipLaunchKernelGGL(bj_init_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(elems, 256), 1024), batch), dim3(256), 0,
-                     st, rows, cols, A, strideA, w);
-  hipLaunchKernelGGL(bj_norm_kernel, dim3(batch), dim3(1024), 0, st, rows, cols, A, strideA, w);
+                     st, rows, cols, it);
+  hipLaunchKernelGGL(bj_norm_kernel, dim3(batch), dim3(1024), 0, st, rows, cols, it);
   for (int sweep = 0; sweep < fast_sweeps; ++sweep) {
     for (int round = 0; round < nb - 1; ++round)
       hipLaunchKernelGGL(bj_round_kernel, dim3(nb / 2 * BJ_SPLIT, batch), dim3(256), 0, st, rows, cols, round, sweep,
-                         w);
+                         it);
   }
-  hipLaunchKernelGGL(bj_finish_kernel, dim3(batch), dim3(1024), 0, st, rows, cols, fast_sweeps, U, strideU, S,
-                     strideS, V, strideV, w);
+  hipLaunchKernelGGL(bj_finish_kernel, dim3(batch), dim3(1024), 0, st, rows, cols, fast_sweeps, it);
   return hipGetLastError();
+}
+
+hipError_t launch_svd(int batch, int rows, int cols, const double* A, int64_t strideA, double* U, int64_t strideU,
+                      double* S, int64_t strideS, double* V, int64_t strideV, void* ws, hipStream_t st,
+                      int fast_sweeps) {
+  SvdItems it{};
+  it.A = A;
+  it.U = U;
+  it.S = S;
+  it.V = V;
+  it.W = (double*)ws;
+  it.sA = strideA;
+  it.sU = strideU;
+  it.sS = strideS;
+  it.sV = strideV;
+  it.sW = (int64_t)svd_ws_doubles(rows, cols);
+  return launch_svd_items(batch, rows, cols, it, st, fast_sweeps);
 }
 
 }  // namespace cabs

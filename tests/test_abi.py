@@ -144,6 +144,26 @@ def test_brcur_planning_and_validation_on_cpu():
     assert b"workspace too small" in lib.cabs_last_error()
 
 
+def test_sketch_batch_rejects_bad_arguments_without_launching():
+    from paper_1607_07395_amd import _ffi as F
+    from paper_1607_07395_amd.api import make_params
+    lib = F.lib()
+    mats = (F.CabsMatrix * 2)(_desc(), _desc(2000, 900))
+    prms = (F.CabsParams * 2)(make_params(20, 20, 20, 20), make_params(20, 20, 20, 24))
+    outs = (F.CabsResult * 2)()
+    ws = (C.c_void_p * 2)(0x100000, 0x200000)
+    wb = (C.c_size_t * 2)(1 << 30, 1 << 30)
+    for n in (0, 5):
+        assert lib.cabs_sketch_batch(n, mats, prms, ws, wb, outs, None) == F.EINVAL
+    assert lib.cabs_sketch_batch(2, mats, prms, ws, wb, outs, None) == F.EINVAL   # different shapes
+    assert b"differs in shape" in lib.cabs_last_error()
+    prms[1].k2_cols = 20
+    prms[0].want_factors = prms[1].want_factors = 1
+    assert lib.cabs_sketch_batch(2, mats, prms, ws, wb, outs, None) == F.EINVAL   # the factor form is not batched
+    prms[0].want_factors = prms[1].want_factors = 0
+    assert lib.cabs_sketch_batch(2, mats, prms, ws, wb, outs, None) == F.EINVAL   # null result buffers
+
+
 def test_server_rejects_invalid_creation():
     from paper_1607_07395_amd import _ffi as F
     lib = F.lib()

@@ -116,3 +116,68 @@ def test_cancel_queued_request(api, requests):
         assert ei.value.status == api.F.ECANCELED
     finally:
         srv.close()
+
+
+def _diag_equal(a, b):
+    da, db = a.diag.cpu().numpy(), b.diag.cpu().numpy()
+    assert np.array_equal(da, db, equal_nan=True)
+
+
+def _shape_class(api, compute, k, follow_up="kmeans", seeds=(3, 4, 5, 6)):
+    """Same-shape requests on matrices of different sizes and kinds (uneven m, n)."""
+    recs = workloads.request_stream(n_requests=len(seeds), qps=1e3, seed=11, m_range=(2_000, 20_000), ks=(k,))
+    out = []
+    for rec, sd in zip(recs, seeds):
+        spec = workloads.request_matrix(rec)
+        prm = api.make_params(k, k, k, k, kmeans_iters=3, compute=compute, seed=sd, follow_up=follow_up)
+        out.append((api.DeviceMatrix(spec, storage="f64" if compute == "f64" else "f32"), prm))
+    return out
+
+
+@pytest.mark.parametrize("compute,k,follow_up,count", [
+    ("f32", 64, "kmeans", 4),      # pivoted Cholesky route: one SVD item per request
+    ("bf16", 240, "kmeans", 4),    # eigen route (p > 204): two items per request, 8 in one launch
+    ("f64", 20, "leverage", 3),    # the one-work-group SVD (p < 24)
+    ("f32", 48, "pilot", 2),       # the pilot sketch alone: one SVD per request
+])
+def test_sketch_batch_is_bitwise_the_single_sketch(api, compute, k, follow_up, count):
+    """cabs_sketch_batch: the same-shape requests share each SVD launch; every output (indices,
+    C, R^T, U_mid, diagnostics) equals cabs_sketch's bit for bit."""
+    reqs = _shape_class(api, compute, k, follow_up, seeds=tuple(range(7, 7 + count)))
+    alone = []
+    for mat, prm in reqs:
+        res = api.sketch(mat, prm)
+        torch.cuda.synchronize()
+        alone.append(res)
+    batch = api.sketch_batch([m for m, _ in reqs], [p for _, p in reqs])
+    torch.cuda.synchronize()
+    for a, b in zip(alone, batch):
+        _same(a, b)
+        _diag_equal(a, b)
+
+
+def test_server_groups_same_shape_requests(api):
+    """Eight same-shape requests submitted at once to a 4-slot server (groups of up to 4 form when
+    several are admitted together): each result, and its sampled error, equals the request run
+    alone; the same with grouping turned off."""
+    reqs = _shape_class(api, "f32", 32, seeds=tuple(range(20, 28)))
+    alone = [_alone(api, mat, prm) for mat, prm in reqs]
+    for gmax in (4, 1):
+        srv = api.Server(0, hbm_budget_bytes=4 << 30, max_slots=4)
+        try:
+            srv.set_group(gmax)
+            outs, errs, tickets = [], [], []
+            for mat, prm in reqs:
+                res = api.alloc_result(mat, prm)
+                e3 = torch.zeros(3, dtype=torch.float64, device="cuda")
+                tickets.append(srv.submit(mat, prm, res, err_samples=ERR_SAMPLES, err_seed=prm.seed + 1, err_out=e3))
+                outs.append(res)
+                errs.append(e3)
+            srv.drain()
+            for t in tickets:
+                assert srv.poll(t) >= 0.0
+        finally:
+            srv.close()
+        for (ra, ea), rm, em in zip(alone, outs, errs):
+            _same(ra, rm)
+            assert torch.equal(ea, em)
