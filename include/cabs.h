@@ -45,7 +45,7 @@ typedef enum {
   CABS_ECANCELED = -6   /* serving: request was cancelled */
 } cabs_status;
 
-/* Arithmetic precisions.  SVDs, eigen-decompositions, Grams for the
+/* Arithmetic precisions.  SVDs, pivoted Cholesky factorisations, Grams for the
  * orthogonalisation and all k x k algebra always run in FP64. */
 typedef enum { CABS_F64 = 0, CABS_F32 = 1, CABS_BF16 = 2, CABS_F16 = 3 } cabs_prec;
 

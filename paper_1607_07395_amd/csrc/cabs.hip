@@ -9,9 +9,9 @@
 //   4  C^ = C V_w, R^ = R^T U_w with FP64 column norms N_c, N_r; kept components,
 //      S (stabilised: S_w sqrt(mn/(kr kc)); pseudo-skeleton: N_c N_r / S_w)
 //   5  orthogonalisation (supplementary Section 3) in FP64: Grams of C^ N_c^-1 and
-//      R^ N_r^-1, their eigen-decompositions, the SVD of T_u^T S T_v; the
-//      embedding maps M_u, M_v (k x k) such that P = C^ M_u, Q = R^ M_v hold
-//      U_o S_o^(1/2) and V_o S_o^(1/2)
+//      R^ N_r^-1, their pivoted Cholesky factors R_u, R_v, the SVD of
+//      K = R_u S R_v^T; the embedding maps M_u, M_v (k x k) such that
+//      P = C^ M_u, Q = R^ M_v hold U_o S_o^(1/2) and V_o S_o^(1/2)
 //   6  P, Q with row norms -> weights Upsilon(|P_l|)
 //   7  weighted k-means + snapping on P (rows) and Q (columns)
 //   8  C_bar, R_bar^T, W_bar; SVD; norms; Umid = V_w diag(S / (N_c N_r)) U_w^T
@@ -102,25 +102,6 @@ __global__ void scale2_kernel(int p, const double* __restrict__ G, const double*
   if (e >= p * p) return;
   const int i = e / p, j = e % p;
   out[e] = dl[i] * G[e] * dr[j];
-}
-
-// Eigen truncation of a PSD Gram with eigenvalues lam (descending):
-// fpos[j] = sqrt(lam_j), fneg[j] = 1/sqrt(lam_j) for kept j, 0 otherwise.
-__global__ void eig_vec_kernel(int p, const double* __restrict__ lam, double* __restrict__ fpos,
-                               double* __restrict__ fneg) {
-  const double eps = 2.220446049250313e-16;
-  const double lmax = lam[0];
-  for (int j = threadIdx.x; j < p; j += blockDim.x) {
-    const double l = lam[j];
-    const bool keep = lmax > 0.0 && l > (double)p * eps * lmax;
-    fpos[j] = keep ? sqrt(l) : 0.0;
-    fneg[j] = keep ? 1.0 / sqrt(l) : 0.0;
-  }
-}
-
-// v[j] = sqrt(max(s[j], 0))
-__global__ void sqrt_vec_kernel(int p, const double* __restrict__ s, double* __restrict__ out) {
-  for (int j = threadIdx.x; j < p; j += blockDim.x) out[j] = s[j] > 0.0 ? sqrt(s[j]) : 0.0;
 }
 
 // w[j] = s[j]^(-1/2) for s[j] > p eps s[0] (s descending), else 0
@@ -319,7 +300,8 @@ struct Carve {
 // FP64 scratch of one sketching round with p components.
 struct RoundWs {
   double *W, *Uw, *Sw, *Vw, *nc2, *nr2, *invc, *invr, *sk, *dk;
-  double *G2, *Gs2, *E2U, *E2S, *E2V, *fpos, *fneg;   // batched (2) Grams and eigen-decompositions
+  double *G2, *Gs2, *E2V, *fpos, *fneg;   // both Grams and their pivoted Cholesky factors
+  void* pch_ws;                           // the factorisation's workspace (used above PCHOL_MAXP)
   double *K, *Us, *S1, *Vs, *T1, *T2, *Mu, *Mv, *sq;
   void *svd_ws, *gram_ws, *ts_ws;
   void *Ch, *Rh;                                      // extrapolated vectors (compute precision)
@@ -344,7 +326,7 @@ static void plan_round(Carve& cv, RoundWs& R, const Plan& pl, int kr, int kc, bo
   R.invr = cv.take<double>(p);
   R.sk = cv.take<double>(p);
   R.dk = cv.take<double>(p);
-  size_t svd_b = std::max(svd_ws_bytes(1, kr, kc), need_ortho ? std::max(svd_ws_bytes(2, p, p), svd_ws_bytes(1, p, p)) : 0);
+  size_t svd_b = std::max(svd_ws_bytes(1, kr, kc), need_ortho ? svd_ws_bytes(1, p, p) : 0);
   R.svd_ws = cv.take_bytes(svd_b);
   const int64_t mx = std::max(pl.m, pl.n);
   R.ts_ws = cv.take_bytes(std::max(tsgemm_ws_bytes(mx, std::max(kr, kc), p, pl.prec), tsgemm_ws_bytes(mx, p, p, pl.prec)));
@@ -357,8 +339,7 @@ static void plan_round(Carve& cv, RoundWs& R, const Plan& pl, int kr, int kc, bo
   if (need_ortho) {
     R.G2 = cv.take<double>(2 * (size_t)p * p);
     R.Gs2 = cv.take<double>(2 * (size_t)p * p);
-    R.E2U = cv.take<double>(2 * (size_t)p * p);
-    R.E2S = cv.take<double>(2 * (size_t)p);
+    R.pch_ws = cv.take_bytes(pchol_ws_bytes(2, p));
     R.E2V = cv.take<double>(2 * (size_t)p * p);
     R.fpos = cv.take<double>(2 * (size_t)p);
     R.fneg = cv.take<double>(2 * (size_t)p);
@@ -375,7 +356,8 @@ static void plan_round(Carve& cv, RoundWs& R, const Plan& pl, int kr, int kc, bo
   } else {
     R.Mu = cv.take<double>((size_t)p * p);
     R.Mv = cv.take<double>((size_t)p * p);
-    R.G2 = R.Gs2 = R.E2U = R.E2S = R.E2V = R.fpos = R.fneg = R.K = R.Us = R.S1 = R.Vs = R.T1 = R.T2 = R.sq = nullptr;
+    R.G2 = R.Gs2 = R.E2V = R.fpos = R.fneg = R.K = R.Us = R.S1 = R.Vs = R.T1 = R.T2 = R.sq = nullptr;
+    R.pch_ws = nullptr;
     R.gram_ws = nullptr;
   }
 }
@@ -568,23 +550,20 @@ static MatView view_of(const cabs_matrix* mat) {
 // results are the same bits either way) and calls advance() again.
 //
 // One sketching round on sampled C (m x kc), R^T (n x kr), W (kr x kc, FP64):
-//   SVD of W | norms and scalings (sketch_vec); with `ortho` the Grams and
-//   either pivoted Cholesky factors or (p > PCHOL_MAXP) | the eigen-
-//   decompositions of both Grams | then K | the SVD of K | the embedding maps.
+//   SVD of W | norms and scalings (sketch_vec); with `ortho` the Grams, their
+//   pivoted Cholesky factors and K | the SVD of K | the embedding maps.
 // ---------------------------------------------------------------------------
 struct SvdJob {
   int n = 0, rows = 0, cols = 0;  // n items (0: no SVD, the sketch has finished)
-  const double* A[2];
-  double *U[2], *S[2], *V[2], *W[2];
+  const double* A[1];
+  double *U[1], *S[1], *V[1], *W[1];
 };
 
 enum Phase {
   PH_START = 0,
   PH_R1_AFTER_W,     // round 1: after the SVD of W
-  PH_R1_AFTER_EIG,   // round 1: after the Grams' eigen-decompositions
   PH_R1_AFTER_K,     // round 1: after the SVD of K
   PH_R2_AFTER_W,
-  PH_R2_AFTER_EIG,
   PH_R2_AFTER_K,
   PH_DONE
 };
@@ -615,16 +594,14 @@ static void svd_job_one(SvdJob& j, int rows, int cols, const double* A, double* 
 }
 
 // Round part after the SVD of W: C^ = C V_w, R^ = R^T U_w with norms, the
-// kept components and scalings; with `ortho` the Grams, then either the
-// pivoted Cholesky factors and K (next: the SVD of K) or the eigen-
-// decompositions of both Grams (next).  `next` receives the following SVD.
+// kept components and scalings; with `ortho` the Grams, their pivoted
+// Cholesky factors and K (next: the SVD of K).  `next` receives the following SVD.
 static cabs_status round_after_w(const SketchRun& c, RoundWs& R, int kr, int kc, const void* C, const void* Rt,
-                                 bool vectors, bool ortho, int slot_rank, int slot_sig, SvdJob& next, bool& eig) {
+                                 bool vectors, bool ortho, int slot_rank, int slot_sig, SvdJob& next) {
   const Plan& pl = c.pl;
   hipStream_t st = c.st;
   const int p = std::min(kr, kc);
   next.n = 0;
-  eig = false;
   HIP_TRY(launch_tsgemm(pl.m, kc, p, pl.prec, C, R.Vw, vectors ? R.Ch : nullptr, R.nc2, nullptr, R.ts_ws, st));
   HIP_TRY(launch_tsgemm(pl.n, kr, p, pl.prec, Rt, R.Uw, vectors ? R.Rh : nullptr, R.nr2, nullptr, R.ts_ws, st));
   hipLaunchKernelGGL(sketch_vec_kernel, dim3(1), dim3(1024), 0, st, p, kr, kc, (double)pl.m, (double)pl.n, R.Sw, R.nc2,
@@ -647,62 +624,27 @@ static cabs_status round_after_w(const SketchRun& c, RoundWs& R, int kr, int kc,
   const unsigned gb = (unsigned)ceil_div((int64_t)pp, 256);
   hipLaunchKernelGGL(scale2_kernel, dim3(gb), dim3(256), 0, st, p, R.Gs2, R.invc, R.invc, R.G2);
   hipLaunchKernelGGL(scale2_kernel, dim3(gb), dim3(256), 0, st, p, R.Gs2 + pp, R.invr, R.invr, R.G2 + pp);
-  if (p <= PCHOL_MAXP) {
-    // Pivoted Cholesky G = R^T R of both Grams (rank-revealing: pivots <= p eps of the unit diagonal
-    // stop it), K = R_u diag(S) R_v^T, then the SVD of K (next).
-    const double eps = 2.220446049250313e-16;
-    HIP_TRY(launch_pchol(2, p, R.G2, pp, (double)p * eps, R.E2V, pp, st));
-    HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, false, R.E2V + pp, p, true, nullptr, R.sk, nullptr, R.K, p, st));
-    svd_job_one(next, p, p, R.K, R.Us, R.S1, R.Vs, R.svd_ws);
-    return CABS_OK;
-  }
-  // Eigen-decompositions G = E Lambda E^T (SVD of a PSD matrix) of both Grams (next, two items).
-  eig = true;
-  next.n = 2;
-  next.rows = next.cols = p;
-  const size_t wsd = svd_ws_item_doubles(p, p);
-  for (int i = 0; i < 2; ++i) {
-    next.A[i] = R.G2 + i * pp;
-    next.U[i] = R.E2U + i * pp;
-    next.S[i] = R.E2S + i * p;
-    next.V[i] = R.E2V + i * pp;
-    next.W[i] = (double*)R.svd_ws + i * wsd;
-  }
-  return CABS_OK;
-}
-
-// Eigen route, after the Grams' eigen-decompositions: K = T_u^T diag(S) T_v (next: its SVD).
-static cabs_status round_after_eig(const SketchRun& c, RoundWs& R, int p, SvdJob& next) {
-  hipStream_t st = c.st;
-  hipLaunchKernelGGL(eig_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.E2S, R.fpos, R.fneg);
-  hipLaunchKernelGGL(eig_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.E2S + p, R.fpos + p, R.fneg + p);
-  // T_u = E_u Lambda_u^(1/2);  K = T_u^T diag(S) T_v
-  const size_t pp = (size_t)p * p;
-  HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, true, R.E2V + pp, p, false, R.fpos, R.sk, R.fpos + p, R.K, p, st));
+  // Pivoted Cholesky G = R^T R of both Grams (rank-revealing: pivots <= p eps of the unit diagonal
+  // stop it), K = R_u diag(S) R_v^T, then the SVD of K (next).
+  const double eps = 2.220446049250313e-16;
+  HIP_TRY(launch_pchol(2, p, R.G2, pp, (double)p * eps, R.E2V, pp, R.pch_ws, st));
+  HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, false, R.E2V + pp, p, true, nullptr, R.sk, nullptr, R.K, p, st));
   svd_job_one(next, p, p, R.K, R.Us, R.S1, R.Vs, R.svd_ws);
   return CABS_OK;
 }
 
 // After the SVD of K: the embedding maps M_u, M_v.
-static cabs_status round_after_k(const SketchRun& c, RoundWs& R, int p, bool eig) {
+static cabs_status round_after_k(const SketchRun& c, RoundWs& R, int p) {
   hipStream_t st = c.st;
   const size_t pp = (size_t)p * p;
-  if (!eig) {
-    // Since K V_s = U_s S_1, R_u^-1 U_s = diag(S) R_v^T V_s S_1^-1, so without any triangular solve
-    //   M_u = diag(invc S) R_v^T V_s S_1^(-1/2),  M_v = diag(invr S) R_u^T U_s S_1^(-1/2)
-    // map C^ and R^ to P = U' S_1^(1/2), Q = V' S_1^(1/2) (components with S_1 <= p eps S_1[0] dropped).
-    hipLaunchKernelGGL(rsqrt_trunc_kernel, dim3(1), dim3(1024), 0, st, p, R.S1, R.sq);
-    hipLaunchKernelGGL(mul_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.invc, R.sk, R.fpos);
-    hipLaunchKernelGGL(mul_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.invr, R.sk, R.fpos + p);
-    HIP_TRY(launch_small_gemm(p, p, p, R.E2V + pp, p, true, R.Vs, p, false, R.fpos, nullptr, R.sq, R.Mu, p, st));
-    HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, true, R.Us, p, false, R.fpos + p, nullptr, R.sq, R.Mv, p, st));
-    HIP_TRY(hipGetLastError());
-    return CABS_OK;
-  }
-  hipLaunchKernelGGL(sqrt_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.S1, R.sq);
-  // M_u = diag(invc) E_u diag(Lambda_u^-1/2) U_s diag(S_1^1/2), M_v likewise with V_s.
-  HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, false, R.Us, p, false, R.invc, R.fneg, R.sq, R.Mu, p, st));
-  HIP_TRY(launch_small_gemm(p, p, p, R.E2V + pp, p, false, R.Vs, p, false, R.invr, R.fneg + p, R.sq, R.Mv, p, st));
+  // Since K V_s = U_s S_1, R_u^-1 U_s = diag(S) R_v^T V_s S_1^-1, so without any triangular solve
+  //   M_u = diag(invc S) R_v^T V_s S_1^(-1/2),  M_v = diag(invr S) R_u^T U_s S_1^(-1/2)
+  // map C^ and R^ to P = U' S_1^(1/2), Q = V' S_1^(1/2) (components with S_1 <= p eps S_1[0] dropped).
+  hipLaunchKernelGGL(rsqrt_trunc_kernel, dim3(1), dim3(1024), 0, st, p, R.S1, R.sq);
+  hipLaunchKernelGGL(mul_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.invc, R.sk, R.fpos);
+  hipLaunchKernelGGL(mul_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.invr, R.sk, R.fpos + p);
+  HIP_TRY(launch_small_gemm(p, p, p, R.E2V + pp, p, true, R.Vs, p, false, R.fpos, nullptr, R.sq, R.Mu, p, st));
+  HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, true, R.Us, p, false, R.fpos + p, nullptr, R.sq, R.Mv, p, st));
   HIP_TRY(hipGetLastError());
   return CABS_OK;
 }
@@ -848,16 +790,11 @@ static cabs_status sketch_final(SketchRun& c) {
   if (fac) {
     const int p = pl.p2;
     RoundWs& R = S.r2;
-    if (p <= PCHOL_MAXP) {  // Cholesky route: M_u = diag(invc S) R_v^T V_s S_1^-1, M_v likewise
-      hipLaunchKernelGGL(mul_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.sq, R.sq, R.fneg);
-      HIP_TRY(launch_small_gemm(p, p, p, R.E2V + (size_t)p * p, p, true, R.Vs, p, false, R.fpos, nullptr, R.fneg,
-                                R.Mu, p, st));
-      HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, true, R.Us, p, false, R.fpos + p, nullptr, R.fneg, R.Mv, p, st));
-    } else {  // eigen route: M_u = diag(invc) E_u Lambda_u^-1/2 U_s
-      HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, false, R.Us, p, false, R.invc, R.fneg, nullptr, R.Mu, p, st));
-      HIP_TRY(launch_small_gemm(p, p, p, R.E2V + (size_t)p * p, p, false, R.Vs, p, false, R.invr, R.fneg + p, nullptr,
-                                R.Mv, p, st));
-    }
+    // M_u = diag(invc S) R_v^T V_s S_1^-1, M_v likewise
+    hipLaunchKernelGGL(mul_vec_kernel, dim3(1), dim3(1024), 0, st, p, R.sq, R.sq, R.fneg);
+    HIP_TRY(launch_small_gemm(p, p, p, R.E2V + (size_t)p * p, p, true, R.Vs, p, false, R.fpos, nullptr, R.fneg,
+                              R.Mu, p, st));
+    HIP_TRY(launch_small_gemm(p, p, p, R.E2V, p, true, R.Us, p, false, R.fpos + p, nullptr, R.fneg, R.Mv, p, st));
     HIP_TRY(launch_tsgemm(pl.m, p, p, pl.prec, R.Ch, R.Mu, out->Uf, nullptr, nullptr, R.ts_ws, st));
     HIP_TRY(launch_tsgemm(pl.n, p, p, pl.prec, R.Rh, R.Mv, out->Vf, nullptr, nullptr, R.ts_ws, st));
     // signs: largest-magnitude entry of each Uf column positive
@@ -905,7 +842,6 @@ static cabs_status sketch_advance(SketchRun& c, SvdJob& job) {
   const bool ortho = prm->orthogonalize != 0, fac = prm->want_factors != 0;
   job.n = 0;
   cabs_status s = CABS_OK;
-  bool eig = false;
   switch (c.phase) {
     case PH_START: {
       hipLaunchKernelGGL(diag_init_kernel, dim3(1), dim3(64), 0, st, c.diag, S.entries, c.counted ? 1 : 0);
@@ -936,21 +872,18 @@ static cabs_status sketch_advance(SketchRun& c, SvdJob& job) {
     case PH_R1_AFTER_W:
       // 4-5: pilot sketch and embedding maps
       s = round_after_w(c, S.r1, pl.kr1, pl.kc1, S.C, S.Rt, true, ortho, CABS_DIAG_RANK_PILOT, CABS_DIAG_SIGMA1_PILOT,
-                        job, eig);
+                        job);
       if (s != CABS_OK) return s;
       if (job.n) {
-        c.phase = eig ? PH_R1_AFTER_EIG : PH_R1_AFTER_K;
+        c.phase = PH_R1_AFTER_K;
         return CABS_OK;
       }
       s = sketch_middle(c);
       if (s != CABS_OK) return s;
       c.phase = PH_R2_AFTER_W;
       return sketch_followup_eval(c, job);
-    case PH_R1_AFTER_EIG:
-      c.phase = PH_R1_AFTER_K;
-      return round_after_eig(c, S.r1, pl.p1, job);
     case PH_R1_AFTER_K:
-      s = round_after_k(c, S.r1, pl.p1, pl.p1 > PCHOL_MAXP);
+      s = round_after_k(c, S.r1, pl.p1);
       if (s != CABS_OK) return s;
       s = sketch_middle(c);
       if (s != CABS_OK) return s;
@@ -958,19 +891,16 @@ static cabs_status sketch_advance(SketchRun& c, SvdJob& job) {
       return sketch_followup_eval(c, job);
     case PH_R2_AFTER_W:
       s = round_after_w(c, S.r2, pl.kr2, pl.kc2, out->C, out->Rt, fac, fac, CABS_DIAG_RANK_FINAL,
-                        CABS_DIAG_SIGMA1_FINAL, job, eig);
+                        CABS_DIAG_SIGMA1_FINAL, job);
       if (s != CABS_OK) return s;
       if (job.n) {
-        c.phase = eig ? PH_R2_AFTER_EIG : PH_R2_AFTER_K;
+        c.phase = PH_R2_AFTER_K;
         return CABS_OK;
       }
       c.phase = PH_DONE;
       return sketch_final(c);
-    case PH_R2_AFTER_EIG:
-      c.phase = PH_R2_AFTER_K;
-      return round_after_eig(c, S.r2, pl.p2, job);
     case PH_R2_AFTER_K:
-      s = round_after_k(c, S.r2, pl.p2, pl.p2 > PCHOL_MAXP);
+      s = round_after_k(c, S.r2, pl.p2);
       if (s != CABS_OK) return s;
       c.phase = PH_DONE;
       return sketch_final(c);

@@ -104,10 +104,13 @@ hipError_t launch_small_gemm(int M, int N, int K, const double* A, int lda, bool
                              bool transB, const double* dl, const double* dm, const double* dr, double* C, int ldc,
                              hipStream_t st);
 
-// Pivoted Cholesky of `batch` PSD p x p matrices (p <= PCHOL_MAXP): Rf row k = R's row k with columns in the
-// original order, rows from the numerical rank on zero (pivots <= tol stop the factorisation).
+// Pivoted Cholesky of `batch` PSD p x p matrices (p <= 1024): Rf row k = R's row k with columns in the
+// original order, rows from the numerical rank on zero (pivots <= tol stop the factorisation).  Up to
+// PCHOL_MAXP one work-group per matrix holds it in registers; above, one launch per step over many
+// work-groups, in ws (pchol_ws_bytes(batch, p) bytes).
+size_t pchol_ws_bytes(int batch, int p);
 hipError_t launch_pchol(int batch, int p, const double* G, int64_t strideG, double tol, double* Rf, int64_t strideR,
-                        hipStream_t st);
+                        void* ws, hipStream_t st);
 constexpr int PCHOL_MAXP = 204;
 
 // --- tall-skinny products, Grams, norms (tsgemm.hip) ---

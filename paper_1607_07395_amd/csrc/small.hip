@@ -242,10 +242,131 @@ __global__ __launch_bounds__(PC_THREADS) void pchol_kernel(int p, const double* 
   for (int e = tid; e < (p - k) * p; e += PC_THREADS) Rb[(int64_t)k * p + e] = 0.0;
 }
 
+// The same factorisation for p > PC_MAXP, one launch per step over many
+// work-groups, in a workspace per matrix: the Schur complement S (upper
+// triangle, row-major p x p), the remaining diagonal and the pivoted flags
+// (each double-buffered, so that a step reads the previous step's values while
+// it writes its own), and a stop word.  Step k: every work-group finds the
+// pivot the same way (largest remaining diagonal, lowest index on ties; stop
+// once it is <= tol), forms row k of R in LDS from the pivot's row and column
+// of S, work-group 0 writes it, and the work-groups update their rows of S
+// (rows dealt cyclically) and of the diagonal.  The pivot's row and column,
+// which the row is read from, are never updated, so the reads and the updates
+// of one step do not overlap.  Entries of R at indices pivoted earlier are
+// exact zeros, as in pchol_kernel.
+constexpr int PCG_WG = 32;  // work-groups per matrix
+
+struct PcgView {
+  double *S, *dg0, *dg1;
+  int *tk0, *tk1, *ctl;
+};
+__host__ __device__ inline size_t pcg_ws_doubles(int p) { return (size_t)p * p + 4 * (size_t)p + 8; }
+__device__ __forceinline__ PcgView pcg_view(void* ws, int p, int b) {
+  double* base = (double*)ws + (size_t)b * pcg_ws_doubles(p);
+  PcgView v;
+  v.S = base;
+  v.dg0 = base + (size_t)p * p;
+  v.dg1 = v.dg0 + p;
+  v.tk0 = (int*)(v.dg1 + p);
+  v.tk1 = v.tk0 + p;
+  v.ctl = v.tk1 + p;
+  return v;
+}
+
+size_t pchol_ws_bytes(int batch, int p) {
+  return p > PC_MAXP ? (size_t)batch * pcg_ws_doubles(p) * sizeof(double) + 256 : 256;
+}
+
+__global__ __launch_bounds__(256) void pcg_init_kernel(int p, const double* __restrict__ G, int64_t strideG,
+                                                       double* __restrict__ Rf, int64_t strideR, void* ws) {
+  const int b = blockIdx.y;
+  const PcgView v = pcg_view(ws, p, b);
+  const double* Gb = G + b * strideG;
+  double* Rb = Rf + b * strideR;
+  const int64_t pp = (int64_t)p * p;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < pp; e += (int64_t)gridDim.x * 256) {
+    v.S[e] = Gb[e];
+    Rb[e] = 0.0;
+  }
+  for (int c = blockIdx.x * 256 + threadIdx.x; c < p; c += gridDim.x * 256) {
+    v.dg0[c] = Gb[(int64_t)c * p + c];
+    v.tk0[c] = 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) v.ctl[0] = 0;
+}
+
+__global__ __launch_bounds__(256) void pcg_step_kernel(int p, int k, double tol, double* __restrict__ Rf,
+                                                       int64_t strideR, void* ws) {
+  __shared__ double rowk[1024];
+  __shared__ double wbd[4];
+  __shared__ int wbi[4];
+  const int b = blockIdx.y, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const PcgView v = pcg_view(ws, p, b);
+  if (v.ctl[0]) return;  // stopped at an earlier step
+  const double* dgc = (k & 1) ? v.dg1 : v.dg0;
+  double* dgn = (k & 1) ? v.dg0 : v.dg1;
+  const int* tkc = (k & 1) ? v.tk1 : v.tk0;
+  int* tkn = (k & 1) ? v.tk0 : v.tk1;
+  // pivot: largest remaining diagonal, lowest index on ties (commutative, so any order gives it)
+  double bd = -1.0;
+  int bi = 0x7fffffff;
+  for (int c = tid; c < p; c += 256)
+    if (!tkc[c]) {
+      const double d = dgc[c];
+      if (d > bd || (d == bd && c < bi)) { bd = d; bi = c; }
+    }
+  for (int off = 1; off < 64; off <<= 1) {
+    const double od = __shfl_xor(bd, off, 64);
+    const int oi = __shfl_xor(bi, off, 64);
+    if (od > bd || (od == bd && oi < bi)) { bd = od; bi = oi; }
+  }
+  if (lane == 0) { wbd[wave] = bd; wbi[wave] = bi; }
+  __syncthreads();
+  double d = wbd[0];
+  int piv = wbi[0];
+  for (int w = 1; w < 4; ++w)
+    if (wbd[w] > d || (wbd[w] == d && wbi[w] < piv)) { d = wbd[w]; piv = wbi[w]; }
+  if (!(d > tol)) {  // uniform: nothing left above the threshold; rows k.. of R stay zero
+    if (blockIdx.x == 0 && tid == 0) v.ctl[0] = 1;
+    return;
+  }
+  const double rkk = sqrt(d);
+  const double inv = 1.0 / rkk;
+  // row k of R: the pivot's row of S (upper triangle: S[piv][c] for c > piv, S[c][piv] for c < piv)
+  for (int c = tid; c < p; c += 256) {
+    double r = 0.0;
+    if (!tkc[c]) r = c == piv ? rkk : (c > piv ? v.S[(int64_t)piv * p + c] : v.S[(int64_t)c * p + piv]) * inv;
+    rowk[c] = r;
+  }
+  __syncthreads();
+  if (blockIdx.x == 0)
+    for (int c = tid; c < p; c += 256) Rf[b * strideR + (int64_t)k * p + c] = rowk[c];
+  // this work-group's rows: the flags and diagonal for the next step, and the Schur update
+  for (int i = blockIdx.x; i < p; i += gridDim.x) {
+    const bool live = !tkc[i] && i != piv;
+    if (tid == 0) {
+      tkn[i] = live ? 0 : 1;
+      dgn[i] = live ? dgc[i] - rowk[i] * rowk[i] : dgc[i];
+    }
+    if (!live) continue;  // uniform
+    const double ri = rowk[i];
+    double* Si = v.S + (int64_t)i * p;
+    for (int j = i + tid; j < p; j += 256)
+      if (!tkc[j] && j != piv) Si[j] -= ri * rowk[j];
+  }
+}
+
 hipError_t launch_pchol(int batch, int p, const double* G, int64_t strideG, double tol, double* Rf, int64_t strideR,
-                        hipStream_t st) {
-  if (batch <= 0 || p <= 0 || p > PC_MAXP) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(pchol_kernel, dim3(batch), dim3(PC_THREADS), 0, st, p, G, strideG, tol, Rf, strideR);
+                        void* ws, hipStream_t st) {
+  if (batch <= 0 || p <= 0 || p > 1024) return hipErrorInvalidValue;
+  if (p <= PC_MAXP) {
+    hipLaunchKernelGGL(pchol_kernel, dim3(batch), dim3(PC_THREADS), 0, st, p, G, strideG, tol, Rf, strideR);
+    return hipGetLastError();
+  }
+  if (!ws) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(pcg_init_kernel, dim3(64, batch), dim3(256), 0, st, p, G, strideG, Rf, strideR, ws);
+  for (int k = 0; k < p; ++k)
+    hipLaunchKernelGGL(pcg_step_kernel, dim3(PCG_WG, batch), dim3(256), 0, st, p, k, tol, Rf, strideR, ws);
   return hipGetLastError();
 }
 

@@ -136,7 +136,7 @@ def _shape_class(api, compute, k, follow_up="kmeans", seeds=(3, 4, 5, 6)):
 
 @pytest.mark.parametrize("compute,k,follow_up,count", [
     ("f32", 64, "kmeans", 4),      # pivoted Cholesky route: one SVD item per request
-    ("bf16", 240, "kmeans", 4),    # eigen route (p > 204): two items per request, 8 in one launch
+    ("bf16", 240, "kmeans", 4),    # p > 204: step-per-launch Cholesky, SVDs of 4 requests per launch
     ("f64", 20, "leverage", 3),    # the one-work-group SVD (p < 24)
     ("f32", 48, "pilot", 2),       # the pilot sketch alone: one SVD per request
 ])

@@ -70,16 +70,16 @@ def test_sketch_f64_rbf_full_config(api):
     assert e[2] == pytest.approx(want, rel=1e-10)
 
 
-def test_sketch_f64_eigen_orthogonalisation_route(api):
-    """p = 256 > 204 kept-or-dropped components: the orthogonalisation eigen-decomposes both Grams
-    (the route the 1e6 x 1e6 RBF configuration's k = 500 takes) instead of the pivoted Cholesky;
-    3000-point RBF kernel, FP64, follow-up indices bit-exact with the oracle."""
+def test_sketch_f64_large_p_orthogonalisation(api):
+    """p = 256 > 204 components: the orthogonalisation factors both Grams with the step-per-launch
+    pivoted Cholesky (the one the 1e6 x 1e6 RBF configuration's k = 500 takes) instead of the
+    register-resident one; 3000-point RBF kernel, FP64, follow-up indices bit-exact with the oracle."""
     spec, _ = workloads.config("rbf2000", 1.5)
     _compare_f64(api, spec, dict(k1_rows=256, k1_cols=256, k2_rows=256, k2_cols=256, seed=2))
 
 
-def test_sketch_f64_eigen_route_rectangular(api):
-    """The eigen route with different row and column sample sizes (p = min = 230)."""
+def test_sketch_f64_large_p_rectangular(api):
+    """The same with different row and column sample sizes (p = min = 230)."""
     spec = workloads.lowrank_noise(4000, 2500, 260, seed=6, noise_std=1e-2, s_kind="scaled")
     _compare_f64(api, spec, dict(k1_rows=240, k1_cols=230, k2_rows=235, k2_cols=250, seed=4))
 
