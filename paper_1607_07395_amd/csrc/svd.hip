@@ -344,26 +344,28 @@ __device__ __forceinline__ f64x4 pair_gram(const BjView& v, int ba, int bb, int 
   return acc;
 }
 
-// The same Gram for at most 64 rows [r0, r1): the 16 row quads are loaded by
+// The same Gram for at most 4 NQ rows [r0, r1): the NQ row quads are loaded by
 // pair_x_load in one batch, then multiplied and kept in the LDS stash.
-__device__ __forceinline__ void pair_x_load(const BjView& v, int ba, int bb, int r0, int r1, double (&x)[16]) {
+template <int NQ>
+__device__ __forceinline__ void pair_x_load(const BjView& v, int ba, int bb, int r0, int r1, double (&x)[NQ]) {
   const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
   const int mycol = c16 < 8 ? ba * BJ_B + c16 : bb * BJ_B + c16 - 8;
   const double* xc = v.X + mycol;
 #pragma unroll
-  for (int u = 0; u < 16; ++u) {
+  for (int u = 0; u < NQ; ++u) {
     const int rr = r0 + 4 * u + g;
     x[u] = *(rr < r1 ? xc + (size_t)rr * v.P : (const double*)kBjZero);
   }
 }
 
-__device__ __forceinline__ f64x4 pair_gram_regs(const double (&x)[16], int r0, int r1, double (*xs)[17]) {
+template <int NQ>
+__device__ __forceinline__ f64x4 pair_gram_regs(const double (&x)[NQ], int r0, int r1, double (*xs)[17]) {
   const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
   f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int u = 0; u < 16; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u], x[u], acc, 0, 0, 0);
+  for (int u = 0; u < NQ; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u], x[u], acc, 0, 0, 0);
 #pragma unroll
-  for (int u = 0; u < 16; ++u) {
+  for (int u = 0; u < NQ; ++u) {
     const int rr = r0 + 4 * u + g;
     if (rr < r1) xs[rr][c16] = x[u];
   }
@@ -444,24 +446,25 @@ __device__ __forceinline__ bool jacobi_rot(double al, double be, double ga, doub
 }
 
 // Rotation of the pair's columns when the X rows sit in the LDS stash (q <=
-// BJ_QS): wave w rotates X tiles w, w + 4, ... from LDS and V tiles w, w + 4,
+// 256 NU): wave w rotates X tiles w, w + 4, ... from LDS and V tiles w, w + 4,
 // ... from vv, which it loaded before the inner solve.  jb[st] = J[4 st + g][c16].
-constexpr int BJ_QS = 256;
+// The stash holds 256 rows (NU = 1) or 512 (NU = 2, one workgroup per CU for
+// its LDS); matrices with more rows read X from global memory twice.
+constexpr int BJ_QS1 = 256;
 
 // With the stash, the 16-row tiles of X and of V are split between the
 // BJ_SPLIT workgroups of a pair: workgroup s, wave w rotates tiles
-// s + BJ_SPLIT (w + 4 u), u < BJ_NU, of each (q, P <= BJ_QS = 16 tiles).
+// s + BJ_SPLIT (w + 4 u), u < NU, of each (q, P <= 256 NU = 16 NU tiles).
 constexpr int BJ_SPLIT = 4;
-constexpr int BJ_NU = 4 / BJ_SPLIT;
 
 __device__ __forceinline__ int pair_tile(int s, int wave, int u) { return s + BJ_SPLIT * (wave + 4 * u); }
 
-__device__ __forceinline__ void pair_v_load(const BjView& v, int ba, int bb, int s, int wave,
-                                            double (&vv)[BJ_NU][4]) {
+template <int NU>
+__device__ __forceinline__ void pair_v_load(const BjView& v, int ba, int bb, int s, int wave, double (&vv)[NU][4]) {
   const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
   const int vt = v.P >> 4;
 #pragma unroll
-  for (int u = 0; u < BJ_NU; ++u) {
+  for (int u = 0; u < NU; ++u) {
     const int t = pair_tile(s, wave, u), rr = t * 16 + c16;
     const bool in = t < vt && rr < v.P;
 #pragma unroll
@@ -473,15 +476,15 @@ __device__ __forceinline__ void pair_v_load(const BjView& v, int ba, int bb, int
   }
 }
 
+template <int NU>
 __device__ __forceinline__ void pair_apply_stash(const BjView& v, double* xo, int ba, int bb, const double (&jb)[4],
-                                                 int s, int wave, const double (*xs)[17],
-                                                 const double (&vv)[BJ_NU][4]) {
+                                                 int s, int wave, const double (*xs)[17], const double (&vv)[NU][4]) {
   const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
   const int qt = (v.q + 15) >> 4, vt = v.P >> 4;
   const int outcol = c16 < 8 ? ba * BJ_B + c16 : bb * BJ_B + c16 - 8;
-  f64x4 dx[BJ_NU], dv[BJ_NU];
+  f64x4 dx[NU], dv[NU];
 #pragma unroll
-  for (int u = 0; u < BJ_NU; ++u) {
+  for (int u = 0; u < NU; ++u) {
     const int t = pair_tile(s, wave, u), rr = t * 16 + c16;
     double a[4];
 #pragma unroll
@@ -495,7 +498,7 @@ __device__ __forceinline__ void pair_apply_stash(const BjView& v, double* xo, in
     }
   }
 #pragma unroll
-  for (int u = 0; u < BJ_NU; ++u) {
+  for (int u = 0; u < NU; ++u) {
     const int t = pair_tile(s, wave, u);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -507,13 +510,14 @@ __device__ __forceinline__ void pair_apply_stash(const BjView& v, double* xo, in
 }
 
 // A pair that does not rotate carries its columns of X over to the other copy.
+template <int NU>
 __device__ __forceinline__ void pair_copy_stash(const BjView& v, double* xo, int ba, int bb, int s, int wave,
                                                 const double (*xs)[17]) {
   const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
   const int qt = (v.q + 15) >> 4;
   const int outcol = c16 < 8 ? ba * BJ_B + c16 : bb * BJ_B + c16 - 8;
 #pragma unroll
-  for (int u = 0; u < BJ_NU; ++u) {
+  for (int u = 0; u < NU; ++u) {
     const int t = pair_tile(s, wave, u);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -547,11 +551,12 @@ __device__ __forceinline__ void pair_copy(const BjView& v, double* xo, int ba, i
 // step (and the matching block of J), computes both rotations itself, and
 // writes the rotated block to the other half of a double buffer.
 
+template <int NU>
 __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int round, int sweep, SvdItems it) {
   __shared__ double gp[4][16][17];
   __shared__ double Gb[2][16][17];
   __shared__ double Jb[2][16][17];
-  __shared__ double xs[BJ_QS][17];
+  __shared__ double xs[BJ_QS1 * NU][17];
   __shared__ int any_off;
   BjView v = bj_view(item_w(it, blockIdx.y), rows, cols);
   const int gr = sweep * (v.nb - 1) + round;
@@ -560,17 +565,17 @@ __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int r
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, c16 = lane & 15, g = lane >> 4;
   const int pr = blockIdx.x / BJ_SPLIT, share = blockIdx.x % BJ_SPLIT;
   const int ba = circle_pos(pr, round, v.nb), bb = circle_pos(v.nb - 1 - pr, round, v.nb);
-  const bool stash = v.q <= BJ_QS;  // uniform
+  const bool stash = v.q <= BJ_QS1 * NU;  // uniform
   // A sweep without rotations leaves X as it was (copied to the other copy),
   // so every later sweep would find none either: the matrix has converged,
   // and the rounds still launched return at once.
   if (sweep > 0 && v.flags[2 + sweep - 1] == 0) return;  // uniform over the grid
-  double vv[BJ_NU][4];
+  double vv[NU][4];
   {
     const int r0 = (int)(((int64_t)v.q * wave) / 4), r1 = (int)(((int64_t)v.q * (wave + 1)) / 4);
     f64x4 acc;
-    if (stash) {  // r1 - r0 <= BJ_QS / 4 = 64 rows: one batch of loads
-      double x[16];
+    if (stash) {  // r1 - r0 <= 64 NU rows: one batch of loads
+      double x[16 * NU];
       pair_x_load(v, ba, bb, r0, r1, x);
       pair_v_load(v, ba, bb, share, wave, vv);  // in flight during the inner solve
       acc = pair_gram_regs(x, r0, r1, xs);
@@ -667,7 +672,7 @@ __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int r
   __syncthreads();
   const int ao = any_off;
   if (!ao) {  // uniform
-    if (stash) pair_copy_stash(v, xo, ba, bb, share, wave, xs);
+    if (stash) pair_copy_stash<NU>(v, xo, ba, bb, share, wave, xs);
     else pair_copy(v, xo, ba, bb, share + BJ_SPLIT * wave, 4 * BJ_SPLIT);
     return;
   }
@@ -880,9 +885,14 @@ hipError_t launch_svd_items(int batch, int rows, int cols, const SvdItems& it, h
                      st, rows, cols, it);
   hipLaunchKernelGGL(bj_norm_kernel, dim3(batch), dim3(1024), 0, st, rows, cols, it);
   for (int sweep = 0; sweep < fast_sweeps; ++sweep) {
-    for (int round = 0; round < nb - 1; ++round)
-      hipLaunchKernelGGL(bj_round_kernel, dim3(nb / 2 * BJ_SPLIT, batch), dim3(256), 0, st, rows, cols, round, sweep,
-                         it);
+    for (int round = 0; round < nb - 1; ++round) {
+      if (q > BJ_QS1 && q <= 2 * BJ_QS1)
+        hipLaunchKernelGGL(bj_round_kernel<2>, dim3(nb / 2 * BJ_SPLIT, batch), dim3(256), 0, st, rows, cols, round,
+                           sweep, it);
+      else
+        hipLaunchKernelGGL(bj_round_kernel<1>, dim3(nb / 2 * BJ_SPLIT, batch), dim3(256), 0, st, rows, cols, round,
+                           sweep, it);
+    }
   }
   hipLaunchKernelGGL(bj_finish_kernel, dim3(batch), dim3(1024), 0, st, rows, cols, fast_sweeps, it);
   return hipGetLastError();

@@ -172,12 +172,14 @@ def test_svd_against_lapack(api, rows, cols, seed):
             assert np.abs(V[:, j] - v0[:, j]).max() <= tol, j
 
 
-@pytest.mark.parametrize("rows,cols,seed", [(240, 240, 14), (256, 200, 16), (250, 250, 15)])
+@pytest.mark.parametrize("rows,cols,seed", [(240, 240, 14), (256, 200, 16), (250, 250, 15), (512, 512, 17),
+                                            (300, 480, 18), (257, 100, 19)])
 def test_svd_block_path_unscaled(api, rows, cols, seed):
     """Ungraded Gaussian matrices on the block path: their Jacobi runs end at
     different sweep counts (odd and even, up to the last sweep of the
     multi-work-group phase), so the outputs come from either copy of the
-    working columns."""
+    working columns.  The long side spans both LDS stash sizes of the round
+    kernel (up to 256 and 257-512 rows)."""
     rng = np.random.default_rng(seed)
     a = rng.normal(size=(rows, cols))
     U, S, V = (x.cpu().numpy() for x in api.svd(torch.from_numpy(a).cuda()))
