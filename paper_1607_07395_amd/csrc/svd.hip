@@ -28,6 +28,8 @@ constexpr int SVD_LDS_BYTES = 60 * 1024;
 __host__ __device__ static inline int even_up(int p) { return p + (p & 1); }
 
 constexpr int BJ_B = 8;               // columns per block of the block-Jacobi path
+constexpr int BJ_QS1 = 256;           // rows of X a round kernel with NU = 1 keeps in LDS (NU = 2: 512)
+constexpr int BJ_SPLIT = 4;           // workgroups per pair of blocks in a round
 constexpr int BJ_MAX_SWEEPS = 40;
 constexpr int BJ_INNER_SWEEPS = 1;   // inner sweeps per pair and round in the finishing kernel
                                       // (one: more outer sweeps, each cheaper; 2 was slower)
@@ -316,10 +318,8 @@ __global__ __launch_bounds__(1024) void bj_norm_kernel(int rows, int cols, SvdIt
 static __device__ double kBjZero[2] = {0.0, 0.0};
 
 // Gram of the 16 columns cols(c) = block ba (c < 8) / bb (c >= 8), rows [r0, r1), by one wave;
-// 8 row quads are loaded before their MFMAs.  With a stash, the rows are also
-// kept in LDS (xs[row][c]) for the rotation that follows.
-__device__ __forceinline__ f64x4 pair_gram(const BjView& v, int ba, int bb, int r0, int r1,
-                                           double (*xs)[17] = nullptr) {
+// 8 row quads are loaded before their MFMAs.
+__device__ __forceinline__ f64x4 pair_gram(const BjView& v, int ba, int bb, int r0, int r1) {
   const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
   const int mycol = c16 < 8 ? ba * BJ_B + c16 : bb * BJ_B + c16 - 8;
   const double* xc = v.X + mycol;
@@ -333,13 +333,6 @@ __device__ __forceinline__ f64x4 pair_gram(const BjView& v, int ba, int bb, int 
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u], x[u], acc, 0, 0, 0);
-    if (xs != nullptr) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int rr = r + 4 * u + g;
-        if (rr < r1) xs[rr][c16] = x[u];
-      }
-    }
   }
   return acc;
 }
@@ -358,16 +351,19 @@ __device__ __forceinline__ void pair_x_load(const BjView& v, int ba, int bb, int
   }
 }
 
+// Rows of the tiles workgroup `share` rotates go to its stash (BJ_SPLIT tiles
+// apart: stash row 16 (t / BJ_SPLIT) + i for row i of tile t).
 template <int NQ>
-__device__ __forceinline__ f64x4 pair_gram_regs(const double (&x)[NQ], int r0, int r1, double (*xs)[17]) {
+__device__ __forceinline__ f64x4 pair_gram_regs(const double (&x)[NQ], int r0, int r1, int share,
+                                                double (*xs)[17]) {
   const int lane = threadIdx.x & 63, c16 = lane & 15, g = lane >> 4;
   f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int u = 0; u < NQ; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u], x[u], acc, 0, 0, 0);
 #pragma unroll
   for (int u = 0; u < NQ; ++u) {
-    const int rr = r0 + 4 * u + g;
-    if (rr < r1) xs[rr][c16] = x[u];
+    const int rr = r0 + 4 * u + g, t = rr >> 4;
+    if (rr < r1 && t % BJ_SPLIT == share) xs[(t / BJ_SPLIT) * 16 + (rr & 15)][c16] = x[u];
   }
   return acc;
 }
@@ -446,16 +442,16 @@ __device__ __forceinline__ bool jacobi_rot(double al, double be, double ga, doub
 }
 
 // Rotation of the pair's columns when the X rows sit in the LDS stash (q <=
-// 256 NU): wave w rotates X tiles w, w + 4, ... from LDS and V tiles w, w + 4,
-// ... from vv, which it loaded before the inner solve.  jb[st] = J[4 st + g][c16].
-// The stash holds 256 rows (NU = 1) or 512 (NU = 2, one workgroup per CU for
-// its LDS); matrices with more rows read X from global memory twice.
-constexpr int BJ_QS1 = 256;
-
+// 256 NU): wave w rotates its X tiles from LDS and its V tiles from vv, which
+// it loaded before the inner solve.  jb[st] = J[4 st + g][c16].  Matrices with
+// more than 512 rows read X from global memory twice.
+//
 // With the stash, the 16-row tiles of X and of V are split between the
 // BJ_SPLIT workgroups of a pair: workgroup s, wave w rotates tiles
-// s + BJ_SPLIT (w + 4 u), u < NU, of each (q, P <= 256 NU = 16 NU tiles).
-constexpr int BJ_SPLIT = 4;
+// s + BJ_SPLIT (w + 4 u), u < NU, of each (q, P <= 256 NU = 16 NU tiles), and
+// its stash holds only those X tiles (64 NU rows, stash row 16 (w + 4 u) + i
+// for row i of tile s + BJ_SPLIT (w + 4 u)), so that the kernel's LDS stays
+// small enough to share a CU with other kernels' work-groups.
 
 __device__ __forceinline__ int pair_tile(int s, int wave, int u) { return s + BJ_SPLIT * (wave + 4 * u); }
 
@@ -488,7 +484,7 @@ __device__ __forceinline__ void pair_apply_stash(const BjView& v, double* xo, in
     const int t = pair_tile(s, wave, u), rr = t * 16 + c16;
     double a[4];
 #pragma unroll
-    for (int st = 0; st < 4; ++st) a[st] = (t < qt && rr < v.q) ? xs[rr][4 * st + g] : 0.0;
+    for (int st = 0; st < 4; ++st) a[st] = (t < qt && rr < v.q) ? xs[(wave + 4 * u) * 16 + c16][4 * st + g] : 0.0;
     dx[u] = f64x4{0.0, 0.0, 0.0, 0.0};
     dv[u] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -522,7 +518,7 @@ __device__ __forceinline__ void pair_copy_stash(const BjView& v, double* xo, int
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int r = t * 16 + out_row<double>(g, i);
-      if (t < qt && r < v.q) xo[(size_t)r * v.P + outcol] = xs[r][c16];
+      if (t < qt && r < v.q) xo[(size_t)r * v.P + outcol] = xs[(wave + 4 * u) * 16 + out_row<double>(g, i)][c16];
     }
   }
 }
@@ -556,7 +552,7 @@ __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int r
   __shared__ double gp[4][16][17];
   __shared__ double Gb[2][16][17];
   __shared__ double Jb[2][16][17];
-  __shared__ double xs[BJ_QS1 * NU][17];
+  __shared__ double xs[BJ_QS1 * NU / BJ_SPLIT][17];
   __shared__ int any_off;
   BjView v = bj_view(item_w(it, blockIdx.y), rows, cols);
   const int gr = sweep * (v.nb - 1) + round;
@@ -578,9 +574,9 @@ __global__ __launch_bounds__(256) void bj_round_kernel(int rows, int cols, int r
       double x[16 * NU];
       pair_x_load(v, ba, bb, r0, r1, x);
       pair_v_load(v, ba, bb, share, wave, vv);  // in flight during the inner solve
-      acc = pair_gram_regs(x, r0, r1, xs);
+      acc = pair_gram_regs(x, r0, r1, share, xs);
     } else {
-      acc = pair_gram(v, ba, bb, r0, r1, nullptr);
+      acc = pair_gram(v, ba, bb, r0, r1);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) gp[wave][out_row<double>(g, i)][c16] = acc[i];
