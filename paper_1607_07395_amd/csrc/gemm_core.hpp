@@ -61,6 +61,16 @@ __device__ __forceinline__ double widen(double v) { return v; }
 // loads need no branches (internal to each code object; never written).
 static __device__ double4 kTileZero[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
 
+// A raw buffer resource over [base, base + bytes) for direct-to-LDS loads:
+// offsets at or past the end (kBufOob) read zeros.  Buffer loads are not FLAT
+// instructions; a FLAT load into LDS (global_load_lds) that is in flight makes
+// the compiler wait for every outstanding LDS read at each use (lgkmcnt(0)),
+// which undoes the read-ahead of B fragments in the MFMA loops.
+constexpr uint32_t kBufOob = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t lds_src_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)bytes, 0x00020000);
+}
+
 // One 16-byte run of MFMA fragments: element s of the run as the fragment of
 // MFMA step s (FP32, FP64: one element per step; 16-bit types: the whole run).
 template <typename TC> struct Vec16;

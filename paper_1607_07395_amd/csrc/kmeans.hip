@@ -185,9 +185,9 @@ __global__ __launch_bounds__(256) void assign_kernel(int64_t rows, int dim, int 
 // of B, so RT = 1 suffices there.
 //
 // Chunks are double-buffered in two LDS arrays and filled by direct
-// global-to-LDS loads (global_load_lds_dwordx4: lane l's 16 bytes land at
+// buffer-to-LDS loads (buffer_load_dwordx4 ... lds: lane l's 16 bytes land at
 // 16 l past the wave's LDS address, so one instruction fills one 1 KB
-// fragment block).  Chunk c + 1 is in flight while chunk c is multiplied, and
+// fragment block; offsets past the centres read zeros).  Chunk c + 1 is in flight while chunk c is multiplied, and
 // no registers hold it.  The two arrays are distinct objects, so the compiler
 // knows that reads of one do not wait for loads into the other; the explicit
 // vmcnt(0) + barrier before a chunk is used is the only wait.  NKB (k blocks)
@@ -227,6 +227,7 @@ __global__ __launch_bounds__(256, OCC) void assign_fast_kernel(int64_t rows, int
   const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * RT);
   const int cbeg = (int)blockIdx.y * gsize;
   const int cend = cbeg + gsize < k ? cbeg + gsize : k;
+  const __amdgpu_buffer_rsrc_t zrs = lds_src_rsrc(Zc, (uint32_t)k * (uint32_t)dim * (uint32_t)sizeof(TC));
   uint4 a[RT][NKB];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
@@ -242,8 +243,8 @@ __global__ __launch_bounds__(256, OCC) void assign_fast_kernel(int64_t rows, int
       if (NBLK % 4 == 0 || blk < NBLK) {
         const int t = blk / NKB, kb = blk - t * NKB;
         const int c = cc + 16 * t + c16, k0 = kb * KBW + g * VE;
-        const TC* src = (c < k && k0 < dim) ? Zc + (int64_t)c * dim + k0 : (const TC*)kTileZero;
-        __builtin_amdgcn_global_load_lds((const void*)src, CABS_LDS_PTR(dst + blk * 64), 16, 0, 0);
+        const uint32_t off = (c < k && k0 < dim) ? ((uint32_t)c * dim + k0) * (uint32_t)sizeof(TC) : kBufOob;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(zrs, CABS_LDS_PTR(dst + blk * 64), 16, off, 0, 0, 0);
       }
     }
 #pragma unroll

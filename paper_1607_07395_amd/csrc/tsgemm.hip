@@ -94,8 +94,8 @@ __global__ __launch_bounds__(256) void tsgemm_kernel(int64_t M, int K, int Kp, i
 // whole kernel (RT row tiles of 16 per wave) and streams B^T through LDS in
 // chunks of CT column tiles, stored in fragment order (each B read is one
 // contiguous 16-byte LDS read per lane).  Chunks are double-buffered in two
-// LDS arrays filled by direct global-to-LDS loads (one global_load_lds_dwordx4
-// per 1 KB fragment block), so chunk c + 1 is in flight while chunk c is
+// LDS arrays filled by direct buffer-to-LDS loads (one buffer_load_dwordx4 ...
+// lds per 1 KB fragment block), so chunk c + 1 is in flight while chunk c is
 // multiplied; the B fragments of k block kb + D are read while block kb is
 // multiplied.  B^T is stored with its rows padded to whole runs (zeros), so
 // every B load is a whole run; rows of X that are not whole runs (K not a
@@ -177,6 +177,7 @@ __global__ __launch_bounds__(256, OCC) void tsgemm_fast_kernel(int64_t M, int K,
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int g = lane >> 4, c16 = lane & 15;
   const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * RT);
+  const __amdgpu_buffer_rsrc_t brs = lds_src_rsrc(Bt, (uint32_t)N * (uint32_t)Kp * (uint32_t)sizeof(TC));
   uint4 a[RT][NKB];
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt)
@@ -189,8 +190,8 @@ __global__ __launch_bounds__(256, OCC) void tsgemm_fast_kernel(int64_t M, int K,
       if (NBLK % 4 == 0 || blk < NBLK) {
         const int t = blk / NKB, kb = blk - t * NKB;
         const int c = cc + 16 * t + c16, k0 = kb * KBW + g * VE;
-        const TC* src = (c < N && k0 < Kp) ? Bt + (int64_t)c * Kp + k0 : (const TC*)kTileZero;
-        __builtin_amdgcn_global_load_lds((const void*)src, CABS_TS_LDS_PTR(dst + blk * 64), 16, 0, 0);
+        const uint32_t off = (c < N && k0 < Kp) ? ((uint32_t)c * Kp + k0) * (uint32_t)sizeof(TC) : kBufOob;
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(brs, CABS_TS_LDS_PTR(dst + blk * 64), 16, off, 0, 0, 0);
       }
     }
   };
@@ -310,7 +311,7 @@ static int64_t tsf_launch_i(int nkb, hipStream_t st, int64_t M, int K, int Kp, i
 // (Y = X B only), X rows and B^T rows whole 16-byte runs (K even): 128 x 128
 // output tiles, 4 waves each owning a 64 x 64 quarter (16 MFMA tiles of
 // 16x16x4 FP64).  K runs in stages of 16, double-
-// buffered in LDS and filled by direct global-to-LDS loads; a stage holds
+// buffered in LDS and filled by direct buffer-to-LDS loads; a stage holds
 // pairs of consecutive k of every row, ordered [pair][row], so one 16-byte LDS
 // read gives a lane its operand for two MFMA steps.  The contraction order is
 // free: in stage s, pair group t and step sigma, lane group g takes
@@ -333,6 +334,10 @@ __global__ __launch_bounds__(256, 1) void tsgemm_f64_kernel(int64_t M, int K, in
   const int col0 = ct * TF_W;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, r = lane & 15, g = lane >> 4;
   const int wr = wave >> 1, wc = wave & 1;
+  // this tile's rows of X, and B^T, as buffers (offsets past them read zeros)
+  const int64_t nrow = M - row0 < TF_W ? M - row0 : TF_W;
+  const __amdgpu_buffer_rsrc_t xrs = lds_src_rsrc(X + row0 * K, (uint32_t)(nrow * K * (int64_t)sizeof(double)));
+  const __amdgpu_buffer_rsrc_t brs = lds_src_rsrc(Bt, (uint32_t)N * (uint32_t)Kp * (uint32_t)sizeof(double));
   // stage loads: instruction i (0..15) of an operand fills pair i / 2, rows / columns 64 (i & 1) .. + 63
   auto issue = [&](uint4* da, uint4* db, int s) {
 #pragma unroll
@@ -341,11 +346,11 @@ __global__ __launch_bounds__(256, 1) void tsgemm_f64_kernel(int64_t M, int K, in
       const int p = i >> 1, rr = ((i & 1) << 6) + lane;
       const int k0 = s * TF_KT + 2 * p;
       const int64_t xr = row0 + rr;
-      const double* xa = (xr < M && k0 < K) ? X + xr * K + k0 : (const double*)kTileZero;
-      __builtin_amdgcn_global_load_lds((const void*)xa, CABS_TS_LDS_PTR(da + i * 64), 16, 0, 0);
+      const uint32_t xo = (xr < M && k0 < K) ? ((uint32_t)rr * K + k0) * (uint32_t)sizeof(double) : kBufOob;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(xrs, CABS_TS_LDS_PTR(da + i * 64), 16, xo, 0, 0, 0);
       const int bc = col0 + rr;
-      const double* xb = (bc < N && k0 < Kp) ? Bt + (int64_t)bc * Kp + k0 : (const double*)kTileZero;
-      __builtin_amdgcn_global_load_lds((const void*)xb, CABS_TS_LDS_PTR(db + i * 64), 16, 0, 0);
+      const uint32_t bo = (bc < N && k0 < Kp) ? ((uint32_t)bc * Kp + k0) * (uint32_t)sizeof(double) : kBufOob;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(brs, CABS_TS_LDS_PTR(db + i * 64), 16, bo, 0, 0, 0);
     }
   };
   f64x4 acc[4][4];
