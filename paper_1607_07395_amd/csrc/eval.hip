@@ -108,6 +108,7 @@ struct EvalArgs {
   double noise_std; uint64_t noise_seed;
   double inv2s2;                            // 1 / (2 sigma^2)
   unsigned long long* counter;              // entries evaluated (may be null)
+  int64_t rb0;                              // first row block of the launch (set by eval_dispatch_src)
 };
 
 // Adds a lane's count of entries to the counter: one atomic per wavefront.
@@ -123,14 +124,25 @@ __device__ __forceinline__ void count_entries(unsigned long long* counter, int c
 // equal on the 10^5 x 200 low-rank block.
 constexpr int EVAL_NT = 5;
 
+// Work-group b of a launch evaluates row block rb0 + rb and column group cg
+// (80 columns) with b = 8 (ncg (rb / 8) + cg) + rb mod 8: work-groups are
+// dealt to the XCDs in turn, so the column groups of one row block run on the
+// same XCD, close in time, and its L2 serves their shared rows of X (read from
+// HBM once, not once per column group).  Launches cover at most EVAL_MAX_RB
+// row blocks.
+constexpr int64_t EVAL_MAX_RB = (int64_t)1 << 20;
+
 template <typename TIn, typename TC, int SRC>
 __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a) {
   typedef typename Mfma<TC>::acc AccV;
   typedef typename NormT<TIn>::type NrmT;
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
-  const int64_t col0 = (int64_t)blockIdx.y * EVAL_NT * 16;
+  const int64_t ncg = (a.N + EVAL_NT * 16 - 1) / (EVAL_NT * 16);
+  const int64_t slot = blockIdx.x >> 3;
+  const int64_t rb = a.rb0 + (slot / ncg) * 8 + (blockIdx.x & 7), cg = slot % ncg;
+  const int64_t row0 = (rb * 4 + wave) * 16;
+  const int64_t col0 = cg * EVAL_NT * 16;
   if (row0 >= a.M) return;
   AccV acc[EVAL_NT];
   NrmT xsq, ysq[EVAL_NT];
@@ -176,11 +188,17 @@ __global__ __launch_bounds__(256) void eval_kernel(EvalArgs a) {
 }
 
 template <typename TIn, typename TC>
-static hipError_t eval_dispatch_src(int src, const EvalArgs& a, dim3 grid, hipStream_t st) {
-  if (src == SRC_LOWRANK)
-    hipLaunchKernelGGL((eval_kernel<TIn, TC, SRC_LOWRANK>), grid, dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL((eval_kernel<TIn, TC, SRC_RBF>), grid, dim3(256), 0, st, a);
+static hipError_t eval_dispatch_src(int src, EvalArgs a, hipStream_t st) {
+  const int64_t nrb = ceil_div(a.M, 64), ncg = ceil_div(a.N, EVAL_NT * 16);
+  for (int64_t rb0 = 0; rb0 < nrb; rb0 += EVAL_MAX_RB) {
+    a.rb0 = rb0;
+    const int64_t nb = nrb - rb0 < EVAL_MAX_RB ? nrb - rb0 : EVAL_MAX_RB;
+    const dim3 grid((unsigned)(ceil_div(nb, 8) * 8 * ncg));
+    if (src == SRC_LOWRANK)
+      hipLaunchKernelGGL((eval_kernel<TIn, TC, SRC_LOWRANK>), grid, dim3(256), 0, st, a);
+    else
+      hipLaunchKernelGGL((eval_kernel<TIn, TC, SRC_RBF>), grid, dim3(256), 0, st, a);
+  }
   return hipGetLastError();
 }
 
@@ -350,15 +368,14 @@ hipError_t launch_eval(const MatView& mv, bool rows_t, const int64_t* idx, int k
   a.noise_std = mv.noise_std;
   a.noise_seed = mv.noise_seed;
   a.counter = counter;
-  dim3 grid((unsigned)ceil_div(M, 64), (unsigned)ceil_div(k, EVAL_NT * 16));
   if (mv.storage == P_F64) {
-    if (compute == P_F64) return eval_dispatch_src<double, double>(mv.kind, a, grid, st);
+    if (compute == P_F64) return eval_dispatch_src<double, double>(mv.kind, a, st);
     return hipErrorInvalidValue;
   }
   switch (compute) {
-    case P_F32: return eval_dispatch_src<float, float>(mv.kind, a, grid, st);
-    case P_BF16: return eval_dispatch_src<float, bf16>(mv.kind, a, grid, st);
-    case P_F16: return eval_dispatch_src<float, f16>(mv.kind, a, grid, st);
+    case P_F32: return eval_dispatch_src<float, float>(mv.kind, a, st);
+    case P_BF16: return eval_dispatch_src<float, bf16>(mv.kind, a, st);
+    case P_F16: return eval_dispatch_src<float, f16>(mv.kind, a, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -442,8 +459,7 @@ static hipError_t block_dispatch(const MatView& mv, const int64_t* ri, int kr, c
   a.noise_std = mv.kind == SRC_LOWRANK ? mv.noise_std : 0.0;
   a.noise_seed = mv.noise_seed;
   a.counter = nullptr;
-  dim3 grid((unsigned)ceil_div(kr, 64), (unsigned)ceil_div(kc, EVAL_NT * 16));
-  return eval_dispatch_src<TIn, TC>(mv.kind, a, grid, st);
+  return eval_dispatch_src<TIn, TC>(mv.kind, a, st);
 }
 
 hipError_t launch_eval_block(const MatView& mv, const int64_t* ri, int kr, const int64_t* ci, int kc, int compute,
