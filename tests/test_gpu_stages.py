@@ -148,6 +148,28 @@ def test_eval_cols_and_rows(api, kind, compute):
     print(f"{kind} {compute}: largest error / bound {worst:.3f}")
 
 
+def test_eval_cols_over_several_launches(api):
+    """More than 2^20 blocks of 64 rows: the evaluation runs as several launches, each a
+    contiguous range of row blocks.  A 2^26 + 4000-point RBF matrix (d = 2), FP32, 7 sampled
+    columns; rows on both sides of the launch boundary, the first and last rows and a random
+    sample are checked against the oracle's entries within the derived bound."""
+    m = (1 << 26) + 4000
+    rng = np.random.default_rng(31)
+    spec = workloads.MatrixSpec(kind="rbf", m=m, n=500, x=rng.normal(size=(m, 2)), y=rng.normal(size=(500, 2)),
+                                sigma=1.5)
+    mat = api.DeviceMatrix(spec, storage="f32")
+    ic = _idx(spec.n, 7, 3)
+    c = api.eval_cols(mat, torch.from_numpy(ic).cuda(), "f32")
+    edge = 1 << 26
+    rows = np.unique(np.concatenate([np.arange(0, 50), np.arange(edge - 200, edge + 200), np.arange(m - 50, m),
+                                     rng.integers(0, m, size=2000)]))
+    got = c[torch.from_numpy(rows).cuda()].cpu().numpy().astype(np.float64)
+    del c, mat
+    want = Matrix(spec).block(rows, ic)
+    bound = _eval_bound(spec, rows, ic, "f32")
+    assert (np.abs(got - want) / bound).max() <= 1.0
+
+
 @pytest.mark.parametrize("rows,cols,seed", [(1, 1, 0), (5, 3, 1), (3, 5, 2), (50, 50, 3), (64, 40, 4), (40, 64, 5),
                                             (200, 200, 6), (129, 200, 7), (300, 257, 8), (500, 500, 9),
                                             (64, 700, 10), (1024, 23, 11)])
