@@ -1345,7 +1345,7 @@ extern "C" cabs_status cabs_kmeans_noalloc(int64_t rows, int32_t dim, int32_t k,
   if (!valid_prec(compute)) return fail(CABS_EINVAL, "unknown precision");
   if (!P || !w || !Z0 || !Z) return fail(CABS_EINVAL, "null pointer");
   if (iters < 0) return fail(CABS_EINVAL, "iters must be >= 0");
-  const size_t need = kmeans_ws_bytes(rows, dim, k, compute);
+  const size_t need = kmeans_ws_bytes(rows, dim, k, compute, true);
   if (need > (size_t)CABS_KMEANS_NOALLOC_SCRATCH_BYTES)
     return fail(CABS_ENOMEM, "cabs_kmeans_noalloc: needs %zu bytes of scratch, the fixed array holds %zu", need,
                 (size_t)CABS_KMEANS_NOALLOC_SCRATCH_BYTES);
@@ -1353,6 +1353,6 @@ extern "C" cabs_status cabs_kmeans_noalloc(int64_t rows, int32_t dim, int32_t k,
   const cabs_status s = scratch_on_current_device(&ws);
   if (s != CABS_OK) return s;
   KMeansOut o{Z, labels, obj2, nullptr, nullptr, snap_out, nullptr};
-  HIP_TRY(launch_kmeans(rows, dim, k, compute, P, w, Z0, iters, o, ws, (hipStream_t)stream));
+  HIP_TRY(launch_kmeans(rows, dim, k, compute, P, w, Z0, iters, o, ws, (hipStream_t)stream, true));
   return CABS_OK;
 }

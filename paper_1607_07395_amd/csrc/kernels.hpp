@@ -126,7 +126,9 @@ size_t gram_ws_bytes(int64_t M, int K);
 hipError_t launch_gram(int64_t M, int K, int compute, const void* X, double* G, void* ws, hipStream_t st);
 
 // --- weighted k-means and snapping (kmeans.hip) ---
-size_t kmeans_ws_bytes(int64_t rows, int dim, int k, int compute);
+// lean: the layout without the final assignment's stored dot products, from
+// which the snap otherwise takes its distances (its top-T pass then forms them).
+size_t kmeans_ws_bytes(int64_t rows, int dim, int k, int compute, bool lean = false);
 struct KMeansOut {
   double* Z;         // k x dim FP64 (in: Z0 if z0 == nullptr)
   int32_t* labels;   // rows (may be null)
@@ -137,7 +139,8 @@ struct KMeansOut {
   double* fallbacks; // number of centres resolved by a full scan (may be null)
 };
 hipError_t launch_kmeans(int64_t rows, int dim, int k, int compute, const void* P, const double* w,
-                         const double* Z0, int iters, const KMeansOut& out, void* ws, hipStream_t st);
+                         const double* Z0, int iters, const KMeansOut& out, void* ws, hipStream_t st,
+                         bool lean = false);
 
 // --- error metric (error.hip) ---
 size_t error_ws_bytes(const MatView& mv, int k2c, int k2r, int compute, int64_t n_samples);

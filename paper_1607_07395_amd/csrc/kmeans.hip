@@ -205,14 +205,18 @@ __global__ __launch_bounds__(256) void assign_kernel(int64_t rows, int dim, int 
 // assign_kernel, so distances, labels and gaps are bit-identical to it.
 #define CABS_LDS_PTR(p) ((__attribute__((address_space(3))) void*)(p))
 
-template <typename TC, int NKB, int RT, int CT, int OCC>
+// SD: the pass also stores every row's dot products with the centres
+// (sacc[row k + centre], the MFMA sums before the epilogue) for the top-T pass
+// of the snap, which then needs no second distance GEMM.
+template <typename TC, int NKB, int RT, int CT, int OCC, bool SD>
 __global__ __launch_bounds__(256, OCC) void assign_fast_kernel(int64_t rows, int dim, int k, int gsize,
                                                                const TC* __restrict__ P, const TC* __restrict__ Zc,
                                                                const double* __restrict__ znorm,
                                                                const double* __restrict__ pnorm,
                                                                int32_t* __restrict__ labels, double* __restrict__ dmin,
                                                                double* __restrict__ gap, float* __restrict__ pb,
-                                                               int32_t* __restrict__ pi, float* __restrict__ ps) {
+                                                               int32_t* __restrict__ pi, float* __restrict__ ps,
+                                                               float* __restrict__ sacc) {
   typedef typename Mfma<TC>::acc AccV;
   constexpr int VE = 16 / sizeof(TC);           // elements per 16-byte run
   constexpr int SPV = VE / Mfma<TC>::KPL;       // MFMA steps per run
@@ -320,6 +324,10 @@ __global__ __launch_bounds__(256, OCC) void assign_fast_kernel(int64_t rows, int
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
+          if constexpr (SD) {
+            const int64_t row = row0 + rt * 16 + out_row<TC>(g, i);
+            if (in && row < rows) sacc[row * k + col] = acc[rt][t][i];
+          }
           const float d0 = zn - 2.0f * acc[rt][t][i];
           const float d = in ? d0 : __builtin_huge_valf();
           const bool lt = d < best[rt][i];
@@ -441,19 +449,26 @@ static int af_groups(int64_t wgs, int nchunk, int64_t slots) {
 template <typename TC, int I>
 static void assign_fast_launch(int nkb, int64_t rows, int dim, int k, const TC* P, const TC* Zc, const double* znorm,
                                const double* pnorm, int32_t* labels, double* dmin, double* gap, float* pb, int32_t* pi,
-                               float* ps, hipStream_t st) {
+                               float* ps, float* sacc, hipStream_t st) {
   constexpr int NKB = AfShape<TC>::nkb[I], RT = AfShape<TC>::rt[I], CT = AfShape<TC>::ct[I];
   constexpr int OCC = AfShape<TC>::occ[I];
   if constexpr (I + 1 < AfShape<TC>::n) {
     if (nkb > NKB)
-      return assign_fast_launch<TC, I + 1>(nkb, rows, dim, k, P, Zc, znorm, pnorm, labels, dmin, gap, pb, pi, ps, st);
+      return assign_fast_launch<TC, I + 1>(nkb, rows, dim, k, P, Zc, znorm, pnorm, labels, dmin, gap, pb, pi, ps, sacc,
+                                           st);
   }
   const int64_t wgs = ceil_div(rows, 64 * RT);
   const int nchunk = (int)ceil_div(k, CT * 16);
   const int G = pb ? af_groups(wgs, nchunk, (int64_t)device_cus() * OCC) : 1;
   const int gsize = (int)ceil_div(nchunk, G) * CT * 16;
-  hipLaunchKernelGGL((assign_fast_kernel<TC, NKB, RT, CT, OCC>), dim3((unsigned)wgs, (unsigned)G), dim3(256), 0, st,
-                     rows, dim, k, gsize, P, Zc, znorm, pnorm, labels, dmin, gap, G > 1 ? pb : nullptr, pi, ps);
+  if (sacc)
+    hipLaunchKernelGGL((assign_fast_kernel<TC, NKB, RT, CT, OCC, true>), dim3((unsigned)wgs, (unsigned)G), dim3(256), 0,
+                       st, rows, dim, k, gsize, P, Zc, znorm, pnorm, labels, dmin, gap, G > 1 ? pb : nullptr, pi, ps,
+                       sacc);
+  else
+    hipLaunchKernelGGL((assign_fast_kernel<TC, NKB, RT, CT, OCC, false>), dim3((unsigned)wgs, (unsigned)G), dim3(256),
+                       0, st, rows, dim, k, gsize, P, Zc, znorm, pnorm, labels, dmin, gap, G > 1 ? pb : nullptr, pi,
+                       ps, nullptr);
   if (G > 1)
     hipLaunchKernelGGL(assign_merge_kernel, dim3((unsigned)ceil_div(rows, 256)), dim3(256), 0, st, rows, G, k, pb, pi,
                        ps, pnorm, labels, dmin, gap);
@@ -462,16 +477,28 @@ static void assign_fast_launch(int nkb, int64_t rows, int dim, int k, const TC* 
 template <typename TC> struct AssignFast { static constexpr bool ok = true; };
 template <> struct AssignFast<double> { static constexpr bool ok = false; };
 
+// Whether the fast assignment kernel takes these rows: its dimension limit,
+// whole 16-byte runs per row, 16-byte aligned P and centres.
+template <typename TC>
+static bool assign_fast_ok(int dim, const void* P, const void* Zc) {
+  if constexpr (AssignFast<TC>::ok) {
+    constexpr int VE = 16 / (int)sizeof(TC);
+    return dim <= af_dim_max<TC>() && dim % VE == 0 && ((uintptr_t)P % 16) == 0 && ((uintptr_t)Zc % 16) == 0;
+  }
+  return false;
+}
+
 // pb / pi / ps: AF_MAXG x rows partials for centre groups (null: one group).
+// sacc (may be null): the fast kernel stores the dot products there.
 template <typename TC>
 static void launch_assign(int64_t rows, int dim, int k, const TC* P, const TC* Zc, const double* znorm,
                           const double* pnorm, int32_t* labels, double* dmin, double* gap, float* pb, int32_t* pi,
-                          float* ps, hipStream_t st) {
+                          float* ps, float* sacc, hipStream_t st) {
   if constexpr (AssignFast<TC>::ok) {
-    constexpr int VE = 16 / (int)sizeof(TC);
-    if (dim <= af_dim_max<TC>() && dim % VE == 0 && ((uintptr_t)P % 16) == 0 && ((uintptr_t)Zc % 16) == 0) {
+    if (assign_fast_ok<TC>(dim, P, Zc)) {
+      constexpr int VE = 16 / (int)sizeof(TC);
       const int nkb = (dim + 4 * VE - 1) / (4 * VE);
-      assign_fast_launch<TC, 0>(nkb, rows, dim, k, P, Zc, znorm, pnorm, labels, dmin, gap, pb, pi, ps, st);
+      assign_fast_launch<TC, 0>(nkb, rows, dim, k, P, Zc, znorm, pnorm, labels, dmin, gap, pb, pi, ps, sacc, st);
       return;
     }
   }
@@ -1032,6 +1059,55 @@ __global__ __launch_bounds__(256) void snap_topt_kernel(int64_t rows, int dim, i
   }
 }
 
+// The same per-block lists from the dot products the final assignment stored
+// (sacc[row k + centre]): that kernel's MFMA sequence per element is the tile
+// core's, so each distance snap_dist(|p|^2, |z|^2, dot) is bit for bit the one
+// snap_topt_kernel forms, and the rows are inserted in the same order.  Wave w
+// takes the 64-centre chunks w, w + 4, ... (lane = centre) and reads the block's
+// rows eight at a time (one coalesced 256-byte run per row).
+__global__ __launch_bounds__(256) void snap_select_kernel(int64_t rows, int k, int64_t rows_per_block,
+                                                          const float* __restrict__ sacc,
+                                                          const double* __restrict__ znorm,
+                                                          const double* __restrict__ pnorm, double* __restrict__ cand_d,
+                                                          int32_t* __restrict__ cand_r) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t rbeg = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t rend = rbeg + rows_per_block < rows ? rbeg + rows_per_block : rows;
+  const int nblk = gridDim.x;
+  constexpr int U = 8;
+  for (int cw = wave * SNAP_CC; cw < k; cw += 4 * SNAP_CC) {
+    const int myc = cw + lane;
+    if (myc >= k) continue;
+    double td[SNAP_T];
+    int tr[SNAP_T];
+#pragma unroll
+    for (int q = 0; q < SNAP_T; ++q) { td[q] = __builtin_huge_val(); tr[q] = 0x7fffffff; }
+    const double zn = znorm[myc];
+    for (int64_t r0 = rbeg; r0 < rend; r0 += U) {
+      float a[U];
+      double pn[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t row = r0 + u < rend ? r0 + u : rend - 1;
+        a[u] = sacc[row * k + myc];
+        pn[u] = pnorm[row];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (r0 + u >= rend) break;
+        const double d = pn[u] != 0.0 ? snap_dist(pn[u], zn, (double)a[u]) : __builtin_huge_val();
+        topt_insert<double>(td, tr, d, (int)(r0 + u));
+      }
+    }
+    const int64_t base = ((int64_t)myc * nblk + blockIdx.x) * SNAP_T;
+#pragma unroll
+    for (int q = 0; q < SNAP_T; ++q) {
+      cand_d[base + q] = td[q];
+      cand_r[base + q] = tr[q];
+    }
+  }
+}
+
 // Per centre: the SNAP_T smallest (distance, row) pairs over the per-block
 // lists, each of which is sorted.  Rows are distinct, so exactly SNAP_T list
 // heads are no greater than tau, the SNAP_T-th smallest head; every pair of
@@ -1438,6 +1514,7 @@ struct KmWs {
   double* part; double* partw; double* red_s; double* red_g; double* obj_tmp; double* tmax_tmp; double* gap_tmp;
   double* cand_d; int32_t* cand_r; double* top_d; int32_t* top_r; int32_t* zrows; int32_t* zcnt;
   float* apb; int32_t* api; float* aps; int32_t* tsum;
+  float* sacc;  // rows x k dot products of the final assignment (null: the top-T pass forms its own)
   size_t total;
 };
 
@@ -1452,7 +1529,19 @@ static inline int snap_nblk(int64_t rows, int k) {
 }
 constexpr int RED_NB = 256;
 
-static KmWs km_layout(void* base, int64_t rows, int dim, int k, int compute) {
+// Whether the snap can take its distances from the final assignment: the
+// precisions with a fast assignment kernel, at dimensions it takes.
+static bool snap_from_assign(int dim, int compute) {
+  switch (compute) {
+    case P_F32: return dim <= af_dim_max<float>() && dim % 4 == 0;
+    case P_BF16: return dim <= af_dim_max<bf16>() && dim % 8 == 0;
+    case P_F16: return dim <= af_dim_max<f16>() && dim % 8 == 0;
+    default: return false;
+  }
+}
+
+// lean: no room for the stored dot products (the snap forms its own distances).
+static KmWs km_layout(void* base, int64_t rows, int dim, int k, int compute, bool lean) {
   KmWs w{};
   char* p = (char*)base;
   size_t off = 0;
@@ -1493,19 +1582,20 @@ static KmWs km_layout(void* base, int64_t rows, int dim, int k, int compute) {
   w.api = (int32_t*)take((size_t)AF_MAXG * rows * 4);
   w.aps = (float*)take((size_t)AF_MAXG * rows * 4);
   w.tsum = (int32_t*)take((size_t)ceil_div((int64_t)k * nsb, SC_TILE) * 4);
+  w.sacc = (!lean && snap_from_assign(dim, compute)) ? (float*)take((size_t)rows * k * 4) : nullptr;
   w.total = off;
   return w;
 }
 
-size_t kmeans_ws_bytes(int64_t rows, int dim, int k, int compute) {
-  return km_layout(nullptr, rows, dim, k, compute).total + 256;
+size_t kmeans_ws_bytes(int64_t rows, int dim, int k, int compute, bool lean) {
+  return km_layout(nullptr, rows, dim, k, compute, lean).total + 256;
 }
 
 template <typename TC>
 static hipError_t kmeans_t(int compute, int64_t rows, int dim, int k, const void* Pv, const double* w, const double* Z0,
-                           int iters, const KMeansOut& out, void* ws, hipStream_t st) {
+                           int iters, const KMeansOut& out, void* ws, bool lean, hipStream_t st) {
   const TC* P = (const TC*)Pv;
-  KmWs W = km_layout(ws, rows, dim, k, compute);
+  KmWs W = km_layout(ws, rows, dim, k, compute, lean);
   TC* Zc = (TC*)W.Zc;
   const int64_t nsb = ceil_div(rows, HIST_SB);
   const unsigned gR = (unsigned)ceil_div(rows, 4);
@@ -1520,12 +1610,14 @@ static hipError_t kmeans_t(int compute, int64_t rows, int dim, int k, const void
   hipLaunchKernelGGL(zprep_kernel<TC>, dim3(k), dim3(256), 0, st, k, dim, out.Z, Zc, W.znorm);
   hipLaunchKernelGGL(rownorm2_kernel<TC>, dim3(gR), dim3(256), 0, st, rows, dim, P, W.pnorm);
 
+  // the final assignment stores its dot products for the snap when there is room and the fast kernel takes P
+  const bool stored = out.snap != nullptr && W.sacc != nullptr && assign_fast_ok<TC>(dim, P, Zc);
   for (int it = 0; it <= iters; ++it) {
     const bool last = it == iters;
     {
       TimerScope ts(T_ASSIGN, st);
       launch_assign<TC>(rows, dim, k, P, (const TC*)Zc, W.znorm, W.pnorm, labels, W.dmin, last ? W.gap : nullptr,
-                        W.apb, W.api, W.aps, st);
+                        W.apb, W.api, W.aps, last && stored ? W.sacc : nullptr, st);
     }
     if (it == 0 || last) {
       hipLaunchKernelGGL(wsum_partial_kernel, dim3(red_nb), dim3(256), 0, st, rows, w, W.dmin,
@@ -1563,8 +1655,12 @@ static hipError_t kmeans_t(int compute, int64_t rows, int dim, int k, const void
     const int64_t rpb = ceil_div(ceil_div(rows, nblk), SNAP_SUB) * SNAP_SUB;
     const int nblk_eff = (int)ceil_div(rows, rpb);
     TimerScope ts(T_SNAP, st);
-    hipLaunchKernelGGL(snap_topt_kernel<TC>, dim3(nblk_eff), dim3(256), 0, st, rows, dim, k, rpb, P, (const TC*)Zc,
-                       W.znorm, W.pnorm, W.cand_d, W.cand_r);
+    if (stored)
+      hipLaunchKernelGGL(snap_select_kernel, dim3(nblk_eff), dim3(256), 0, st, rows, k, rpb, (const float*)W.sacc,
+                         W.znorm, W.pnorm, W.cand_d, W.cand_r);
+    else
+      hipLaunchKernelGGL(snap_topt_kernel<TC>, dim3(nblk_eff), dim3(256), 0, st, rows, dim, k, rpb, P, (const TC*)Zc,
+                         W.znorm, W.pnorm, W.cand_d, W.cand_r);
     hipLaunchKernelGGL(snap_merge_kernel, dim3(k), dim3(256), 0, st, nblk_eff, W.cand_d, W.cand_r, W.top_d, W.top_r);
     int32_t* zoff = W.zcnt + ZR_NB + 1;
     hipLaunchKernelGGL(zero_rows_count_kernel, dim3(ZR_NB), dim3(256), 0, st, rows, W.pnorm, W.zcnt);
@@ -1581,14 +1677,14 @@ static hipError_t kmeans_t(int compute, int64_t rows, int dim, int k, const void
 }
 
 hipError_t launch_kmeans(int64_t rows, int dim, int k, int compute, const void* P, const double* w, const double* Z0,
-                         int iters, const KMeansOut& out, void* ws, hipStream_t st) {
+                         int iters, const KMeansOut& out, void* ws, hipStream_t st, bool lean) {
   if (rows <= 0 || rows > INT32_MAX || dim <= 0 || k <= 0 || k > KM_MAXK || k > rows || iters < 0 || out.Z == nullptr)
     return hipErrorInvalidValue;
   switch (compute) {
-    case P_F64: return kmeans_t<double>(compute, rows, dim, k, P, w, Z0, iters, out, ws, st);
-    case P_F32: return kmeans_t<float>(compute, rows, dim, k, P, w, Z0, iters, out, ws, st);
-    case P_BF16: return kmeans_t<bf16>(compute, rows, dim, k, P, w, Z0, iters, out, ws, st);
-    case P_F16: return kmeans_t<f16>(compute, rows, dim, k, P, w, Z0, iters, out, ws, st);
+    case P_F64: return kmeans_t<double>(compute, rows, dim, k, P, w, Z0, iters, out, ws, lean, st);
+    case P_F32: return kmeans_t<float>(compute, rows, dim, k, P, w, Z0, iters, out, ws, lean, st);
+    case P_BF16: return kmeans_t<bf16>(compute, rows, dim, k, P, w, Z0, iters, out, ws, lean, st);
+    case P_F16: return kmeans_t<f16>(compute, rows, dim, k, P, w, Z0, iters, out, ws, lean, st);
     default: return hipErrorInvalidValue;
   }
 }
