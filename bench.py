@@ -60,8 +60,8 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "f16": 2500.0}
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=4)
     ap.add_argument("--config", default="rbf1e6", help="workload name from workloads.CONFIGS")
     ap.add_argument("--compute", default=None, help="f64 | f32 | bf16 | f16 (default: the workload's)")
     ap.add_argument("--err-samples", type=int, default=None)
