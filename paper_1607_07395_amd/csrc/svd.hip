@@ -37,12 +37,40 @@ constexpr int BJ_INNER_SWEEPS = 1;   // inner sweeps per pair and round in the f
 // Number of column blocks (even) and padded column count of the block-Jacobi path.
 __host__ __device__ static inline int bj_blocks(int p) { int nb = (p + BJ_B - 1) / BJ_B; return nb + (nb & 1); }
 
-// Per-matrix scratch in doubles: X (q x P), V (P x P) with P >= p the padded
-// column count, sigma (p), rank / sign (p each), and 64 words of flags.
-__host__ __device__ static inline size_t svd_ws_doubles(int rows, int cols) {
+// Per-matrix scratch of the block-Jacobi path in doubles: X (q x P), V (P x P)
+// with P >= p the padded column count, sigma (p), rank / sign (p each), and 64
+// words of flags.
+__host__ __device__ static inline size_t bj_ws_doubles(int rows, int cols) {
   const size_t p = rows < cols ? rows : cols, q = rows < cols ? cols : rows;
   const size_t P = (size_t)bj_blocks((int)p) * BJ_B;
   return 2 * q * P + P * P + 3 * p + 64;
+}
+
+// The QR-preconditioned path (below) for matrices with 256 <= min and max <=
+// 1024 at the default sweep count: the working matrix A (q x p, q >= p; A^T
+// when rows < cols) is factored A Pi = Q R by Householder QR with column
+// pivoting, and the block-Jacobi SVD runs on R^T, whose columns are far closer
+// to orthogonal (on 500 x 500 RBF kernel blocks about 11 sweeps instead of 24).
+constexpr int QRP_MINP = 256;
+constexpr int QRP_MAXQ = 1024;
+__host__ __device__ static inline bool qrp_applies(int rows, int cols) {
+  const int p = rows < cols ? rows : cols, q = rows < cols ? cols : rows;
+  return p >= QRP_MINP && q <= QRP_MAXQ;
+}
+// Its scratch in doubles: Ac (q x p, column-major), Q (q x q, row-major),
+// R, R^T in pivot order and the two factors of its SVD (p x p each), the
+// column norms (two buffers of p), the taken flags (two of p ints) and the
+// pivots (p ints), then the block-Jacobi scratch of the p x p problem.
+__host__ __device__ static inline size_t qrp_ws_doubles(int rows, int cols) {
+  const size_t p = rows < cols ? rows : cols, q = rows < cols ? cols : rows;
+  return q * p + q * q + 4 * p * p + 2 * p + (3 * p + 1) / 2 + 8 + bj_ws_doubles((int)p, (int)p);
+}
+
+__host__ __device__ static inline size_t svd_ws_doubles(int rows, int cols) {
+  const size_t bj = bj_ws_doubles(rows, cols);
+  if (!qrp_applies(rows, cols)) return bj;
+  const size_t qr = qrp_ws_doubles(rows, cols);
+  return qr > bj ? qr : bj;
 }
 
 size_t svd_ws_item_doubles(int rows, int cols) { return svd_ws_doubles(rows, cols); }
@@ -860,16 +888,14 @@ __global__ __launch_bounds__(1024) void bj_finish_kernel(int rows, int cols, int
   svd_finalize_rm(v, fin, item_u(it, b), item_s(it, b), item_v(it, b));
 }
 
-hipError_t launch_svd_items(int batch, int rows, int cols, const SvdItems& it, hipStream_t st, int fast_sweeps) {
-  if (batch <= 0 || rows <= 0 || cols <= 0 || std::min(rows, cols) > 1024 || std::max(rows, cols) > 4096)
-    return hipErrorInvalidValue;
-  if (it.n_ptr && (it.n_ptr != batch || batch > SVD_MAX_PTR)) return hipErrorInvalidValue;
-  if (fast_sweeps == 0) fast_sweeps = bj_default_fast_sweeps(rows < cols ? rows : cols);
-  if (fast_sweeps < 1 || fast_sweeps > BJ_FAST_SWEEPS) return hipErrorInvalidValue;
+static hipError_t launch_svd_qrp(int batch, int rows, int cols, const SvdItems& it, hipStream_t st);
+
+// The Jacobi SVD itself (no QR preconditioning).
+static hipError_t launch_svd_jacobi(int batch, int rows, int cols, const SvdItems& it, hipStream_t st,
+                                    int fast_sweeps) {
   const size_t p = rows < cols ? rows : cols, q = rows < cols ? cols : rows;
   const size_t lds_bytes = (q * p + p * p) * sizeof(double);
   const int use_lds = lds_bytes <= (size_t)SVD_LDS_BYTES ? 1 : 0;
-  TimerScope ts(T_SVD, st);
   if (p < 24) {
     hipLaunchKernelGGL(svd_jacobi_kernel, dim3(batch), dim3(SVD_THREADS), use_lds ? lds_bytes : 0, st, rows, cols, it,
                        use_lds);
@@ -891,6 +917,303 @@ hipError_t launch_svd_items(int batch, int rows, int cols, const SvdItems& it, h
     }
   }
   hipLaunchKernelGGL(bj_finish_kernel, dim3(batch), dim3(1024), 0, st, rows, cols, fast_sweeps, it);
+  return hipGetLastError();
+}
+
+hipError_t launch_svd_items(int batch, int rows, int cols, const SvdItems& it, hipStream_t st, int fast_sweeps) {
+  if (batch <= 0 || rows <= 0 || cols <= 0 || std::min(rows, cols) > 1024 || std::max(rows, cols) > 4096)
+    return hipErrorInvalidValue;
+  if (it.n_ptr && (it.n_ptr != batch || batch > SVD_MAX_PTR)) return hipErrorInvalidValue;
+  if (fast_sweeps < 0 || fast_sweeps > BJ_FAST_SWEEPS) return hipErrorInvalidValue;
+  TimerScope ts(T_SVD, st);
+  if (fast_sweeps == 0 && qrp_applies(rows, cols)) return launch_svd_qrp(batch, rows, cols, it, st);
+  if (fast_sweeps == 0) fast_sweeps = bj_default_fast_sweeps(rows < cols ? rows : cols);
+  return launch_svd_jacobi(batch, rows, cols, it, st, fast_sweeps);
+}
+
+// ---------------------------------------------------------------------------
+// QR-preconditioned SVD.  A Pi = Q R (Householder, column pivoting: each step
+// takes the remaining column of largest norm, lowest index on ties), then the
+// block-Jacobi SVD of M = R^T in pivot order, M = U' S V'^T.  Since
+// A Pi = Q V' S U'^T, the working matrix has left factor Q V' and right factor
+// Pi U' (row pi_i of it is row i of U'); for rows < cols the working matrix is
+// A^T and the two swap.  The signs are then set as on the plain path (the
+// largest-magnitude entry of each left singular vector, lowest row on ties,
+// positive).
+//
+// Step j is one launch of QRP_WG work-groups per matrix.  Every work-group
+// finds the pivot and forms the reflector from the pivot column itself (the
+// same code on the same data, so the same values), then each wave updates its
+// columns (v^T a, a -= tau (v^T a) v, and the exact squared norm of rows
+// j + 1.. as the next step's pivot key) and its rows of Q (Q <- Q H_j).  The pivot column is only read in its step, the norms and taken
+// flags are double-buffered between steps, so no work-group reads what another
+// writes in the same launch.
+// ---------------------------------------------------------------------------
+constexpr int QRP_WG = 128;  // work-groups per matrix and step (one column and one row of Q per wave at q <= 512)
+
+struct QrpView {
+  double *Ac, *Q, *R, *M, *Up, *Vp, *nrm;
+  int *tk, *piv;
+  double* jw;
+  int q, p;
+  bool trans;
+};
+
+__host__ __device__ inline QrpView qrp_view(double* base, int rows, int cols) {
+  QrpView v;
+  v.trans = rows < cols;
+  v.p = v.trans ? rows : cols;
+  v.q = v.trans ? cols : rows;
+  const size_t p = v.p, q = v.q;
+  v.Ac = base;
+  v.Q = v.Ac + q * p;
+  v.R = v.Q + q * q;
+  v.M = v.R + p * p;
+  v.Up = v.M + p * p;
+  v.Vp = v.Up + p * p;
+  v.nrm = v.Vp + p * p;
+  v.tk = (int*)(v.nrm + 2 * p);
+  v.piv = v.tk + 2 * p;
+  v.jw = v.nrm + 2 * p + (3 * p + 1) / 2 + 8;
+  return v;
+}
+
+// Ac = the working matrix column-major, Q = I, R = 0, no column taken.
+__global__ __launch_bounds__(256) void qrp_init_kernel(int rows, int cols, SvdItems it) {
+  const QrpView v = qrp_view(item_w(it, blockIdx.y), rows, cols);
+  const double* A = item_a(it, blockIdx.y);
+  const int64_t q = v.q, p = v.p;
+  const int64_t n1 = q * p, n2 = n1 + q * q, n3 = n2 + p * p, n4 = n3 + 2 * p;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n4; e += (int64_t)gridDim.x * 256) {
+    if (e < n1) {
+      const int64_t c = e / q, i = e - c * q;  // Ac[c q + i] = working A[i][c]
+      v.Ac[e] = v.trans ? A[c * cols + i] : A[i * cols + c];
+    } else if (e < n2) {
+      const int64_t f = e - n1;
+      v.Q[f] = (f / q == f % q) ? 1.0 : 0.0;
+    } else if (e < n3) {
+      v.R[e - n2] = 0.0;
+    } else {
+      v.tk[e - n3] = 0;
+    }
+  }
+}
+
+// Squared column norms of Ac, one wave per column (fixed order), into buffer 0.
+__global__ __launch_bounds__(256) void qrp_norm_kernel(int rows, int cols, SvdItems it) {
+  const QrpView v = qrp_view(item_w(it, blockIdx.y), rows, cols);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int c = blockIdx.x * 4 + wave; c < v.p; c += gridDim.x * 4) {
+    const double* col = v.Ac + (size_t)c * v.q;
+    double s2 = 0.0;
+    for (int i = lane; i < v.q; i += 64) s2 += col[i] * col[i];
+    s2 = wave_sum(s2);
+    if (lane == 0) v.nrm[c] = s2;
+  }
+}
+
+__global__ __launch_bounds__(256) void qrp_step_kernel(int rows, int cols, int j, SvdItems it) {
+  __shared__ double xv[QRP_MAXQ];  // the reflector v (rows j .. q - 1)
+  __shared__ double rd[4];
+  __shared__ int ri[4];
+  const QrpView v = qrp_view(item_w(it, blockIdx.y), rows, cols);
+  const int q = v.q, p = v.p, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int sb = j & 1;
+  const double* nin = v.nrm + sb * p;
+  double* nout = v.nrm + (sb ^ 1) * p;
+  const int* tin = v.tk + sb * p;
+  int* tout = v.tk + (sb ^ 1) * p;
+  const int len = q - j;
+  // pivot: the untaken column of largest norm, lowest index on ties (NaN below
+  // every number); the maximum is order-independent, so a butterfly does
+  double bv = -2.0;
+  int bi = 0x7fffffff;
+  for (int c = tid; c < p; c += 256) {
+    if (tin[c]) continue;
+    const double x = nin[c] == nin[c] ? nin[c] : -1.0;
+    if (x > bv) { bv = x; bi = c; }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double ov = __shfl_xor(bv, o, 64);
+    const int oi = __shfl_xor(bi, o, 64);
+    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+  }
+  if (lane == 0) { rd[wave] = bv; ri[wave] = bi; }
+  __syncthreads();
+  int piv = ri[0];
+  {
+    double m = rd[0];
+    for (int w = 1; w < 4; ++w)
+      if (rd[w] > m || (rd[w] == m && ri[w] < piv)) { m = rd[w]; piv = ri[w]; }
+  }
+  __syncthreads();
+  // the pivot column's rows j .. q - 1 and their squared norm (the same fixed
+  // order in every work-group)
+  const double* pc = v.Ac + (size_t)piv * q + j;
+  double ss = 0.0;
+  for (int i = tid; i < len; i += 256) {
+    const double x = pc[i];
+    xv[i] = x;
+    ss += x * x;
+  }
+  ss = wave_sum(ss);
+  if (lane == 0) rd[wave] = ss;
+  __syncthreads();
+  const double sig2 = ((rd[0] + rd[1]) + rd[2]) + rd[3], x0 = xv[0];
+  const double sigma = sqrt(sig2);
+  const double alpha = x0 >= 0.0 ? -sigma : sigma;  // H x = alpha e_0
+  const double v0 = x0 - alpha;
+  const double vtv = sig2 - x0 * x0 + v0 * v0;
+  const double tau = vtv > 0.0 ? 2.0 / vtv : 0.0;
+  __syncthreads();
+  if (tid == 0) xv[0] = v0;
+  __syncthreads();
+  if (blockIdx.x == 0 && tid == 0) {
+    v.piv[j] = piv;
+    v.R[(size_t)j * p + piv] = alpha;
+  }
+  // wave g (over the grid) updates column g and row g of Q (then g + 4 QRP_WG,
+  // ...); the two are independent, so their loads are in flight together
+  const int gw = blockIdx.x * 4 + wave, stride = 4 * gridDim.x;
+  const int n = p > q ? p : q;
+  for (int g = gw; g < n; g += stride) {
+    const bool hc = g < p;
+    const bool live = hc && tin[g] == 0 && g != piv;
+    const bool hr = g < q;
+    double* col = v.Ac + (size_t)(hc ? g : 0) * q + j;
+    double* qr = v.Q + (size_t)(hr ? g : 0) * q + j;
+    double dc = 0.0, dr = 0.0;
+    for (int i = lane; i < len; i += 64) {
+      const double x = xv[i];
+      if (live) dc += x * col[i];
+      if (hr) dr += x * qr[i];
+    }
+    dc = wave_sum(dc);
+    dr = wave_sum(dr);
+    const double fc = tau * dc, fr = tau * dr;
+    double s2 = 0.0, head = 0.0;
+    for (int i = lane; i < len; i += 64) {
+      const double x = xv[i];
+      if (live) {
+        const double y = col[i] - fc * x;
+        col[i] = y;
+        if (i == 0) head = y;
+        else s2 += y * y;
+      }
+      if (hr) qr[i] -= fr * x;
+    }
+    if (hc) {
+      s2 = wave_sum(s2);
+      if (lane == 0) {
+        tout[g] = live ? 0 : 1;
+        nout[g] = live ? s2 : 0.0;
+        if (live) v.R[(size_t)j * p + g] = head;
+      }
+    }
+  }
+}
+
+// M = R^T in pivot order: M[i][k] = R[k][pi_i] (lower triangular).
+__global__ __launch_bounds__(256) void qrp_form_kernel(int rows, int cols, SvdItems it) {
+  const QrpView v = qrp_view(item_w(it, blockIdx.y), rows, cols);
+  const int64_t p = v.p;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < p * p; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e / p, k = e - i * p;
+    v.M[e] = v.R[k * p + v.piv[i]];
+  }
+}
+
+// The permuted factor: row pi_i of Pi U' is row i of U' (into U for rows <
+// cols, else into V; both p x p there).
+__global__ __launch_bounds__(256) void qrp_perm_kernel(int rows, int cols, SvdItems it) {
+  const QrpView v = qrp_view(item_w(it, blockIdx.y), rows, cols);
+  double* out = v.trans ? item_u(it, blockIdx.y) : item_v(it, blockIdx.y);
+  const int64_t p = v.p;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < p * p; e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e / p, c = e - i * p;
+    out[(int64_t)v.piv[i] * p + c] = v.Up[e];
+  }
+}
+
+// Signs: per singular vector (one wave each), the largest-magnitude entry of
+// the left vector (lowest row on ties) made positive, flipping both vectors.
+__global__ __launch_bounds__(256) void qrp_sign_kernel(int rows, int cols, SvdItems it) {
+  const int b = blockIdx.y;
+  double* U = item_u(it, b);
+  double* V = item_v(it, b);
+  const int p = rows < cols ? rows : cols;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int c = blockIdx.x * 4 + wave; c < p; c += gridDim.x * 4) {
+    double best = -1.0, bval = 0.0;
+    int bi = 0x7fffffff;
+    for (int i = lane; i < rows; i += 64) {
+      const double x = U[(int64_t)i * p + c];
+      if (fabs(x) > best) { best = fabs(x); bval = x; bi = i; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(best, o, 64), ov = __shfl_xor(bval, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bval = ov; bi = oi; }
+    }
+    if (bval < 0.0) {
+      for (int i = lane; i < rows; i += 64) U[(int64_t)i * p + c] = -U[(int64_t)i * p + c];
+      for (int i = lane; i < cols; i += 64) V[(int64_t)i * p + c] = -V[(int64_t)i * p + c];
+    }
+  }
+}
+
+// Host views of an item's pointers.
+static const double* h_item_a(const SvdItems& it, int b) { return it.n_ptr ? it.Ap[b] : it.A + b * it.sA; }
+static double* h_item_u(const SvdItems& it, int b) { return it.n_ptr ? it.Up[b] : it.U + b * it.sU; }
+static double* h_item_s(const SvdItems& it, int b) { return it.n_ptr ? it.Sp[b] : it.S + b * it.sS; }
+static double* h_item_v(const SvdItems& it, int b) { return it.n_ptr ? it.Vp[b] : it.V + b * it.sV; }
+static double* h_item_w(const SvdItems& it, int b) { return it.n_ptr ? it.Wp[b] : it.W + b * it.sW; }
+
+static hipError_t launch_svd_qrp(int batch, int rows, int cols, const SvdItems& it, hipStream_t st) {
+  const int p = rows < cols ? rows : cols, q = rows < cols ? cols : rows;
+  const int64_t elems = (int64_t)q * p + (int64_t)q * q + (int64_t)p * p + 2 * p;
+  hipLaunchKernelGGL(qrp_init_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(elems, 256), 1024), batch), dim3(256),
+                     0, st, rows, cols, it);
+  hipLaunchKernelGGL(qrp_norm_kernel, dim3((unsigned)ceil_div(p, 4), batch), dim3(256), 0, st, rows, cols, it);
+  for (int j = 0; j < p; ++j)
+    hipLaunchKernelGGL(qrp_step_kernel, dim3(QRP_WG, batch), dim3(256), 0, st, rows, cols, j, it);
+  hipLaunchKernelGGL(qrp_form_kernel, dim3((unsigned)ceil_div((int64_t)p * p, 256), batch), dim3(256), 0, st, rows,
+                     cols, it);
+  // the Jacobi SVD of M (p x p) into U', the item's S, V'
+  SvdItems in{};
+  if (it.n_ptr) {
+    in.n_ptr = batch;
+    for (int b = 0; b < batch; ++b) {
+      const QrpView v = qrp_view(h_item_w(it, b), rows, cols);
+      in.Ap[b] = v.M;
+      in.Up[b] = v.Up;
+      in.Sp[b] = h_item_s(it, b);
+      in.Vp[b] = v.Vp;
+      in.Wp[b] = v.jw;
+    }
+  } else {
+    const QrpView v = qrp_view(it.W, rows, cols);
+    in.A = v.M;
+    in.U = v.Up;
+    in.S = it.S;
+    in.V = v.Vp;
+    in.W = v.jw;
+    in.sA = in.sU = in.sV = in.sW = it.sW;
+    in.sS = it.sS;
+  }
+  hipError_t e = launch_svd_jacobi(batch, p, p, in, st, 16);
+  if (e != hipSuccess) return e;
+  // left factor of the working matrix Q V' (q x p); right factor Pi U'
+  for (int b = 0; b < batch; ++b) {
+    const QrpView v = qrp_view(h_item_w(it, b), rows, cols);
+    double* lo = v.trans ? h_item_v(it, b) : h_item_u(it, b);
+    e = launch_small_gemm(q, p, p, v.Q, q, false, v.Vp, p, false, nullptr, nullptr, nullptr, lo, p, st);
+    if (e != hipSuccess) return e;
+    (void)h_item_a;
+  }
+  hipLaunchKernelGGL(qrp_perm_kernel, dim3((unsigned)ceil_div((int64_t)p * p, 256), batch), dim3(256), 0, st, rows,
+                     cols, it);
+  hipLaunchKernelGGL(qrp_sign_kernel, dim3((unsigned)ceil_div(p, 4), batch), dim3(256), 0, st, rows, cols, it);
   return hipGetLastError();
 }
 
