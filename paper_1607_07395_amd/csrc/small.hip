@@ -254,7 +254,7 @@ __global__ __launch_bounds__(PC_THREADS) void pchol_kernel(int p, const double* 
 // which the row is read from, are never updated, so the reads and the updates
 // of one step do not overlap.  Entries of R at indices pivoted earlier are
 // exact zeros, as in pchol_kernel.
-constexpr int PCG_WG = 32;  // work-groups per matrix
+constexpr int PCG_WG = 128;  // work-groups per matrix (about four rows of the update each at p = 500)
 
 struct PcgView {
   double *S, *dg0, *dg1;
