@@ -46,12 +46,12 @@ __host__ __device__ static inline size_t bj_ws_doubles(int rows, int cols) {
   return 2 * q * P + P * P + 3 * p + 64;
 }
 
-// The QR-preconditioned path (below) for matrices with 256 <= min and max <=
+// The QR-preconditioned path (below) for matrices with 384 <= min and max <=
 // 1024 at the default sweep count: the working matrix A (q x p, q >= p; A^T
 // when rows < cols) is factored A Pi = Q R by Householder QR with column
 // pivoting, and the block-Jacobi SVD runs on R^T, whose columns are far closer
 // to orthogonal (on 500 x 500 RBF kernel blocks about 11 sweeps instead of 24).
-constexpr int QRP_MINP = 256;
+constexpr int QRP_MINP = 384;  // below this the plain path takes fewer launches
 constexpr int QRP_MAXQ = 1024;
 __host__ __device__ static inline bool qrp_applies(int rows, int cols) {
   const int p = rows < cols ? rows : cols, q = rows < cols ? cols : rows;

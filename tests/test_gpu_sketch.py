@@ -78,6 +78,14 @@ def test_sketch_f64_large_p_orthogonalisation(api):
     _compare_f64(api, spec, dict(k1_rows=256, k1_cols=256, k2_rows=256, k2_cols=256, seed=2))
 
 
+def test_sketch_f64_qr_preconditioned_svds(api):
+    """k = 420 >= 384: the SVDs of W (both rounds) and of K take the QR-preconditioned path
+    (Householder QR with column pivoting, then the block-Jacobi SVD of R^T); 3000-point RBF kernel,
+    FP64, follow-up indices bit-exact with the oracle."""
+    spec, _ = workloads.config("rbf2000", 1.5)
+    _compare_f64(api, spec, dict(k1_rows=420, k1_cols=420, k2_rows=420, k2_cols=420, seed=5))
+
+
 def test_sketch_f64_large_p_rectangular(api):
     """The same with different row and column sample sizes (p = min = 230)."""
     spec = workloads.lowrank_noise(4000, 2500, 260, seed=6, noise_std=1e-2, s_kind="scaled")

@@ -148,6 +148,30 @@ def test_eval_cols_and_rows(api, kind, compute):
     print(f"{kind} {compute}: largest error / bound {worst:.3f}")
 
 
+@pytest.mark.parametrize("compute", ["f64", "f32", "bf16"])
+def test_dense_gathers_at_stand_in_size(api, compute):
+    """Dense gathers (C = A(:, J) row by row, R^T = A(I, :)^T through LDS tiles) on the full
+    6480 x 7680 natural-scene-like stand-in with 700 sampled rows and columns (ragged against the
+    64 x 64 tiles): a gather is a copy, so every entry equals the oracle's value rounded to the
+    storage type and then to the compute type."""
+    spec = workloads.natural_scene_like(6480, 7680, seed=3)
+    storage = "f64" if compute == "f64" else "f32"
+    mat = api.DeviceMatrix(spec, storage=storage)
+    om = Matrix(spec)
+    ic = _idx(spec.n, 700, 5)
+    ir = _idx(spec.m, 700, 6)
+    c = api.eval_cols(mat, torch.from_numpy(ic).cuda(), compute).cpu()
+    rt = api.eval_rows_t(mat, torch.from_numpy(ir).cuda(), compute).cpu()
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[compute]
+
+    def rounded(a):
+        t = torch.from_numpy(a if compute == "f64" else a.astype(np.float32))
+        return t.to(tdt)
+
+    assert torch.equal(c, rounded(om.cols(ic)))
+    assert torch.equal(rt, rounded(om.rows_t(ir)))
+
+
 def test_eval_cols_over_several_launches(api):
     """More than 2^20 blocks of 64 rows: the evaluation runs as several launches, each a
     contiguous range of row blocks.  A 2^26 + 4000-point RBF matrix (d = 2), FP32, 7 sampled
@@ -172,7 +196,8 @@ def test_eval_cols_over_several_launches(api):
 
 @pytest.mark.parametrize("rows,cols,seed", [(1, 1, 0), (5, 3, 1), (3, 5, 2), (50, 50, 3), (64, 40, 4), (40, 64, 5),
                                             (200, 200, 6), (129, 200, 7), (300, 257, 8), (500, 500, 9),
-                                            (64, 700, 10), (1024, 23, 11)])
+                                            (64, 700, 10), (1024, 23, 11), (700, 400, 12), (400, 1000, 13),
+                                            (1024, 384, 14)])
 def test_svd_against_lapack(api, rows, cols, seed):
     rng = np.random.default_rng(seed)
     a = rng.normal(size=(rows, cols)) * np.exp(-0.2 * np.arange(cols))[None, :]
@@ -201,7 +226,8 @@ def test_svd_block_path_unscaled(api, rows, cols, seed):
     different sweep counts (odd and even, up to the last sweep of the
     multi-work-group phase), so the outputs come from either copy of the
     working columns.  The long side spans both LDS stash sizes of the round
-    kernel (up to 256 and 257-512 rows)."""
+    kernel (up to 256 and 257-512 rows); 512 x 512 takes the QR-preconditioned
+    path (both sides at least 384, at most 1024)."""
     rng = np.random.default_rng(seed)
     a = rng.normal(size=(rows, cols))
     U, S, V = (x.cpu().numpy() for x in api.svd(torch.from_numpy(a).cuda()))
