@@ -139,6 +139,7 @@ def _shape_class(api, compute, k, follow_up="kmeans", seeds=(3, 4, 5, 6)):
     ("bf16", 240, "kmeans", 4),    # p > 204: step-per-launch Cholesky, SVDs of 4 requests per launch
     ("f64", 20, "leverage", 3),    # the one-work-group SVD (p < 24)
     ("f32", 48, "pilot", 2),       # the pilot sketch alone: one SVD per request
+    ("bf16", 400, "kmeans", 3),    # k >= 384: the QR-preconditioned SVDs, items from per-request pointers
 ])
 def test_sketch_batch_is_bitwise_the_single_sketch(api, compute, k, follow_up, count):
     """cabs_sketch_batch: the same-shape requests share each SVD launch; every output (indices,
