@@ -310,22 +310,29 @@ static int64_t tsf_launch_i(int nkb, hipStream_t st, int64_t M, int K, int Kp, i
 // FP64 products with K > 256 (rows too wide for registers) and without norms
 // (Y = X B only), X rows and B^T rows whole 16-byte runs (K even): 128 x 128
 // output tiles, 4 waves each owning a 64 x 64 quarter (16 MFMA tiles of
-// 16x16x4 FP64).  K runs in stages of 16, double-
-// buffered in LDS and filled by direct buffer-to-LDS loads; a stage holds
+// 16x16x4 FP64).  K runs in stages of 16, double-buffered in LDS (64 KB, two
+// work-groups per CU, so that one's barriers and first loads hide behind the
+// other's MFMAs) and filled by direct buffer-to-LDS loads; a stage holds
 // pairs of consecutive k of every row, ordered [pair][row], so one 16-byte LDS
-// read gives a lane its operand for two MFMA steps.  The contraction order is
-// free: in stage s, pair group t and step sigma, lane group g takes
-// k = 16 s + 8 t + 2 g + sigma, for A and B alike.  Row and column tiles are
-// dealt so that the column tiles of one row tile share an XCD (its L2 serves
-// the rows of X to all of them).
+// read gives a lane its operand for two MFMA steps.  Each stage reads all of
+// its operands from LDS before the next stage's loads are issued: an LDS read
+// issued after a pending buffer-to-LDS load makes the compiler wait for that
+// load unless it can prove the two apart, which would stall every stage on
+// the global latency.  The contraction order is free: in stage s, pair group
+// t and step sigma, lane group g takes k = 16 s + 8 t + 2 g + sigma, for A and
+// B alike.  Row and column tiles are dealt so that the column tiles of one row
+// tile share an XCD (its L2 serves the rows of X to all of them).
 constexpr int TF_W = 128;   // output tile edge
 constexpr int TF_KT = 16;   // k per stage
+constexpr int TF_NG = TF_KT / 8;         // pair groups per stage (4 lane groups x 2 k each)
 constexpr int TF_NP = TF_KT / 2 * TF_W;  // 16-byte runs per operand and stage
+constexpr int TF_IPW = TF_KT / 4;        // load instructions per wave, operand and stage (TF_KT over 4 waves)
+typedef double tf_d2 __attribute__((ext_vector_type(2)));
 
-__global__ __launch_bounds__(256, 1) void tsgemm_f64_kernel(int64_t M, int K, int Kp, int N, int ntc,
+__global__ __launch_bounds__(256, 2) void tsgemm_f64_kernel(int64_t M, int K, int Kp, int N, int ntc,
                                                             const double* __restrict__ X,
                                                             const double* __restrict__ Bt, double* __restrict__ Y) {
-  __shared__ uint4 sa0[TF_NP], sa1[TF_NP], sb0[TF_NP], sb1[TF_NP];
+  __shared__ uint4 sa[2][TF_NP], sb[2][TF_NP];
   const int id = blockIdx.x, xcd = id & 7, slot = id >> 3;
   const int ct = slot % ntc;
   const int64_t rt = (int64_t)(slot / ntc) * 8 + xcd;
@@ -338,11 +345,11 @@ __global__ __launch_bounds__(256, 1) void tsgemm_f64_kernel(int64_t M, int K, in
   const int64_t nrow = M - row0 < TF_W ? M - row0 : TF_W;
   const __amdgpu_buffer_rsrc_t xrs = lds_src_rsrc(X + row0 * K, (uint32_t)(nrow * K * (int64_t)sizeof(double)));
   const __amdgpu_buffer_rsrc_t brs = lds_src_rsrc(Bt, (uint32_t)N * (uint32_t)Kp * (uint32_t)sizeof(double));
-  // stage loads: instruction i (0..15) of an operand fills pair i / 2, rows / columns 64 (i & 1) .. + 63
+  // stage loads: instruction i (0 .. TF_KT - 1) of an operand fills pair i / 2, rows / columns 64 (i & 1) .. + 63
   auto issue = [&](uint4* da, uint4* db, int s) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = wave * 4 + u;  // 16 instructions per operand over 4 waves
+    for (int u = 0; u < TF_IPW; ++u) {
+      const int i = wave * TF_IPW + u;  // TF_KT instructions per operand over 4 waves
       const int p = i >> 1, rr = ((i & 1) << 6) + lane;
       const int k0 = s * TF_KT + 2 * p;
       const int64_t xr = row0 + rr;
@@ -358,37 +365,38 @@ __global__ __launch_bounds__(256, 1) void tsgemm_f64_kernel(int64_t M, int K, in
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-  auto compute = [&](const uint4* sa, const uint4* sb) {
+  // one stage: its operands from LDS into registers, then the next stage's loads, then the MFMAs
+  auto stage = [&](const uint4* ca, const uint4* cb, uint4* na, uint4* nb, int snext) {
+    const tf_d2* xa = (const tf_d2*)ca;
+    const tf_d2* xb = (const tf_d2*)cb;
+    tf_d2 ra[TF_NG][4], rb[TF_NG][4];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-      uint4 ra[4], rb[4];
+    for (int t = 0; t < TF_NG; ++t) {
 #pragma unroll
-      for (int a = 0; a < 4; ++a) ra[a] = sa[(4 * t + g) * TF_W + 64 * wr + 16 * a + r];
+      for (int a = 0; a < 4; ++a) ra[t][a] = xa[(4 * t + g) * TF_W + 64 * wr + 16 * a + r];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) rb[b] = sb[(4 * t + g) * TF_W + 64 * wc + 16 * b + r];
+      for (int b = 0; b < 4; ++b) rb[t][b] = xb[(4 * t + g) * TF_W + 64 * wc + 16 * b + r];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (snext >= 0) issue(na, nb, snext);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < TF_NG; ++t)
 #pragma unroll
       for (int sg = 0; sg < 2; ++sg)
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
           for (int b = 0; b < 4; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(Vec16<double>::frag(ra[a], sg),
-                                                             Vec16<double>::frag(rb[b], sg), acc[a][b], 0, 0, 0);
-      __builtin_amdgcn_sched_barrier(0);  // one pair group's operands live at a time
-    }
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[t][a][sg], rb[t][b][sg], acc[a][b], 0, 0, 0);
   };
   const int nks = (K + TF_KT - 1) / TF_KT;
-  issue(sa0, sb0, 0);
-  for (int s = 0; s < nks; s += 2) {
+  issue(sa[0], sb[0], 0);
+  for (int s = 0; s < nks; ++s) {
+    const int cur = s & 1;
     __builtin_amdgcn_s_waitcnt(0x3f70);  // vmcnt(0): this wave's loads of stage s
     __syncthreads();                     // every wave's loads landed; the other buffers are no longer read
-    if (s + 1 < nks) issue(sa1, sb1, s + 1);
-    compute(sa0, sb0);
-    if (s + 1 >= nks) break;
-    __builtin_amdgcn_s_waitcnt(0x3f70);
-    __syncthreads();
-    if (s + 2 < nks) issue(sa0, sb0, s + 2);
-    compute(sa1, sb1);
+    stage(sa[cur], sb[cur], sa[cur ^ 1], sb[cur ^ 1], s + 1 < nks ? s + 1 : -1);
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a)

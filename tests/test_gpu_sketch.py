@@ -143,6 +143,20 @@ def test_error_sampled_matches_oracle(api, m, n, ns):
     assert e[2] == pytest.approx(rel, rel=1e-8)
 
 
+@pytest.mark.parametrize("k,seed", [(270, 7), (288, 8)])
+def test_error_exact_with_wide_samples(api, k, seed):
+    """k > 256: C U is formed by the FP64 product kernel for rows wider than the register-resident
+    one takes (K in stages of 16: 270 gives 17, the last one partial, 288 eighteen full ones); 3000
+    rows (23 full 128-row tiles and a ragged one) and k columns (ragged 128-column tiles); the
+    exact error against the oracle's."""
+    spec, _ = workloads.config("rbf2000", 1.5)
+    kw = dict(k1_rows=k, k1_cols=k, k2_rows=k, k2_cols=k, seed=seed)
+    mat, prm, res, ref = _compare_f64(api, spec, kw)
+    e = api.error(mat, prm, res, 0).cpu().numpy()
+    want = oc.rel_error_exact(Matrix(spec), ref.C, ref.Umid, ref.Rt)
+    assert e[2] == pytest.approx(want, rel=1e-9)
+
+
 def test_zero_matrix_reports_rank_loss(api):
     spec = workloads.dense_matrix(np.zeros((100, 80)))
     mat, prm, res = _run(api, spec, dict(k1_rows=5, k1_cols=5, k2_rows=5, k2_cols=5))
