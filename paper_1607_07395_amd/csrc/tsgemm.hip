@@ -545,13 +545,28 @@ __device__ __forceinline__ int tri_row_dev(int t) {
   return a;
 }
 
+// Row blocks: every block holds a CU slot for the time of its rows, so the
+// launch takes (waves of GR_TARGET_BLOCKS blocks) x (rows per block); nb (a
+// multiple of 8, at most GR_MAX_BLOCKS blocks in all) minimises that product,
+// the smallest nb on ties.  (A grid just past one wave, e.g. 560 blocks for
+// K = 500, would run its last 48 blocks alone for a whole block time.)
+constexpr int GR_MAX_BLOCKS = 2 * GR_TARGET_BLOCKS;
+
 static inline GramPlan gram_plan(int64_t M, int K) {
   GramPlan g;
   g.nst = (K + GR_W - 1) / GR_W;
   g.ns = g.nst * (g.nst + 1) / 2;
-  int64_t nb = ceil_div(GR_TARGET_BLOCKS, g.ns);
-  nb = std::min<int64_t>(nb, ceil_div(M, GR_RS));
-  nb = ceil_div(std::max<int64_t>(nb, 1), 8) * 8;
+  const int64_t nb_rows = ceil_div(ceil_div(std::max<int64_t>(M, 1), GR_RS), 8) * 8;  // one stage per block at least
+  const int64_t nb_cap = std::max<int64_t>(8, std::min<int64_t>(nb_rows, GR_MAX_BLOCKS / g.ns / 8 * 8));
+  int64_t nb = 8, best = -1;
+  for (int64_t b = 8; b <= nb_cap; b += 8) {
+    const int64_t rows_per = ceil_div(ceil_div(M, b), GR_RS) * GR_RS;
+    const int64_t cost = ceil_div(g.ns * b, GR_TARGET_BLOCKS) * rows_per;
+    if (best < 0 || cost < best) {
+      best = cost;
+      nb = b;
+    }
+  }
   g.rows_per = ceil_div(ceil_div(M, nb), GR_RS) * GR_RS;
   g.nb = (int)nb;
   return g;
