@@ -1059,58 +1059,12 @@ __global__ __launch_bounds__(256) void snap_topt_kernel(int64_t rows, int dim, i
   }
 }
 
-// (distance, row) pairs in lexicographic order, swapped into place.
-__device__ __forceinline__ void pair_cex(double& da, int& ra, double& db, int& rb) {
-  const bool sw = db < da || (db == da && rb < ra);
-  const double d0 = sw ? db : da, d1 = sw ? da : db;
-  const int r0 = sw ? rb : ra, r1 = sw ? ra : rb;
-  da = d0; db = d1; ra = r0; rb = r1;
-}
-
-// The SNAP_T = 16 smallest pairs of a sorted list and a batch of eight newer
-// rows (larger indices): the batch is sorted by an optimal 19-comparator
-// network, the list's last eight are replaced by the elementwise smaller of
-// them and the reversed batch (which leaves the 16 smallest of the union, as a
-// bitonic sequence), and a bitonic merge sorts those.  Lexicographic order on
-// (distance, row) keeps the result that of inserting the rows one at a time
-// in increasing order (an equal distance goes after the older rows).
-__device__ __forceinline__ void topt_merge8(double (&d)[SNAP_T], int (&r)[SNAP_T], double (&bd)[8], int (&br)[8]) {
-  static_assert(SNAP_T == 16, "the merge network is for 16-entry lists");
-#define CABS_CX(i, j) pair_cex(bd[i], br[i], bd[j], br[j])
-  CABS_CX(0, 2); CABS_CX(1, 3); CABS_CX(4, 6); CABS_CX(5, 7);
-  CABS_CX(0, 4); CABS_CX(1, 5); CABS_CX(2, 6); CABS_CX(3, 7);
-  CABS_CX(0, 1); CABS_CX(2, 3); CABS_CX(4, 5); CABS_CX(6, 7);
-  CABS_CX(2, 4); CABS_CX(3, 5);
-  CABS_CX(1, 4); CABS_CX(3, 6);
-  CABS_CX(1, 2); CABS_CX(3, 4); CABS_CX(5, 6);
-#undef CABS_CX
-#pragma unroll
-  for (int i = 8; i < 16; ++i) {
-    const double b = bd[15 - i];
-    const int rb = br[15 - i];
-    const bool tb = b < d[i] || (b == d[i] && rb < r[i]);
-    d[i] = tb ? b : d[i];
-    r[i] = tb ? rb : r[i];
-  }
-#pragma unroll
-  for (int st = 8; st >= 1; st >>= 1)
-#pragma unroll
-    for (int i = 0; i < 16; ++i)
-      if ((i & st) == 0) pair_cex(d[i], r[i], d[i + st], r[i + st]);
-}
-
 // The same per-block lists from the dot products the final assignment stored
 // (sacc[row k + centre]): that kernel's MFMA sequence per element is the tile
 // core's, so each distance snap_dist(|p|^2, |z|^2, dot) is bit for bit the one
-// snap_topt_kernel forms, and the lists are those of inserting the rows in the
-// same order.  Wave w takes the 64-centre chunks w, w + 4, ... (lane = centre)
-// and reads the block's rows eight at a time (one coalesced 256-byte run per
-// row); a batch with no distance below some lane's current 16th is skipped,
-// the others are merged into the lists as a whole (topt_merge8: about half the
-// work of eight single insertions, which a wave runs whenever any of its lanes
-// inserts).  Zero rows, rows past the block and non-finite distances carry an
-// infinite distance and the largest row index, like the lists' empty entries,
-// so they never enter.
+// snap_topt_kernel forms, and the rows are inserted in the same order.  Wave w
+// takes the 64-centre chunks w, w + 4, ... (lane = centre) and reads the block's
+// rows eight at a time (one coalesced 256-byte run per row).
 __global__ __launch_bounds__(256) void snap_select_kernel(int64_t rows, int k, int64_t rows_per_block,
                                                           const float* __restrict__ sacc,
                                                           const double* __restrict__ znorm,
@@ -1130,7 +1084,6 @@ __global__ __launch_bounds__(256) void snap_select_kernel(int64_t rows, int k, i
     for (int q = 0; q < SNAP_T; ++q) { td[q] = __builtin_huge_val(); tr[q] = 0x7fffffff; }
     const double zn = znorm[myc];
     for (int64_t r0 = rbeg; r0 < rend; r0 += U) {
-      static_assert(U == 8, "batches of eight rows (topt_merge8)");
       float a[U];
       double pn[U];
 #pragma unroll
@@ -1139,19 +1092,12 @@ __global__ __launch_bounds__(256) void snap_select_kernel(int64_t rows, int k, i
         a[u] = sacc[row * k + myc];
         pn[u] = pnorm[row];
       }
-      double bd[U];
-      int br[U];
-      double bmin = __builtin_huge_val();
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const double d = snap_dist(pn[u], zn, (double)a[u]);
-        // as with single insertions, an infinite or NaN distance never enters
-        const bool in = r0 + u < rend && pn[u] != 0.0 && d < __builtin_huge_val();
-        bd[u] = in ? d : __builtin_huge_val();
-        br[u] = in ? (int)(r0 + u) : 0x7fffffff;
-        bmin = bd[u] < bmin ? bd[u] : bmin;
+        if (r0 + u >= rend) break;
+        const double d = pn[u] != 0.0 ? snap_dist(pn[u], zn, (double)a[u]) : __builtin_huge_val();
+        topt_insert<double>(td, tr, d, (int)(r0 + u));
       }
-      if (__any(bmin < td[SNAP_T - 1])) topt_merge8(td, tr, bd, br);
     }
     const int64_t base = ((int64_t)myc * nblk + blockIdx.x) * SNAP_T;
 #pragma unroll
