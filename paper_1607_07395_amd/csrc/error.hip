@@ -472,41 +472,31 @@ __global__ __launch_bounds__(256) void eb_eval_kernel(MatView mv, int kr, const 
   err_block_store(num, den, part, b);
 }
 
-// Low-rank sources with FP32 tables (r <= ER_TMAX) and RBF sources with FP32
-// points (d <= ER_TMAX), row buckets of at most ER_RB rows, k <= ER_KMAX.
-// Samples are keyed by (row bucket, column stripe) with up to ER_S stripes
-// (as many as keep the buckets within ER_RB rows), one work-group per key;
-// block ids are dealt to the XCDs in turn, so all work-groups of a stripe run
-// on one XCD and the column side of their samples (R^T_j and qf_j or y_j)
-// comes from that XCD's L2.  Within a work-group the samples are laid out by
-// row (16-lane group g takes rows g, g + 16, ...; a row's samples stay in key
-// order), every lane drawing the noise of the samples it places.  A group
-// walks its samples holding the current row's FP64 CU run and its FP32 table
-// run (pf o s, or x_i) in registers, loads only the column side per sample,
-// with the next ER_D samples' loads in flight (one at k > 256, where the row
-// side takes twice the registers), and lane q keeps the sums of
-// every 16th sample so that residuals are formed 16 at a time.  The row side
-// is thus read once per row and bucket instead of once per sample (at the
-// 1e6 x 1e6 RBF workload's k = 500 it was two thirds of the gathered bytes).
+// Low-rank source with FP32 tables, row buckets of at most ER_RB rows and k,
+// r <= ER_KMAX.  Samples are keyed by (row bucket, column stripe) with ER_S
+// stripes, one work-group per key; block ids are dealt to the XCDs in turn,
+// so all work-groups of a stripe run on one XCD and the column side of their
+// samples (R^T_j and qf_j) comes from that XCD's L2.  Within a work-group the
+// samples are laid out by row (16-lane group g takes rows g, g + 16, ...; a
+// row's samples stay in key order), every lane drawing the noise of the
+// samples it places.  A group walks its samples holding the current row's
+// FP64 CU run and FP32 pf o s run in registers, loads only the column side
+// per sample, with the next ER_D samples' loads in flight, and lane q keeps
+// the sums of every 16th sample so that residuals are formed 16 at a time.
 // Sums are per lane in sample order, then lanes, groups and work-groups, in
-// fixed orders.  NR: 256-element segments of a k-long row per lane group.
+// fixed orders.
 constexpr int ER_RB = 128;
 constexpr int ER_CH = 2048;
-constexpr int ER_TMAX = 256;
-constexpr int ER_KMAX = 512;
+constexpr int ER_KMAX = 256;
 constexpr int ER_D = 2;
 constexpr int ER_S = 8;
 
-template <int SRC, int NR, typename TC, bool VEC>
+template <typename TC, bool VEC>
 __global__ __launch_bounds__(256) void eb_eval_rows_kernel(MatView mv, int kr, const double* __restrict__ CU,
                                                            const TC* __restrict__ Rt, EbPlan pl,
                                                            const int32_t* __restrict__ starts,
                                                            const int2* __restrict__ sorted,
                                                            double* __restrict__ part) {
-  static_assert(SRC == SRC_LOWRANK || SRC == SRC_RBF, "table sources only");
-  typedef typename SvT<SRC, float>::type SV;  // low rank: FP32 table products; RBF: FP64 distance
-  constexpr int NV = 4 * NR;         // runs of a k-long row per lane
-  constexpr int D = NR == 1 ? ER_D : 1;  // samples in flight per group (registers allow two at k <= 256)
   constexpr int SETS = ER_CH / 256;  // 64-record sets per wave and chunk
   __shared__ int32_t sj[ER_CH];
   __shared__ double snz[ER_CH];
@@ -519,23 +509,16 @@ __global__ __launch_bounds__(256) void eb_eval_rows_kernel(MatView mv, int kr, c
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, grp = tid >> 4;
   const int key = blockIdx.x;
   const int64_t row0 = (int64_t)(key / pl.ns) * pl.rb;
-  const int tn = SRC == SRC_LOWRANK ? mv.r : mv.d;  // table width
-  // per-lane byte offsets of the runs in a row; with whole runs (VEC) a run
-  // past k or the table width is moved to the row's last run, whose values then
-  // meet a zero run of the row side (the RBF difference is masked there: tin);
-  // the other case loads element by element, zeros past the end on both sides
-  int off_rt[NV], off_qf[4];
-  bool tin[4];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const int c = 64 * v + 4 * l16;
-    off_rt[v] = (c + 4 <= kr ? c : kr - 4) * (int)sizeof(TC);
-  }
+  const int r = mv.r;
+  // per-lane byte offsets of the four runs in a row; with whole runs (VEC) a
+  // run past k or r is moved to the row's last run, whose values then meet a
+  // zero run of the row side (the other case loads element by element)
+  int off_rt[4], off_qf[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int c = 64 * v + 4 * l16;
-    off_qf[v] = (c + 4 <= tn ? c : tn - 4) * (int)sizeof(float);
-    tin[v] = c < tn;
+    off_rt[v] = (c + 4 <= kr ? c : kr - 4) * (int)sizeof(TC);
+    off_qf[v] = (c + 4 <= r ? c : r - 4) * (int)sizeof(float);
   }
   double num = 0.0, den = 0.0;  // per lane: its samples' residuals
   const int s0 = starts[key], s1 = starts[key + 1];
@@ -610,48 +593,44 @@ __global__ __launch_bounds__(256) void eb_eval_rows_kernel(MatView mv, int kr, c
         const int ro = ((lk & 7) << 4) | (lk >> 3);
         sj[pos] = t.y;
         sro[pos] = (uint8_t)ro;
-        snz[pos] = SRC == SRC_LOWRANK && mv.noise_std != 0.0
-                       ? noise_f64(mv.noise_seed, (uint64_t)(row0 + ro), (uint64_t)t.y)
-                       : 0.0;
+        snz[pos] = mv.noise_std != 0.0 ? noise_f64(mv.noise_seed, (uint64_t)(row0 + ro), (uint64_t)t.y) : 0.0;
       }
     }
     __syncthreads();
-    // group grp: its samples in order, D of them in flight
+    // group grp: its samples in order, ER_D of them in flight
     const int p0 = gbeg[grp], p1 = gbeg[grp + 1];
     if (p0 < p1) {
       const char* rtb = (const char*)Rt;
-      const char* qfb = (const char*)(SRC == SRC_LOWRANK ? mv.qf : mv.y);
-      TC bq[D][NV][4];  // raw R^T_j runs (widened at use)
-      float yq[D][4][4];  // qf_j or y_j
-      auto fetch = [&](int p, TC (&bo)[NV][4], float (&yo)[4][4]) {
+      const char* qfb = (const char*)mv.qf;
+      TC bq[ER_D][4][4];  // raw R^T_j runs (widened at use)
+      float yq[ER_D][4][4];
+      auto fetch = [&](int p, TC (&bo)[4][4], float (&yo)[4][4]) {
         const int64_t j = sj[p];
         const char* rrow = rtb + j * kr * (int64_t)sizeof(TC);
-        const char* qrow = qfb + j * tn * (int64_t)sizeof(float);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          if constexpr (VEC) {
-            RawRun4<TC, true>::get((const TC*)(rrow + off_rt[v]), 0, 4, bo[v]);
-          } else {
-            RawRun4<TC, false>::get((const TC*)rrow, 64 * v + 4 * l16, kr, bo[v]);
-          }
-        }
+        const char* qrow = qfb + j * r * (int64_t)sizeof(float);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          if constexpr (VEC) run4_f32<true>((const float*)(qrow + off_qf[v]), 0, 4, yo[v]);
-          else run4_f32<false>((const float*)qrow, 64 * v + 4 * l16, tn, yo[v]);
+          if constexpr (VEC) {
+            RawRun4<TC, true>::get((const TC*)(rrow + off_rt[v]), 0, 4, bo[v]);
+            run4_f32<true>((const float*)(qrow + off_qf[v]), 0, 4, yo[v]);
+          } else {
+            const int c = 64 * v + 4 * l16;
+            RawRun4<TC, false>::get((const TC*)rrow, c, kr, bo[v]);
+            run4_f32<false>((const float*)qrow, c, r, yo[v]);
+          }
         }
       };
 #pragma unroll
-      for (int d = 0; d < D; ++d)
+      for (int d = 0; d < ER_D; ++d)
         if (p0 + d < p1) fetch(p0 + d, bq[d], yq[d]);
-      double cu[NV][4];
-      float ps[4][4];  // pf_i o s, or x_i
+      double cu[4][4];
+      float ps[4][4];
       int cur = -1;
       double my_ap = 0.0;
-      SV my_sv = (SV)0;
-      for (int p = p0; p < p1; p += D) {
+      float my_sv = 0.0f;
+      for (int p = p0; p < p1; p += ER_D) {
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
+        for (int d = 0; d < ER_D; ++d) {
           const int pp = p + d;
           if (pp < p1) {
             const int ro = sro[pp];
@@ -659,48 +638,33 @@ __global__ __launch_bounds__(256) void eb_eval_rows_kernel(MatView mv, int kr, c
               cur = ro;
               const int64_t row = row0 + ro;
 #pragma unroll
-              for (int v = 0; v < NV; ++v) Run4<double, VEC>::get(CU + row * kr, 64 * v + 4 * l16, kr, cu[v]);
-#pragma unroll
               for (int v = 0; v < 4; ++v) {
                 const int c = 64 * v + 4 * l16;
-                if constexpr (SRC == SRC_LOWRANK) {
-                  float pv[4], sv4[4];
-                  run4_f32<VEC>((const float*)mv.pf + row * tn, c, tn, pv);
-                  run4_f32<VEC>((const float*)mv.s, c, tn, sv4);
+                Run4<double, VEC>::get(CU + row * kr, c, kr, cu[v]);
+                float pv[4], sv4[4];
+                run4_f32<VEC>((const float*)mv.pf + row * r, c, r, pv);
+                run4_f32<VEC>((const float*)mv.s, c, r, sv4);
 #pragma unroll
-                  for (int w = 0; w < 4; ++w) ps[v][w] = pv[w] * sv4[w];
-                } else {
-                  run4_f32<VEC>((const float*)mv.x + row * tn, c, tn, ps[v]);
-                }
+                for (int w = 0; w < 4; ++w) ps[v][w] = pv[w] * sv4[w];
               }
             }
             double ap = 0.0;
-            SV sv = (SV)0;
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-#pragma unroll
-              for (int w = 0; w < 4; ++w) ap += cu[v][w] * to_f64(bq[d][v][w]);
+            float sv = 0.0f;
 #pragma unroll
             for (int v = 0; v < 4; ++v)
 #pragma unroll
               for (int w = 0; w < 4; ++w) {
-                if constexpr (SRC == SRC_LOWRANK) {
-                  sv += ps[v][w] * yq[d][v][w];
-                } else {
-                  const double df = tin[v] ? (double)ps[v][w] - (double)yq[d][v][w] : 0.0;
-                  sv += df * df;
-                }
+                ap += cu[v][w] * to_f64(bq[d][v][w]);
+                sv += ps[v][w] * yq[d][v][w];
               }
-            if (pp + D < p1) fetch(pp + D, bq[d], yq[d]);
+            if (pp + ER_D < p1) fetch(pp + ER_D, bq[d], yq[d]);
             ap = row16_sum(ap);
             sv = row16_sum(sv);
             const int q = (pp - p0) & 15;
             if (l16 == q) { my_ap = ap; my_sv = sv; }
             if (q == 15 || pp + 1 == p1) {  // residuals of the last 16 samples, one per lane
               if (l16 <= q) {
-                double av;
-                if constexpr (SRC == SRC_LOWRANK) av = (double)my_sv + mv.noise_std * snz[pp - q + l16];
-                else av = exp(-my_sv / (2.0 * mv.sigma * mv.sigma));
+                const double av = (double)my_sv + mv.noise_std * snz[pp - q + l16];
                 num += (av - my_ap) * (av - my_ap);
                 den += av * av;
               }
@@ -723,24 +687,15 @@ __global__ __launch_bounds__(256) void eb_eval_rows_kernel(MatView mv, int kr, c
   }
 }
 
-// Column stripes for the row kernel: as many (up to ER_S) as keep a row
-// bucket within ER_RB rows; 0 if even one stripe cannot.
-static inline int er_stripes(const MatView& mv, int64_t ns) {
-  for (int st = ER_S; st >= 1; st >>= 1)
-    if (eb_plan(mv.m, mv.n, ns, st).rb <= ER_RB) return st;
-  return 0;
-}
-
 static inline bool er_rows_ok(const MatView& mv, int kr, int64_t ns) {
-  if (mv.storage != P_F32 || (mv.kind != SRC_LOWRANK && mv.kind != SRC_RBF)) return false;
-  const int tn = mv.kind == SRC_LOWRANK ? mv.r : mv.d;
-  if (tn < 4 || tn > ER_TMAX || kr < 4 || kr > ER_KMAX) return false;
-  return eb_use(mv.m, mv.n, ns) && er_stripes(mv, ns) > 0;
+  if (mv.kind != SRC_LOWRANK || mv.storage != P_F32) return false;
+  if (!eb_use(mv.m, mv.n, ns)) return false;
+  return eb_plan(mv.m, mv.n, ns, ER_S).rb <= ER_RB && kr >= 4 && kr <= ER_KMAX && mv.r >= 4 && mv.r <= ER_KMAX;
 }
 
 // The sorted path's plan: column stripes when the row kernel takes it.
 static inline EbPlan eb_plan_for(const MatView& mv, int kr, int64_t ns) {
-  return eb_plan(mv.m, mv.n, ns, er_rows_ok(mv, kr, ns) ? er_stripes(mv, ns) : 1);
+  return eb_plan(mv.m, mv.n, ns, er_rows_ok(mv, kr, ns) ? ER_S : 1);
 }
 
 template <typename TIn>
@@ -984,24 +939,14 @@ static hipError_t error_t(const MatView& mv, int kr, const double* CU, const TC*
     hipLaunchKernelGGL(eb_scan_kernel, dim3(1), dim3(1024), 0, st, pl, totals, starts);
     hipLaunchKernelGGL(eb_offsets_kernel, dim3(gw), dim3(256), 0, st, pl, counts, starts, offs);
     hipLaunchKernelGGL(eb_scatter_kernel, dim3(EB_G), dim3(256), 0, st, ns, pl, ij, offs, sorted);
-    if (sizeof(TC) < 8 && er_rows_ok(mv, kr, ns)) {  // (FP64 compute has FP64 tables: never this kernel)
+    if (er_rows_ok(mv, kr, ns)) {
       nb = pl.nbk;
-      auto rows = [&](auto src, auto nr) {
-        constexpr int S = decltype(src)::value, R = decltype(nr)::value;
-        if constexpr (sizeof(TC) == 8) return;
-        else if (vec)
-          hipLaunchKernelGGL((eb_eval_rows_kernel<S, R, TC, true>), dim3(nb), dim3(256), 0, st, mv, kr, CU, Rt, pl,
-                             starts, sorted, part);
-        else
-          hipLaunchKernelGGL((eb_eval_rows_kernel<S, R, TC, false>), dim3(nb), dim3(256), 0, st, mv, kr, CU, Rt, pl,
-                             starts, sorted, part);
-      };
-      auto by_k = [&](auto src) {
-        if (kr <= 256) rows(src, std::integral_constant<int, 1>{});
-        else rows(src, std::integral_constant<int, 2>{});
-      };
-      if (mv.kind == SRC_LOWRANK) by_k(std::integral_constant<int, SRC_LOWRANK>{});
-      else by_k(std::integral_constant<int, SRC_RBF>{});
+      if (vec)
+        hipLaunchKernelGGL((eb_eval_rows_kernel<TC, true>), dim3(nb), dim3(256), 0, st, mv, kr, CU, Rt, pl, starts,
+                           sorted, part);
+      else
+        hipLaunchKernelGGL((eb_eval_rows_kernel<TC, false>), dim3(nb), dim3(256), 0, st, mv, kr, CU, Rt, pl, starts,
+                           sorted, part);
     } else {
       nb = pl.nbk;
       with_src(mv.kind, vec, [&](auto src, auto vc) {
