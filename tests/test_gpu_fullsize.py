@@ -88,6 +88,30 @@ def _error(spec, res, e3, ns, seed):
     assert g[2] == pytest.approx(np.sqrt(num / den), rel=1e-3)
 
 
+@pytest.mark.skip(reason="written for a row-wise sampled-error kernel for RBF sources and k up to 512 that was "
+                         "taken out: the profiling run of the version that had it ended with the GPU box faulted, "
+                         "and no cause was found in the code; kept off the GPU until one is")
+@pytest.mark.parametrize("name,scale,k,compute", [
+    ("rbf1e6", 0.55, 300, "f32"),      # 550000 points, d = 64: one column stripe, two 256-element segments
+    ("rbf1e6", 0.02, 100, "bf16"),     # 20000 points: eight stripes, one segment, BF16 R^T
+    ("rbf2000", 4.0, 270, "f32"),      # d = 10: element loads, two segments
+    ("rbf2000", 4.0, 40, "f16"),       # d = 10, one segment, FP16 R^T
+    ("lowrank1e5", 0.1, 300, "f32"),   # low rank, r = 200, two segments
+])
+def test_sampled_error_row_kernel(api, name, scale, k, compute):
+    """Sampled errors with at least one sample per row (the bucketed path) on RBF and low-rank sources,
+    against the oracle's arithmetic at the same samples and factors."""
+    spec, _ = workloads.config(name, scale)
+    ns = spec.m + 1000
+    mat = api.DeviceMatrix(spec, storage="f32")
+    prm = api.make_params(k, k, k, k, kmeans_iters=3, compute=compute, seed=4)
+    res = api.sketch(mat, prm)
+    e3 = api.error(mat, prm, res, ns, seed=77)
+    torch.cuda.synchronize()
+    assert res.diagnostics()["status"] == 0
+    _error(spec, res, e3, ns, seed=77)
+
+
 def test_lowrank_1e5_x_2e4_rank200_fullsize(api):
     ns = 100_000
     spec, k, prm, res, e3 = _sketch(api, "lowrank1e5", seed=3, ns=ns)
