@@ -945,9 +945,10 @@ hipError_t launch_svd_items(int batch, int rows, int cols, const SvdItems& it, h
 // finds the pivot and forms the reflector from the pivot column itself (the
 // same code on the same data, so the same values), then each wave updates its
 // columns (v^T a, a -= tau (v^T a) v, and the exact squared norm of rows
-// j + 1.. as the next step's pivot key) and its rows of Q (Q <- Q H_j).  The pivot column is only read in its step, the norms and taken
-// flags are double-buffered between steps, so no work-group reads what another
-// writes in the same launch.
+// j + 1.. as the next step's pivot key) and its rows of Q (Q <- Q H_j).  The
+// pivot column is only read in its step, and the norms and taken flags are
+// double-buffered between steps, so no work-group reads what another writes
+// in the same launch.
 // ---------------------------------------------------------------------------
 constexpr int QRP_WG = 128;  // work-groups per matrix and step (one column and one row of Q per wave at q <= 512)
 
@@ -1163,7 +1164,6 @@ __global__ __launch_bounds__(256) void qrp_sign_kernel(int rows, int cols, SvdIt
 }
 
 // Host views of an item's pointers.
-static const double* h_item_a(const SvdItems& it, int b) { return it.n_ptr ? it.Ap[b] : it.A + b * it.sA; }
 static double* h_item_u(const SvdItems& it, int b) { return it.n_ptr ? it.Up[b] : it.U + b * it.sU; }
 static double* h_item_s(const SvdItems& it, int b) { return it.n_ptr ? it.Sp[b] : it.S + b * it.sS; }
 static double* h_item_v(const SvdItems& it, int b) { return it.n_ptr ? it.Vp[b] : it.V + b * it.sV; }
@@ -1209,7 +1209,6 @@ static hipError_t launch_svd_qrp(int batch, int rows, int cols, const SvdItems& 
     double* lo = v.trans ? h_item_v(it, b) : h_item_u(it, b);
     e = launch_small_gemm(q, p, p, v.Q, q, false, v.Vp, p, false, nullptr, nullptr, nullptr, lo, p, st);
     if (e != hipSuccess) return e;
-    (void)h_item_a;
   }
   hipLaunchKernelGGL(qrp_perm_kernel, dim3((unsigned)ceil_div((int64_t)p * p, 256), batch), dim3(256), 0, st, rows,
                      cols, it);
