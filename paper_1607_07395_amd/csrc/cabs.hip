@@ -54,6 +54,8 @@ static cabs_status fail(cabs_status st, const char* fmt, ...) {
   } while (0)
 
 extern "C" const char* cabs_last_error(void) { return g_last_error.c_str(); }
+
+void cabs::set_last_error(const char* msg) { g_last_error = msg; }
 extern "C" const char* cabs_version(void) { return "libcabs 0.1 (gfx950)"; }
 
 // ---------------------------------------------------------------------------

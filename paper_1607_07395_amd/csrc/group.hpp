@@ -1,4 +1,5 @@
-// Same-shape sketches run as one group (cabs.hip), for the server.
+// What the server takes from cabs.hip: same-shape sketches run as one group,
+// and the calling thread's error message.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,5 +20,8 @@ bool sketch_groupable(const cabs_params* a, const cabs_params* b);
 cabs_status sketch_group(int G, const cabs_matrix* const* mats, const cabs_params* const* prms,
                          cabs_result* const* outs, void* const* ws, const size_t* ws_bytes, const hipStream_t* streams,
                          const hipEvent_t* join_ev, hipEvent_t fork_ev, cabs_status* status);
+
+// Sets the message cabs_last_error returns on this thread.
+void set_last_error(const char* msg);
 
 }  // namespace cabs

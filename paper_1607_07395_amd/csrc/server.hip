@@ -197,12 +197,19 @@ static void scheduler(cabs_server* s) {
 }
 
 extern "C" cabs_server* cabs_server_create(int32_t device, size_t hbm_budget_bytes, int32_t max_slots) {
-  if (max_slots < 1 || max_slots > 64 || hbm_budget_bytes < 4096) return nullptr;
-  if (hipSetDevice(device) != hipSuccess) return nullptr;
+  if (max_slots < 1 || max_slots > 64 || hbm_budget_bytes < 4096) {
+    cabs::set_last_error("cabs_server_create: max_slots must be 1..64 and the budget at least 4096 bytes");
+    return nullptr;
+  }
+  if (hipSetDevice(device) != hipSuccess) {
+    cabs::set_last_error("cabs_server_create: hipSetDevice failed");
+    return nullptr;
+  }
   cabs_server* s = new cabs_server();
   s->device = device;
   s->budget = hbm_budget_bytes;
   if (hipMalloc((void**)&s->pool_base, hbm_budget_bytes) != hipSuccess) {
+    cabs::set_last_error("cabs_server_create: the memory pool could not be allocated");
     delete s;
     return nullptr;
   }
@@ -210,10 +217,29 @@ extern "C" cabs_server* cabs_server_create(int32_t device, size_t hbm_budget_byt
   s->streams.resize(max_slots);
   s->events.resize(max_slots);
   s->join_events.resize(max_slots);
-  for (int k = 0; k < max_slots; ++k) {
-    (void)hipStreamCreateWithFlags(&s->streams[k], hipStreamNonBlocking);
-    (void)hipEventCreateWithFlags(&s->events[k], hipEventDisableTiming);
-    (void)hipEventCreateWithFlags(&s->join_events[k], hipEventDisableTiming);
+  // a slot's stream and events, or none of the server if one cannot be made
+  bool made = true;
+  for (int k = 0; k < max_slots && made; ++k) {
+    hipStream_t st = nullptr;
+    hipEvent_t done = nullptr, join = nullptr;
+    made = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+    if (made) s->streams[k] = st;
+    made = made && hipEventCreateWithFlags(&done, hipEventDisableTiming) == hipSuccess;
+    if (made) s->events[k] = done;
+    made = made && hipEventCreateWithFlags(&join, hipEventDisableTiming) == hipSuccess;
+    if (made) s->join_events[k] = join;
+  }
+  if (!made) {
+    cabs::set_last_error("cabs_server_create: a slot's stream or events could not be created");
+    for (int k = 0; k < max_slots; ++k) {
+      if (s->streams[k]) (void)hipStreamDestroy(s->streams[k]);
+      if (s->events[k]) (void)hipEventDestroy(s->events[k]);
+      if (s->join_events[k]) (void)hipEventDestroy(s->join_events[k]);
+    }
+    (void)hipFree(s->pool_base);
+    delete s->core;
+    delete s;
+    return nullptr;
   }
   s->worker = std::thread(scheduler, s);
   return s;
