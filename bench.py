@@ -537,7 +537,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        print(json.dumps({"error": "the library runs on one GPU (no sharding across GPUs); use --gpus 1"}))
         sys.exit(2)
 
     import numpy as np
