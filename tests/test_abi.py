@@ -169,3 +169,12 @@ def test_server_rejects_invalid_creation():
     lib = F.lib()
     assert not lib.cabs_server_create(0, 1 << 20, 0)
     assert not lib.cabs_server_create(0, 16, 4)
+
+
+def test_server_rejects_bad_arguments_with_a_reason():
+    """cabs_server_create checks its arguments before any device call and says why through cabs_last_error."""
+    from paper_1607_07395_amd import _ffi as F
+    from paper_1607_07395_amd import api
+    for budget, slots in ((1024, 2), (1 << 20, 0), (1 << 20, 65)):
+        with pytest.raises(F.CabsError, match="max_slots must be 1..64"):
+            api.Server(0, budget, slots)
